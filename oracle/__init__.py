@@ -1,0 +1,165 @@
+"""FP64 CPU oracle for doubly periodic Laplace, Yukawa and Stokes sums.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the
+benchmark's CPU-baseline leg are the only callers. The product library
+never imports, links or runs anything here, and nothing here comes from
+the product library: the C++ source (``oracle.cpp``) is compiled on its
+own with g++ and loaded through ctypes.
+
+Every function evaluates the plain definition of the periodic sum
+(Sec. 1, eq. psum) -- see the header of ``oracle.cpp`` for the methods
+(Ewald splits, closed-form row sums, truncated lattice sums). Coordinates
+are arrays of shape (2, n) (row 0 = x, row 1 = y) in float64.
+
+Parity status: every function here is pinned by ``tests/test_oracle.py``
+(split-parameter independence, agreement of two independent Laplace
+formulas, free-space limits, lattice periodicity, Yukawa -> Laplace limit,
+divergence-free Stokes velocity, library special functions).
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+def build(force=False):
+    """Compile oracle.cpp into liboracle.so (g++, OpenMP, -O2)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["g++", "-std=c++17", "-O2", "-fopenmp", "-fPIC", "-shared",
+                               "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        i64 = ctypes.c_int64
+        common = [i64, _dp, _dp, _dp, i64, _dp, _dp, ctypes.c_int, _dp, _dp]
+        lib.oracle_laplace_ewald.argtypes = [_dp, _dp, ctypes.c_double, ctypes.c_double] + common
+        lib.oracle_laplace_rowsum.argtypes = [ctypes.c_double] * 3 + [ctypes.c_int] + common
+        lib.oracle_yukawa_lattice.argtypes = [_dp, _dp, ctypes.c_double, ctypes.c_double] + common
+        lib.oracle_stokes_ewald.argtypes = [_dp, _dp, ctypes.c_double, ctypes.c_double] + common
+        lib.oracle_free_space.argtypes = [ctypes.c_int, ctypes.c_double] + common
+        for f in (lib.oracle_laplace_ewald, lib.oracle_laplace_rowsum, lib.oracle_yukawa_lattice,
+                  lib.oracle_stokes_ewald, lib.oracle_free_space):
+            f.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _arr(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def _p(a):
+    return a.ctypes.data_as(_dp) if a is not None else None
+
+
+def _prep(src, dens, trg, ncomp):
+    src = _arr(src)
+    assert src.ndim == 2 and src.shape[0] == 2
+    ns = src.shape[1]
+    self_exclude = trg is None
+    trg = src if trg is None else _arr(trg)
+    assert trg.ndim == 2 and trg.shape[0] == 2
+    dens = _arr(dens, (ncomp, ns) if ncomp > 1 else (ns,))
+    return src, dens, trg, ns, trg.shape[1], int(self_exclude)
+
+
+def _check(rc, name):
+    if rc != 0:
+        raise ValueError(f"{name} failed with code {rc}")
+
+
+def laplace(e1, e2, src, q, trg=None, tol=1e-14, alpha=0.0):
+    """Zero-mean periodic Laplace potential and gradient (Ewald split).
+
+    trg=None means the targets are the sources, self term excluded.
+    Returns (pot[nt], grad[2, nt]).
+    """
+    lib = _load()
+    src, q, trg, ns, nt, se = _prep(src, q, trg, 1)
+    e1 = _arr(e1); e2 = _arr(e2)
+    pot = np.empty(nt); grad = np.empty((2, nt))
+    _check(lib.oracle_laplace_ewald(_p(e1), _p(e2), alpha, tol, ns, _p(src[0]), _p(src[1]), _p(q),
+                                    nt, _p(trg[0]), _p(trg[1]), se, _p(pot), _p(grad)),
+           "oracle_laplace_ewald")
+    return pot, grad
+
+
+def laplace_rowsum(d, xi, eta, src, q, trg=None, nrows=None):
+    """Same quantity as laplace() from closed-form row sums (canonical lattice
+    e1=(d,0), e2=(xi,eta), all points with |y| <= eta/2)."""
+    lib = _load()
+    src, q, trg, ns, nt, se = _prep(src, q, trg, 1)
+    if nrows is None:
+        # terms decay like exp(-2 pi n eta/d); 40 digits of margin
+        nrows = int(np.ceil(40.0 * d / (2 * np.pi * eta))) + 2
+    pot = np.empty(nt); grad = np.empty((2, nt))
+    _check(lib.oracle_laplace_rowsum(d, xi, eta, nrows, ns, _p(src[0]), _p(src[1]), _p(q),
+                                     nt, _p(trg[0]), _p(trg[1]), se, _p(pot), _p(grad)),
+           "oracle_laplace_rowsum")
+    return pot, grad
+
+
+def yukawa(e1, e2, beta, src, q, trg=None, tol=1e-15):
+    """Periodic modified-Helmholtz sum with G = K0(beta r)/(2 pi) (truncated lattice sum)."""
+    lib = _load()
+    src, q, trg, ns, nt, se = _prep(src, q, trg, 1)
+    e1 = _arr(e1); e2 = _arr(e2)
+    pot = np.empty(nt); grad = np.empty((2, nt))
+    _check(lib.oracle_yukawa_lattice(_p(e1), _p(e2), beta, tol, ns, _p(src[0]), _p(src[1]), _p(q),
+                                     nt, _p(trg[0]), _p(trg[1]), se, _p(pot), _p(grad)),
+           "oracle_yukawa_lattice")
+    return pot, grad
+
+
+def stokes(e1, e2, src, f, trg=None, tol=1e-14, alpha=0.0):
+    """Zero-mean periodic Stokeslet velocity u[2, nt] and gradient g[4, nt]
+    (du1/dx, du1/dy, du2/dx, du2/dy); f has shape (2, ns) with zero sum."""
+    lib = _load()
+    src, f, trg, ns, nt, se = _prep(src, f, trg, 2)
+    e1 = _arr(e1); e2 = _arr(e2)
+    vel = np.empty((2, nt)); grad = np.empty((4, nt))
+    _check(lib.oracle_stokes_ewald(_p(e1), _p(e2), alpha, tol, ns, _p(src[0]), _p(src[1]), _p(f),
+                                   nt, _p(trg[0]), _p(trg[1]), se, _p(vel), _p(grad)),
+           "oracle_stokes_ewald")
+    return vel, grad
+
+
+def free_space(kernel, src, dens, trg=None, beta=0.0):
+    """Non-periodic direct sums ('laplace' | 'yukawa' | 'stokes'), same layouts."""
+    lib = _load()
+    k = {"laplace": 0, "yukawa": 1, "stokes": 2}[kernel]
+    src, dens, trg, ns, nt, se = _prep(src, dens, trg, 2 if k == 2 else 1)
+    pot = np.empty((2, nt)) if k == 2 else np.empty(nt)
+    grad = np.empty((4, nt)) if k == 2 else np.empty((2, nt))
+    _check(lib.oracle_free_space(k, beta, ns, _p(src[0]), _p(src[1]), _p(dens), nt,
+                                 _p(trg[0]), _p(trg[1]), se, _p(pot), _p(grad)), "oracle_free_space")
+    return pot, grad
+
+
+def evaluate(kernel, e1, e2, src, dens, trg=None, beta=0.0, tol=1e-14):
+    """Dispatch by kernel name; dens is q[ns] (scalar kernels) or f[2, ns] (Stokes)."""
+    if kernel == "laplace":
+        return laplace(e1, e2, src, dens, trg, tol=tol)
+    if kernel == "yukawa":
+        return yukawa(e1, e2, beta, src, dens, trg, tol=max(tol, 1e-16))
+    if kernel == "stokes":
+        return stokes(e1, e2, src, dens, trg, tol=tol)
+    raise ValueError(kernel)

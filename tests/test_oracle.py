@@ -1,0 +1,227 @@
+"""Pins for the FP64 oracle: each check compares it with something other
+than itself (a second independent formula, a library routine, a limit, an
+invariant of the periodic problem), so that a dropped term, a wrong sign
+or a wrong normalisation in any of its functions fails at least one test.
+"""
+import numpy as np
+import pytest
+import scipy.special as sp
+
+import oracle
+import workloads as W
+
+SHEARED = ((2.0, 0.0), (0.4, 1.0))          # d = 2, xi = 0.4, eta = 1
+GENERAL = ((1.1, 0.35), (-0.2, 0.9))        # not canonical, rotated basis
+
+
+def _setup(e1, e2, ns=12, nt=9, seed=1, stokes=False):
+    rng = np.random.default_rng(seed)
+    src = W.cell_points(rng, e1, e2, ns)
+    trg = W.cell_points(rng, e1, e2, nt)
+    dens = W.neutral_forces(rng, ns) if stokes else W.neutral_charges(rng, ns)
+    return src, dens, trg
+
+
+def rel(a, b):
+    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b))
+
+
+# --- library special functions the oracle calls -----------------------------
+
+def test_free_space_yukawa_matches_scipy_bessel():
+    rng = np.random.default_rng(3)
+    src = rng.random((2, 7)); trg = rng.random((2, 5)) + 0.01
+    q = rng.standard_normal(7)
+    beta = 2.7
+    pot, grad = oracle.free_space("yukawa", src, q, trg, beta=beta)
+    r = trg[:, :, None] - src[:, None, :]
+    rr = np.hypot(r[0], r[1])
+    ref = (sp.k0(beta * rr) @ q) / (2 * np.pi)
+    gref = -(beta / (2 * np.pi)) * np.einsum("tj,ktj->kt", sp.k1(beta * rr) / rr * q, r)
+    assert rel(pot, ref) < 1e-14 and rel(grad, gref) < 1e-14
+
+
+def test_free_space_laplace_and_stokes_match_numpy():
+    rng = np.random.default_rng(4)
+    src = rng.random((2, 6)); trg = rng.random((2, 4)) + 0.02
+    q = rng.standard_normal(6); f = rng.standard_normal((2, 6))
+    r = trg[:, :, None] - src[:, None, :]
+    r2 = r[0] ** 2 + r[1] ** 2
+    pot, grad = oracle.free_space("laplace", src, q, trg)
+    assert rel(pot, -(np.log(np.sqrt(r2)) @ q) / (2 * np.pi)) < 1e-14
+    assert rel(grad, -np.einsum("ktj,j->kt", r / r2, q) / (2 * np.pi)) < 1e-14
+    vel, _ = oracle.free_space("stokes", src, f, trg)
+    rf = np.einsum("ktj,kj->tj", r, f)
+    u = (-np.log(np.sqrt(r2))[None] * f[:, None, :] + rf[None] * r / r2[None]).sum(-1) / (4 * np.pi)
+    assert rel(vel, u) < 1e-14
+
+
+# --- Laplace ------------------------------------------------------------------
+
+@pytest.mark.parametrize("e1,e2", [SHEARED, GENERAL])
+@pytest.mark.parametrize("self_trg", [False, True])
+def test_laplace_ewald_independent_of_split(e1, e2, self_trg):
+    src, q, trg = _setup(e1, e2)
+    trg = None if self_trg else trg
+    base = oracle.laplace(e1, e2, src, q, trg, alpha=2.0)
+    for a in (1.2, 3.5, 7.0):
+        p, g = oracle.laplace(e1, e2, src, q, trg, alpha=a)
+        assert rel(p, base[0]) < 1e-12 and rel(g, base[1]) < 1e-12
+
+
+@pytest.mark.parametrize("self_trg", [False, True])
+def test_laplace_ewald_equals_row_sum_formula(self_trg):
+    (d, _), (xi, eta) = SHEARED
+    src, q, trg = _setup(*SHEARED, ns=15, nt=11)
+    trg = None if self_trg else trg
+    p1, g1 = oracle.laplace(*SHEARED, src, q, trg)
+    p2, g2 = oracle.laplace_rowsum(d, xi, eta, src, q, trg)
+    assert rel(p1, p2) < 1e-12 and rel(g1, g2) < 1e-12
+
+
+def test_laplace_row_sum_high_aspect_matches_ewald():
+    e1, e2 = (20.0, 0.0), (3.0, 1.0)
+    src, q, trg = _setup(e1, e2, ns=10, nt=6, seed=5)
+    p1, g1 = oracle.laplace(e1, e2, src, q, trg)
+    p2, g2 = oracle.laplace_rowsum(20.0, 3.0, 1.0, src, q, trg)
+    assert rel(p1, p2) < 1e-11 and rel(g1, g2) < 1e-11
+
+
+def test_laplace_periodic_across_both_lattice_vectors():
+    # Row-sum formula on targets of the bottom edge and the same targets
+    # moved by e2 (top edge), and left/right edges: the periodicity
+    # requirement (Sec. 1 eq. pbc).
+    (d, _), (xi, eta) = SHEARED
+    src, q, _ = _setup(*SHEARED, ns=10)
+    s = np.linspace(-0.5, 0.5, 13)
+    bottom = np.stack([s * d - 0.5 * xi, np.full_like(s, -0.5 * eta)])
+    top = bottom + np.array([[xi], [eta]])
+    pb, gb = oracle.laplace_rowsum(d, xi, eta, src, q, bottom)
+    pt, gt = oracle.laplace_rowsum(d, xi, eta, src, q, top)
+    assert rel(pt, pb) < 1e-12 and rel(gt, gb) < 1e-12
+    left = np.stack([-0.5 * d + s * xi, s * eta])
+    right = left + np.array([[d], [0.0]])
+    pl, gl = oracle.laplace_rowsum(d, xi, eta, src, q, left)
+    pr, gr = oracle.laplace_rowsum(d, xi, eta, src, q, right)
+    assert rel(pr, pl) < 1e-12 and rel(gr, gl) < 1e-12
+
+
+def test_laplace_cell_mean_is_zero():
+    # midpoint rule over the cell (sources kept off the grid points); the
+    # log singularities limit this to a few digits.
+    e1, e2 = (1.0, 0.0), (0.0, 1.0)
+    src = np.array([[0.1037, -0.2519, 0.3311], [0.2203, -0.1107, -0.3391]])
+    q = np.array([1.0, -0.4, -0.6])
+    n = 160
+    g = (np.arange(n) + 0.5) / n - 0.5
+    X, Y = np.meshgrid(g, g)
+    p, _ = oracle.laplace(e1, e2, src, q, np.stack([X.ravel(), Y.ravel()]), tol=1e-10)
+    assert abs(p.mean()) < 2e-3 * np.abs(p).mean()
+
+
+def test_laplace_gradient_is_derivative_of_potential():
+    src, q, trg = _setup(*GENERAL, ns=8, nt=4)
+    _, g = oracle.laplace(*GENERAL, src, q, trg)
+    h = 1e-5
+    for k in range(2):
+        dp = np.zeros((2, 1)); dp[k] = h
+        fd = (oracle.laplace(*GENERAL, src, q, trg + dp)[0] - oracle.laplace(*GENERAL, src, q, trg - dp)[0]) / (2 * h)
+        assert rel(g[k], fd) < 1e-6
+
+
+def test_laplace_tight_dipole_reduces_to_free_space():
+    # A +-q pair of separation delta in a unit cell: near the pair the
+    # images add a field of relative size O(delta).
+    e1, e2 = (1.0, 0.0), (0.0, 1.0)
+    delta = 1e-4
+    src = np.array([[0.0, delta], [0.0, 0.0]])
+    q = np.array([1.0, -1.0])
+    trg = np.array([[0.5 * delta, 2 * delta, -delta], [delta, -delta, 0.5 * delta]])
+    p, g = oracle.laplace(e1, e2, src, q, trg)
+    pf, gf = oracle.free_space("laplace", src, q, trg)
+    assert np.max(np.abs(p - pf)) < 10 * delta and rel(g, gf) < 10 * delta
+
+
+# --- Yukawa -------------------------------------------------------------------
+
+def test_yukawa_lattice_sum_converged_in_truncation():
+    src, q, trg = _setup(*SHEARED)
+    p1, g1 = oracle.yukawa(*SHEARED, 1.5, src, q, trg, tol=1e-9)
+    p2, g2 = oracle.yukawa(*SHEARED, 1.5, src, q, trg, tol=1e-16)
+    assert rel(p1, p2) < 1e-7 and rel(g1, g2) < 1e-7
+
+
+def test_yukawa_large_beta_is_free_space():
+    e1, e2 = (1.0, 0.0), (0.0, 1.0)
+    rng = np.random.default_rng(6)
+    src = 0.2 * (rng.random((2, 6)) - 0.5)      # well inside the cell
+    trg = 0.2 * (rng.random((2, 4)) - 0.5)
+    q = rng.standard_normal(6)
+    beta = 60.0      # nearest image >= 0.8 away: K0(48) ~ 1e-22
+    p, g = oracle.yukawa(e1, e2, beta, src, q, trg)
+    pf, gf = oracle.free_space("yukawa", src, q, trg, beta=beta)
+    assert rel(p, pf) < 1e-13 and rel(g, gf) < 1e-13
+
+
+def test_yukawa_tends_to_laplace_quadratically_in_beta():
+    # neutral charges: the periodic symbols 1/(k^2+beta^2) and 1/k^2 differ by O(beta^2)
+    src, q, trg = _setup(*SHEARED, ns=6, nt=4, seed=7)
+    pl, gl = oracle.laplace(*SHEARED, src, q, trg)
+    errs = []
+    for beta in (0.4, 0.2):
+        p, g = oracle.yukawa(*SHEARED, beta, src, q, trg, tol=1e-13)
+        errs.append(np.linalg.norm(p - pl) + np.linalg.norm(g - gl))
+    ratio = errs[0] / errs[1]
+    assert 3.3 < ratio < 4.7, ratio
+    assert errs[1] < 0.05 * (np.linalg.norm(pl) + np.linalg.norm(gl))
+
+
+# --- Stokes -------------------------------------------------------------------
+
+@pytest.mark.parametrize("self_trg", [False, True])
+def test_stokes_ewald_independent_of_split(self_trg):
+    src, f, trg = _setup(*GENERAL, stokes=True)
+    trg = None if self_trg else trg
+    u0, g0 = oracle.stokes(*GENERAL, src, f, trg, alpha=2.0)
+    for a in (1.3, 4.0, 7.5):
+        u, g = oracle.stokes(*GENERAL, src, f, trg, alpha=a)
+        assert rel(u, u0) < 1e-12 and rel(g, g0) < 1e-12
+
+
+def test_stokes_trace_is_laplace():
+    # tr G_stokeslet = -(1/2pi) log r + const, and the periodic symbols obey
+    # tr (I - k k^T/k^2)/k^2 = 1/k^2: u1[f=(q,0)] + u2[f=(0,q)] = Laplace[q].
+    src, q, trg = _setup(*SHEARED, ns=10, nt=7, seed=8)
+    z = np.zeros_like(q)
+    ua, ga = oracle.stokes(*SHEARED, src, np.stack([q, z]), trg)
+    ub, gb = oracle.stokes(*SHEARED, src, np.stack([z, q]), trg)
+    pl, gl = oracle.laplace(*SHEARED, src, q, trg)
+    assert rel(ua[0] + ub[1], pl) < 1e-12
+    assert rel(np.stack([ga[0] + gb[2], ga[1] + gb[3]]), gl) < 1e-12
+
+
+def test_stokes_divergence_free_and_gradient_consistent():
+    src, f, trg = _setup(*SHEARED, ns=9, nt=5, seed=9, stokes=True)
+    u, g = oracle.stokes(*SHEARED, src, f, trg)
+    assert np.max(np.abs(g[0] + g[3])) < 1e-12 * np.max(np.abs(g))
+    h = 1e-5
+    for k in range(2):
+        dp = np.zeros((2, 1)); dp[k] = h
+        fd = (oracle.stokes(*SHEARED, src, f, trg + dp)[0] - oracle.stokes(*SHEARED, src, f, trg - dp)[0]) / (2 * h)
+        assert rel(np.stack([g[k], g[2 + k]]), fd) < 1e-6
+
+
+def test_stokes_periodic_and_tight_pair_free_space():
+    src, f, _ = _setup(*SHEARED, ns=8, seed=10, stokes=True)
+    t = np.array([[0.13, -0.61], [0.27, 0.05]])
+    u0, g0 = oracle.stokes(*SHEARED, src, f, t)
+    for sh in (SHEARED[0], SHEARED[1]):
+        u1, g1 = oracle.stokes(*SHEARED, src, f, t + np.array(sh)[:, None])
+        assert rel(u1, u0) < 1e-12 and rel(g1, g0) < 1e-12
+    delta = 1e-4
+    src = np.array([[0.0, delta], [0.0, 0.0]])
+    f = np.array([[1.0, -1.0], [0.5, -0.5]])
+    trg = np.array([[0.5 * delta, 2 * delta], [delta, -delta]])
+    u, g = oracle.stokes((1.0, 0.0), (0.0, 1.0), src, f, trg)
+    uf, gf = oracle.free_space("stokes", src, f, trg)
+    assert np.max(np.abs(u - uf)) < 10 * delta and rel(g, gf) < 10 * delta
