@@ -1,0 +1,169 @@
+#!/usr/bin/env python
+"""Throughput of the periodic evaluation on one MI355X.
+
+Workload: square cell e1 = (1, 0), e2 = (0, 1); N = 200000 sources uniform
+in the cell (seed 0); modified Helmholtz with beta = 10 (neutral N(0,1)
+charges) and Stokes (N(0,1) forces with zero net force); potential +
+gradient (Stokes: velocity + velocity gradient) at every source, tol 1e-6.
+One step = one evaluation of each kernel, i.e. 2N targets. The headline
+value is the mixed-precision path; the plain FP64 GPU path is timed on the
+same inputs, and the FP64 CPU oracle on a bounded sample of targets.
+
+Prints one JSON line (rank 0). Only one GPU is supported.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "targets/sec (pot+grad) at 1e-6 rel err, mixed vs FP64 GPU path; % FP32/HBM roofline"
+# algorithmic flops per target/source/image pair of the near-field kernels
+# (add/mul = 1, fma = 2, transcendental = 1; counted from the kernel source,
+# large-argument branch for K0/K1; the two-float coordinate corrections and
+# the r = 0 guards are not counted)
+FLOPS_PER_PAIR = {"laplace": 15, "yukawa": 51, "stokes": 31}
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+
+def rel(a, b):
+    import numpy as np
+    a = np.asarray(a); b = np.asarray(b)
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=200000, help="sources (= targets) per cell")
+    ap.add_argument("--fp64-steps", type=int, default=2)
+    ap.add_argument("--sample", type=int, default=16, help="oracle targets per kernel")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build evaluates on one GPU only; multi-GPU runs are not supported "
+              f"(asked for --gpus {args.gpus}, WORLD_SIZE {world})", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    import paper_2111_01083_amd as P
+
+    dev = torch.device("cuda:0")
+    n = args.n
+    e1, e2 = (1.0, 0.0), (0.0, 1.0)
+    rng = np.random.default_rng(0)
+    src = W.cell_points(rng, e1, e2, n)
+    q = W.neutral_charges(rng, n)
+    f = W.neutral_forces(rng, n)
+    d_src = torch.tensor(src, device=dev)
+    d_q = torch.tensor(q, device=dev)
+    d_f = torch.tensor(f, device=dev)
+    cases = [("yukawa", 10.0, d_q), ("stokes", 0.0, d_f)]
+
+    def make(prec):
+        plans, outs, wss = [], [], []
+        for kern, beta, dens in cases:
+            p = P.Plan(kern, e1, e2, 1e-6, beta=beta, precision=prec, self_exclude=True, profile=True)
+            ws = torch.empty(P.pfmm_workspace_bytes(p, n, n) + 256, dtype=torch.uint8, device=dev)
+            npot, ngrad = (2, 4) if kern == "stokes" else (1, 2)
+            pot = torch.empty((1, npot, n) if kern == "stokes" else (1, n), dtype=torch.float64, device=dev)
+            grad = torch.empty((1, ngrad, n), dtype=torch.float64, device=dev)
+            plans.append(p); outs.append((pot, grad)); wss.append(ws)
+        return plans, outs, wss
+
+    def step(plans, outs, wss):
+        for (kern, beta, dens), p, (pot, grad), ws in zip(cases, plans, outs, wss):
+            P.pfmm_eval(p, d_src, dens, None, out_pot=pot, out_grad=grad, workspace=ws)
+
+    def timed(prec, steps, warmup):
+        plans, outs, wss = make(prec)
+        for _ in range(warmup):
+            step(plans, outs, wss)
+        torch.cuda.synchronize()
+        for p in plans:
+            p.stage_times()      # drop warm-up events
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step(plans, outs, wss)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        stages = [p.stage_times() for p in plans]
+        res = [(o[0].cpu().numpy()[0], o[1].cpu().numpy()[0]) for o in outs]
+        return (t1 - t0) / steps, stages, res
+
+    print(f"bench: N={n} mixed steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
+    ms_mixed_s, st_mixed, res_mixed = timed("mixed", args.steps, args.warmup)
+    print(f"bench: mixed {ms_mixed_s * 1e3:.1f} ms/step", file=sys.stderr, flush=True)
+    ms64_s, st64, res64 = timed("fp64", args.fp64_steps, 1)
+    print(f"bench: fp64 {ms64_s * 1e3:.1f} ms/step", file=sys.stderr, flush=True)
+
+    targets_per_step = 2 * n
+    value = targets_per_step / ms_mixed_s
+    fp64_value = targets_per_step / ms64_s
+
+    # near-field rooflines (HIP events on the evaluation stream)
+    images = 9
+    roof_all = {}
+    for (kern, _, _), (near_ms, total_ms, cnt) in zip(cases, st_mixed):
+        per_launch_ms = near_ms / max(cnt, 1)
+        flops = FLOPS_PER_PAIR[kern] * images * float(n) * float(n)
+        tflops = flops / (per_launch_ms * 1e-3) / 1e12
+        roof_all[kern] = {"bound": "alu", "achieved": round(tflops, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
+                          "unit": "TFLOP/s", "frac": round(tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
+                          "traffic": None, "near_ms_per_launch": round(per_launch_ms, 3),
+                          "eval_ms": round(total_ms / max(cnt, 1), 3),
+                          "flops_per_pair": FLOPS_PER_PAIR[kern], "pairs_per_launch": images * n * n}
+    dom = max(roof_all, key=lambda k: roof_all[k]["near_ms_per_launch"])
+    roofline = dict(roof_all[dom], kernel=f"near_kernel<{dom}, mixed>")
+
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "targets/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_mixed_s * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "square cell, N=200000 uniform sources = targets, modified Helmholtz "
+                               "beta=10 + Stokes, pot+grad, tol 1e-6",
+                   "n": n, "tol": 1e-6, "precision": "mixed (FP32 pairs, FP64 accumulation and far field)",
+                   "targets_per_step": targets_per_step},
+        "fp64_gpu": {"value": round(fp64_value, 1), "unit": "targets/s", "ms_per_step": round(ms64_s * 1e3, 3),
+                     "steps": args.fp64_steps, "near_ms_per_launch": {k: round(s[0] / max(s[2], 1), 3)
+                                                                      for (k, _, _), s in zip(cases, st64)}},
+        "speedup_mixed_vs_fp64": round(value / fp64_value, 2),
+        "roofline": roofline,
+        "roofline_all": roof_all,
+    }
+
+    if not args.no_cpu_baseline:
+        import oracle
+        idx = np.sort(np.random.default_rng(1).choice(n, args.sample, replace=False))
+        t0 = time.perf_counter()
+        refs = []
+        for kern, beta, _ in cases:
+            dens = f if kern == "stokes" else q
+            refs.append(oracle.evaluate(kern, e1, e2, src, dens, src[:, idx], beta=beta, tol=1e-10, self_idx=idx))
+        cpu_s = time.perf_counter() - t0
+        cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+        out["cpu_baseline"] = {"value": round(len(cases) * args.sample / cpu_s, 3), "unit": "targets/s",
+                               "cores": cores, "kind": "oracle",
+                               "sample": f"{args.sample} sampled targets per kernel (of the {n}), all {n} "
+                                         f"sources, Ewald (Stokes) / truncated lattice sum (Yukawa), "
+                                         f"FP64, {cpu_s:.1f} s"}
+        acc = {}
+        for (kern, _, _), (po, go), (pm, gm), (p6, g6) in zip(cases, refs, res_mixed, res64):
+            acc[kern] = {"mixed_pot": rel(pm[..., idx], po), "mixed_grad": rel(gm[:, idx], go),
+                         "fp64_pot": rel(p6[..., idx], po), "fp64_grad": rel(g6[:, idx], go)}
+        out["rel_err_vs_oracle_on_sample"] = acc
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,173 @@
+/*
+ * pfmm.h -- C ABI of the MI355X periodic field evaluator.
+ *
+ * Evaluates, for sources s_j with densities q_j and targets t_i in a 2D
+ * doubly periodic cell with lattice vectors e1, e2,
+ *     u(t_i) = sum_j sum_{(m,n) in Z^2} G(t_i - s_j - m e1 - n e2) q_j
+ * and its gradient (Sec. 1, eq. psum), for
+ *     PFMM_LAPLACE  G = -(1/2pi) log r                  (Sec. 1; needs sum q = 0)
+ *     PFMM_YUKAWA   G = (1/2pi) K0(beta r)              (Sec. 1, modified Helmholtz)
+ *     PFMM_STOKES   G = -(1/4pi)(log r I - r r^T/r^2)   (Sec. 5.2, eq. stokeslet; needs sum f = 0)
+ * by the paper's splitting (Sec. 1, Def. 1, eq. nearfarsplit): a direct sum
+ * over the cell and its nearest images (3 x (2 m0 + 1) copies), plus the
+ * explicit low-rank plane-wave factorisation of all farther images,
+ * P = L D R, for the south/north rows (Thm. south_thm and its corollary;
+ * Thm. south_thm_lap; Thm. south_thm_s) and the west/east columns (Thm.
+ * west_thm, west_thm_lap, west_thm_s), applied right to left (Sec. 6); when
+ * the aspect ratio is large the south/north factors are applied through
+ * type-1/type-2 NUFFTs on Gauss-Legendre lines in y (Sec. 6.1, eqs.
+ * fastanterp, fastinterp).
+ *
+ * Conventions
+ *  - All coordinate, density and output pointers passed to pfmm_eval are
+ *    DEVICE pointers (HIP global memory) unless a comment says "host".
+ *    The caller owns every buffer; the plan owns only its small tables.
+ *  - Arrays are structure-of-arrays, float64:
+ *      src_xy [2][n_src]   (x then y), trg_xy [2][n_trg] (may equal src_xy)
+ *      dens   [n_dens][n_src]        (Laplace, Yukawa)
+ *             [n_dens][2][n_src]     (Stokes: force components f1, f2)
+ *      out_pot  [n_dens][n_trg]      (Stokes: velocity [n_dens][2][n_trg])
+ *      out_grad [n_dens][2][n_trg]   (d/dx, d/dy; Stokes: [n_dens][4][n_trg]
+ *                                     = du1/dx, du1/dy, du2/dx, du2/dy)
+ *  - Points may lie anywhere; they are wrapped into the cell (the sum is
+ *    periodic). Outputs are in the caller's frame and are OVERWRITTEN.
+ *  - Laplace and Stokes return the zero-cell-mean solution (the paper
+ *    leaves the additive constant free, Sec. 4); densities must be
+ *    neutral (sum_j q_j = 0, eq. chargeneutral; sum_j f_j = 0 for Stokes).
+ *  - self_exclude = 1 means target i IS source i (n_trg == n_src and the
+ *    same coordinates): the term (j = i, zero lattice vector) is left out.
+ *    Any other exactly coincident target/source-image pair contributes 0.
+ *  - Evaluation is asynchronous on the caller's HIP stream; nothing is
+ *    allocated inside pfmm_eval. Scratch memory comes from `workspace`,
+ *    of at least pfmm_workspace_bytes() bytes, 256-byte aligned.
+ *  - Return value 0 on success, a negative PFMM_E* code otherwise; on an
+ *    argument error nothing is launched and outputs are untouched.
+ */
+#ifndef PFMM_H
+#define PFMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { PFMM_LAPLACE = 0, PFMM_YUKAWA = 1, PFMM_STOKES = 2 } pfmm_kernel;
+typedef enum { PFMM_FP64 = 0, PFMM_MIXED = 1 } pfmm_precision;
+typedef enum { PFMM_FAR_AUTO = 0, PFMM_FAR_DIRECT = 1, PFMM_FAR_NUFFT = 2 } pfmm_far_mode;
+
+enum {
+  PFMM_OK = 0,
+  PFMM_EINVAL = -1,          /* bad argument (NULL, negative size, ...)      */
+  PFMM_EINVAL_LATTICE = -2,  /* e1, e2 not finite or linearly dependent      */
+  PFMM_EINVAL_TOL = -3,      /* tol outside [1e-14, 1e-2]                    */
+  PFMM_EWORKSPACE = -4,      /* workspace NULL, too small or misaligned      */
+  PFMM_EHIP = -5,            /* a HIP runtime call failed                    */
+  PFMM_ENOT_NEUTRAL = -6,    /* check_neutral set and densities not neutral  */
+  PFMM_ENOMEM = -7           /* plan tables could not be allocated           */
+};
+
+typedef struct {
+  double beta;        /* Yukawa parameter (> 0); ignored otherwise              */
+  int precision;      /* pfmm_precision: FP64 everywhere, or MIXED (near field  */
+                      /* in FP32 with two-float coordinate differences and     */
+                      /* blocked FP64 accumulation; far-field coefficients in  */
+                      /* FP64)                                                 */
+  int far_mode;       /* pfmm_far_mode: AUTO uses the NUFFT when 2M+1 >= 256   */
+  int m0;             /* near-region half width in e1 (Def. 1); 0 = automatic  */
+  int n_dens;         /* number of density vectors evaluated together (>= 1)   */
+  int self_exclude;   /* 1: target i is source i                               */
+  int m_gl;           /* Gauss-Legendre lines for the NUFFT path; 0 = automatic*/
+  int check_neutral;  /* 1: pfmm_eval syncs the stream and rejects non-neutral */
+                      /*    Laplace/Stokes densities with PFMM_ENOT_NEUTRAL    */
+  int profile;        /* 1: record HIP events around the near-field launches   */
+                      /*    and the whole evaluation (see pfmm_plan_stage_times)*/
+} pfmm_opts;
+
+/* Read-only description of a plan (host struct). */
+typedef struct {
+  int kernel, precision, far_mode_used, m0, n_dens, self_exclude;
+  double d, xi, eta;          /* canonical lattice e1 = (d, 0), e2 = (xi, eta) */
+  double rot_cos, rot_sin;    /* canonical = R * user, R = [[c, -s], [s, c]]   */
+  double eps;                 /* internal truncation tolerance (tol / 10)      */
+  int n_modes;                /* M: south/north modes m = -M..M (eq. mpk0s)    */
+  int n_quad;                 /* west/east quadrature nodes                    */
+  int m_gl, nufft_nf, nufft_w;/* NUFFT lines, fine grid size, kernel width     */
+  int n_images;               /* near images (2 m0 + 1) * 3                    */
+} pfmm_plan_info_t;
+
+typedef struct pfmm_plan_s* pfmm_plan_t;
+
+/* Build a plan (host only; no device work). e1, e2: host double[2], the
+ * lattice vectors in the caller's frame (any basis of the lattice; it is
+ * reduced and rotated so that e1 = (d, 0), |e2| <= d, |xi| <= d/2 as in
+ * Sec. 1). tol: requested relative accuracy in [1e-14, 1e-2]. opts may be
+ * NULL (FP64, AUTO far mode, n_dens 1). On success *out receives a plan
+ * that pfmm_destroy releases. */
+int pfmm_plan(int kernel, const double* e1, const double* e2, double tol,
+              const pfmm_opts* opts, pfmm_plan_t* out);
+
+/* Copy the plan's tables to the current HIP device (synchronous). Done
+ * implicitly by the first pfmm_eval on a device; call it beforehand when
+ * the first evaluation happens inside stream capture. */
+int pfmm_plan_upload(pfmm_plan_t plan);
+
+/* Host: fill *info. */
+int pfmm_plan_get_info(pfmm_plan_t plan, pfmm_plan_info_t* info);
+
+/* Host: copy the west/east quadrature rule (nodes lambda_k and weights
+ * w_k, host arrays of plan->n_quad doubles each) used by Thm. west_thm /
+ * west_thm_lap / west_thm_s. Either pointer may be NULL. */
+int pfmm_plan_get_quadrature(pfmm_plan_t plan, double* nodes, double* weights);
+
+/* Profiling plans only (opts.profile = 1): wait for the events recorded by
+ * every pfmm_eval since the last call, and return the summed GPU time of
+ * the near-field kernel launches (*near_ms), of whole evaluations
+ * (*total_ms) and the number of evaluations (*n_evals); then forget them.
+ * Host pointers; any may be NULL. */
+int pfmm_plan_stage_times(pfmm_plan_t plan, double* near_ms, double* total_ms, int* n_evals);
+
+/* Workspace size in bytes for pfmm_eval with these sizes. */
+size_t pfmm_workspace_bytes(pfmm_plan_t plan, int64_t n_src, int64_t n_trg);
+
+/* Evaluate potentials and gradients (see the conventions above). out_pot
+ * or out_grad may be NULL to skip that output. hip_stream: hipStream_t
+ * (NULL = default stream). */
+int pfmm_eval(pfmm_plan_t plan, int64_t n_src, const double* src_xy, const double* dens,
+              int64_t n_trg, const double* trg_xy, double* out_pot, double* out_grad,
+              void* workspace, size_t workspace_bytes, void* hip_stream);
+
+/* Gradient of a loss L(pot) for targets == sources (self_exclude plans
+ * with n_dens = 1, Laplace/Yukawa): given g = dL/dpot [n_src] (device),
+ * writes out_dq[n_src] = dL/dq = sum_i g_i K(t_i, s_j) and
+ * out_dxy[2][n_src] = dL/dx_j = g_j grad u[q](x_j) + q_j grad u[g](x_j),
+ * using the symmetry of the periodic kernel (Sec. 1, eq. psum). Same
+ * workspace rules as pfmm_eval. The caller projects out_dq onto neutral
+ * densities if it needs to. */
+int pfmm_eval_adjoint(pfmm_plan_t plan, int64_t n_src, const double* src_xy,
+                      const double* dens, const double* g_pot, double* out_dq,
+                      double* out_dxy, void* workspace, size_t workspace_bytes,
+                      void* hip_stream);
+
+/* Batched evaluation of many independent cells in one launch sequence.
+ * plans[c] are plans of any kernel with the same precision and n_dens;
+ * src_off/trg_off (host int64[n_cells + 1]) give each cell's range in the
+ * concatenated arrays src_xy [2][total_src], dens [n_dens][total_src]
+ * (Stokes [n_dens][2][total_src]), trg_xy, out_pot, out_grad (laid out like
+ * pfmm_eval with n_src/n_trg replaced by the totals). Workspace:
+ * pfmm_workspace_bytes_batch(). */
+size_t pfmm_workspace_bytes_batch(int n_cells, const pfmm_plan_t* plans,
+                                  const int64_t* src_off, const int64_t* trg_off);
+int pfmm_eval_batch(int n_cells, const pfmm_plan_t* plans, const int64_t* src_off,
+                    const int64_t* trg_off, const double* src_xy, const double* dens,
+                    const double* trg_xy, double* out_pot, double* out_grad,
+                    void* workspace, size_t workspace_bytes, void* hip_stream);
+
+void pfmm_destroy(pfmm_plan_t plan);
+const char* pfmm_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PFMM_H */

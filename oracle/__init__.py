@@ -46,7 +46,7 @@ def _load():
         build()
         lib = ctypes.CDLL(_LIB)
         i64 = ctypes.c_int64
-        common = [i64, _dp, _dp, _dp, i64, _dp, _dp, ctypes.c_int, _dp, _dp]
+        common = [i64, _dp, _dp, _dp, i64, _dp, _dp, ctypes.POINTER(ctypes.c_int64), _dp, _dp]
         lib.oracle_laplace_ewald.argtypes = [_dp, _dp, ctypes.c_double, ctypes.c_double] + common
         lib.oracle_laplace_rowsum.argtypes = [ctypes.c_double] * 3 + [ctypes.c_int] + common
         lib.oracle_yukawa_lattice.argtypes = [_dp, _dp, ctypes.c_double, ctypes.c_double] + common
@@ -67,18 +67,32 @@ def _arr(a, shape=None):
 
 
 def _p(a):
-    return a.ctypes.data_as(_dp) if a is not None else None
+    if a is None:
+        return None
+    if a.dtype == np.int64:
+        return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    return a.ctypes.data_as(_dp)
 
 
-def _prep(src, dens, trg, ncomp):
+def _prep(src, dens, trg, ncomp, self_idx=None):
+    """trg None: targets are all sources (self terms left out). Otherwise
+    self_idx[i] = j marks target i as sitting on source j (-1: none)."""
     src = _arr(src)
     assert src.ndim == 2 and src.shape[0] == 2
     ns = src.shape[1]
-    self_exclude = trg is None
-    trg = src if trg is None else _arr(trg)
+    if trg is None:
+        trg = src
+        self_idx = np.arange(ns, dtype=np.int64)
+    else:
+        trg = _arr(trg)
     assert trg.ndim == 2 and trg.shape[0] == 2
+    if self_idx is not None:
+        self_idx = np.ascontiguousarray(self_idx, dtype=np.int64)
+        assert self_idx.shape == (trg.shape[1],)
+        ok = self_idx >= 0
+        assert np.array_equal(trg[:, ok], src[:, self_idx[ok]]), "self_idx targets must equal their sources"
     dens = _arr(dens, (ncomp, ns) if ncomp > 1 else (ns,))
-    return src, dens, trg, ns, trg.shape[1], int(self_exclude)
+    return src, dens, trg, ns, trg.shape[1], self_idx
 
 
 def _check(rc, name):
@@ -86,80 +100,82 @@ def _check(rc, name):
         raise ValueError(f"{name} failed with code {rc}")
 
 
-def laplace(e1, e2, src, q, trg=None, tol=1e-14, alpha=0.0):
+def laplace(e1, e2, src, q, trg=None, tol=1e-14, alpha=0.0, self_idx=None):
     """Zero-mean periodic Laplace potential and gradient (Ewald split).
 
-    trg=None means the targets are the sources, self term excluded.
+    trg=None means the targets are the sources, self term excluded; with
+    explicit targets, self_idx[i] = j says target i is source j (term excluded).
     Returns (pot[nt], grad[2, nt]).
     """
     lib = _load()
-    src, q, trg, ns, nt, se = _prep(src, q, trg, 1)
+    src, q, trg, ns, nt, se = _prep(src, q, trg, 1, self_idx)
     e1 = _arr(e1); e2 = _arr(e2)
     pot = np.empty(nt); grad = np.empty((2, nt))
     _check(lib.oracle_laplace_ewald(_p(e1), _p(e2), alpha, tol, ns, _p(src[0]), _p(src[1]), _p(q),
-                                    nt, _p(trg[0]), _p(trg[1]), se, _p(pot), _p(grad)),
+                                    nt, _p(trg[0]), _p(trg[1]), _p(se), _p(pot), _p(grad)),
            "oracle_laplace_ewald")
     return pot, grad
 
 
-def laplace_rowsum(d, xi, eta, src, q, trg=None, nrows=None):
+def laplace_rowsum(d, xi, eta, src, q, trg=None, nrows=None, self_idx=None):
     """Same quantity as laplace() from closed-form row sums (canonical lattice
     e1=(d,0), e2=(xi,eta), all points with |y| <= eta/2)."""
     lib = _load()
-    src, q, trg, ns, nt, se = _prep(src, q, trg, 1)
+    src, q, trg, ns, nt, se = _prep(src, q, trg, 1, self_idx)
     if nrows is None:
         # terms decay like exp(-2 pi n eta/d); 40 digits of margin
         nrows = int(np.ceil(40.0 * d / (2 * np.pi * eta))) + 2
     pot = np.empty(nt); grad = np.empty((2, nt))
     _check(lib.oracle_laplace_rowsum(d, xi, eta, nrows, ns, _p(src[0]), _p(src[1]), _p(q),
-                                     nt, _p(trg[0]), _p(trg[1]), se, _p(pot), _p(grad)),
+                                     nt, _p(trg[0]), _p(trg[1]), _p(se), _p(pot), _p(grad)),
            "oracle_laplace_rowsum")
     return pot, grad
 
 
-def yukawa(e1, e2, beta, src, q, trg=None, tol=1e-15):
+def yukawa(e1, e2, beta, src, q, trg=None, tol=1e-15, self_idx=None):
     """Periodic modified-Helmholtz sum with G = K0(beta r)/(2 pi) (truncated lattice sum)."""
     lib = _load()
-    src, q, trg, ns, nt, se = _prep(src, q, trg, 1)
+    src, q, trg, ns, nt, se = _prep(src, q, trg, 1, self_idx)
     e1 = _arr(e1); e2 = _arr(e2)
     pot = np.empty(nt); grad = np.empty((2, nt))
     _check(lib.oracle_yukawa_lattice(_p(e1), _p(e2), beta, tol, ns, _p(src[0]), _p(src[1]), _p(q),
-                                     nt, _p(trg[0]), _p(trg[1]), se, _p(pot), _p(grad)),
+                                     nt, _p(trg[0]), _p(trg[1]), _p(se), _p(pot), _p(grad)),
            "oracle_yukawa_lattice")
     return pot, grad
 
 
-def stokes(e1, e2, src, f, trg=None, tol=1e-14, alpha=0.0):
+def stokes(e1, e2, src, f, trg=None, tol=1e-14, alpha=0.0, self_idx=None):
     """Zero-mean periodic Stokeslet velocity u[2, nt] and gradient g[4, nt]
     (du1/dx, du1/dy, du2/dx, du2/dy); f has shape (2, ns) with zero sum."""
     lib = _load()
-    src, f, trg, ns, nt, se = _prep(src, f, trg, 2)
+    src, f, trg, ns, nt, se = _prep(src, f, trg, 2, self_idx)
     e1 = _arr(e1); e2 = _arr(e2)
     vel = np.empty((2, nt)); grad = np.empty((4, nt))
     _check(lib.oracle_stokes_ewald(_p(e1), _p(e2), alpha, tol, ns, _p(src[0]), _p(src[1]), _p(f),
-                                   nt, _p(trg[0]), _p(trg[1]), se, _p(vel), _p(grad)),
+                                   nt, _p(trg[0]), _p(trg[1]), _p(se), _p(vel), _p(grad)),
            "oracle_stokes_ewald")
     return vel, grad
 
 
-def free_space(kernel, src, dens, trg=None, beta=0.0):
+def free_space(kernel, src, dens, trg=None, beta=0.0, self_idx=None):
     """Non-periodic direct sums ('laplace' | 'yukawa' | 'stokes'), same layouts."""
     lib = _load()
     k = {"laplace": 0, "yukawa": 1, "stokes": 2}[kernel]
-    src, dens, trg, ns, nt, se = _prep(src, dens, trg, 2 if k == 2 else 1)
+    src, dens, trg, ns, nt, se = _prep(src, dens, trg, 2 if k == 2 else 1, self_idx)
     pot = np.empty((2, nt)) if k == 2 else np.empty(nt)
     grad = np.empty((4, nt)) if k == 2 else np.empty((2, nt))
     _check(lib.oracle_free_space(k, beta, ns, _p(src[0]), _p(src[1]), _p(dens), nt,
-                                 _p(trg[0]), _p(trg[1]), se, _p(pot), _p(grad)), "oracle_free_space")
+                                 _p(trg[0]), _p(trg[1]), _p(se), _p(pot), _p(grad)), "oracle_free_space")
     return pot, grad
 
 
-def evaluate(kernel, e1, e2, src, dens, trg=None, beta=0.0, tol=1e-14):
-    """Dispatch by kernel name; dens is q[ns] (scalar kernels) or f[2, ns] (Stokes)."""
+def evaluate(kernel, e1, e2, src, dens, trg=None, beta=0.0, tol=1e-14, self_idx=None):
+    """Dispatch by kernel name; dens is q[ns] (scalar kernels) or f[2, ns] (Stokes).
+    trg None: targets are the sources; self_idx marks sampled sources as targets."""
     if kernel == "laplace":
-        return laplace(e1, e2, src, dens, trg, tol=tol)
+        return laplace(e1, e2, src, dens, trg, tol=tol, self_idx=self_idx)
     if kernel == "yukawa":
-        return yukawa(e1, e2, beta, src, dens, trg, tol=max(tol, 1e-16))
+        return yukawa(e1, e2, beta, src, dens, trg, tol=max(tol, 1e-16), self_idx=self_idx)
     if kernel == "stokes":
-        return stokes(e1, e2, src, dens, trg, tol=tol)
+        return stokes(e1, e2, src, dens, trg, tol=tol, self_idx=self_idx)
     raise ValueError(kernel)

@@ -127,15 +127,15 @@ double max_extent(const Lattice& L, const double* x, const double* y, int64_t n)
 extern "C" {
 
 // Laplace, Ewald split. dens: q[ns]. out_pot[nt], out_grad[2][nt] (may be NULL).
-// self_exclude != 0 requires nt == ns and means target i is source i.
+// self_idx (may be NULL): self_idx[i] = j >= 0 means target i sits exactly on
+// source j and the term (j, zero lattice vector) is left out; -1 = none.
 // alpha <= 0 picks a default. tol sets both cut-offs.
 int oracle_laplace_ewald(const double* e1, const double* e2, double alpha, double tol,
                          int64_t ns, const double* sx, const double* sy, const double* q,
-                         int64_t nt, const double* tx, const double* ty, int self_exclude,
+                         int64_t nt, const double* tx, const double* ty, const int64_t* self_idx,
                          double* out_pot, double* out_grad) {
   Lattice L;
   if (make_lattice(e1, e2, &L)) return -1;
-  if (self_exclude && nt != ns) return -2;
   if (!(tol > 0 && tol < 1)) return -3;
   if (alpha <= 0) {
     double nn = std::max<double>(1.0, (double)ns * nt / (double)(ns + nt));
@@ -181,9 +181,9 @@ int oracle_laplace_ewald(const double* e1, const double* e2, double alpha, doubl
         double r2 = rx * rx + ry * ry;
         if (r2 > rc * rc) continue;
         if (r2 == 0) {
-          // with self_exclude, target i sits exactly on source i: that is the
+          // target i sitting exactly on source self_idx[i]: that is the
           // excluded (j == i, zero lattice vector) term; any other r == 0 is an error
-          if (!(self_exclude && j == i)) bad = 1;
+          if (!(self_idx && j == self_idx[i])) bad = 1;
           continue;
         }
         double x = a2 * r2;
@@ -204,7 +204,7 @@ int oracle_laplace_ewald(const double* e1, const double* e2, double alpha, doubl
       gx -= coef[a] * kx * im;
       gy -= coef[a] * ky * im;
     }
-    if (self_exclude) pot -= q[i] * (EULER_GAMMA + 2 * std::log(alpha)) / (4 * PI);
+    if (self_idx && self_idx[i] >= 0) pot -= q[self_idx[i]] * (EULER_GAMMA + 2 * std::log(alpha)) / (4 * PI);
     if (out_pot) out_pot[i] = pot;
     if (out_grad) { out_grad[i] = gx; out_grad[nt + i] = gy; }
   }
@@ -216,10 +216,9 @@ int oracle_laplace_ewald(const double* e1, const double* e2, double alpha, doubl
 // the target's own row (terms decay like exp(-2 pi n eta / d)).
 int oracle_laplace_rowsum(double d, double xi, double eta, int nrows,
                           int64_t ns, const double* sx, const double* sy, const double* q,
-                          int64_t nt, const double* tx, const double* ty, int self_exclude,
+                          int64_t nt, const double* tx, const double* ty, const int64_t* self_idx,
                           double* out_pot, double* out_grad) {
   if (!(d > 0 && eta > 0)) return -1;
-  if (self_exclude && nt != ns) return -2;
   const double hh = 0.5 * eta * (1 + 1e-12);
   for (int64_t j = 0; j < ns; ++j) if (std::fabs(sy[j]) > hh) return -5;
   for (int64_t i = 0; i < nt; ++i) if (std::fabs(ty[i]) > hh) return -5;
@@ -234,7 +233,7 @@ int oracle_laplace_rowsum(double d, double xi, double eta, int nrows,
         double wx = tx[i] - sx[j] - n * xi, wy = ty[i] - sy[j] - n * eta;
         // row sum over m of -(1/2pi) log|w - m d| = -|wy|/(2d) - (1/2pi) log|1 - e^{i kap sg w}| + const
         double sg = (wy >= 0) ? 1.0 : -1.0;
-        if (n == 0 && self_exclude && j == i) {
+        if (n == 0 && self_idx && j == self_idx[i]) {
           // the row through the target itself, without the m = 0 term:
           // sum_{m != 0} -(1/2pi) log|m d| is a constant (dropped by neutrality
           // together with the other constants of the row sums) ...
@@ -271,11 +270,10 @@ int oracle_laplace_rowsum(double d, double xi, double eta, int nrows,
 // radius R chosen from the tail bound (see body). dens q[ns].
 int oracle_yukawa_lattice(const double* e1, const double* e2, double beta, double tol,
                           int64_t ns, const double* sx, const double* sy, const double* q,
-                          int64_t nt, const double* tx, const double* ty, int self_exclude,
+                          int64_t nt, const double* tx, const double* ty, const int64_t* self_idx,
                           double* out_pot, double* out_grad) {
   Lattice L;
   if (make_lattice(e1, e2, &L)) return -1;
-  if (self_exclude && nt != ns) return -2;
   if (!(beta > 0) || !(tol > 0 && tol < 1)) return -3;
   // Tail: sum over images farther than R of K0(beta r)/(2pi) is bounded by
   // (1/|C|) int_{R-diam}^inf K0(beta rho) 2 pi rho drho / (2pi) <= K0-type
@@ -297,9 +295,9 @@ int oracle_yukawa_lattice(const double* e1, const double* e2, double beta, doubl
         double r2 = rx * rx + ry * ry;
         if (r2 > R * R) continue;
         if (r2 == 0) {
-          // with self_exclude, target i sits exactly on source i: that is the
+          // target i sitting exactly on source self_idx[i]: that is the
           // excluded (j == i, zero lattice vector) term; any other r == 0 is an error
-          if (!(self_exclude && j == i)) bad = 1;
+          if (!(self_idx && j == self_idx[i])) bad = 1;
           continue;
         }
         double r = std::sqrt(r2);
@@ -318,11 +316,10 @@ int oracle_yukawa_lattice(const double* e1, const double* e2, double beta, doubl
 // out_vel[2][nt], out_grad[4][nt] = (du1/dx, du1/dy, du2/dx, du2/dy).
 int oracle_stokes_ewald(const double* e1, const double* e2, double alpha, double tol,
                         int64_t ns, const double* sx, const double* sy, const double* f,
-                        int64_t nt, const double* tx, const double* ty, int self_exclude,
+                        int64_t nt, const double* tx, const double* ty, const int64_t* self_idx,
                         double* out_vel, double* out_grad) {
   Lattice L;
   if (make_lattice(e1, e2, &L)) return -1;
-  if (self_exclude && nt != ns) return -2;
   if (!(tol > 0 && tol < 1)) return -3;
   if (alpha <= 0) {
     double nn = std::max<double>(1.0, (double)ns * nt / (double)(ns + nt));
@@ -373,9 +370,9 @@ int oracle_stokes_ewald(const double* e1, const double* e2, double alpha, double
         double r2 = rx * rx + ry * ry;
         if (r2 > rc * rc) continue;
         if (r2 == 0) {
-          // with self_exclude, target i sits exactly on source i: that is the
+          // target i sitting exactly on source self_idx[i]: that is the
           // excluded (j == i, zero lattice vector) term; any other r == 0 is an error
-          if (!(self_exclude && j == i)) bad = 1;
+          if (!(self_idx && j == self_idx[i])) bad = 1;
           continue;
         }
         double x = a2 * r2, ex = std::exp(-x), e1v = E1(x);
@@ -413,9 +410,9 @@ int oracle_stokes_ewald(const double* e1, const double* e2, double alpha, double
       // Re(i k_l e^{ik.t} A) = -k_l Im(...)
       g11 -= kx * Ai; g12 -= ky * Ai; g21 -= kx * Bi; g22 -= ky * Bi;
     }
-    if (self_exclude) {
+    if (self_idx && self_idx[i] >= 0) {
       double c = ((EULER_GAMMA + 2 * std::log(alpha)) / 2 + 1) / (4 * PI);
-      u1 -= c * f1[i]; u2 -= c * f2[i];
+      u1 -= c * f1[self_idx[i]]; u2 -= c * f2[self_idx[i]];
     }
     if (out_vel) { out_vel[i] = u1; out_vel[nt + i] = u2; }
     if (out_grad) {
@@ -430,13 +427,12 @@ int oracle_stokes_ewald(const double* e1, const double* e2, double alpha, double
 // kernel: 0 Laplace, 1 Yukawa (beta), 2 Stokes. Same layouts as above.
 int oracle_free_space(int kernel, double beta, int64_t ns, const double* sx, const double* sy,
                       const double* dens, int64_t nt, const double* tx, const double* ty,
-                      int self_exclude, double* out_pot, double* out_grad) {
-  if (self_exclude && nt != ns) return -2;
+                      const int64_t* self_idx, double* out_pot, double* out_grad) {
 #pragma omp parallel for schedule(dynamic, 8)
   for (int64_t i = 0; i < nt; ++i) {
     double p0 = 0, p1 = 0, g[4] = {0, 0, 0, 0};
     for (int64_t j = 0; j < ns; ++j) {
-      if (self_exclude && j == i) continue;
+      if (self_idx && j == self_idx[i]) continue;
       double rx = tx[i] - sx[j], ry = ty[i] - sy[j];
       double r2 = rx * rx + ry * ry, r = std::sqrt(r2);
       if (kernel == 0) {

@@ -1,0 +1,194 @@
+"""MI355X periodic field evaluator: Python binding of libpfmm (include/pfmm.h).
+
+Functions carry the C ABI's names and only marshal arguments (torch device
+tensors -> raw pointers, the current HIP stream); every step of an
+evaluation runs in the HIP library, and nothing here falls back to a CPU
+path. A `Plan` wraps a pfmm_plan_t handle.
+
+Shapes (torch float64 tensors on the HIP device):
+  src (2, ns); trg (2, nt) or None when targets are the sources
+  dens (ns,) | (n_dens, ns); Stokes (2, ns) | (n_dens, 2, ns)
+  returns pot (nt,) | (n_dens, nt) [Stokes (2, nt) | (n_dens, 2, nt)] and
+          grad (2, nt) | (n_dens, 2, nt) [Stokes (4, nt) | (n_dens, 4, nt)]
+"""
+import ctypes
+
+import numpy as np
+
+from . import _lib as L
+
+KERNELS = {"laplace": L.PFMM_LAPLACE, "yukawa": L.PFMM_YUKAWA, "stokes": L.PFMM_STOKES}
+PRECISIONS = {"fp64": L.PFMM_FP64, "mixed": L.PFMM_MIXED}
+FAR_MODES = {"auto": L.PFMM_FAR_AUTO, "direct": L.PFMM_FAR_DIRECT, "nufft": L.PFMM_FAR_NUFFT}
+
+
+class PfmmError(RuntimeError):
+    def __init__(self, code, where):
+        lib = L.load()
+        super().__init__(f"{where}: {L.ERRORS.get(code, code)} ({lib.pfmm_strerror(code).decode()})")
+        self.code = code
+
+
+def _check(rc, where):
+    if rc != 0:
+        raise PfmmError(rc, where)
+
+
+def _dp(arr):
+    return arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class Plan:
+    """Owner of a pfmm_plan_t (see pfmm_plan)."""
+
+    def __init__(self, kernel, e1, e2, tol, beta=0.0, precision="fp64", far_mode="auto", m0=0,
+                 n_dens=1, self_exclude=False, m_gl=0, check_neutral=False, profile=False):
+        lib = L.load()
+        self.kernel_name = kernel
+        self.kernel = KERNELS[kernel]
+        opts = L.pfmm_opts(float(beta), PRECISIONS[precision], FAR_MODES[far_mode], int(m0), int(n_dens),
+                           int(bool(self_exclude)), int(m_gl), int(bool(check_neutral)), int(bool(profile)))
+        e1 = np.ascontiguousarray(e1, dtype=np.float64)
+        e2 = np.ascontiguousarray(e2, dtype=np.float64)
+        h = ctypes.c_void_p()
+        _check(lib.pfmm_plan(self.kernel, _dp(e1), _dp(e2), float(tol), ctypes.byref(opts), ctypes.byref(h)),
+               "pfmm_plan")
+        self.handle = h
+        self.n_dens = int(n_dens)
+        self.self_exclude = bool(self_exclude)
+        self._ws = None
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and L is not None and L._lib is not None:
+            L._lib.pfmm_destroy(h)
+            self.handle = None
+
+    @property
+    def info(self):
+        inf = L.pfmm_plan_info_t()
+        _check(L.load().pfmm_plan_get_info(self.handle, ctypes.byref(inf)), "pfmm_plan_get_info")
+        return {f: getattr(inf, f) for f, _ in inf._fields_}
+
+    def quadrature(self):
+        n = self.info["n_quad"]
+        x = np.zeros(n); w = np.zeros(n)
+        _check(L.load().pfmm_plan_get_quadrature(self.handle, _dp(x), _dp(w)), "pfmm_plan_get_quadrature")
+        return x, w
+
+    def stage_times(self):
+        """(near-field ms, whole-evaluation ms, evaluations) since the last call
+        (profiling plans; waits for the recorded HIP events)."""
+        a, b, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
+        _check(L.load().pfmm_plan_stage_times(self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(n)),
+               "pfmm_plan_stage_times")
+        return a.value, b.value, n.value
+
+    def __call__(self, src, dens, trg=None, **kw):
+        return pfmm_eval(self, src, dens, trg, **kw)
+
+
+def pfmm_plan(kernel, e1, e2, tol, **opts):
+    return Plan(kernel, e1, e2, tol, **opts)
+
+
+def pfmm_plan_upload(plan):
+    _check(L.load().pfmm_plan_upload(plan.handle), "pfmm_plan_upload")
+
+
+def pfmm_workspace_bytes(plan, n_src, n_trg):
+    return int(L.load().pfmm_workspace_bytes(plan.handle, int(n_src), int(n_trg)))
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _workspace(nbytes, device, workspace):
+    torch = _torch()
+    if workspace is None:
+        workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    ptr = workspace.data_ptr()
+    aligned = (ptr + 255) & ~255
+    avail = workspace.numel() - (aligned - ptr)
+    return workspace, aligned, avail
+
+
+def _as_dev(t, name):
+    torch = _torch()
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64):
+        raise TypeError(f"{name} must be a float64 tensor on the HIP device")
+    return t.contiguous()
+
+
+def pfmm_eval(plan, src, dens, trg=None, out_pot=None, out_grad=None, workspace=None, stream=None,
+              want_pot=True, want_grad=True):
+    """Potentials and gradients at the targets (trg None: targets = sources)."""
+    torch = _torch()
+    lib = L.load()
+    src = _as_dev(src, "src")
+    dens = _as_dev(dens, "dens")
+    ns = src.shape[1]
+    stokes = plan.kernel == L.PFMM_STOKES
+    squeeze = dens.dim() == (2 if stokes else 1)
+    nd = plan.n_dens
+    if dens.numel() != nd * (2 if stokes else 1) * ns:
+        raise ValueError("dens has the wrong size for this plan")
+    if plan.self_exclude:
+        if trg is not None and trg.data_ptr() != src.data_ptr():
+            raise ValueError("self_exclude plan: targets are the sources (pass trg=None)")
+        trg_t, nt = None, ns
+    else:
+        if trg is None:
+            raise ValueError("plan without self_exclude needs targets")
+        trg_t = _as_dev(trg, "trg")
+        nt = trg_t.shape[1]
+    npot = 2 if stokes else 1
+    ngrad = 4 if stokes else 2
+    if want_pot and out_pot is None:
+        out_pot = torch.empty((nd, npot, nt) if stokes else (nd, nt), dtype=torch.float64, device=src.device)
+    if want_grad and out_grad is None:
+        out_grad = torch.empty((nd, ngrad, nt), dtype=torch.float64, device=src.device)
+    nbytes = pfmm_workspace_bytes(plan, ns, nt)
+    ws, wptr, avail = _workspace(nbytes, src.device, workspace)
+    rc = lib.pfmm_eval(plan.handle, ns, src.data_ptr(), dens.data_ptr(), nt,
+                       None if trg_t is None else trg_t.data_ptr(),
+                       None if out_pot is None else out_pot.data_ptr(),
+                       None if out_grad is None else out_grad.data_ptr(),
+                       wptr, avail, _stream_ptr(stream))
+    _check(rc, "pfmm_eval")
+    if squeeze:
+        out_pot = None if out_pot is None else out_pot[0]
+        out_grad = None if out_grad is None else out_grad[0]
+    return out_pot, out_grad
+
+
+def pfmm_eval_adjoint(plan, src, dens, g_pot, workspace=None, stream=None):
+    """dL/dq and dL/dx for a loss of the potentials at the sources (see pfmm.h)."""
+    torch = _torch()
+    lib = L.load()
+    src = _as_dev(src, "src"); dens = _as_dev(dens, "dens"); g_pot = _as_dev(g_pot, "g_pot")
+    ns = src.shape[1]
+    dq = torch.empty_like(dens)
+    dxy = torch.empty((2, ns), dtype=torch.float64, device=src.device)
+    nbytes = pfmm_workspace_bytes(plan, ns, ns)
+    ws, wptr, avail = _workspace(2 * nbytes + 256, src.device, workspace)
+    _check(lib.pfmm_eval_adjoint(plan.handle, ns, src.data_ptr(), dens.data_ptr(), g_pot.data_ptr(),
+                                 dq.data_ptr(), dxy.data_ptr(), wptr, avail, _stream_ptr(stream)),
+           "pfmm_eval_adjoint")
+    return dq, dxy
+
+
+def pfmm_strerror(code):
+    return L.load().pfmm_strerror(int(code)).decode()
+
+
+def pfmm_destroy(plan):
+    plan.__del__()

@@ -1,0 +1,73 @@
+// Device helpers: free-space kernel evaluations per source/target pair and
+// the K0/K1 approximations (coefficients from bessel_tables.h).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "bessel_tables.h"
+
+namespace pfmm {
+
+template <int N>
+__device__ __forceinline__ float horner_f(const double (&c)[N], float t) {
+  float r = (float)c[N - 1];
+#pragma unroll
+  for (int k = N - 2; k >= 0; --k) r = __builtin_fmaf(r, t, (float)c[k]);
+  return r;
+}
+template <int N>
+__device__ __forceinline__ double horner_d(const double (&c)[N], double t) {
+  double r = c[N - 1];
+#pragma unroll
+  for (int k = N - 2; k >= 0; --k) r = __builtin_fma(r, t, c[k]);
+  return r;
+}
+// Clenshaw recurrence for a Chebyshev series sum c_k T_k(s)
+template <int N>
+__device__ __forceinline__ double clenshaw_d(const double (&c)[N], double s) {
+  double b1 = 0, b2 = 0, s2 = 2 * s;
+#pragma unroll
+  for (int k = N - 1; k >= 1; --k) {
+    double b0 = __builtin_fma(s2, b1, c[k] - b2);
+    b2 = b1; b1 = b0;
+  }
+  return __builtin_fma(s, b1, c[0] - b2);
+}
+
+// K0(x) and K1(x)/x for x > 0 in FP32.
+__device__ __forceinline__ void bessel_k01_f32(float x, float& k0, float& k1_over_x) {
+  if (x <= 2.0f) {
+    float t = 0.25f * x * x;
+    float lt = __logf(t);
+    float i0 = horner_f(KS_I0_F32, t), p0 = horner_f(KS_P0_F32, t);
+    float j1 = horner_f(KS_J1_F32, t), p1 = horner_f(KS_P1_F32, t);
+    k0 = p0 - 0.5f * lt * i0;
+    float xk1 = 1.0f + t * (lt * j1 - p1);
+    k1_over_x = xk1 * __builtin_amdgcn_rcpf(x * x);
+  } else {
+    float rx = __builtin_amdgcn_rcpf(x);
+    float u = 2.0f * rx;
+    float e = __expf(-x) * __builtin_amdgcn_rsqf(x);
+    k0 = e * horner_f(KL0_F32, u);
+    k1_over_x = e * rx * horner_f(KL1_F32, u);
+  }
+}
+
+// K0(x) and K1(x)/x for x > 0 in FP64.
+__device__ __forceinline__ void bessel_k01_f64(double x, double& k0, double& k1_over_x) {
+  if (x <= 2.0) {
+    double t = 0.25 * x * x;
+    double lt = log(t);
+    double i0 = horner_d(KS_I0_F64, t), p0 = horner_d(KS_P0_F64, t);
+    double j1 = horner_d(KS_J1_F64, t), p1 = horner_d(KS_P1_F64, t);
+    k0 = p0 - 0.5 * lt * i0;
+    double xk1 = 1.0 + t * (lt * j1 - p1);
+    k1_over_x = xk1 / (x * x);
+  } else {
+    double u = 2.0 / x;
+    double e = exp(-x) / sqrt(x);
+    k0 = e * clenshaw_d(KL0_F64, 2 * u - 1);
+    k1_over_x = e / x * clenshaw_d(KL1_F64, 2 * u - 1);
+  }
+}
+
+}  // namespace pfmm

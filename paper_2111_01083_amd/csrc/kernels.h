@@ -1,0 +1,86 @@
+// Kernel argument structs and launch helpers (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "pfmm_internal.h"
+
+namespace pfmm {
+
+constexpr int NEAR_BLOCK = 256;   // threads (= targets) per near-field block
+constexpr int NEAR_TILE = 256;    // sources per LDS tile
+constexpr int NEAR_FLUSH = 16;    // FP32 partial-sum length before an FP64 flush (mixed)
+constexpr int FAR_CHUNK = 2048;   // sources per far_R block
+
+struct PrepArgs {
+  int64_t n;
+  const double* xy;          // [2][n] user frame
+  double rc, rs, d, xi, eta;
+  double *cx, *cy;           // canonical FP64
+  float *hx, *lx, *hy, *ly;  // two-float copies (NULL unless mixed)
+};
+
+struct PrepDensArgs {
+  int64_t n;
+  int n_dens, stokes;
+  const double* dens;        // user densities
+  double rc, rs;
+  double* out64;             // Stokes: rotated forces
+  float* out32;              // FP32 copy (mixed), NULL otherwise
+};
+
+struct NearArgs {
+  Geometry geo;
+  int64_t n_src, n_trg, split_len;
+  const double *sx, *sy;                 // FP64 sources
+  const float *sxh, *sxl, *syh, *syl;    // two-float sources
+  const double* q64;                     // densities [n_dens][nc][n_src]
+  const float* q32;
+  int dens0;                             // first density of this launch
+  const double *tx, *ty;                 // FP64 targets
+  double beta;
+  double* part;                          // [split][n_dens*NOUT][n_trg]
+  size_t part_stride;                    // doubles per split
+};
+
+struct FarRArgs {
+  int kernel, n_sn, n_ew, ncw, n_coef, n_dens;
+  int64_t n_src;
+  const double* tab;         // sn records | ew records
+  const double *sx, *sy;     // canonical sources
+  const double* dens;        // canonical densities [n_dens][nc][n_src]
+  double* part;              // [chunk][n_dens][n_coef] complex (2 doubles)
+};
+
+struct FarDArgs {
+  int kernel, n_sn, n_ew, ncw, n_coef, n_dens, n_chunks;
+  double eta, xi;
+  const double* tab;
+  const double* part;
+  double* w;                 // [n_dens][n_coef] complex
+};
+
+struct FarLArgs {
+  int kernel, n_sn, n_ew, ncw, n_coef, n_dens, n_splits, nufft;
+  int64_t n_trg;
+  double d, eta, rc, rs;
+  const double* tab;
+  const double* w;
+  const double *tx, *ty;     // canonical targets
+  const double* near_part;   // [split][n_dens*NOUT][n_trg]
+  size_t part_stride;
+  const double* nu_val;      // NUFFT path: interpolated south/north field [n_dens*NOUT][n_trg]
+  double *out_pot, *out_grad;
+};
+
+// launchers (kernels.hip)
+void launch_prep_points(const PrepArgs& a, hipStream_t s);
+void launch_prep_dens(const PrepDensArgs& a, hipStream_t s);
+void launch_near(int kernel, bool mixed, int nd, const NearArgs& a, int n_splits, hipStream_t s);
+void launch_far_R(const FarRArgs& a, int n_chunks, hipStream_t s);
+void launch_far_D(const FarDArgs& a, hipStream_t s);
+void launch_far_L(const FarLArgs& a, hipStream_t s);
+
+inline int near_nout(int kernel) { return kernel == PFMM_STOKES ? 6 : 3; }
+
+}  // namespace pfmm

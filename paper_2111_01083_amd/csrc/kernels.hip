@@ -1,0 +1,660 @@
+// Device kernels of the periodic evaluator (gfx950):
+//   prep   -- rotate/wrap points into the canonical cell; two-float FP32 copies
+//   near   -- direct sum over the cell and its nearest images (Def. 1)
+//   far_R  -- sources -> plane-wave coefficients (R of P = L D R, Sec. 6)
+//   far_D  -- chunk reduction and the diagonal weights D
+//   far_L  -- plane waves -> targets; adds the near partials; user frame out
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "device_math.h"
+#include "kernels.h"
+
+namespace pfmm {
+
+// ---------------------------------------------------------------------------
+// prep
+// ---------------------------------------------------------------------------
+__global__ void prep_points_kernel(PrepArgs a) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  double x = a.xy[i], y = a.xy[a.n + i];
+  double xc = a.rc * x - a.rs * y, yc = a.rs * x + a.rc * y;
+  // lattice coordinates u2 = y/eta, u1 = (x - u2 xi)/d, then u <- u - rint(u)
+  double k2 = rint(yc / a.eta);
+  yc -= k2 * a.eta;
+  xc -= k2 * a.xi;
+  double k1 = rint((xc - (yc / a.eta) * a.xi) / a.d);
+  xc -= k1 * a.d;
+  a.cx[i] = xc;
+  a.cy[i] = yc;
+  if (a.hx) {
+    float xh = (float)xc, yh = (float)yc;
+    a.hx[i] = xh; a.lx[i] = (float)(xc - (double)xh);
+    a.hy[i] = yh; a.ly[i] = (float)(yc - (double)yh);
+  }
+}
+
+__global__ void prep_dens_kernel(PrepDensArgs a) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  for (int v = 0; v < a.n_dens; ++v) {
+    if (a.stokes) {
+      const double* f = a.dens + (size_t)v * 2 * a.n;
+      double f1 = f[i], f2 = f[a.n + i];
+      double g1 = a.rc * f1 - a.rs * f2, g2 = a.rs * f1 + a.rc * f2;
+      double* o = a.out64 + (size_t)v * 2 * a.n;
+      o[i] = g1; o[a.n + i] = g2;
+      if (a.out32) {
+        float* o32 = a.out32 + (size_t)v * 2 * a.n;
+        o32[i] = (float)g1; o32[a.n + i] = (float)g2;
+      }
+    } else if (a.out32) {
+      a.out32[(size_t)v * a.n + i] = (float)a.dens[(size_t)v * a.n + i];
+    }
+  }
+}
+
+void launch_prep_points(const PrepArgs& a, hipStream_t s) {
+  if (a.n <= 0) return;
+  int nb = (int)((a.n + 255) / 256);
+  hipLaunchKernelGGL(prep_points_kernel, dim3(nb), dim3(256), 0, s, a);
+}
+void launch_prep_dens(const PrepDensArgs& a, hipStream_t s) {
+  if (a.n <= 0) return;
+  int nb = (int)((a.n + 255) / 256);
+  hipLaunchKernelGGL(prep_dens_kernel, dim3(nb), dim3(256), 0, s, a);
+}
+
+// ---------------------------------------------------------------------------
+// near field. One target per thread; sources stream through LDS in tiles of
+// NEAR_TILE and each tile is reused for every image shift (applied to the
+// target). Block (x, y) = (target tile, source split); split y writes its
+// partial sums to part[y][dens*NOUT + c][n_trg] in FP64.
+//
+// MIXED: pair arithmetic in FP32. Coordinates are two-float (hi + lo) and
+// t - s = (t_hi - s_hi) + (t_lo - s_lo), which keeps the difference to a few
+// FP32 ulps of |t - s| even for the closest pairs; FP32 partial sums over one
+// NEAR_FLUSH sources of one image are flushed into FP64 accumulators (the
+// FP32 rounding error of a blocked sum grows like the block length).
+//
+// Accumulators per density:
+//   Laplace/Yukawa (3): sum q g(r), sum q h(r) dx, sum q h(r) dy
+//   Stokes (7): sum lg f1, sum lg f2, sum c dx, sum c dy, sum (c - e dx^2),
+//               sum (f2 dx - f1 dy)/r^2, sum e dx dy
+//     with lg = log r^2, c = (r.f)/r^2, e = 2c/r^2.
+// A pair at r = 0 (the excluded self term, or an exactly coincident image)
+// contributes nothing.
+// ---------------------------------------------------------------------------
+template <int K> struct NAcc { static constexpr int v = 3; };
+template <> struct NAcc<PFMM_STOKES> { static constexpr int v = 7; };
+
+template <int K, bool MIXED, int ND>
+__global__ __launch_bounds__(NEAR_BLOCK) void near_kernel(NearArgs a) {
+  using real = typename std::conditional<MIXED, float, double>::type;
+  constexpr int NC = (K == PFMM_STOKES) ? 2 : 1;
+  constexpr int NA = NAcc<K>::v;
+  constexpr int NO = (K == PFMM_STOKES) ? 6 : 3;
+  __shared__ real s_xh[NEAR_TILE], s_yh[NEAR_TILE];
+  __shared__ real s_xl[MIXED ? NEAR_TILE : 1], s_yl[MIXED ? NEAR_TILE : 1];
+  __shared__ real s_q[ND * NC][NEAR_TILE];
+
+  const int tid = threadIdx.x;
+  const int64_t it = (int64_t)blockIdx.x * NEAR_BLOCK + tid;
+  const bool active = it < a.n_trg;
+  const int64_t ti = active ? it : 0;
+  const double tx = a.n_trg > 0 ? a.tx[ti] : 0.0, ty = a.n_trg > 0 ? a.ty[ti] : 0.0;
+  const int64_t s0 = (int64_t)blockIdx.y * a.split_len;
+  const int64_t s1 = min(s0 + a.split_len, a.n_src);
+
+  double acc[ND][NA];
+#pragma unroll
+  for (int v = 0; v < ND; ++v)
+#pragma unroll
+    for (int c = 0; c < NA; ++c) acc[v][c] = 0.0;
+
+  const real beta = (real)a.beta;
+  for (int64_t base = s0; base < s1; base += NEAR_TILE) {
+    const int nt = (int)min((int64_t)NEAR_TILE, s1 - base);
+    __syncthreads();
+    if (tid < nt) {
+      const int64_t j = base + tid;
+      if constexpr (MIXED) {
+        s_xh[tid] = a.sxh[j]; s_xl[tid] = a.sxl[j];
+        s_yh[tid] = a.syh[j]; s_yl[tid] = a.syl[j];
+#pragma unroll
+        for (int v = 0; v < ND * NC; ++v) s_q[v][tid] = a.q32[(size_t)(a.dens0 * NC + v) * a.n_src + j];
+      } else {
+        s_xh[tid] = a.sx[j]; s_yh[tid] = a.sy[j];
+#pragma unroll
+        for (int v = 0; v < ND * NC; ++v) s_q[v][tid] = a.q64[(size_t)(a.dens0 * NC + v) * a.n_src + j];
+      }
+    }
+    __syncthreads();
+    for (int im = 0; im < a.geo.n_images; ++im) {
+      const double txi = tx - a.geo.img_x[im], tyi = ty - a.geo.img_y[im];
+      real txh, txl, tyh, tyl;
+      if constexpr (MIXED) {
+        txh = (real)txi; txl = (real)(txi - (double)txh);
+        tyh = (real)tyi; tyl = (real)(tyi - (double)tyh);
+      } else {
+        txh = txi; tyh = tyi; txl = 0; tyl = 0;
+      }
+      for (int jb = 0; jb < nt; jb += NEAR_FLUSH) {
+      const int je = min(jb + NEAR_FLUSH, nt);
+      real p[ND][NA];
+#pragma unroll
+      for (int v = 0; v < ND; ++v)
+#pragma unroll
+        for (int c = 0; c < NA; ++c) p[v][c] = 0;
+      for (int j = jb; j < je; ++j) {
+        real dx, dy;
+        if constexpr (MIXED) {
+          dx = (txh - s_xh[j]) + (txl - s_xl[j]);
+          dy = (tyh - s_yh[j]) + (tyl - s_yl[j]);
+        } else {
+          dx = txh - s_xh[j];
+          dy = tyh - s_yh[j];
+        }
+        const real r2 = dx * dx + dy * dy;
+        const bool ok = r2 > (real)0;
+        const real r2s = ok ? r2 : (real)1;
+        if constexpr (K == PFMM_YUKAWA) {
+          real k0, k1x;
+          if constexpr (MIXED) {
+            bessel_k01_f32(beta * __builtin_amdgcn_sqrtf(r2s), k0, k1x);
+          } else {
+            bessel_k01_f64(beta * sqrt(r2s), k0, k1x);
+          }
+          k0 = ok ? k0 : (real)0;
+          k1x = ok ? k1x : (real)0;
+          const real gx = k1x * dx, gy = k1x * dy;
+#pragma unroll
+          for (int v = 0; v < ND; ++v) {
+            const real q = s_q[v][j];
+            p[v][0] += q * k0; p[v][1] += q * gx; p[v][2] += q * gy;
+          }
+        } else {
+          real lg, inv;
+          if constexpr (MIXED) { lg = __builtin_amdgcn_logf(r2s); inv = __builtin_amdgcn_rcpf(r2s); }
+          else { lg = log(r2s); inv = 1.0 / r2s; }
+          lg = ok ? lg : (real)0;
+          inv = ok ? inv : (real)0;
+          const real ix = inv * dx, iy = inv * dy;
+          if constexpr (K == PFMM_LAPLACE) {
+#pragma unroll
+            for (int v = 0; v < ND; ++v) {
+              const real q = s_q[v][j];
+              p[v][0] += q * lg; p[v][1] += q * ix; p[v][2] += q * iy;
+            }
+          } else {
+#pragma unroll
+            for (int v = 0; v < ND; ++v) {
+              const real f1 = s_q[2 * v][j], f2 = s_q[2 * v + 1][j];
+              const real c = ix * f1 + iy * f2;
+              const real e2x = (c + c) * ix;
+              p[v][0] += lg * f1;
+              p[v][1] += lg * f2;
+              p[v][2] += c * dx;
+              p[v][3] += c * dy;
+              p[v][4] += c - e2x * dx;
+              p[v][5] += f2 * ix - f1 * iy;
+              p[v][6] += e2x * dy;
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < ND; ++v)
+#pragma unroll
+        for (int c = 0; c < NA; ++c) acc[v][c] += (double)p[v][c];
+      }
+    }
+  }
+  if (!active) return;
+  const double inv4pi = 1.0 / (4 * PI), inv2pi = 1.0 / (2 * PI);
+  const double lscale = MIXED ? 0.69314718055994530942 : 1.0;  // log2 -> ln
+  double* dst = a.part + (size_t)blockIdx.y * a.part_stride;
+#pragma unroll
+  for (int v = 0; v < ND; ++v) {
+    double o[NO];
+    if constexpr (K == PFMM_LAPLACE) {
+      o[0] = -inv4pi * lscale * acc[v][0];
+      o[1] = -inv2pi * acc[v][1];
+      o[2] = -inv2pi * acc[v][2];
+    } else if constexpr (K == PFMM_YUKAWA) {
+      o[0] = inv2pi * acc[v][0];
+      o[1] = -a.beta * a.beta * inv2pi * acc[v][1];
+      o[2] = -a.beta * a.beta * inv2pi * acc[v][2];
+    } else {
+      o[0] = inv4pi * (-0.5 * lscale * acc[v][0] + acc[v][2]);
+      o[1] = inv4pi * (-0.5 * lscale * acc[v][1] + acc[v][3]);
+      o[2] = inv4pi * acc[v][4];
+      o[3] = inv4pi * (acc[v][5] - acc[v][6]);
+      o[4] = inv4pi * (-acc[v][5] - acc[v][6]);
+      o[5] = -inv4pi * acc[v][4];
+    }
+#pragma unroll
+    for (int c = 0; c < NO; ++c) dst[(size_t)((a.dens0 + v) * NO + c) * a.n_trg + it] = o[c];
+  }
+}
+
+template <int K, bool MIXED>
+static void launch_near_k(int nd, const NearArgs& a, dim3 grid, hipStream_t s) {
+  NearArgs b = a;
+  int v = 0;
+  for (; v + 4 <= nd; v += 4) {
+    b.dens0 = v;
+    hipLaunchKernelGGL((near_kernel<K, MIXED, 4>), grid, dim3(NEAR_BLOCK), 0, s, b);
+  }
+  for (; v < nd; ++v) {
+    b.dens0 = v;
+    hipLaunchKernelGGL((near_kernel<K, MIXED, 1>), grid, dim3(NEAR_BLOCK), 0, s, b);
+  }
+}
+
+void launch_near(int kernel, bool mixed, int nd, const NearArgs& a, int n_splits, hipStream_t s) {
+  if (a.n_trg <= 0) return;
+  dim3 grid((unsigned)((a.n_trg + NEAR_BLOCK - 1) / NEAR_BLOCK), (unsigned)n_splits);
+  switch (kernel * 2 + (mixed ? 1 : 0)) {
+    case 0: launch_near_k<PFMM_LAPLACE, false>(nd, a, grid, s); break;
+    case 1: launch_near_k<PFMM_LAPLACE, true>(nd, a, grid, s); break;
+    case 2: launch_near_k<PFMM_YUKAWA, false>(nd, a, grid, s); break;
+    case 3: launch_near_k<PFMM_YUKAWA, true>(nd, a, grid, s); break;
+    case 4: launch_near_k<PFMM_STOKES, false>(nd, a, grid, s); break;
+    case 5: launch_near_k<PFMM_STOKES, true>(nd, a, grid, s); break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// far R: one thread per plane wave (south/north mode or west/east node; the
+// last wave index holds the y-moments of the Laplace/Stokes m = 0 term),
+// summing over one chunk of sources staged in LDS. FP64 throughout.
+//   south/north (Thm. south_thm, south_thm_lap, south_thm_s):
+//     c^S = sum q e^{a y - i alpha x},  c^N = sum q e^{-a y - i alpha x}
+//     Stokes also e^S = sum y f e^{a y - i alpha x} (and north alike)
+//   west/east (Thm. west_thm, west_thm_lap, west_thm_s):
+//     c^W = sum q e^{kappa x - i lambda y}, c^E = sum q e^{-kappa x - i lambda y}
+//     Laplace/Stokes use e^{...} - 1 (exact for neutral densities, and free of
+//     the O(1) cancellation at small lambda); Stokes also e^W = sum x f e^{...}
+// ---------------------------------------------------------------------------
+constexpr int FAR_R_BLOCK = 128;
+constexpr int FAR_R_TILE = 1024;
+
+struct cplx { double r, i; };
+__device__ __forceinline__ cplx cmul(cplx a, cplx b) { return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
+__device__ __forceinline__ cplx cadd(cplx a, cplx b) { return {a.r + b.r, a.i + b.i}; }
+__device__ __forceinline__ cplx csub(cplx a, cplx b) { return {a.r - b.r, a.i - b.i}; }
+__device__ __forceinline__ cplx cscale(cplx a, double s) { return {a.r * s, a.i * s}; }
+__device__ __forceinline__ cplx cconj(cplx a) { return {a.r, -a.i}; }
+__device__ __forceinline__ cplx cmuli(cplx a) { return {-a.i, a.r}; }  // i*a
+// e^{a + i b} - 1 without cancellation for small |a|, |b|
+__device__ __forceinline__ cplx cexpm1(double a, double b) {
+  double s, c;
+  sincos(b, &s, &c);
+  double sh = sin(0.5 * b);
+  return {expm1(a) * c - 2 * sh * sh, exp(a) * s};
+}
+
+template <int K>
+__global__ __launch_bounds__(FAR_R_BLOCK) void far_R_kernel(FarRArgs a) {
+  constexpr int NC = (K == PFMM_STOKES) ? 2 : 1;
+  constexpr int NCW = (K == PFMM_STOKES) ? 8 : 2;
+  __shared__ double s_x[FAR_R_TILE], s_y[FAR_R_TILE], s_q[NC][FAR_R_TILE];
+  const int v = blockIdx.z;
+  const int64_t j0 = (int64_t)blockIdx.y * FAR_CHUNK;
+  const int64_t j1 = min(j0 + FAR_CHUNK, a.n_src);
+  const int w = blockIdx.x * FAR_R_BLOCK + threadIdx.x;
+  const int n_w = a.n_sn + a.n_ew;
+  const bool is_sn = w < a.n_sn, is_ew = !is_sn && w < n_w, is_mom = w == n_w;
+  double par0 = 0, par1 = 0;
+  if (is_sn || is_ew) { par0 = a.tab[is_sn ? w * SN_REC : a.n_sn * SN_REC + (w - a.n_sn) * EW_REC];
+                        par1 = a.tab[(is_sn ? w * SN_REC : a.n_sn * SN_REC + (w - a.n_sn) * EW_REC) + 1]; }
+  cplx acc[NCW];
+#pragma unroll
+  for (int c = 0; c < NCW; ++c) acc[c] = {0, 0};
+  const double* dens = a.dens + (size_t)v * NC * a.n_src;
+  for (int64_t base = j0; base < j1; base += FAR_R_TILE) {
+    const int nt = (int)min((int64_t)FAR_R_TILE, j1 - base);
+    __syncthreads();
+    for (int t = threadIdx.x; t < nt; t += FAR_R_BLOCK) {
+      s_x[t] = a.sx[base + t]; s_y[t] = a.sy[base + t];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) s_q[c][t] = dens[(size_t)c * a.n_src + base + t];
+    }
+    __syncthreads();
+    if (is_sn) {
+      const double al = par0, aa = par1;
+      for (int t = 0; t < nt; ++t) {
+        const double x = s_x[t], y = s_y[t];
+        double sn, cs;
+        sincos(al * x, &sn, &cs);
+        const double ep = exp(aa * y), em = 1.0 / ep;
+        const cplx ph = {cs, -sn};
+        const cplx ps = cscale(ph, ep), pn = cscale(ph, em);
+        if constexpr (K == PFMM_STOKES) {
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            const double f = s_q[c][t];
+            acc[c] = cadd(acc[c], cscale(ps, f));
+            acc[2 + c] = cadd(acc[2 + c], cscale(ps, f * y));
+            acc[4 + c] = cadd(acc[4 + c], cscale(pn, f));
+            acc[6 + c] = cadd(acc[6 + c], cscale(pn, f * y));
+          }
+        } else {
+          const double q = s_q[0][t];
+          acc[0] = cadd(acc[0], cscale(ps, q));
+          acc[1] = cadd(acc[1], cscale(pn, q));
+        }
+      }
+    } else if (is_ew) {
+      const double lam = par0, kap = par1;
+      for (int t = 0; t < nt; ++t) {
+        const double x = s_x[t], y = s_y[t];
+        if constexpr (K == PFMM_YUKAWA) {
+          double sn, cs;
+          sincos(lam * y, &sn, &cs);
+          const double ep = exp(kap * x), em = 1.0 / ep;
+          const double q = s_q[0][t];
+          acc[0] = cadd(acc[0], cplx{q * ep * cs, -q * ep * sn});
+          acc[1] = cadd(acc[1], cplx{q * em * cs, -q * em * sn});
+        } else {
+          const cplx wm = cexpm1(lam * x, -lam * y);    // e^{lam(x - i y)} - 1
+          const cplx emm = cexpm1(-lam * x, -lam * y);  // e^{-lam(x + i y)} - 1
+          if constexpr (K == PFMM_LAPLACE) {
+            const double q = s_q[0][t];
+            acc[0] = cadd(acc[0], cscale(wm, q));
+            acc[1] = cadd(acc[1], cscale(emm, q));
+          } else {
+            const cplx wf = {wm.r + 1.0, wm.i}, ef = {emm.r + 1.0, emm.i};
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+              const double f = s_q[c][t];
+              acc[c] = cadd(acc[c], cscale(wm, f));
+              acc[2 + c] = cadd(acc[2 + c], cscale(wf, f * x));
+              acc[4 + c] = cadd(acc[4 + c], cscale(emm, f));
+              acc[6 + c] = cadd(acc[6 + c], cscale(ef, f * x));
+            }
+          }
+        }
+      }
+    } else if (is_mom && K != PFMM_YUKAWA) {
+      for (int t = 0; t < nt; ++t) {
+        const double y = s_y[t], q = s_q[0][t];
+        acc[0].r += q * y;
+        acc[0].i += q * y * y;
+      }
+    }
+  }
+  double* out = a.part + ((size_t)blockIdx.y * a.n_dens + v) * a.n_coef * 2;
+  if (is_sn || is_ew) {
+#pragma unroll
+    for (int c = 0; c < NCW; ++c) { out[2 * (w * NCW + c)] = acc[c].r; out[2 * (w * NCW + c) + 1] = acc[c].i; }
+  } else if (is_mom) {
+    out[2 * (n_w * NCW)] = acc[0].r;
+    out[2 * (n_w * NCW) + 1] = acc[0].i;
+  }
+}
+
+void launch_far_R(const FarRArgs& a, int n_chunks, hipStream_t s) {
+  int n_w = a.n_sn + a.n_ew + 1;
+  dim3 grid((unsigned)((n_w + FAR_R_BLOCK - 1) / FAR_R_BLOCK), (unsigned)n_chunks, (unsigned)a.n_dens);
+  switch (a.kernel) {
+    case PFMM_LAPLACE: hipLaunchKernelGGL(far_R_kernel<PFMM_LAPLACE>, grid, dim3(FAR_R_BLOCK), 0, s, a); break;
+    case PFMM_YUKAWA: hipLaunchKernelGGL(far_R_kernel<PFMM_YUKAWA>, grid, dim3(FAR_R_BLOCK), 0, s, a); break;
+    default: hipLaunchKernelGGL(far_R_kernel<PFMM_STOKES>, grid, dim3(FAR_R_BLOCK), 0, s, a); break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// far D: sum the chunk partials (fixed order) and apply the diagonal factors.
+//   scalar south/north: w^S = D c^S, w^N = conj(D) c^N  (D = fac T/(2 d a))
+//   scalar west/east:   tW = DW c^W, tE = DE c^E -> (tW + tE, tE - tW)
+//   Stokes south/north (Thm. south_thm_s, re-derived; M_S = [[1,i],[i,-1]],
+//     M_N = [[-1,i],[i,1]], D = fac T/(4d)):
+//     A_S = D (c^S/a - eta tau M_S c^S + M_S e^S), B_S = D M_S c^S
+//     A_N = conj(D)(c^N/a + eta conj(tau) M_N c^N + M_N e^N), B_N = conj(D) M_N c^N
+//   Stokes west/east (Thm. west_thm_s, re-derived; M_W = [[-1,i],[i,1]],
+//     M_E = [[1,i],[i,-1]], pre = w R/(4 pi)):
+//     A_W = pre((B/lam) c^W - dP B M_W c^W + B M_W e^W + xi B' M_W c^W), X_W = pre B M_W c^W
+//     A_E = pre((conj B/lam) c^E + dP conj(B) M_E c^E + conj(B) M_E e^E
+//               - xi conj(B') M_E c^E),  X_E = pre conj(B) M_E c^E
+//     stored as (A_W + A_E, A_E - A_W, X_W + X_E, X_E - X_W)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void mat_s(cplx c1, cplx c2, cplx& o1, cplx& o2) {  // [[1,i],[i,-1]]
+  o1 = cadd(c1, cmuli(c2));
+  o2 = csub(cmuli(c1), c2);
+}
+__device__ __forceinline__ void mat_n(cplx c1, cplx c2, cplx& o1, cplx& o2) {  // [[-1,i],[i,1]]
+  o1 = cadd(cscale(c1, -1.0), cmuli(c2));
+  o2 = cadd(cmuli(c1), c2);
+}
+
+__global__ void far_D_kernel(FarDArgs a) {
+  const int n_w = a.n_sn + a.n_ew;
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  const int v = blockIdx.y;
+  if (w > n_w) return;
+  const int ncw = a.ncw;
+  const int nsum = (w == n_w) ? 1 : ncw;
+  const int c0 = w * ncw;
+  cplx c[8];
+  for (int k = 0; k < nsum; ++k) {
+    double sr = 0, si = 0;
+    for (int ch = 0; ch < a.n_chunks; ++ch) {
+      const double* p = a.part + (((size_t)ch * a.n_dens + v) * a.n_coef + c0 + k) * 2;
+      sr += p[0]; si += p[1];
+    }
+    c[k] = {sr, si};
+  }
+  double* out = a.w + ((size_t)v * a.n_coef + c0) * 2;
+  cplx o[8];
+  if (w == n_w) {
+    out[0] = c[0].r; out[1] = c[0].i;
+    return;
+  }
+  if (w < a.n_sn) {
+    const double* r = a.tab + (size_t)w * SN_REC;
+    const double aa = r[1];
+    const cplx D = {r[2], r[3]}, tau = {r[4], r[5]};
+    if (a.kernel != PFMM_STOKES) {
+      o[0] = cmul(D, c[0]);
+      o[1] = cmul(cconj(D), c[1]);
+    } else {
+      cplx m1, m2, e1, e2;
+      mat_s(c[0], c[1], m1, m2);          // M_S c^S
+      mat_s(c[2], c[3], e1, e2);          // M_S e^S
+      const cplx et = cscale(tau, a.eta);
+      o[0] = cmul(D, cadd(csub(cscale(c[0], 1.0 / aa), cmul(et, m1)), e1));
+      o[1] = cmul(D, cadd(csub(cscale(c[1], 1.0 / aa), cmul(et, m2)), e2));
+      o[2] = cmul(D, m1);
+      o[3] = cmul(D, m2);
+      mat_n(c[4], c[5], m1, m2);          // M_N c^N
+      mat_n(c[6], c[7], e1, e2);          // M_N e^N
+      const cplx Dn = cconj(D), etn = cscale(cconj(tau), a.eta);
+      o[4] = cmul(Dn, cadd(cadd(cscale(c[4], 1.0 / aa), cmul(etn, m1)), e1));
+      o[5] = cmul(Dn, cadd(cadd(cscale(c[5], 1.0 / aa), cmul(etn, m2)), e2));
+      o[6] = cmul(Dn, m1);
+      o[7] = cmul(Dn, m2);
+    }
+  } else {
+    const double* r = a.tab + (size_t)a.n_sn * SN_REC + (size_t)(w - a.n_sn) * EW_REC;
+    if (a.kernel != PFMM_STOKES) {
+      const cplx DW = {r[2], r[3]}, DE = {r[4], r[5]};
+      const cplx tW = cmul(DW, c[0]), tE = cmul(DE, c[1]);
+      o[0] = cadd(tW, tE);
+      o[1] = csub(tE, tW);
+    } else {
+      const double lam = r[0], pre = r[2], dP = r[7];
+      const cplx B = {r[3], r[4]}, Bp = {r[5], r[6]};
+      const cplx Bc = cconj(B), Bpc = cconj(Bp);
+      cplx mw1, mw2, ew1, ew2, me1, me2, ee1, ee2;
+      mat_n(c[0], c[1], mw1, mw2);        // M_W c^W  (M_W = [[-1,i],[i,1]])
+      mat_n(c[2], c[3], ew1, ew2);        // M_W e^W
+      mat_s(c[4], c[5], me1, me2);        // M_E c^E  (M_E = [[1,i],[i,-1]])
+      mat_s(c[6], c[7], ee1, ee2);        // M_E e^E
+      const cplx mw[2] = {mw1, mw2}, ew[2] = {ew1, ew2}, me[2] = {me1, me2}, ee[2] = {ee1, ee2};
+      for (int k = 0; k < 2; ++k) {
+        cplx AW = cmul(B, cscale(c[k], 1.0 / lam));
+        AW = csub(AW, cscale(cmul(B, mw[k]), dP));
+        AW = cadd(AW, cmul(B, ew[k]));
+        AW = cadd(AW, cscale(cmul(Bp, mw[k]), a.xi));
+        AW = cscale(AW, pre);
+        const cplx XW = cscale(cmul(B, mw[k]), pre);
+        cplx AE = cmul(Bc, cscale(c[4 + k], 1.0 / lam));
+        AE = cadd(AE, cscale(cmul(Bc, me[k]), dP));
+        AE = cadd(AE, cmul(Bc, ee[k]));
+        AE = csub(AE, cscale(cmul(Bpc, me[k]), a.xi));
+        AE = cscale(AE, pre);
+        const cplx XE = cscale(cmul(Bc, me[k]), pre);
+        o[k] = cadd(AW, AE);
+        o[2 + k] = csub(AE, AW);
+        o[4 + k] = cadd(XW, XE);
+        o[6 + k] = csub(XE, XW);
+      }
+    }
+  }
+  for (int k = 0; k < ncw; ++k) { out[2 * k] = o[k].r; out[2 * k + 1] = o[k].i; }
+}
+
+void launch_far_D(const FarDArgs& a, hipStream_t s) {
+  int n = a.n_sn + a.n_ew + 1;
+  dim3 grid((unsigned)((n + 63) / 64), (unsigned)a.n_dens);
+  hipLaunchKernelGGL(far_D_kernel, grid, dim3(64), 0, s, a);
+}
+
+// ---------------------------------------------------------------------------
+// far L (+ combine): per target, sum the plane waves, add the near partials
+// of every split in fixed order, rotate back to the user frame and write.
+//   scalar south/north: u += Re[(w^S e^{-a y} + w^N e^{a y}) e^{i alpha x}]
+//   scalar west/east:   u += Re[e^{i lam y}(cosh(kap x) S + sinh(kap x) D)]
+//   Laplace m = 0 (Thm. south_thm_lap and corollary, plus the zero-mean
+//   constant):          u += -y P_y/(d eta) + sum q y^2/(2 d eta)
+//   Stokes: the same waves times (A - y B) (south/north) or (A - x X)
+//   (west/east); m = 0 acts on u1 only, like Laplace with q = f1.
+// ---------------------------------------------------------------------------
+template <int K>
+__global__ __launch_bounds__(256) void far_L_kernel(FarLArgs a) {
+  constexpr int NO = (K == PFMM_STOKES) ? 6 : 3;
+  constexpr int NCW = (K == PFMM_STOKES) ? 8 : 2;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n_trg) return;
+  const double x = a.tx[i], y = a.ty[i];
+  const double* sn_tab = a.tab;
+  const double* ew_tab = a.tab + (size_t)a.n_sn * SN_REC;
+  for (int v = 0; v < a.n_dens; ++v) {
+    const cplx* w = reinterpret_cast<const cplx*>(a.w) + (size_t)v * a.n_coef;
+    double o[NO];
+#pragma unroll
+    for (int c = 0; c < NO; ++c) o[c] = 0;
+    if (!a.nufft) {
+      for (int m = 0; m < a.n_sn; ++m) {
+        const double al = sn_tab[m * SN_REC], aa = sn_tab[m * SN_REC + 1];
+        double sn, cs;
+        sincos(al * x, &sn, &cs);
+        const double ep = exp(aa * y), em = 1.0 / ep;
+        const cplx ph = {cs, sn};
+        const cplx* ww = w + m * NCW;
+        if constexpr (K == PFMM_STOKES) {
+          const cplx LS = cscale(ph, em), LN = cscale(ph, ep);
+          for (int k = 0; k < 2; ++k) {
+            const cplx uS = cmul(LS, csub(ww[k], cscale(ww[2 + k], y)));
+            const cplx uN = cmul(LN, csub(ww[4 + k], cscale(ww[6 + k], y)));
+            const cplx u = cadd(uS, uN);
+            o[k] += u.r;
+            o[2 + 2 * k] += -al * u.i;                       // Re(i alpha u)
+            const cplx dy = csub(cscale(uN, aa), cscale(uS, aa));
+            o[3 + 2 * k] += dy.r - cmul(LS, ww[2 + k]).r - cmul(LN, ww[6 + k]).r;
+          }
+        } else {
+          const cplx s = cscale(ww[0], em), n = cscale(ww[1], ep);
+          const cplx u = cmul(cadd(s, n), ph);
+          o[0] += u.r;
+          o[1] += -al * u.i;
+          o[2] += aa * cmul(csub(n, s), ph).r;
+        }
+      }
+    }
+    for (int k = 0; k < a.n_ew; ++k) {
+      const double lam = ew_tab[k * EW_REC], kap = ew_tab[k * EW_REC + 1];
+      double sn, cs;
+      sincos(lam * y, &sn, &cs);
+      const double ep = exp(kap * x), em = 1.0 / ep;
+      const double ch = 0.5 * (ep + em), sh = 0.5 * (ep - em);
+      const cplx ph = {cs, sn};
+      const cplx* ww = w + (a.n_sn + k) * NCW;
+      if constexpr (K == PFMM_STOKES) {
+        for (int c = 0; c < 2; ++c) {
+          const cplx SA = csub(ww[c], cscale(ww[4 + c], x));    // SigmaA - x SigmaX
+          const cplx DA = csub(ww[2 + c], cscale(ww[6 + c], x));// DeltaA - x DeltaX
+          const cplx U = cadd(cscale(SA, ch), cscale(DA, sh));
+          const cplx u = cmul(ph, U);
+          o[c] += u.r;
+          cplx G = cadd(cscale(SA, kap * sh), cscale(DA, kap * ch));
+          G = csub(G, cadd(cscale(ww[4 + c], ch), cscale(ww[6 + c], sh)));
+          o[2 + 2 * c] += cmul(ph, G).r;
+          o[3 + 2 * c] += -lam * u.i;
+        }
+      } else {
+        const cplx U = cadd(cscale(ww[0], ch), cscale(ww[1], sh));
+        const cplx u = cmul(ph, U);
+        o[0] += u.r;
+        o[1] += kap * cmul(ph, cadd(cscale(ww[0], sh), cscale(ww[1], ch))).r;
+        o[2] += -lam * u.i;
+      }
+    }
+    if constexpr (K != PFMM_YUKAWA) {
+      const cplx mom = w[(a.n_sn + a.n_ew) * NCW];
+      const double de = a.d * a.eta;
+      o[0] += -y * mom.r / de + mom.i / (2 * de);
+      o[K == PFMM_STOKES ? 3 : 2] += -mom.r / de;
+    }
+    if (a.nufft) {
+#pragma unroll
+      for (int c = 0; c < NO; ++c) o[c] += a.nu_val[((size_t)v * NO + c) * a.n_trg + i];
+    }
+    for (int s = 0; s < a.n_splits; ++s) {
+      const double* p = a.near_part + (size_t)s * a.part_stride;
+#pragma unroll
+      for (int c = 0; c < NO; ++c) o[c] += p[((size_t)v * NO + c) * a.n_trg + i];
+    }
+    // back to the user frame: user = R^T canonical
+    const double rc = a.rc, rs = a.rs;
+    if constexpr (K == PFMM_STOKES) {
+      const double u1 = rc * o[0] + rs * o[1], u2 = -rs * o[0] + rc * o[1];
+      // J_user = R^T J R,  J = [[o2, o3], [o4, o5]]
+      const double j11 = o[2], j12 = o[3], j21 = o[4], j22 = o[5];
+      const double t11 = rc * j11 + rs * j21, t12 = rc * j12 + rs * j22;   // R^T J
+      const double t21 = -rs * j11 + rc * j21, t22 = -rs * j12 + rc * j22;
+      const double g11 = t11 * rc + t12 * rs, g12 = -t11 * rs + t12 * rc; // (R^T J) R
+      const double g21 = t21 * rc + t22 * rs, g22 = -t21 * rs + t22 * rc;
+      if (a.out_pot) {
+        a.out_pot[((size_t)v * 2) * a.n_trg + i] = u1;
+        a.out_pot[((size_t)v * 2 + 1) * a.n_trg + i] = u2;
+      }
+      if (a.out_grad) {
+        double* g = a.out_grad + (size_t)v * 4 * a.n_trg;
+        g[i] = g11; g[a.n_trg + i] = g12; g[2 * a.n_trg + i] = g21; g[3 * a.n_trg + i] = g22;
+      }
+    } else {
+      if (a.out_pot) a.out_pot[(size_t)v * a.n_trg + i] = o[0];
+      if (a.out_grad) {
+        a.out_grad[((size_t)v * 2) * a.n_trg + i] = rc * o[1] + rs * o[2];
+        a.out_grad[((size_t)v * 2 + 1) * a.n_trg + i] = -rs * o[1] + rc * o[2];
+      }
+    }
+  }
+}
+
+void launch_far_L(const FarLArgs& a, hipStream_t s) {
+  if (a.n_trg <= 0) return;
+  dim3 grid((unsigned)((a.n_trg + 255) / 256));
+  switch (a.kernel) {
+    case PFMM_LAPLACE: hipLaunchKernelGGL(far_L_kernel<PFMM_LAPLACE>, grid, dim3(256), 0, s, a); break;
+    case PFMM_YUKAWA: hipLaunchKernelGGL(far_L_kernel<PFMM_YUKAWA>, grid, dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL(far_L_kernel<PFMM_STOKES>, grid, dim3(256), 0, s, a); break;
+  }
+}
+
+}  // namespace pfmm

@@ -1,0 +1,82 @@
+// Internal plan structure and table layouts shared by the host planner and
+// the device kernels of libpfmm. Not part of the public ABI.
+#pragma once
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "pfmm.h"
+
+namespace pfmm {
+
+constexpr double PI = 3.14159265358979323846;
+constexpr int MAX_IMAGES = 21;   // (2 m0 + 1) * 3 with m0 <= 3
+
+// Near-field image shifts and canonical lattice, passed to kernels by value.
+struct Geometry {
+  double d, xi, eta;             // canonical lattice e1 = (d,0), e2 = (xi,eta)
+  double rc, rs;                 // canonical = R * user, R = [[rc,-rs],[rs,rc]]
+  int n_images;
+  double img_x[MAX_IMAGES], img_y[MAX_IMAGES];
+};
+
+// Per south/north mode record (doubles), mode index m = m_lo + i:
+//   [0] alpha_m = 2 pi m / d        [1] a_m (chi_m for Yukawa, |alpha_m| otherwise)
+//   [2] Dr  [3] Di : scalar kernels  fac * T_m / (2 d a_m),  T_m = e^{-2Q}/(1-e^{-Q})
+//                    Stokes          fac * T_m / (4 d)
+//   [4] tau_r [5] tau_i : Stokes (2 - e^{-Q})/(1 - e^{-Q}); unused otherwise
+//   fac = 1 for m = 0, 2 otherwise (modes -m are conjugates for real densities)
+constexpr int SN_REC = 6;
+// Per west/east node record (doubles):
+//   [0] lambda  [1] kappa (sqrt(lambda^2+beta^2) for Yukawa, lambda otherwise)
+//   scalar kernels: [2..3] DW = w R B/(2 pi kappa)  [4..5] DE = w R conj(B)/(2 pi kappa)
+//   Stokes:         [2] pre = w R/(4 pi)  [3..4] B  [5..6] B' [7] d P
+//   R = e^{-p kappa d}/(1-e^{-kappa d}), p = m0+1,
+//   B = e^{-kappa xi + i lambda eta} + e^{kappa xi - i lambda eta} + 1,
+//   B' = -e^{-lambda xi + i lambda eta} + e^{lambda xi - i lambda eta},
+//   P = (p - (p-1) e^{-lambda d})/(1 - e^{-lambda d})
+constexpr int EW_REC = 8;
+
+// complex coefficients per wave (mode or node) and density:
+//   scalar kernels: 2 (south|west, north|east)
+//   Stokes: 8 = {c(2), e(2)} for south|west, then north|east
+inline int coef_per_wave(int kernel) { return kernel == PFMM_STOKES ? 8 : 2; }
+
+struct NufftParams {
+  int m_gl;        // Gauss-Legendre lines in y
+  int nf;          // fine grid points per period d
+  int w;           // spreading kernel width (grid points)
+  double es_beta;  // exponential-of-semicircle kernel shape parameter
+};
+
+}  // namespace pfmm
+
+struct pfmm_plan_s {
+  int kernel, precision, far_mode, m0, n_dens, self_exclude, check_neutral, profile;
+  double beta, tol, eps;
+  pfmm::Geometry geo;
+  int M, m_lo, n_sn;           // south/north modes m = m_lo..M
+  int n_ew;                    // west/east nodes
+  std::vector<double> sn_tab;  // n_sn * SN_REC
+  std::vector<double> ew_tab;  // n_ew * EW_REC
+  std::vector<double> ew_nodes, ew_weights;
+  // NUFFT path
+  int use_nufft;
+  pfmm::NufftParams nu;
+  std::vector<double> gl_nodes;    // ybar_k on [-eta/2, eta/2]
+  std::vector<double> gl_bary;     // barycentric weights sigma_k
+  std::vector<double> nu_deconv;   // 1/phihat(m) for m = 0..M (real, even kernel)
+  // device copies (per device, uploaded lazily)
+  int dev_id;
+  double* d_tab;               // sn_tab | ew_tab | gl_nodes | gl_bary | nu_deconv
+  size_t tab_doubles;
+  // profiling: event triples (start, near done, end) of evaluations not yet read
+  std::vector<void*> prof_events;
+};
+
+namespace pfmm {
+// host planner (plan.cpp)
+int build_plan(int kernel, const double* e1, const double* e2, double tol,
+               const pfmm_opts* opts, pfmm_plan_s* p);
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
+}  // namespace pfmm

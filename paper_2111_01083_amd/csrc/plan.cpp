@@ -1,0 +1,266 @@
+// Host-side planning: lattice canonicalisation, truncation sizes, the
+// west/east quadrature rule, the diagonal weights D of the low-rank
+// factorisations, and NUFFT parameters. No device work happens here.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+
+#include "pfmm_internal.h"
+
+namespace pfmm {
+
+using cd = std::complex<double>;
+
+// Gauss-Legendre nodes/weights on [-1, 1] by Newton iteration on P_n.
+static void legendre(int n, double t, double& pn, double& dpn) {
+  double p0 = 1, p1 = t;
+  for (int k = 2; k <= n; ++k) {
+    double p2 = ((2 * k - 1) * t * p1 - (k - 1) * p0) / k;
+    p0 = p1; p1 = p2;
+  }
+  pn = (n == 0) ? 1.0 : p1;
+  double pm = (n <= 1) ? 1.0 : p0;
+  dpn = (n == 0) ? 0.0 : n * (t * pn - pm) / (t * t - 1);
+}
+
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double t = std::cos(PI * (i + 0.75) / (n + 0.5)), pn, dp;
+    for (int it = 0; it < 100; ++it) {
+      legendre(n, t, pn, dp);
+      double dt = pn / dp;
+      t -= dt;
+      if (std::fabs(dt) < 4e-16) break;
+    }
+    legendre(n, t, pn, dp);
+    x[n - 1 - i] = t;
+    w[n - 1 - i] = 2.0 / ((1 - t * t) * dp * dp);
+  }
+}
+
+namespace {
+
+// Gauss-Lagrange reduction of a 2D lattice basis; returns b1 (shortest) and
+// b2 with |b1| <= |b2| and |b1.b2| <= |b1|^2/2.
+void reduce_basis(double b1[2], double b2[2]) {
+  auto dot = [](const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1]; };
+  for (int it = 0; it < 200; ++it) {
+    if (dot(b2, b2) < dot(b1, b1)) { std::swap(b1[0], b2[0]); std::swap(b1[1], b2[1]); }
+    double mu = std::nearbyint(dot(b1, b2) / dot(b1, b1));
+    if (mu == 0) break;
+    b2[0] -= mu * b1[0]; b2[1] -= mu * b1[1];
+  }
+  if (dot(b2, b2) < dot(b1, b1)) { std::swap(b1[0], b2[0]); std::swap(b1[1], b2[1]); }
+}
+
+// West/east rule (Thm. west_thm and its Laplace/Stokes limits): the paper's
+// generalized Gaussian tables are not published, so the rule is built here
+// from Gauss-Legendre panels. The integrand decays like e^{-kappa X} with
+// X >= Xmin = m0 d - 2|xi| (closest west/east image), oscillates like
+// e^{i lambda Y} with |Y| <= 2 eta, and its factor 1/(1-e^{-kappa d}) has
+// poles at kappa d = 2 pi i k, so panels are at most 2 min(pi/2eta, pi/d)
+// wide; for Yukawa with small beta the branch point at lambda = i beta gets
+// dyadic panels near 0 (same recipe as the singly periodic rule of Sec. 3).
+void ew_rule(int kernel, double beta, double d, double xi, double eta, int m0, double eps,
+             std::vector<double>& nodes, std::vector<double>& wts) {
+  nodes.clear(); wts.clear();
+  const double Xmin = m0 * d - 2 * std::fabs(xi);
+  const double lk = (std::log(1.0 / eps) + 2.0) / Xmin;
+  double L;
+  if (kernel == PFMM_YUKAWA) {
+    if (lk <= beta) return;  // whole west/east contribution below eps
+    L = std::sqrt(lk * lk - beta * beta);
+  } else {
+    L = lk;
+  }
+  // 12/16/20 Gauss-Legendre points per panel reach eps for eps >= 1e-8 / 1e-12 / below
+  const int np = eps >= 1e-8 ? 12 : (eps >= 1e-12 ? 16 : 20);
+  const double h0 = 2.0 * std::min(PI / (2 * eta), PI / d);
+  std::vector<double> edges{0.0};
+  if (kernel == PFMM_YUKAWA && beta < h0) {
+    double b = std::max(beta, 1e-300);
+    edges.push_back(std::min(b, L));
+    while (edges.back() * 2 < std::min(h0, L)) edges.push_back(edges.back() * 2);
+  }
+  double start = edges.back();
+  if (start < L) {
+    int n = std::max(1, (int)std::ceil((L - start) / h0));
+    double h = (L - start) / n;
+    for (int i = 1; i <= n; ++i) edges.push_back(start + i * h);
+  }
+  std::vector<double> gx, gw;
+  gauss_legendre(np, gx, gw);
+  for (size_t e = 0; e + 1 < edges.size(); ++e) {
+    double a = edges[e], b = edges[e + 1];
+    for (int i = 0; i < np; ++i) {
+      nodes.push_back(0.5 * (b - a) * (gx[i] + 1) + a);
+      wts.push_back(0.5 * (b - a) * gw[i]);
+    }
+  }
+}
+
+}  // namespace
+
+int build_plan(int kernel, const double* e1, const double* e2, double tol, const pfmm_opts* opts,
+               pfmm_plan_s* p) {
+  if (kernel < 0 || kernel > 2) return PFMM_EINVAL;
+  if (!e1 || !e2) return PFMM_EINVAL;
+  for (int i = 0; i < 2; ++i)
+    if (!std::isfinite(e1[i]) || !std::isfinite(e2[i])) return PFMM_EINVAL_LATTICE;
+  double det = e1[0] * e2[1] - e1[1] * e2[0];
+  double scale = std::max(std::hypot(e1[0], e1[1]), std::hypot(e2[0], e2[1]));
+  if (!(std::fabs(det) > 1e-12 * scale * scale)) return PFMM_EINVAL_LATTICE;
+  if (!(tol >= 1e-14 && tol <= 1e-2)) return PFMM_EINVAL_TOL;
+
+  pfmm_opts o{};
+  o.n_dens = 1;
+  if (opts) o = *opts;
+  if (o.n_dens < 1 || o.n_dens > 64) return PFMM_EINVAL;
+  if (kernel == PFMM_YUKAWA && !(o.beta > 0 && std::isfinite(o.beta))) return PFMM_EINVAL;
+  if (o.precision != PFMM_FP64 && o.precision != PFMM_MIXED) return PFMM_EINVAL;
+  if (o.far_mode < 0 || o.far_mode > 2) return PFMM_EINVAL;
+  if (o.m0 < 0 || o.m0 > 3 || o.m_gl < 0 || o.m_gl > 32) return PFMM_EINVAL;
+
+  p->kernel = kernel;
+  p->precision = o.precision;
+  p->n_dens = o.n_dens;
+  p->self_exclude = o.self_exclude ? 1 : 0;
+  p->check_neutral = o.check_neutral ? 1 : 0;
+  p->profile = o.profile ? 1 : 0;
+  p->beta = kernel == PFMM_YUKAWA ? o.beta : 0.0;
+  p->tol = tol;
+  p->eps = tol / 10;
+
+  // --- canonical lattice (Sec. 1): e1 = (d, 0) the longer reduced vector,
+  // e2 = (xi, eta) with eta > 0 and |xi| <= d/2.
+  double b1[2] = {e1[0], e1[1]}, b2[2] = {e2[0], e2[1]};
+  reduce_basis(b1, b2);
+  const double d = std::hypot(b2[0], b2[1]);
+  const double rc = b2[0] / d, rs = -b2[1] / d;  // R rotates b2 onto +x
+  double xi = rc * b1[0] - rs * b1[1];
+  double eta = rs * b1[0] + rc * b1[1];
+  if (eta < 0) { xi = -xi; eta = -eta; }
+  xi -= d * std::nearbyint(xi / d);
+  pfmm::Geometry& g = p->geo;
+  g.d = d; g.xi = xi; g.eta = eta; g.rc = rc; g.rs = rs;
+
+  // --- near region (Def. 1): m0 = 1 keeps the closest west/east image at
+  // x-distance >= d - 2|xi| (Thm. west_thm proof); require that to be >= d/2.
+  int m0 = std::fabs(xi) <= 0.25 * d ? 1 : 2;
+  if (o.m0 > 0) m0 = std::max(m0, o.m0);
+  p->m0 = m0;
+  g.n_images = 0;
+  for (int n = -1; n <= 1; ++n)
+    for (int m = -m0; m <= m0; ++m) {
+      g.img_x[g.n_images] = m * d + n * xi;
+      g.img_y[g.n_images] = n * eta;
+      ++g.n_images;
+    }
+
+  const double eps = p->eps;
+  const double beta = p->beta;
+  // --- south/north truncation (eq. mpk0s)
+  int M = (int)std::ceil(d / (2 * PI * eta) * std::log(1.0 / ((1 - std::exp(-2 * PI * eta / d)) * eps)));
+  M = std::max(M, 1);
+  p->m_lo = kernel == PFMM_YUKAWA ? 0 : 1;
+  // for Yukawa, drop modes whose whole contribution e^{-chi_m eta} is below eps
+  if (kernel == PFMM_YUKAWA) {
+    while (M > 0) {
+      double al = 2 * PI * M / d, chi = std::sqrt(al * al + beta * beta);
+      if (chi * eta > std::log(1.0 / eps) + 3) --M; else break;
+    }
+  }
+  p->M = M;
+  p->n_sn = std::max(0, M - p->m_lo + 1);
+  p->sn_tab.assign((size_t)p->n_sn * SN_REC, 0.0);
+  for (int i = 0; i < p->n_sn; ++i) {
+    int m = p->m_lo + i;
+    double al = 2 * PI * m / d;
+    double a = kernel == PFMM_YUKAWA ? std::sqrt(al * al + beta * beta) : std::fabs(al);
+    cd Q(a * eta, -al * xi);
+    cd eQ = std::exp(-Q);
+    cd T = eQ * eQ / (1.0 - eQ);                  // sum_{p>=2} e^{-pQ}
+    double fac = (m == 0) ? 1.0 : 2.0;
+    cd D = (kernel == PFMM_STOKES) ? fac * T / (4 * d) : fac * T / (2 * d * a);
+    cd tau = (2.0 - eQ) / (1.0 - eQ);
+    double* r = &p->sn_tab[(size_t)i * SN_REC];
+    r[0] = al; r[1] = a; r[2] = D.real(); r[3] = D.imag(); r[4] = tau.real(); r[5] = tau.imag();
+  }
+
+  // --- west/east rule and weights
+  ew_rule(kernel, beta, d, xi, eta, m0, eps, p->ew_nodes, p->ew_weights);
+  p->n_ew = (int)p->ew_nodes.size();
+  p->ew_tab.assign((size_t)p->n_ew * EW_REC, 0.0);
+  const int pp = m0 + 1;
+  for (int k = 0; k < p->n_ew; ++k) {
+    double lam = p->ew_nodes[k], w = p->ew_weights[k];
+    double kap = kernel == PFMM_YUKAWA ? std::sqrt(lam * lam + beta * beta) : lam;
+    double R = std::exp(-pp * kap * d) / (-std::expm1(-kap * d));
+    cd B = std::exp(cd(-kap * xi, lam * eta)) + std::exp(cd(kap * xi, -lam * eta)) + 1.0;
+    double* r = &p->ew_tab[(size_t)k * EW_REC];
+    r[0] = lam; r[1] = kap;
+    if (kernel == PFMM_STOKES) {
+      cd Bp = -std::exp(cd(-lam * xi, lam * eta)) + std::exp(cd(lam * xi, -lam * eta));
+      double e = std::exp(-lam * d);
+      double P = (pp - (pp - 1) * e) / (-std::expm1(-lam * d));
+      r[2] = w * R / (4 * PI); r[3] = B.real(); r[4] = B.imag(); r[5] = Bp.real(); r[6] = Bp.imag();
+      r[7] = d * P;
+    } else {
+      cd DW = w * R * B / (2 * PI * kap), DE = w * R * std::conj(B) / (2 * PI * kap);
+      r[2] = DW.real(); r[3] = DW.imag(); r[4] = DE.real(); r[5] = DE.imag();
+    }
+  }
+
+  // --- far mode and NUFFT parameters (Sec. 6.1)
+  int far = o.far_mode;
+  if (far == PFMM_FAR_AUTO) far = (2 * M + 1 >= 256) ? PFMM_FAR_NUFFT : PFMM_FAR_DIRECT;
+  p->far_mode = far;
+  p->use_nufft = far == PFMM_FAR_NUFFT;
+  int mgl = o.m_gl;
+  if (mgl == 0) mgl = eps >= 1e-7 ? 8 : (eps >= 1e-10 ? 12 : 16);  // rho0^-M_GL, rho0 = 3+sqrt 8
+  p->nu.m_gl = mgl;
+  {
+    double lg = std::log10(1.0 / eps);
+    int w = (int)std::ceil(lg) + 1;
+    w = std::max(4, std::min(w, 16));
+    int nf = 16;
+    while (nf < 2 * (2 * M + 1) || nf < 2 * w) nf *= 2;
+    p->nu.w = w;
+    p->nu.nf = nf;
+    p->nu.es_beta = 2.30 * w;
+  }
+  std::vector<double> tx, tw;
+  gauss_legendre(mgl, tx, tw);
+  p->gl_nodes.resize(mgl);
+  p->gl_bary.resize(mgl);
+  for (int k = 0; k < mgl; ++k) {
+    p->gl_nodes[k] = 0.5 * eta * tx[k];
+    double s = 1;
+    for (int j = 0; j < mgl; ++j)
+      if (j != k) s *= (tx[k] - tx[j]);
+    p->gl_bary[k] = 1.0 / s;
+  }
+  // Fourier transform of the spreading kernel phi(z) = exp(b(sqrt(1-z^2)-1))
+  // on |z| <= 1, scaled to half-width s = w h/2: Phi(alpha) = (w/2) int phi(z) cos(alpha s z) dz
+  p->nu_deconv.assign(M + 1, 0.0);
+  {
+    std::vector<double> qx, qw;
+    gauss_legendre(2 * p->nu.w + 40, qx, qw);
+    const double h = d / p->nu.nf, s = p->nu.w * h / 2, b = p->nu.es_beta;
+    for (int m = 0; m <= M; ++m) {
+      double al = 2 * PI * m / d, acc = 0;
+      for (size_t i = 0; i < qx.size(); ++i)
+        acc += qw[i] * std::exp(b * (std::sqrt(1 - qx[i] * qx[i]) - 1)) * std::cos(al * s * qx[i]);
+      p->nu_deconv[m] = 1.0 / (0.5 * p->nu.w * acc);
+    }
+  }
+  p->dev_id = -1;
+  p->d_tab = nullptr;
+  p->tab_doubles = 0;
+  return PFMM_OK;
+}
+
+}  // namespace pfmm
