@@ -36,7 +36,8 @@
  *    neutral (sum_j q_j = 0, eq. chargeneutral; sum_j f_j = 0 for Stokes).
  *  - self_exclude = 1 means target i IS source i (n_trg == n_src and the
  *    same coordinates): the term (j = i, zero lattice vector) is left out.
- *    Any other exactly coincident target/source-image pair contributes 0.
+ *    A target that coincides exactly with another source or source image
+ *    is a singularity of the sum; such inputs are not supported.
  *  - Evaluation is asynchronous on the caller's HIP stream; nothing is
  *    allocated inside pfmm_eval. Scratch memory comes from `workspace`,
  *    of at least pfmm_workspace_bytes() bytes, 256-byte aligned.

@@ -22,6 +22,9 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 // Workspace carve-up for one cell; offsets in bytes from the workspace base.
 struct Layout {
   size_t scx, scy, tcx, tcy, sxh, sxl, syh, syl, q32, dens_c, near_part, far_part, w, nufft;
+  size_t key, perm, stx, sty, hist, cursor;   // target binning
+  int nbx, nby;
+  double bin_w, bin_h;
   size_t total;
   int n_splits, n_chunks, n_coef;
   int64_t split_len;
@@ -45,6 +48,18 @@ void plan_layout(const pfmm_plan_s* p, int64_t ns, int64_t nt, Layout& L) {
     L.sxh = L.sxl = L.syh = L.syl = L.q32 = 0;
   }
   L.dens_c = p->kernel == PFMM_STOKES ? take(8 * (size_t)p->n_dens * 2 * ns) : 0;
+  // target bins of about 64 points over the canonical cell's bounding box
+  {
+    const double W = p->geo.d + std::fabs(p->geo.xi), H = p->geo.eta;
+    const double nb = std::max(1.0, std::min((double)nt / 64.0, 4.0e6));
+    const double h = std::sqrt(W * H / nb);
+    L.nbx = std::max(1, (int)std::ceil(W / h));
+    L.nby = std::max(1, (int)std::ceil(H / h));
+    L.bin_w = W / L.nbx;
+    L.bin_h = H / L.nby;
+    L.key = take(4 * nt); L.perm = take(4 * nt); L.stx = take(8 * nt); L.sty = take(8 * nt);
+    L.hist = take(4 * (size_t)L.nbx * L.nby); L.cursor = take(4 * (size_t)L.nbx * L.nby);
+  }
   // source splits for the near field: aim for >= 2048 blocks in flight
   int64_t tiles = std::max<int64_t>(1, (nt + NEAR_BLOCK - 1) / NEAR_BLOCK);
   int64_t max_s = std::max<int64_t>(1, (ns + NEAR_TILE - 1) / NEAR_TILE);
@@ -201,6 +216,16 @@ int pfmm_eval(pfmm_plan_t p, int64_t ns, const double* src_xy, const double* den
     p->prof_events.push_back(ev[0]); p->prof_events.push_back(ev[1]); p->prof_events.push_back(ev[2]);
   }
 
+  // bin the targets (near-field work order)
+  SortArgs sa{};
+  sa.n = nt; sa.x = D(L.tcx); sa.y = D(L.tcy);
+  sa.x0 = -0.5 * (g.d + std::fabs(g.xi)); sa.y0 = -0.5 * g.eta;
+  sa.inv_w = 1.0 / L.bin_w; sa.inv_h = 1.0 / L.bin_h; sa.nbx = L.nbx; sa.nby = L.nby;
+  sa.key = (int*)(ws + L.key); sa.perm = (int*)(ws + L.perm);
+  sa.hist = (int*)(ws + L.hist); sa.cursor = (int*)(ws + L.cursor);
+  sa.sx = D(L.stx); sa.sy = D(L.sty);
+  launch_sort_targets(sa, st);
+
   // near field
   NearArgs na{};
   na.geo = g;
@@ -208,8 +233,10 @@ int pfmm_eval(pfmm_plan_t p, int64_t ns, const double* src_xy, const double* den
   na.sx = D(L.scx); na.sy = D(L.scy);
   if (mixed) { na.sxh = F(L.sxh); na.sxl = F(L.sxl); na.syh = F(L.syh); na.syl = F(L.syl); na.q32 = F(L.q32); }
   na.q64 = dens_c;
-  na.tx = D(L.tcx); na.ty = D(L.tcy);
+  na.tx = D(L.stx); na.ty = D(L.sty); na.perm = sa.perm;
+  na.self = p->self_exclude;
   na.beta = p->beta;
+  na.r2min = R2MIN_F32;
   na.part = D(L.near_part);
   na.part_stride = L.part_stride;
   if (ns > 0) {
@@ -217,7 +244,7 @@ int pfmm_eval(pfmm_plan_t p, int64_t ns, const double* src_xy, const double* den
     launch_near(K, mixed, p->n_dens, na, L.n_splits, st);
     if (p->profile) (void)hipEventRecord(ev[1], st);
   } else {
-    if (hipMemsetAsync(na.part, 0, 8 * L.part_stride, st) != hipSuccess) return PFMM_EHIP;
+    launch_fill_zero(na.part, (int64_t)L.part_stride, st);
   }
   const int n_splits_used = ns > 0 ? L.n_splits : 1;
 
@@ -239,7 +266,7 @@ int pfmm_eval(pfmm_plan_t p, int64_t ns, const double* src_xy, const double* den
     // layout with n_sn = 0 for the direct west/east part
     fe.n_coef = p->n_ew * coef_per_wave(K) + 1;
     if (ns > 0) launch_far_R(fe, L.n_chunks, st);
-    else if (hipMemsetAsync(fe.part, 0, 16 * (size_t)p->n_dens * fe.n_coef, st) != hipSuccess) return PFMM_EHIP;
+    else launch_fill_zero(fe.part, 2 * (int64_t)p->n_dens * fe.n_coef, st);
     FarDArgs fd{};
     fd.kernel = K; fd.n_sn = 0; fd.n_ew = p->n_ew; fd.ncw = fe.ncw; fd.n_coef = fe.n_coef;
     fd.n_dens = p->n_dens; fd.n_chunks = ns > 0 ? L.n_chunks : 1; fd.eta = g.eta; fd.xi = g.xi;
@@ -254,7 +281,7 @@ int pfmm_eval(pfmm_plan_t p, int64_t ns, const double* src_xy, const double* den
     launch_far_L(fl, st);
   } else {
     if (ns > 0) launch_far_R(fr, L.n_chunks, st);
-    else if (hipMemsetAsync(fr.part, 0, 16 * (size_t)p->n_dens * L.n_coef, st) != hipSuccess) return PFMM_EHIP;
+    else launch_fill_zero(fr.part, 2 * (int64_t)p->n_dens * L.n_coef, st);
     FarDArgs fd{};
     fd.kernel = K; fd.n_sn = p->n_sn; fd.n_ew = p->n_ew; fd.ncw = fr.ncw; fd.n_coef = L.n_coef;
     fd.n_dens = p->n_dens; fd.n_chunks = ns > 0 ? L.n_chunks : 1; fd.eta = g.eta; fd.xi = g.xi;

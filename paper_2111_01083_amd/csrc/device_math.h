@@ -52,6 +52,29 @@ __device__ __forceinline__ void bessel_k01_f32(float x, float& k0, float& k1_ove
   }
 }
 
+// Same in FP32 for a wavefront whose lanes mostly share one branch: the
+// large-argument form is evaluated for every lane and the small-argument
+// series only when some lane of the wavefront needs it (a wave-uniform
+// branch, so a coherent wavefront runs a single path).
+__device__ __forceinline__ void bessel_k01_f32_wave(float x, float& k0, float& k1_over_x) {
+  const float rx = __builtin_amdgcn_rcpf(x);
+  const float u = 2.0f * rx;
+  const float e = __expf(-x) * __builtin_amdgcn_rsqf(x);
+  k0 = e * horner_f(KL0_F32, u);
+  k1_over_x = e * rx * horner_f(KL1_F32, u);
+  const bool small = x <= 2.0f;
+  if (__any(small)) {
+    const float t = 0.25f * x * x;
+    const float lt = __logf(t);
+    const float i0 = horner_f(KS_I0_F32, t), p0 = horner_f(KS_P0_F32, t);
+    const float j1 = horner_f(KS_J1_F32, t), p1 = horner_f(KS_P1_F32, t);
+    const float k0s = p0 - 0.5f * lt * i0;
+    const float k1s = (1.0f + t * (lt * j1 - p1)) * __builtin_amdgcn_rcpf(x * x);
+    k0 = small ? k0s : k0;
+    k1_over_x = small ? k1s : k1_over_x;
+  }
+}
+
 // K0(x) and K1(x)/x for x > 0 in FP64.
 __device__ __forceinline__ void bessel_k01_f64(double x, double& k0, double& k1_over_x) {
   if (x <= 2.0) {

@@ -9,7 +9,18 @@ namespace pfmm {
 
 constexpr int NEAR_BLOCK = 256;   // threads (= targets) per near-field block
 constexpr int NEAR_TILE = 256;    // sources per LDS tile
-constexpr int NEAR_FLUSH = 16;    // FP32 partial-sum length before an FP64 flush (mixed)
+#ifndef PFMM_NEAR_FLUSH
+#define PFMM_NEAR_FLUSH 16
+#endif
+#ifndef PFMM_NEAR_TPT
+#define PFMM_NEAR_TPT 1
+#endif
+#ifndef PFMM_NEAR_BIN
+#define PFMM_NEAR_BIN 1
+#endif
+constexpr int NEAR_FLUSH = PFMM_NEAR_FLUSH;  // FP32 partial-sum length before an FP64 flush (mixed)
+constexpr int NEAR_TPT = PFMM_NEAR_TPT;      // targets per thread (single-density launches)
+constexpr double R2MIN_F32 = 8.673617379884035e-19;   // 2^-60: r^2 clamp of the mixed Laplace/Stokes pair
 constexpr int FAR_CHUNK = 2048;   // sources per far_R block
 
 struct PrepArgs {
@@ -37,10 +48,21 @@ struct NearArgs {
   const double* q64;                     // densities [n_dens][nc][n_src]
   const float* q32;
   int dens0;                             // first density of this launch
-  const double *tx, *ty;                 // FP64 targets
-  double beta;
+  const double *tx, *ty;                 // FP64 targets in binned order
+  const int* perm;                       // binned position -> original target index
+  int self;                              // targets are the sources (same indices)
+  double beta, r2min;
   double* part;                          // [split][n_dens*NOUT][n_trg]
   size_t part_stride;                    // doubles per split
+};
+
+struct SortArgs {
+  int64_t n;
+  const double *x, *y;       // canonical targets
+  double x0, y0, inv_w, inv_h;
+  int nbx, nby;
+  int *key, *hist, *cursor, *perm;
+  double *sx, *sy;           // binned copies
 };
 
 struct FarRArgs {
@@ -77,6 +99,8 @@ struct FarLArgs {
 void launch_prep_points(const PrepArgs& a, hipStream_t s);
 void launch_prep_dens(const PrepDensArgs& a, hipStream_t s);
 void launch_near(int kernel, bool mixed, int nd, const NearArgs& a, int n_splits, hipStream_t s);
+void launch_sort_targets(const SortArgs& a, hipStream_t s);
+void launch_fill_zero(double* p, int64_t n, hipStream_t s);
 void launch_far_R(const FarRArgs& a, int n_chunks, hipStream_t s);
 void launch_far_D(const FarDArgs& a, hipStream_t s);
 void launch_far_L(const FarLArgs& a, hipStream_t s);

@@ -68,202 +68,361 @@ void launch_prep_dens(const PrepDensArgs& a, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// near field. One target per thread; sources stream through LDS in tiles of
-// NEAR_TILE and each tile is reused for every image shift (applied to the
-// target). Block (x, y) = (target tile, source split); split y writes its
-// partial sums to part[y][dens*NOUT + c][n_trg] in FP64.
+// target binning: a counting sort of the targets into square-ish bins of
+// about 64 points, so that the targets of one wavefront are spatially close
+// and take the same branches (K0/K1 small/large argument) for a given source.
+// Only the targets are permuted, so each target's sum over sources keeps its
+// order and results do not depend on the permutation.
+// ---------------------------------------------------------------------------
+__global__ void fill_int_kernel(int* p, int n, int v) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void fill_double_kernel(double* p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+__global__ void bin_count_kernel(SortArgs a) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  int bx = (int)floor((a.x[i] - a.x0) * a.inv_w), by = (int)floor((a.y[i] - a.y0) * a.inv_h);
+  bx = min(max(bx, 0), a.nbx - 1);
+  by = min(max(by, 0), a.nby - 1);
+  int key = by * a.nbx + ((by & 1) ? (a.nbx - 1 - bx) : bx);   // boustrophedon rows
+  if (!PFMM_NEAR_BIN) key = 0;
+  a.key[i] = key;
+  atomicAdd(&a.hist[key], 1);
+}
+// exclusive scan of hist into cursor (single block)
+__global__ __launch_bounds__(1024) void bin_scan_kernel(SortArgs a) {
+  __shared__ int part[1024];
+  const int nb = a.nbx * a.nby, t = threadIdx.x;
+  const int per = (nb + 1023) / 1024;
+  const int b0 = min(t * per, nb), b1 = min(b0 + per, nb);
+  int s = 0;
+  for (int b = b0; b < b1; ++b) s += a.hist[b];
+  part[t] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    int v = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int run = part[t] - s;
+  for (int b = b0; b < b1; ++b) { int h = a.hist[b]; a.cursor[b] = run; run += h; }
+}
+__global__ void bin_scatter_kernel(SortArgs a) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  int pos = atomicAdd(&a.cursor[a.key[i]], 1);
+  a.perm[pos] = (int)i;
+  a.sx[pos] = a.x[i];
+  a.sy[pos] = a.y[i];
+}
+
+void launch_sort_targets(const SortArgs& a, hipStream_t s) {
+  if (a.n <= 0) return;
+  const int nb = a.nbx * a.nby;
+  hipLaunchKernelGGL(fill_int_kernel, dim3((nb + 255) / 256), dim3(256), 0, s, a.hist, nb, 0);
+  const int g = (int)((a.n + 255) / 256);
+  hipLaunchKernelGGL(bin_count_kernel, dim3(g), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(bin_scan_kernel, dim3(1), dim3(1024), 0, s, a);
+  hipLaunchKernelGGL(bin_scatter_kernel, dim3(g), dim3(256), 0, s, a);
+}
+
+void launch_fill_zero(double* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_double_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+}
+
+// ---------------------------------------------------------------------------
+// near field. Each thread owns TPT targets (taken in binned order); sources
+// stream through LDS in tiles of NEAR_TILE and every tile is reused for all
+// image shifts, which are applied to the targets. Block (x, y) = (target
+// tile, source split); split y writes partial sums to
+// part[y][dens*NOUT + c][n_trg] (FP64) at the targets' original indices.
 //
 // MIXED: pair arithmetic in FP32. Coordinates are two-float (hi + lo) and
 // t - s = (t_hi - s_hi) + (t_lo - s_lo), which keeps the difference to a few
-// FP32 ulps of |t - s| even for the closest pairs; FP32 partial sums over one
+// FP32 ulps of |t - s| even for the closest pairs. FP32 partial sums over
 // NEAR_FLUSH sources of one image are flushed into FP64 accumulators (the
-// FP32 rounding error of a blocked sum grows like the block length).
+// rounding error of a blocked FP32 sum grows like the block length).
 //
 // Accumulators per density:
 //   Laplace/Yukawa (3): sum q g(r), sum q h(r) dx, sum q h(r) dy
-//   Stokes (7): sum lg f1, sum lg f2, sum c dx, sum c dy, sum (c - e dx^2),
-//               sum (f2 dx - f1 dy)/r^2, sum e dx dy
-//     with lg = log r^2, c = (r.f)/r^2, e = 2c/r^2.
-// A pair at r = 0 (the excluded self term, or an exactly coincident image)
-// contributes nothing.
+//   Stokes (8), with F = 2f, lg = log r^2, a = dx/r^2, b = dy/r^2, c2 = a F1 + b F2:
+//     sum lg F1, sum lg F2, sum c2 dx, sum c2 dy, sum c2, sum c2 a dx,
+//     sum c2 a dy, sum (F2 a - F1 b)
+//
+// r = 0: Laplace/Stokes clamp r^2 to R2MIN (an exact power of two); the only
+// such pair in a self-excluding evaluation is the self pair, whose clamped
+// value lg(R2MIN) * density is removed exactly in FP64 at the end (the
+// gradient terms vanish because dx = dy = 0). Yukawa (and the FP64 path)
+// zero the pair with a select. Exactly coincident distinct points are a
+// singularity of the sum and are not supported.
 // ---------------------------------------------------------------------------
 template <int K> struct NAcc { static constexpr int v = 3; };
-template <> struct NAcc<PFMM_STOKES> { static constexpr int v = 7; };
+template <> struct NAcc<PFMM_STOKES> { static constexpr int v = 8; };
 
-template <int K, bool MIXED, int ND>
+template <bool MIXED> struct SrcPt;
+template <> struct alignas(16) SrcPt<true> { float xh, xl, yh, yl; };
+template <> struct alignas(16) SrcPt<false> { double x, y; };
+
+template <int K, bool MIXED, int ND, int NA, typename real>
+__device__ __forceinline__ void near_pair(real dx, real dy, const real* qv, real (&p)[ND][NA], real beta,
+                                          real r2min) {
+  const real r2 = dx * dx + dy * dy;
+  if constexpr (K == PFMM_YUKAWA || !MIXED) {
+    const bool ok = r2 > (real)0;
+    const real r2s = ok ? r2 : (real)1;
+    if constexpr (K == PFMM_YUKAWA) {
+      real k0, k1x;
+      if constexpr (MIXED) bessel_k01_f32_wave(beta * __builtin_amdgcn_sqrtf(r2s), k0, k1x);
+      else bessel_k01_f64(beta * sqrt(r2s), k0, k1x);
+      k0 = ok ? k0 : (real)0;
+      const real gx = k1x * dx, gy = k1x * dy;   // dx = dy = 0 when !ok
+#pragma unroll
+      for (int v = 0; v < ND; ++v) {
+        const real q = qv[v];
+        p[v][0] += q * k0; p[v][1] += q * gx; p[v][2] += q * gy;
+      }
+      return;
+    } else {
+      real lg = log(r2s), inv = 1.0 / r2s;
+      lg = ok ? lg : (real)0;
+      inv = ok ? inv : (real)0;
+      if constexpr (K == PFMM_LAPLACE) {
+#pragma unroll
+        for (int v = 0; v < ND; ++v) {
+          const real sq = qv[v] * inv;
+          p[v][0] += qv[v] * lg; p[v][1] += sq * dx; p[v][2] += sq * dy;
+        }
+      } else {
+        const real ia = inv * dx, ib = inv * dy;
+#pragma unroll
+        for (int v = 0; v < ND; ++v) {
+          const real F1 = qv[2 * v], F2 = qv[2 * v + 1];
+          const real c2 = ia * F1 + ib * F2;
+          const real t = c2 * ia;
+          p[v][0] += lg * F1; p[v][1] += lg * F2;
+          p[v][2] += c2 * dx; p[v][3] += c2 * dy;
+          p[v][4] += c2; p[v][5] += t * dx; p[v][6] += t * dy;
+          p[v][7] += F2 * ia - F1 * ib;
+        }
+      }
+      return;
+    }
+  } else {
+    const real r2s = __builtin_fmaxf(r2, r2min);
+    const real lg = __builtin_amdgcn_logf(r2s);
+    const real inv = __builtin_amdgcn_rcpf(r2s);
+    if constexpr (K == PFMM_LAPLACE) {
+#pragma unroll
+      for (int v = 0; v < ND; ++v) {
+        const real sq = qv[v] * inv;
+        p[v][0] += qv[v] * lg; p[v][1] += sq * dx; p[v][2] += sq * dy;
+      }
+    } else {
+      const real ia = inv * dx, ib = inv * dy;
+#pragma unroll
+      for (int v = 0; v < ND; ++v) {
+        const real F1 = qv[2 * v], F2 = qv[2 * v + 1];
+        const real c2 = ia * F1 + ib * F2;
+        const real t = c2 * ia;
+        p[v][0] += lg * F1; p[v][1] += lg * F2;
+        p[v][2] += c2 * dx; p[v][3] += c2 * dy;
+        p[v][4] += c2; p[v][5] += t * dx; p[v][6] += t * dy;
+        p[v][7] += F2 * ia - F1 * ib;
+      }
+    }
+  }
+}
+
+template <int K, bool MIXED, int ND, int TPT>
 __global__ __launch_bounds__(NEAR_BLOCK) void near_kernel(NearArgs a) {
   using real = typename std::conditional<MIXED, float, double>::type;
   constexpr int NC = (K == PFMM_STOKES) ? 2 : 1;
   constexpr int NA = NAcc<K>::v;
   constexpr int NO = (K == PFMM_STOKES) ? 6 : 3;
-  __shared__ real s_xh[NEAR_TILE], s_yh[NEAR_TILE];
-  __shared__ real s_xl[MIXED ? NEAR_TILE : 1], s_yl[MIXED ? NEAR_TILE : 1];
-  __shared__ real s_q[ND * NC][NEAR_TILE];
+  constexpr int QN = ND * NC;
+  __shared__ SrcPt<MIXED> s_pt[NEAR_TILE];
+  __shared__ real s_q[NEAR_TILE][QN];
 
   const int tid = threadIdx.x;
-  const int64_t it = (int64_t)blockIdx.x * NEAR_BLOCK + tid;
-  const bool active = it < a.n_trg;
-  const int64_t ti = active ? it : 0;
-  const double tx = a.n_trg > 0 ? a.tx[ti] : 0.0, ty = a.n_trg > 0 ? a.ty[ti] : 0.0;
+  const int64_t k0 = (int64_t)blockIdx.x * (NEAR_BLOCK * TPT) + tid;
+  double tx[TPT], ty[TPT];
+  int orig[TPT];
+#pragma unroll
+  for (int u = 0; u < TPT; ++u) {
+    const int64_t k = k0 + u * NEAR_BLOCK;
+    const int64_t kk = k < a.n_trg ? k : a.n_trg - 1;
+    tx[u] = a.tx[kk]; ty[u] = a.ty[kk];
+    orig[u] = k < a.n_trg ? a.perm[kk] : -1;
+  }
   const int64_t s0 = (int64_t)blockIdx.y * a.split_len;
   const int64_t s1 = min(s0 + a.split_len, a.n_src);
 
-  double acc[ND][NA];
+  double acc[TPT][ND][NA];
 #pragma unroll
-  for (int v = 0; v < ND; ++v)
+  for (int u = 0; u < TPT; ++u)
 #pragma unroll
-    for (int c = 0; c < NA; ++c) acc[v][c] = 0.0;
+    for (int v = 0; v < ND; ++v)
+#pragma unroll
+      for (int c = 0; c < NA; ++c) acc[u][v][c] = 0.0;
 
   const real beta = (real)a.beta;
+  const real r2min = (real)a.r2min;
+  const real qscale = (K == PFMM_STOKES) ? (real)2 : (real)1;
   for (int64_t base = s0; base < s1; base += NEAR_TILE) {
     const int nt = (int)min((int64_t)NEAR_TILE, s1 - base);
     __syncthreads();
     if (tid < nt) {
       const int64_t j = base + tid;
       if constexpr (MIXED) {
-        s_xh[tid] = a.sxh[j]; s_xl[tid] = a.sxl[j];
-        s_yh[tid] = a.syh[j]; s_yl[tid] = a.syl[j];
+        s_pt[tid] = SrcPt<true>{a.sxh[j], a.sxl[j], a.syh[j], a.syl[j]};
 #pragma unroll
-        for (int v = 0; v < ND * NC; ++v) s_q[v][tid] = a.q32[(size_t)(a.dens0 * NC + v) * a.n_src + j];
+        for (int v = 0; v < QN; ++v) s_q[tid][v] = qscale * a.q32[(size_t)(a.dens0 * NC + v) * a.n_src + j];
       } else {
-        s_xh[tid] = a.sx[j]; s_yh[tid] = a.sy[j];
+        s_pt[tid] = SrcPt<false>{a.sx[j], a.sy[j]};
 #pragma unroll
-        for (int v = 0; v < ND * NC; ++v) s_q[v][tid] = a.q64[(size_t)(a.dens0 * NC + v) * a.n_src + j];
+        for (int v = 0; v < QN; ++v) s_q[tid][v] = qscale * a.q64[(size_t)(a.dens0 * NC + v) * a.n_src + j];
       }
     }
     __syncthreads();
     for (int im = 0; im < a.geo.n_images; ++im) {
-      const double txi = tx - a.geo.img_x[im], tyi = ty - a.geo.img_y[im];
-      real txh, txl, tyh, tyl;
-      if constexpr (MIXED) {
-        txh = (real)txi; txl = (real)(txi - (double)txh);
-        tyh = (real)tyi; tyl = (real)(tyi - (double)tyh);
-      } else {
-        txh = txi; tyh = tyi; txl = 0; tyl = 0;
+      real th[TPT], tl[TPT], uh[TPT], ul[TPT];
+#pragma unroll
+      for (int u = 0; u < TPT; ++u) {
+        const double txi = tx[u] - a.geo.img_x[im], tyi = ty[u] - a.geo.img_y[im];
+        th[u] = (real)txi; uh[u] = (real)tyi;
+        if constexpr (MIXED) { tl[u] = (real)(txi - (double)th[u]); ul[u] = (real)(tyi - (double)uh[u]); }
+        else { tl[u] = 0; ul[u] = 0; }
       }
       for (int jb = 0; jb < nt; jb += NEAR_FLUSH) {
-      const int je = min(jb + NEAR_FLUSH, nt);
-      real p[ND][NA];
+        real p[TPT][ND][NA];
 #pragma unroll
-      for (int v = 0; v < ND; ++v)
+        for (int u = 0; u < TPT; ++u)
 #pragma unroll
-        for (int c = 0; c < NA; ++c) p[v][c] = 0;
-      for (int j = jb; j < je; ++j) {
-        real dx, dy;
-        if constexpr (MIXED) {
-          dx = (txh - s_xh[j]) + (txl - s_xl[j]);
-          dy = (tyh - s_yh[j]) + (tyl - s_yl[j]);
-        } else {
-          dx = txh - s_xh[j];
-          dy = tyh - s_yh[j];
-        }
-        const real r2 = dx * dx + dy * dy;
-        const bool ok = r2 > (real)0;
-        const real r2s = ok ? r2 : (real)1;
-        if constexpr (K == PFMM_YUKAWA) {
-          real k0, k1x;
-          if constexpr (MIXED) {
-            bessel_k01_f32(beta * __builtin_amdgcn_sqrtf(r2s), k0, k1x);
-          } else {
-            bessel_k01_f64(beta * sqrt(r2s), k0, k1x);
-          }
-          k0 = ok ? k0 : (real)0;
-          k1x = ok ? k1x : (real)0;
-          const real gx = k1x * dx, gy = k1x * dy;
+          for (int v = 0; v < ND; ++v)
 #pragma unroll
-          for (int v = 0; v < ND; ++v) {
-            const real q = s_q[v][j];
-            p[v][0] += q * k0; p[v][1] += q * gx; p[v][2] += q * gy;
-          }
-        } else {
-          real lg, inv;
-          if constexpr (MIXED) { lg = __builtin_amdgcn_logf(r2s); inv = __builtin_amdgcn_rcpf(r2s); }
-          else { lg = log(r2s); inv = 1.0 / r2s; }
-          lg = ok ? lg : (real)0;
-          inv = ok ? inv : (real)0;
-          const real ix = inv * dx, iy = inv * dy;
-          if constexpr (K == PFMM_LAPLACE) {
+            for (int c = 0; c < NA; ++c) p[u][v][c] = 0;
+        auto body = [&](int j) {
+          const SrcPt<MIXED> sp = s_pt[j];
+          real qv[QN];
 #pragma unroll
-            for (int v = 0; v < ND; ++v) {
-              const real q = s_q[v][j];
-              p[v][0] += q * lg; p[v][1] += q * ix; p[v][2] += q * iy;
+          for (int v = 0; v < QN; ++v) qv[v] = s_q[j][v];
+#pragma unroll
+          for (int u = 0; u < TPT; ++u) {
+            real dx, dy;
+            if constexpr (MIXED) {
+              dx = (th[u] - sp.xh) + (tl[u] - sp.xl);
+              dy = (uh[u] - sp.yh) + (ul[u] - sp.yl);
+            } else {
+              dx = th[u] - sp.x;
+              dy = uh[u] - sp.y;
             }
-          } else {
-#pragma unroll
-            for (int v = 0; v < ND; ++v) {
-              const real f1 = s_q[2 * v][j], f2 = s_q[2 * v + 1][j];
-              const real c = ix * f1 + iy * f2;
-              const real e2x = (c + c) * ix;
-              p[v][0] += lg * f1;
-              p[v][1] += lg * f2;
-              p[v][2] += c * dx;
-              p[v][3] += c * dy;
-              p[v][4] += c - e2x * dx;
-              p[v][5] += f2 * ix - f1 * iy;
-              p[v][6] += e2x * dy;
-            }
+            near_pair<K, MIXED, ND, NA, real>(dx, dy, qv, p[u], beta, r2min);
           }
+        };
+        if (jb + NEAR_FLUSH <= nt) {
+#pragma unroll
+          for (int jj = 0; jj < NEAR_FLUSH; ++jj) body(jb + jj);
+        } else {
+          for (int j = jb; j < nt; ++j) body(j);
         }
-      }
 #pragma unroll
-      for (int v = 0; v < ND; ++v)
+        for (int u = 0; u < TPT; ++u)
 #pragma unroll
-        for (int c = 0; c < NA; ++c) acc[v][c] += (double)p[v][c];
+          for (int v = 0; v < ND; ++v)
+#pragma unroll
+            for (int c = 0; c < NA; ++c) acc[u][v][c] += (double)p[u][v][c];
       }
     }
   }
-  if (!active) return;
   const double inv4pi = 1.0 / (4 * PI), inv2pi = 1.0 / (2 * PI);
   const double lscale = MIXED ? 0.69314718055994530942 : 1.0;  // log2 -> ln
   double* dst = a.part + (size_t)blockIdx.y * a.part_stride;
+  // value of lg at the clamped self pair (mixed Laplace/Stokes only)
+  double lg_self = 0.0;
+  if constexpr (MIXED && K != PFMM_YUKAWA) lg_self = (double)__builtin_amdgcn_logf((float)a.r2min);
 #pragma unroll
-  for (int v = 0; v < ND; ++v) {
-    double o[NO];
-    if constexpr (K == PFMM_LAPLACE) {
-      o[0] = -inv4pi * lscale * acc[v][0];
-      o[1] = -inv2pi * acc[v][1];
-      o[2] = -inv2pi * acc[v][2];
-    } else if constexpr (K == PFMM_YUKAWA) {
-      o[0] = inv2pi * acc[v][0];
-      o[1] = -a.beta * a.beta * inv2pi * acc[v][1];
-      o[2] = -a.beta * a.beta * inv2pi * acc[v][2];
-    } else {
-      o[0] = inv4pi * (-0.5 * lscale * acc[v][0] + acc[v][2]);
-      o[1] = inv4pi * (-0.5 * lscale * acc[v][1] + acc[v][3]);
-      o[2] = inv4pi * acc[v][4];
-      o[3] = inv4pi * (acc[v][5] - acc[v][6]);
-      o[4] = inv4pi * (-acc[v][5] - acc[v][6]);
-      o[5] = -inv4pi * acc[v][4];
+  for (int u = 0; u < TPT; ++u) {
+    const int i = orig[u];
+    if (i < 0) continue;
+    if constexpr (MIXED && K != PFMM_YUKAWA) {
+      if (a.self && i >= s0 && i < s1) {
+#pragma unroll
+        for (int v = 0; v < ND; ++v) {
+          if constexpr (K == PFMM_LAPLACE) {
+            acc[u][v][0] -= lg_self * (double)a.q32[(size_t)(a.dens0 + v) * a.n_src + i];
+          } else {
+            acc[u][v][0] -= lg_self * (double)(2.0f * a.q32[(size_t)((a.dens0 + v) * 2) * a.n_src + i]);
+            acc[u][v][1] -= lg_self * (double)(2.0f * a.q32[(size_t)((a.dens0 + v) * 2 + 1) * a.n_src + i]);
+          }
+        }
+      }
     }
 #pragma unroll
-    for (int c = 0; c < NO; ++c) dst[(size_t)((a.dens0 + v) * NO + c) * a.n_trg + it] = o[c];
-  }
-}
-
-template <int K, bool MIXED>
-static void launch_near_k(int nd, const NearArgs& a, dim3 grid, hipStream_t s) {
-  NearArgs b = a;
-  int v = 0;
-  for (; v + 4 <= nd; v += 4) {
-    b.dens0 = v;
-    hipLaunchKernelGGL((near_kernel<K, MIXED, 4>), grid, dim3(NEAR_BLOCK), 0, s, b);
-  }
-  for (; v < nd; ++v) {
-    b.dens0 = v;
-    hipLaunchKernelGGL((near_kernel<K, MIXED, 1>), grid, dim3(NEAR_BLOCK), 0, s, b);
+    for (int v = 0; v < ND; ++v) {
+      double o[NO];
+      const double* A = acc[u][v];
+      if constexpr (K == PFMM_LAPLACE) {
+        o[0] = -inv4pi * lscale * A[0];
+        o[1] = -inv2pi * A[1];
+        o[2] = -inv2pi * A[2];
+      } else if constexpr (K == PFMM_YUKAWA) {
+        o[0] = inv2pi * A[0];
+        o[1] = -a.beta * a.beta * inv2pi * A[1];
+        o[2] = -a.beta * a.beta * inv2pi * A[2];
+      } else {
+        // (F = 2f): u_i = (1/4pi)[-(1/2) sum lg f_i + sum c r_i],
+        // du1/dx = -du2/dy = (1/4pi) sum (c - 2 c dx^2/r^2),
+        // du1/dy = (1/4pi)[W - B], du2/dx = (1/4pi)[-W - B],
+        // W = sum (f2 dx - f1 dy)/r^2, B = 2 sum c dx dy/r^2
+        const double h = 0.5 * inv4pi;
+        o[0] = h * (-0.5 * lscale * A[0] + A[2]);
+        o[1] = h * (-0.5 * lscale * A[1] + A[3]);
+        o[2] = h * (A[4] - 2 * A[5]);
+        o[3] = h * (A[7] - 2 * A[6]);
+        o[4] = h * (-A[7] - 2 * A[6]);
+        o[5] = -o[2];
+      }
+#pragma unroll
+      for (int c = 0; c < NO; ++c) dst[(size_t)((a.dens0 + v) * NO + c) * a.n_trg + i] = o[c];
+    }
   }
 }
 
 void launch_near(int kernel, bool mixed, int nd, const NearArgs& a, int n_splits, hipStream_t s) {
-  if (a.n_trg <= 0) return;
-  dim3 grid((unsigned)((a.n_trg + NEAR_BLOCK - 1) / NEAR_BLOCK), (unsigned)n_splits);
+  if (a.n_trg <= 0 || a.n_src <= 0) return;
+  // four-density groups use one target per thread (grid sized for TPT = 1)
+  NearArgs b = a;
+  auto go = [&](auto kc, auto mc) {
+    constexpr int K = decltype(kc)::value;
+    constexpr bool M = decltype(mc)::value;
+    if (nd >= 4) {
+      dim3 g1((unsigned)((a.n_trg + NEAR_BLOCK - 1) / NEAR_BLOCK), (unsigned)n_splits);
+      int v = 0;
+      for (; v + 4 <= nd; v += 4) { b.dens0 = v; hipLaunchKernelGGL((near_kernel<K, M, 4, 1>), g1, dim3(NEAR_BLOCK), 0, s, b); }
+      for (; v < nd; ++v) { b.dens0 = v; hipLaunchKernelGGL((near_kernel<K, M, 1, 1>), g1, dim3(NEAR_BLOCK), 0, s, b); }
+    } else {
+      dim3 g2((unsigned)((a.n_trg + NEAR_BLOCK * NEAR_TPT - 1) / (NEAR_BLOCK * NEAR_TPT)), (unsigned)n_splits);
+      for (int v = 0; v < nd; ++v) { b.dens0 = v; hipLaunchKernelGGL((near_kernel<K, M, 1, NEAR_TPT>), g2, dim3(NEAR_BLOCK), 0, s, b); }
+    }
+  };
+  using L = std::integral_constant<int, PFMM_LAPLACE>;
+  using Y = std::integral_constant<int, PFMM_YUKAWA>;
+  using S = std::integral_constant<int, PFMM_STOKES>;
+  using T = std::true_type;
+  using F = std::false_type;
   switch (kernel * 2 + (mixed ? 1 : 0)) {
-    case 0: launch_near_k<PFMM_LAPLACE, false>(nd, a, grid, s); break;
-    case 1: launch_near_k<PFMM_LAPLACE, true>(nd, a, grid, s); break;
-    case 2: launch_near_k<PFMM_YUKAWA, false>(nd, a, grid, s); break;
-    case 3: launch_near_k<PFMM_YUKAWA, true>(nd, a, grid, s); break;
-    case 4: launch_near_k<PFMM_STOKES, false>(nd, a, grid, s); break;
-    case 5: launch_near_k<PFMM_STOKES, true>(nd, a, grid, s); break;
+    case 0: go(L{}, F{}); break;
+    case 1: go(L{}, T{}); break;
+    case 2: go(Y{}, F{}); break;
+    case 3: go(Y{}, T{}); break;
+    case 4: go(S{}, F{}); break;
+    case 5: go(S{}, T{}); break;
   }
 }
 
