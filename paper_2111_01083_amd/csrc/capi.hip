@@ -21,7 +21,7 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Workspace carve-up for one cell; offsets in bytes from the workspace base.
 struct Layout {
-  size_t scx, scy, tcx, tcy, sxh, sxl, syh, syl, q32, dens_c, near_part, far_part, w, nufft;
+  size_t scx, scy, tcx, tcy, sxh, sxl, syh, syl, q32, dens_c, near_part, far_part, w, nufft, nu_val;
   size_t key, perm, stx, sty, hist, cursor;   // target binning
   int nbx, nby;
   double bin_w, bin_h;
@@ -76,6 +76,7 @@ void plan_layout(const pfmm_plan_s* p, int64_t ns, int64_t nt, Layout& L) {
   L.far_part = take(16 * (size_t)L.n_chunks * p->n_dens * L.n_coef);
   L.w = take(16 * (size_t)p->n_dens * L.n_coef);
   L.nufft = p->use_nufft ? take(nufft_workspace_bytes(p, ns, nt)) : 0;
+  L.nu_val = p->use_nufft ? take(8 * L.part_stride) : 0;
   L.total = off;
 }
 
@@ -248,53 +249,36 @@ int pfmm_eval(pfmm_plan_t p, int64_t ns, const double* src_xy, const double* den
   }
   const int n_splits_used = ns > 0 ? L.n_splits : 1;
 
-  // far field
+  // far field: R (direct plane waves, or NUFFT for south/north), D, L
   FarRArgs fr{};
   fr.kernel = K; fr.n_sn = p->n_sn; fr.n_ew = p->n_ew; fr.ncw = coef_per_wave(K);
   fr.n_coef = L.n_coef; fr.n_dens = p->n_dens; fr.n_src = ns; fr.tab = p->d_tab;
   fr.sx = D(L.scx); fr.sy = D(L.scy); fr.dens = dens_c; fr.part = D(L.far_part);
+  fr.skip_sn = p->use_nufft;
+  const double* csn = nullptr;
+  if (p->use_nufft) {
+    rc = nufft_R(p, ns, D(L.scx), D(L.scy), dens_c, ws + L.nufft, st, &csn);
+    if (rc) return rc;
+  }
+  if (ns > 0) launch_far_R(fr, L.n_chunks, st);
+  else launch_fill_zero(fr.part, 2 * (int64_t)p->n_dens * L.n_coef, st);
+  FarDArgs fd{};
+  fd.kernel = K; fd.n_sn = p->n_sn; fd.n_ew = p->n_ew; fd.ncw = fr.ncw; fd.n_coef = L.n_coef;
+  fd.n_dens = p->n_dens; fd.n_chunks = ns > 0 ? L.n_chunks : 1; fd.eta = g.eta; fd.xi = g.xi;
+  fd.tab = p->d_tab; fd.part = fr.part; fd.extra = csn; fd.w = D(L.w);
+  launch_far_D(fd, st);
   const double* nu_val = nullptr;
   if (p->use_nufft) {
-    // south/north waves through the NUFFT path; west/east and moments direct
-    FarRArgs fe = fr;
-    rc = nufft_far(p, ns, nt, D(L.scx), D(L.scy), dens_c, D(L.tcx), D(L.tcy), ws + L.nufft, st, &nu_val);
+    rc = nufft_L(p, nt, D(L.tcx), D(L.tcy), D(L.w), L.n_coef, ws + L.nufft, st, &nu_val, D(L.nu_val));
     if (rc) return rc;
-    fe.n_sn = 0;
-    // the table pointer must skip the south/north records
-    fe.tab = p->d_tab + (size_t)p->n_sn * SN_REC;
-    fe.n_coef = L.n_coef;  // keep layout; indices shift below
-    // layout with n_sn = 0 for the direct west/east part
-    fe.n_coef = p->n_ew * coef_per_wave(K) + 1;
-    if (ns > 0) launch_far_R(fe, L.n_chunks, st);
-    else launch_fill_zero(fe.part, 2 * (int64_t)p->n_dens * fe.n_coef, st);
-    FarDArgs fd{};
-    fd.kernel = K; fd.n_sn = 0; fd.n_ew = p->n_ew; fd.ncw = fe.ncw; fd.n_coef = fe.n_coef;
-    fd.n_dens = p->n_dens; fd.n_chunks = ns > 0 ? L.n_chunks : 1; fd.eta = g.eta; fd.xi = g.xi;
-    fd.tab = fe.tab; fd.part = fe.part; fd.w = D(L.w);
-    launch_far_D(fd, st);
-    FarLArgs fl{};
-    fl.kernel = K; fl.n_sn = 0; fl.n_ew = p->n_ew; fl.ncw = fe.ncw; fl.n_coef = fe.n_coef;
-    fl.n_dens = p->n_dens; fl.n_splits = n_splits_used; fl.nufft = 1; fl.n_trg = nt;
-    fl.d = g.d; fl.eta = g.eta; fl.rc = g.rc; fl.rs = g.rs; fl.tab = fe.tab; fl.w = D(L.w);
-    fl.tx = D(L.tcx); fl.ty = D(L.tcy); fl.near_part = D(L.near_part); fl.part_stride = L.part_stride;
-    fl.nu_val = nu_val; fl.out_pot = out_pot; fl.out_grad = out_grad;
-    launch_far_L(fl, st);
-  } else {
-    if (ns > 0) launch_far_R(fr, L.n_chunks, st);
-    else launch_fill_zero(fr.part, 2 * (int64_t)p->n_dens * L.n_coef, st);
-    FarDArgs fd{};
-    fd.kernel = K; fd.n_sn = p->n_sn; fd.n_ew = p->n_ew; fd.ncw = fr.ncw; fd.n_coef = L.n_coef;
-    fd.n_dens = p->n_dens; fd.n_chunks = ns > 0 ? L.n_chunks : 1; fd.eta = g.eta; fd.xi = g.xi;
-    fd.tab = p->d_tab; fd.part = fr.part; fd.w = D(L.w);
-    launch_far_D(fd, st);
-    FarLArgs fl{};
-    fl.kernel = K; fl.n_sn = p->n_sn; fl.n_ew = p->n_ew; fl.ncw = fr.ncw; fl.n_coef = L.n_coef;
-    fl.n_dens = p->n_dens; fl.n_splits = n_splits_used; fl.nufft = 0; fl.n_trg = nt;
-    fl.d = g.d; fl.eta = g.eta; fl.rc = g.rc; fl.rs = g.rs; fl.tab = p->d_tab; fl.w = D(L.w);
-    fl.tx = D(L.tcx); fl.ty = D(L.tcy); fl.near_part = D(L.near_part); fl.part_stride = L.part_stride;
-    fl.nu_val = nullptr; fl.out_pot = out_pot; fl.out_grad = out_grad;
-    launch_far_L(fl, st);
   }
+  FarLArgs fl{};
+  fl.kernel = K; fl.n_sn = p->n_sn; fl.n_ew = p->n_ew; fl.ncw = fr.ncw; fl.n_coef = L.n_coef;
+  fl.n_dens = p->n_dens; fl.n_splits = n_splits_used; fl.nufft = p->use_nufft; fl.n_trg = nt;
+  fl.d = g.d; fl.eta = g.eta; fl.rc = g.rc; fl.rs = g.rs; fl.tab = p->d_tab; fl.w = D(L.w);
+  fl.tx = D(L.tcx); fl.ty = D(L.tcy); fl.near_part = D(L.near_part); fl.part_stride = L.part_stride;
+  fl.nu_val = nu_val; fl.out_pot = out_pot; fl.out_grad = out_grad;
+  launch_far_L(fl, st);
   if (p->profile) {
     if (ns == 0) { (void)hipEventRecord(ev[0], st); (void)hipEventRecord(ev[1], st); }
     (void)hipEventRecord(ev[2], st);

@@ -67,6 +67,7 @@ struct SortArgs {
 
 struct FarRArgs {
   int kernel, n_sn, n_ew, ncw, n_coef, n_dens;
+  int skip_sn;               // south/north slots come from the NUFFT path (write zeros)
   int64_t n_src;
   const double* tab;         // sn records | ew records
   const double *sx, *sy;     // canonical sources
@@ -79,6 +80,7 @@ struct FarDArgs {
   double eta, xi;
   const double* tab;
   const double* part;
+  const double* extra;       // NUFFT south/north coefficients [n_dens][n_sn][ncw] or NULL
   double* w;                 // [n_dens][n_coef] complex
 };
 

@@ -466,7 +466,8 @@ __global__ __launch_bounds__(FAR_R_BLOCK) void far_R_kernel(FarRArgs a) {
   const int64_t j1 = min(j0 + FAR_CHUNK, a.n_src);
   const int w = blockIdx.x * FAR_R_BLOCK + threadIdx.x;
   const int n_w = a.n_sn + a.n_ew;
-  const bool is_sn = w < a.n_sn, is_ew = !is_sn && w < n_w, is_mom = w == n_w;
+  const bool in_sn = w < a.n_sn;
+  const bool is_sn = in_sn && !a.skip_sn, is_ew = !in_sn && w < n_w, is_mom = w == n_w;
   double par0 = 0, par1 = 0;
   if (is_sn || is_ew) { par0 = a.tab[is_sn ? w * SN_REC : a.n_sn * SN_REC + (w - a.n_sn) * EW_REC];
                         par1 = a.tab[(is_sn ? w * SN_REC : a.n_sn * SN_REC + (w - a.n_sn) * EW_REC) + 1]; }
@@ -547,7 +548,7 @@ __global__ __launch_bounds__(FAR_R_BLOCK) void far_R_kernel(FarRArgs a) {
     }
   }
   double* out = a.part + ((size_t)blockIdx.y * a.n_dens + v) * a.n_coef * 2;
-  if (is_sn || is_ew) {
+  if (in_sn || is_ew) {
 #pragma unroll
     for (int c = 0; c < NCW; ++c) { out[2 * (w * NCW + c)] = acc[c].r; out[2 * (w * NCW + c) + 1] = acc[c].i; }
   } else if (is_mom) {
@@ -604,6 +605,10 @@ __global__ void far_D_kernel(FarDArgs a) {
     for (int ch = 0; ch < a.n_chunks; ++ch) {
       const double* p = a.part + (((size_t)ch * a.n_dens + v) * a.n_coef + c0 + k) * 2;
       sr += p[0]; si += p[1];
+    }
+    if (a.extra && w < a.n_sn) {
+      const double* e = a.extra + (((size_t)v * a.n_sn + w) * ncw + k) * 2;
+      sr += e[0]; si += e[1];
     }
     c[k] = {sr, si};
   }

@@ -1,4 +1,4 @@
-// NUFFT-accelerated south/north part (internal).
+// NUFFT-accelerated south/north factors (internal).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstdint>
@@ -7,9 +7,12 @@
 
 namespace pfmm {
 size_t nufft_workspace_bytes(const pfmm_plan_s* p, int64_t ns, int64_t nt);
-// Adds nothing to the outputs itself: fills *val_out (inside ws) with the
-// south/north field [n_dens][NOUT][nt] in the canonical frame.
-int nufft_far(const pfmm_plan_s* p, int64_t ns, int64_t nt, const double* sx, const double* sy,
-              const double* dens, const double* tx, const double* ty, char* ws, hipStream_t st,
-              const double** val_out);
+// R side: south/north coefficients [n_dens][n_sn][ncw] (complex) into the
+// workspace; *csn_out points at them.
+int nufft_R(const pfmm_plan_s* p, int64_t ns, const double* sx, const double* sy, const double* dens,
+            char* ws, hipStream_t st, const double** csn_out);
+// L side: south/north field at the targets, [n_dens][NOUT][nt] into val
+// (canonical frame), from the weighted coefficients w [n_dens][n_coef].
+int nufft_L(const pfmm_plan_s* p, int64_t nt, const double* tx, const double* ty, const double* w,
+            int n_coef, char* ws, hipStream_t st, const double** val_out, double* val);
 }  // namespace pfmm

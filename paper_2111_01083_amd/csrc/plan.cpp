@@ -215,8 +215,12 @@ int build_plan(int kernel, const double* e1, const double* e2, double tol, const
   }
 
   // --- far mode and NUFFT parameters (Sec. 6.1)
+  // the in-LDS line FFT holds at most 4096 complex points; NUFFT needs a grid
+  // of at least twice the 2M+1 modes
+  const bool nufft_fits = 2 * (2 * M + 1) <= 4096;
   int far = o.far_mode;
-  if (far == PFMM_FAR_AUTO) far = (2 * M + 1 >= 256) ? PFMM_FAR_NUFFT : PFMM_FAR_DIRECT;
+  if (far == PFMM_FAR_AUTO) far = (2 * M + 1 >= 256 && nufft_fits) ? PFMM_FAR_NUFFT : PFMM_FAR_DIRECT;
+  if (far == PFMM_FAR_NUFFT && !nufft_fits) return PFMM_EINVAL;
   p->far_mode = far;
   p->use_nufft = far == PFMM_FAR_NUFFT;
   int mgl = o.m_gl;
