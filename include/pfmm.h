@@ -139,13 +139,20 @@ int pfmm_eval(pfmm_plan_t plan, int64_t n_src, const double* src_xy, const doubl
               int64_t n_trg, const double* trg_xy, double* out_pot, double* out_grad,
               void* workspace, size_t workspace_bytes, void* hip_stream);
 
-/* Gradient of a loss L(pot) for targets == sources (self_exclude plans
- * with n_dens = 1, Laplace/Yukawa): given g = dL/dpot [n_src] (device),
- * writes out_dq[n_src] = dL/dq = sum_i g_i K(t_i, s_j) and
- * out_dxy[2][n_src] = dL/dx_j = g_j grad u[q](x_j) + q_j grad u[g](x_j),
- * using the symmetry of the periodic kernel (Sec. 1, eq. psum). Same
- * workspace rules as pfmm_eval. The caller projects out_dq onto neutral
- * densities if it needs to. */
+/* Adjoint for targets == sources (plans with self_exclude = 1 and n_dens = 1,
+ * any kernel). With pot = K q the potential at the sources and g = dL/dpot
+ * (device, laid out like out_pot: [n_src], Stokes [2][n_src]) for a loss L,
+ * writes
+ *   out_dq  (like dens)  = dL/dq_j = sum_i g_i K(t_i, s_j) = u[g](x_j)
+ *   out_dxy [2][n_src]   = dL/dx_j = g_j grad u[q](x_j) + q_j grad u[g](x_j)
+ *                          (Stokes: summed over the two velocity components)
+ * using the symmetry of the periodic kernel (Sec. 1, eq. psum). For Laplace
+ * and Stokes, g is first projected onto neutral vectors (its mean is
+ * removed), which is exact when L does not depend on the free constant of
+ * the potential (e.g. the energy 1/2 q.pot); out_dq is not projected.
+ * Workspace: at least pfmm_workspace_bytes_adjoint() bytes. A plan must not
+ * be used by two host threads at once. Either output may be NULL. */
+size_t pfmm_workspace_bytes_adjoint(pfmm_plan_t plan, int64_t n_src);
 int pfmm_eval_adjoint(pfmm_plan_t plan, int64_t n_src, const double* src_xy,
                       const double* dens, const double* g_pot, double* out_dq,
                       double* out_dxy, void* workspace, size_t workspace_bytes,

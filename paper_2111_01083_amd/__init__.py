@@ -170,20 +170,61 @@ def pfmm_eval(plan, src, dens, trg=None, out_pot=None, out_grad=None, workspace=
     return out_pot, out_grad
 
 
+def pfmm_workspace_bytes_adjoint(plan, n_src):
+    return int(L.load().pfmm_workspace_bytes_adjoint(plan.handle, int(n_src)))
+
+
 def pfmm_eval_adjoint(plan, src, dens, g_pot, workspace=None, stream=None):
-    """dL/dq and dL/dx for a loss of the potentials at the sources (see pfmm.h)."""
+    """dL/dq and dL/dx (2, ns) for a loss of the potentials at the sources,
+    given g_pot = dL/dpot (see pfmm.h)."""
     torch = _torch()
     lib = L.load()
     src = _as_dev(src, "src"); dens = _as_dev(dens, "dens"); g_pot = _as_dev(g_pot, "g_pot")
     ns = src.shape[1]
+    if g_pot.numel() != dens.numel():
+        raise ValueError("g_pot must have the shape of the potential (= shape of dens)")
     dq = torch.empty_like(dens)
     dxy = torch.empty((2, ns), dtype=torch.float64, device=src.device)
-    nbytes = pfmm_workspace_bytes(plan, ns, ns)
-    ws, wptr, avail = _workspace(2 * nbytes + 256, src.device, workspace)
+    ws, wptr, avail = _workspace(pfmm_workspace_bytes_adjoint(plan, ns), src.device, workspace)
     _check(lib.pfmm_eval_adjoint(plan.handle, ns, src.data_ptr(), dens.data_ptr(), g_pot.data_ptr(),
                                  dq.data_ptr(), dxy.data_ptr(), wptr, avail, _stream_ptr(stream)),
            "pfmm_eval_adjoint")
     return dq, dxy
+
+
+def _autograd():
+    torch = _torch()
+
+    class PeriodicPotential(torch.autograd.Function):
+        """pot = periodic potential at the sources (self terms excluded), with
+        a backward pass through pfmm_eval_adjoint (dL/dx and dL/dq)."""
+
+        @staticmethod
+        def forward(ctx, src, dens, plan):
+            pot, _ = pfmm_eval(plan, src, dens, None, want_grad=False)
+            ctx.plan = plan
+            ctx.save_for_backward(src, dens)
+            return pot
+
+        @staticmethod
+        def backward(ctx, g_pot):
+            src, dens = ctx.saved_tensors
+            dq, dxy = pfmm_eval_adjoint(ctx.plan, src, dens, g_pot.contiguous())
+            return dxy, dq, None
+
+    return PeriodicPotential
+
+
+_PP = None
+
+
+def periodic_potential(plan, src, dens):
+    """Differentiable periodic potential at the sources (plan: self_exclude=True,
+    n_dens=1). E.g. the energy is 0.5 * (dens * periodic_potential(...)).sum()."""
+    global _PP
+    if _PP is None:
+        _PP = _autograd()
+    return _PP.apply(src, dens, plan)
 
 
 def pfmm_strerror(code):

@@ -18,7 +18,8 @@ ERRORS = {0: "PFMM_OK", -1: "PFMM_EINVAL", -2: "PFMM_EINVAL_LATTICE", -3: "PFMM_
 # every function declared in include/pfmm.h
 EXPORTS = ["pfmm_plan", "pfmm_plan_upload", "pfmm_plan_get_info", "pfmm_plan_get_quadrature",
            "pfmm_plan_stage_times",
-           "pfmm_workspace_bytes", "pfmm_eval", "pfmm_eval_adjoint", "pfmm_workspace_bytes_batch",
+           "pfmm_workspace_bytes", "pfmm_eval", "pfmm_workspace_bytes_adjoint", "pfmm_eval_adjoint",
+           "pfmm_workspace_bytes_batch",
            "pfmm_eval_batch", "pfmm_destroy", "pfmm_strerror"]
 
 
@@ -64,6 +65,8 @@ def load():
     lib.pfmm_workspace_bytes.restype = ctypes.c_size_t
     lib.pfmm_eval.argtypes = [vp, i64, vp, vp, i64, vp, vp, vp, vp, ctypes.c_size_t, vp]
     lib.pfmm_eval.restype = c_int
+    lib.pfmm_workspace_bytes_adjoint.argtypes = [vp, i64]
+    lib.pfmm_workspace_bytes_adjoint.restype = ctypes.c_size_t
     lib.pfmm_eval_adjoint.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
     lib.pfmm_eval_adjoint.restype = c_int
     lib.pfmm_workspace_bytes_batch.argtypes = [c_int, ctypes.POINTER(vp), ctypes.POINTER(i64),

@@ -3,6 +3,4 @@ extern "C" {
 size_t pfmm_workspace_bytes_batch(int, const pfmm_plan_t*, const int64_t*, const int64_t*) { return 0; }
 int pfmm_eval_batch(int, const pfmm_plan_t*, const int64_t*, const int64_t*, const double*, const double*,
                     const double*, double*, double*, void*, size_t, void*) { return PFMM_EINVAL; }
-int pfmm_eval_adjoint(pfmm_plan_t, int64_t, const double*, const double*, const double*, double*, double*,
-                      void*, size_t, void*) { return PFMM_EINVAL; }
 }

@@ -158,6 +158,14 @@ size_t pfmm_workspace_bytes(pfmm_plan_t p, int64_t ns, int64_t nt) {
 int pfmm_eval(pfmm_plan_t p, int64_t ns, const double* src_xy, const double* dens, int64_t nt,
               const double* trg_xy, double* out_pot, double* out_grad, void* workspace,
               size_t ws_bytes, void* hip_stream) {
+  return pfmm::eval_core(p, ns, src_xy, dens, nt, trg_xy, out_pot, out_grad, workspace, ws_bytes, hip_stream);
+}
+
+}  // extern "C"
+
+int pfmm::eval_core(pfmm_plan_t p, int64_t ns, const double* src_xy, const double* dens, int64_t nt,
+                    const double* trg_xy, double* out_pot, double* out_grad, void* workspace,
+                    size_t ws_bytes, void* hip_stream) {
   if (!p || ns < 0 || nt < 0) return PFMM_EINVAL;
   if (p->self_exclude && nt != ns) return PFMM_EINVAL;
   if (ns > 0 && (!src_xy || !dens)) return PFMM_EINVAL;
@@ -285,6 +293,8 @@ int pfmm_eval(pfmm_plan_t p, int64_t ns, const double* src_xy, const double* den
   }
   return hip_ok(hipGetLastError());
 }
+
+extern "C" {
 
 int pfmm_plan_stage_times(pfmm_plan_t p, double* near_ms, double* total_ms, int* n_evals) {
   if (!p) return PFMM_EINVAL;

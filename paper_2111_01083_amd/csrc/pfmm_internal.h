@@ -79,4 +79,8 @@ namespace pfmm {
 int build_plan(int kernel, const double* e1, const double* e2, double tol,
                const pfmm_opts* opts, pfmm_plan_s* p);
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
+// one evaluation with the plan's current n_dens (capi.hip)
+int eval_core(pfmm_plan_s* p, int64_t ns, const double* src_xy, const double* dens, int64_t nt,
+              const double* trg_xy, double* out_pot, double* out_grad, void* workspace,
+              size_t ws_bytes, void* hip_stream);
 }  // namespace pfmm
