@@ -44,6 +44,8 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--sample", type=int, default=16, help="oracle targets per kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="only run a plain 1 GiB elementwise copy (to calibrate HBM byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -53,6 +55,16 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_calib:
+        n = 1 << 27                      # float64 elements = 1 GiB
+        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)   # elementwise kernel: reads and writes 1 GiB
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "copies": 3}), flush=True)
+        return
 
     import workloads as W
     import paper_2111_01083_amd as P

@@ -158,19 +158,28 @@ int pfmm_eval_adjoint(pfmm_plan_t plan, int64_t n_src, const double* src_xy,
                       double* out_dxy, void* workspace, size_t workspace_bytes,
                       void* hip_stream);
 
-/* Batched evaluation of many independent cells in one launch sequence.
- * plans[c] are plans of any kernel with the same precision and n_dens;
- * src_off/trg_off (host int64[n_cells + 1]) give each cell's range in the
- * concatenated arrays src_xy [2][total_src], dens [n_dens][total_src]
- * (Stokes [n_dens][2][total_src]), trg_xy, out_pot, out_grad (laid out like
- * pfmm_eval with n_src/n_trg replaced by the totals). Workspace:
- * pfmm_workspace_bytes_batch(). */
-size_t pfmm_workspace_bytes_batch(int n_cells, const pfmm_plan_t* plans,
-                                  const int64_t* src_off, const int64_t* trg_off);
-int pfmm_eval_batch(int n_cells, const pfmm_plan_t* plans, const int64_t* src_off,
-                    const int64_t* trg_off, const double* src_xy, const double* dens,
+/* Batched evaluation of many independent cells. plans[c] (n_cells of them)
+ * must share precision, n_dens and self_exclude, and be all scalar kernels
+ * (Laplace/Yukawa, mixed freely) or all Stokes. src_off/trg_off (host
+ * int64[n_cells + 1], starting at 0; trg_off ignored and may be NULL for
+ * self_exclude plans) give each cell's range in concatenated device arrays:
+ *   src_xy [2][S], dens [n_dens][S] (Stokes [n_dens][2][S]), trg_xy [2][T],
+ *   out_pot [n_dens][T] (Stokes [n_dens][2][T]), out_grad [n_dens][2|4][T]
+ * with S = src_off[n_cells], T = trg_off[n_cells]. The near fields of all
+ * cells run in one persistent launch over (cell, target tile, source split)
+ * tasks; each cell's far field follows (Sec. 6). Creation uploads the plans'
+ * tables and a task table to the device; use_graph = 1 captures the whole
+ * launch sequence into a hipGraph on the first pfmm_eval_batch call (and
+ * again whenever a pointer argument changes) and replays it afterwards.
+ * The plans must outlive the batch. */
+typedef struct pfmm_batch_s* pfmm_batch_t;
+int pfmm_batch_create(int n_cells, const pfmm_plan_t* plans, const int64_t* src_off,
+                      const int64_t* trg_off, int use_graph, pfmm_batch_t* out);
+size_t pfmm_batch_workspace_bytes(pfmm_batch_t batch);
+int pfmm_eval_batch(pfmm_batch_t batch, const double* src_xy, const double* dens,
                     const double* trg_xy, double* out_pot, double* out_grad,
                     void* workspace, size_t workspace_bytes, void* hip_stream);
+void pfmm_batch_destroy(pfmm_batch_t batch);
 
 void pfmm_destroy(pfmm_plan_t plan);
 const char* pfmm_strerror(int code);

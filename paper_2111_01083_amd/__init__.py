@@ -227,6 +227,61 @@ def periodic_potential(plan, src, dens):
     return _PP.apply(src, dens, plan)
 
 
+class Batch:
+    """Owner of a pfmm_batch_t: many cells evaluated together (see pfmm.h).
+
+    plans: list of Plan (same precision, n_dens, self_exclude); src_off /
+    trg_off: int sequences of length n_cells + 1 into concatenated arrays."""
+
+    def __init__(self, plans, src_off, trg_off=None, use_graph=False):
+        lib = L.load()
+        n = len(plans)
+        self.plans = list(plans)               # keep the plans alive
+        self.src_off = np.ascontiguousarray(src_off, dtype=np.int64)
+        self.trg_off = None if trg_off is None else np.ascontiguousarray(trg_off, dtype=np.int64)
+        arr = (ctypes.c_void_p * n)(*[p.handle.value for p in plans])
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        h = ctypes.c_void_p()
+        _check(lib.pfmm_batch_create(n, arr, self.src_off.ctypes.data_as(i64p),
+                                     None if self.trg_off is None else self.trg_off.ctypes.data_as(i64p),
+                                     int(bool(use_graph)), ctypes.byref(h)), "pfmm_batch_create")
+        self.handle = h
+        self.stokes = plans[0].kernel == L.PFMM_STOKES
+        self.n_dens = plans[0].n_dens
+        self.self_exclude = plans[0].self_exclude
+        self.workspace_bytes = int(lib.pfmm_batch_workspace_bytes(h))
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and L is not None and L._lib is not None:
+            L._lib.pfmm_batch_destroy(h)
+            self.handle = None
+
+    def __call__(self, src, dens, trg=None, out_pot=None, out_grad=None, workspace=None, stream=None):
+        return pfmm_eval_batch(self, src, dens, trg, out_pot, out_grad, workspace, stream)
+
+
+def pfmm_eval_batch(batch, src, dens, trg=None, out_pot=None, out_grad=None, workspace=None, stream=None):
+    """Evaluate every cell of a Batch; arrays are concatenated over cells.
+    Returns pot (n_dens, T) [Stokes (n_dens, 2, T)] and grad (n_dens, 2|4, T)."""
+    torch = _torch()
+    lib = L.load()
+    src = _as_dev(src, "src"); dens = _as_dev(dens, "dens")
+    T = int(batch.src_off[-1] if batch.self_exclude else batch.trg_off[-1])
+    trg_t = None if batch.self_exclude else _as_dev(trg, "trg")
+    nd = batch.n_dens
+    if out_pot is None:
+        out_pot = torch.empty((nd, 2, T) if batch.stokes else (nd, T), dtype=torch.float64, device=src.device)
+    if out_grad is None:
+        out_grad = torch.empty((nd, 4 if batch.stokes else 2, T), dtype=torch.float64, device=src.device)
+    ws, wptr, avail = _workspace(batch.workspace_bytes, src.device, workspace)
+    batch._ws_keep = ws
+    _check(lib.pfmm_eval_batch(batch.handle, src.data_ptr(), dens.data_ptr(),
+                               None if trg_t is None else trg_t.data_ptr(), out_pot.data_ptr(),
+                               out_grad.data_ptr(), wptr, avail, _stream_ptr(stream)), "pfmm_eval_batch")
+    return out_pot, out_grad
+
+
 def pfmm_strerror(code):
     return L.load().pfmm_strerror(int(code)).decode()
 

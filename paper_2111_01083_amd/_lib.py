@@ -19,8 +19,8 @@ ERRORS = {0: "PFMM_OK", -1: "PFMM_EINVAL", -2: "PFMM_EINVAL_LATTICE", -3: "PFMM_
 EXPORTS = ["pfmm_plan", "pfmm_plan_upload", "pfmm_plan_get_info", "pfmm_plan_get_quadrature",
            "pfmm_plan_stage_times",
            "pfmm_workspace_bytes", "pfmm_eval", "pfmm_workspace_bytes_adjoint", "pfmm_eval_adjoint",
-           "pfmm_workspace_bytes_batch",
-           "pfmm_eval_batch", "pfmm_destroy", "pfmm_strerror"]
+           "pfmm_batch_create", "pfmm_batch_workspace_bytes", "pfmm_eval_batch", "pfmm_batch_destroy",
+           "pfmm_destroy", "pfmm_strerror"]
 
 
 class pfmm_opts(ctypes.Structure):
@@ -69,12 +69,15 @@ def load():
     lib.pfmm_workspace_bytes_adjoint.restype = ctypes.c_size_t
     lib.pfmm_eval_adjoint.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
     lib.pfmm_eval_adjoint.restype = c_int
-    lib.pfmm_workspace_bytes_batch.argtypes = [c_int, ctypes.POINTER(vp), ctypes.POINTER(i64),
-                                               ctypes.POINTER(i64)]
-    lib.pfmm_workspace_bytes_batch.restype = ctypes.c_size_t
-    lib.pfmm_eval_batch.argtypes = [c_int, ctypes.POINTER(vp), ctypes.POINTER(i64), ctypes.POINTER(i64),
-                                    vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.pfmm_batch_create.argtypes = [c_int, ctypes.POINTER(vp), ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                      c_int, ctypes.POINTER(vp)]
+    lib.pfmm_batch_create.restype = c_int
+    lib.pfmm_batch_workspace_bytes.argtypes = [vp]
+    lib.pfmm_batch_workspace_bytes.restype = ctypes.c_size_t
+    lib.pfmm_eval_batch.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
     lib.pfmm_eval_batch.restype = c_int
+    lib.pfmm_batch_destroy.argtypes = [vp]
+    lib.pfmm_batch_destroy.restype = None
     lib.pfmm_destroy.argtypes = [vp]
     lib.pfmm_destroy.restype = None
     lib.pfmm_strerror.argtypes = [c_int]

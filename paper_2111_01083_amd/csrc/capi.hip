@@ -23,6 +23,7 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 struct Layout {
   size_t scx, scy, tcx, tcy, sxh, sxl, syh, syl, q32, dens_c, near_part, far_part, w, nufft, nu_val;
   size_t key, perm, stx, sty, hist, cursor;   // target binning
+  size_t qsum;                                // per-split FP32 density sums (mixed Laplace/Stokes)
   int nbx, nby;
   double bin_w, bin_h;
   size_t total;
@@ -31,7 +32,7 @@ struct Layout {
   size_t part_stride;  // doubles per split
 };
 
-void plan_layout(const pfmm_plan_s* p, int64_t ns, int64_t nt, Layout& L) {
+void plan_layout(const pfmm_plan_s* p, int64_t ns, int64_t nt, Layout& L, int64_t forced_split = 0) {
   const bool mixed = p->precision == PFMM_MIXED;
   const int nc = p->kernel == PFMM_STOKES ? 2 : 1;
   const int no = near_nout(p->kernel);
@@ -47,7 +48,7 @@ void plan_layout(const pfmm_plan_s* p, int64_t ns, int64_t nt, Layout& L) {
   } else {
     L.sxh = L.sxl = L.syh = L.syl = L.q32 = 0;
   }
-  L.dens_c = p->kernel == PFMM_STOKES ? take(8 * (size_t)p->n_dens * 2 * ns) : 0;
+  L.dens_c = take(8 * (size_t)p->n_dens * nc * ns);   // contiguous FP64 densities (Stokes: rotated)
   // target bins of about 64 points over the canonical cell's bounding box
   {
     const double W = p->geo.d + std::fabs(p->geo.xi), H = p->geo.eta;
@@ -66,10 +67,12 @@ void plan_layout(const pfmm_plan_s* p, int64_t ns, int64_t nt, Layout& L) {
   int64_t S = std::min<int64_t>(std::min<int64_t>((2048 + tiles - 1) / tiles, max_s), 64);
   S = std::max<int64_t>(S, 1);
   int64_t per = (ns + S - 1) / S;
+  if (forced_split > 0) per = forced_split;
   per = std::max<int64_t>(NEAR_TILE, (per + NEAR_TILE - 1) / NEAR_TILE * NEAR_TILE);
   L.split_len = per;
   L.n_splits = (int)std::max<int64_t>(1, (ns + per - 1) / per);
   L.part_stride = (size_t)p->n_dens * no * nt;
+  L.qsum = (mixed && p->kernel != PFMM_YUKAWA) ? take(8 * (size_t)L.n_splits * p->n_dens * nc) : 0;
   L.near_part = take(8 * L.part_stride * L.n_splits);
   L.n_chunks = (int)std::max<int64_t>(1, (ns + FAR_CHUNK - 1) / FAR_CHUNK);
   L.n_coef = (p->n_sn + p->n_ew) * coef_per_wave(p->kernel) + 1;
@@ -163,101 +166,100 @@ int pfmm_eval(pfmm_plan_t p, int64_t ns, const double* src_xy, const double* den
 
 }  // extern "C"
 
-int pfmm::eval_core(pfmm_plan_t p, int64_t ns, const double* src_xy, const double* dens, int64_t nt,
-                    const double* trg_xy, double* out_pot, double* out_grad, void* workspace,
-                    size_t ws_bytes, void* hip_stream) {
-  if (!p || ns < 0 || nt < 0) return PFMM_EINVAL;
-  if (p->self_exclude && nt != ns) return PFMM_EINVAL;
-  if (ns > 0 && (!src_xy || !dens)) return PFMM_EINVAL;
-  if (nt > 0 && !p->self_exclude && !trg_xy) return PFMM_EINVAL;
-  if (nt == 0 || (!out_pot && !out_grad)) return PFMM_OK;
+// ---------------------------------------------------------------------------
+// One cell's evaluation as three phases (shared by pfmm_eval and the batch):
+//   prep  -- canonical points, densities, binned targets
+//   near  -- near-field partial sums (single launch per cell, or batched)
+//   far   -- far_R (or NUFFT R) -> far_D -> (NUFFT L) -> far_L
+// ---------------------------------------------------------------------------
+namespace pfmm {
+
+struct CellRun {
+  pfmm_plan_s* p;
+  int64_t ns, nt;
   Layout L;
-  plan_layout(p, ns, nt, L);
-  if (!workspace || ws_bytes < L.total || ((uintptr_t)workspace & 255)) return PFMM_EWORKSPACE;
-  hipStream_t st = (hipStream_t)hip_stream;
-  int rc = pfmm_plan_upload(p);
-  if (rc) return rc;
-  const int K = p->kernel;
-  const bool mixed = p->precision == PFMM_MIXED;
-  const int nc = K == PFMM_STOKES ? 2 : 1;
-  if (p->check_neutral && K != PFMM_YUKAWA && ns > 0) {
-    std::vector<double> h((size_t)p->n_dens * nc * ns);
-    if (hipStreamSynchronize(st) != hipSuccess) return PFMM_EHIP;
-    if (hipMemcpy(h.data(), dens, h.size() * 8, hipMemcpyDeviceToHost) != hipSuccess) return PFMM_EHIP;
-    for (int v = 0; v < p->n_dens * nc; ++v) {
-      double s = 0, a = 0;
-      for (int64_t j = 0; j < ns; ++j) { s += h[(size_t)v * ns + j]; a += std::fabs(h[(size_t)v * ns + j]); }
-      if (std::fabs(s) > 1e-12 * a) return PFMM_ENOT_NEUTRAL;
-    }
-  }
-  char* ws = (char*)workspace;
+  char* ws;
+  int* perm;
+};
+
+static void cell_prep(CellRun& r, const double* src_xy, int64_t src_stride, const double* dens,
+                      int64_t dens_stride, const double* trg_xy, int64_t trg_stride, hipStream_t st) {
+  pfmm_plan_s* p = r.p;
+  const Layout& L = r.L;
+  char* ws = r.ws;
   auto D = [&](size_t off) { return (double*)(ws + off); };
   auto F = [&](size_t off) { return (float*)(ws + off); };
   const Geometry& g = p->geo;
-
-  // prep
+  const bool mixed = p->precision == PFMM_MIXED;
   PrepArgs pa{};
   pa.rc = g.rc; pa.rs = g.rs; pa.d = g.d; pa.xi = g.xi; pa.eta = g.eta;
-  pa.n = ns; pa.xy = src_xy; pa.cx = D(L.scx); pa.cy = D(L.scy);
+  pa.n = r.ns; pa.ystride = src_stride; pa.xy = src_xy; pa.cx = D(L.scx); pa.cy = D(L.scy);
+  pa.sigma = g.sigma;
   if (mixed) { pa.hx = F(L.sxh); pa.lx = F(L.sxl); pa.hy = F(L.syh); pa.ly = F(L.syl); }
   launch_prep_points(pa, st);
   if (!p->self_exclude) {
     PrepArgs pt = pa;
-    pt.n = nt; pt.xy = trg_xy; pt.cx = D(L.tcx); pt.cy = D(L.tcy);
+    pt.n = r.nt; pt.ystride = trg_stride; pt.xy = trg_xy; pt.cx = D(L.tcx); pt.cy = D(L.tcy);
     pt.hx = pt.lx = pt.hy = pt.ly = nullptr;
     launch_prep_points(pt, st);
   }
-  const double* dens_c = dens;
-  if (K == PFMM_STOKES || mixed) {
-    PrepDensArgs pd{};
-    pd.n = ns; pd.n_dens = p->n_dens; pd.stokes = K == PFMM_STOKES; pd.dens = dens;
-    pd.rc = g.rc; pd.rs = g.rs;
-    pd.out64 = K == PFMM_STOKES ? D(L.dens_c) : nullptr;
-    pd.out32 = mixed ? F(L.q32) : nullptr;
-    launch_prep_dens(pd, st);
-    if (K == PFMM_STOKES) dens_c = D(L.dens_c);
+  PrepDensArgs pd{};
+  pd.n = r.ns; pd.in_stride = dens_stride; pd.n_dens = p->n_dens; pd.stokes = p->kernel == PFMM_STOKES;
+  pd.dens = dens; pd.rc = g.rc; pd.rs = g.rs;
+  pd.out64 = D(L.dens_c);
+  pd.out32 = mixed ? F(L.q32) : nullptr;
+  launch_prep_dens(pd, st);
+  if (L.qsum) {
+    QsumArgs qa{};
+    qa.n_src = r.ns; qa.split_len = L.split_len; qa.ncomp = p->n_dens * (p->kernel == PFMM_STOKES ? 2 : 1);
+    qa.q64 = D(L.dens_c); qa.qsum = D(L.qsum);
+    launch_qsum(qa, L.n_splits, st);
   }
-
-  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
-  if (p->profile) {
-    for (int k = 0; k < 3; ++k)
-      if (hipEventCreate(&ev[k]) != hipSuccess) return PFMM_EHIP;
-    p->prof_events.push_back(ev[0]); p->prof_events.push_back(ev[1]); p->prof_events.push_back(ev[2]);
-  }
-
-  // bin the targets (near-field work order)
   SortArgs sa{};
-  sa.n = nt; sa.x = D(L.tcx); sa.y = D(L.tcy);
+  sa.n = r.nt; sa.x = D(L.tcx); sa.y = D(L.tcy);
   sa.x0 = -0.5 * (g.d + std::fabs(g.xi)); sa.y0 = -0.5 * g.eta;
   sa.inv_w = 1.0 / L.bin_w; sa.inv_h = 1.0 / L.bin_h; sa.nbx = L.nbx; sa.nby = L.nby;
   sa.key = (int*)(ws + L.key); sa.perm = (int*)(ws + L.perm);
   sa.hist = (int*)(ws + L.hist); sa.cursor = (int*)(ws + L.cursor);
   sa.sx = D(L.stx); sa.sy = D(L.sty);
   launch_sort_targets(sa, st);
+  r.perm = sa.perm;
+}
 
-  // near field
+static NearArgs cell_near_args(const CellRun& r) {
+  const pfmm_plan_s* p = r.p;
+  const Layout& L = r.L;
+  char* ws = r.ws;
+  auto D = [&](size_t off) { return (double*)(ws + off); };
+  auto F = [&](size_t off) { return (float*)(ws + off); };
   NearArgs na{};
-  na.geo = g;
-  na.n_src = ns; na.n_trg = nt; na.split_len = L.split_len;
+  na.geo = p->geo;
+  na.n_src = r.ns; na.n_trg = r.nt; na.split_len = L.split_len;
   na.sx = D(L.scx); na.sy = D(L.scy);
-  if (mixed) { na.sxh = F(L.sxh); na.sxl = F(L.sxl); na.syh = F(L.syh); na.syl = F(L.syl); na.q32 = F(L.q32); }
-  na.q64 = dens_c;
-  na.tx = D(L.stx); na.ty = D(L.sty); na.perm = sa.perm;
+  if (p->precision == PFMM_MIXED) {
+    na.sxh = F(L.sxh); na.sxl = F(L.sxl); na.syh = F(L.syh); na.syl = F(L.syl); na.q32 = F(L.q32);
+  }
+  na.q64 = D(L.dens_c);
+  na.tx = D(L.stx); na.ty = D(L.sty); na.perm = (const int*)(ws + L.perm);
   na.self = p->self_exclude;
   na.beta = p->beta;
   na.r2min = R2MIN_F32;
+  na.qsum = L.qsum ? D(L.qsum) : nullptr;
+  na.qsum_stride = p->n_dens * (p->kernel == PFMM_STOKES ? 2 : 1);
   na.part = D(L.near_part);
   na.part_stride = L.part_stride;
-  if (ns > 0) {
-    if (p->profile) (void)hipEventRecord(ev[0], st);
-    launch_near(K, mixed, p->n_dens, na, L.n_splits, st);
-    if (p->profile) (void)hipEventRecord(ev[1], st);
-  } else {
-    launch_fill_zero(na.part, (int64_t)L.part_stride, st);
-  }
-  const int n_splits_used = ns > 0 ? L.n_splits : 1;
+  return na;
+}
 
-  // far field: R (direct plane waves, or NUFFT for south/north), D, L
+static int cell_far(CellRun& r, double* out_pot, double* out_grad, int64_t out_stride, hipStream_t st) {
+  pfmm_plan_s* p = r.p;
+  const Layout& L = r.L;
+  char* ws = r.ws;
+  auto D = [&](size_t off) { return (double*)(ws + off); };
+  const Geometry& g = p->geo;
+  const int K = p->kernel;
+  const int64_t ns = r.ns, nt = r.nt;
+  const double* dens_c = D(L.dens_c);
   FarRArgs fr{};
   fr.kernel = K; fr.n_sn = p->n_sn; fr.n_ew = p->n_ew; fr.ncw = coef_per_wave(K);
   fr.n_coef = L.n_coef; fr.n_dens = p->n_dens; fr.n_src = ns; fr.tab = p->d_tab;
@@ -265,7 +267,7 @@ int pfmm::eval_core(pfmm_plan_t p, int64_t ns, const double* src_xy, const doubl
   fr.skip_sn = p->use_nufft;
   const double* csn = nullptr;
   if (p->use_nufft) {
-    rc = nufft_R(p, ns, D(L.scx), D(L.scy), dens_c, ws + L.nufft, st, &csn);
+    int rc = nufft_R(p, ns, D(L.scx), D(L.scy), dens_c, ws + L.nufft, st, &csn);
     if (rc) return rc;
   }
   if (ns > 0) launch_far_R(fr, L.n_chunks, st);
@@ -277,20 +279,74 @@ int pfmm::eval_core(pfmm_plan_t p, int64_t ns, const double* src_xy, const doubl
   launch_far_D(fd, st);
   const double* nu_val = nullptr;
   if (p->use_nufft) {
-    rc = nufft_L(p, nt, D(L.tcx), D(L.tcy), D(L.w), L.n_coef, ws + L.nufft, st, &nu_val, D(L.nu_val));
+    int rc = nufft_L(p, nt, D(L.stx), D(L.sty), D(L.w), L.n_coef, ws + L.nufft, st, &nu_val, D(L.nu_val));
     if (rc) return rc;
   }
   FarLArgs fl{};
   fl.kernel = K; fl.n_sn = p->n_sn; fl.n_ew = p->n_ew; fl.ncw = fr.ncw; fl.n_coef = L.n_coef;
-  fl.n_dens = p->n_dens; fl.n_splits = n_splits_used; fl.nufft = p->use_nufft; fl.n_trg = nt;
+  fl.n_dens = p->n_dens; fl.n_splits = ns > 0 ? L.n_splits : 1; fl.nufft = p->use_nufft; fl.n_trg = nt;
   fl.d = g.d; fl.eta = g.eta; fl.rc = g.rc; fl.rs = g.rs; fl.tab = p->d_tab; fl.w = D(L.w);
-  fl.tx = D(L.tcx); fl.ty = D(L.tcy); fl.near_part = D(L.near_part); fl.part_stride = L.part_stride;
-  fl.nu_val = nu_val; fl.out_pot = out_pot; fl.out_grad = out_grad;
+  fl.tx = D(L.stx); fl.ty = D(L.sty); fl.perm = (const int*)(ws + L.perm);
+  fl.near_part = D(L.near_part); fl.part_stride = L.part_stride;
+  fl.nu_val = nu_val; fl.out_pot = out_pot; fl.out_grad = out_grad; fl.out_stride = out_stride;
   launch_far_L(fl, st);
-  if (p->profile) {
-    if (ns == 0) { (void)hipEventRecord(ev[0], st); (void)hipEventRecord(ev[1], st); }
-    (void)hipEventRecord(ev[2], st);
+  return PFMM_OK;
+}
+
+size_t cell_workspace(pfmm_plan_s* p, int64_t ns, int64_t nt, int64_t forced_split) {
+  Layout L;
+  plan_layout(p, ns, p->self_exclude ? ns : nt, L, forced_split);
+  return L.total;
+}
+
+int cell_setup(pfmm_plan_s* p, int64_t ns, int64_t nt, char* ws, int64_t forced_split, CellRun& r) {
+  r.p = p; r.ns = ns; r.nt = nt; r.ws = ws; r.perm = nullptr;
+  plan_layout(p, ns, nt, r.L, forced_split);
+  return PFMM_OK;
+}
+
+}  // namespace pfmm
+
+int pfmm::eval_core(pfmm_plan_t p, int64_t ns, const double* src_xy, const double* dens, int64_t nt,
+                    const double* trg_xy, double* out_pot, double* out_grad, void* workspace,
+                    size_t ws_bytes, void* hip_stream) {
+  if (!p || ns < 0 || nt < 0) return PFMM_EINVAL;
+  if (p->self_exclude && nt != ns) return PFMM_EINVAL;
+  if (ns > 0 && (!src_xy || !dens)) return PFMM_EINVAL;
+  if (nt > 0 && !p->self_exclude && !trg_xy) return PFMM_EINVAL;
+  if (nt == 0 || (!out_pot && !out_grad)) return PFMM_OK;
+  CellRun r;
+  cell_setup(p, ns, nt, (char*)workspace, 0, r);
+  if (!workspace || ws_bytes < r.L.total || ((uintptr_t)workspace & 255)) return PFMM_EWORKSPACE;
+  hipStream_t st = (hipStream_t)hip_stream;
+  int rc = pfmm_plan_upload(p);
+  if (rc) return rc;
+  const int nc = p->kernel == PFMM_STOKES ? 2 : 1;
+  if (p->check_neutral && p->kernel != PFMM_YUKAWA && ns > 0) {
+    std::vector<double> h((size_t)p->n_dens * nc * ns);
+    if (hipStreamSynchronize(st) != hipSuccess) return PFMM_EHIP;
+    if (hipMemcpy(h.data(), dens, h.size() * 8, hipMemcpyDeviceToHost) != hipSuccess) return PFMM_EHIP;
+    for (int v = 0; v < p->n_dens * nc; ++v) {
+      double s = 0, a = 0;
+      for (int64_t j = 0; j < ns; ++j) { s += h[(size_t)v * ns + j]; a += std::fabs(h[(size_t)v * ns + j]); }
+      if (std::fabs(s) > 1e-12 * a) return PFMM_ENOT_NEUTRAL;
+    }
   }
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  if (p->profile) {
+    for (int k = 0; k < 3; ++k)
+      if (hipEventCreate(&ev[k]) != hipSuccess) return PFMM_EHIP;
+    p->prof_events.push_back(ev[0]); p->prof_events.push_back(ev[1]); p->prof_events.push_back(ev[2]);
+  }
+  cell_prep(r, src_xy, ns, dens, ns, trg_xy, nt, st);
+  NearArgs na = cell_near_args(r);
+  if (p->profile) (void)hipEventRecord(ev[0], st);
+  if (ns > 0) launch_near(p->kernel, p->precision == PFMM_MIXED, p->n_dens, na, r.L.n_splits, st);
+  else launch_fill_zero(na.part, (int64_t)r.L.part_stride, st);
+  if (p->profile) (void)hipEventRecord(ev[1], st);
+  rc = cell_far(r, out_pot, out_grad, nt, st);
+  if (rc) return rc;
+  if (p->profile) (void)hipEventRecord(ev[2], st);
   return hip_ok(hipGetLastError());
 }
 
@@ -336,6 +392,194 @@ const char* pfmm_strerror(int code) {
     case PFMM_ENOMEM: return "out of memory for plan tables";
     default: return "unknown error";
   }
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched evaluation: per-cell prep, one persistent near-field launch over the
+// tasks (cell, target tile, source split) of every cell, per-cell far field.
+// Optionally captured once into a hipGraph and replayed.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int64_t BATCH_SPLIT = 8192;   // sources per near-field task
+}
+
+struct pfmm_batch_s {
+  int n_cells, n_recs, n_dens, mixed, self_exclude, nc, use_graph;
+  std::vector<pfmm_plan_s*> plans;
+  std::vector<int64_t> soff, toff;
+  std::vector<size_t> base;            // workspace offset of each cell
+  size_t counter_off, total;
+  long long n_tasks;
+  int grid;
+  BatchCell* d_recs;
+  hipStream_t cap_stream;
+  hipGraphExec_t exec;
+  const void* cap_args[5];
+  void* cap_ws;
+};
+
+extern "C" {
+
+int pfmm_batch_create(int n_cells, const pfmm_plan_t* plans, const int64_t* src_off, const int64_t* trg_off,
+                      int use_graph, pfmm_batch_t* out) {
+  if (n_cells <= 0 || !plans || !src_off || !out) return PFMM_EINVAL;
+  pfmm_plan_s* p0 = plans[0];
+  if (!p0) return PFMM_EINVAL;
+  const int nc = p0->kernel == PFMM_STOKES ? 2 : 1;
+  for (int c = 0; c < n_cells; ++c) {
+    pfmm_plan_s* p = plans[c];
+    if (!p || p->precision != p0->precision || p->n_dens != p0->n_dens || p->self_exclude != p0->self_exclude ||
+        (p->kernel == PFMM_STOKES ? 2 : 1) != nc)
+      return PFMM_EINVAL;
+    if (src_off[c + 1] < src_off[c]) return PFMM_EINVAL;
+    if (!p0->self_exclude && (!trg_off || trg_off[c + 1] < trg_off[c])) return PFMM_EINVAL;
+  }
+  if (src_off[0] != 0 || (!p0->self_exclude && trg_off[0] != 0)) return PFMM_EINVAL;
+  pfmm_batch_s* b = new (std::nothrow) pfmm_batch_s();
+  if (!b) return PFMM_ENOMEM;
+  b->n_cells = n_cells; b->n_dens = p0->n_dens; b->mixed = p0->precision == PFMM_MIXED;
+  b->self_exclude = p0->self_exclude; b->nc = nc; b->use_graph = use_graph ? 1 : 0;
+  b->plans.assign(plans, plans + n_cells);
+  b->soff.assign(src_off, src_off + n_cells + 1);
+  if (p0->self_exclude) b->toff = b->soff; else b->toff.assign(trg_off, trg_off + n_cells + 1);
+  b->d_recs = nullptr; b->cap_stream = nullptr; b->exec = nullptr; b->cap_ws = nullptr;
+  for (auto& a : b->cap_args) a = nullptr;
+  for (int c = 0; c < n_cells; ++c) {
+    int rc = pfmm_plan_upload(plans[c]);
+    if (rc) { delete b; return rc; }
+  }
+  // workspace: cells in order, then the task counter
+  size_t off = 0;
+  b->base.resize(n_cells);
+  std::vector<CellRun> runs(n_cells);
+  for (int c = 0; c < n_cells; ++c) {
+    const int64_t ns = b->soff[c + 1] - b->soff[c], nt = b->toff[c + 1] - b->toff[c];
+    b->base[c] = off;
+    cell_setup(plans[c], ns, nt, nullptr, BATCH_SPLIT, runs[c]);
+    off += align_up(runs[c].L.total);
+  }
+  b->counter_off = off;
+  b->total = off + 256;
+  // task records, most expensive cells first
+  std::vector<int> order(n_cells);
+  for (int c = 0; c < n_cells; ++c) order[c] = c;
+  auto cost = [&](int c) {
+    return (double)(b->soff[c + 1] - b->soff[c]) * (double)(b->toff[c + 1] - b->toff[c]) * plans[c]->geo.n_images;
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int bb) { return cost(a) > cost(bb); });
+  std::vector<BatchCell> recs;
+  long long task = 0;
+  for (int c : order) {
+    const CellRun& r = runs[c];
+    if (r.ns == 0 || r.nt == 0) continue;
+    BatchCell bc{};
+    CellRun rr = r;
+    rr.ws = nullptr;
+    bc.args = cell_near_args(rr);
+    const size_t B = b->base[c];
+    const Layout& L = r.L;
+    const bool mixed = b->mixed;
+    bc.o_sx = B + L.scx; bc.o_sy = B + L.scy;
+    bc.o_sxh = mixed ? B + L.sxh : 0; bc.o_sxl = mixed ? B + L.sxl : 0;
+    bc.o_syh = mixed ? B + L.syh : 0; bc.o_syl = mixed ? B + L.syl : 0;
+    bc.o_q64 = B + L.dens_c; bc.o_q32 = mixed ? B + L.q32 : 0;
+    bc.o_tx = B + L.stx; bc.o_ty = B + L.sty; bc.o_perm = B + L.perm; bc.o_part = B + L.near_part;
+    bc.o_qsum = L.qsum ? B + L.qsum : 0;
+    bc.kernel = plans[c]->kernel; bc.n_dens = b->n_dens;
+    bc.n_tiles = (int)((r.nt + NEAR_BLOCK - 1) / NEAR_BLOCK);
+    bc.task0 = task;
+    task += (long long)bc.n_tiles * L.n_splits;
+    recs.push_back(bc);
+  }
+  b->n_tasks = task;
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  b->grid = (int)std::max<long long>(1, std::min<long long>(task, 4LL * cus));
+  if (!recs.empty()) {
+    if (hipMalloc(&b->d_recs, recs.size() * sizeof(BatchCell)) != hipSuccess) { delete b; return PFMM_ENOMEM; }
+    if (hipMemcpy(b->d_recs, recs.data(), recs.size() * sizeof(BatchCell), hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipFree(b->d_recs); delete b; return PFMM_EHIP;
+    }
+  }
+  b->n_recs = (int)recs.size();
+  *out = b;
+  return PFMM_OK;
+}
+
+size_t pfmm_batch_workspace_bytes(pfmm_batch_t b) { return b ? b->total : 0; }
+
+}  // extern "C"
+
+static int batch_launch(pfmm_batch_s* b, const double* src_xy, const double* dens, const double* trg_xy,
+                        double* out_pot, double* out_grad, char* ws, hipStream_t st) {
+  const int64_t S = b->soff[b->n_cells], T = b->toff[b->n_cells];
+  std::vector<CellRun> runs(b->n_cells);
+  for (int c = 0; c < b->n_cells; ++c) {
+    const int64_t ns = b->soff[c + 1] - b->soff[c], nt = b->toff[c + 1] - b->toff[c];
+    cell_setup(b->plans[c], ns, nt, ws + b->base[c], BATCH_SPLIT, runs[c]);
+    if (nt == 0) continue;
+    cell_prep(runs[c], src_xy + b->soff[c], S, dens + b->soff[c], S,
+              b->self_exclude ? nullptr : trg_xy + b->toff[c], T, st);
+    if (ns == 0) launch_fill_zero((double*)(ws + b->base[c] + runs[c].L.near_part), (int64_t)runs[c].L.part_stride, st);
+  }
+  launch_fill_zero((double*)(ws + b->counter_off), 1, st);
+  BatchNearArgs na{};
+  na.recs = b->d_recs;
+  na.n_cells = b->n_recs;
+  na.n_tasks = b->n_tasks;
+  na.ws = ws;
+  na.counter = (unsigned long long*)(ws + b->counter_off);
+  launch_near_batch(b->mixed, na, b->grid, st);
+  for (int c = 0; c < b->n_cells; ++c) {
+    if (runs[c].nt == 0) continue;
+    int rc = cell_far(runs[c], out_pot ? out_pot + b->toff[c] : nullptr, out_grad ? out_grad + b->toff[c] : nullptr,
+                      T, st);
+    if (rc) return rc;
+  }
+  return hip_ok(hipGetLastError());
+}
+
+extern "C" {
+
+int pfmm_eval_batch(pfmm_batch_t b, const double* src_xy, const double* dens, const double* trg_xy,
+                    double* out_pot, double* out_grad, void* workspace, size_t ws_bytes, void* hip_stream) {
+  if (!b) return PFMM_EINVAL;
+  if (!src_xy || !dens || (!b->self_exclude && !trg_xy)) return PFMM_EINVAL;
+  if (!out_pot && !out_grad) return PFMM_OK;
+  if (!workspace || ws_bytes < b->total || ((uintptr_t)workspace & 255)) return PFMM_EWORKSPACE;
+  hipStream_t st = (hipStream_t)hip_stream;
+  char* ws = (char*)workspace;
+  if (!b->use_graph) return batch_launch(b, src_xy, dens, trg_xy, out_pot, out_grad, ws, st);
+  const void* args[5] = {src_xy, dens, trg_xy, out_pot, out_grad};
+  bool same = b->exec && b->cap_ws == workspace;
+  for (int k = 0; k < 5 && same; ++k) same = args[k] == b->cap_args[k];
+  if (!same) {
+    if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+    if (!b->cap_stream && hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess)
+      return PFMM_EHIP;
+    if (hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return PFMM_EHIP;
+    int rc = batch_launch(b, src_xy, dens, trg_xy, out_pot, out_grad, ws, b->cap_stream);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(b->cap_stream, &graph);
+    if (rc) { if (graph) (void)hipGraphDestroy(graph); return rc; }
+    if (e != hipSuccess || !graph) return PFMM_EHIP;
+    e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) { b->exec = nullptr; return PFMM_EHIP; }
+    for (int k = 0; k < 5; ++k) b->cap_args[k] = args[k];
+    b->cap_ws = workspace;
+  }
+  return hip_ok(hipGraphLaunch(b->exec, st));
+}
+
+void pfmm_batch_destroy(pfmm_batch_t b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  if (b->d_recs) (void)hipFree(b->d_recs);
+  delete b;
 }
 
 }  // extern "C"

@@ -12,31 +12,28 @@ constexpr int NEAR_TILE = 256;    // sources per LDS tile
 #ifndef PFMM_NEAR_FLUSH
 #define PFMM_NEAR_FLUSH 16
 #endif
-#ifndef PFMM_NEAR_TPT
-#define PFMM_NEAR_TPT 1
-#endif
 #ifndef PFMM_NEAR_BIN
 #define PFMM_NEAR_BIN 1
 #endif
 constexpr int NEAR_FLUSH = PFMM_NEAR_FLUSH;  // FP32 partial-sum length before an FP64 flush (mixed)
-constexpr int NEAR_TPT = PFMM_NEAR_TPT;      // targets per thread (single-density launches)
 constexpr double R2MIN_F32 = 8.673617379884035e-19;   // 2^-60: r^2 clamp of the mixed Laplace/Stokes pair
 constexpr int FAR_CHUNK = 2048;   // sources per far_R block
 
 struct PrepArgs {
-  int64_t n;
-  const double* xy;          // [2][n] user frame
+  int64_t n, ystride;        // y coordinates at xy[ystride + i]
+  const double* xy;          // [2][*] user frame
   double rc, rs, d, xi, eta;
   double *cx, *cy;           // canonical FP64
-  float *hx, *lx, *hy, *ly;  // two-float copies (NULL unless mixed)
+  float *hx, *lx, *hy, *ly;  // two-float copies of sigma * (x, y) (NULL unless mixed)
+  double sigma;
 };
 
 struct PrepDensArgs {
-  int64_t n;
+  int64_t n, in_stride;      // user density rows are in_stride apart
   int n_dens, stokes;
   const double* dens;        // user densities
   double rc, rs;
-  double* out64;             // Stokes: rotated forces
+  double* out64;             // contiguous FP64 copy (Stokes: rotated forces) or NULL
   float* out32;              // FP32 copy (mixed), NULL otherwise
 };
 
@@ -52,8 +49,18 @@ struct NearArgs {
   const int* perm;                       // binned position -> original target index
   int self;                              // targets are the sources (same indices)
   double beta, r2min;
+  const double* qsum;                    // mixed Laplace/Stokes: per split, sum of the FP32
+                                         // densities [split][qsum_stride] (NULL: no log shift)
+  int qsum_stride;                       // n_dens * nc
   double* part;                          // [split][n_dens*NOUT][n_trg]
   size_t part_stride;                    // doubles per split
+};
+
+struct QsumArgs {
+  int64_t n_src, split_len;
+  int ncomp;                             // n_dens * nc
+  const double* q64;                     // [ncomp][n_src]
+  double* qsum;                          // [split][ncomp]
 };
 
 struct SortArgs {
@@ -90,11 +97,30 @@ struct FarLArgs {
   double d, eta, rc, rs;
   const double* tab;
   const double* w;
-  const double *tx, *ty;     // canonical targets
-  const double* near_part;   // [split][n_dens*NOUT][n_trg]
+  const double *tx, *ty;     // canonical targets in binned order
+  const int* perm;           // binned position -> original index
+  const double* near_part;   // [split][n_dens*NOUT][n_trg] in binned order
   size_t part_stride;
-  const double* nu_val;      // NUFFT path: interpolated south/north field [n_dens*NOUT][n_trg]
+  const double* nu_val;      // NUFFT path: south/north field [n_dens*NOUT][n_trg], binned order
   double *out_pot, *out_grad;
+  int64_t out_stride;        // output rows are out_stride apart (n_trg for one cell)
+};
+
+// one cell of a batched near-field launch; array offsets are byte offsets
+// into the batch workspace
+struct BatchCell {
+  NearArgs args;             // sizes, geometry, beta, split length, flags
+  int kernel, n_dens, n_tiles;
+  long long task0;           // first task index of this cell
+  int64_t o_sx, o_sy, o_sxh, o_sxl, o_syh, o_syl, o_q64, o_q32, o_tx, o_ty, o_perm, o_part, o_qsum;
+};
+
+struct BatchNearArgs {
+  const BatchCell* recs;     // device array [n_cells], task0 ascending
+  int n_cells;
+  long long n_tasks;
+  char* ws;
+  unsigned long long* counter;   // zeroed before the launch
 };
 
 // launchers (kernels.hip)
@@ -102,6 +128,8 @@ void launch_prep_points(const PrepArgs& a, hipStream_t s);
 void launch_prep_dens(const PrepDensArgs& a, hipStream_t s);
 void launch_near(int kernel, bool mixed, int nd, const NearArgs& a, int n_splits, hipStream_t s);
 void launch_sort_targets(const SortArgs& a, hipStream_t s);
+void launch_near_batch(bool mixed, const BatchNearArgs& b, int grid, hipStream_t s);
+void launch_qsum(const QsumArgs& a, int n_splits, hipStream_t s);
 void launch_fill_zero(double* p, int64_t n, hipStream_t s);
 void launch_far_R(const FarRArgs& a, int n_chunks, hipStream_t s);
 void launch_far_D(const FarDArgs& a, hipStream_t s);

@@ -19,7 +19,7 @@ namespace pfmm {
 __global__ void prep_points_kernel(PrepArgs a) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
-  double x = a.xy[i], y = a.xy[a.n + i];
+  double x = a.xy[i], y = a.xy[a.ystride + i];
   double xc = a.rc * x - a.rs * y, yc = a.rs * x + a.rc * y;
   // lattice coordinates u2 = y/eta, u1 = (x - u2 xi)/d, then u <- u - rint(u)
   double k2 = rint(yc / a.eta);
@@ -30,19 +30,21 @@ __global__ void prep_points_kernel(PrepArgs a) {
   a.cx[i] = xc;
   a.cy[i] = yc;
   if (a.hx) {
-    float xh = (float)xc, yh = (float)yc;
-    a.hx[i] = xh; a.lx[i] = (float)(xc - (double)xh);
-    a.hy[i] = yh; a.ly[i] = (float)(yc - (double)yh);
+    const double xs = xc * a.sigma, ys = yc * a.sigma;   // exact: sigma is a power of two
+    float xh = (float)xs, yh = (float)ys;
+    a.hx[i] = xh; a.lx[i] = (float)(xs - (double)xh);
+    a.hy[i] = yh; a.ly[i] = (float)(ys - (double)yh);
   }
 }
 
 __global__ void prep_dens_kernel(PrepDensArgs a) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
+  const int64_t is = a.in_stride;
   for (int v = 0; v < a.n_dens; ++v) {
     if (a.stokes) {
-      const double* f = a.dens + (size_t)v * 2 * a.n;
-      double f1 = f[i], f2 = f[a.n + i];
+      const double* f = a.dens + (size_t)v * 2 * is;
+      double f1 = f[i], f2 = f[is + i];
       double g1 = a.rc * f1 - a.rs * f2, g2 = a.rs * f1 + a.rc * f2;
       double* o = a.out64 + (size_t)v * 2 * a.n;
       o[i] = g1; o[a.n + i] = g2;
@@ -50,8 +52,10 @@ __global__ void prep_dens_kernel(PrepDensArgs a) {
         float* o32 = a.out32 + (size_t)v * 2 * a.n;
         o32[i] = (float)g1; o32[a.n + i] = (float)g2;
       }
-    } else if (a.out32) {
-      a.out32[(size_t)v * a.n + i] = (float)a.dens[(size_t)v * a.n + i];
+    } else {
+      const double q = a.dens[(size_t)v * is + i];
+      if (a.out64) a.out64[(size_t)v * a.n + i] = q;
+      if (a.out32) a.out32[(size_t)v * a.n + i] = (float)q;
     }
   }
 }
@@ -137,17 +141,21 @@ void launch_fill_zero(double* p, int64_t n, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// near field. Each thread owns TPT targets (taken in binned order); sources
+// near field. Each thread owns one target (taken in binned order); sources
 // stream through LDS in tiles of NEAR_TILE and every tile is reused for all
 // image shifts, which are applied to the targets. Block (x, y) = (target
 // tile, source split); split y writes partial sums to
-// part[y][dens*NOUT + c][n_trg] (FP64) at the targets' original indices.
+// part[y][dens*NOUT + c][n_trg] (FP64) in binned target order.
 //
 // MIXED: pair arithmetic in FP32. Coordinates are two-float (hi + lo) and
 // t - s = (t_hi - s_hi) + (t_lo - s_lo), which keeps the difference to a few
-// FP32 ulps of |t - s| even for the closest pairs. FP32 partial sums over
-// NEAR_FLUSH sources of one image are flushed into FP64 accumulators (the
-// rounding error of a blocked FP32 sum grows like the block length).
+// FP32 ulps of |t - s| even for the closest pairs. Laplace/Stokes coordinates
+// are pre-scaled by sigma = 2^k (exact) so that log2 of a typical scaled r^2
+// is near zero; the shift 2k per pair is removed in FP64 at the end. The log
+// terms are accumulated in FP64 pair by pair (one FP64 fma each); the other
+// terms are FP32 partial sums over NEAR_FLUSH sources of one image flushed
+// into FP64 accumulators (the rounding error of a blocked FP32 sum grows like
+// the block length).
 //
 // Accumulators per density:
 //   Laplace/Yukawa (3): sum q g(r), sum q h(r) dx, sum q h(r) dy
@@ -170,8 +178,8 @@ template <> struct alignas(16) SrcPt<true> { float xh, xl, yh, yl; };
 template <> struct alignas(16) SrcPt<false> { double x, y; };
 
 template <int K, bool MIXED, int ND, int NA, typename real>
-__device__ __forceinline__ void near_pair(real dx, real dy, const real* qv, real (&p)[ND][NA], real beta,
-                                          real r2min) {
+__device__ __forceinline__ void near_pair(real dx, real dy, const real* qv, const double* qd, real (&p)[ND][NA],
+                                          double (&acc)[ND][NA], real beta, real r2min) {
   const real r2 = dx * dx + dy * dy;
   if constexpr (K == PFMM_YUKAWA || !MIXED) {
     const bool ok = r2 > (real)0;
@@ -217,11 +225,15 @@ __device__ __forceinline__ void near_pair(real dx, real dy, const real* qv, real
     const real r2s = __builtin_fmaxf(r2, r2min);
     const real lg = __builtin_amdgcn_logf(r2s);
     const real inv = __builtin_amdgcn_rcpf(r2s);
+    // log terms go straight into the FP64 accumulators (their FP32 partial
+    // sums would carry the largest rounding error of the pair sum)
+    const double lgd = (double)lg;
     if constexpr (K == PFMM_LAPLACE) {
 #pragma unroll
       for (int v = 0; v < ND; ++v) {
         const real sq = qv[v] * inv;
-        p[v][0] += qv[v] * lg; p[v][1] += sq * dx; p[v][2] += sq * dy;
+        acc[v][0] = __builtin_fma(qd[v], lgd, acc[v][0]);
+        p[v][1] += sq * dx; p[v][2] += sq * dy;
       }
     } else {
       const real ia = inv * dx, ib = inv * dy;
@@ -230,7 +242,8 @@ __device__ __forceinline__ void near_pair(real dx, real dy, const real* qv, real
         const real F1 = qv[2 * v], F2 = qv[2 * v + 1];
         const real c2 = ia * F1 + ib * F2;
         const real t = c2 * ia;
-        p[v][0] += lg * F1; p[v][1] += lg * F2;
+        acc[v][0] = __builtin_fma(qd[2 * v], lgd, acc[v][0]);
+        acc[v][1] = __builtin_fma(qd[2 * v + 1], lgd, acc[v][1]);
         p[v][2] += c2 * dx; p[v][3] += c2 * dy;
         p[v][4] += c2; p[v][5] += t * dx; p[v][6] += t * dy;
         p[v][7] += F2 * ia - F1 * ib;
@@ -239,37 +252,35 @@ __device__ __forceinline__ void near_pair(real dx, real dy, const real* qv, real
   }
 }
 
-template <int K, bool MIXED, int ND, int TPT>
-__global__ __launch_bounds__(NEAR_BLOCK) void near_kernel(NearArgs a) {
+// One block's share of the near field: targets [tile*NEAR_BLOCK, +NEAR_BLOCK)
+// in binned order against sources of split `split`, ND densities from dens0.
+// Used by the single-cell kernel (block = (tile, split)) and by the batched
+// persistent kernel (block pulls (cell, tile, split) tasks).
+template <int K, bool MIXED, int ND>
+__device__ __forceinline__ void near_block(const NearArgs& a, int64_t tile, int64_t split, SrcPt<MIXED>* s_pt,
+                                           typename std::conditional<MIXED, float, double>::type* s_q,
+                                           double* s_qd) {
   using real = typename std::conditional<MIXED, float, double>::type;
   constexpr int NC = (K == PFMM_STOKES) ? 2 : 1;
   constexpr int NA = NAcc<K>::v;
+  // accumulators [0, NLOG) (the log terms) are summed in FP64 pair by pair
+  constexpr int NLOG = (MIXED && K != PFMM_YUKAWA) ? NC : 0;
   constexpr int NO = (K == PFMM_STOKES) ? 6 : 3;
   constexpr int QN = ND * NC;
-  __shared__ SrcPt<MIXED> s_pt[NEAR_TILE];
-  __shared__ real s_q[NEAR_TILE][QN];
 
   const int tid = threadIdx.x;
-  const int64_t k0 = (int64_t)blockIdx.x * (NEAR_BLOCK * TPT) + tid;
-  double tx[TPT], ty[TPT];
-  int orig[TPT];
-#pragma unroll
-  for (int u = 0; u < TPT; ++u) {
-    const int64_t k = k0 + u * NEAR_BLOCK;
-    const int64_t kk = k < a.n_trg ? k : a.n_trg - 1;
-    tx[u] = a.tx[kk]; ty[u] = a.ty[kk];
-    orig[u] = k < a.n_trg ? a.perm[kk] : -1;
-  }
-  const int64_t s0 = (int64_t)blockIdx.y * a.split_len;
+  const int64_t k = tile * NEAR_BLOCK + tid;
+  const int64_t kk = k < a.n_trg ? k : a.n_trg - 1;
+  const double tx = a.tx[kk], ty = a.ty[kk];
+  const int orig = k < a.n_trg ? a.perm[kk] : -1;
+  const int64_t s0 = split * a.split_len;
   const int64_t s1 = min(s0 + a.split_len, a.n_src);
 
-  double acc[TPT][ND][NA];
+  double acc[ND][NA];
 #pragma unroll
-  for (int u = 0; u < TPT; ++u)
+  for (int v = 0; v < ND; ++v)
 #pragma unroll
-    for (int v = 0; v < ND; ++v)
-#pragma unroll
-      for (int c = 0; c < NA; ++c) acc[u][v][c] = 0.0;
+    for (int c = 0; c < NA; ++c) acc[v][c] = 0.0;
 
   const real beta = (real)a.beta;
   const real r2min = (real)a.r2min;
@@ -282,48 +293,52 @@ __global__ __launch_bounds__(NEAR_BLOCK) void near_kernel(NearArgs a) {
       if constexpr (MIXED) {
         s_pt[tid] = SrcPt<true>{a.sxh[j], a.sxl[j], a.syh[j], a.syl[j]};
 #pragma unroll
-        for (int v = 0; v < QN; ++v) s_q[tid][v] = qscale * a.q32[(size_t)(a.dens0 * NC + v) * a.n_src + j];
+        for (int v = 0; v < QN; ++v) {
+          const size_t at = (size_t)(a.dens0 * NC + v) * a.n_src + j;
+          s_q[tid * QN + v] = qscale * a.q32[at];
+          // log terms take the exact FP64 densities: their sum stays neutral,
+          // so no net-charge term times the log of cell-size distances appears
+          if constexpr (NLOG > 0) s_qd[tid * QN + v] = (double)qscale * a.q64[at];
+        }
       } else {
         s_pt[tid] = SrcPt<false>{a.sx[j], a.sy[j]};
 #pragma unroll
-        for (int v = 0; v < QN; ++v) s_q[tid][v] = qscale * a.q64[(size_t)(a.dens0 * NC + v) * a.n_src + j];
+        for (int v = 0; v < QN; ++v) s_q[tid * QN + v] = qscale * a.q64[(size_t)(a.dens0 * NC + v) * a.n_src + j];
       }
     }
     __syncthreads();
     for (int im = 0; im < a.geo.n_images; ++im) {
-      real th[TPT], tl[TPT], uh[TPT], ul[TPT];
-#pragma unroll
-      for (int u = 0; u < TPT; ++u) {
-        const double txi = tx[u] - a.geo.img_x[im], tyi = ty[u] - a.geo.img_y[im];
-        th[u] = (real)txi; uh[u] = (real)tyi;
-        if constexpr (MIXED) { tl[u] = (real)(txi - (double)th[u]); ul[u] = (real)(tyi - (double)uh[u]); }
-        else { tl[u] = 0; ul[u] = 0; }
-      }
+      double txi = tx - a.geo.img_x[im], tyi = ty - a.geo.img_y[im];
+      if constexpr (MIXED) { txi *= a.geo.sigma; tyi *= a.geo.sigma; }
+      real th, tl, uh, ul;
+      th = (real)txi; uh = (real)tyi;
+      if constexpr (MIXED) { tl = (real)(txi - (double)th); ul = (real)(tyi - (double)uh); }
+      else { tl = 0; ul = 0; }
       for (int jb = 0; jb < nt; jb += NEAR_FLUSH) {
-        real p[TPT][ND][NA];
+        real p[ND][NA];
 #pragma unroll
-        for (int u = 0; u < TPT; ++u)
+        for (int v = 0; v < ND; ++v)
 #pragma unroll
-          for (int v = 0; v < ND; ++v)
-#pragma unroll
-            for (int c = 0; c < NA; ++c) p[u][v][c] = 0;
+          for (int c = 0; c < NA; ++c) p[v][c] = 0;
         auto body = [&](int j) {
           const SrcPt<MIXED> sp = s_pt[j];
           real qv[QN];
+          double qd[NLOG > 0 ? QN : 1];
 #pragma unroll
-          for (int v = 0; v < QN; ++v) qv[v] = s_q[j][v];
+          for (int v = 0; v < QN; ++v) qv[v] = s_q[j * QN + v];
+          if constexpr (NLOG > 0) {
 #pragma unroll
-          for (int u = 0; u < TPT; ++u) {
-            real dx, dy;
-            if constexpr (MIXED) {
-              dx = (th[u] - sp.xh) + (tl[u] - sp.xl);
-              dy = (uh[u] - sp.yh) + (ul[u] - sp.yl);
-            } else {
-              dx = th[u] - sp.x;
-              dy = uh[u] - sp.y;
-            }
-            near_pair<K, MIXED, ND, NA, real>(dx, dy, qv, p[u], beta, r2min);
+            for (int v = 0; v < QN; ++v) qd[v] = s_qd[j * QN + v];
           }
+          real dx, dy;
+          if constexpr (MIXED) {
+            dx = (th - sp.xh) + (tl - sp.xl);
+            dy = (uh - sp.yh) + (ul - sp.yl);
+          } else {
+            dx = th - sp.x;
+            dy = uh - sp.y;
+          }
+          near_pair<K, MIXED, ND, NA, real>(dx, dy, qv, qd, p, acc, beta, r2min);
         };
         if (jb + NEAR_FLUSH <= nt) {
 #pragma unroll
@@ -332,84 +347,162 @@ __global__ __launch_bounds__(NEAR_BLOCK) void near_kernel(NearArgs a) {
           for (int j = jb; j < nt; ++j) body(j);
         }
 #pragma unroll
-        for (int u = 0; u < TPT; ++u)
+        for (int v = 0; v < ND; ++v)
 #pragma unroll
-          for (int v = 0; v < ND; ++v)
-#pragma unroll
-            for (int c = 0; c < NA; ++c) acc[u][v][c] += (double)p[u][v][c];
+          for (int c = NLOG; c < NA; ++c) acc[v][c] += (double)p[v][c];
       }
     }
   }
+  if (orig < 0) return;
   const double inv4pi = 1.0 / (4 * PI), inv2pi = 1.0 / (2 * PI);
   const double lscale = MIXED ? 0.69314718055994530942 : 1.0;  // log2 -> ln
-  double* dst = a.part + (size_t)blockIdx.y * a.part_stride;
-  // value of lg at the clamped self pair (mixed Laplace/Stokes only)
-  double lg_self = 0.0;
-  if constexpr (MIXED && K != PFMM_YUKAWA) lg_self = (double)__builtin_amdgcn_logf((float)a.r2min);
-#pragma unroll
-  for (int u = 0; u < TPT; ++u) {
-    const int i = orig[u];
-    if (i < 0) continue;
-    if constexpr (MIXED && K != PFMM_YUKAWA) {
-      if (a.self && i >= s0 && i < s1) {
-#pragma unroll
-        for (int v = 0; v < ND; ++v) {
-          if constexpr (K == PFMM_LAPLACE) {
-            acc[u][v][0] -= lg_self * (double)a.q32[(size_t)(a.dens0 + v) * a.n_src + i];
-          } else {
-            acc[u][v][0] -= lg_self * (double)(2.0f * a.q32[(size_t)((a.dens0 + v) * 2) * a.n_src + i]);
-            acc[u][v][1] -= lg_self * (double)(2.0f * a.q32[(size_t)((a.dens0 + v) * 2 + 1) * a.n_src + i]);
-          }
-        }
-      }
-    }
+  double* dst = a.part + (size_t)split * a.part_stride;
+  double gscale = 1.0;   // gradients in scaled coordinates -> physical
+  if constexpr (MIXED && K != PFMM_YUKAWA) {
+    gscale = a.geo.sigma;
+    // the self pair was evaluated at the clamped r^2: remove its exact value
+    const double lg_self = (double)__builtin_amdgcn_logf((float)a.r2min);
+    const int i = orig;
+    const bool self_here = a.self && i >= s0 && i < s1;
+    // log2 of the scaled r^2 is log2 r^2 + lg_shift for every other pair of
+    // the split: remove lg_shift * (images * sum of the split's densities - own)
+    const double ls = (double)a.geo.lg_shift;
 #pragma unroll
     for (int v = 0; v < ND; ++v) {
-      double o[NO];
-      const double* A = acc[u][v];
-      if constexpr (K == PFMM_LAPLACE) {
-        o[0] = -inv4pi * lscale * A[0];
-        o[1] = -inv2pi * A[1];
-        o[2] = -inv2pi * A[2];
-      } else if constexpr (K == PFMM_YUKAWA) {
-        o[0] = inv2pi * A[0];
-        o[1] = -a.beta * a.beta * inv2pi * A[1];
-        o[2] = -a.beta * a.beta * inv2pi * A[2];
-      } else {
-        // (F = 2f): u_i = (1/4pi)[-(1/2) sum lg f_i + sum c r_i],
-        // du1/dx = -du2/dy = (1/4pi) sum (c - 2 c dx^2/r^2),
-        // du1/dy = (1/4pi)[W - B], du2/dx = (1/4pi)[-W - B],
-        // W = sum (f2 dx - f1 dy)/r^2, B = 2 sum c dx dy/r^2
-        const double h = 0.5 * inv4pi;
-        o[0] = h * (-0.5 * lscale * A[0] + A[2]);
-        o[1] = h * (-0.5 * lscale * A[1] + A[3]);
-        o[2] = h * (A[4] - 2 * A[5]);
-        o[3] = h * (A[7] - 2 * A[6]);
-        o[4] = h * (-A[7] - 2 * A[6]);
-        o[5] = -o[2];
-      }
 #pragma unroll
-      for (int c = 0; c < NO; ++c) dst[(size_t)((a.dens0 + v) * NO + c) * a.n_trg + i] = o[c];
+      for (int c = 0; c < NC; ++c) {
+        const int comp = (a.dens0 + v) * NC + c;
+        const double own = self_here ? (double)qscale * a.q64[(size_t)comp * a.n_src + i] : 0.0;
+        double corr = self_here ? lg_self * own : 0.0;
+        if (a.qsum) corr += ls * ((double)a.geo.n_images * (double)qscale * a.qsum[(size_t)split * a.qsum_stride + comp] - own);
+        acc[v][c] -= corr;
+      }
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < ND; ++v) {
+    double o[NO];
+    const double* A = acc[v];
+    if constexpr (K == PFMM_LAPLACE) {
+      o[0] = -inv4pi * lscale * A[0];
+      o[1] = -inv2pi * gscale * A[1];
+      o[2] = -inv2pi * gscale * A[2];
+    } else if constexpr (K == PFMM_YUKAWA) {
+      o[0] = inv2pi * A[0];
+      o[1] = -a.beta * a.beta * inv2pi * A[1];
+      o[2] = -a.beta * a.beta * inv2pi * A[2];
+    } else {
+      // (F = 2f): u_i = (1/4pi)[-(1/2) sum lg f_i + sum c r_i],
+      // du1/dx = -du2/dy = (1/4pi) sum (c - 2 c dx^2/r^2),
+      // du1/dy = (1/4pi)[W - B], du2/dx = (1/4pi)[-W - B],
+      // W = sum (f2 dx - f1 dy)/r^2, B = 2 sum c dx dy/r^2
+      const double h = 0.5 * inv4pi;
+      o[0] = h * (-0.5 * lscale * A[0] + A[2]);
+      o[1] = h * (-0.5 * lscale * A[1] + A[3]);
+      o[2] = h * gscale * (A[4] - 2 * A[5]);
+      o[3] = h * gscale * (A[7] - 2 * A[6]);
+      o[4] = h * gscale * (-A[7] - 2 * A[6]);
+      o[5] = -o[2];
+    }
+#pragma unroll
+    for (int c = 0; c < NO; ++c) dst[(size_t)((a.dens0 + v) * NO + c) * a.n_trg + k] = o[c];
+  }
+}
+
+template <int K, bool MIXED, int ND>
+__global__ __launch_bounds__(NEAR_BLOCK) void near_kernel(NearArgs a) {
+  using real = typename std::conditional<MIXED, float, double>::type;
+  constexpr int QN = ND * ((K == PFMM_STOKES) ? 2 : 1);
+  constexpr int QD = (MIXED && K != PFMM_YUKAWA) ? NEAR_TILE * QN : 1;
+  __shared__ SrcPt<MIXED> s_pt[NEAR_TILE];
+  __shared__ real s_q[NEAR_TILE * QN];
+  __shared__ double s_qd[QD];
+  near_block<K, MIXED, ND>(a, blockIdx.x, blockIdx.y, s_pt, s_q, s_qd);
+}
+
+// Batched near field: a persistent grid; each block takes (cell, tile, split)
+// tasks from an atomic counter until none are left (every block reaches the
+// exit once the counter passes n_tasks).
+template <bool MIXED>
+__global__ __launch_bounds__(NEAR_BLOCK) void near_batch_kernel(BatchNearArgs b) {
+  using real = typename std::conditional<MIXED, float, double>::type;
+  __shared__ SrcPt<MIXED> s_pt[NEAR_TILE];
+  __shared__ real s_q[NEAR_TILE * 8];
+  __shared__ double s_qd[MIXED ? NEAR_TILE * 8 : 1];
+  __shared__ long long s_task;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) s_task = (long long)atomicAdd(b.counter, 1ULL);
+    __syncthreads();
+    const long long t = s_task;
+    if (t >= b.n_tasks) break;
+    int c = 0;
+    while (c + 1 < b.n_cells && b.recs[c + 1].task0 <= t) ++c;
+    const BatchCell& r = b.recs[c];
+    const long long local = t - r.task0;
+    const int64_t tile = local % r.n_tiles, split = local / r.n_tiles;
+    NearArgs a = r.args;
+    char* ws = b.ws;
+    a.sx = (const double*)(ws + r.o_sx); a.sy = (const double*)(ws + r.o_sy);
+    a.sxh = (const float*)(ws + r.o_sxh); a.sxl = (const float*)(ws + r.o_sxl);
+    a.syh = (const float*)(ws + r.o_syh); a.syl = (const float*)(ws + r.o_syl);
+    a.q64 = (const double*)(ws + r.o_q64); a.q32 = (const float*)(ws + r.o_q32);
+    a.tx = (const double*)(ws + r.o_tx); a.ty = (const double*)(ws + r.o_ty);
+    a.perm = (const int*)(ws + r.o_perm); a.part = (double*)(ws + r.o_part);
+    a.qsum = r.o_qsum ? (const double*)(ws + r.o_qsum) : nullptr;
+    const int kern = r.kernel, nd = r.n_dens;
+    int v = 0;
+    if (kern == PFMM_LAPLACE) {
+      for (; v + 4 <= nd; v += 4) { a.dens0 = v; near_block<PFMM_LAPLACE, MIXED, 4>(a, tile, split, s_pt, s_q, s_qd); }
+      for (; v < nd; ++v) { a.dens0 = v; near_block<PFMM_LAPLACE, MIXED, 1>(a, tile, split, s_pt, s_q, s_qd); }
+    } else if (kern == PFMM_YUKAWA) {
+      for (; v + 4 <= nd; v += 4) { a.dens0 = v; near_block<PFMM_YUKAWA, MIXED, 4>(a, tile, split, s_pt, s_q, s_qd); }
+      for (; v < nd; ++v) { a.dens0 = v; near_block<PFMM_YUKAWA, MIXED, 1>(a, tile, split, s_pt, s_q, s_qd); }
+    } else {
+      for (; v + 4 <= nd; v += 4) { a.dens0 = v; near_block<PFMM_STOKES, MIXED, 4>(a, tile, split, s_pt, s_q, s_qd); }
+      for (; v < nd; ++v) { a.dens0 = v; near_block<PFMM_STOKES, MIXED, 1>(a, tile, split, s_pt, s_q, s_qd); }
     }
   }
 }
 
+// per-split sums of the FP64 densities, used to remove the log2 shift
+__global__ __launch_bounds__(256) void qsum_kernel(QsumArgs a) {
+  __shared__ double red[256];
+  const int64_t s0 = (int64_t)blockIdx.x * a.split_len;
+  const int64_t s1 = min(s0 + a.split_len, a.n_src);
+  const int comp = blockIdx.y;
+  double s = 0.0;
+  for (int64_t j = s0 + threadIdx.x; j < s1; j += 256) s += a.q64[(size_t)comp * a.n_src + j];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.qsum[(size_t)blockIdx.x * a.ncomp + comp] = red[0];
+}
+
+void launch_qsum(const QsumArgs& a, int n_splits, hipStream_t s) {
+  if (a.n_src <= 0 || n_splits <= 0) return;
+  hipLaunchKernelGGL(qsum_kernel, dim3(n_splits, a.ncomp), dim3(256), 0, s, a);
+}
+
+void launch_near_batch(bool mixed, const BatchNearArgs& b, int grid, hipStream_t s) {
+  if (b.n_tasks <= 0) return;
+  if (mixed) hipLaunchKernelGGL(near_batch_kernel<true>, dim3(grid), dim3(NEAR_BLOCK), 0, s, b);
+  else hipLaunchKernelGGL(near_batch_kernel<false>, dim3(grid), dim3(NEAR_BLOCK), 0, s, b);
+}
+
 void launch_near(int kernel, bool mixed, int nd, const NearArgs& a, int n_splits, hipStream_t s) {
   if (a.n_trg <= 0 || a.n_src <= 0) return;
-  // four-density groups use one target per thread (grid sized for TPT = 1)
   NearArgs b = a;
+  const dim3 grid((unsigned)((a.n_trg + NEAR_BLOCK - 1) / NEAR_BLOCK), (unsigned)n_splits);
   auto go = [&](auto kc, auto mc) {
     constexpr int K = decltype(kc)::value;
     constexpr bool M = decltype(mc)::value;
-    if (nd >= 4) {
-      dim3 g1((unsigned)((a.n_trg + NEAR_BLOCK - 1) / NEAR_BLOCK), (unsigned)n_splits);
-      int v = 0;
-      for (; v + 4 <= nd; v += 4) { b.dens0 = v; hipLaunchKernelGGL((near_kernel<K, M, 4, 1>), g1, dim3(NEAR_BLOCK), 0, s, b); }
-      for (; v < nd; ++v) { b.dens0 = v; hipLaunchKernelGGL((near_kernel<K, M, 1, 1>), g1, dim3(NEAR_BLOCK), 0, s, b); }
-    } else {
-      dim3 g2((unsigned)((a.n_trg + NEAR_BLOCK * NEAR_TPT - 1) / (NEAR_BLOCK * NEAR_TPT)), (unsigned)n_splits);
-      for (int v = 0; v < nd; ++v) { b.dens0 = v; hipLaunchKernelGGL((near_kernel<K, M, 1, NEAR_TPT>), g2, dim3(NEAR_BLOCK), 0, s, b); }
-    }
+    int v = 0;
+    for (; v + 4 <= nd; v += 4) { b.dens0 = v; hipLaunchKernelGGL((near_kernel<K, M, 4>), grid, dim3(NEAR_BLOCK), 0, s, b); }
+    for (; v < nd; ++v) { b.dens0 = v; hipLaunchKernelGGL((near_kernel<K, M, 1>), grid, dim3(NEAR_BLOCK), 0, s, b); }
   };
   using L = std::integral_constant<int, PFMM_LAPLACE>;
   using Y = std::integral_constant<int, PFMM_YUKAWA>;
@@ -689,8 +782,9 @@ void launch_far_D(const FarDArgs& a, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// far L (+ combine): per target, sum the plane waves, add the near partials
-// of every split in fixed order, rotate back to the user frame and write.
+// far L (+ combine): per target (in binned order, like the near partials),
+// sum the plane waves, add the near partials of every split in fixed order,
+// rotate back to the user frame and write at the target's original index.
 //   scalar south/north: u += Re[(w^S e^{-a y} + w^N e^{a y}) e^{i alpha x}]
 //   scalar west/east:   u += Re[e^{i lam y}(cosh(kap x) S + sinh(kap x) D)]
 //   Laplace m = 0 (Thm. south_thm_lap and corollary, plus the zero-mean
@@ -702,9 +796,10 @@ template <int K>
 __global__ __launch_bounds__(256) void far_L_kernel(FarLArgs a) {
   constexpr int NO = (K == PFMM_STOKES) ? 6 : 3;
   constexpr int NCW = (K == PFMM_STOKES) ? 8 : 2;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.n_trg) return;
-  const double x = a.tx[i], y = a.ty[i];
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // binned position
+  if (k >= a.n_trg) return;
+  const int64_t i = a.perm[k];                                          // original index
+  const double x = a.tx[k], y = a.ty[k];
   const double* sn_tab = a.tab;
   const double* ew_tab = a.tab + (size_t)a.n_sn * SN_REC;
   for (int v = 0; v < a.n_dens; ++v) {
@@ -776,12 +871,12 @@ __global__ __launch_bounds__(256) void far_L_kernel(FarLArgs a) {
     }
     if (a.nufft) {
 #pragma unroll
-      for (int c = 0; c < NO; ++c) o[c] += a.nu_val[((size_t)v * NO + c) * a.n_trg + i];
+      for (int c = 0; c < NO; ++c) o[c] += a.nu_val[((size_t)v * NO + c) * a.n_trg + k];
     }
     for (int s = 0; s < a.n_splits; ++s) {
       const double* p = a.near_part + (size_t)s * a.part_stride;
 #pragma unroll
-      for (int c = 0; c < NO; ++c) o[c] += p[((size_t)v * NO + c) * a.n_trg + i];
+      for (int c = 0; c < NO; ++c) o[c] += p[((size_t)v * NO + c) * a.n_trg + k];
     }
     // back to the user frame: user = R^T canonical
     const double rc = a.rc, rs = a.rs;
@@ -793,19 +888,21 @@ __global__ __launch_bounds__(256) void far_L_kernel(FarLArgs a) {
       const double t21 = -rs * j11 + rc * j21, t22 = -rs * j12 + rc * j22;
       const double g11 = t11 * rc + t12 * rs, g12 = -t11 * rs + t12 * rc; // (R^T J) R
       const double g21 = t21 * rc + t22 * rs, g22 = -t21 * rs + t22 * rc;
+      const int64_t os = a.out_stride;
       if (a.out_pot) {
-        a.out_pot[((size_t)v * 2) * a.n_trg + i] = u1;
-        a.out_pot[((size_t)v * 2 + 1) * a.n_trg + i] = u2;
+        a.out_pot[((size_t)v * 2) * os + i] = u1;
+        a.out_pot[((size_t)v * 2 + 1) * os + i] = u2;
       }
       if (a.out_grad) {
-        double* g = a.out_grad + (size_t)v * 4 * a.n_trg;
-        g[i] = g11; g[a.n_trg + i] = g12; g[2 * a.n_trg + i] = g21; g[3 * a.n_trg + i] = g22;
+        double* g = a.out_grad + (size_t)v * 4 * os;
+        g[i] = g11; g[os + i] = g12; g[2 * os + i] = g21; g[3 * os + i] = g22;
       }
     } else {
-      if (a.out_pot) a.out_pot[(size_t)v * a.n_trg + i] = o[0];
+      const int64_t os = a.out_stride;
+      if (a.out_pot) a.out_pot[(size_t)v * os + i] = o[0];
       if (a.out_grad) {
-        a.out_grad[((size_t)v * 2) * a.n_trg + i] = rc * o[1] + rs * o[2];
-        a.out_grad[((size_t)v * 2 + 1) * a.n_trg + i] = -rs * o[1] + rc * o[2];
+        a.out_grad[((size_t)v * 2) * os + i] = rc * o[1] + rs * o[2];
+        a.out_grad[((size_t)v * 2 + 1) * os + i] = -rs * o[1] + rc * o[2];
       }
     }
   }

@@ -18,6 +18,11 @@ struct Geometry {
   double rc, rs;                 // canonical = R * user, R = [[rc,-rs],[rs,rc]]
   int n_images;
   double img_x[MAX_IMAGES], img_y[MAX_IMAGES];
+  // mixed Laplace/Stokes near field: coordinates are scaled by sigma = 2^k
+  // (exact) so that sigma^2 * cell area ~ 1, which keeps |log2 r^2| small for
+  // most pairs; log2 r^2 is then shifted by lg_shift = 2k, removed in FP64
+  double sigma;
+  int lg_shift;
 };
 
 // Per south/north mode record (doubles), mode index m = m_lo + i:
@@ -80,6 +85,7 @@ int build_plan(int kernel, const double* e1, const double* e2, double tol,
                const pfmm_opts* opts, pfmm_plan_s* p);
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
 // one evaluation with the plan's current n_dens (capi.hip)
+size_t cell_workspace(pfmm_plan_s* p, int64_t ns, int64_t nt, int64_t forced_split);
 int eval_core(pfmm_plan_s* p, int64_t ns, const double* src_xy, const double* dens, int64_t nt,
               const double* trg_xy, double* out_pot, double* out_grad, void* workspace,
               size_t ws_bytes, void* hip_stream);

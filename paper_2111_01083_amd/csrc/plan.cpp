@@ -149,6 +149,13 @@ int build_plan(int kernel, const double* e1, const double* e2, double tol, const
 
   // --- near region (Def. 1): m0 = 1 keeps the closest west/east image at
   // x-distance >= d - 2|xi| (Thm. west_thm proof); require that to be >= d/2.
+  g.sigma = 1.0;
+  g.lg_shift = 0;
+  if (o.precision == PFMM_MIXED && kernel != PFMM_YUKAWA) {
+    const int k = (int)std::lround(-0.5 * std::log2(d * eta));
+    g.sigma = std::ldexp(1.0, k);
+    g.lg_shift = 2 * k;
+  }
   int m0 = std::fabs(xi) <= 0.25 * d ? 1 : 2;
   if (o.m0 > 0) m0 = std::max(m0, o.m0);
   p->m0 = m0;
