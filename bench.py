@@ -23,9 +23,9 @@ sys.path.insert(0, ROOT)
 METRIC = "targets/sec (pot+grad) at 1e-6 rel err, mixed vs FP64 GPU path; % FP32/HBM roofline"
 # algorithmic flops per target/source/image pair of the near-field kernels
 # (add/mul = 1, fma = 2, transcendental = 1; counted from the kernel source,
-# large-argument branch for K0/K1; the two-float coordinate corrections and
-# the r = 0 guards are not counted)
-FLOPS_PER_PAIR = {"laplace": 15, "yukawa": 51, "stokes": 31}
+# large-argument branch for K0/K1; FP64/FP32 conversions and the r = 0
+# guards are not counted)
+FLOPS_PER_PAIR = {"laplace": 14, "yukawa": 51, "stokes": 30}
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 
 

@@ -21,7 +21,7 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Workspace carve-up for one cell; offsets in bytes from the workspace base.
 struct Layout {
-  size_t scx, scy, tcx, tcy, sxh, sxl, syh, syl, q32, dens_c, near_part, far_part, w, nufft, nu_val;
+  size_t scx, scy, tcx, tcy, q32, dens_c, near_part, far_part, w, nufft, nu_val;
   size_t key, perm, stx, sty, hist, cursor;   // target binning
   size_t qsum;                                // per-split FP32 density sums (mixed Laplace/Stokes)
   int nbx, nby;
@@ -43,10 +43,9 @@ void plan_layout(const pfmm_plan_s* p, int64_t ns, int64_t nt, Layout& L, int64_
   if (p->self_exclude) { L.tcx = L.scx; L.tcy = L.scy; }
   else { L.tcx = take(8 * nt); L.tcy = take(8 * nt); }
   if (mixed) {
-    L.sxh = take(4 * ns); L.sxl = take(4 * ns); L.syh = take(4 * ns); L.syl = take(4 * ns);
     L.q32 = take(4 * (size_t)p->n_dens * nc * ns);
   } else {
-    L.sxh = L.sxl = L.syh = L.syl = L.q32 = 0;
+    L.q32 = 0;
   }
   L.dens_c = take(8 * (size_t)p->n_dens * nc * ns);   // contiguous FP64 densities (Stokes: rotated)
   // target bins of about 64 points over the canonical cell's bounding box
@@ -194,13 +193,10 @@ static void cell_prep(CellRun& r, const double* src_xy, int64_t src_stride, cons
   PrepArgs pa{};
   pa.rc = g.rc; pa.rs = g.rs; pa.d = g.d; pa.xi = g.xi; pa.eta = g.eta;
   pa.n = r.ns; pa.ystride = src_stride; pa.xy = src_xy; pa.cx = D(L.scx); pa.cy = D(L.scy);
-  pa.sigma = g.sigma;
-  if (mixed) { pa.hx = F(L.sxh); pa.lx = F(L.sxl); pa.hy = F(L.syh); pa.ly = F(L.syl); }
   launch_prep_points(pa, st);
   if (!p->self_exclude) {
     PrepArgs pt = pa;
     pt.n = r.nt; pt.ystride = trg_stride; pt.xy = trg_xy; pt.cx = D(L.tcx); pt.cy = D(L.tcy);
-    pt.hx = pt.lx = pt.hy = pt.ly = nullptr;
     launch_prep_points(pt, st);
   }
   PrepDensArgs pd{};
@@ -237,7 +233,7 @@ static NearArgs cell_near_args(const CellRun& r) {
   na.n_src = r.ns; na.n_trg = r.nt; na.split_len = L.split_len;
   na.sx = D(L.scx); na.sy = D(L.scy);
   if (p->precision == PFMM_MIXED) {
-    na.sxh = F(L.sxh); na.sxl = F(L.sxl); na.syh = F(L.syh); na.syl = F(L.syl); na.q32 = F(L.q32);
+    na.q32 = F(L.q32);
   }
   na.q64 = D(L.dens_c);
   na.tx = D(L.stx); na.ty = D(L.sty); na.perm = (const int*)(ws + L.perm);
@@ -482,8 +478,6 @@ int pfmm_batch_create(int n_cells, const pfmm_plan_t* plans, const int64_t* src_
     const Layout& L = r.L;
     const bool mixed = b->mixed;
     bc.o_sx = B + L.scx; bc.o_sy = B + L.scy;
-    bc.o_sxh = mixed ? B + L.sxh : 0; bc.o_sxl = mixed ? B + L.sxl : 0;
-    bc.o_syh = mixed ? B + L.syh : 0; bc.o_syl = mixed ? B + L.syl : 0;
     bc.o_q64 = B + L.dens_c; bc.o_q32 = mixed ? B + L.q32 : 0;
     bc.o_tx = B + L.stx; bc.o_ty = B + L.sty; bc.o_perm = B + L.perm; bc.o_part = B + L.near_part;
     bc.o_qsum = L.qsum ? B + L.qsum : 0;

@@ -24,8 +24,6 @@ struct PrepArgs {
   const double* xy;          // [2][*] user frame
   double rc, rs, d, xi, eta;
   double *cx, *cy;           // canonical FP64
-  float *hx, *lx, *hy, *ly;  // two-float copies of sigma * (x, y) (NULL unless mixed)
-  double sigma;
 };
 
 struct PrepDensArgs {
@@ -41,7 +39,6 @@ struct NearArgs {
   Geometry geo;
   int64_t n_src, n_trg, split_len;
   const double *sx, *sy;                 // FP64 sources
-  const float *sxh, *sxl, *syh, *syl;    // two-float sources
   const double* q64;                     // densities [n_dens][nc][n_src]
   const float* q32;
   int dens0;                             // first density of this launch
@@ -49,7 +46,7 @@ struct NearArgs {
   const int* perm;                       // binned position -> original target index
   int self;                              // targets are the sources (same indices)
   double beta, r2min;
-  const double* qsum;                    // mixed Laplace/Stokes: per split, sum of the FP32
+  const double* qsum;                    // mixed Laplace/Stokes: per split, sum of the
                                          // densities [split][qsum_stride] (NULL: no log shift)
   int qsum_stride;                       // n_dens * nc
   double* part;                          // [split][n_dens*NOUT][n_trg]
@@ -112,7 +109,7 @@ struct BatchCell {
   NearArgs args;             // sizes, geometry, beta, split length, flags
   int kernel, n_dens, n_tiles;
   long long task0;           // first task index of this cell
-  int64_t o_sx, o_sy, o_sxh, o_sxl, o_syh, o_syl, o_q64, o_q32, o_tx, o_ty, o_perm, o_part, o_qsum;
+  int64_t o_sx, o_sy, o_q64, o_q32, o_tx, o_ty, o_perm, o_part, o_qsum;
 };
 
 struct BatchNearArgs {

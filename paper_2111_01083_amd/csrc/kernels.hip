@@ -29,12 +29,6 @@ __global__ void prep_points_kernel(PrepArgs a) {
   xc -= k1 * a.d;
   a.cx[i] = xc;
   a.cy[i] = yc;
-  if (a.hx) {
-    const double xs = xc * a.sigma, ys = yc * a.sigma;   // exact: sigma is a power of two
-    float xh = (float)xs, yh = (float)ys;
-    a.hx[i] = xh; a.lx[i] = (float)(xs - (double)xh);
-    a.hy[i] = yh; a.ly[i] = (float)(ys - (double)yh);
-  }
 }
 
 __global__ void prep_dens_kernel(PrepDensArgs a) {
@@ -147,10 +141,10 @@ void launch_fill_zero(double* p, int64_t n, hipStream_t s) {
 // tile, source split); split y writes partial sums to
 // part[y][dens*NOUT + c][n_trg] (FP64) in binned target order.
 //
-// MIXED: pair arithmetic in FP32. Coordinates are two-float (hi + lo) and
-// t - s = (t_hi - s_hi) + (t_lo - s_lo), which keeps the difference to a few
-// FP32 ulps of |t - s| even for the closest pairs. Laplace/Stokes coordinates
-// are pre-scaled by sigma = 2^k (exact) so that log2 of a typical scaled r^2
+// MIXED: pair arithmetic in FP32 except the coordinate difference, which is
+// taken in FP64 (full rate on CDNA4, exact for close pairs) and rounded once
+// to FP32, so dx carries half an FP32 ulp of |dx| even for the closest pairs.
+// Laplace/Stokes coordinates are pre-scaled by sigma = 2^k (exact) so that log2 of a typical scaled r^2
 // is near zero; the shift 2k per pair is removed in FP64 at the end. The log
 // terms are accumulated in FP64 pair by pair (one FP64 fma each); the other
 // terms are FP32 partial sums over NEAR_FLUSH sources of one image flushed
@@ -163,25 +157,23 @@ void launch_fill_zero(double* p, int64_t n, hipStream_t s) {
 //     sum lg F1, sum lg F2, sum c2 dx, sum c2 dy, sum c2, sum c2 a dx,
 //     sum c2 a dy, sum (F2 a - F1 b)
 //
-// r = 0: Laplace/Stokes clamp r^2 to R2MIN (an exact power of two); the only
-// such pair in a self-excluding evaluation is the self pair, whose clamped
-// value lg(R2MIN) * density is removed exactly in FP64 at the end (the
-// gradient terms vanish because dx = dy = 0). Yukawa (and the FP64 path)
+// r = 0: Laplace/Stokes evaluate at r^2 + R2MIN (R2MIN = 2^-60, so log2 is
+// exact for the self pair, the only pair with r = 0 in a self-excluding
+// evaluation); its value lg(R2MIN) * density is removed exactly in FP64 at
+// the end (the gradient terms vanish because dx = dy = 0). Yukawa (and the FP64 path)
 // zero the pair with a select. Exactly coincident distinct points are a
 // singularity of the sum and are not supported.
 // ---------------------------------------------------------------------------
 template <int K> struct NAcc { static constexpr int v = 3; };
 template <> struct NAcc<PFMM_STOKES> { static constexpr int v = 8; };
 
-template <bool MIXED> struct SrcPt;
-template <> struct alignas(16) SrcPt<true> { float xh, xl, yh, yl; };
-template <> struct alignas(16) SrcPt<false> { double x, y; };
+struct alignas(16) SrcPt { double x, y; };
 
 template <int K, bool MIXED, int ND, int NA, typename real>
 __device__ __forceinline__ void near_pair(real dx, real dy, const real* qv, const double* qd, real (&p)[ND][NA],
                                           double (&acc)[ND][NA], real beta, real r2min) {
-  const real r2 = dx * dx + dy * dy;
   if constexpr (K == PFMM_YUKAWA || !MIXED) {
+    const real r2 = dx * dx + dy * dy;
     const bool ok = r2 > (real)0;
     const real r2s = ok ? r2 : (real)1;
     if constexpr (K == PFMM_YUKAWA) {
@@ -222,7 +214,9 @@ __device__ __forceinline__ void near_pair(real dx, real dy, const real* qv, cons
       return;
     }
   } else {
-    const real r2s = __builtin_fmaxf(r2, r2min);
+    // r^2 + R2MIN: exactly R2MIN for the self pair, below half an ulp of r^2
+    // for every pair with scaled r^2 >= 2^-36
+    const real r2s = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, r2min));
     const real lg = __builtin_amdgcn_logf(r2s);
     const real inv = __builtin_amdgcn_rcpf(r2s);
     // log terms go straight into the FP64 accumulators (their FP32 partial
@@ -257,7 +251,7 @@ __device__ __forceinline__ void near_pair(real dx, real dy, const real* qv, cons
 // Used by the single-cell kernel (block = (tile, split)) and by the batched
 // persistent kernel (block pulls (cell, tile, split) tasks).
 template <int K, bool MIXED, int ND>
-__device__ __forceinline__ void near_block(const NearArgs& a, int64_t tile, int64_t split, SrcPt<MIXED>* s_pt,
+__device__ __forceinline__ void near_block(const NearArgs& a, int64_t tile, int64_t split, SrcPt* s_pt,
                                            typename std::conditional<MIXED, float, double>::type* s_q,
                                            double* s_qd) {
   using real = typename std::conditional<MIXED, float, double>::type;
@@ -290,8 +284,8 @@ __device__ __forceinline__ void near_block(const NearArgs& a, int64_t tile, int6
     __syncthreads();
     if (tid < nt) {
       const int64_t j = base + tid;
+      s_pt[tid] = SrcPt{a.sx[j] * a.geo.sigma, a.sy[j] * a.geo.sigma};   // exact scaling
       if constexpr (MIXED) {
-        s_pt[tid] = SrcPt<true>{a.sxh[j], a.sxl[j], a.syh[j], a.syl[j]};
 #pragma unroll
         for (int v = 0; v < QN; ++v) {
           const size_t at = (size_t)(a.dens0 * NC + v) * a.n_src + j;
@@ -301,19 +295,13 @@ __device__ __forceinline__ void near_block(const NearArgs& a, int64_t tile, int6
           if constexpr (NLOG > 0) s_qd[tid * QN + v] = (double)qscale * a.q64[at];
         }
       } else {
-        s_pt[tid] = SrcPt<false>{a.sx[j], a.sy[j]};
 #pragma unroll
         for (int v = 0; v < QN; ++v) s_q[tid * QN + v] = qscale * a.q64[(size_t)(a.dens0 * NC + v) * a.n_src + j];
       }
     }
     __syncthreads();
     for (int im = 0; im < a.geo.n_images; ++im) {
-      double txi = tx - a.geo.img_x[im], tyi = ty - a.geo.img_y[im];
-      if constexpr (MIXED) { txi *= a.geo.sigma; tyi *= a.geo.sigma; }
-      real th, tl, uh, ul;
-      th = (real)txi; uh = (real)tyi;
-      if constexpr (MIXED) { tl = (real)(txi - (double)th); ul = (real)(tyi - (double)uh); }
-      else { tl = 0; ul = 0; }
+      const double txi = (tx - a.geo.img_x[im]) * a.geo.sigma, tyi = (ty - a.geo.img_y[im]) * a.geo.sigma;
       for (int jb = 0; jb < nt; jb += NEAR_FLUSH) {
         real p[ND][NA];
 #pragma unroll
@@ -321,7 +309,7 @@ __device__ __forceinline__ void near_block(const NearArgs& a, int64_t tile, int6
 #pragma unroll
           for (int c = 0; c < NA; ++c) p[v][c] = 0;
         auto body = [&](int j) {
-          const SrcPt<MIXED> sp = s_pt[j];
+          const SrcPt sp = s_pt[j];
           real qv[QN];
           double qd[NLOG > 0 ? QN : 1];
 #pragma unroll
@@ -330,14 +318,8 @@ __device__ __forceinline__ void near_block(const NearArgs& a, int64_t tile, int6
 #pragma unroll
             for (int v = 0; v < QN; ++v) qd[v] = s_qd[j * QN + v];
           }
-          real dx, dy;
-          if constexpr (MIXED) {
-            dx = (th - sp.xh) + (tl - sp.xl);
-            dy = (uh - sp.yh) + (ul - sp.yl);
-          } else {
-            dx = th - sp.x;
-            dy = uh - sp.y;
-          }
+          // FP64 difference (exact for close pairs), rounded once to FP32 in mixed
+          const real dx = (real)(txi - sp.x), dy = (real)(tyi - sp.y);
           near_pair<K, MIXED, ND, NA, real>(dx, dy, qv, qd, p, acc, beta, r2min);
         };
         if (jb + NEAR_FLUSH <= nt) {
@@ -414,7 +396,7 @@ __global__ __launch_bounds__(NEAR_BLOCK) void near_kernel(NearArgs a) {
   using real = typename std::conditional<MIXED, float, double>::type;
   constexpr int QN = ND * ((K == PFMM_STOKES) ? 2 : 1);
   constexpr int QD = (MIXED && K != PFMM_YUKAWA) ? NEAR_TILE * QN : 1;
-  __shared__ SrcPt<MIXED> s_pt[NEAR_TILE];
+  __shared__ SrcPt s_pt[NEAR_TILE];
   __shared__ real s_q[NEAR_TILE * QN];
   __shared__ double s_qd[QD];
   near_block<K, MIXED, ND>(a, blockIdx.x, blockIdx.y, s_pt, s_q, s_qd);
@@ -426,7 +408,7 @@ __global__ __launch_bounds__(NEAR_BLOCK) void near_kernel(NearArgs a) {
 template <bool MIXED>
 __global__ __launch_bounds__(NEAR_BLOCK) void near_batch_kernel(BatchNearArgs b) {
   using real = typename std::conditional<MIXED, float, double>::type;
-  __shared__ SrcPt<MIXED> s_pt[NEAR_TILE];
+  __shared__ SrcPt s_pt[NEAR_TILE];
   __shared__ real s_q[NEAR_TILE * 8];
   __shared__ double s_qd[MIXED ? NEAR_TILE * 8 : 1];
   __shared__ long long s_task;
@@ -444,8 +426,6 @@ __global__ __launch_bounds__(NEAR_BLOCK) void near_batch_kernel(BatchNearArgs b)
     NearArgs a = r.args;
     char* ws = b.ws;
     a.sx = (const double*)(ws + r.o_sx); a.sy = (const double*)(ws + r.o_sy);
-    a.sxh = (const float*)(ws + r.o_sxh); a.sxl = (const float*)(ws + r.o_sxl);
-    a.syh = (const float*)(ws + r.o_syh); a.syl = (const float*)(ws + r.o_syl);
     a.q64 = (const double*)(ws + r.o_q64); a.q32 = (const float*)(ws + r.o_q32);
     a.tx = (const double*)(ws + r.o_tx); a.ty = (const double*)(ws + r.o_ty);
     a.perm = (const int*)(ws + r.o_perm); a.part = (double*)(ws + r.o_part);
