@@ -71,10 +71,11 @@ enum {
 
 typedef struct {
   double beta;        /* Yukawa parameter (> 0); ignored otherwise              */
-  int precision;      /* pfmm_precision: FP64 everywhere, or MIXED (near field  */
-                      /* in FP32 with two-float coordinate differences and     */
-                      /* blocked FP64 accumulation; far-field coefficients in  */
-                      /* FP64)                                                 */
+  int precision;      /* pfmm_precision: FP64 everywhere, or MIXED (near-field  */
+                      /* pair arithmetic in FP32 on coordinate differences     */
+                      /* taken in FP64; log terms accumulated in FP64 pair by  */
+                      /* pair, other terms in short FP32 blocks flushed to     */
+                      /* FP64; far field in FP64)                              */
   int far_mode;       /* pfmm_far_mode: AUTO uses the NUFFT when 2M+1 >= 256   */
   int m0;             /* near-region half width in e1 (Def. 1); 0 = automatic  */
   int n_dens;         /* number of density vectors evaluated together (>= 1)   */
