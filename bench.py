@@ -26,6 +26,10 @@ METRIC = "targets/sec (pot+grad) at 1e-6 rel err, mixed vs FP64 GPU path; % FP32
 # large-argument branch for K0/K1; FP64/FP32 conversions and the r = 0
 # guards are not counted)
 FLOPS_PER_PAIR = {"laplace": 14, "yukawa": 51, "stokes": 30}
+# the same for one symmetric evaluation of a pair and its mirror (targets ==
+# sources: shared r^2 and kernel values, both points updated)
+FLOPS_PER_MUTUAL_PAIR = {"laplace": 21, "yukawa": 57, "stokes": 51}
+TILE = 256    # targets per near-field block (the diagonal tiles are one-sided)
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 
 
@@ -153,20 +157,28 @@ def main():
 
     # near-field rooflines (HIP events on the evaluation stream)
     images = 9
+    # pair evaluations of one launch: each target tile against itself
+    # one-sided, every other pair once for both points
+    tiles = [min(TILE, n - t0) for t0 in range(0, n, TILE)]
+    diag_pairs = images * sum(float(t) * t for t in tiles)
+    mutual_pairs = images * (float(n) * n - sum(float(t) * t for t in tiles)) / 2
     roof_all = {}
     traffic = measured_traffic()
     for (kern, _, _), (near_ms, total_ms, cnt) in zip(cases, st_mixed):
         per_launch_ms = near_ms / max(cnt, 1)
-        flops = FLOPS_PER_PAIR[kern] * images * float(n) * float(n)
+        flops = FLOPS_PER_PAIR[kern] * diag_pairs + FLOPS_PER_MUTUAL_PAIR[kern] * mutual_pairs
         tflops = flops / (per_launch_ms * 1e-3) / 1e12
         roof_all[kern] = {"bound": "alu", "achieved": round(tflops, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
                           "unit": "TFLOP/s", "frac": round(tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
-                          "traffic": traffic.get(f"near_kernel<{kern}, mixed, nd=1>"),
+                          "traffic": traffic.get(f"near_mutual_kernel<{kern}, mixed>"),
                           "near_ms_per_launch": round(per_launch_ms, 3),
                           "eval_ms": round(total_ms / max(cnt, 1), 3),
-                          "flops_per_pair": FLOPS_PER_PAIR[kern], "pairs_per_launch": images * n * n}
+                          "flops_per_pair": FLOPS_PER_PAIR[kern],
+                          "flops_per_mutual_pair": FLOPS_PER_MUTUAL_PAIR[kern],
+                          "pairs_per_launch": images * n * n,
+                          "pair_evaluations_per_launch": {"one_sided": diag_pairs, "mutual": mutual_pairs}}
     dom = max(roof_all, key=lambda k: roof_all[k]["near_ms_per_launch"])
-    roofline = dict(roof_all[dom], kernel=f"near_kernel<{dom}, mixed>")
+    roofline = dict(roof_all[dom], kernel=f"near_mutual_kernel<{dom}, mixed> + diagonal near_kernel")
 
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "targets/s", "n_gpus": 1,

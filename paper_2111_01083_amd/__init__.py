@@ -20,6 +20,7 @@ from . import _lib as L
 KERNELS = {"laplace": L.PFMM_LAPLACE, "yukawa": L.PFMM_YUKAWA, "stokes": L.PFMM_STOKES}
 PRECISIONS = {"fp64": L.PFMM_FP64, "mixed": L.PFMM_MIXED}
 FAR_MODES = {"auto": L.PFMM_FAR_AUTO, "direct": L.PFMM_FAR_DIRECT, "nufft": L.PFMM_FAR_NUFFT}
+NEAR_MODES = {"auto": L.PFMM_NEAR_AUTO, "one_sided": L.PFMM_NEAR_ONE_SIDED, "mutual": L.PFMM_NEAR_MUTUAL}
 
 
 class PfmmError(RuntimeError):
@@ -42,12 +43,13 @@ class Plan:
     """Owner of a pfmm_plan_t (see pfmm_plan)."""
 
     def __init__(self, kernel, e1, e2, tol, beta=0.0, precision="fp64", far_mode="auto", m0=0,
-                 n_dens=1, self_exclude=False, m_gl=0, check_neutral=False, profile=False):
+                 n_dens=1, self_exclude=False, m_gl=0, check_neutral=False, profile=False, near_mode="auto"):
         lib = L.load()
         self.kernel_name = kernel
         self.kernel = KERNELS[kernel]
         opts = L.pfmm_opts(float(beta), PRECISIONS[precision], FAR_MODES[far_mode], int(m0), int(n_dens),
-                           int(bool(self_exclude)), int(m_gl), int(bool(check_neutral)), int(bool(profile)))
+                           int(bool(self_exclude)), int(m_gl), int(bool(check_neutral)), int(bool(profile)),
+                           NEAR_MODES[near_mode])
         e1 = np.ascontiguousarray(e1, dtype=np.float64)
         e2 = np.ascontiguousarray(e2, dtype=np.float64)
         h = ctypes.c_void_p()

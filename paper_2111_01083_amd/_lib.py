@@ -12,6 +12,7 @@ LIB_PATH = os.path.join(_PKG, "libpfmm.so")
 PFMM_LAPLACE, PFMM_YUKAWA, PFMM_STOKES = 0, 1, 2
 PFMM_FP64, PFMM_MIXED = 0, 1
 PFMM_FAR_AUTO, PFMM_FAR_DIRECT, PFMM_FAR_NUFFT = 0, 1, 2
+PFMM_NEAR_AUTO, PFMM_NEAR_ONE_SIDED, PFMM_NEAR_MUTUAL = 0, 1, 2
 ERRORS = {0: "PFMM_OK", -1: "PFMM_EINVAL", -2: "PFMM_EINVAL_LATTICE", -3: "PFMM_EINVAL_TOL",
           -4: "PFMM_EWORKSPACE", -5: "PFMM_EHIP", -6: "PFMM_ENOT_NEUTRAL", -7: "PFMM_ENOMEM"}
 
@@ -26,7 +27,8 @@ EXPORTS = ["pfmm_plan", "pfmm_plan_upload", "pfmm_plan_get_info", "pfmm_plan_get
 class pfmm_opts(ctypes.Structure):
     _fields_ = [("beta", ctypes.c_double), ("precision", ctypes.c_int), ("far_mode", ctypes.c_int),
                 ("m0", ctypes.c_int), ("n_dens", ctypes.c_int), ("self_exclude", ctypes.c_int),
-                ("m_gl", ctypes.c_int), ("check_neutral", ctypes.c_int), ("profile", ctypes.c_int)]
+                ("m_gl", ctypes.c_int), ("check_neutral", ctypes.c_int), ("profile", ctypes.c_int),
+                ("near_mode", ctypes.c_int)]
 
 
 class pfmm_plan_info_t(ctypes.Structure):

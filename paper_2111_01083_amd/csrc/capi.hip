@@ -22,12 +22,18 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 // Workspace carve-up for one cell; offsets in bytes from the workspace base.
 struct Layout {
   size_t scx, scy, tcx, tcy, q32, dens_c, near_part, far_part, w, nufft, nu_val;
-  size_t key, perm, stx, sty, hist, cursor;   // target binning
-  size_t qsum;                                // per-split FP32 density sums (mixed Laplace/Stokes)
+  size_t key, perm, stx, sty, cnt;            // target binning
+  int nblk;
+  int64_t bp;
+  size_t qsum;                                // per-split density sums (mixed Laplace/Stokes)
+  size_t qb64, qb32;                          // binned densities (symmetric near field)
+  int mutual;                                 // symmetric near field in this evaluation
+  int64_t mu_chunk;                           // its source chunk length
   int nbx, nby;
   double bin_w, bin_h;
   size_t total;
   int n_splits, n_chunks, n_coef;
+  int64_t chunk_len;
   int64_t split_len;
   size_t part_stride;  // doubles per split
 };
@@ -58,7 +64,12 @@ void plan_layout(const pfmm_plan_s* p, int64_t ns, int64_t nt, Layout& L, int64_
     L.bin_w = W / L.nbx;
     L.bin_h = H / L.nby;
     L.key = take(4 * nt); L.perm = take(4 * nt); L.stx = take(8 * nt); L.sty = take(8 * nt);
-    L.hist = take(4 * (size_t)L.nbx * L.nby); L.cursor = take(4 * (size_t)L.nbx * L.nby);
+    // stable placement in blocks of bp consecutive points (at most 256 blocks)
+    const int64_t nbins = (int64_t)L.nbx * L.nby;
+    L.nblk = (int)std::min<int64_t>(std::min<int64_t>(256, std::max<int64_t>(1, (1 << 26) / nbins)),
+                                    std::max<int64_t>(1, (nt + 1023) / 1024));
+    L.bp = std::max<int64_t>(1, (nt + L.nblk - 1) / L.nblk);
+    L.cnt = take(4 * (size_t)L.nbx * L.nby * L.nblk);
   }
   // source splits for the near field: aim for >= 2048 blocks in flight
   int64_t tiles = std::max<int64_t>(1, (nt + NEAR_BLOCK - 1) / NEAR_BLOCK);
@@ -67,14 +78,38 @@ void plan_layout(const pfmm_plan_s* p, int64_t ns, int64_t nt, Layout& L, int64_
   S = std::max<int64_t>(S, 1);
   int64_t per = (ns + S - 1) / S;
   if (forced_split > 0) per = forced_split;
+  // the symmetric near field needs targets == sources and one density; its
+  // diagonal pass writes a single partial row
+  L.mutual = (p->mutual && p->self_exclude && p->n_dens == 1 && forced_split == 0 && ns == nt) ? 1 : 0;
+  if (L.mutual) per = std::max<int64_t>(ns, 1);
   per = std::max<int64_t>(NEAR_TILE, (per + NEAR_TILE - 1) / NEAR_TILE * NEAR_TILE);
   L.split_len = per;
   L.n_splits = (int)std::max<int64_t>(1, (ns + per - 1) / per);
   L.part_stride = (size_t)p->n_dens * no * nt;
   L.qsum = (mixed && p->kernel != PFMM_YUKAWA) ? take(8 * (size_t)L.n_splits * p->n_dens * nc) : 0;
   L.near_part = take(8 * L.part_stride * L.n_splits);
-  L.n_chunks = (int)std::max<int64_t>(1, (ns + FAR_CHUNK - 1) / FAR_CHUNK);
+  L.qb64 = L.qb32 = 0;
+  L.mu_chunk = 0;
+  if (L.mutual) {
+    L.qb64 = take(8 * (size_t)nc * ns);
+    L.qb32 = mixed ? take(4 * (size_t)nc * ns) : 0;
+    // about 8192 source chunks x target tiles in total (half of them empty)
+    const int64_t tiles = (ns + NEAR_BLOCK - 1) / NEAR_BLOCK;
+    const int64_t want = std::max<int64_t>(1, (8192 + tiles - 1) / tiles);
+    int64_t cl = std::max<int64_t>(1024, (ns + want - 1) / want);
+    L.mu_chunk = (cl + 63) / 64 * 64;
+  }
   L.n_coef = (p->n_sn + p->n_ew) * coef_per_wave(p->kernel) + 1;
+  {
+    // far_R: enough source chunks for about 1024 blocks (each block streams
+    // its chunk once for up to FAR_R_BLOCK modes/nodes)
+    const int64_t wblocks = (p->n_sn + p->n_ew + 1 + FAR_R_BLOCK - 1) / FAR_R_BLOCK;
+    const int64_t want = std::max<int64_t>(1, (1024 + wblocks * p->n_dens - 1) / (wblocks * p->n_dens));
+    int64_t clen = std::max<int64_t>(256, (ns + want - 1) / want);
+    clen = (clen + 255) / 256 * 256;
+    L.chunk_len = clen;
+    L.n_chunks = (int)std::max<int64_t>(1, (ns + clen - 1) / clen);
+  }
   L.far_part = take(16 * (size_t)L.n_chunks * p->n_dens * L.n_coef);
   L.w = take(16 * (size_t)p->n_dens * L.n_coef);
   L.nufft = p->use_nufft ? take(nufft_workspace_bytes(p, ns, nt)) : 0;
@@ -180,6 +215,7 @@ struct CellRun {
   char* ws;
   int* perm;
 };
+static double* D_(const CellRun& r, size_t off) { return (double*)(r.ws + off); }
 
 static void cell_prep(CellRun& r, const double* src_xy, int64_t src_stride, const double* dens,
                       int64_t dens_stride, const double* trg_xy, int64_t trg_stride, hipStream_t st) {
@@ -216,10 +252,13 @@ static void cell_prep(CellRun& r, const double* src_xy, int64_t src_stride, cons
   sa.x0 = -0.5 * (g.d + std::fabs(g.xi)); sa.y0 = -0.5 * g.eta;
   sa.inv_w = 1.0 / L.bin_w; sa.inv_h = 1.0 / L.bin_h; sa.nbx = L.nbx; sa.nby = L.nby;
   sa.key = (int*)(ws + L.key); sa.perm = (int*)(ws + L.perm);
-  sa.hist = (int*)(ws + L.hist); sa.cursor = (int*)(ws + L.cursor);
+  sa.cnt = (int*)(ws + L.cnt); sa.nblk = L.nblk; sa.bp = L.bp;
   sa.sx = D(L.stx); sa.sy = D(L.sty);
   launch_sort_targets(sa, st);
   r.perm = sa.perm;
+  if (L.mutual)
+    launch_gather_dens(D(L.dens_c), sa.perm, r.ns, p->n_dens * (p->kernel == PFMM_STOKES ? 2 : 1), D(L.qb64),
+                       mixed ? F(L.qb32) : nullptr, st);
 }
 
 static NearArgs cell_near_args(const CellRun& r) {
@@ -260,17 +299,26 @@ static int cell_far(CellRun& r, double* out_pot, double* out_grad, int64_t out_s
   fr.kernel = K; fr.n_sn = p->n_sn; fr.n_ew = p->n_ew; fr.ncw = coef_per_wave(K);
   fr.n_coef = L.n_coef; fr.n_dens = p->n_dens; fr.n_src = ns; fr.tab = p->d_tab;
   fr.sx = D(L.scx); fr.sy = D(L.scy); fr.dens = dens_c; fr.part = D(L.far_part);
-  fr.skip_sn = p->use_nufft;
+  fr.skip_sn = p->use_nufft; fr.chunk_len = L.chunk_len;
   const double* csn = nullptr;
   if (p->use_nufft) {
     int rc = nufft_R(p, ns, D(L.scx), D(L.scy), dens_c, ws + L.nufft, st, &csn);
     if (rc) return rc;
   }
-  if (ns > 0) launch_far_R(fr, L.n_chunks, st);
-  else launch_fill_zero(fr.part, 2 * (int64_t)p->n_dens * L.n_coef, st);
+  int d_chunks = 1;
+  if (ns > 0) {
+    launch_far_R(fr, L.n_chunks, st);
+    d_chunks = L.n_chunks;
+    if (L.n_chunks > 4) {
+      launch_far_sum(fr.part, L.n_chunks, (int64_t)p->n_dens * L.n_coef, st);
+      d_chunks = 1;
+    }
+  } else {
+    launch_fill_zero(fr.part, 2 * (int64_t)p->n_dens * L.n_coef, st);
+  }
   FarDArgs fd{};
   fd.kernel = K; fd.n_sn = p->n_sn; fd.n_ew = p->n_ew; fd.ncw = fr.ncw; fd.n_coef = L.n_coef;
-  fd.n_dens = p->n_dens; fd.n_chunks = ns > 0 ? L.n_chunks : 1; fd.eta = g.eta; fd.xi = g.xi;
+  fd.n_dens = p->n_dens; fd.n_chunks = d_chunks; fd.eta = g.eta; fd.xi = g.xi;
   fd.tab = p->d_tab; fd.part = fr.part; fd.extra = csn; fd.w = D(L.w);
   launch_far_D(fd, st);
   const double* nu_val = nullptr;
@@ -337,8 +385,30 @@ int pfmm::eval_core(pfmm_plan_t p, int64_t ns, const double* src_xy, const doubl
   cell_prep(r, src_xy, ns, dens, ns, trg_xy, nt, st);
   NearArgs na = cell_near_args(r);
   if (p->profile) (void)hipEventRecord(ev[0], st);
-  if (ns > 0) launch_near(p->kernel, p->precision == PFMM_MIXED, p->n_dens, na, r.L.n_splits, st);
-  else launch_fill_zero(na.part, (int64_t)r.L.part_stride, st);
+  if (ns > 0 && r.L.mutual) {
+    // diagonal tiles (one-sided, writes the partial row), then every other
+    // pair once for both of its points (atomic adds into the same row)
+    const bool mixed = p->precision == PFMM_MIXED;
+    NearArgs nd = na;
+    nd.diag = 1;
+    nd.sx = D_(r, r.L.stx); nd.sy = D_(r, r.L.sty);
+    nd.q64 = D_(r, r.L.qb64); nd.q32 = mixed ? (const float*)(r.ws + r.L.qb32) : nullptr;
+    launch_near(p->kernel, mixed, 1, nd, 1, st);
+    MutualArgs ma{};
+    const Geometry& g = p->geo;
+    ma.n_images = g.n_images;
+    for (int i = 0; i < g.n_images; ++i) { ma.img_x[i] = g.img_x[i] * g.sigma; ma.img_y[i] = g.img_y[i] * g.sigma; }
+    ma.sigma = g.sigma;
+    ma.n = ns; ma.chunk_len = r.L.mu_chunk;
+    ma.x = nd.sx; ma.y = nd.sy; ma.q64 = nd.q64; ma.q32 = nd.q32;
+    ma.beta = p->beta;
+    ma.acc = na.part;
+    launch_near_mutual(p->kernel, mixed, ma, st);
+  } else if (ns > 0) {
+    launch_near(p->kernel, p->precision == PFMM_MIXED, p->n_dens, na, r.L.n_splits, st);
+  } else {
+    launch_fill_zero(na.part, (int64_t)r.L.part_stride, st);
+  }
   if (p->profile) (void)hipEventRecord(ev[1], st);
   rc = cell_far(r, out_pot, out_grad, nt, st);
   if (rc) return rc;

@@ -17,7 +17,7 @@ constexpr int NEAR_TILE = 256;    // sources per LDS tile
 #endif
 constexpr int NEAR_FLUSH = PFMM_NEAR_FLUSH;  // FP32 partial-sum length before an FP64 flush (mixed)
 constexpr double R2MIN_F32 = 8.673617379884035e-19;   // 2^-60: r^2 clamp of the mixed Laplace/Stokes pair
-constexpr int FAR_CHUNK = 2048;   // sources per far_R block
+constexpr int FAR_R_BLOCK = 128;  // threads (= modes/nodes) per far_R block
 
 struct PrepArgs {
   int64_t n, ystride;        // y coordinates at xy[ystride + i]
@@ -49,6 +49,8 @@ struct NearArgs {
   const double* qsum;                    // mixed Laplace/Stokes: per split, sum of the
                                          // densities [split][qsum_stride] (NULL: no log shift)
   int qsum_stride;                       // n_dens * nc
+  int diag;                              // 1: block t sums only the sources of its own target
+                                         // tile (sources in binned order, self index = binned)
   double* part;                          // [split][n_dens*NOUT][n_trg]
   size_t part_stride;                    // doubles per split
 };
@@ -65,14 +67,16 @@ struct SortArgs {
   const double *x, *y;       // canonical targets
   double x0, y0, inv_w, inv_h;
   int nbx, nby;
-  int *key, *hist, *cursor, *perm;
+  int nblk;                  // point blocks of bp consecutive indices (stable placement)
+  int64_t bp;
+  int *key, *cnt, *perm;     // cnt: [bin][block] counts, then their exclusive prefix
   double *sx, *sy;           // binned copies
 };
 
 struct FarRArgs {
   int kernel, n_sn, n_ew, ncw, n_coef, n_dens;
   int skip_sn;               // south/north slots come from the NUFFT path (write zeros)
-  int64_t n_src;
+  int64_t n_src, chunk_len;  // sources per block (grid y = source chunks)
   const double* tab;         // sn records | ew records
   const double *sx, *sy;     // canonical sources
   const double* dens;        // canonical densities [n_dens][nc][n_src]
@@ -103,6 +107,22 @@ struct FarLArgs {
   int64_t out_stride;        // output rows are out_stride apart (n_trg for one cell)
 };
 
+// symmetric near field for targets == sources, one density vector: block
+// (c, a) evaluates every pair (target tile a, source j in chunk c with j past
+// tile a) and all images once, for both points; results are added with FP64
+// atomics to acc, which already holds the tiles' own (diagonal) sums
+struct MutualArgs {
+  int n_images;
+  double img_x[MAX_IMAGES], img_y[MAX_IMAGES];   // image shifts times sigma
+  double sigma;                          // coordinate scale (mixed Laplace/Stokes)
+  int64_t n, chunk_len;
+  const double *x, *y;                   // canonical points in binned order
+  const double* q64;                     // binned densities [nc][n]
+  const float* q32;                      // binned FP32 densities (mixed)
+  double beta;
+  double* acc;                           // [NOUT][n] in binned order
+};
+
 // one cell of a batched near-field launch; array offsets are byte offsets
 // into the batch workspace
 struct BatchCell {
@@ -127,8 +147,14 @@ void launch_near(int kernel, bool mixed, int nd, const NearArgs& a, int n_splits
 void launch_sort_targets(const SortArgs& a, hipStream_t s);
 void launch_near_batch(bool mixed, const BatchNearArgs& b, int grid, hipStream_t s);
 void launch_qsum(const QsumArgs& a, int n_splits, hipStream_t s);
+void launch_near_mutual(int kernel, bool mixed, const MutualArgs& a, hipStream_t s);
+// dst[c][k] = src[c][perm[k]] for c < ncomp (binned copies of the densities)
+void launch_gather_dens(const double* src, const int* perm, int64_t n, int ncomp, double* dst64,
+                        float* dst32, hipStream_t s);
 void launch_fill_zero(double* p, int64_t n, hipStream_t s);
 void launch_far_R(const FarRArgs& a, int n_chunks, hipStream_t s);
+// part[0][i] = sum over chunks of part[chunk][i], i < n_cplx (complex entries)
+void launch_far_sum(double* part, int n_chunks, int64_t n_cplx, hipStream_t s);
 void launch_far_D(const FarDArgs& a, hipStream_t s);
 void launch_far_L(const FarLArgs& a, hipStream_t s);
 

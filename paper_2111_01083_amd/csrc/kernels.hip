@@ -89,16 +89,17 @@ __global__ void bin_count_kernel(SortArgs a) {
   int key = by * a.nbx + ((by & 1) ? (a.nbx - 1 - bx) : bx);   // boustrophedon rows
   if (!PFMM_NEAR_BIN) key = 0;
   a.key[i] = key;
-  atomicAdd(&a.hist[key], 1);
+  atomicAdd(&a.cnt[(int64_t)key * a.nblk + i / a.bp], 1);
 }
-// exclusive scan of hist into cursor (single block)
+// in-place exclusive scan of cnt[bin][block] (single block)
 __global__ __launch_bounds__(1024) void bin_scan_kernel(SortArgs a) {
   __shared__ int part[1024];
-  const int nb = a.nbx * a.nby, t = threadIdx.x;
-  const int per = (nb + 1023) / 1024;
-  const int b0 = min(t * per, nb), b1 = min(b0 + per, nb);
+  const int64_t n = (int64_t)a.nbx * a.nby * a.nblk;
+  const int t = threadIdx.x;
+  const int64_t per = (n + 1023) / 1024;
+  const int64_t b0 = min((int64_t)t * per, n), b1 = min(b0 + per, n);
   int s = 0;
-  for (int b = b0; b < b1; ++b) s += a.hist[b];
+  for (int64_t b = b0; b < b1; ++b) s += a.cnt[b];
   part[t] = s;
   __syncthreads();
   for (int off = 1; off < 1024; off <<= 1) {
@@ -108,25 +109,50 @@ __global__ __launch_bounds__(1024) void bin_scan_kernel(SortArgs a) {
     __syncthreads();
   }
   int run = part[t] - s;
-  for (int b = b0; b < b1; ++b) { int h = a.hist[b]; a.cursor[b] = run; run += h; }
+  for (int64_t b = b0; b < b1; ++b) { const int h = a.cnt[b]; a.cnt[b] = run; run += h; }
 }
-__global__ void bin_scatter_kernel(SortArgs a) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.n) return;
-  int pos = atomicAdd(&a.cursor[a.key[i]], 1);
-  a.perm[pos] = (int)i;
-  a.sx[pos] = a.x[i];
-  a.sy[pos] = a.y[i];
+// Stable placement: block b owns points [b bp, (b+1) bp) and, for every bin,
+// the range that the scan gave to its points; it walks its points in index
+// order, 256 at a time, and ranks equal keys by thread index, so points of a
+// bin end up in ascending original index (the binned order, and with it every
+// summation order downstream, does not depend on scheduling).
+__global__ __launch_bounds__(256) void bin_scatter_kernel(SortArgs a) {
+  __shared__ int s_key[256];
+  const int blk = blockIdx.x, tid = threadIdx.x;
+  const int64_t p0 = (int64_t)blk * a.bp, p1 = min(p0 + a.bp, a.n);
+  for (int64_t base = p0; base < p1; base += 256) {
+    const int64_t i = base + tid;
+    const int key = i < p1 ? a.key[i] : -1;
+    s_key[tid] = key;
+    __syncthreads();
+    int rank = 0;
+    bool last = true;
+    for (int u = 0; u < 256; ++u) {
+      const bool eq = s_key[u] == key;
+      rank += (eq && u < tid) ? 1 : 0;
+      last = last && !(eq && u > tid);
+    }
+    const int64_t slot = (int64_t)key * a.nblk + blk;
+    if (key >= 0) {
+      const int64_t pos = a.cnt[slot] + rank;
+      a.perm[pos] = (int)i;
+      a.sx[pos] = a.x[i];
+      a.sy[pos] = a.y[i];
+    }
+    __syncthreads();
+    if (key >= 0 && last) a.cnt[slot] += rank + 1;
+    __syncthreads();
+  }
 }
 
 void launch_sort_targets(const SortArgs& a, hipStream_t s) {
   if (a.n <= 0) return;
-  const int nb = a.nbx * a.nby;
-  hipLaunchKernelGGL(fill_int_kernel, dim3((nb + 255) / 256), dim3(256), 0, s, a.hist, nb, 0);
+  const int64_t nc = (int64_t)a.nbx * a.nby * a.nblk;
+  hipLaunchKernelGGL(fill_int_kernel, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s, a.cnt, (int)nc, 0);
   const int g = (int)((a.n + 255) / 256);
   hipLaunchKernelGGL(bin_count_kernel, dim3(g), dim3(256), 0, s, a);
   hipLaunchKernelGGL(bin_scan_kernel, dim3(1), dim3(1024), 0, s, a);
-  hipLaunchKernelGGL(bin_scatter_kernel, dim3(g), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(bin_scatter_kernel, dim3(a.nblk), dim3(256), 0, s, a);
 }
 
 void launch_fill_zero(double* p, int64_t n, hipStream_t s) {
@@ -246,6 +272,37 @@ __device__ __forceinline__ void near_pair(real dx, real dy, const real* qv, cons
   }
 }
 
+// Accumulators of one target (see above) -> potential and gradient (NOUT
+// values). MIXED Laplace/Stokes: logs are log2 and gradients are in
+// coordinates scaled by sigma.
+template <int K, bool MIXED>
+__device__ __forceinline__ void near_outputs(const double* A, double* o, double beta, double sigma) {
+  const double inv4pi = 1.0 / (4 * PI), inv2pi = 1.0 / (2 * PI);
+  const double lscale = MIXED ? 0.69314718055994530942 : 1.0;  // log2 -> ln
+  const double gscale = (MIXED && K != PFMM_YUKAWA) ? sigma : 1.0;
+  if constexpr (K == PFMM_LAPLACE) {
+    o[0] = -inv4pi * lscale * A[0];
+    o[1] = -inv2pi * gscale * A[1];
+    o[2] = -inv2pi * gscale * A[2];
+  } else if constexpr (K == PFMM_YUKAWA) {
+    o[0] = inv2pi * A[0];
+    o[1] = -beta * beta * inv2pi * A[1];
+    o[2] = -beta * beta * inv2pi * A[2];
+  } else {
+    // (F = 2f): u_i = (1/4pi)[-(1/2) sum lg f_i + sum c r_i],
+    // du1/dx = -du2/dy = (1/4pi) sum (c - 2 c dx^2/r^2),
+    // du1/dy = (1/4pi)[W - B], du2/dx = (1/4pi)[-W - B],
+    // W = sum (f2 dx - f1 dy)/r^2, B = 2 sum c dx dy/r^2
+    const double h = 0.5 * inv4pi;
+    o[0] = h * (-0.5 * lscale * A[0] + A[2]);
+    o[1] = h * (-0.5 * lscale * A[1] + A[3]);
+    o[2] = h * gscale * (A[4] - 2 * A[5]);
+    o[3] = h * gscale * (A[7] - 2 * A[6]);
+    o[4] = h * gscale * (-A[7] - 2 * A[6]);
+    o[5] = -o[2];
+  }
+}
+
 // One block's share of the near field: targets [tile*NEAR_BLOCK, +NEAR_BLOCK)
 // in binned order against sources of split `split`, ND densities from dens0.
 // Used by the single-cell kernel (block = (tile, split)) and by the batched
@@ -267,8 +324,9 @@ __device__ __forceinline__ void near_block(const NearArgs& a, int64_t tile, int6
   const int64_t kk = k < a.n_trg ? k : a.n_trg - 1;
   const double tx = a.tx[kk], ty = a.ty[kk];
   const int orig = k < a.n_trg ? a.perm[kk] : -1;
-  const int64_t s0 = split * a.split_len;
-  const int64_t s1 = min(s0 + a.split_len, a.n_src);
+  // diag: the block's own tile of sources (binned order, same points as the targets)
+  const int64_t s0 = a.diag ? tile * NEAR_BLOCK : split * a.split_len;
+  const int64_t s1 = min(s0 + (a.diag ? (int64_t)NEAR_BLOCK : a.split_len), a.n_src);
 
   double acc[ND][NA];
 #pragma unroll
@@ -336,15 +394,11 @@ __device__ __forceinline__ void near_block(const NearArgs& a, int64_t tile, int6
     }
   }
   if (orig < 0) return;
-  const double inv4pi = 1.0 / (4 * PI), inv2pi = 1.0 / (2 * PI);
-  const double lscale = MIXED ? 0.69314718055994530942 : 1.0;  // log2 -> ln
   double* dst = a.part + (size_t)split * a.part_stride;
-  double gscale = 1.0;   // gradients in scaled coordinates -> physical
   if constexpr (MIXED && K != PFMM_YUKAWA) {
-    gscale = a.geo.sigma;
     // the self pair was evaluated at the clamped r^2: remove its exact value
     const double lg_self = (double)__builtin_amdgcn_logf((float)a.r2min);
-    const int i = orig;
+    const int64_t i = a.diag ? k : (int64_t)orig;   // index of the target's own source
     const bool self_here = a.self && i >= s0 && i < s1;
     // log2 of the scaled r^2 is log2 r^2 + lg_shift for every other pair of
     // the split: remove lg_shift * (images * sum of the split's densities - own)
@@ -364,28 +418,7 @@ __device__ __forceinline__ void near_block(const NearArgs& a, int64_t tile, int6
 #pragma unroll
   for (int v = 0; v < ND; ++v) {
     double o[NO];
-    const double* A = acc[v];
-    if constexpr (K == PFMM_LAPLACE) {
-      o[0] = -inv4pi * lscale * A[0];
-      o[1] = -inv2pi * gscale * A[1];
-      o[2] = -inv2pi * gscale * A[2];
-    } else if constexpr (K == PFMM_YUKAWA) {
-      o[0] = inv2pi * A[0];
-      o[1] = -a.beta * a.beta * inv2pi * A[1];
-      o[2] = -a.beta * a.beta * inv2pi * A[2];
-    } else {
-      // (F = 2f): u_i = (1/4pi)[-(1/2) sum lg f_i + sum c r_i],
-      // du1/dx = -du2/dy = (1/4pi) sum (c - 2 c dx^2/r^2),
-      // du1/dy = (1/4pi)[W - B], du2/dx = (1/4pi)[-W - B],
-      // W = sum (f2 dx - f1 dy)/r^2, B = 2 sum c dx dy/r^2
-      const double h = 0.5 * inv4pi;
-      o[0] = h * (-0.5 * lscale * A[0] + A[2]);
-      o[1] = h * (-0.5 * lscale * A[1] + A[3]);
-      o[2] = h * gscale * (A[4] - 2 * A[5]);
-      o[3] = h * gscale * (A[7] - 2 * A[6]);
-      o[4] = h * gscale * (-A[7] - 2 * A[6]);
-      o[5] = -o[2];
-    }
+    near_outputs<K, MIXED>(acc[v], o, a.beta, a.geo.sigma);
 #pragma unroll
     for (int c = 0; c < NO; ++c) dst[(size_t)((a.dens0 + v) * NO + c) * a.n_trg + k] = o[c];
   }
@@ -443,6 +476,226 @@ __global__ __launch_bounds__(NEAR_BLOCK) void near_batch_kernel(BatchNearArgs b)
       for (; v < nd; ++v) { a.dens0 = v; near_block<PFMM_STOKES, MIXED, 1>(a, tile, split, s_pt, s_q, s_qd); }
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Symmetric near field (targets == sources, one density vector). The free-
+// space kernel is even, G(-r) = G(r), so the pair (i, j, l) seen from i and
+// the pair (j, i, -l) seen from j share r^2 and every transcendental; only
+// the gradient changes sign. Block (a, c): the 256 points of binned tile a
+// (one per thread) against the sources of chunk c that come after tile a.
+// Sources pass through LDS in sub-tiles of 64; in step st lane t pairs its
+// point with source (t + st) mod 64, so within a wavefront every lane works
+// on a different source and the source-side sums go to a per-wavefront LDS
+// row without conflicts or atomics. Block (a, c) = (blockIdx.x, blockIdx.y).
+// The 9 (or 15) images of a pair are
+// summed in registers first. Each sub-tile's source-side sums and, at the
+// end, each thread's own sums are converted to outputs and added to acc with
+// FP64 atomics (the summation order of these few adds is not fixed).
+// Precision as in the one-sided kernel: MIXED takes the coordinate
+// difference in FP64, the rest in FP32, log terms summed in FP64 with the
+// FP64 densities; the r = 0 guard is not needed (no point meets itself).
+// ---------------------------------------------------------------------------
+constexpr int MU_SUB = 64;
+
+template <int K, bool MIXED, typename real>
+__device__ __forceinline__ void mutual_pair(real dx, real dy, const real* qi, const double* qid,
+                                            const real* qj, const double* qjd, real* pA, real* pB,
+                                            double* lA, double* lB, real beta) {
+  if constexpr (K == PFMM_YUKAWA) {
+    const real r2 = dx * dx + dy * dy;
+    real k0, k1x;
+    if constexpr (MIXED) bessel_k01_f32_wave(beta * __builtin_amdgcn_sqrtf(r2), k0, k1x);
+    else bessel_k01_f64(beta * sqrt(r2), k0, k1x);
+    const real gx = k1x * dx, gy = k1x * dy;
+    pA[0] += qj[0] * k0; pA[1] += qj[0] * gx; pA[2] += qj[0] * gy;
+    pB[0] += qi[0] * k0; pB[1] -= qi[0] * gx; pB[2] -= qi[0] * gy;
+  } else {
+    real lg, inv;
+    if constexpr (MIXED) {
+      const real r2 = __builtin_fmaf(dx, dx, dy * dy);
+      lg = __builtin_amdgcn_logf(r2);
+      inv = __builtin_amdgcn_rcpf(r2);
+    } else {
+      const real r2 = dx * dx + dy * dy;
+      lg = log(r2);
+      inv = 1.0 / r2;
+    }
+    if constexpr (K == PFMM_LAPLACE) {
+      if constexpr (MIXED) {
+        const double lgd = (double)lg;
+        lA[0] = __builtin_fma(qjd[0], lgd, lA[0]);
+        lB[0] = __builtin_fma(qid[0], lgd, lB[0]);
+      } else {
+        pA[0] += qj[0] * lg; pB[0] += qi[0] * lg;
+      }
+      const real sj = qj[0] * inv, si = qi[0] * inv;
+      pA[1] += sj * dx; pA[2] += sj * dy;
+      pB[1] -= si * dx; pB[2] -= si * dy;
+    } else {
+      const real ia = inv * dx, ib = inv * dy;
+      if constexpr (MIXED) {
+        const double lgd = (double)lg;
+        lA[0] = __builtin_fma(qjd[0], lgd, lA[0]); lA[1] = __builtin_fma(qjd[1], lgd, lA[1]);
+        lB[0] = __builtin_fma(qid[0], lgd, lB[0]); lB[1] = __builtin_fma(qid[1], lgd, lB[1]);
+      } else {
+        pA[0] += lg * qj[0]; pA[1] += lg * qj[1];
+        pB[0] += lg * qi[0]; pB[1] += lg * qi[1];
+      }
+      // seen from i (force F = qj): c2 = ia F1 + ib F2, t = c2 ia
+      const real cA = ia * qj[0] + ib * qj[1], tA = cA * ia;
+      pA[2] += cA * dx; pA[3] += cA * dy; pA[4] += cA;
+      pA[5] += tA * dx; pA[6] += tA * dy; pA[7] += qj[1] * ia - qj[0] * ib;
+      // seen from j (force qi, displacement -r): ia, ib change sign
+      const real cB = ia * qi[0] + ib * qi[1], tB = cB * ia;
+      pB[2] += cB * dx; pB[3] += cB * dy; pB[4] -= cB;
+      pB[5] -= tB * dx; pB[6] -= tB * dy; pB[7] -= qi[1] * ia - qi[0] * ib;
+    }
+  }
+}
+
+template <int K, bool MIXED>
+__global__ __launch_bounds__(NEAR_BLOCK) void near_mutual_kernel(MutualArgs a) {
+  using real = typename std::conditional<MIXED, float, double>::type;
+  constexpr int NC = (K == PFMM_STOKES) ? 2 : 1;
+  constexpr int NA = NAcc<K>::v;
+  constexpr int NO = (K == PFMM_STOKES) ? 6 : 3;
+  constexpr int NLOG = (MIXED && K != PFMM_YUKAWA) ? NC : 0;   // accumulators kept in FP64 pair by pair
+  constexpr int NW = NEAR_BLOCK / 64;
+  __shared__ double s_x[MU_SUB], s_y[MU_SUB], s_qd[NC][MU_SUB];
+  __shared__ real s_q[NC][MU_SUB];
+  __shared__ double s_acc[NW][NA][MU_SUB];
+
+  const int64_t a0 = (int64_t)blockIdx.x * NEAR_BLOCK;
+  const int64_t a_end = min(a0 + (int64_t)NEAR_BLOCK, a.n);
+  const int64_t b0 = max((int64_t)blockIdx.y * a.chunk_len, a_end);
+  const int64_t b1 = min((int64_t)(blockIdx.y + 1) * a.chunk_len, a.n);
+  if (b0 >= b1) return;                                   // uniform over the block
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t k = a0 + tid;
+  const bool act = k < a.n;
+  const double sg = a.sigma;
+  const double qscale = (K == PFMM_STOKES) ? 2.0 : 1.0;
+  // an inactive lane sits far from every point with zero density
+  const double tx = act ? a.x[k] * sg : 1.0e4, ty = act ? a.y[k] * sg : 1.0e4;
+  real qi[NC];
+  double qid[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    qid[c] = act ? qscale * a.q64[(size_t)c * a.n + k] : 0.0;
+    qi[c] = MIXED ? (act ? (real)(qscale * a.q32[(size_t)c * a.n + k]) : (real)0) : (real)qid[c];
+  }
+  const real beta = (real)a.beta;
+  double accA[NA];
+#pragma unroll
+  for (int c = 0; c < NA; ++c) accA[c] = 0.0;
+
+  for (int64_t sb = b0; sb < b1; sb += MU_SUB) {
+    const int nsb = (int)min((int64_t)MU_SUB, b1 - sb);
+    __syncthreads();
+    if (tid < MU_SUB) {
+      const bool ok = tid < nsb;
+      const int64_t j = sb + tid;
+      s_x[tid] = ok ? a.x[j] * sg : -1.0e4;               // padding: far away, zero density
+      s_y[tid] = ok ? a.y[j] * sg : -1.0e4;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const double qd = ok ? qscale * a.q64[(size_t)c * a.n + j] : 0.0;
+        s_qd[c][tid] = qd;
+        s_q[c][tid] = MIXED ? (ok ? (real)(qscale * a.q32[(size_t)c * a.n + j]) : (real)0) : (real)qd;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < NA; ++c) s_acc[wv][c][lane] = 0.0;
+    __syncthreads();
+    for (int st = 0; st < MU_SUB; ++st) {
+      const int b = (lane + st) & (MU_SUB - 1);
+      const double d0x = tx - s_x[b], d0y = ty - s_y[b];
+      real qj[NC];
+      double qjd[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) { qj[c] = s_q[c][b]; qjd[c] = s_qd[c][b]; }
+      real pA[NA], pB[NA];
+      double lA[NC], lB[NC];
+#pragma unroll
+      for (int c = 0; c < NA; ++c) { pA[c] = 0; pB[c] = 0; }
+#pragma unroll
+      for (int c = 0; c < NC; ++c) { lA[c] = 0; lB[c] = 0; }
+      for (int im = 0; im < a.n_images; ++im) {
+        const real dx = (real)(d0x - a.img_x[im]), dy = (real)(d0y - a.img_y[im]);
+        mutual_pair<K, MIXED, real>(dx, dy, qi, qid, qj, qjd, pA, pB, lA, lB, beta);
+      }
+#pragma unroll
+      for (int c = 0; c < NA; ++c) {
+        const double ea = c < NLOG ? lA[c < NC ? c : 0] : (double)pA[c];
+        const double eb = c < NLOG ? lB[c < NC ? c : 0] : (double)pB[c];
+        accA[c] += ea;
+        s_acc[wv][c][b] += eb;
+      }
+    }
+    __syncthreads();
+    if (tid < nsb) {
+      double A[NA], o[NO];
+#pragma unroll
+      for (int c = 0; c < NA; ++c) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) t += s_acc[w][c][tid];
+        A[c] = t;
+      }
+      near_outputs<K, MIXED>(A, o, a.beta, sg);
+#pragma unroll
+      for (int c = 0; c < NO; ++c) unsafeAtomicAdd(&a.acc[(size_t)c * a.n + sb + tid], o[c]);
+    }
+  }
+  if (act) {
+    double o[NO];
+    near_outputs<K, MIXED>(accA, o, a.beta, sg);
+#pragma unroll
+    for (int c = 0; c < NO; ++c) unsafeAtomicAdd(&a.acc[(size_t)c * a.n + k], o[c]);
+  }
+}
+
+void launch_near_mutual(int kernel, bool mixed, const MutualArgs& a, hipStream_t s) {
+  if (a.n <= NEAR_BLOCK) return;                         // one tile: the diagonal pass has it all
+  const unsigned tiles = (unsigned)((a.n + NEAR_BLOCK - 1) / NEAR_BLOCK);
+  const unsigned chunks = (unsigned)((a.n + a.chunk_len - 1) / a.chunk_len);
+  const dim3 grid(tiles, chunks);
+  auto go = [&](auto kc, auto mc) {
+    constexpr int K = decltype(kc)::value;
+    constexpr bool M = decltype(mc)::value;
+    hipLaunchKernelGGL((near_mutual_kernel<K, M>), grid, dim3(NEAR_BLOCK), 0, s, a);
+  };
+  using L = std::integral_constant<int, PFMM_LAPLACE>;
+  using Y = std::integral_constant<int, PFMM_YUKAWA>;
+  using S = std::integral_constant<int, PFMM_STOKES>;
+  switch (kernel * 2 + (mixed ? 1 : 0)) {
+    case 0: go(L{}, std::false_type{}); break;
+    case 1: go(L{}, std::true_type{}); break;
+    case 2: go(Y{}, std::false_type{}); break;
+    case 3: go(Y{}, std::true_type{}); break;
+    case 4: go(S{}, std::false_type{}); break;
+    case 5: go(S{}, std::true_type{}); break;
+  }
+}
+
+__global__ void gather_dens_kernel(const double* src, const int* perm, int64_t n, int ncomp, double* d64,
+                                   float* d32) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int64_t i = perm[k];
+  for (int c = 0; c < ncomp; ++c) {
+    const double q = src[(size_t)c * n + i];
+    d64[(size_t)c * n + k] = q;
+    if (d32) d32[(size_t)c * n + k] = (float)q;
+  }
+}
+
+void launch_gather_dens(const double* src, const int* perm, int64_t n, int ncomp, double* dst64, float* dst32,
+                        hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(gather_dens_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, perm, n, ncomp,
+                     dst64, dst32);
 }
 
 // per-split sums of the FP64 densities, used to remove the log2 shift
@@ -511,7 +764,6 @@ void launch_near(int kernel, bool mixed, int nd, const NearArgs& a, int n_splits
 //     Laplace/Stokes use e^{...} - 1 (exact for neutral densities, and free of
 //     the O(1) cancellation at small lambda); Stokes also e^W = sum x f e^{...}
 // ---------------------------------------------------------------------------
-constexpr int FAR_R_BLOCK = 128;
 constexpr int FAR_R_TILE = 1024;
 
 struct cplx { double r, i; };
@@ -535,8 +787,8 @@ __global__ __launch_bounds__(FAR_R_BLOCK) void far_R_kernel(FarRArgs a) {
   constexpr int NCW = (K == PFMM_STOKES) ? 8 : 2;
   __shared__ double s_x[FAR_R_TILE], s_y[FAR_R_TILE], s_q[NC][FAR_R_TILE];
   const int v = blockIdx.z;
-  const int64_t j0 = (int64_t)blockIdx.y * FAR_CHUNK;
-  const int64_t j1 = min(j0 + FAR_CHUNK, a.n_src);
+  const int64_t j0 = (int64_t)blockIdx.y * a.chunk_len;
+  const int64_t j1 = min(j0 + a.chunk_len, a.n_src);
   const int w = blockIdx.x * FAR_R_BLOCK + threadIdx.x;
   const int n_w = a.n_sn + a.n_ew;
   const bool in_sn = w < a.n_sn;
@@ -628,6 +880,32 @@ __global__ __launch_bounds__(FAR_R_BLOCK) void far_R_kernel(FarRArgs a) {
     out[2 * (n_w * NCW)] = acc[0].r;
     out[2 * (n_w * NCW) + 1] = acc[0].i;
   }
+}
+
+// chunk partials -> chunk 0, one block per complex entry (fixed order)
+__global__ __launch_bounds__(256) void far_sum_kernel(double* part, int n_chunks, int64_t n_cplx) {
+  __shared__ double red[2][256];
+  const int64_t e = blockIdx.x;
+  double sr = 0, si = 0;
+  for (int ch = threadIdx.x; ch < n_chunks; ch += 256) {
+    const double* q = part + ((size_t)ch * n_cplx + e) * 2;
+    sr += q[0]; si += q[1];
+  }
+  red[0][threadIdx.x] = sr; red[1][threadIdx.x] = si;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + off];
+      red[1][threadIdx.x] += red[1][threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) { part[e * 2] = red[0][0]; part[e * 2 + 1] = red[1][0]; }
+}
+
+void launch_far_sum(double* part, int n_chunks, int64_t n_cplx, hipStream_t s) {
+  if (n_cplx <= 0 || n_chunks <= 1) return;
+  hipLaunchKernelGGL(far_sum_kernel, dim3((unsigned)n_cplx), dim3(256), 0, s, part, n_chunks, n_cplx);
 }
 
 void launch_far_R(const FarRArgs& a, int n_chunks, hipStream_t s) {

@@ -58,6 +58,7 @@ struct NufftParams {
 
 struct pfmm_plan_s {
   int kernel, precision, far_mode, m0, n_dens, self_exclude, check_neutral, profile;
+  int mutual;                  // near field by symmetric pair evaluation (self targets, one density)
   double beta, tol, eps;
   pfmm::Geometry geo;
   int M, m_lo, n_sn;           // south/north modes m = m_lo..M

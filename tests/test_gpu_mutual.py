@@ -1,0 +1,95 @@
+"""Symmetric near field (targets == sources, one density vector): every pair
+(i, j, l) and its mirror (j, i, -l) are evaluated once for both points (the
+free-space kernels are even, Sec. 1 eq. psum). Parity with the FP64 oracle
+and with the one-sided near field on the same inputs, over sizes that leave
+ragged target tiles and source sub-tiles."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+CELLS = {"square": ((1.0, 0.0), (0.0, 1.0)), "sheared": ((2.0, 0.0), (0.9, 1.3)),
+         "long": ((10.0, 0.0), (0.0, 1.0))}
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    import paper_2111_01083_amd as P
+    return P, torch, torch.device("cuda:0")
+
+
+def rel(a, b):
+    return np.linalg.norm((np.asarray(a) - np.asarray(b)).ravel()) / np.linalg.norm(np.asarray(b).ravel())
+
+
+def run(env, kernel, e1, e2, src, dens, prec, tol, beta, mode):
+    P, torch, dev = env
+    plan = P.Plan(kernel, e1, e2, tol, beta=beta, precision=prec, self_exclude=True, near_mode=mode)
+    pot, grad = plan(torch.tensor(src, device=dev), torch.tensor(dens, device=dev))
+    torch.cuda.synchronize()
+    return pot.cpu().numpy(), grad.cpu().numpy()
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 256, 257, 700, 1537])
+@pytest.mark.parametrize("cell", list(CELLS))
+@pytest.mark.parametrize("kernel,beta", [("laplace", 0.0), ("yukawa", 3.0), ("stokes", 0.0)])
+@pytest.mark.parametrize("prec,tol,bar", [("fp64", 1e-10, 1e-10), ("mixed", 1e-6, 1e-6)])
+def test_mutual_matches_oracle_and_one_sided(env, n, cell, kernel, beta, prec, tol, bar):
+    e1, e2 = CELLS[cell]
+    rng = np.random.default_rng(n)
+    src = W.cell_points(rng, e1, e2, n)
+    if kernel == "yukawa":
+        dens = rng.standard_normal(n)          # Yukawa needs no neutrality
+    else:
+        dens = W.neutral_forces(rng, n) if kernel == "stokes" else W.neutral_charges(rng, n)
+    if n == 1 and kernel != "yukawa":
+        pytest.skip("a single neutral charge is zero")
+    print(f"case mutual {kernel} {cell} n={n} {prec}", flush=True)
+    pm, gm = run(env, kernel, e1, e2, src, dens, prec, tol, beta, "mutual")
+    po, go = oracle.evaluate(kernel, e1, e2, src, dens, None, beta=beta)
+    p1, g1 = run(env, kernel, e1, e2, src, dens, prec, tol, beta, "one_sided")
+    agree = 1e-12 if prec == "fp64" else 1e-6
+    if n == 1:
+        # one charge and its images: the field at the charge vanishes by symmetry
+        assert rel(pm, po) < bar and np.abs(gm).max() < 1e-10 * np.abs(pm).max()
+        return
+    assert rel(pm, po) < bar and rel(gm, go) < bar, (rel(pm, po), rel(gm, go))
+    assert rel(pm, p1) < agree and rel(gm, g1) < agree, (rel(pm, p1), rel(gm, g1))
+
+
+def test_auto_uses_the_symmetric_path_and_full_size_is_accurate(env):
+    # square cell, N = 2e5 uniform, Yukawa beta = 10, mixed, tol 1e-6: AUTO takes
+    # the symmetric path; sampled outputs against the oracle
+    P, torch, dev = env
+    n = 200_000
+    rng = np.random.default_rng(0)
+    e1, e2 = CELLS["square"]
+    src = W.cell_points(rng, e1, e2, n)
+    q = W.neutral_charges(rng, n)
+    print("mutual full size", flush=True)
+    pa, ga = run(env, "yukawa", e1, e2, src, q, "mixed", 1e-6, 10.0, "auto")
+    pm, gm = run(env, "yukawa", e1, e2, src, q, "mixed", 1e-6, 10.0, "mutual")
+    assert rel(pa, pm) < 1e-12 and rel(ga, gm) < 1e-12
+    idx = np.sort(np.random.default_rng(1).choice(n, 16, replace=False))
+    po, go = oracle.evaluate("yukawa", e1, e2, src, q, src[:, idx], beta=10.0, tol=1e-10, self_idx=idx)
+    assert rel(pa[idx], po) < 1e-6 and rel(ga[:, idx], go) < 1e-6
+
+
+@pytest.mark.parametrize("kernel,beta", [("laplace", 0.0), ("yukawa", 10.0), ("stokes", 0.0)])
+def test_repeated_evaluations_agree_to_fp64_rounding(env, kernel, beta):
+    # the binned order is stable (ascending index within a bin), so two runs
+    # differ only through the order of the FP64 atomic adds
+    P, torch, dev = env
+    n = 20000
+    rng = np.random.default_rng(5)
+    e1, e2 = CELLS["sheared"]
+    src = torch.tensor(W.cell_points(rng, e1, e2, n), device=dev)
+    dens = torch.tensor(W.neutral_forces(rng, n) if kernel == "stokes" else W.neutral_charges(rng, n), device=dev)
+    plan = P.Plan(kernel, e1, e2, 1e-6, beta=beta, precision="mixed", self_exclude=True)
+    a = [t.cpu().numpy() for t in plan(src, dens)]
+    b = [t.cpu().numpy() for t in plan(src, dens)]
+    assert rel(a[0], b[0]) < 1e-13 and rel(a[1], b[1]) < 1e-13
