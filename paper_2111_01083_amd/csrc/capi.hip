@@ -94,8 +94,8 @@ void plan_layout(const pfmm_plan_s* p, int64_t ns, int64_t nt, Layout& L, int64_
     L.qb64 = take(8 * (size_t)nc * ns);
     L.qb32 = mixed ? take(4 * (size_t)nc * ns) : 0;
     // about 8192 source chunks x target tiles in total (half of them empty)
-    const int64_t tiles = (ns + NEAR_BLOCK - 1) / NEAR_BLOCK;
-    const int64_t want = std::max<int64_t>(1, (8192 + tiles - 1) / tiles);
+    const int64_t tiles = (ns + MU_BLOCK - 1) / MU_BLOCK;
+    const int64_t want = std::max<int64_t>(1, (8192 * 256 / MU_BLOCK + tiles - 1) / tiles);
     int64_t cl = std::max<int64_t>(1024, (ns + want - 1) / want);
     L.mu_chunk = (cl + 63) / 64 * 64;
   }
@@ -391,6 +391,7 @@ int pfmm::eval_core(pfmm_plan_t p, int64_t ns, const double* src_xy, const doubl
     const bool mixed = p->precision == PFMM_MIXED;
     NearArgs nd = na;
     nd.diag = 1;
+    nd.diag_len = MU_BLOCK;
     nd.sx = D_(r, r.L.stx); nd.sy = D_(r, r.L.sty);
     nd.q64 = D_(r, r.L.qb64); nd.q32 = mixed ? (const float*)(r.ws + r.L.qb32) : nullptr;
     launch_near(p->kernel, mixed, 1, nd, 1, st);

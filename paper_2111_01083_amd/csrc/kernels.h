@@ -9,6 +9,10 @@ namespace pfmm {
 
 constexpr int NEAR_BLOCK = 256;   // threads (= targets) per near-field block
 constexpr int NEAR_TILE = 256;    // sources per LDS tile
+#ifndef PFMM_MU_BLOCK
+#define PFMM_MU_BLOCK 256
+#endif
+constexpr int MU_BLOCK = PFMM_MU_BLOCK;   // points per block of the symmetric near field (multiple of 256)
 #ifndef PFMM_NEAR_FLUSH
 #define PFMM_NEAR_FLUSH 16
 #endif
@@ -49,8 +53,9 @@ struct NearArgs {
   const double* qsum;                    // mixed Laplace/Stokes: per split, sum of the
                                          // densities [split][qsum_stride] (NULL: no log shift)
   int qsum_stride;                       // n_dens * nc
-  int diag;                              // 1: block t sums only the sources of its own target
-                                         // tile (sources in binned order, self index = binned)
+  int diag;                              // 1: block t sums only the sources of the diag_len-point
+                                         // tile that holds its targets (sources in binned order,
+  int64_t diag_len;                      // self index = binned)
   double* part;                          // [split][n_dens*NOUT][n_trg]
   size_t part_stride;                    // doubles per split
 };

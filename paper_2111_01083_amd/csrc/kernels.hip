@@ -325,8 +325,8 @@ __device__ __forceinline__ void near_block(const NearArgs& a, int64_t tile, int6
   const double tx = a.tx[kk], ty = a.ty[kk];
   const int orig = k < a.n_trg ? a.perm[kk] : -1;
   // diag: the block's own tile of sources (binned order, same points as the targets)
-  const int64_t s0 = a.diag ? tile * NEAR_BLOCK : split * a.split_len;
-  const int64_t s1 = min(s0 + (a.diag ? (int64_t)NEAR_BLOCK : a.split_len), a.n_src);
+  const int64_t s0 = a.diag ? (tile * NEAR_BLOCK) / a.diag_len * a.diag_len : split * a.split_len;
+  const int64_t s1 = min(s0 + (a.diag ? a.diag_len : a.split_len), a.n_src);
 
   double acc[ND][NA];
 #pragma unroll
@@ -482,7 +482,7 @@ __global__ __launch_bounds__(NEAR_BLOCK) void near_batch_kernel(BatchNearArgs b)
 // Symmetric near field (targets == sources, one density vector). The free-
 // space kernel is even, G(-r) = G(r), so the pair (i, j, l) seen from i and
 // the pair (j, i, -l) seen from j share r^2 and every transcendental; only
-// the gradient changes sign. Block (a, c): the 256 points of binned tile a
+// the gradient changes sign. Block (a, c): the MU_BLOCK points of binned tile a
 // (one per thread) against the sources of chunk c that come after tile a.
 // Sources pass through LDS in sub-tiles of 64; in step st lane t pairs its
 // point with source (t + st) mod 64, so within a wavefront every lane works
@@ -555,19 +555,19 @@ __device__ __forceinline__ void mutual_pair(real dx, real dy, const real* qi, co
 }
 
 template <int K, bool MIXED>
-__global__ __launch_bounds__(NEAR_BLOCK) void near_mutual_kernel(MutualArgs a) {
+__global__ __launch_bounds__(MU_BLOCK) void near_mutual_kernel(MutualArgs a) {
   using real = typename std::conditional<MIXED, float, double>::type;
   constexpr int NC = (K == PFMM_STOKES) ? 2 : 1;
   constexpr int NA = NAcc<K>::v;
   constexpr int NO = (K == PFMM_STOKES) ? 6 : 3;
   constexpr int NLOG = (MIXED && K != PFMM_YUKAWA) ? NC : 0;   // accumulators kept in FP64 pair by pair
-  constexpr int NW = NEAR_BLOCK / 64;
+  constexpr int NW = MU_BLOCK / 64;
   __shared__ double s_x[MU_SUB], s_y[MU_SUB], s_qd[NC][MU_SUB];
   __shared__ real s_q[NC][MU_SUB];
   __shared__ double s_acc[NW][NA][MU_SUB];
 
-  const int64_t a0 = (int64_t)blockIdx.x * NEAR_BLOCK;
-  const int64_t a_end = min(a0 + (int64_t)NEAR_BLOCK, a.n);
+  const int64_t a0 = (int64_t)blockIdx.x * MU_BLOCK;
+  const int64_t a_end = min(a0 + (int64_t)MU_BLOCK, a.n);
   const int64_t b0 = max((int64_t)blockIdx.y * a.chunk_len, a_end);
   const int64_t b1 = min((int64_t)(blockIdx.y + 1) * a.chunk_len, a.n);
   if (b0 >= b1) return;                                   // uniform over the block
@@ -657,14 +657,14 @@ __global__ __launch_bounds__(NEAR_BLOCK) void near_mutual_kernel(MutualArgs a) {
 }
 
 void launch_near_mutual(int kernel, bool mixed, const MutualArgs& a, hipStream_t s) {
-  if (a.n <= NEAR_BLOCK) return;                         // one tile: the diagonal pass has it all
-  const unsigned tiles = (unsigned)((a.n + NEAR_BLOCK - 1) / NEAR_BLOCK);
+  if (a.n <= MU_BLOCK) return;                           // one tile: the diagonal pass has it all
+  const unsigned tiles = (unsigned)((a.n + MU_BLOCK - 1) / MU_BLOCK);
   const unsigned chunks = (unsigned)((a.n + a.chunk_len - 1) / a.chunk_len);
   const dim3 grid(tiles, chunks);
   auto go = [&](auto kc, auto mc) {
     constexpr int K = decltype(kc)::value;
     constexpr bool M = decltype(mc)::value;
-    hipLaunchKernelGGL((near_mutual_kernel<K, M>), grid, dim3(NEAR_BLOCK), 0, s, a);
+    hipLaunchKernelGGL((near_mutual_kernel<K, M>), grid, dim3(MU_BLOCK), 0, s, a);
   };
   using L = std::integral_constant<int, PFMM_LAPLACE>;
   using Y = std::integral_constant<int, PFMM_YUKAWA>;
