@@ -86,9 +86,9 @@ typedef struct {
   int profile;        /* 1: record HIP events around the near-field launches   */
                       /*    and the whole evaluation (see pfmm_plan_stage_times)*/
   int near_mode;      /* pfmm_near_mode: AUTO evaluates each pair of a         */
-                      /* self-target plan with one density vector once for     */
-                      /* both of its points (the kernel is symmetric, Sec. 1   */
-                      /* eq. psum); ONE_SIDED always sums per target           */
+                      /* self-target plan once for both of its points (the     */
+                      /* kernel is symmetric, Sec. 1 eq. psum); ONE_SIDED      */
+                      /* always sums per target; MUTUAL needs self_exclude     */
 } pfmm_opts;
 
 typedef enum { PFMM_NEAR_AUTO = 0, PFMM_NEAR_ONE_SIDED = 1, PFMM_NEAR_MUTUAL = 2 } pfmm_near_mode;

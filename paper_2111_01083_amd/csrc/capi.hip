@@ -78,9 +78,10 @@ void plan_layout(const pfmm_plan_s* p, int64_t ns, int64_t nt, Layout& L, int64_
   S = std::max<int64_t>(S, 1);
   int64_t per = (ns + S - 1) / S;
   if (forced_split > 0) per = forced_split;
-  // the symmetric near field needs targets == sources and one density; its
-  // diagonal pass writes a single partial row
-  L.mutual = (p->mutual && p->self_exclude && p->n_dens == 1 && forced_split == 0 && ns == nt) ? 1 : 0;
+  // the symmetric near field needs targets == sources; its diagonal pass
+  // writes a single partial row
+  // (forced_split > 0: batched cell; its symmetric tasks use chunks of that length)
+  L.mutual = (p->mutual && p->self_exclude && ns == nt) ? 1 : 0;
   if (L.mutual) per = std::max<int64_t>(ns, 1);
   per = std::max<int64_t>(NEAR_TILE, (per + NEAR_TILE - 1) / NEAR_TILE * NEAR_TILE);
   L.split_len = per;
@@ -91,12 +92,12 @@ void plan_layout(const pfmm_plan_s* p, int64_t ns, int64_t nt, Layout& L, int64_
   L.qb64 = L.qb32 = 0;
   L.mu_chunk = 0;
   if (L.mutual) {
-    L.qb64 = take(8 * (size_t)nc * ns);
-    L.qb32 = mixed ? take(4 * (size_t)nc * ns) : 0;
+    L.qb64 = take(8 * (size_t)p->n_dens * nc * ns);
+    L.qb32 = mixed ? take(4 * (size_t)p->n_dens * nc * ns) : 0;
     // about 8192 source chunks x target tiles in total (half of them empty)
     const int64_t tiles = (ns + MU_BLOCK - 1) / MU_BLOCK;
     const int64_t want = std::max<int64_t>(1, (8192 * 256 / MU_BLOCK + tiles - 1) / tiles);
-    int64_t cl = std::max<int64_t>(1024, (ns + want - 1) / want);
+    int64_t cl = forced_split > 0 ? forced_split : std::max<int64_t>(1024, (ns + want - 1) / want);
     L.mu_chunk = (cl + 63) / 64 * 64;
   }
   L.n_coef = (p->n_sn + p->n_ew) * coef_per_wave(p->kernel) + 1;
@@ -145,6 +146,13 @@ int pfmm_plan_upload(pfmm_plan_t p) {
   tab.insert(tab.end(), p->gl_nodes.begin(), p->gl_nodes.end());
   tab.insert(tab.end(), p->gl_bary.begin(), p->gl_bary.end());
   tab.insert(tab.end(), p->nu_deconv.begin(), p->nu_deconv.end());
+  p->tab_img = tab.size();
+  const Geometry& g = p->geo;
+  for (int s = 0; s < 2; ++s) {
+    const double f = s ? g.sigma : 1.0;
+    for (int i = 0; i < g.n_images; ++i) tab.push_back(g.img_x[i] * f);
+    for (int i = 0; i < g.n_images; ++i) tab.push_back(g.img_y[i] * f);
+  }
   tab.push_back(0.0);
   if (p->d_tab) { (void)hipFree(p->d_tab); p->d_tab = nullptr; }
   double* d = nullptr;
@@ -269,6 +277,7 @@ static NearArgs cell_near_args(const CellRun& r) {
   auto F = [&](size_t off) { return (float*)(ws + off); };
   NearArgs na{};
   na.geo = p->geo;
+  na.imx = p->d_tab + p->tab_img; na.imy = na.imx + p->geo.n_images;   // plan uploaded beforehand
   na.n_src = r.ns; na.n_trg = r.nt; na.split_len = L.split_len;
   na.sx = D(L.scx); na.sy = D(L.scy);
   if (p->precision == PFMM_MIXED) {
@@ -394,17 +403,17 @@ int pfmm::eval_core(pfmm_plan_t p, int64_t ns, const double* src_xy, const doubl
     nd.diag_len = MU_BLOCK;
     nd.sx = D_(r, r.L.stx); nd.sy = D_(r, r.L.sty);
     nd.q64 = D_(r, r.L.qb64); nd.q32 = mixed ? (const float*)(r.ws + r.L.qb32) : nullptr;
-    launch_near(p->kernel, mixed, 1, nd, 1, st);
+    launch_near(p->kernel, mixed, p->n_dens, nd, 1, st);
     MutualArgs ma{};
     const Geometry& g = p->geo;
     ma.n_images = g.n_images;
-    for (int i = 0; i < g.n_images; ++i) { ma.img_x[i] = g.img_x[i] * g.sigma; ma.img_y[i] = g.img_y[i] * g.sigma; }
+    ma.imx = p->d_tab + p->tab_img + 2 * g.n_images; ma.imy = ma.imx + g.n_images;
     ma.sigma = g.sigma;
     ma.n = ns; ma.chunk_len = r.L.mu_chunk;
     ma.x = nd.sx; ma.y = nd.sy; ma.q64 = nd.q64; ma.q32 = nd.q32;
     ma.beta = p->beta;
     ma.acc = na.part;
-    launch_near_mutual(p->kernel, mixed, ma, st);
+    launch_near_mutual(p->kernel, mixed, ma, p->n_dens, st);
   } else if (ns > 0) {
     launch_near(p->kernel, p->precision == PFMM_MIXED, p->n_dens, na, r.L.n_splits, st);
   } else {
@@ -478,8 +487,10 @@ struct pfmm_batch_s {
   std::vector<int64_t> soff, toff;
   std::vector<size_t> base;            // workspace offset of each cell
   size_t counter_off, total;
-  long long n_tasks;
-  int grid;
+  // per kernel type: records [rec0, rec0 + n_recs), tasks of the one-sided /
+  // diagonal launch and of the symmetric launch
+  struct Group { int kernel, rec0, n_recs; long long n_tasks, n_tasks_m; int grid, grid_m; } groups[3];
+  int n_groups;
   BatchCell* d_recs;
   hipStream_t cap_stream;
   hipGraphExec_t exec;
@@ -535,12 +546,33 @@ int pfmm_batch_create(int n_cells, const pfmm_plan_t* plans, const int64_t* src_
   auto cost = [&](int c) {
     return (double)(b->soff[c + 1] - b->soff[c]) * (double)(b->toff[c + 1] - b->toff[c]) * plans[c]->geo.n_images;
   };
-  std::stable_sort(order.begin(), order.end(), [&](int a, int bb) { return cost(a) > cost(bb); });
+  // one persistent launch per kernel type; within it, most expensive cells first
+  std::stable_sort(order.begin(), order.end(), [&](int a, int bb) {
+    if (plans[a]->kernel != plans[bb]->kernel) return plans[a]->kernel < plans[bb]->kernel;
+    return cost(a) > cost(bb);
+  });
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   std::vector<BatchCell> recs;
-  long long task = 0;
+  long long task = 0, task_m = 0;
+  b->n_groups = 0;
+  auto close_group = [&]() {
+    if (b->n_groups == 0) return;
+    pfmm_batch_s::Group& gr = b->groups[b->n_groups - 1];
+    gr.n_recs = (int)recs.size() - gr.rec0;
+    gr.n_tasks = task;
+    gr.n_tasks_m = task_m;
+    gr.grid = (int)std::max<long long>(1, std::min<long long>(task, 4LL * cus));
+    gr.grid_m = (int)std::max<long long>(1, std::min<long long>(task_m, 4LL * cus));
+  };
   for (int c : order) {
     const CellRun& r = runs[c];
     if (r.ns == 0 || r.nt == 0) continue;
+    if (b->n_groups == 0 || b->groups[b->n_groups - 1].kernel != plans[c]->kernel) {
+      close_group();
+      b->groups[b->n_groups++] = {plans[c]->kernel, (int)recs.size(), 0, 0, 0, 1, 1};
+      task = 0; task_m = 0;
+    }
     BatchCell bc{};
     CellRun rr = r;
     rr.ws = nullptr;
@@ -555,13 +587,24 @@ int pfmm_batch_create(int n_cells, const pfmm_plan_t* plans, const int64_t* src_
     bc.kernel = plans[c]->kernel; bc.n_dens = b->n_dens;
     bc.n_tiles = (int)((r.nt + NEAR_BLOCK - 1) / NEAR_BLOCK);
     bc.task0 = task;
-    task += (long long)bc.n_tiles * L.n_splits;
+    bc.task0m = task_m;
+    bc.mutual = L.mutual;
+    if (L.mutual) {
+      const Geometry& g = plans[c]->geo;
+      MutualArgs& m = bc.margs;
+      m.n_images = g.n_images;
+      m.imx = plans[c]->d_tab + plans[c]->tab_img + 2 * g.n_images; m.imy = m.imx + g.n_images;
+      m.sigma = g.sigma; m.n = r.ns; m.chunk_len = L.mu_chunk; m.beta = plans[c]->beta;
+      bc.n_chunks = (int)((r.ns + L.mu_chunk - 1) / L.mu_chunk);
+      bc.o_qb64 = B + L.qb64; bc.o_qb32 = mixed ? B + L.qb32 : 0;
+      task += bc.n_tiles;
+      task_m += (long long)bc.n_tiles * bc.n_chunks;
+    } else {
+      task += (long long)bc.n_tiles * L.n_splits;
+    }
     recs.push_back(bc);
   }
-  b->n_tasks = task;
-  int dev = 0, cus = 256;
-  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  b->grid = (int)std::max<long long>(1, std::min<long long>(task, 4LL * cus));
+  close_group();
   if (!recs.empty()) {
     if (hipMalloc(&b->d_recs, recs.size() * sizeof(BatchCell)) != hipSuccess) { delete b; return PFMM_ENOMEM; }
     if (hipMemcpy(b->d_recs, recs.data(), recs.size() * sizeof(BatchCell), hipMemcpyHostToDevice) != hipSuccess) {
@@ -589,14 +632,22 @@ static int batch_launch(pfmm_batch_s* b, const double* src_xy, const double* den
               b->self_exclude ? nullptr : trg_xy + b->toff[c], T, st);
     if (ns == 0) launch_fill_zero((double*)(ws + b->base[c] + runs[c].L.near_part), (int64_t)runs[c].L.part_stride, st);
   }
-  launch_fill_zero((double*)(ws + b->counter_off), 1, st);
-  BatchNearArgs na{};
-  na.recs = b->d_recs;
-  na.n_cells = b->n_recs;
-  na.n_tasks = b->n_tasks;
-  na.ws = ws;
-  na.counter = (unsigned long long*)(ws + b->counter_off);
-  launch_near_batch(b->mixed, na, b->grid, st);
+  launch_fill_zero((double*)(ws + b->counter_off), 9, st);
+  for (int gi = 0; gi < b->n_groups; ++gi) {
+    const pfmm_batch_s::Group& gr = b->groups[gi];
+    BatchNearArgs na{};
+    na.recs = b->d_recs + gr.rec0;
+    na.n_cells = gr.n_recs;
+    na.ws = ws;
+    na.n_dens = b->n_dens;
+    na.n_tasks = gr.n_tasks;
+    na.counter = (unsigned long long*)(ws + b->counter_off) + 3 * gi;
+    launch_near_batch(gr.kernel, b->mixed, 0, na, gr.grid, st);
+    na.n_tasks = gr.n_tasks_m;
+    na.counter = (unsigned long long*)(ws + b->counter_off) + 3 * gi + 1;
+    na.counter2 = (unsigned long long*)(ws + b->counter_off) + 3 * gi + 2;
+    launch_near_batch(gr.kernel, b->mixed, 1, na, gr.grid_m, st);
+  }
   for (int c = 0; c < b->n_cells; ++c) {
     if (runs[c].nt == 0) continue;
     int rc = cell_far(runs[c], out_pot ? out_pot + b->toff[c] : nullptr, out_grad ? out_grad + b->toff[c] : nullptr,

@@ -50,12 +50,14 @@ struct NearArgs {
   const int* perm;                       // binned position -> original target index
   int self;                              // targets are the sources (same indices)
   double beta, r2min;
+  const double *imx, *imy;               // image shifts (device, n_images each)
   const double* qsum;                    // mixed Laplace/Stokes: per split, sum of the
                                          // densities [split][qsum_stride] (NULL: no log shift)
   int qsum_stride;                       // n_dens * nc
   int diag;                              // 1: block t sums only the sources of the diag_len-point
                                          // tile that holds its targets (sources in binned order,
   int64_t diag_len;                      // self index = binned)
+  int atomic_out;                        // 1: add results to part with FP64 atomics
   double* part;                          // [split][n_dens*NOUT][n_trg]
   size_t part_stride;                    // doubles per split
 };
@@ -112,20 +114,21 @@ struct FarLArgs {
   int64_t out_stride;        // output rows are out_stride apart (n_trg for one cell)
 };
 
-// symmetric near field for targets == sources, one density vector: block
+// symmetric near field for targets == sources: block
 // (c, a) evaluates every pair (target tile a, source j in chunk c with j past
 // tile a) and all images once, for both points; results are added with FP64
 // atomics to acc, which already holds the tiles' own (diagonal) sums
 struct MutualArgs {
   int n_images;
-  double img_x[MAX_IMAGES], img_y[MAX_IMAGES];   // image shifts times sigma
+  const double *imx, *imy;               // image shifts times sigma (device, n_images each)
   double sigma;                          // coordinate scale (mixed Laplace/Stokes)
   int64_t n, chunk_len;
   const double *x, *y;                   // canonical points in binned order
-  const double* q64;                     // binned densities [nc][n]
+  const double* q64;                     // binned densities [n_dens][nc][n]
   const float* q32;                      // binned FP32 densities (mixed)
+  int dens0;                             // first density of this launch
   double beta;
-  double* acc;                           // [NOUT][n] in binned order
+  double* acc;                           // [n_dens][NOUT][n] in binned order
 };
 
 // one cell of a batched near-field launch; array offsets are byte offsets
@@ -133,8 +136,15 @@ struct MutualArgs {
 struct BatchCell {
   NearArgs args;             // sizes, geometry, beta, split length, flags
   int kernel, n_dens, n_tiles;
-  long long task0;           // first task index of this cell
+  long long task0;           // first task of this cell in the one-sided / diagonal launch
+  long long task0m;          // first task of this cell in the symmetric launch
   int64_t o_sx, o_sy, o_q64, o_q32, o_tx, o_ty, o_perm, o_part, o_qsum;
+  // symmetric near field (self targets): n_tiles diagonal tasks in the first
+  // launch, n_tiles * n_chunks (tile, chunk) tasks in the second; margs
+  // pointers are set per task
+  int mutual, n_chunks;
+  int64_t o_qb64, o_qb32;
+  MutualArgs margs;
 };
 
 struct BatchNearArgs {
@@ -143,6 +153,8 @@ struct BatchNearArgs {
   long long n_tasks;
   char* ws;
   unsigned long long* counter;   // zeroed before the launch
+  unsigned long long* counter2;  // second symmetric launch (remainder densities), zeroed
+  int n_dens, dens_begin, dens_end;
 };
 
 // launchers (kernels.hip)
@@ -150,9 +162,10 @@ void launch_prep_points(const PrepArgs& a, hipStream_t s);
 void launch_prep_dens(const PrepDensArgs& a, hipStream_t s);
 void launch_near(int kernel, bool mixed, int nd, const NearArgs& a, int n_splits, hipStream_t s);
 void launch_sort_targets(const SortArgs& a, hipStream_t s);
-void launch_near_batch(bool mixed, const BatchNearArgs& b, int grid, hipStream_t s);
+// phase 0: one-sided and diagonal tasks; phase 1: symmetric (tile, chunk) tasks
+void launch_near_batch(int kernel, bool mixed, int phase, const BatchNearArgs& b, int grid, hipStream_t s);
 void launch_qsum(const QsumArgs& a, int n_splits, hipStream_t s);
-void launch_near_mutual(int kernel, bool mixed, const MutualArgs& a, hipStream_t s);
+void launch_near_mutual(int kernel, bool mixed, const MutualArgs& a, int n_dens, hipStream_t s);
 // dst[c][k] = src[c][perm[k]] for c < ncomp (binned copies of the densities)
 void launch_gather_dens(const double* src, const int* perm, int64_t n, int ncomp, double* dst64,
                         float* dst32, hipStream_t s);

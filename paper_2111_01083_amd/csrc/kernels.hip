@@ -16,6 +16,11 @@ namespace pfmm {
 // ---------------------------------------------------------------------------
 // prep
 // ---------------------------------------------------------------------------
+// read-only tables (plan tables): loads through the constant address space
+// with a uniform index become scalar loads
+typedef const __attribute__((address_space(4))) double cdouble;
+__device__ __forceinline__ const cdouble* as_const(const double* p) { return (const cdouble*)p; }
+
 __global__ void prep_points_kernel(PrepArgs a) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
@@ -359,7 +364,7 @@ __device__ __forceinline__ void near_block(const NearArgs& a, int64_t tile, int6
     }
     __syncthreads();
     for (int im = 0; im < a.geo.n_images; ++im) {
-      const double txi = (tx - a.geo.img_x[im]) * a.geo.sigma, tyi = (ty - a.geo.img_y[im]) * a.geo.sigma;
+      const double txi = (tx - as_const(a.imx)[im]) * a.geo.sigma, tyi = (ty - as_const(a.imy)[im]) * a.geo.sigma;
       for (int jb = 0; jb < nt; jb += NEAR_FLUSH) {
         real p[ND][NA];
 #pragma unroll
@@ -420,7 +425,11 @@ __device__ __forceinline__ void near_block(const NearArgs& a, int64_t tile, int6
     double o[NO];
     near_outputs<K, MIXED>(acc[v], o, a.beta, a.geo.sigma);
 #pragma unroll
-    for (int c = 0; c < NO; ++c) dst[(size_t)((a.dens0 + v) * NO + c) * a.n_trg + k] = o[c];
+    for (int c = 0; c < NO; ++c) {
+      double* d = &dst[(size_t)((a.dens0 + v) * NO + c) * a.n_trg + k];
+      if (a.atomic_out) unsafeAtomicAdd(d, o[c]);
+      else *d = o[c];
+    }
   }
 }
 
@@ -435,81 +444,42 @@ __global__ __launch_bounds__(NEAR_BLOCK) void near_kernel(NearArgs a) {
   near_block<K, MIXED, ND>(a, blockIdx.x, blockIdx.y, s_pt, s_q, s_qd);
 }
 
-// Batched near field: a persistent grid; each block takes (cell, tile, split)
-// tasks from an atomic counter until none are left (every block reaches the
-// exit once the counter passes n_tasks).
-template <bool MIXED>
-__global__ __launch_bounds__(NEAR_BLOCK) void near_batch_kernel(BatchNearArgs b) {
-  using real = typename std::conditional<MIXED, float, double>::type;
-  __shared__ SrcPt s_pt[NEAR_TILE];
-  __shared__ real s_q[NEAR_TILE * 8];
-  __shared__ double s_qd[MIXED ? NEAR_TILE * 8 : 1];
-  __shared__ long long s_task;
-  for (;;) {
-    __syncthreads();
-    if (threadIdx.x == 0) s_task = (long long)atomicAdd(b.counter, 1ULL);
-    __syncthreads();
-    const long long t = s_task;
-    if (t >= b.n_tasks) break;
-    int c = 0;
-    while (c + 1 < b.n_cells && b.recs[c + 1].task0 <= t) ++c;
-    const BatchCell& r = b.recs[c];
-    const long long local = t - r.task0;
-    const int64_t tile = local % r.n_tiles, split = local / r.n_tiles;
-    NearArgs a = r.args;
-    char* ws = b.ws;
-    a.sx = (const double*)(ws + r.o_sx); a.sy = (const double*)(ws + r.o_sy);
-    a.q64 = (const double*)(ws + r.o_q64); a.q32 = (const float*)(ws + r.o_q32);
-    a.tx = (const double*)(ws + r.o_tx); a.ty = (const double*)(ws + r.o_ty);
-    a.perm = (const int*)(ws + r.o_perm); a.part = (double*)(ws + r.o_part);
-    a.qsum = r.o_qsum ? (const double*)(ws + r.o_qsum) : nullptr;
-    const int kern = r.kernel, nd = r.n_dens;
-    int v = 0;
-    if (kern == PFMM_LAPLACE) {
-      for (; v + 4 <= nd; v += 4) { a.dens0 = v; near_block<PFMM_LAPLACE, MIXED, 4>(a, tile, split, s_pt, s_q, s_qd); }
-      for (; v < nd; ++v) { a.dens0 = v; near_block<PFMM_LAPLACE, MIXED, 1>(a, tile, split, s_pt, s_q, s_qd); }
-    } else if (kern == PFMM_YUKAWA) {
-      for (; v + 4 <= nd; v += 4) { a.dens0 = v; near_block<PFMM_YUKAWA, MIXED, 4>(a, tile, split, s_pt, s_q, s_qd); }
-      for (; v < nd; ++v) { a.dens0 = v; near_block<PFMM_YUKAWA, MIXED, 1>(a, tile, split, s_pt, s_q, s_qd); }
-    } else {
-      for (; v + 4 <= nd; v += 4) { a.dens0 = v; near_block<PFMM_STOKES, MIXED, 4>(a, tile, split, s_pt, s_q, s_qd); }
-      for (; v < nd; ++v) { a.dens0 = v; near_block<PFMM_STOKES, MIXED, 1>(a, tile, split, s_pt, s_q, s_qd); }
-    }
-  }
-}
-
 // ---------------------------------------------------------------------------
-// Symmetric near field (targets == sources, one density vector). The free-
-// space kernel is even, G(-r) = G(r), so the pair (i, j, l) seen from i and
-// the pair (j, i, -l) seen from j share r^2 and every transcendental; only
-// the gradient changes sign. Block (a, c): the MU_BLOCK points of binned tile a
-// (one per thread) against the sources of chunk c that come after tile a.
-// Sources pass through LDS in sub-tiles of 64; in step st lane t pairs its
-// point with source (t + st) mod 64, so within a wavefront every lane works
-// on a different source and the source-side sums go to a per-wavefront LDS
-// row without conflicts or atomics. Block (a, c) = (blockIdx.x, blockIdx.y).
-// The 9 (or 15) images of a pair are
-// summed in registers first. Each sub-tile's source-side sums and, at the
-// end, each thread's own sums are converted to outputs and added to acc with
-// FP64 atomics (the summation order of these few adds is not fixed).
-// Precision as in the one-sided kernel: MIXED takes the coordinate
-// difference in FP64, the rest in FP32, log terms summed in FP64 with the
-// FP64 densities; the r = 0 guard is not needed (no point meets itself).
+// Symmetric near field (targets == sources). The free-space kernel is even,
+// G(-r) = G(r), so the pair (i, j, l) seen from i and the pair (j, i, -l)
+// seen from j share r^2 and every transcendental; only the gradient changes
+// sign. Block (a, c): the MU_BLOCK points of binned tile a (one per thread)
+// against the sources of chunk c that come after tile a, for ND density
+// vectors at once. Sources pass through LDS in sub-tiles of 64; in step st
+// lane t pairs its point with source (t + st) mod 64, so within a wavefront
+// every lane works on a different source and the source-side sums go to a
+// per-wavefront LDS row without conflicts or atomics. The 9 (or 15) images of
+// a pair are summed in registers first. Each sub-tile's source-side sums
+// and, at the end, each thread's own sums are converted to outputs and added
+// to acc with FP64 atomics (the order of these adds is not fixed, so repeated
+// runs agree to FP64 rounding). Precision as in the one-sided kernel: MIXED
+// takes the coordinate difference in FP64, the rest in FP32, log terms summed
+// in FP64 with the FP64 densities; no r = 0 guard is needed (no point meets
+// itself here).
 // ---------------------------------------------------------------------------
 constexpr int MU_SUB = 64;
 
-template <int K, bool MIXED, typename real>
+
+template <int K, bool MIXED, int ND, typename real>
 __device__ __forceinline__ void mutual_pair(real dx, real dy, const real* qi, const double* qid,
-                                            const real* qj, const double* qjd, real* pA, real* pB,
-                                            double* lA, double* lB, real beta) {
+                                            const real* qj, const double* qjd, real (*pA)[NAcc<K>::v],
+                                            real (*pB)[NAcc<K>::v], double (*lA)[2], double (*lB)[2], real beta) {
   if constexpr (K == PFMM_YUKAWA) {
     const real r2 = dx * dx + dy * dy;
     real k0, k1x;
     if constexpr (MIXED) bessel_k01_f32_wave(beta * __builtin_amdgcn_sqrtf(r2), k0, k1x);
     else bessel_k01_f64(beta * sqrt(r2), k0, k1x);
     const real gx = k1x * dx, gy = k1x * dy;
-    pA[0] += qj[0] * k0; pA[1] += qj[0] * gx; pA[2] += qj[0] * gy;
-    pB[0] += qi[0] * k0; pB[1] -= qi[0] * gx; pB[2] -= qi[0] * gy;
+#pragma unroll
+    for (int v = 0; v < ND; ++v) {
+      pA[v][0] += qj[v] * k0; pA[v][1] += qj[v] * gx; pA[v][2] += qj[v] * gy;
+      pB[v][0] += qi[v] * k0; pB[v][1] -= qi[v] * gx; pB[v][2] -= qi[v] * gy;
+    }
   } else {
     real lg, inv;
     if constexpr (MIXED) {
@@ -521,74 +491,103 @@ __device__ __forceinline__ void mutual_pair(real dx, real dy, const real* qi, co
       lg = log(r2);
       inv = 1.0 / r2;
     }
+    double lgd = 0.0;
+    if constexpr (MIXED) lgd = (double)lg;
     if constexpr (K == PFMM_LAPLACE) {
-      if constexpr (MIXED) {
-        const double lgd = (double)lg;
-        lA[0] = __builtin_fma(qjd[0], lgd, lA[0]);
-        lB[0] = __builtin_fma(qid[0], lgd, lB[0]);
-      } else {
-        pA[0] += qj[0] * lg; pB[0] += qi[0] * lg;
+#pragma unroll
+      for (int v = 0; v < ND; ++v) {
+        if constexpr (MIXED) {
+          lA[v][0] = __builtin_fma(qjd[v], lgd, lA[v][0]);
+          lB[v][0] = __builtin_fma(qid[v], lgd, lB[v][0]);
+        } else {
+          pA[v][0] += qj[v] * lg; pB[v][0] += qi[v] * lg;
+        }
+        const real sj = qj[v] * inv, si = qi[v] * inv;
+        pA[v][1] += sj * dx; pA[v][2] += sj * dy;
+        pB[v][1] -= si * dx; pB[v][2] -= si * dy;
       }
-      const real sj = qj[0] * inv, si = qi[0] * inv;
-      pA[1] += sj * dx; pA[2] += sj * dy;
-      pB[1] -= si * dx; pB[2] -= si * dy;
     } else {
       const real ia = inv * dx, ib = inv * dy;
-      if constexpr (MIXED) {
-        const double lgd = (double)lg;
-        lA[0] = __builtin_fma(qjd[0], lgd, lA[0]); lA[1] = __builtin_fma(qjd[1], lgd, lA[1]);
-        lB[0] = __builtin_fma(qid[0], lgd, lB[0]); lB[1] = __builtin_fma(qid[1], lgd, lB[1]);
-      } else {
-        pA[0] += lg * qj[0]; pA[1] += lg * qj[1];
-        pB[0] += lg * qi[0]; pB[1] += lg * qi[1];
+#pragma unroll
+      for (int v = 0; v < ND; ++v) {
+        const real* fj = qj + 2 * v;
+        const real* fi = qi + 2 * v;
+        if constexpr (MIXED) {
+          lA[v][0] = __builtin_fma(qjd[2 * v], lgd, lA[v][0]); lA[v][1] = __builtin_fma(qjd[2 * v + 1], lgd, lA[v][1]);
+          lB[v][0] = __builtin_fma(qid[2 * v], lgd, lB[v][0]); lB[v][1] = __builtin_fma(qid[2 * v + 1], lgd, lB[v][1]);
+        } else {
+          pA[v][0] += lg * fj[0]; pA[v][1] += lg * fj[1];
+          pB[v][0] += lg * fi[0]; pB[v][1] += lg * fi[1];
+        }
+        // seen from i (force F = f_j): c2 = ia F1 + ib F2, t = c2 ia
+        const real cA = ia * fj[0] + ib * fj[1], tA = cA * ia;
+        pA[v][2] += cA * dx; pA[v][3] += cA * dy; pA[v][4] += cA;
+        pA[v][5] += tA * dx; pA[v][6] += tA * dy; pA[v][7] += fj[1] * ia - fj[0] * ib;
+        // seen from j (force f_i, displacement -r): ia, ib change sign
+        const real cB = ia * fi[0] + ib * fi[1], tB = cB * ia;
+        pB[v][2] += cB * dx; pB[v][3] += cB * dy; pB[v][4] -= cB;
+        pB[v][5] -= tB * dx; pB[v][6] -= tB * dy; pB[v][7] -= fi[1] * ia - fi[0] * ib;
       }
-      // seen from i (force F = qj): c2 = ia F1 + ib F2, t = c2 ia
-      const real cA = ia * qj[0] + ib * qj[1], tA = cA * ia;
-      pA[2] += cA * dx; pA[3] += cA * dy; pA[4] += cA;
-      pA[5] += tA * dx; pA[6] += tA * dy; pA[7] += qj[1] * ia - qj[0] * ib;
-      // seen from j (force qi, displacement -r): ia, ib change sign
-      const real cB = ia * qi[0] + ib * qi[1], tB = cB * ia;
-      pB[2] += cB * dx; pB[3] += cB * dy; pB[4] -= cB;
-      pB[5] -= tB * dx; pB[6] -= tB * dy; pB[7] -= qi[1] * ia - qi[0] * ib;
     }
   }
 }
 
-template <int K, bool MIXED>
-__global__ __launch_bounds__(MU_BLOCK) void near_mutual_kernel(MutualArgs a) {
+// LDS bytes of one mutual_block
+template <int K, bool MIXED, int ND>
+constexpr size_t mutual_lds_bytes() {
+  using real = typename std::conditional<MIXED, float, double>::type;
+  constexpr int QN = ND * ((K == PFMM_STOKES) ? 2 : 1);
+  return 8 * (2 * MU_SUB) + 8 * (size_t)QN * MU_SUB + sizeof(real) * (size_t)QN * MU_SUB +
+         8 * (size_t)(MU_BLOCK / 64) * ND * NAcc<K>::v * MU_SUB;
+}
+
+// One (tile, chunk) task of the symmetric near field for densities
+// [a.dens0, a.dens0 + ND); smem: mutual_lds_bytes<K, MIXED, ND>() bytes,
+// 16-byte aligned. Every thread of the block must call it.
+template <int K, bool MIXED, int ND>
+__device__ __forceinline__ void mutual_block(const MutualArgs& a, int64_t tile, int64_t chunk, char* smem) {
   using real = typename std::conditional<MIXED, float, double>::type;
   constexpr int NC = (K == PFMM_STOKES) ? 2 : 1;
+  constexpr int QN = ND * NC;
   constexpr int NA = NAcc<K>::v;
   constexpr int NO = (K == PFMM_STOKES) ? 6 : 3;
   constexpr int NLOG = (MIXED && K != PFMM_YUKAWA) ? NC : 0;   // accumulators kept in FP64 pair by pair
   constexpr int NW = MU_BLOCK / 64;
-  __shared__ double s_x[MU_SUB], s_y[MU_SUB], s_qd[NC][MU_SUB];
-  __shared__ real s_q[NC][MU_SUB];
-  __shared__ double s_acc[NW][NA][MU_SUB];
+  double* s_x = (double*)smem;
+  double* s_y = s_x + MU_SUB;
+  double* s_qd = s_y + MU_SUB;                         // [QN][MU_SUB]
+  double* s_acc = s_qd + QN * MU_SUB;                  // [NW][ND*NA][MU_SUB]
+  real* s_q = (real*)(s_acc + NW * ND * NA * MU_SUB);  // [QN][MU_SUB]
 
-  const int64_t a0 = (int64_t)blockIdx.x * MU_BLOCK;
+  const int64_t a0 = tile * MU_BLOCK;
   const int64_t a_end = min(a0 + (int64_t)MU_BLOCK, a.n);
-  const int64_t b0 = max((int64_t)blockIdx.y * a.chunk_len, a_end);
-  const int64_t b1 = min((int64_t)(blockIdx.y + 1) * a.chunk_len, a.n);
+  const int64_t b0 = max(chunk * a.chunk_len, a_end);
+  const int64_t b1 = min((chunk + 1) * a.chunk_len, a.n);
   if (b0 >= b1) return;                                   // uniform over the block
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t k = a0 + tid;
   const bool act = k < a.n;
   const double sg = a.sigma;
   const double qscale = (K == PFMM_STOKES) ? 2.0 : 1.0;
+  const size_t qoff = (size_t)a.dens0 * NC * a.n;
   // an inactive lane sits far from every point with zero density
   const double tx = act ? a.x[k] * sg : 1.0e4, ty = act ? a.y[k] * sg : 1.0e4;
-  real qi[NC];
-  double qid[NC];
+  real qi[QN];
+  double qid[QN];
 #pragma unroll
-  for (int c = 0; c < NC; ++c) {
-    qid[c] = act ? qscale * a.q64[(size_t)c * a.n + k] : 0.0;
-    qi[c] = MIXED ? (act ? (real)(qscale * a.q32[(size_t)c * a.n + k]) : (real)0) : (real)qid[c];
+  for (int c = 0; c < QN; ++c) {
+    qid[c] = act ? qscale * a.q64[qoff + (size_t)c * a.n + k] : 0.0;
+    if constexpr (MIXED) qi[c] = act ? (real)(qscale * a.q32[qoff + (size_t)c * a.n + k]) : (real)0;
+    else qi[c] = qid[c];
   }
   const real beta = (real)a.beta;
-  double accA[NA];
+  const cdouble* imx = as_const(a.imx);
+  const cdouble* imy = as_const(a.imy);
+  double accA[ND][NA];
 #pragma unroll
-  for (int c = 0; c < NA; ++c) accA[c] = 0.0;
+  for (int v = 0; v < ND; ++v)
+#pragma unroll
+    for (int c = 0; c < NA; ++c) accA[v][c] = 0.0;
 
   for (int64_t sb = b0; sb < b1; sb += MU_SUB) {
     const int nsb = (int)min((int64_t)MU_SUB, b1 - sb);
@@ -599,64 +598,88 @@ __global__ __launch_bounds__(MU_BLOCK) void near_mutual_kernel(MutualArgs a) {
       s_x[tid] = ok ? a.x[j] * sg : -1.0e4;               // padding: far away, zero density
       s_y[tid] = ok ? a.y[j] * sg : -1.0e4;
 #pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        const double qd = ok ? qscale * a.q64[(size_t)c * a.n + j] : 0.0;
-        s_qd[c][tid] = qd;
-        s_q[c][tid] = MIXED ? (ok ? (real)(qscale * a.q32[(size_t)c * a.n + j]) : (real)0) : (real)qd;
+      for (int c = 0; c < QN; ++c) {
+        const double qd = ok ? qscale * a.q64[qoff + (size_t)c * a.n + j] : 0.0;
+        s_qd[c * MU_SUB + tid] = qd;
+        if constexpr (MIXED) s_q[c * MU_SUB + tid] = ok ? (real)(qscale * a.q32[qoff + (size_t)c * a.n + j]) : (real)0;
+        else s_q[c * MU_SUB + tid] = qd;
       }
     }
+    double* my_acc = s_acc + (size_t)wv * ND * NA * MU_SUB;
 #pragma unroll
-    for (int c = 0; c < NA; ++c) s_acc[wv][c][lane] = 0.0;
+    for (int c = 0; c < ND * NA; ++c) my_acc[c * MU_SUB + lane] = 0.0;
     __syncthreads();
     for (int st = 0; st < MU_SUB; ++st) {
       const int b = (lane + st) & (MU_SUB - 1);
       const double d0x = tx - s_x[b], d0y = ty - s_y[b];
-      real qj[NC];
-      double qjd[NC];
+      real qj[QN];
+      double qjd[QN];
 #pragma unroll
-      for (int c = 0; c < NC; ++c) { qj[c] = s_q[c][b]; qjd[c] = s_qd[c][b]; }
-      real pA[NA], pB[NA];
-      double lA[NC], lB[NC];
+      for (int c = 0; c < QN; ++c) { qj[c] = s_q[c * MU_SUB + b]; qjd[c] = s_qd[c * MU_SUB + b]; }
+      real pA[ND][NA], pB[ND][NA];
+      double lA[ND][2], lB[ND][2];
 #pragma unroll
-      for (int c = 0; c < NA; ++c) { pA[c] = 0; pB[c] = 0; }
+      for (int v = 0; v < ND; ++v) {
 #pragma unroll
-      for (int c = 0; c < NC; ++c) { lA[c] = 0; lB[c] = 0; }
+        for (int c = 0; c < NA; ++c) { pA[v][c] = 0; pB[v][c] = 0; }
+        lA[v][0] = lA[v][1] = lB[v][0] = lB[v][1] = 0.0;
+      }
       for (int im = 0; im < a.n_images; ++im) {
-        const real dx = (real)(d0x - a.img_x[im]), dy = (real)(d0y - a.img_y[im]);
-        mutual_pair<K, MIXED, real>(dx, dy, qi, qid, qj, qjd, pA, pB, lA, lB, beta);
+        const real dx = (real)(d0x - imx[im]), dy = (real)(d0y - imy[im]);
+        mutual_pair<K, MIXED, ND, real>(dx, dy, qi, qid, qj, qjd, pA, pB, lA, lB, beta);
       }
 #pragma unroll
-      for (int c = 0; c < NA; ++c) {
-        const double ea = c < NLOG ? lA[c < NC ? c : 0] : (double)pA[c];
-        const double eb = c < NLOG ? lB[c < NC ? c : 0] : (double)pB[c];
-        accA[c] += ea;
-        s_acc[wv][c][b] += eb;
+      for (int v = 0; v < ND; ++v) {
+#pragma unroll
+        for (int c = 0; c < NA; ++c) {
+          const double ea = c < NLOG ? lA[v][c < 2 ? c : 0] : (double)pA[v][c];
+          const double eb = c < NLOG ? lB[v][c < 2 ? c : 0] : (double)pB[v][c];
+          accA[v][c] += ea;
+          my_acc[(v * NA + c) * MU_SUB + b] += eb;
+        }
       }
     }
     __syncthreads();
     if (tid < nsb) {
-      double A[NA], o[NO];
 #pragma unroll
-      for (int c = 0; c < NA; ++c) {
-        double t = 0.0;
+      for (int v = 0; v < ND; ++v) {
+        double A[NA], o[NO];
 #pragma unroll
-        for (int w = 0; w < NW; ++w) t += s_acc[w][c][tid];
-        A[c] = t;
+        for (int c = 0; c < NA; ++c) {
+          double t = 0.0;
+#pragma unroll
+          for (int w = 0; w < NW; ++w) t += s_acc[((size_t)w * ND * NA + v * NA + c) * MU_SUB + tid];
+          A[c] = t;
+        }
+        near_outputs<K, MIXED>(A, o, a.beta, sg);
+#pragma unroll
+        for (int c = 0; c < NO; ++c)
+          unsafeAtomicAdd(&a.acc[((size_t)(a.dens0 + v) * NO + c) * a.n + sb + tid], o[c]);
       }
-      near_outputs<K, MIXED>(A, o, a.beta, sg);
-#pragma unroll
-      for (int c = 0; c < NO; ++c) unsafeAtomicAdd(&a.acc[(size_t)c * a.n + sb + tid], o[c]);
     }
   }
   if (act) {
-    double o[NO];
-    near_outputs<K, MIXED>(accA, o, a.beta, sg);
 #pragma unroll
-    for (int c = 0; c < NO; ++c) unsafeAtomicAdd(&a.acc[(size_t)c * a.n + k], o[c]);
+    for (int v = 0; v < ND; ++v) {
+      double o[NO];
+      near_outputs<K, MIXED>(accA[v], o, a.beta, sg);
+#pragma unroll
+      for (int c = 0; c < NO; ++c) unsafeAtomicAdd(&a.acc[((size_t)(a.dens0 + v) * NO + c) * a.n + k], o[c]);
+    }
   }
 }
 
-void launch_near_mutual(int kernel, bool mixed, const MutualArgs& a, hipStream_t s) {
+template <int K, bool MIXED, int ND>
+__global__ __launch_bounds__(MU_BLOCK) void near_mutual_kernel(MutualArgs a) {
+  __shared__ __align__(16) char smem[mutual_lds_bytes<K, MIXED, ND>()];
+  mutual_block<K, MIXED, ND>(a, blockIdx.x, blockIdx.y, smem);
+}
+
+// densities per pass of the symmetric kernel (register budget)
+template <int K> struct MuGroup { static constexpr int v = 4; };
+template <> struct MuGroup<PFMM_STOKES> { static constexpr int v = 2; };
+
+void launch_near_mutual(int kernel, bool mixed, const MutualArgs& a, int n_dens, hipStream_t s) {
   if (a.n <= MU_BLOCK) return;                           // one tile: the diagonal pass has it all
   const unsigned tiles = (unsigned)((a.n + MU_BLOCK - 1) / MU_BLOCK);
   const unsigned chunks = (unsigned)((a.n + a.chunk_len - 1) / a.chunk_len);
@@ -664,7 +687,11 @@ void launch_near_mutual(int kernel, bool mixed, const MutualArgs& a, hipStream_t
   auto go = [&](auto kc, auto mc) {
     constexpr int K = decltype(kc)::value;
     constexpr bool M = decltype(mc)::value;
-    hipLaunchKernelGGL((near_mutual_kernel<K, M>), grid, dim3(MU_BLOCK), 0, s, a);
+    constexpr int G = MuGroup<K>::v;
+    MutualArgs b = a;
+    int v = 0;
+    for (; v + G <= n_dens; v += G) { b.dens0 = v; hipLaunchKernelGGL((near_mutual_kernel<K, M, G>), grid, dim3(MU_BLOCK), 0, s, b); }
+    for (; v < n_dens; ++v) { b.dens0 = v; hipLaunchKernelGGL((near_mutual_kernel<K, M, 1>), grid, dim3(MU_BLOCK), 0, s, b); }
   };
   using L = std::integral_constant<int, PFMM_LAPLACE>;
   using Y = std::integral_constant<int, PFMM_YUKAWA>;
@@ -676,6 +703,81 @@ void launch_near_mutual(int kernel, bool mixed, const MutualArgs& a, hipStream_t
     case 3: go(Y{}, std::true_type{}); break;
     case 4: go(S{}, std::false_type{}); break;
     case 5: go(S{}, std::true_type{}); break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Batched near field: a persistent grid; each block takes tasks from an
+// atomic counter until none are left (every block reaches the exit once the
+// counter passes n_tasks). A one-sided cell has (target tile, source split)
+// tasks; a symmetric cell (self targets) has its diagonal tile tasks, which
+// write the partial row in a first launch, and its (tile, chunk) pair tasks,
+// which add to it with FP64 atomics in a second launch.
+// ---------------------------------------------------------------------------
+template <int K> constexpr size_t near_lds_bytes(bool mixed) {
+  return sizeof(SrcPt) * NEAR_TILE + (mixed ? 4 : 8) * NEAR_TILE * 8 + (mixed ? 8 * NEAR_TILE * 8 : 8);
+}
+
+template <int K, bool MIXED>
+__device__ __forceinline__ void batch_near_task(const BatchCell& r, char* ws, long long local, char* smem) {
+  using real = typename std::conditional<MIXED, float, double>::type;
+  SrcPt* s_pt = (SrcPt*)smem;
+  real* s_q = (real*)(smem + sizeof(SrcPt) * NEAR_TILE);
+  double* s_qd = (double*)(smem + sizeof(SrcPt) * NEAR_TILE + sizeof(real) * NEAR_TILE * 8);
+  NearArgs a = r.args;
+  int64_t tile, split;
+  if (r.mutual) {
+    // diagonal task: the tile's own sources in binned order
+    tile = local; split = 0;
+    a.sx = (const double*)(ws + r.o_tx); a.sy = (const double*)(ws + r.o_ty);
+    a.q64 = (const double*)(ws + r.o_qb64); a.q32 = (const float*)(ws + r.o_qb32);
+    a.diag = 1; a.diag_len = MU_BLOCK;
+  } else {
+    tile = local % r.n_tiles; split = local / r.n_tiles;
+    a.sx = (const double*)(ws + r.o_sx); a.sy = (const double*)(ws + r.o_sy);
+    a.q64 = (const double*)(ws + r.o_q64); a.q32 = (const float*)(ws + r.o_q32);
+  }
+  a.tx = (const double*)(ws + r.o_tx); a.ty = (const double*)(ws + r.o_ty);
+  a.perm = (const int*)(ws + r.o_perm); a.part = (double*)(ws + r.o_part);
+  a.qsum = r.o_qsum ? (const double*)(ws + r.o_qsum) : nullptr;
+  const int nd = r.n_dens;
+  int v = 0;
+  for (; v + 4 <= nd; v += 4) { a.dens0 = v; near_block<K, MIXED, 4>(a, tile, split, s_pt, s_q, s_qd); }
+  for (; v < nd; ++v) { a.dens0 = v; near_block<K, MIXED, 1>(a, tile, split, s_pt, s_q, s_qd); }
+}
+
+// densities [d0, d1) in groups of ND
+template <int K, bool MIXED, int ND>
+__device__ __forceinline__ void batch_mutual_task(const BatchCell& r, char* ws, long long local, int d0, int d1,
+                                                  char* smem) {
+  const int64_t tile = local % r.n_tiles, chunk = local / r.n_tiles;
+  MutualArgs m = r.margs;
+  m.x = (const double*)(ws + r.o_tx); m.y = (const double*)(ws + r.o_ty);
+  m.q64 = (const double*)(ws + r.o_qb64); m.q32 = (const float*)(ws + r.o_qb32);
+  m.acc = (double*)(ws + r.o_part);
+  for (int v = d0; v + ND <= d1; v += ND) { m.dens0 = v; mutual_block<K, MIXED, ND>(m, tile, chunk, smem); }
+}
+
+// one launch per kernel type and phase (phase 0: one-sided and diagonal
+// tasks, which write the partial rows; phase 1: symmetric tasks, which add)
+// (phase 1 is launched once per density group size ND, for densities
+// [b.dens_begin, b.dens_end))
+template <int K, bool MIXED, int PHASE, int ND>
+__global__ __launch_bounds__(NEAR_BLOCK) void near_batch_kernel(BatchNearArgs b) {
+  static_assert(MU_BLOCK == NEAR_BLOCK, "batched tasks share one block size");
+  __shared__ __align__(16) char smem[PHASE ? mutual_lds_bytes<K, MIXED, ND>() : near_lds_bytes<K>(MIXED)];
+  __shared__ long long s_task;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) s_task = (long long)atomicAdd(b.counter, 1ULL);
+    __syncthreads();
+    const long long t = s_task;
+    if (t >= b.n_tasks) break;
+    int c = 0;
+    while (c + 1 < b.n_cells && (PHASE ? b.recs[c + 1].task0m : b.recs[c + 1].task0) <= t) ++c;
+    const BatchCell& r = b.recs[c];
+    if constexpr (PHASE) batch_mutual_task<K, MIXED, ND>(r, b.ws, t - r.task0m, b.dens_begin, b.dens_end, smem);
+    else batch_near_task<K, MIXED>(r, b.ws, t - r.task0, smem);
   }
 }
 
@@ -720,10 +822,38 @@ void launch_qsum(const QsumArgs& a, int n_splits, hipStream_t s) {
   hipLaunchKernelGGL(qsum_kernel, dim3(n_splits, a.ncomp), dim3(256), 0, s, a);
 }
 
-void launch_near_batch(bool mixed, const BatchNearArgs& b, int grid, hipStream_t s) {
+void launch_near_batch(int kernel, bool mixed, int phase, const BatchNearArgs& b, int grid, hipStream_t s) {
   if (b.n_tasks <= 0) return;
-  if (mixed) hipLaunchKernelGGL(near_batch_kernel<true>, dim3(grid), dim3(NEAR_BLOCK), 0, s, b);
-  else hipLaunchKernelGGL(near_batch_kernel<false>, dim3(grid), dim3(NEAR_BLOCK), 0, s, b);
+  auto go = [&](auto kc, auto mc) {
+    constexpr int K = decltype(kc)::value;
+    constexpr bool M = decltype(mc)::value;
+    if (phase == 0) {
+      hipLaunchKernelGGL((near_batch_kernel<K, M, 0, 1>), dim3(grid), dim3(NEAR_BLOCK), 0, s, b);
+    } else {
+      constexpr int G = MuGroup<K>::v;
+      const int full = b.n_dens / G * G;
+      BatchNearArgs c = b;
+      if (full > 0) {
+        c.dens_begin = 0; c.dens_end = full;
+        hipLaunchKernelGGL((near_batch_kernel<K, M, 1, G>), dim3(grid), dim3(NEAR_BLOCK), 0, s, c);
+      }
+      if (full < b.n_dens) {
+        c.dens_begin = full; c.dens_end = b.n_dens; c.counter = b.counter2;
+        hipLaunchKernelGGL((near_batch_kernel<K, M, 1, 1>), dim3(grid), dim3(NEAR_BLOCK), 0, s, c);
+      }
+    }
+  };
+  using L = std::integral_constant<int, PFMM_LAPLACE>;
+  using Y = std::integral_constant<int, PFMM_YUKAWA>;
+  using S = std::integral_constant<int, PFMM_STOKES>;
+  switch (kernel * 2 + (mixed ? 1 : 0)) {
+    case 0: go(L{}, std::false_type{}); break;
+    case 1: go(L{}, std::true_type{}); break;
+    case 2: go(Y{}, std::false_type{}); break;
+    case 3: go(Y{}, std::true_type{}); break;
+    case 4: go(S{}, std::false_type{}); break;
+    case 5: go(S{}, std::true_type{}); break;
+  }
 }
 
 void launch_near(int kernel, bool mixed, int nd, const NearArgs& a, int n_splits, hipStream_t s) {

@@ -58,7 +58,7 @@ struct NufftParams {
 
 struct pfmm_plan_s {
   int kernel, precision, far_mode, m0, n_dens, self_exclude, check_neutral, profile;
-  int mutual;                  // near field by symmetric pair evaluation (self targets, one density)
+  int mutual;                  // near field by symmetric pair evaluation (self targets)
   double beta, tol, eps;
   pfmm::Geometry geo;
   int M, m_lo, n_sn;           // south/north modes m = m_lo..M
@@ -74,7 +74,8 @@ struct pfmm_plan_s {
   std::vector<double> nu_deconv;   // 1/phihat(m) for m = 0..M (real, even kernel)
   // device copies (per device, uploaded lazily)
   int dev_id;
-  double* d_tab;               // sn_tab | ew_tab | gl_nodes | gl_bary | nu_deconv
+  double* d_tab;               // sn_tab | ew_tab | gl_nodes | gl_bary | nu_deconv | images
+  size_t tab_img;              // offset in d_tab of img_x, img_y, then both times sigma
   size_t tab_doubles;
   // profiling: event triples (start, near done, end) of evaluations not yet read
   std::vector<void*> prof_events;

@@ -131,8 +131,8 @@ int build_plan(int kernel, const double* e1, const double* e2, double tol, const
   p->check_neutral = o.check_neutral ? 1 : 0;
   p->profile = o.profile ? 1 : 0;
   if (o.near_mode < 0 || o.near_mode > 2) return PFMM_EINVAL;
-  if (o.near_mode == PFMM_NEAR_MUTUAL && !(o.self_exclude && o.n_dens == 1)) return PFMM_EINVAL;
-  p->mutual = (o.near_mode != PFMM_NEAR_ONE_SIDED && o.self_exclude && o.n_dens == 1) ? 1 : 0;
+  if (o.near_mode == PFMM_NEAR_MUTUAL && !o.self_exclude) return PFMM_EINVAL;
+  p->mutual = (o.near_mode != PFMM_NEAR_ONE_SIDED && o.self_exclude) ? 1 : 0;
   p->beta = kernel == PFMM_YUKAWA ? o.beta : 0.0;
   p->tol = tol;
   p->eps = tol / 10;

@@ -124,10 +124,8 @@ def test_yukawa_west_east_dropped_when_negligible(P):
     (dict(kernel="laplace", e1=(1.0, 0.0), e2=(0.0, 1.0), tol=0.5), "PFMM_EINVAL_TOL"),
     (dict(kernel="yukawa", e1=(1.0, 0.0), e2=(0.0, 1.0), tol=1e-6), "PFMM_EINVAL"),
     (dict(kernel="laplace", e1=(1.0, 0.0), e2=(0.0, 1.0), tol=1e-6, n_dens=0), "PFMM_EINVAL"),
-    # symmetric pair evaluation needs targets == sources and one density vector
+    # symmetric pair evaluation needs targets == sources
     (dict(kernel="laplace", e1=(1.0, 0.0), e2=(0.0, 1.0), tol=1e-6, near_mode="mutual"), "PFMM_EINVAL"),
-    (dict(kernel="laplace", e1=(1.0, 0.0), e2=(0.0, 1.0), tol=1e-6, near_mode="mutual", self_exclude=True,
-          n_dens=2), "PFMM_EINVAL"),
 ])
 def test_plan_rejects_bad_arguments(P, kw, code):
     with pytest.raises(P.PfmmError) as e:
