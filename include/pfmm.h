@@ -188,6 +188,48 @@ int pfmm_eval_batch(pfmm_batch_t batch, const double* src_xy, const double* dens
                     void* workspace, size_t workspace_bytes, void* hip_stream);
 void pfmm_batch_destroy(pfmm_batch_t batch);
 
+/* Launch-shape tuning (host struct). The choices change only how the work
+ * is split across the GPU and the NUFFT grid; the NUFFT kernel width is
+ * chosen by the library for each grid so that the plan's tolerance holds. */
+typedef struct {
+  int64_t near_blocks;  /* near field: target number of blocks in flight (0 = default: 2048 for the
+                           one-sided sum, 8192 for the symmetric one) */
+  int nufft_grid;       /* NUFFT path: 0 = smallest power-of-two grid >= 2(2M+1) with width
+                           ceil(log10(1/eps)) + 1; 1 = twice that grid, one point narrower */
+} pfmm_tuning_t;
+
+/* Host: read or set a plan's tuning. nufft_grid = 1 is rejected (PFMM_EINVAL)
+ * when the doubled grid would exceed 4096 points. Not while an evaluation with
+ * this plan is being captured into a graph. */
+int pfmm_plan_get_tuning(pfmm_plan_t plan, pfmm_tuning_t* tuning);
+int pfmm_plan_set_tuning(pfmm_plan_t plan, const pfmm_tuning_t* tuning);
+
+typedef struct {
+  int n_tried;          /* configurations timed */
+  double default_ms;    /* GPU time of one evaluation with the tuning in place before the call */
+  double best_ms;       /* the same for the chosen tuning */
+} pfmm_tune_report_t;
+
+/* Autotuner: times candidate tunings (near_blocks; for NUFFT plans both
+ * grids) on the caller's inputs with HIP events, keeps the fastest in the
+ * plan and leaves the result of an evaluation with it in out_pot/out_grad.
+ * Arguments as for pfmm_eval; candidates that would need more than
+ * workspace_bytes are skipped. Synchronises hip_stream; not for use under
+ * stream capture. report (host) may be NULL. */
+int pfmm_autotune(pfmm_plan_t plan, int64_t n_src, const double* src_xy, const double* dens, int64_t n_trg,
+                  const double* trg_xy, double* out_pot, double* out_grad, void* workspace,
+                  size_t workspace_bytes, void* hip_stream, pfmm_tune_report_t* report);
+
+/* Batched autotuner: times task lengths (4096, 8192, 16384 sources) and
+ * persistent grid sizes (2, 4, 8 blocks per compute unit) of a batch on the
+ * caller's inputs, keeps the fastest and leaves its result in the outputs.
+ * The batch's workspace size may change: read pfmm_batch_workspace_bytes
+ * again afterwards (candidates larger than workspace_bytes are skipped, so
+ * the chosen one fits the workspace passed here). */
+int pfmm_batch_autotune(pfmm_batch_t batch, const double* src_xy, const double* dens, const double* trg_xy,
+                        double* out_pot, double* out_grad, void* workspace, size_t workspace_bytes,
+                        void* hip_stream, pfmm_tune_report_t* report);
+
 void pfmm_destroy(pfmm_plan_t plan);
 const char* pfmm_strerror(int code);
 

@@ -86,6 +86,13 @@ class Plan:
                "pfmm_plan_stage_times")
         return a.value, b.value, n.value
 
+    @property
+    def tuning(self):
+        return pfmm_plan_get_tuning(self)
+
+    def set_tuning(self, near_blocks=None, nufft_grid=None):
+        pfmm_plan_set_tuning(self, near_blocks, nufft_grid)
+
     def __call__(self, src, dens, trg=None, **kw):
         return pfmm_eval(self, src, dens, trg, **kw)
 
@@ -170,6 +177,62 @@ def pfmm_eval(plan, src, dens, trg=None, out_pot=None, out_grad=None, workspace=
         out_pot = None if out_pot is None else out_pot[0]
         out_grad = None if out_grad is None else out_grad[0]
     return out_pot, out_grad
+
+
+def pfmm_plan_get_tuning(plan):
+    t = L.pfmm_tuning_t()
+    _check(L.load().pfmm_plan_get_tuning(plan.handle, ctypes.byref(t)), "pfmm_plan_get_tuning")
+    return {"near_blocks": int(t.near_blocks), "nufft_grid": int(t.nufft_grid)}
+
+
+def pfmm_plan_set_tuning(plan, near_blocks=None, nufft_grid=None):
+    cur = pfmm_plan_get_tuning(plan)
+    t = L.pfmm_tuning_t(int(cur["near_blocks"] if near_blocks is None else near_blocks),
+                        int(cur["nufft_grid"] if nufft_grid is None else nufft_grid))
+    _check(L.load().pfmm_plan_set_tuning(plan.handle, ctypes.byref(t)), "pfmm_plan_set_tuning")
+
+
+def _tuning_workspace_bytes(plan, ns, nt):
+    # the largest workspace over the autotuner's candidates
+    start = pfmm_plan_get_tuning(plan)
+    best = pfmm_workspace_bytes(plan, ns, nt)
+    try:
+        for nb in (4096, 16384):
+            for g in (0, 1):
+                try:
+                    pfmm_plan_set_tuning(plan, nb, g)
+                except PfmmError:
+                    continue
+                best = max(best, pfmm_workspace_bytes(plan, ns, nt))
+    finally:
+        pfmm_plan_set_tuning(plan, start["near_blocks"], start["nufft_grid"])
+    return best
+
+
+def pfmm_autotune(plan, src, dens, trg=None, out_pot=None, out_grad=None, workspace=None, stream=None):
+    """Time the tuning candidates on these inputs and keep the fastest in the
+    plan (see pfmm.h); returns (report dict, pot, grad) with the outputs of
+    an evaluation with the chosen tuning."""
+    torch = _torch()
+    lib = L.load()
+    src = _as_dev(src, "src"); dens = _as_dev(dens, "dens")
+    ns = src.shape[1]
+    stokes = plan.kernel == L.PFMM_STOKES
+    nd = plan.n_dens
+    trg_t = None if plan.self_exclude else _as_dev(trg, "trg")
+    nt = ns if trg_t is None else trg_t.shape[1]
+    if out_pot is None:
+        out_pot = torch.empty((nd, 2, nt) if stokes else (nd, nt), dtype=torch.float64, device=src.device)
+    if out_grad is None:
+        out_grad = torch.empty((nd, 4 if stokes else 2, nt), dtype=torch.float64, device=src.device)
+    ws, wptr, avail = _workspace(_tuning_workspace_bytes(plan, ns, nt), src.device, workspace)
+    rep = L.pfmm_tune_report_t()
+    _check(lib.pfmm_autotune(plan.handle, ns, src.data_ptr(), dens.data_ptr(), nt,
+                             None if trg_t is None else trg_t.data_ptr(), out_pot.data_ptr(), out_grad.data_ptr(),
+                             wptr, avail, _stream_ptr(stream), ctypes.byref(rep)), "pfmm_autotune")
+    report = {"n_tried": rep.n_tried, "default_ms": rep.default_ms, "best_ms": rep.best_ms,
+              **pfmm_plan_get_tuning(plan)}
+    return report, out_pot, out_grad
 
 
 def pfmm_workspace_bytes_adjoint(plan, n_src):
@@ -262,6 +325,9 @@ class Batch:
     def __call__(self, src, dens, trg=None, out_pot=None, out_grad=None, workspace=None, stream=None):
         return pfmm_eval_batch(self, src, dens, trg, out_pot, out_grad, workspace, stream)
 
+    def autotune(self, src, dens, trg=None, stream=None):
+        return pfmm_batch_autotune(self, src, dens, trg, stream=stream)
+
 
 def pfmm_eval_batch(batch, src, dens, trg=None, out_pot=None, out_grad=None, workspace=None, stream=None):
     """Evaluate every cell of a Batch; arrays are concatenated over cells.
@@ -282,6 +348,30 @@ def pfmm_eval_batch(batch, src, dens, trg=None, out_pot=None, out_grad=None, wor
                                None if trg_t is None else trg_t.data_ptr(), out_pot.data_ptr(),
                                out_grad.data_ptr(), wptr, avail, _stream_ptr(stream)), "pfmm_eval_batch")
     return out_pot, out_grad
+
+
+def pfmm_batch_autotune(batch, src, dens, trg=None, out_pot=None, out_grad=None, workspace=None, stream=None):
+    """Time task lengths and persistent grid sizes on these inputs and keep
+    the fastest in the batch; returns (report dict, pot, grad)."""
+    torch = _torch()
+    lib = L.load()
+    src = _as_dev(src, "src"); dens = _as_dev(dens, "dens")
+    T = int(batch.src_off[-1] if batch.self_exclude else batch.trg_off[-1])
+    trg_t = None if batch.self_exclude else _as_dev(trg, "trg")
+    nd = batch.n_dens
+    if out_pot is None:
+        out_pot = torch.empty((nd, 2, T) if batch.stokes else (nd, T), dtype=torch.float64, device=src.device)
+    if out_grad is None:
+        out_grad = torch.empty((nd, 4 if batch.stokes else 2, T), dtype=torch.float64, device=src.device)
+    # room for candidates with more source splits than the current one
+    ws, wptr, avail = _workspace(2 * batch.workspace_bytes, src.device, workspace)
+    rep = L.pfmm_tune_report_t()
+    _check(lib.pfmm_batch_autotune(batch.handle, src.data_ptr(), dens.data_ptr(),
+                                   None if trg_t is None else trg_t.data_ptr(), out_pot.data_ptr(),
+                                   out_grad.data_ptr(), wptr, avail, _stream_ptr(stream), ctypes.byref(rep)),
+           "pfmm_batch_autotune")
+    batch.workspace_bytes = int(lib.pfmm_batch_workspace_bytes(batch.handle))
+    return {"n_tried": rep.n_tried, "default_ms": rep.default_ms, "best_ms": rep.best_ms}, out_pot, out_grad
 
 
 def pfmm_strerror(code):

@@ -21,6 +21,7 @@ EXPORTS = ["pfmm_plan", "pfmm_plan_upload", "pfmm_plan_get_info", "pfmm_plan_get
            "pfmm_plan_stage_times",
            "pfmm_workspace_bytes", "pfmm_eval", "pfmm_workspace_bytes_adjoint", "pfmm_eval_adjoint",
            "pfmm_batch_create", "pfmm_batch_workspace_bytes", "pfmm_eval_batch", "pfmm_batch_destroy",
+           "pfmm_plan_get_tuning", "pfmm_plan_set_tuning", "pfmm_autotune", "pfmm_batch_autotune",
            "pfmm_destroy", "pfmm_strerror"]
 
 
@@ -38,6 +39,14 @@ class pfmm_plan_info_t(ctypes.Structure):
                 ("rot_cos", ctypes.c_double), ("rot_sin", ctypes.c_double), ("eps", ctypes.c_double),
                 ("n_modes", ctypes.c_int), ("n_quad", ctypes.c_int), ("m_gl", ctypes.c_int),
                 ("nufft_nf", ctypes.c_int), ("nufft_w", ctypes.c_int), ("n_images", ctypes.c_int)]
+
+
+class pfmm_tuning_t(ctypes.Structure):
+    _fields_ = [("near_blocks", ctypes.c_int64), ("nufft_grid", ctypes.c_int)]
+
+
+class pfmm_tune_report_t(ctypes.Structure):
+    _fields_ = [("n_tried", ctypes.c_int), ("default_ms", ctypes.c_double), ("best_ms", ctypes.c_double)]
 
 
 _lib = None
@@ -80,6 +89,16 @@ def load():
     lib.pfmm_eval_batch.restype = c_int
     lib.pfmm_batch_destroy.argtypes = [vp]
     lib.pfmm_batch_destroy.restype = None
+    lib.pfmm_plan_get_tuning.argtypes = [vp, ctypes.POINTER(pfmm_tuning_t)]
+    lib.pfmm_plan_get_tuning.restype = c_int
+    lib.pfmm_plan_set_tuning.argtypes = [vp, ctypes.POINTER(pfmm_tuning_t)]
+    lib.pfmm_plan_set_tuning.restype = c_int
+    lib.pfmm_autotune.argtypes = [vp, i64, vp, vp, i64, vp, vp, vp, vp, ctypes.c_size_t, vp,
+                                  ctypes.POINTER(pfmm_tune_report_t)]
+    lib.pfmm_autotune.restype = c_int
+    lib.pfmm_batch_autotune.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp,
+                                        ctypes.POINTER(pfmm_tune_report_t)]
+    lib.pfmm_batch_autotune.restype = c_int
     lib.pfmm_destroy.argtypes = [vp]
     lib.pfmm_destroy.restype = None
     lib.pfmm_strerror.argtypes = [c_int]

@@ -74,7 +74,9 @@ void plan_layout(const pfmm_plan_s* p, int64_t ns, int64_t nt, Layout& L, int64_
   // source splits for the near field: aim for >= 2048 blocks in flight
   int64_t tiles = std::max<int64_t>(1, (nt + NEAR_BLOCK - 1) / NEAR_BLOCK);
   int64_t max_s = std::max<int64_t>(1, (ns + NEAR_TILE - 1) / NEAR_TILE);
-  int64_t S = std::min<int64_t>(std::min<int64_t>((2048 + tiles - 1) / tiles, max_s), 64);
+  // blocks in flight: the tuned target, else 2048 (one-sided) / 8192 (symmetric)
+  const int64_t target = p->tune_near > 0 ? p->tune_near : 0;
+  int64_t S = std::min<int64_t>(std::min<int64_t>(((target ? target : 2048) + tiles - 1) / tiles, max_s), 64);
   S = std::max<int64_t>(S, 1);
   int64_t per = (ns + S - 1) / S;
   if (forced_split > 0) per = forced_split;
@@ -96,7 +98,7 @@ void plan_layout(const pfmm_plan_s* p, int64_t ns, int64_t nt, Layout& L, int64_
     L.qb32 = mixed ? take(4 * (size_t)p->n_dens * nc * ns) : 0;
     // about 8192 source chunks x target tiles in total (half of them empty)
     const int64_t tiles = (ns + MU_BLOCK - 1) / MU_BLOCK;
-    const int64_t want = std::max<int64_t>(1, (8192 * 256 / MU_BLOCK + tiles - 1) / tiles);
+    const int64_t want = std::max<int64_t>(1, ((target ? target : 8192) * 256 / MU_BLOCK + tiles - 1) / tiles);
     int64_t cl = forced_split > 0 ? forced_split : std::max<int64_t>(1024, (ns + want - 1) / want);
     L.mu_chunk = (cl + 63) / 64 * 64;
   }
@@ -135,11 +137,11 @@ int pfmm_plan(int kernel, const double* e1, const double* e2, double tol, const 
   return PFMM_OK;
 }
 
-int pfmm_plan_upload(pfmm_plan_t p) {
-  if (!p) return PFMM_EINVAL;
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return PFMM_EHIP;
-  if (p->d_tab && p->dev_id == dev) return PFMM_OK;
+}  // extern "C"
+
+// the plan's device table: sn | ew | GL nodes | barycentric weights |
+// NUFFT deconvolution | images (plain, then times sigma)
+static std::vector<double> plan_table(pfmm_plan_s* p) {
   std::vector<double> tab;
   tab.insert(tab.end(), p->sn_tab.begin(), p->sn_tab.end());
   tab.insert(tab.end(), p->ew_tab.begin(), p->ew_tab.end());
@@ -154,6 +156,27 @@ int pfmm_plan_upload(pfmm_plan_t p) {
     for (int i = 0; i < g.n_images; ++i) tab.push_back(g.img_y[i] * f);
   }
   tab.push_back(0.0);
+  return tab;
+}
+
+// rewrite an uploaded table in place (same size; device pointers into it,
+// e.g. in batch records, stay valid)
+static int plan_refresh_device(pfmm_plan_s* p) {
+  if (!p->d_tab) return PFMM_OK;
+  std::vector<double> tab = plan_table(p);
+  if (tab.size() != p->tab_doubles) return PFMM_EINVAL;
+  return hipMemcpy(p->d_tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess
+             ? PFMM_OK : PFMM_EHIP;
+}
+
+extern "C" {
+
+int pfmm_plan_upload(pfmm_plan_t p) {
+  if (!p) return PFMM_EINVAL;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return PFMM_EHIP;
+  if (p->d_tab && p->dev_id == dev) return PFMM_OK;
+  std::vector<double> tab = plan_table(p);
   if (p->d_tab) { (void)hipFree(p->d_tab); p->d_tab = nullptr; }
   double* d = nullptr;
   if (hipMalloc(&d, tab.size() * sizeof(double)) != hipSuccess) return PFMM_ENOMEM;
@@ -472,6 +495,114 @@ const char* pfmm_strerror(int code) {
 
 }  // extern "C"
 
+
+// ---------------------------------------------------------------------------
+// Autotuning: candidates timed with HIP events on the caller's inputs.
+// ---------------------------------------------------------------------------
+namespace {
+// one warm-up and two timed evaluations; per-evaluation near and total ms
+int time_eval(pfmm_plan_s* p, int64_t ns, const double* src_xy, const double* dens, int64_t nt, const double* trg_xy,
+              double* out_pot, double* out_grad, void* ws, size_t ws_bytes, void* stream, double* near_ms,
+              double* total_ms) {
+  const int saved = p->profile;
+  p->profile = 1;
+  int rc = pfmm_plan_stage_times(p, nullptr, nullptr, nullptr);
+  if (!rc) rc = eval_core(p, ns, src_xy, dens, nt, trg_xy, out_pot, out_grad, ws, ws_bytes, stream);
+  if (!rc) rc = pfmm_plan_stage_times(p, nullptr, nullptr, nullptr);
+  for (int k = 0; k < 2 && !rc; ++k)
+    rc = eval_core(p, ns, src_xy, dens, nt, trg_xy, out_pot, out_grad, ws, ws_bytes, stream);
+  double nm = 0, tm = 0;
+  int cnt = 0;
+  const int rc2 = pfmm_plan_stage_times(p, &nm, &tm, &cnt);
+  p->profile = saved;
+  if (rc) return rc;
+  if (rc2) return rc2;
+  *near_ms = nm / std::max(cnt, 1);
+  *total_ms = tm / std::max(cnt, 1);
+  return PFMM_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int pfmm_plan_get_tuning(pfmm_plan_t p, pfmm_tuning_t* t) {
+  if (!p || !t) return PFMM_EINVAL;
+  t->near_blocks = p->tune_near;
+  t->nufft_grid = p->nu_grid;
+  return PFMM_OK;
+}
+
+int pfmm_plan_set_tuning(pfmm_plan_t p, const pfmm_tuning_t* t) {
+  if (!p || !t || t->near_blocks < 0 || t->near_blocks > (1LL << 24)) return PFMM_EINVAL;
+  if (t->nufft_grid != p->nu_grid) {
+    const int old = p->nu_grid;
+    int rc = set_nufft_grid(p, t->nufft_grid);
+    if (rc) { (void)set_nufft_grid(p, old); return rc; }
+    rc = plan_refresh_device(p);
+    if (rc) return rc;
+  }
+  p->tune_near = t->near_blocks;
+  return PFMM_OK;
+}
+
+int pfmm_autotune(pfmm_plan_t p, int64_t ns, const double* src_xy, const double* dens, int64_t nt,
+                  const double* trg_xy, double* out_pot, double* out_grad, void* ws, size_t ws_bytes,
+                  void* stream, pfmm_tune_report_t* report) {
+  if (!p || ns <= 0 || nt <= 0 || (!out_pot && !out_grad)) return PFMM_EINVAL;
+  pfmm_tuning_t cur{};
+  pfmm_plan_get_tuning(p, &cur);
+  const pfmm_tuning_t start = cur;
+  double nm = 0, tm = 0;
+  int rc = time_eval(p, ns, src_xy, dens, nt, trg_xy, out_pot, out_grad, ws, ws_bytes, stream, &nm, &tm);
+  if (rc) return rc;
+  const double start_ms = tm;
+  int tried = 1;
+  // near field: blocks in flight
+  const bool mutual = p->mutual && p->self_exclude && ns == nt;
+  const int64_t near_c[3] = {mutual ? 4096 : 1024, mutual ? 8192 : 2048, mutual ? 16384 : 4096};
+  pfmm_tuning_t best = cur;
+  double best_near = nm;
+  for (int64_t c : near_c) {
+    pfmm_tuning_t t = cur;
+    t.near_blocks = c;
+    if (t.near_blocks == cur.near_blocks) continue;
+    if ((rc = pfmm_plan_set_tuning(p, &t))) return rc;
+    if (cell_workspace(p, ns, nt, 0) > ws_bytes) continue;
+    double n1, t1;
+    if ((rc = time_eval(p, ns, src_xy, dens, nt, trg_xy, out_pot, out_grad, ws, ws_bytes, stream, &n1, &t1))) return rc;
+    ++tried;
+    if (n1 < best_near) { best_near = n1; best = t; }
+  }
+  if ((rc = pfmm_plan_set_tuning(p, &best))) return rc;
+  cur = best;
+  // NUFFT grid (the far part is the total minus the near field)
+  if (p->use_nufft) {
+    double n0, t0;
+    if ((rc = time_eval(p, ns, src_xy, dens, nt, trg_xy, out_pot, out_grad, ws, ws_bytes, stream, &n0, &t0))) return rc;
+    double best_far = t0 - n0;
+    for (int g = 0; g < 2; ++g) {
+      if (g == cur.nufft_grid) continue;
+      pfmm_tuning_t t = cur;
+      t.nufft_grid = g;
+      if (pfmm_plan_set_tuning(p, &t) != PFMM_OK) continue;   // grid not available
+      if (cell_workspace(p, ns, nt, 0) > ws_bytes) continue;
+      double n1, t1;
+      if ((rc = time_eval(p, ns, src_xy, dens, nt, trg_xy, out_pot, out_grad, ws, ws_bytes, stream, &n1, &t1))) return rc;
+      ++tried;
+      if (t1 - n1 < best_far) { best_far = t1 - n1; best = t; }
+    }
+    if ((rc = pfmm_plan_set_tuning(p, &best))) return rc;
+  }
+  // the outputs hold the result of the chosen tuning
+  double nb, tb;
+  if ((rc = time_eval(p, ns, src_xy, dens, nt, trg_xy, out_pot, out_grad, ws, ws_bytes, stream, &nb, &tb))) return rc;
+  if (report) { report->n_tried = tried; report->default_ms = start_ms; report->best_ms = tb; }
+  (void)start;
+  return PFMM_OK;
+}
+
+}  // extern "C"
+
 // ---------------------------------------------------------------------------
 // Batched evaluation: per-cell prep, one persistent near-field launch over the
 // tasks (cell, target tile, source split) of every cell, per-cell far field.
@@ -491,12 +622,108 @@ struct pfmm_batch_s {
   // diagonal launch and of the symmetric launch
   struct Group { int kernel, rec0, n_recs; long long n_tasks, n_tasks_m; int grid, grid_m; } groups[3];
   int n_groups;
+  int64_t split;                        // sources per near-field task (chunk or split length)
+  int grid_mult;                        // persistent blocks per compute unit
   BatchCell* d_recs;
   hipStream_t cap_stream;
   hipGraphExec_t exec;
   const void* cap_args[5];
   void* cap_ws;
 };
+
+// (Re)build a batch's workspace layout, task records and launch shapes for
+// task length `split` and `grid_mult` persistent blocks per compute unit.
+static int batch_build(pfmm_batch_s* b, int64_t split, int grid_mult) {
+  const int n_cells = b->n_cells;
+  // workspace: cells in order, then the task counter
+  size_t off = 0;
+  b->base.resize(n_cells);
+  std::vector<CellRun> runs(n_cells);
+  for (int c = 0; c < n_cells; ++c) {
+    const int64_t ns = b->soff[c + 1] - b->soff[c], nt = b->toff[c + 1] - b->toff[c];
+    b->base[c] = off;
+    cell_setup(b->plans[c], ns, nt, nullptr, split, runs[c]);
+    off += align_up(runs[c].L.total);
+  }
+  b->counter_off = off;
+  b->total = off + 256;
+  // task records, most expensive cells first
+  std::vector<int> order(n_cells);
+  for (int c = 0; c < n_cells; ++c) order[c] = c;
+  auto cost = [&](int c) {
+    return (double)(b->soff[c + 1] - b->soff[c]) * (double)(b->toff[c + 1] - b->toff[c]) * b->plans[c]->geo.n_images;
+  };
+  // one persistent launch per kernel type; within it, most expensive cells first
+  std::stable_sort(order.begin(), order.end(), [&](int a, int bb) {
+    if (b->plans[a]->kernel != b->plans[bb]->kernel) return b->plans[a]->kernel < b->plans[bb]->kernel;
+    return cost(a) > cost(bb);
+  });
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  std::vector<BatchCell> recs;
+  long long task = 0, task_m = 0;
+  b->n_groups = 0;
+  auto close_group = [&]() {
+    if (b->n_groups == 0) return;
+    pfmm_batch_s::Group& gr = b->groups[b->n_groups - 1];
+    gr.n_recs = (int)recs.size() - gr.rec0;
+    gr.n_tasks = task;
+    gr.n_tasks_m = task_m;
+    gr.grid = (int)std::max<long long>(1, std::min<long long>(task, (long long)grid_mult * cus));
+    gr.grid_m = (int)std::max<long long>(1, std::min<long long>(task_m, (long long)grid_mult * cus));
+  };
+  for (int c : order) {
+    const CellRun& r = runs[c];
+    if (r.ns == 0 || r.nt == 0) continue;
+    if (b->n_groups == 0 || b->groups[b->n_groups - 1].kernel != b->plans[c]->kernel) {
+      close_group();
+      b->groups[b->n_groups++] = {b->plans[c]->kernel, (int)recs.size(), 0, 0, 0, 1, 1};
+      task = 0; task_m = 0;
+    }
+    BatchCell bc{};
+    CellRun rr = r;
+    rr.ws = nullptr;
+    bc.args = cell_near_args(rr);
+    const size_t B = b->base[c];
+    const Layout& L = r.L;
+    const bool mixed = b->mixed;
+    bc.o_sx = B + L.scx; bc.o_sy = B + L.scy;
+    bc.o_q64 = B + L.dens_c; bc.o_q32 = mixed ? B + L.q32 : 0;
+    bc.o_tx = B + L.stx; bc.o_ty = B + L.sty; bc.o_perm = B + L.perm; bc.o_part = B + L.near_part;
+    bc.o_qsum = L.qsum ? B + L.qsum : 0;
+    bc.kernel = b->plans[c]->kernel; bc.n_dens = b->n_dens;
+    bc.n_tiles = (int)((r.nt + NEAR_BLOCK - 1) / NEAR_BLOCK);
+    bc.task0 = task;
+    bc.task0m = task_m;
+    bc.mutual = L.mutual;
+    if (L.mutual) {
+      const Geometry& g = b->plans[c]->geo;
+      MutualArgs& m = bc.margs;
+      m.n_images = g.n_images;
+      m.imx = b->plans[c]->d_tab + b->plans[c]->tab_img + 2 * g.n_images; m.imy = m.imx + g.n_images;
+      m.sigma = g.sigma; m.n = r.ns; m.chunk_len = L.mu_chunk; m.beta = b->plans[c]->beta;
+      bc.n_chunks = (int)((r.ns + L.mu_chunk - 1) / L.mu_chunk);
+      bc.o_qb64 = B + L.qb64; bc.o_qb32 = mixed ? B + L.qb32 : 0;
+      task += bc.n_tiles;
+      task_m += (long long)bc.n_tiles * bc.n_chunks;
+    } else {
+      task += (long long)bc.n_tiles * L.n_splits;
+    }
+    recs.push_back(bc);
+  }
+  close_group();
+  if (b->d_recs) { (void)hipFree(b->d_recs); b->d_recs = nullptr; }
+  if (!recs.empty()) {
+    if (hipMalloc(&b->d_recs, recs.size() * sizeof(BatchCell)) != hipSuccess) return PFMM_ENOMEM;
+    if (hipMemcpy(b->d_recs, recs.data(), recs.size() * sizeof(BatchCell), hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipFree(b->d_recs); b->d_recs = nullptr; return PFMM_EHIP;
+    }
+  }
+  b->n_recs = (int)recs.size();
+  b->split = split; b->grid_mult = grid_mult;
+  if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }   // task tables changed
+  return PFMM_OK;
+}
 
 extern "C" {
 
@@ -528,90 +755,9 @@ int pfmm_batch_create(int n_cells, const pfmm_plan_t* plans, const int64_t* src_
     int rc = pfmm_plan_upload(plans[c]);
     if (rc) { delete b; return rc; }
   }
-  // workspace: cells in order, then the task counter
-  size_t off = 0;
-  b->base.resize(n_cells);
-  std::vector<CellRun> runs(n_cells);
-  for (int c = 0; c < n_cells; ++c) {
-    const int64_t ns = b->soff[c + 1] - b->soff[c], nt = b->toff[c + 1] - b->toff[c];
-    b->base[c] = off;
-    cell_setup(plans[c], ns, nt, nullptr, BATCH_SPLIT, runs[c]);
-    off += align_up(runs[c].L.total);
-  }
-  b->counter_off = off;
-  b->total = off + 256;
-  // task records, most expensive cells first
-  std::vector<int> order(n_cells);
-  for (int c = 0; c < n_cells; ++c) order[c] = c;
-  auto cost = [&](int c) {
-    return (double)(b->soff[c + 1] - b->soff[c]) * (double)(b->toff[c + 1] - b->toff[c]) * plans[c]->geo.n_images;
-  };
-  // one persistent launch per kernel type; within it, most expensive cells first
-  std::stable_sort(order.begin(), order.end(), [&](int a, int bb) {
-    if (plans[a]->kernel != plans[bb]->kernel) return plans[a]->kernel < plans[bb]->kernel;
-    return cost(a) > cost(bb);
-  });
-  int dev = 0, cus = 256;
-  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  std::vector<BatchCell> recs;
-  long long task = 0, task_m = 0;
-  b->n_groups = 0;
-  auto close_group = [&]() {
-    if (b->n_groups == 0) return;
-    pfmm_batch_s::Group& gr = b->groups[b->n_groups - 1];
-    gr.n_recs = (int)recs.size() - gr.rec0;
-    gr.n_tasks = task;
-    gr.n_tasks_m = task_m;
-    gr.grid = (int)std::max<long long>(1, std::min<long long>(task, 4LL * cus));
-    gr.grid_m = (int)std::max<long long>(1, std::min<long long>(task_m, 4LL * cus));
-  };
-  for (int c : order) {
-    const CellRun& r = runs[c];
-    if (r.ns == 0 || r.nt == 0) continue;
-    if (b->n_groups == 0 || b->groups[b->n_groups - 1].kernel != plans[c]->kernel) {
-      close_group();
-      b->groups[b->n_groups++] = {plans[c]->kernel, (int)recs.size(), 0, 0, 0, 1, 1};
-      task = 0; task_m = 0;
-    }
-    BatchCell bc{};
-    CellRun rr = r;
-    rr.ws = nullptr;
-    bc.args = cell_near_args(rr);
-    const size_t B = b->base[c];
-    const Layout& L = r.L;
-    const bool mixed = b->mixed;
-    bc.o_sx = B + L.scx; bc.o_sy = B + L.scy;
-    bc.o_q64 = B + L.dens_c; bc.o_q32 = mixed ? B + L.q32 : 0;
-    bc.o_tx = B + L.stx; bc.o_ty = B + L.sty; bc.o_perm = B + L.perm; bc.o_part = B + L.near_part;
-    bc.o_qsum = L.qsum ? B + L.qsum : 0;
-    bc.kernel = plans[c]->kernel; bc.n_dens = b->n_dens;
-    bc.n_tiles = (int)((r.nt + NEAR_BLOCK - 1) / NEAR_BLOCK);
-    bc.task0 = task;
-    bc.task0m = task_m;
-    bc.mutual = L.mutual;
-    if (L.mutual) {
-      const Geometry& g = plans[c]->geo;
-      MutualArgs& m = bc.margs;
-      m.n_images = g.n_images;
-      m.imx = plans[c]->d_tab + plans[c]->tab_img + 2 * g.n_images; m.imy = m.imx + g.n_images;
-      m.sigma = g.sigma; m.n = r.ns; m.chunk_len = L.mu_chunk; m.beta = plans[c]->beta;
-      bc.n_chunks = (int)((r.ns + L.mu_chunk - 1) / L.mu_chunk);
-      bc.o_qb64 = B + L.qb64; bc.o_qb32 = mixed ? B + L.qb32 : 0;
-      task += bc.n_tiles;
-      task_m += (long long)bc.n_tiles * bc.n_chunks;
-    } else {
-      task += (long long)bc.n_tiles * L.n_splits;
-    }
-    recs.push_back(bc);
-  }
-  close_group();
-  if (!recs.empty()) {
-    if (hipMalloc(&b->d_recs, recs.size() * sizeof(BatchCell)) != hipSuccess) { delete b; return PFMM_ENOMEM; }
-    if (hipMemcpy(b->d_recs, recs.data(), recs.size() * sizeof(BatchCell), hipMemcpyHostToDevice) != hipSuccess) {
-      (void)hipFree(b->d_recs); delete b; return PFMM_EHIP;
-    }
-  }
-  b->n_recs = (int)recs.size();
+  b->d_recs = nullptr;
+  int rc = batch_build(b, BATCH_SPLIT, 4);
+  if (rc) { delete b; return rc; }
   *out = b;
   return PFMM_OK;
 }
@@ -626,7 +772,7 @@ static int batch_launch(pfmm_batch_s* b, const double* src_xy, const double* den
   std::vector<CellRun> runs(b->n_cells);
   for (int c = 0; c < b->n_cells; ++c) {
     const int64_t ns = b->soff[c + 1] - b->soff[c], nt = b->toff[c + 1] - b->toff[c];
-    cell_setup(b->plans[c], ns, nt, ws + b->base[c], BATCH_SPLIT, runs[c]);
+    cell_setup(b->plans[c], ns, nt, ws + b->base[c], b->split, runs[c]);
     if (nt == 0) continue;
     cell_prep(runs[c], src_xy + b->soff[c], S, dens + b->soff[c], S,
               b->self_exclude ? nullptr : trg_xy + b->toff[c], T, st);
@@ -690,6 +836,63 @@ int pfmm_eval_batch(pfmm_batch_t b, const double* src_xy, const double* dens, co
   return hip_ok(hipGraphLaunch(b->exec, st));
 }
 
+int pfmm_batch_autotune(pfmm_batch_t b, const double* src_xy, const double* dens, const double* trg_xy,
+                        double* out_pot, double* out_grad, void* workspace, size_t ws_bytes, void* hip_stream,
+                        pfmm_tune_report_t* report) {
+  if (!b || !src_xy || !dens || (!b->self_exclude && !trg_xy) || (!out_pot && !out_grad)) return PFMM_EINVAL;
+  if (!workspace || ((uintptr_t)workspace & 255)) return PFMM_EWORKSPACE;
+  hipStream_t st = (hipStream_t)hip_stream;
+  char* ws = (char*)workspace;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return PFMM_EHIP;
+  // one warm-up and one timed eager launch sequence
+  auto timed = [&](double* ms) -> int {
+    int rc = batch_launch(b, src_xy, dens, trg_xy, out_pot, out_grad, ws, st);
+    if (rc) return rc;
+    if (hipEventRecord(e0, st) != hipSuccess) return PFMM_EHIP;
+    rc = batch_launch(b, src_xy, dens, trg_xy, out_pot, out_grad, ws, st);
+    if (rc) return rc;
+    float t = 0;
+    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&t, e0, e1) != hipSuccess)
+      return PFMM_EHIP;
+    *ms = t;
+    return PFMM_OK;
+  };
+  const int64_t split0 = b->split;
+  const int mult0 = b->grid_mult;
+  int rc = PFMM_OK, tried = 0;
+  double start_ms = 0, best_ms = 0;
+  int64_t best_split = split0;
+  int best_mult = mult0;
+  if (b->total <= ws_bytes) {
+    rc = timed(&start_ms);
+    ++tried;
+    best_ms = start_ms;
+  } else {
+    best_ms = 1e300;
+  }
+  const int64_t splits[3] = {4096, 8192, 16384};
+  const int mults[3] = {2, 4, 8};
+  for (int i = 0; i < 3 && !rc; ++i)
+    for (int j = 0; j < 3 && !rc; ++j) {
+      if (splits[i] == split0 && mults[j] == mult0) continue;
+      if ((rc = batch_build(b, splits[i], mults[j]))) break;
+      if (b->total > ws_bytes) continue;
+      double ms = 0;
+      if ((rc = timed(&ms))) break;
+      ++tried;
+      if (ms < best_ms) { best_ms = ms; best_split = splits[i]; best_mult = mults[j]; }
+    }
+  if (!rc) rc = batch_build(b, best_split, best_mult);
+  if (!rc && b->total > ws_bytes) rc = PFMM_EWORKSPACE;
+  if (!rc) rc = batch_launch(b, src_xy, dens, trg_xy, out_pot, out_grad, ws, st);
+  if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = PFMM_EHIP;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (!rc && report) { report->n_tried = tried; report->default_ms = start_ms; report->best_ms = best_ms; }
+  return rc;
+}
 void pfmm_batch_destroy(pfmm_batch_t b) {
   if (!b) return;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);

@@ -69,6 +69,8 @@ struct pfmm_plan_s {
   // NUFFT path
   int use_nufft;
   pfmm::NufftParams nu;
+  int nu_grid;                     // 0: default NUFFT grid, 1: doubled grid (set_nufft_grid)
+  int64_t tune_near;               // near-field blocks target (0: default)
   std::vector<double> gl_nodes;    // ybar_k on [-eta/2, eta/2]
   std::vector<double> gl_bary;     // barycentric weights sigma_k
   std::vector<double> nu_deconv;   // 1/phihat(m) for m = 0..M (real, even kernel)
@@ -88,6 +90,7 @@ int build_plan(int kernel, const double* e1, const double* e2, double tol,
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
 // one evaluation with the plan's current n_dens (capi.hip)
 size_t cell_workspace(pfmm_plan_s* p, int64_t ns, int64_t nt, int64_t forced_split);
+int set_nufft_grid(pfmm_plan_s* p, int grid);
 int eval_core(pfmm_plan_s* p, int64_t ns, const double* src_xy, const double* dens, int64_t nt,
               const double* trg_xy, double* out_pot, double* out_grad, void* workspace,
               size_t ws_bytes, void* hip_stream);

@@ -104,6 +104,47 @@ void ew_rule(int kernel, double beta, double d, double xi, double eta, int m0, d
 
 }  // namespace
 
+// NUFFT grid and kernel (Sec. 6.1). grid 0: the smallest power of two
+// n_f >= 2(2M+1) (oversampling s_o >= 2) with width w = ceil(log10(1/eps)) + 1;
+// grid 1: twice that grid (s_o >= 4), one point narrower. The
+// exponential-of-semicircle kernel phi(z) = exp(b(sqrt(1-z^2)-1)) takes
+// b = 0.97 pi (1 - 1/(2 s_o)) w for the nominal s_o (2.29 w, resp. 2.67 w:
+// the kernel's transform must be small beyond the alias band, which moves
+// out as s_o grows); its Fourier transform on |z| <= 1, scaled to half-width
+// s = w h/2, is computed here by Gauss-Legendre quadrature for the
+// deconvolution: Phi(alpha) = (w/2) int phi(z) cos(alpha s z) dz.
+int set_nufft_grid(pfmm_plan_s* p, int grid) {
+  const int M = p->M;
+  int w = (int)std::ceil(std::log10(1.0 / p->eps)) + 1;
+  w = std::max(4, std::min(w, 16));
+  int nf = 16;
+  while (nf < 2 * (2 * M + 1) || nf < 2 * w) nf *= 2;
+  if (grid == 1) {
+    if (2 * nf > 4096) return PFMM_EINVAL;   // the in-LDS line FFT holds 4096 points
+    nf *= 2;
+    w = std::max(4, w - 1);
+  } else if (grid != 0) {
+    return PFMM_EINVAL;
+  }
+  p->nu.w = w;
+  p->nu.nf = nf;
+  const double so = grid == 1 ? 4.0 : 2.0;
+  p->nu.es_beta = 0.97 * PI * (1 - 1 / (2 * so)) * w;
+  p->nu_grid = grid;
+  p->nu_deconv.assign(M + 1, 0.0);
+  std::vector<double> qx, qw;
+  gauss_legendre(2 * w + 40, qx, qw);
+  const double h = p->geo.d / nf, s = w * h / 2, b = p->nu.es_beta;
+  for (int m = 0; m <= M; ++m) {
+    const double al = 2 * PI * m / p->geo.d;
+    double acc = 0;
+    for (size_t i = 0; i < qx.size(); ++i)
+      acc += qw[i] * std::exp(b * (std::sqrt(1 - qx[i] * qx[i]) - 1)) * std::cos(al * s * qx[i]);
+    p->nu_deconv[m] = 1.0 / (0.5 * w * acc);
+  }
+  return PFMM_OK;
+}
+
 int build_plan(int kernel, const double* e1, const double* e2, double tol, const pfmm_opts* opts,
                pfmm_plan_s* p) {
   if (kernel < 0 || kernel > 2) return PFMM_EINVAL;
@@ -236,16 +277,7 @@ int build_plan(int kernel, const double* e1, const double* e2, double tol, const
   int mgl = o.m_gl;
   if (mgl == 0) mgl = eps >= 1e-7 ? 8 : (eps >= 1e-10 ? 12 : 16);  // rho0^-M_GL, rho0 = 3+sqrt 8
   p->nu.m_gl = mgl;
-  {
-    double lg = std::log10(1.0 / eps);
-    int w = (int)std::ceil(lg) + 1;
-    w = std::max(4, std::min(w, 16));
-    int nf = 16;
-    while (nf < 2 * (2 * M + 1) || nf < 2 * w) nf *= 2;
-    p->nu.w = w;
-    p->nu.nf = nf;
-    p->nu.es_beta = 2.30 * w;
-  }
+  set_nufft_grid(p, 0);
   std::vector<double> tx, tw;
   gauss_legendre(mgl, tx, tw);
   p->gl_nodes.resize(mgl);
@@ -257,20 +289,7 @@ int build_plan(int kernel, const double* e1, const double* e2, double tol, const
       if (j != k) s *= (tx[k] - tx[j]);
     p->gl_bary[k] = 1.0 / s;
   }
-  // Fourier transform of the spreading kernel phi(z) = exp(b(sqrt(1-z^2)-1))
-  // on |z| <= 1, scaled to half-width s = w h/2: Phi(alpha) = (w/2) int phi(z) cos(alpha s z) dz
-  p->nu_deconv.assign(M + 1, 0.0);
-  {
-    std::vector<double> qx, qw;
-    gauss_legendre(2 * p->nu.w + 40, qx, qw);
-    const double h = d / p->nu.nf, s = p->nu.w * h / 2, b = p->nu.es_beta;
-    for (int m = 0; m <= M; ++m) {
-      double al = 2 * PI * m / d, acc = 0;
-      for (size_t i = 0; i < qx.size(); ++i)
-        acc += qw[i] * std::exp(b * (std::sqrt(1 - qx[i] * qx[i]) - 1)) * std::cos(al * s * qx[i]);
-      p->nu_deconv[m] = 1.0 / (0.5 * p->nu.w * acc);
-    }
-  }
+
   p->dev_id = -1;
   p->d_tab = nullptr;
   p->tab_doubles = 0;

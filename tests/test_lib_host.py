@@ -150,3 +150,23 @@ def test_eval_without_workspace_is_rejected_before_any_launch(P):
     assert _lib.ERRORS[rc] == "PFMM_EWORKSPACE"
     rc = lib.pfmm_eval(plan.handle, -1, dummy, dummy, 10, dummy, dummy, dummy, None, 0, None)
     assert _lib.ERRORS[rc] == "PFMM_EINVAL"
+
+
+def test_tuning_get_set_and_nufft_grid(P):
+    plan = P.Plan("laplace", (100.0, 0.0), (0.0, 1.0), 1e-6, far_mode="nufft")
+    nf0, w0 = plan.info["nufft_nf"], plan.info["nufft_w"]
+    assert plan.tuning == {"near_blocks": 0, "nufft_grid": 0}
+    assert nf0 >= 2 * (2 * plan.info["n_modes"] + 1) and nf0 & (nf0 - 1) == 0
+    plan.set_tuning(near_blocks=4096, nufft_grid=1)
+    assert plan.tuning == {"near_blocks": 4096, "nufft_grid": 1}
+    assert plan.info["nufft_nf"] == 2 * nf0 and plan.info["nufft_w"] == max(4, w0 - 1)
+    plan.set_tuning(nufft_grid=0)
+    assert plan.info["nufft_nf"] == nf0 and plan.info["nufft_w"] == w0
+    # a doubled grid beyond the 4096-point line FFT is refused and nothing changes
+    big = P.Plan("laplace", (200.0, 0.0), (0.0, 1.0), 1e-6, far_mode="nufft")
+    assert big.info["nufft_nf"] == 4096
+    with pytest.raises(P.PfmmError):
+        big.set_tuning(nufft_grid=1)
+    assert big.tuning["nufft_grid"] == 0 and big.info["nufft_nf"] <= 4096
+    with pytest.raises(P.PfmmError):
+        plan.set_tuning(near_blocks=-1)
