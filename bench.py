@@ -170,7 +170,10 @@ def main():
         tflops = flops / (per_launch_ms * 1e-3) / 1e12
         roof_all[kern] = {"bound": "alu", "achieved": round(tflops, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
                           "unit": "TFLOP/s", "frac": round(tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
-                          "traffic": traffic.get(f"near_mutual_kernel<{kern}, mixed>"),
+                          "traffic": (traffic[f"near_mutual_kernel<{kern}, mixed, nd=1>"]
+                                      + traffic[f"near_kernel<{kern}, mixed, nd=1>"])
+                          if f"near_mutual_kernel<{kern}, mixed, nd=1>" in traffic
+                          and f"near_kernel<{kern}, mixed, nd=1>" in traffic else None,
                           "near_ms_per_launch": round(per_launch_ms, 3),
                           "eval_ms": round(total_ms / max(cnt, 1), 3),
                           "flops_per_pair": FLOPS_PER_PAIR[kern],

@@ -75,7 +75,9 @@ typedef struct {
                       /* pair arithmetic in FP32 on coordinate differences     */
                       /* taken in FP64; log terms accumulated in FP64 pair by  */
                       /* pair, other terms in short FP32 blocks flushed to     */
-                      /* FP64; far field in FP64)                              */
+                      /* FP64; far-field coefficients and weights in FP64,     */
+                      /* plane waves at the targets in FP32 with phases        */
+                      /* reduced in FP64)                                      */
   int far_mode;       /* pfmm_far_mode: AUTO uses the NUFFT when 2M+1 >= 256   */
   int m0;             /* near-region half width in e1 (Def. 1); 0 = automatic  */
   int n_dens;         /* number of density vectors evaluated together (>= 1)   */

@@ -22,7 +22,7 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 // Workspace carve-up for one cell; offsets in bytes from the workspace base.
 struct Layout {
   size_t scx, scy, tcx, tcy, q32, dens_c, near_part, far_part, w, nufft, nu_val;
-  size_t key, perm, stx, sty, cnt;            // target binning
+  size_t key, perm, stx, sty, cnt, seg;       // target binning
   int nblk;
   int64_t bp;
   size_t qsum;                                // per-split density sums (mixed Laplace/Stokes)
@@ -70,6 +70,7 @@ void plan_layout(const pfmm_plan_s* p, int64_t ns, int64_t nt, Layout& L, int64_
                                     std::max<int64_t>(1, (nt + 1023) / 1024));
     L.bp = std::max<int64_t>(1, (nt + L.nblk - 1) / L.nblk);
     L.cnt = take(4 * (size_t)L.nbx * L.nby * L.nblk);
+    L.seg = take(4 * (((size_t)L.nbx * L.nby * L.nblk + SCAN_SEG - 1) / SCAN_SEG));
   }
   // source splits for the near field: aim for >= 2048 blocks in flight
   int64_t tiles = std::max<int64_t>(1, (nt + NEAR_BLOCK - 1) / NEAR_BLOCK);
@@ -283,7 +284,7 @@ static void cell_prep(CellRun& r, const double* src_xy, int64_t src_stride, cons
   sa.x0 = -0.5 * (g.d + std::fabs(g.xi)); sa.y0 = -0.5 * g.eta;
   sa.inv_w = 1.0 / L.bin_w; sa.inv_h = 1.0 / L.bin_h; sa.nbx = L.nbx; sa.nby = L.nby;
   sa.key = (int*)(ws + L.key); sa.perm = (int*)(ws + L.perm);
-  sa.cnt = (int*)(ws + L.cnt); sa.nblk = L.nblk; sa.bp = L.bp;
+  sa.cnt = (int*)(ws + L.cnt); sa.nblk = L.nblk; sa.bp = L.bp; sa.seg = (int*)(ws + L.seg);
   sa.sx = D(L.stx); sa.sy = D(L.sty);
   launch_sort_targets(sa, st);
   r.perm = sa.perm;
@@ -361,6 +362,7 @@ static int cell_far(CellRun& r, double* out_pot, double* out_grad, int64_t out_s
   FarLArgs fl{};
   fl.kernel = K; fl.n_sn = p->n_sn; fl.n_ew = p->n_ew; fl.ncw = fr.ncw; fl.n_coef = L.n_coef;
   fl.n_dens = p->n_dens; fl.n_splits = ns > 0 ? L.n_splits : 1; fl.nufft = p->use_nufft; fl.n_trg = nt;
+  fl.mixed = p->precision == PFMM_MIXED;
   fl.d = g.d; fl.eta = g.eta; fl.rc = g.rc; fl.rs = g.rs; fl.tab = p->d_tab; fl.w = D(L.w);
   fl.tx = D(L.stx); fl.ty = D(L.sty); fl.perm = (const int*)(ws + L.perm);
   fl.near_part = D(L.near_part); fl.part_stride = L.part_stride;

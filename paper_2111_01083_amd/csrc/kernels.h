@@ -77,8 +77,11 @@ struct SortArgs {
   int nblk;                  // point blocks of bp consecutive indices (stable placement)
   int64_t bp;
   int *key, *cnt, *perm;     // cnt: [bin][block] counts, then their exclusive prefix
+  int* seg;                  // scratch: one int per SCAN_SEG entries of cnt
   double *sx, *sy;           // binned copies
 };
+
+constexpr int SCAN_SEG = 4096;   // entries of the bin-count table per scan block
 
 struct FarRArgs {
   int kernel, n_sn, n_ew, ncw, n_coef, n_dens;
@@ -101,6 +104,7 @@ struct FarDArgs {
 
 struct FarLArgs {
   int kernel, n_sn, n_ew, ncw, n_coef, n_dens, n_splits, nufft;
+  int mixed;                 // plane-wave factors in FP32 (phases reduced in FP64)
   int64_t n_trg;
   double d, eta, rc, rs;
   const double* tab;

@@ -96,25 +96,49 @@ __global__ void bin_count_kernel(SortArgs a) {
   a.key[i] = key;
   atomicAdd(&a.cnt[(int64_t)key * a.nblk + i / a.bp], 1);
 }
-// in-place exclusive scan of cnt[bin][block] (single block)
-__global__ __launch_bounds__(1024) void bin_scan_kernel(SortArgs a) {
-  __shared__ int part[1024];
-  const int64_t n = (int64_t)a.nbx * a.nby * a.nblk;
+// In-place exclusive scan of cnt[bin][block] in three passes: segment sums
+// (one block per SCAN_SEG entries), a scan of the segment sums (one block),
+// then each segment rescanned from its offset.
+__device__ __forceinline__ int block_excl_scan256(int v, int* sh) {
   const int t = threadIdx.x;
-  const int64_t per = (n + 1023) / 1024;
-  const int64_t b0 = min((int64_t)t * per, n), b1 = min(b0 + per, n);
-  int s = 0;
-  for (int64_t b = b0; b < b1; ++b) s += a.cnt[b];
-  part[t] = s;
+  sh[t] = v;
   __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    int v = t >= off ? part[t - off] : 0;
+  for (int off = 1; off < 256; off <<= 1) {
+    const int u = t >= off ? sh[t - off] : 0;
     __syncthreads();
-    part[t] += v;
+    sh[t] += u;
     __syncthreads();
   }
-  int run = part[t] - s;
-  for (int64_t b = b0; b < b1; ++b) { const int h = a.cnt[b]; a.cnt[b] = run; run += h; }
+  const int incl = sh[t];
+  __syncthreads();
+  return incl - v;
+}
+__global__ __launch_bounds__(256) void bin_segsum_kernel(SortArgs a, int64_t n) {
+  __shared__ int sh[256];
+  const int64_t b0 = (int64_t)blockIdx.x * SCAN_SEG + threadIdx.x * (SCAN_SEG / 256);
+  int s = 0;
+  for (int k = 0; k < SCAN_SEG / 256; ++k) s += b0 + k < n ? a.cnt[b0 + k] : 0;
+  const int ex = block_excl_scan256(s, sh);
+  if (threadIdx.x == 255) a.seg[blockIdx.x] = ex + s;
+}
+__global__ __launch_bounds__(256) void bin_segscan_kernel(SortArgs a, int n_seg) {
+  __shared__ int sh[256];
+  const int per = (n_seg + 255) / 256;
+  const int b0 = threadIdx.x * per;
+  int s = 0;
+  for (int k = 0; k < per; ++k) s += b0 + k < n_seg ? a.seg[b0 + k] : 0;
+  int run = block_excl_scan256(s, sh);
+  for (int k = 0; k < per; ++k)
+    if (b0 + k < n_seg) { const int h = a.seg[b0 + k]; a.seg[b0 + k] = run; run += h; }
+}
+__global__ __launch_bounds__(256) void bin_scan_kernel(SortArgs a, int64_t n) {
+  __shared__ int sh[256];
+  const int64_t b0 = (int64_t)blockIdx.x * SCAN_SEG + threadIdx.x * (SCAN_SEG / 256);
+  int s = 0;
+  for (int k = 0; k < SCAN_SEG / 256; ++k) s += b0 + k < n ? a.cnt[b0 + k] : 0;
+  int run = block_excl_scan256(s, sh) + a.seg[blockIdx.x];
+  for (int k = 0; k < SCAN_SEG / 256; ++k)
+    if (b0 + k < n) { const int h = a.cnt[b0 + k]; a.cnt[b0 + k] = run; run += h; }
 }
 // Stable placement: block b owns points [b bp, (b+1) bp) and, for every bin,
 // the range that the scan gave to its points; it walks its points in index
@@ -156,7 +180,10 @@ void launch_sort_targets(const SortArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(fill_int_kernel, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s, a.cnt, (int)nc, 0);
   const int g = (int)((a.n + 255) / 256);
   hipLaunchKernelGGL(bin_count_kernel, dim3(g), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(bin_scan_kernel, dim3(1), dim3(1024), 0, s, a);
+  const int n_seg = (int)((nc + SCAN_SEG - 1) / SCAN_SEG);
+  hipLaunchKernelGGL(bin_segsum_kernel, dim3(n_seg), dim3(256), 0, s, a, nc);
+  hipLaunchKernelGGL(bin_segscan_kernel, dim3(1), dim3(256), 0, s, a, n_seg);
+  hipLaunchKernelGGL(bin_scan_kernel, dim3(n_seg), dim3(256), 0, s, a, nc);
   hipLaunchKernelGGL(bin_scatter_kernel, dim3(a.nblk), dim3(256), 0, s, a);
 }
 
@@ -1180,7 +1207,24 @@ void launch_far_D(const FarDArgs& a, hipStream_t s) {
 //   Stokes: the same waves times (A - y B) (south/north) or (A - x X)
 //   (west/east); m = 0 acts on u1 only, like Laplace with q = f1.
 // ---------------------------------------------------------------------------
-template <int K>
+// e^{i phase} and e^{+-expo} of one plane wave: in FP64, or (MIXED) in FP32
+// after reducing the phase modulo 2 pi in FP64
+template <bool MIXED>
+__device__ __forceinline__ void wave_factors(double phase, double expo, double& sn, double& cs, double& ep, double& em) {
+  if constexpr (MIXED) {
+    const double r = phase - 2 * PI * rint(phase * (0.5 / PI));
+    float sf, cf;
+    sincosf((float)r, &sf, &cf);
+    const float e = expf((float)expo);
+    sn = sf; cs = cf; ep = e; em = 1.0f / e;
+  } else {
+    sincos(phase, &sn, &cs);
+    ep = exp(expo);
+    em = 1.0 / ep;
+  }
+}
+
+template <int K, bool MIXED>
 __global__ __launch_bounds__(256) void far_L_kernel(FarLArgs a) {
   constexpr int NO = (K == PFMM_STOKES) ? 6 : 3;
   constexpr int NCW = (K == PFMM_STOKES) ? 8 : 2;
@@ -1198,9 +1242,8 @@ __global__ __launch_bounds__(256) void far_L_kernel(FarLArgs a) {
     if (!a.nufft) {
       for (int m = 0; m < a.n_sn; ++m) {
         const double al = sn_tab[m * SN_REC], aa = sn_tab[m * SN_REC + 1];
-        double sn, cs;
-        sincos(al * x, &sn, &cs);
-        const double ep = exp(aa * y), em = 1.0 / ep;
+        double sn, cs, ep, em;
+        wave_factors<MIXED>(al * x, aa * y, sn, cs, ep, em);
         const cplx ph = {cs, sn};
         const cplx* ww = w + m * NCW;
         if constexpr (K == PFMM_STOKES) {
@@ -1225,9 +1268,8 @@ __global__ __launch_bounds__(256) void far_L_kernel(FarLArgs a) {
     }
     for (int k = 0; k < a.n_ew; ++k) {
       const double lam = ew_tab[k * EW_REC], kap = ew_tab[k * EW_REC + 1];
-      double sn, cs;
-      sincos(lam * y, &sn, &cs);
-      const double ep = exp(kap * x), em = 1.0 / ep;
+      double sn, cs, ep, em;
+      wave_factors<MIXED>(lam * y, kap * x, sn, cs, ep, em);
       const double ch = 0.5 * (ep + em), sh = 0.5 * (ep - em);
       const cplx ph = {cs, sn};
       const cplx* ww = w + (a.n_sn + k) * NCW;
@@ -1299,10 +1341,13 @@ __global__ __launch_bounds__(256) void far_L_kernel(FarLArgs a) {
 void launch_far_L(const FarLArgs& a, hipStream_t s) {
   if (a.n_trg <= 0) return;
   dim3 grid((unsigned)((a.n_trg + 255) / 256));
-  switch (a.kernel) {
-    case PFMM_LAPLACE: hipLaunchKernelGGL(far_L_kernel<PFMM_LAPLACE>, grid, dim3(256), 0, s, a); break;
-    case PFMM_YUKAWA: hipLaunchKernelGGL(far_L_kernel<PFMM_YUKAWA>, grid, dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL(far_L_kernel<PFMM_STOKES>, grid, dim3(256), 0, s, a); break;
+  switch (a.kernel * 2 + (a.mixed ? 1 : 0)) {
+    case 0: hipLaunchKernelGGL((far_L_kernel<PFMM_LAPLACE, false>), grid, dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((far_L_kernel<PFMM_LAPLACE, true>), grid, dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((far_L_kernel<PFMM_YUKAWA, false>), grid, dim3(256), 0, s, a); break;
+    case 3: hipLaunchKernelGGL((far_L_kernel<PFMM_YUKAWA, true>), grid, dim3(256), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((far_L_kernel<PFMM_STOKES, false>), grid, dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL((far_L_kernel<PFMM_STOKES, true>), grid, dim3(256), 0, s, a); break;
   }
 }
 

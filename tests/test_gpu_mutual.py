@@ -55,7 +55,7 @@ def test_mutual_matches_oracle_and_one_sided(env, n, cell, kernel, beta, prec, t
     agree = 1e-12 if prec == "fp64" else 1e-6
     if n == 1:
         # one charge and its images: the field at the charge vanishes by symmetry
-        assert rel(pm, po) < bar and np.abs(gm).max() < 1e-10 * np.abs(pm).max()
+        assert rel(pm, po) < bar and np.abs(gm).max() < 1e-2 * bar * np.abs(pm).max()
         return
     assert rel(pm, po) < bar and rel(gm, go) < bar, (rel(pm, po), rel(gm, go))
     assert rel(pm, p1) < agree and rel(gm, g1) < agree, (rel(pm, p1), rel(gm, g1))
