@@ -25,7 +25,7 @@ struct Layout {
   size_t key, perm, stx, sty, cnt, seg;       // target binning
   int nblk;
   int64_t bp;
-  size_t qsum;                                // per-split density sums (mixed Laplace/Stokes)
+  size_t qsum, qpart;                         // per-split density sums (mixed Laplace/Stokes), scratch
   size_t qb64, qb32;                          // binned densities (symmetric near field)
   int mutual;                                 // symmetric near field in this evaluation
   int64_t mu_chunk;                           // its source chunk length
@@ -91,6 +91,7 @@ void plan_layout(const pfmm_plan_s* p, int64_t ns, int64_t nt, Layout& L, int64_
   L.n_splits = (int)std::max<int64_t>(1, (ns + per - 1) / per);
   L.part_stride = (size_t)p->n_dens * no * nt;
   L.qsum = (mixed && p->kernel != PFMM_YUKAWA) ? take(8 * (size_t)L.n_splits * p->n_dens * nc) : 0;
+  L.qpart = L.qsum ? take(8 * (size_t)L.n_splits * QSUM_PARTS * p->n_dens * nc) : 0;
   L.near_part = take(8 * L.part_stride * L.n_splits);
   L.qb64 = L.qb32 = 0;
   L.mu_chunk = 0;
@@ -106,8 +107,9 @@ void plan_layout(const pfmm_plan_s* p, int64_t ns, int64_t nt, Layout& L, int64_
   L.n_coef = (p->n_sn + p->n_ew) * coef_per_wave(p->kernel) + 1;
   {
     // far_R: enough source chunks for about 1024 blocks (each block streams
-    // its chunk once for up to FAR_R_BLOCK modes/nodes)
-    const int64_t wblocks = (p->n_sn + p->n_ew + 1 + FAR_R_BLOCK - 1) / FAR_R_BLOCK;
+    // its chunk once for all modes/nodes of its lanes)
+    const int n_w1 = (p->use_nufft ? 0 : p->n_sn) + p->n_ew + 1, lanes = far_r_lanes(n_w1);
+    const int64_t wblocks = (n_w1 + lanes - 1) / lanes;
     const int64_t want = std::max<int64_t>(1, (1024 + wblocks * p->n_dens - 1) / (wblocks * p->n_dens));
     int64_t clen = std::max<int64_t>(256, (ns + want - 1) / want);
     clen = (clen + 255) / 256 * 256;
@@ -276,7 +278,7 @@ static void cell_prep(CellRun& r, const double* src_xy, int64_t src_stride, cons
   if (L.qsum) {
     QsumArgs qa{};
     qa.n_src = r.ns; qa.split_len = L.split_len; qa.ncomp = p->n_dens * (p->kernel == PFMM_STOKES ? 2 : 1);
-    qa.q64 = D(L.dens_c); qa.qsum = D(L.qsum);
+    qa.q64 = D(L.dens_c); qa.qsum = D(L.qsum); qa.qpart = D(L.qpart);
     launch_qsum(qa, L.n_splits, st);
   }
   SortArgs sa{};
@@ -333,6 +335,7 @@ static int cell_far(CellRun& r, double* out_pot, double* out_grad, int64_t out_s
   fr.n_coef = L.n_coef; fr.n_dens = p->n_dens; fr.n_src = ns; fr.tab = p->d_tab;
   fr.sx = D(L.scx); fr.sy = D(L.scy); fr.dens = dens_c; fr.part = D(L.far_part);
   fr.skip_sn = p->use_nufft; fr.chunk_len = L.chunk_len;
+  fr.lanes = far_r_lanes((p->use_nufft ? 0 : p->n_sn) + p->n_ew + 1);
   const double* csn = nullptr;
   if (p->use_nufft) {
     int rc = nufft_R(p, ns, D(L.scx), D(L.scy), dens_c, ws + L.nufft, st, &csn);

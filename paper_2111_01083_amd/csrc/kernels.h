@@ -21,7 +21,15 @@ constexpr int MU_BLOCK = PFMM_MU_BLOCK;   // points per block of the symmetric n
 #endif
 constexpr int NEAR_FLUSH = PFMM_NEAR_FLUSH;  // FP32 partial-sum length before an FP64 flush (mixed)
 constexpr double R2MIN_F32 = 8.673617379884035e-19;   // 2^-60: r^2 clamp of the mixed Laplace/Stokes pair
-constexpr int FAR_R_BLOCK = 128;  // threads (= modes/nodes) per far_R block
+constexpr int FAR_R_BLOCK = 256;  // threads per far_R block: mode lanes x source slices
+// mode lanes of a far_R block for n_w1 modes/nodes (incl. the moment slot):
+// the smallest power of two >= n_w1 in [32, 256]; the other 256/lanes
+// thread slices split the block's sources
+inline int far_r_lanes(int n_w1) {
+  int l = 32;
+  while (l < n_w1 && l < FAR_R_BLOCK) l *= 2;
+  return l;
+}
 
 struct PrepArgs {
   int64_t n, ystride;        // y coordinates at xy[ystride + i]
@@ -67,7 +75,9 @@ struct QsumArgs {
   int ncomp;                             // n_dens * nc
   const double* q64;                     // [ncomp][n_src]
   double* qsum;                          // [split][ncomp]
+  double* qpart;                         // scratch [split][QSUM_PARTS][ncomp]
 };
+constexpr int QSUM_PARTS = 64;           // blocks per split in the first pass
 
 struct SortArgs {
   int64_t n;
@@ -85,8 +95,9 @@ constexpr int SCAN_SEG = 4096;   // entries of the bin-count table per scan bloc
 
 struct FarRArgs {
   int kernel, n_sn, n_ew, ncw, n_coef, n_dens;
-  int skip_sn;               // south/north slots come from the NUFFT path (write zeros)
+  int skip_sn;               // south/north slots come from the NUFFT path (not computed here)
   int64_t n_src, chunk_len;  // sources per block (grid y = source chunks)
+  int lanes;                 // far_r_lanes(n_sn + n_ew + 1)
   const double* tab;         // sn records | ew records
   const double *sx, *sy;     // canonical sources
   const double* dens;        // canonical densities [n_dens][nc][n_src]

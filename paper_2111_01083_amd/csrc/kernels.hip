@@ -827,26 +827,41 @@ void launch_gather_dens(const double* src, const int* perm, int64_t n, int ncomp
                      dst64, dst32);
 }
 
-// per-split sums of the FP64 densities, used to remove the log2 shift
-__global__ __launch_bounds__(256) void qsum_kernel(QsumArgs a) {
+// per-split sums of the FP64 densities, used to remove the log2 shift.
+// Two passes in a fixed order: QSUM_PARTS blocks per split sum their share
+// of the split, then one thread per (split, component) adds the parts.
+__global__ __launch_bounds__(256) void qsum_part_kernel(QsumArgs a) {
   __shared__ double red[256];
-  const int64_t s0 = (int64_t)blockIdx.x * a.split_len;
+  const int split = blockIdx.x / QSUM_PARTS, part = blockIdx.x % QSUM_PARTS;
+  const int64_t s0 = (int64_t)split * a.split_len;
   const int64_t s1 = min(s0 + a.split_len, a.n_src);
+  const int64_t per = (s1 - s0 + QSUM_PARTS - 1) / QSUM_PARTS;
+  const int64_t p0 = min(s0 + part * per, s1), p1 = min(p0 + per, s1);
   const int comp = blockIdx.y;
   double s = 0.0;
-  for (int64_t j = s0 + threadIdx.x; j < s1; j += 256) s += a.q64[(size_t)comp * a.n_src + j];
+  for (int64_t j = p0 + threadIdx.x; j < p1; j += 256) s += a.q64[(size_t)comp * a.n_src + j];
   red[threadIdx.x] = s;
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
     if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
     __syncthreads();
   }
-  if (threadIdx.x == 0) a.qsum[(size_t)blockIdx.x * a.ncomp + comp] = red[0];
+  if (threadIdx.x == 0) a.qpart[((size_t)split * QSUM_PARTS + part) * a.ncomp + comp] = red[0];
+}
+__global__ void qsum_final_kernel(QsumArgs a, int n_splits) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_splits * a.ncomp) return;
+  const int split = t / a.ncomp, comp = t % a.ncomp;
+  double s = 0.0;
+  for (int p = 0; p < QSUM_PARTS; ++p) s += a.qpart[((size_t)split * QSUM_PARTS + p) * a.ncomp + comp];
+  a.qsum[(size_t)split * a.ncomp + comp] = s;
 }
 
 void launch_qsum(const QsumArgs& a, int n_splits, hipStream_t s) {
   if (a.n_src <= 0 || n_splits <= 0) return;
-  hipLaunchKernelGGL(qsum_kernel, dim3(n_splits, a.ncomp), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(qsum_part_kernel, dim3(n_splits * QSUM_PARTS, a.ncomp), dim3(256), 0, s, a);
+  const int n = n_splits * a.ncomp;
+  hipLaunchKernelGGL(qsum_final_kernel, dim3((n + 63) / 64), dim3(64), 0, s, a, n_splits);
 }
 
 void launch_near_batch(int kernel, bool mixed, int phase, const BatchNearArgs& b, int grid, hipStream_t s) {
@@ -938,15 +953,26 @@ __device__ __forceinline__ cplx cexpm1(double a, double b) {
   return {expm1(a) * c - 2 * sh * sh, exp(a) * s};
 }
 
+// Block (x, y, z) = (mode group, source chunk, density): thread (slice, lane)
+// owns mode/node x * lanes + lane and every slices-th source of each LDS
+// tile; the slices' partial sums are added in a fixed order at the end.
 template <int K>
 __global__ __launch_bounds__(FAR_R_BLOCK) void far_R_kernel(FarRArgs a) {
   constexpr int NC = (K == PFMM_STOKES) ? 2 : 1;
   constexpr int NCW = (K == PFMM_STOKES) ? 8 : 2;
-  __shared__ double s_x[FAR_R_TILE], s_y[FAR_R_TILE], s_q[NC][FAR_R_TILE];
+  constexpr int TILE_D = (2 + NC) * FAR_R_TILE, RED_D = FAR_R_BLOCK * NCW * 2;
+  __shared__ double smem[TILE_D > RED_D ? TILE_D : RED_D];
+  double* s_x = smem;
+  double* s_y = smem + FAR_R_TILE;
+  double* s_qb = smem + 2 * FAR_R_TILE;   // [NC][FAR_R_TILE]
   const int v = blockIdx.z;
   const int64_t j0 = (int64_t)blockIdx.y * a.chunk_len;
   const int64_t j1 = min(j0 + a.chunk_len, a.n_src);
-  const int w = blockIdx.x * FAR_R_BLOCK + threadIdx.x;
+  const int lanes = a.lanes, n_slices = FAR_R_BLOCK / lanes;
+  const int lane = threadIdx.x % lanes, slice = threadIdx.x / lanes;
+  // with skip_sn the lanes start at the first west/east node (the NUFFT path
+  // supplies the south/north coefficients and far_D ignores those slots here)
+  const int w = (a.skip_sn ? a.n_sn : 0) + blockIdx.x * lanes + lane;
   const int n_w = a.n_sn + a.n_ew;
   const bool in_sn = w < a.n_sn;
   const bool is_sn = in_sn && !a.skip_sn, is_ew = !in_sn && w < n_w, is_mom = w == n_w;
@@ -963,12 +989,12 @@ __global__ __launch_bounds__(FAR_R_BLOCK) void far_R_kernel(FarRArgs a) {
     for (int t = threadIdx.x; t < nt; t += FAR_R_BLOCK) {
       s_x[t] = a.sx[base + t]; s_y[t] = a.sy[base + t];
 #pragma unroll
-      for (int c = 0; c < NC; ++c) s_q[c][t] = dens[(size_t)c * a.n_src + base + t];
+      for (int c = 0; c < NC; ++c) s_qb[c * FAR_R_TILE + t] = dens[(size_t)c * a.n_src + base + t];
     }
     __syncthreads();
     if (is_sn) {
       const double al = par0, aa = par1;
-      for (int t = 0; t < nt; ++t) {
+      for (int t = slice; t < nt; t += n_slices) {
         const double x = s_x[t], y = s_y[t];
         double sn, cs;
         sincos(al * x, &sn, &cs);
@@ -978,41 +1004,41 @@ __global__ __launch_bounds__(FAR_R_BLOCK) void far_R_kernel(FarRArgs a) {
         if constexpr (K == PFMM_STOKES) {
 #pragma unroll
           for (int c = 0; c < 2; ++c) {
-            const double f = s_q[c][t];
+            const double f = s_qb[c * FAR_R_TILE + t];
             acc[c] = cadd(acc[c], cscale(ps, f));
             acc[2 + c] = cadd(acc[2 + c], cscale(ps, f * y));
             acc[4 + c] = cadd(acc[4 + c], cscale(pn, f));
             acc[6 + c] = cadd(acc[6 + c], cscale(pn, f * y));
           }
         } else {
-          const double q = s_q[0][t];
+          const double q = s_qb[t];
           acc[0] = cadd(acc[0], cscale(ps, q));
           acc[1] = cadd(acc[1], cscale(pn, q));
         }
       }
     } else if (is_ew) {
       const double lam = par0, kap = par1;
-      for (int t = 0; t < nt; ++t) {
+      for (int t = slice; t < nt; t += n_slices) {
         const double x = s_x[t], y = s_y[t];
         if constexpr (K == PFMM_YUKAWA) {
           double sn, cs;
           sincos(lam * y, &sn, &cs);
           const double ep = exp(kap * x), em = 1.0 / ep;
-          const double q = s_q[0][t];
+          const double q = s_qb[t];
           acc[0] = cadd(acc[0], cplx{q * ep * cs, -q * ep * sn});
           acc[1] = cadd(acc[1], cplx{q * em * cs, -q * em * sn});
         } else {
           const cplx wm = cexpm1(lam * x, -lam * y);    // e^{lam(x - i y)} - 1
           const cplx emm = cexpm1(-lam * x, -lam * y);  // e^{-lam(x + i y)} - 1
           if constexpr (K == PFMM_LAPLACE) {
-            const double q = s_q[0][t];
+            const double q = s_qb[t];
             acc[0] = cadd(acc[0], cscale(wm, q));
             acc[1] = cadd(acc[1], cscale(emm, q));
           } else {
             const cplx wf = {wm.r + 1.0, wm.i}, ef = {emm.r + 1.0, emm.i};
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
-              const double f = s_q[c][t];
+              const double f = s_qb[c * FAR_R_TILE + t];
               acc[c] = cadd(acc[c], cscale(wm, f));
               acc[2 + c] = cadd(acc[2 + c], cscale(wf, f * x));
               acc[4 + c] = cadd(acc[4 + c], cscale(emm, f));
@@ -1022,12 +1048,31 @@ __global__ __launch_bounds__(FAR_R_BLOCK) void far_R_kernel(FarRArgs a) {
         }
       }
     } else if (is_mom && K != PFMM_YUKAWA) {
-      for (int t = 0; t < nt; ++t) {
-        const double y = s_y[t], q = s_q[0][t];
+      for (int t = slice; t < nt; t += n_slices) {
+        const double y = s_y[t], q = s_qb[t];
         acc[0].r += q * y;
         acc[0].i += q * y * y;
       }
     }
+  }
+  // slice partials -> LDS (reusing the tile), summed by slice 0 in order
+  __syncthreads();
+  double* red = smem;   // [slice][lane][NCW] complex
+#pragma unroll
+  for (int c = 0; c < NCW; ++c) {
+    red[((size_t)(slice * lanes + lane) * NCW + c) * 2] = acc[c].r;
+    red[((size_t)(slice * lanes + lane) * NCW + c) * 2 + 1] = acc[c].i;
+  }
+  __syncthreads();
+  if (slice != 0) return;
+#pragma unroll
+  for (int c = 0; c < NCW; ++c) {
+    double sr = 0, si = 0;
+    for (int sl = 0; sl < n_slices; ++sl) {
+      sr += red[((size_t)(sl * lanes + lane) * NCW + c) * 2];
+      si += red[((size_t)(sl * lanes + lane) * NCW + c) * 2 + 1];
+    }
+    acc[c] = {sr, si};
   }
   double* out = a.part + ((size_t)blockIdx.y * a.n_dens + v) * a.n_coef * 2;
   if (in_sn || is_ew) {
@@ -1066,8 +1111,8 @@ void launch_far_sum(double* part, int n_chunks, int64_t n_cplx, hipStream_t s) {
 }
 
 void launch_far_R(const FarRArgs& a, int n_chunks, hipStream_t s) {
-  int n_w = a.n_sn + a.n_ew + 1;
-  dim3 grid((unsigned)((n_w + FAR_R_BLOCK - 1) / FAR_R_BLOCK), (unsigned)n_chunks, (unsigned)a.n_dens);
+  const int n_w = a.n_sn + a.n_ew + 1 - (a.skip_sn ? a.n_sn : 0);
+  dim3 grid((unsigned)((n_w + a.lanes - 1) / a.lanes), (unsigned)n_chunks, (unsigned)a.n_dens);
   switch (a.kernel) {
     case PFMM_LAPLACE: hipLaunchKernelGGL(far_R_kernel<PFMM_LAPLACE>, grid, dim3(FAR_R_BLOCK), 0, s, a); break;
     case PFMM_YUKAWA: hipLaunchKernelGGL(far_R_kernel<PFMM_YUKAWA>, grid, dim3(FAR_R_BLOCK), 0, s, a); break;
@@ -1110,11 +1155,12 @@ __global__ void far_D_kernel(FarDArgs a) {
   cplx c[8];
   for (int k = 0; k < nsum; ++k) {
     double sr = 0, si = 0;
-    for (int ch = 0; ch < a.n_chunks; ++ch) {
+    const bool sn_extra = a.extra && w < a.n_sn;     // south/north from the NUFFT path only
+    for (int ch = 0; ch < (sn_extra ? 0 : a.n_chunks); ++ch) {
       const double* p = a.part + (((size_t)ch * a.n_dens + v) * a.n_coef + c0 + k) * 2;
       sr += p[0]; si += p[1];
     }
-    if (a.extra && w < a.n_sn) {
+    if (sn_extra) {
       const double* e = a.extra + (((size_t)v * a.n_sn + w) * ncw + k) * 2;
       sr += e[0]; si += e[1];
     }

@@ -81,23 +81,33 @@ __device__ __forceinline__ double es_kernel(double z, double b) {
   return t > 0.0 ? exp(b * (sqrt(t) - 1.0)) : 0.0;
 }
 
-// barycentric weights gamma(y, k) for all lines (second form, eq. baryweights)
+// barycentric weights gamma(y, k) for all lines (second form, eq. baryweights);
+// MG > 0: n == MG lines known at compile time (the arrays stay in registers)
+template <int MG>
 __device__ __forceinline__ void bary_weights(double y, const double* ybar, const double* sig, int n, double* g) {
+  constexpr int NA = MG > 0 ? MG : 32;
+  const int m = MG > 0 ? MG : n;
   int hit = -1;
   double s = 0.0;
-  for (int k = 0; k < n; ++k) {
-    const double dy = y - ybar[k];
-    if (dy == 0.0) hit = k;
-    g[k] = sig[k] / (dy == 0.0 ? 1.0 : dy);
-    s += g[k];
+#pragma unroll
+  for (int k = 0; k < NA; ++k) {
+    if (k < m) {
+      const double dy = y - ybar[k];
+      if (dy == 0.0) hit = k;
+      g[k] = sig[k] / (dy == 0.0 ? 1.0 : dy);
+      s += g[k];
+    }
   }
-  if (hit >= 0) {
-    for (int k = 0; k < n; ++k) g[k] = (k == hit) ? 1.0 : 0.0;
-  } else {
-    const double is = 1.0 / s;
-    for (int k = 0; k < n; ++k) g[k] *= is;
-  }
+  const double is = 1.0 / s;
+#pragma unroll
+  for (int k = 0; k < NA; ++k)
+    if (k < m) g[k] = hit >= 0 ? (k == hit ? 1.0 : 0.0) : g[k] * is;
 }
+
+// launch-time choices: lines MG in {8, 12, 16} (else 0 = any, up to 32) and
+// the kernel support NP in {9, 13, 17} points (w + 1 <= NP)
+inline int mg_class(int mgl) { return (mgl == 8 || mgl == 12 || mgl == 16) ? mgl : 0; }
+inline int np_class(int w) { return w + 1 <= 9 ? 9 : (w + 1 <= 13 ? 13 : 17); }
 
 struct SpreadArgs {
   int64_t ns;
@@ -109,7 +119,9 @@ struct SpreadArgs {
 };
 
 // grid (x: source chunk, y: line group, z: dens * field)
+template <int MG, int NP>
 __global__ __launch_bounds__(NU_BLOCK) void spread_kernel(SpreadArgs a) {
+  constexpr int NA = MG > 0 ? MG : 32;
   __shared__ double sg[NU_LDS_DOUBLES];
   const int vf = blockIdx.z;
   const int v = vf / a.nfield, fld = vf % a.nfield;
@@ -123,20 +135,24 @@ __global__ __launch_bounds__(NU_BLOCK) void spread_kernel(SpreadArgs a) {
   const int64_t j1 = min(j0 + NU_SPREAD_CHUNK, a.ns);
   const double half_w = 0.5 * a.w;
   for (int64_t j = j0 + threadIdx.x; j < j1; j += NU_BLOCK) {
-    double gam[32];
-    bary_weights(a.sy[j], a.ybar, a.bary, a.mgl, gam);
+    double gam[NA];
+    bary_weights<MG>(a.sy[j], a.ybar, a.bary, a.mgl, gam);
     double x = a.sx[j];
     x -= a.d * rint(x / a.d);                       // wrap into [-d/2, d/2]
     const double g = (x + 0.5 * a.d) * a.inv_h;      // grid coordinate
     const int l0 = (int)ceil(g - half_w);
     const double qj = q[j];
-    for (int t = 0; t <= a.w; ++t) {
+#pragma unroll
+    for (int t = 0; t < NP; ++t) {
+      if (t > a.w) break;
       const int l = l0 + t;
       const double ph = es_kernel((l - g) / half_w, a.b);
       if (ph == 0.0) continue;
       const int lw = ((l % nf) + nf) % nf;
       const double val = qj * ph;
-      for (int kk = 0; kk < nk; ++kk) atomicAdd(&sg[kk * nf + lw], val * gam[k0 + kk]);
+#pragma unroll
+      for (int kk = 0; kk < NA; ++kk)
+        if (kk >= k0 && kk < k0 + nk) atomicAdd(&sg[(kk - k0) * nf + lw], val * gam[kk]);
     }
   }
   __syncthreads();
@@ -266,51 +282,101 @@ struct InterpArgs {
   double* val;           // [dens][NOUT][nt]
 };
 
+// One target per thread. The barycentric weight of line k is formed inside
+// the line loop from the normalising sum (no per-thread weight array), the
+// NP kernel values stay in registers, and the line fields go through LDS.
+template <int NP, bool STOKES>
 __global__ __launch_bounds__(NU_BLOCK) void interp_kernel(InterpArgs a) {
+  constexpr int NLF = STOKES ? 12 : 3, NO = STOKES ? 6 : 3;
+  __shared__ double sF[NLF][NU_BLOCK];
   const int64_t l = (int64_t)blockIdx.x * NU_BLOCK + threadIdx.x;
-  if (l >= a.nt) return;
-  double gam[32];
+  if (l >= a.nt) return;                 // no block-wide barrier below
+  const int tid = threadIdx.x;
   const double y = a.ty[l];
-  bary_weights(y, a.t.ybar, a.t.bary, a.mgl, gam);
+  // barycentric weights (second form): g_k = (sig_k / (y - ybar_k)) / sum_j sig_j / (y - ybar_j)
+  int hit = -1;
+  double ssum = 0.0;
+  for (int k = 0; k < a.mgl; ++k) {
+    const double dy = y - a.t.ybar[k];
+    if (dy == 0.0) hit = k;
+    ssum += a.t.bary[k] / (dy == 0.0 ? 1.0 : dy);
+  }
+  const double inv_s = 1.0 / ssum;
   double x = a.tx[l];
   x -= a.d * rint(x / a.d);
   const double g = (x + 0.5 * a.d) * a.inv_h;
   const double half_w = 0.5 * a.w;
   const int l0 = (int)ceil(g - half_w);
-  double ph[33];
-  int idx[33];
-  for (int t = 0; t <= a.w; ++t) {
+  double ph[NP];
+  int idx[NP];
+#pragma unroll
+  for (int t = 0; t < NP; ++t) {
     const int li = l0 + t;
-    ph[t] = es_kernel((li - g) / half_w, a.b);
+    ph[t] = t <= a.w ? es_kernel((li - g) / half_w, a.b) : 0.0;
     idx[t] = ((li % a.nf) + a.nf) % a.nf;
   }
-  const int nlf = a.kernel == PFMM_STOKES ? 12 : 3;
-  const int no = a.kernel == PFMM_STOKES ? 6 : 3;
   for (int v = 0; v < a.n_dens; ++v) {
-    double F[12];
-    for (int f = 0; f < nlf; ++f) {
+    for (int f = 0; f < NLF; ++f) {
       double s = 0.0;
       for (int k = 0; k < a.mgl; ++k) {
-        const c2* row = a.grid + (((size_t)v * nlf + f) * a.mgl + k) * a.nf;
+        const double gk = hit >= 0 ? (k == hit ? 1.0 : 0.0) : a.t.bary[k] / (y - a.t.ybar[k]) * inv_s;
+        const c2* row = a.grid + (((size_t)v * NLF + f) * a.mgl + k) * a.nf;
         double r = 0.0;
-        for (int t = 0; t <= a.w; ++t) r += ph[t] * row[idx[t]].r;
-        s += gam[k] * r;
+#pragma unroll
+        for (int t = 0; t < NP; ++t)
+          if (t <= a.w) r += ph[t] * row[idx[t]].r;
+        s += gk * r;
       }
-      F[f] = s;
+      sF[f][tid] = s;
     }
-    double* o = a.val + (size_t)v * no * a.nt;
-    if (a.kernel == PFMM_STOKES) {
+    double* o = a.val + (size_t)v * NO * a.nt;
+    if constexpr (STOKES) {
       // u = P - y Q; du/dx = P_x - y Q_x; du/dy = P_y - y Q_y - Q
+#pragma unroll
       for (int c = 0; c < 2; ++c) {
-        o[(size_t)c * a.nt + l] = F[c] - y * F[2 + c];
-        o[(size_t)(2 + 2 * c) * a.nt + l] = F[4 + c] - y * F[6 + c];
-        o[(size_t)(3 + 2 * c) * a.nt + l] = F[8 + c] - y * F[10 + c] - F[2 + c];
+        o[(size_t)c * a.nt + l] = sF[c][tid] - y * sF[2 + c][tid];
+        o[(size_t)(2 + 2 * c) * a.nt + l] = sF[4 + c][tid] - y * sF[6 + c][tid];
+        o[(size_t)(3 + 2 * c) * a.nt + l] = sF[8 + c][tid] - y * sF[10 + c][tid] - sF[2 + c][tid];
       }
     } else {
-      o[l] = F[0];
-      o[a.nt + l] = F[1];
-      o[2 * a.nt + l] = F[2];
+      o[l] = sF[0][tid];
+      o[a.nt + l] = sF[1][tid];
+      o[2 * a.nt + l] = sF[2][tid];
     }
+  }
+}
+
+// dispatch over the compile-time classes
+template <int MG, int NP>
+void launch_spread_np(dim3 g, const SpreadArgs& sa, hipStream_t st) {
+  hipLaunchKernelGGL((spread_kernel<MG, NP>), g, dim3(NU_BLOCK), 0, st, sa);
+}
+template <int MG>
+void launch_spread_mg(dim3 g, const SpreadArgs& sa, hipStream_t st) {
+  switch (np_class(sa.w)) {
+    case 9: launch_spread_np<MG, 9>(g, sa, st); break;
+    case 13: launch_spread_np<MG, 13>(g, sa, st); break;
+    default: launch_spread_np<MG, 17>(g, sa, st); break;
+  }
+}
+void launch_spread(dim3 g, const SpreadArgs& sa, hipStream_t st) {
+  switch (mg_class(sa.mgl)) {
+    case 8: launch_spread_mg<8>(g, sa, st); break;
+    case 12: launch_spread_mg<12>(g, sa, st); break;
+    case 16: launch_spread_mg<16>(g, sa, st); break;
+    default: launch_spread_mg<0>(g, sa, st); break;
+  }
+}
+template <int NP>
+void launch_interp_np(dim3 g, const InterpArgs& ia, hipStream_t st) {
+  if (ia.kernel == PFMM_STOKES) hipLaunchKernelGGL((interp_kernel<NP, true>), g, dim3(NU_BLOCK), 0, st, ia);
+  else hipLaunchKernelGGL((interp_kernel<NP, false>), g, dim3(NU_BLOCK), 0, st, ia);
+}
+void launch_interp(dim3 g, const InterpArgs& ia, hipStream_t st) {
+  switch (np_class(ia.w)) {
+    case 9: launch_interp_np<9>(g, ia, st); break;
+    case 13: launch_interp_np<13>(g, ia, st); break;
+    default: launch_interp_np<17>(g, ia, st); break;
   }
 }
 
@@ -348,7 +414,7 @@ int nufft_R(const pfmm_plan_s* p, int64_t ns, const double* sx, const double* sy
     sa.d = p->geo.d; sa.b = p->nu.es_beta; sa.inv_h = nf / p->geo.d;
     sa.sx = sx; sa.sy = sy; sa.dens = dens; sa.ybar = t.ybar; sa.bary = t.bary; sa.grid = grid;
     dim3 g((unsigned)((ns + NU_SPREAD_CHUNK - 1) / NU_SPREAD_CHUNK), (unsigned)L.n_groups, (unsigned)(nd * nfr));
-    hipLaunchKernelGGL(spread_kernel, g, dim3(NU_BLOCK), 0, st, sa);
+    launch_spread(g, sa, st);
   }
   const int nfft = nd * nfr * mgl;
   hipLaunchKernelGGL(fft_kernel, dim3(nfft), dim3(NU_BLOCK), nf * sizeof(c2), st, (const double*)grid,
@@ -380,7 +446,7 @@ int nufft_L(const pfmm_plan_s* p, int64_t nt, const double* tx, const double* ty
     ia.nt = nt; ia.kernel = p->kernel; ia.mgl = mgl; ia.nf = nf; ia.w = p->nu.w; ia.n_dens = nd;
     ia.d = p->geo.d; ia.b = p->nu.es_beta; ia.inv_h = nf / p->geo.d; ia.t = t; ia.tx = tx; ia.ty = ty;
     ia.grid = grid; ia.val = val;
-    hipLaunchKernelGGL(interp_kernel, dim3((unsigned)((nt + NU_BLOCK - 1) / NU_BLOCK)), dim3(NU_BLOCK), 0, st, ia);
+    launch_interp(dim3((unsigned)((nt + NU_BLOCK - 1) / NU_BLOCK)), ia, st);
   }
   *val_out = val;
   return PFMM_OK;
