@@ -45,10 +45,9 @@ __device__ __forceinline__ void bessel_k01_f32(float x, float& k0, float& k1_ove
     k1_over_x = xk1 * __builtin_amdgcn_rcpf(x * x);
   } else {
     float rx = __builtin_amdgcn_rcpf(x);
-    float u = 2.0f * rx;
     float e = __expf(-x) * __builtin_amdgcn_rsqf(x);
-    k0 = e * horner_f(KL0_F32, u);
-    k1_over_x = e * rx * horner_f(KL1_F32, u);
+    k0 = e * horner_f(KL0_F32, rx);             // polynomials in 1/x
+    k1_over_x = e * rx * horner_f(KL1_F32, rx);
   }
 }
 
@@ -58,10 +57,9 @@ __device__ __forceinline__ void bessel_k01_f32(float x, float& k0, float& k1_ove
 // branch, so a coherent wavefront runs a single path).
 __device__ __forceinline__ void bessel_k01_f32_wave(float x, float& k0, float& k1_over_x) {
   const float rx = __builtin_amdgcn_rcpf(x);
-  const float u = 2.0f * rx;
   const float e = __expf(-x) * __builtin_amdgcn_rsqf(x);
-  k0 = e * horner_f(KL0_F32, u);
-  k1_over_x = e * rx * horner_f(KL1_F32, u);
+  k0 = e * horner_f(KL0_F32, rx);               // polynomials in 1/x
+  k1_over_x = e * rx * horner_f(KL1_F32, rx);
   const bool small = x <= 2.0f;
   if (__any(small)) {
     const float t = 0.25f * x * x;

@@ -170,3 +170,40 @@ def test_tuning_get_set_and_nufft_grid(P):
     assert big.tuning["nufft_grid"] == 0 and big.info["nufft_nf"] <= 4096
     with pytest.raises(P.PfmmError):
         plan.set_tuning(near_blocks=-1)
+
+
+def _tables():
+    import re
+    txt = open(os.path.join(ROOT, "paper_2111_01083_amd", "csrc", "bessel_tables.h")).read()
+    tabs = {}
+    for name, body in re.findall(r"(\w+)\[\d+\] = \{([^}]*)\}", txt):
+        tabs[name] = np.array([float(v) for v in body.split(",") if v.strip()])
+    return tabs
+
+
+@pytest.mark.parametrize("tag,bar", [("F32", 1e-7), ("F64", 1e-14)])
+def test_device_bessel_tables_against_scipy(tag, bar):
+    # the K0/K1 forms the device evaluates (ascending series for x <= 2, scaled
+    # large-argument fit for x > 2), in FP64 here, against scipy.special
+    import scipy.special as sp
+    from numpy.polynomial import chebyshev as C
+    t = _tables()
+    xs = np.linspace(2e-3, 2.0, 2001)
+    tt = 0.25 * xs * xs
+    lt = np.log(tt)
+    hz = lambda c, v: np.polyval(c[::-1], v)
+    k0 = hz(t[f"KS_P0_{tag}"], tt) - 0.5 * lt * hz(t[f"KS_I0_{tag}"], tt)
+    k1x = (1 + tt * (lt * hz(t[f"KS_J1_{tag}"], tt) - hz(t[f"KS_P1_{tag}"], tt))) / xs ** 2
+    assert np.max(np.abs(k0 / sp.k0(xs) - 1)) < bar
+    assert np.max(np.abs(k1x * xs / sp.k1(xs) - 1)) < bar
+    xl = np.linspace(2.0, 80.0, 4001)
+    if tag == "F32":
+        rx = 1.0 / xl
+        k0l = hz(t["KL0_F32"], rx)
+        k1l = hz(t["KL1_F32"], rx)
+    else:
+        s = 2 * (2.0 / xl) - 1
+        k0l = C.chebval(s, t["KL0_F64"])
+        k1l = C.chebval(s, t["KL1_F64"])
+    assert np.max(np.abs(k0l / (sp.k0e(xl) * np.sqrt(xl)) - 1)) < bar
+    assert np.max(np.abs(k1l / (sp.k1e(xl) * np.sqrt(xl)) - 1)) < bar
