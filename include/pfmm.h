@@ -105,6 +105,8 @@ typedef struct {
   int n_quad;                 /* west/east quadrature nodes                    */
   int m_gl, nufft_nf, nufft_w;/* NUFFT lines, fine grid size, kernel width     */
   int n_images;               /* near images (2 m0 + 1) * 3                    */
+  int n_log_groups;           /* mixed symmetric near field: image groups whose
+                                 r^2 product shares one log2 (1, 3 or n_images) */
 } pfmm_plan_info_t;
 
 typedef struct pfmm_plan_s* pfmm_plan_t;

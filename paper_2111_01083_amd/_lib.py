@@ -38,7 +38,8 @@ class pfmm_plan_info_t(ctypes.Structure):
                 ("d", ctypes.c_double), ("xi", ctypes.c_double), ("eta", ctypes.c_double),
                 ("rot_cos", ctypes.c_double), ("rot_sin", ctypes.c_double), ("eps", ctypes.c_double),
                 ("n_modes", ctypes.c_int), ("n_quad", ctypes.c_int), ("m_gl", ctypes.c_int),
-                ("nufft_nf", ctypes.c_int), ("nufft_w", ctypes.c_int), ("n_images", ctypes.c_int)]
+                ("nufft_nf", ctypes.c_int), ("nufft_w", ctypes.c_int), ("n_images", ctypes.c_int),
+                ("n_log_groups", ctypes.c_int)]
 
 
 class pfmm_tuning_t(ctypes.Structure):

@@ -142,6 +142,16 @@ int pfmm_plan(int kernel, const double* e1, const double* e2, double tol, const 
 
 }  // extern "C"
 
+// image groups of the symmetric mixed near field (one log2 per group)
+static void set_log_groups(MutualArgs& m, const Geometry& g) {
+  m.n_lg = g.n_lg;
+  for (int i = 0; i < g.n_lg; ++i) {
+    m.lg_end[i] = g.lg_end[i];
+    m.lg_p0[i] = std::ldexp(1.0f, g.lg_e0[i]);
+    m.lg_e0[i] = (double)g.lg_e0[i];
+  }
+}
+
 // the plan's device table: sn | ew | GL nodes | barycentric weights |
 // NUFFT deconvolution | images (plain, then times sigma)
 static std::vector<double> plan_table(pfmm_plan_s* p) {
@@ -208,6 +218,7 @@ int pfmm_plan_get_info(pfmm_plan_t p, pfmm_plan_info_t* info) {
   info->n_quad = p->n_ew;
   info->m_gl = p->nu.m_gl; info->nufft_nf = p->nu.nf; info->nufft_w = p->nu.w;
   info->n_images = p->geo.n_images;
+  info->n_log_groups = p->geo.n_lg;
   return PFMM_OK;
 }
 
@@ -437,6 +448,7 @@ int pfmm::eval_core(pfmm_plan_t p, int64_t ns, const double* src_xy, const doubl
     ma.n_images = g.n_images;
     ma.imx = p->d_tab + p->tab_img + 2 * g.n_images; ma.imy = ma.imx + g.n_images;
     ma.sigma = g.sigma;
+    set_log_groups(ma, g);
     ma.n = ns; ma.chunk_len = r.L.mu_chunk;
     ma.x = nd.sx; ma.y = nd.sy; ma.q64 = nd.q64; ma.q32 = nd.q32;
     ma.beta = p->beta;
@@ -706,7 +718,7 @@ static int batch_build(pfmm_batch_s* b, int64_t split, int grid_mult) {
       MutualArgs& m = bc.margs;
       m.n_images = g.n_images;
       m.imx = b->plans[c]->d_tab + b->plans[c]->tab_img + 2 * g.n_images; m.imy = m.imx + g.n_images;
-      m.sigma = g.sigma; m.n = r.ns; m.chunk_len = L.mu_chunk; m.beta = b->plans[c]->beta;
+      m.sigma = g.sigma; set_log_groups(m, g); m.n = r.ns; m.chunk_len = L.mu_chunk; m.beta = b->plans[c]->beta;
       bc.n_chunks = (int)((r.ns + L.mu_chunk - 1) / L.mu_chunk);
       bc.o_qb64 = B + L.qb64; bc.o_qb32 = mixed ? B + L.qb32 : 0;
       task += bc.n_tiles;

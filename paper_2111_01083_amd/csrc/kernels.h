@@ -20,7 +20,7 @@ constexpr int MU_BLOCK = PFMM_MU_BLOCK;   // points per block of the symmetric n
 #define PFMM_NEAR_BIN 1
 #endif
 constexpr int NEAR_FLUSH = PFMM_NEAR_FLUSH;  // FP32 partial-sum length before an FP64 flush (mixed)
-constexpr double R2MIN_F32 = 8.673617379884035e-19;   // 2^-60: r^2 clamp of the mixed Laplace/Stokes pair
+constexpr double R2MIN_F32 = 7.888609052210118e-31;   // 2^-100: r^2 guard of the mixed Laplace/Stokes pair
 constexpr int FAR_R_BLOCK = 256;  // threads per far_R block: mode lanes x source slices
 // mode lanes of a far_R block for n_w1 modes/nodes (incl. the moment slot):
 // the smallest power of two >= n_w1 in [32, 256]; the other 256/lanes
@@ -137,6 +137,10 @@ struct MutualArgs {
   int n_images;
   const double *imx, *imy;               // image shifts times sigma (device, n_images each)
   double sigma;                          // coordinate scale (mixed Laplace/Stokes)
+  int n_lg;                              // log groups of the images (mixed Laplace/Stokes)
+  int lg_end[MAX_IMAGES];                // one past the last image of each group
+  float lg_p0[MAX_IMAGES];               // 2^e0: start of each group's r^2 product
+  double lg_e0[MAX_IMAGES];              // e0, removed from each group's log2
   int64_t n, chunk_len;
   const double *x, *y;                   // canonical points in binned order
   const double* q64;                     // binned densities [n_dens][nc][n]

@@ -215,10 +215,11 @@ void launch_fill_zero(double* p, int64_t n, hipStream_t s) {
 //     sum lg F1, sum lg F2, sum c2 dx, sum c2 dy, sum c2, sum c2 a dx,
 //     sum c2 a dy, sum (F2 a - F1 b)
 //
-// r = 0: Laplace/Stokes evaluate at r^2 + R2MIN (R2MIN = 2^-60, so log2 is
+// r = 0: Laplace/Stokes evaluate at r^2 + R2MIN (R2MIN = 2^-100, so log2 is
 // exact for the self pair, the only pair with r = 0 in a self-excluding
 // evaluation); its value lg(R2MIN) * density is removed exactly in FP64 at
-// the end (the gradient terms vanish because dx = dy = 0). Yukawa (and the FP64 path)
+// the end (the gradient terms vanish because dx = dy = 0; 1/R2MIN = 2^100 is
+// still finite in FP32). Yukawa (and the FP64 path)
 // zero the pair with a select. Exactly coincident distinct points are a
 // singularity of the sum and are not supported.
 // ---------------------------------------------------------------------------
@@ -273,7 +274,7 @@ __device__ __forceinline__ void near_pair(real dx, real dy, const real* qv, cons
     }
   } else {
     // r^2 + R2MIN: exactly R2MIN for the self pair, below half an ulp of r^2
-    // for every pair with scaled r^2 >= 2^-36
+    // for every pair with scaled r^2 >= 2^-76
     const real r2s = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, r2min));
     const real lg = __builtin_amdgcn_logf(r2s);
     const real inv = __builtin_amdgcn_rcpf(r2s);
@@ -486,16 +487,21 @@ __global__ __launch_bounds__(NEAR_BLOCK) void near_kernel(NearArgs a) {
 // to acc with FP64 atomics (the order of these adds is not fixed, so repeated
 // runs agree to FP64 rounding). Precision as in the one-sided kernel: MIXED
 // takes the coordinate difference in FP64, the rest in FP32, log terms summed
-// in FP64 with the FP64 densities; no r = 0 guard is needed (no point meets
-// itself here).
+// in FP64 with the FP64 densities; the log2 of a group of images is that of
+// the FP32 product of their r^2 (the plan bounds the product's range), which
+// is as accurate as per-image logs and saves a log, a conversion and the FP64
+// fmas per image. No r = 0 guard is needed (no point meets itself here).
 // ---------------------------------------------------------------------------
 constexpr int MU_SUB = 64;
 
 
+// One pair (i, j) under one image. Log terms: FP64 mode adds lg f to the
+// FP32/FP64 partials; mixed mode multiplies r^2 into the group product P
+// (one log2 per image group, taken by the caller).
 template <int K, bool MIXED, int ND, typename real>
-__device__ __forceinline__ void mutual_pair(real dx, real dy, const real* qi, const double* qid,
-                                            const real* qj, const double* qjd, real (*pA)[NAcc<K>::v],
-                                            real (*pB)[NAcc<K>::v], double (*lA)[2], double (*lB)[2], real beta) {
+__device__ __forceinline__ void mutual_pair(real dx, real dy, const real* qi, const real* qj,
+                                            real (*pA)[NAcc<K>::v], real (*pB)[NAcc<K>::v], real& P,
+                                            real beta) {
   if constexpr (K == PFMM_YUKAWA) {
     const real r2 = dx * dx + dy * dy;
     real k0, k1x;
@@ -508,27 +514,20 @@ __device__ __forceinline__ void mutual_pair(real dx, real dy, const real* qi, co
       pB[v][0] += qi[v] * k0; pB[v][1] -= qi[v] * gx; pB[v][2] -= qi[v] * gy;
     }
   } else {
-    real lg, inv;
+    real lg = 0, inv;
     if constexpr (MIXED) {
       const real r2 = __builtin_fmaf(dx, dx, dy * dy);
-      lg = __builtin_amdgcn_logf(r2);
+      P *= r2;
       inv = __builtin_amdgcn_rcpf(r2);
     } else {
       const real r2 = dx * dx + dy * dy;
       lg = log(r2);
       inv = 1.0 / r2;
     }
-    double lgd = 0.0;
-    if constexpr (MIXED) lgd = (double)lg;
     if constexpr (K == PFMM_LAPLACE) {
 #pragma unroll
       for (int v = 0; v < ND; ++v) {
-        if constexpr (MIXED) {
-          lA[v][0] = __builtin_fma(qjd[v], lgd, lA[v][0]);
-          lB[v][0] = __builtin_fma(qid[v], lgd, lB[v][0]);
-        } else {
-          pA[v][0] += qj[v] * lg; pB[v][0] += qi[v] * lg;
-        }
+        if constexpr (!MIXED) { pA[v][0] += qj[v] * lg; pB[v][0] += qi[v] * lg; }
         const real sj = qj[v] * inv, si = qi[v] * inv;
         pA[v][1] += sj * dx; pA[v][2] += sj * dy;
         pB[v][1] -= si * dx; pB[v][2] -= si * dy;
@@ -539,10 +538,7 @@ __device__ __forceinline__ void mutual_pair(real dx, real dy, const real* qi, co
       for (int v = 0; v < ND; ++v) {
         const real* fj = qj + 2 * v;
         const real* fi = qi + 2 * v;
-        if constexpr (MIXED) {
-          lA[v][0] = __builtin_fma(qjd[2 * v], lgd, lA[v][0]); lA[v][1] = __builtin_fma(qjd[2 * v + 1], lgd, lA[v][1]);
-          lB[v][0] = __builtin_fma(qid[2 * v], lgd, lB[v][0]); lB[v][1] = __builtin_fma(qid[2 * v + 1], lgd, lB[v][1]);
-        } else {
+        if constexpr (!MIXED) {
           pA[v][0] += lg * fj[0]; pA[v][1] += lg * fj[1];
           pB[v][0] += lg * fi[0]; pB[v][1] += lg * fi[1];
         }
@@ -651,9 +647,33 @@ __device__ __forceinline__ void mutual_block(const MutualArgs& a, int64_t tile, 
         for (int c = 0; c < NA; ++c) { pA[v][c] = 0; pB[v][c] = 0; }
         lA[v][0] = lA[v][1] = lB[v][0] = lB[v][1] = 0.0;
       }
-      for (int im = 0; im < a.n_images; ++im) {
-        const real dx = (real)(d0x - imx[im]), dy = (real)(d0y - imy[im]);
-        mutual_pair<K, MIXED, ND, real>(dx, dy, qi, qid, qj, qjd, pA, pB, lA, lB, beta);
+      if constexpr (NLOG > 0) {
+        // one log2 per image group of the product of its r^2 (FP32), then FP64
+        // fmas with the FP64 densities
+        int im = 0;
+        for (int g = 0; g < a.n_lg; ++g) {
+          real P = a.lg_p0[g];
+          for (const int ie = a.lg_end[g]; im < ie; ++im) {
+            const real dx = (real)(d0x - imx[im]), dy = (real)(d0y - imy[im]);
+            mutual_pair<K, MIXED, ND, real>(dx, dy, qi, qj, pA, pB, P, beta);
+          }
+          // padding sources (far away, zero density) may overflow P; the clamp
+          // keeps 0 * log2(P) finite (valid pairs stay below 2^122)
+          const double lgd = (double)__builtin_amdgcn_logf(__builtin_fminf(P, 3.40282347e38f)) - a.lg_e0[g];
+#pragma unroll
+          for (int v = 0; v < ND; ++v)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+              lA[v][c] = __builtin_fma(qjd[v * NC + c], lgd, lA[v][c]);
+              lB[v][c] = __builtin_fma(qid[v * NC + c], lgd, lB[v][c]);
+            }
+        }
+      } else {
+        real P = 1;
+        for (int im = 0; im < a.n_images; ++im) {
+          const real dx = (real)(d0x - imx[im]), dy = (real)(d0y - imy[im]);
+          mutual_pair<K, MIXED, ND, real>(dx, dy, qi, qj, pA, pB, P, beta);
+        }
       }
 #pragma unroll
       for (int v = 0; v < ND; ++v) {

@@ -23,6 +23,13 @@ struct Geometry {
   // most pairs; log2 r^2 is then shifted by lg_shift = 2k, removed in FP64
   double sigma;
   int lg_shift;
+  // symmetric mixed near field: the r^2 values of a run of consecutive images
+  // are multiplied in FP32 and share one log2. Group g covers images
+  // [lg_end[g-1], lg_end[g]) and starts its product at 2^lg_e0[g]; the plan
+  // bounds every partial product away from FP32 overflow and underflow
+  int n_lg;
+  int lg_end[MAX_IMAGES];
+  int lg_e0[MAX_IMAGES];
 };
 
 // Per south/north mode record (doubles), mode index m = m_lo + i:

@@ -56,6 +56,54 @@ void reduce_basis(double b1[2], double b2[2]) {
   if (dot(b2, b2) < dot(b1, b1)) { std::swap(b1[0], b2[0]); std::swap(b1[1], b2[1]); }
 }
 
+// Log groups of the symmetric mixed near field. The log terms of a pair sum
+// log2 r^2 over the images l of the near region; the kernel multiplies the
+// FP32 r^2 of a run of images and takes one log2 of the product. Bounds for
+// a group (coordinates scaled by sigma; a pair difference d0 lies in
+// {u e1 + v e2 : |u|, |v| < 1}, so |d0| < dmax):
+//   every factor |d0 - l|^2 < (dmax + |l|)^2, and
+//   with l* the group image nearest to d0, |d0 - l| >= |l - l*| / 2 for the
+//   others, so the product without l*'s factor is >= prod min(1, |l - l*|^2/4).
+// Starting the product at 2^e0 keeps every partial product below 2^124 and,
+// for the closest image's r^2 down to 2^-100, above 2^-124. The groups tried
+// are all images, the rows of fixed n (images one period d apart), and
+// single images (always valid: the per-image log).
+void plan_log_groups(pfmm::Geometry& g, int per_row) {
+  const double s = g.sigma;
+  const double dmax = s * std::max(std::hypot(g.d + g.xi, g.eta), std::hypot(g.d - g.xi, g.eta));
+  const int sizes[3] = {g.n_images, per_row, 1};
+  for (int gs : sizes) {
+    if (gs < 1 || g.n_images % gs) continue;
+    bool ok = true;
+    int n_lg = 0;
+    for (int g0 = 0; g0 < g.n_images && ok; g0 += gs) {
+      double fmax = 0, gmin = 0;
+      for (int i = g0; i < g0 + gs; ++i) {
+        const double li = s * std::hypot(g.img_x[i], g.img_y[i]);
+        fmax += std::max(0.0, 2 * std::log2(dmax + li));
+      }
+      for (int k = g0; k < g0 + gs; ++k) {
+        double t = 0;
+        for (int i = g0; i < g0 + gs; ++i) {
+          if (i == k) continue;
+          const double sep2 = s * s * (std::pow(g.img_x[i] - g.img_x[k], 2) + std::pow(g.img_y[i] - g.img_y[k], 2));
+          t += std::min(0.0, std::log2(sep2 / 4));
+        }
+        gmin = std::min(gmin, t);
+      }
+      // need e0 + fmax <= 124 and -100 + e0 + gmin >= -124 (two bits of slack each)
+      const double lo = std::ceil(-22 - gmin), hi = std::floor(122 - fmax);
+      if (lo > hi) { ok = false; break; }
+      g.lg_e0[n_lg] = (int)std::min(std::max(0.0, lo), hi);
+      g.lg_end[n_lg] = g0 + gs;
+      ++n_lg;
+    }
+    if (ok) { g.n_lg = n_lg; return; }
+  }
+  g.n_lg = g.n_images;   // unreachable: single images always qualify
+  for (int i = 0; i < g.n_images; ++i) { g.lg_end[i] = i + 1; g.lg_e0[i] = 0; }
+}
+
 // West/east rule (Thm. west_thm and its Laplace/Stokes limits): the paper's
 // generalized Gaussian tables are not published, so the rule is built here
 // from Gauss-Legendre panels. The integrand decays like e^{-kappa X} with
@@ -210,6 +258,7 @@ int build_plan(int kernel, const double* e1, const double* e2, double tol, const
       g.img_y[g.n_images] = n * eta;
       ++g.n_images;
     }
+  plan_log_groups(g, 2 * m0 + 1);
 
   const double eps = p->eps;
   const double beta = p->beta;

@@ -93,3 +93,51 @@ def test_repeated_evaluations_agree_to_fp64_rounding(env, kernel, beta):
     a = [t.cpu().numpy() for t in plan(src, dens)]
     b = [t.cpu().numpy() for t in plan(src, dens)]
     assert rel(a[0], b[0]) < 1e-13 and rel(a[1], b[1]) < 1e-13
+
+
+@pytest.mark.parametrize("a_ratio,groups", [(2000.0, 1), (4000.0, 3)])
+@pytest.mark.parametrize("kernel", ["laplace", "stokes"])
+def test_thin_cells_share_logs_across_images(env, a_ratio, groups, kernel):
+    # the mixed symmetric kernel takes one log2 of the FP32 product of r^2 over
+    # a group of images; in very thin cells the y-images are close together, so
+    # the product starts at 2^e0 > 1 (A = 2000) or the groups are the rows of
+    # images one period apart (A = 4000)
+    P, torch, dev = env
+    n = 1537
+    e1, e2 = (a_ratio, 0.0), (0.0, 1.0)
+    rng = np.random.default_rng(11)
+    src = W.cell_points(rng, e1, e2, n)
+    dens = W.neutral_forces(rng, n) if kernel == "stokes" else W.neutral_charges(rng, n)
+    plan = P.Plan(kernel, e1, e2, 1e-6, precision="mixed", self_exclude=True)
+    assert plan.info["n_log_groups"] == groups
+    print(f"case thin {kernel} A={a_ratio}", flush=True)
+    pm, gm = run(env, kernel, e1, e2, src, dens, "mixed", 1e-6, 0.0, "mutual")
+    p1, g1 = run(env, kernel, e1, e2, src, dens, "mixed", 1e-6, 0.0, "one_sided")
+    po, go = oracle.evaluate(kernel, e1, e2, src, dens, None)
+    assert rel(pm, po) < 1e-6 and rel(gm, go) < 1e-6, (rel(pm, po), rel(gm, go))
+    assert rel(pm, p1) < 1e-6 and rel(gm, g1) < 1e-6, (rel(pm, p1), rel(gm, g1))
+
+
+@pytest.mark.parametrize("kernel", ["laplace", "stokes"])
+def test_near_coincident_points(env, kernel):
+    # pairs 1e-6, 1e-9 and 1e-11 apart (r^2 down to 1e-22): exact in the
+    # diagonal tiles (the self-pair guard 2^-100 is far below their r^2) and in
+    # the images' FP32 r^2 product of the symmetric kernel (no underflow)
+    P, torch, dev = env
+    n = 600
+    e1, e2 = CELLS["square"]
+    rng = np.random.default_rng(12)
+    src = W.cell_points(rng, e1, e2, n)
+    for k, sep in enumerate([1e-6, 1e-9, 1e-11]):
+        ang = rng.uniform(0, 2 * np.pi)
+        src[:, 2 * k + 1] = src[:, 2 * k] + sep * np.array([np.cos(ang), np.sin(ang)])
+    # pairs 1e-9 apart through an edge and through a corner of the cell: close
+    # only under a nonzero image shift, and far apart in the binned order
+    src[:, 6], src[:, 7] = (0.5 - 5e-10, 0.1), (-0.5 + 5e-10, 0.1)
+    src[:, 8], src[:, 9] = (0.5 - 3e-10, 0.5 - 4e-10), (-0.5 + 3e-10, -0.5 + 4e-10)
+    dens = W.neutral_forces(rng, n) if kernel == "stokes" else W.neutral_charges(rng, n)
+    print(f"case coincident {kernel}", flush=True)
+    pm, gm = run(env, kernel, e1, e2, src, dens, "mixed", 1e-6, 0.0, "mutual")
+    po, go = oracle.evaluate(kernel, e1, e2, src, dens, None)
+    assert np.isfinite(pm).all() and np.isfinite(gm).all()
+    assert rel(pm, po) < 1e-6 and rel(gm, go) < 1e-6, (rel(pm, po), rel(gm, go))

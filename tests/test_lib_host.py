@@ -207,3 +207,12 @@ def test_device_bessel_tables_against_scipy(tag, bar):
         k1l = C.chebval(s, t["KL1_F64"])
     assert np.max(np.abs(k0l / (sp.k0e(xl) * np.sqrt(xl)) - 1)) < bar
     assert np.max(np.abs(k1l / (sp.k1e(xl) * np.sqrt(xl)) - 1)) < bar
+
+
+@pytest.mark.parametrize("e1,e2,groups", [((1.0, 0.0), (0.0, 1.0), 1), ((1.0, 0.0), (0.5, 0.866), 1),
+                                          ((100.0, 0.0), (0.0, 1.0), 1), ((4000.0, 0.0), (0.0, 1.0), 3)])
+def test_log_groups_of_the_symmetric_mixed_near_field(P, e1, e2, groups):
+    # one group of all images unless the cell is so thin that the product could
+    # leave the FP32 range; then one group per row of images (one period apart)
+    inf = P.Plan("laplace", e1, e2, 1e-6, precision="mixed", self_exclude=True).info
+    assert inf["n_log_groups"] == groups and inf["n_images"] % groups == 0
