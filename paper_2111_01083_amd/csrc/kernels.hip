@@ -495,62 +495,82 @@ __global__ __launch_bounds__(NEAR_BLOCK) void near_kernel(NearArgs a) {
 constexpr int MU_SUB = 64;
 
 
-// One pair (i, j) under one image. Log terms: FP64 mode adds lg f to the
-// FP32/FP64 partials; mixed mode multiplies r^2 into the group product P
-// (one log2 per image group, taken by the caller).
-template <int K, bool MIXED, int ND, typename real>
-__device__ __forceinline__ void mutual_pair(real dx, real dy, const real* qi, const real* qj,
-                                            real (*pA)[NAcc<K>::v], real (*pB)[NAcc<K>::v], real& P,
-                                            real beta) {
+// The densities of a pair (i, j) are the same under every image, so the image
+// loop only accumulates density-free moments of the kernel, and the densities
+// multiply them once per pair. Moments (dx, dy = r under one image,
+// inv = 1/r^2, ia = dx inv, ib = dy inv):
+//   Laplace: [0] sum ia, [1] sum ib (FP64 mode: [2] sum ln r^2)
+//   Yukawa:  [0] sum K0(x), [1] sum k dx, [2] sum k dy, k = K1(x)/x
+//   Stokes:  [0] sum ia, [1] sum ib, [2] sum ia dx, [3] sum ia dy, [4] sum ib dy,
+//            [5] sum ia^2 dx, [6] sum ia^2 dy, [7] sum ib^2 dx
+//            (FP64 mode: [8] sum ln r^2)
+// The mixed log terms take the product of r^2 instead (P, one log2 per group).
+template <int K, bool MIXED>
+constexpr int mu_moments() {
+  return (K == PFMM_STOKES ? 8 : (K == PFMM_YUKAWA ? 3 : 2)) + ((!MIXED && K != PFMM_YUKAWA) ? 1 : 0);
+}
+
+template <int K, bool MIXED, typename real>
+__device__ __forceinline__ void mutual_image(real dx, real dy, real* m, real& P, real beta) {
   if constexpr (K == PFMM_YUKAWA) {
     const real r2 = dx * dx + dy * dy;
     real k0, k1x;
     if constexpr (MIXED) bessel_k01_f32_wave(beta * __builtin_amdgcn_sqrtf(r2), k0, k1x);
     else bessel_k01_f64(beta * sqrt(r2), k0, k1x);
-    const real gx = k1x * dx, gy = k1x * dy;
-#pragma unroll
-    for (int v = 0; v < ND; ++v) {
-      pA[v][0] += qj[v] * k0; pA[v][1] += qj[v] * gx; pA[v][2] += qj[v] * gy;
-      pB[v][0] += qi[v] * k0; pB[v][1] -= qi[v] * gx; pB[v][2] -= qi[v] * gy;
-    }
+    m[0] += k0; m[1] += k1x * dx; m[2] += k1x * dy;
   } else {
-    real lg = 0, inv;
+    real inv;
     if constexpr (MIXED) {
       const real r2 = __builtin_fmaf(dx, dx, dy * dy);
       P *= r2;
       inv = __builtin_amdgcn_rcpf(r2);
     } else {
       const real r2 = dx * dx + dy * dy;
-      lg = log(r2);
+      m[mu_moments<K, MIXED>() - 1] += log(r2);
       inv = 1.0 / r2;
     }
     if constexpr (K == PFMM_LAPLACE) {
-#pragma unroll
-      for (int v = 0; v < ND; ++v) {
-        if constexpr (!MIXED) { pA[v][0] += qj[v] * lg; pB[v][0] += qi[v] * lg; }
-        const real sj = qj[v] * inv, si = qi[v] * inv;
-        pA[v][1] += sj * dx; pA[v][2] += sj * dy;
-        pB[v][1] -= si * dx; pB[v][2] -= si * dy;
-      }
+      m[0] += inv * dx; m[1] += inv * dy;
     } else {
       const real ia = inv * dx, ib = inv * dy;
+      m[0] += ia; m[1] += ib;
+      m[2] += ia * dx; m[3] += ia * dy; m[4] += ib * dy;
+      const real ia2 = ia * ia, ib2 = ib * ib;
+      m[5] += ia2 * dx; m[6] += ia2 * dy; m[7] += ib2 * dx;
+    }
+  }
+}
+
+// pair partials of both points from the moments: pA for i (source j, force
+// f_j), pB for j (source i, displacement -r: odd moments change sign).
+// Mixed Laplace/Stokes log terms [0, NC) are left to the caller.
+template <int K, bool MIXED, int ND, typename real>
+__device__ __forceinline__ void mutual_combine(const real* m, const real* qi, const real* qj,
+                                               real (*pA)[NAcc<K>::v], real (*pB)[NAcc<K>::v]) {
 #pragma unroll
-      for (int v = 0; v < ND; ++v) {
-        const real* fj = qj + 2 * v;
-        const real* fi = qi + 2 * v;
-        if constexpr (!MIXED) {
-          pA[v][0] += lg * fj[0]; pA[v][1] += lg * fj[1];
-          pB[v][0] += lg * fi[0]; pB[v][1] += lg * fi[1];
-        }
-        // seen from i (force F = f_j): c2 = ia F1 + ib F2, t = c2 ia
-        const real cA = ia * fj[0] + ib * fj[1], tA = cA * ia;
-        pA[v][2] += cA * dx; pA[v][3] += cA * dy; pA[v][4] += cA;
-        pA[v][5] += tA * dx; pA[v][6] += tA * dy; pA[v][7] += fj[1] * ia - fj[0] * ib;
-        // seen from j (force f_i, displacement -r): ia, ib change sign
-        const real cB = ia * fi[0] + ib * fi[1], tB = cB * ia;
-        pB[v][2] += cB * dx; pB[v][3] += cB * dy; pB[v][4] -= cB;
-        pB[v][5] -= tB * dx; pB[v][6] -= tB * dy; pB[v][7] -= fi[1] * ia - fi[0] * ib;
+  for (int v = 0; v < ND; ++v) {
+    if constexpr (K == PFMM_YUKAWA) {
+      pA[v][0] = qj[v] * m[0]; pA[v][1] = qj[v] * m[1]; pA[v][2] = qj[v] * m[2];
+      pB[v][0] = qi[v] * m[0]; pB[v][1] = -qi[v] * m[1]; pB[v][2] = -qi[v] * m[2];
+    } else if constexpr (K == PFMM_LAPLACE) {
+      if constexpr (!MIXED) { pA[v][0] = qj[v] * m[2]; pB[v][0] = qi[v] * m[2]; }
+      pA[v][1] = qj[v] * m[0]; pA[v][2] = qj[v] * m[1];
+      pB[v][1] = -qi[v] * m[0]; pB[v][2] = -qi[v] * m[1];
+    } else {
+      // (2..7) = sum c dx, sum c dy, sum c, sum c ia dx, sum c ia dy,
+      // sum (F2 ia - F1 ib), c = ia F1 + ib F2 (F = 2f as stored)
+      const real a1 = qj[2 * v], a2 = qj[2 * v + 1], b1 = qi[2 * v], b2 = qi[2 * v + 1];
+      if constexpr (!MIXED) {
+        pA[v][0] = m[8] * a1; pA[v][1] = m[8] * a2; pB[v][0] = m[8] * b1; pB[v][1] = m[8] * b2;
       }
+      pA[v][2] = a1 * m[2] + a2 * m[3]; pA[v][3] = a1 * m[3] + a2 * m[4];
+      pA[v][4] = a1 * m[0] + a2 * m[1];
+      pA[v][5] = a1 * m[5] + a2 * m[6]; pA[v][6] = a1 * m[6] + a2 * m[7];
+      pA[v][7] = a2 * m[0] - a1 * m[1];
+      pB[v][2] = b1 * m[2] + b2 * m[3]; pB[v][3] = b1 * m[3] + b2 * m[4];
+      pB[v][4] = -(b1 * m[0] + b2 * m[1]);
+      pB[v][5] = -(b1 * m[5] + b2 * m[6]); pB[v][6] = -(b1 * m[6] + b2 * m[7]);
+      pB[v][7] = b1 * m[1] - b2 * m[0];
     }
   }
 }
@@ -639,48 +659,39 @@ __device__ __forceinline__ void mutual_block(const MutualArgs& a, int64_t tile, 
       double qjd[QN];
 #pragma unroll
       for (int c = 0; c < QN; ++c) { qj[c] = s_q[c * MU_SUB + b]; qjd[c] = s_qd[c * MU_SUB + b]; }
-      real pA[ND][NA], pB[ND][NA];
-      double lA[ND][2], lB[ND][2];
+      real m[mu_moments<K, MIXED>()];
 #pragma unroll
-      for (int v = 0; v < ND; ++v) {
-#pragma unroll
-        for (int c = 0; c < NA; ++c) { pA[v][c] = 0; pB[v][c] = 0; }
-        lA[v][0] = lA[v][1] = lB[v][0] = lB[v][1] = 0.0;
-      }
+      for (int c = 0; c < mu_moments<K, MIXED>(); ++c) m[c] = 0;
+      double lsum = 0.0;   // mixed Laplace/Stokes: sum of log2 r^2 over the images
       if constexpr (NLOG > 0) {
-        // one log2 per image group of the product of its r^2 (FP32), then FP64
-        // fmas with the FP64 densities
+        // one log2 per image group of the product of its r^2 (FP32)
         int im = 0;
         for (int g = 0; g < a.n_lg; ++g) {
           real P = a.lg_p0[g];
           for (const int ie = a.lg_end[g]; im < ie; ++im) {
             const real dx = (real)(d0x - imx[im]), dy = (real)(d0y - imy[im]);
-            mutual_pair<K, MIXED, ND, real>(dx, dy, qi, qj, pA, pB, P, beta);
+            mutual_image<K, MIXED, real>(dx, dy, m, P, beta);
           }
           // padding sources (far away, zero density) may overflow P; the clamp
           // keeps 0 * log2(P) finite (valid pairs stay below 2^122)
-          const double lgd = (double)__builtin_amdgcn_logf(__builtin_fminf(P, 3.40282347e38f)) - a.lg_e0[g];
-#pragma unroll
-          for (int v = 0; v < ND; ++v)
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-              lA[v][c] = __builtin_fma(qjd[v * NC + c], lgd, lA[v][c]);
-              lB[v][c] = __builtin_fma(qid[v * NC + c], lgd, lB[v][c]);
-            }
+          lsum += (double)__builtin_amdgcn_logf(__builtin_fminf(P, 3.40282347e38f)) - a.lg_e0[g];
         }
       } else {
         real P = 1;
         for (int im = 0; im < a.n_images; ++im) {
           const real dx = (real)(d0x - imx[im]), dy = (real)(d0y - imy[im]);
-          mutual_pair<K, MIXED, ND, real>(dx, dy, qi, qj, pA, pB, P, beta);
+          mutual_image<K, MIXED, real>(dx, dy, m, P, beta);
         }
       }
+      real pA[ND][NA], pB[ND][NA];
+      mutual_combine<K, MIXED, ND, real>(m, qi, qj, pA, pB);
 #pragma unroll
       for (int v = 0; v < ND; ++v) {
 #pragma unroll
         for (int c = 0; c < NA; ++c) {
-          const double ea = c < NLOG ? lA[v][c < 2 ? c : 0] : (double)pA[v][c];
-          const double eb = c < NLOG ? lB[v][c < 2 ? c : 0] : (double)pB[v][c];
+          // log terms with the exact FP64 densities
+          const double ea = c < NLOG ? qjd[v * NC + (c < NC ? c : 0)] * lsum : (double)pA[v][c];
+          const double eb = c < NLOG ? qid[v * NC + (c < NC ? c : 0)] * lsum : (double)pB[v][c];
           accA[v][c] += ea;
           my_acc[(v * NA + c) * MU_SUB + b] += eb;
         }
