@@ -30,8 +30,8 @@ FLOPS_PER_PAIR = {"laplace": 14, "yukawa": 51, "stokes": 30}
 # image of a pair (kernel moments without densities) and per pair (densities
 # times moments for both points, the log2 of the images' r^2 product, the
 # additions into both points' sums)
-FLOPS_MUTUAL_PER_IMAGE = {"laplace": 11, "yukawa": 44, "stokes": 25}
-FLOPS_MUTUAL_PER_PAIR = {"laplace": 15, "yukawa": 12, "stokes": 59}
+FLOPS_MUTUAL_PER_IMAGE = {"laplace": 11, "yukawa": 44, "stokes": 22}
+FLOPS_MUTUAL_PER_PAIR = {"laplace": 15, "yukawa": 12, "stokes": 60}
 TILE = 256    # targets per near-field block (the diagonal tiles are one-sided)
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 

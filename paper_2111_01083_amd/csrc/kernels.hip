@@ -502,12 +502,14 @@ constexpr int MU_SUB = 64;
 //   Laplace: [0] sum ia, [1] sum ib (FP64 mode: [2] sum ln r^2)
 //   Yukawa:  [0] sum K0(x), [1] sum k dx, [2] sum k dy, k = K1(x)/x
 //   Stokes:  [0] sum ia, [1] sum ib, [2] sum ia dx, [3] sum ia dy, [4] sum ib dy,
-//            [5] sum ia^2 dx, [6] sum ia^2 dy, [7] sum ib^2 dx
-//            (FP64 mode: [8] sum ln r^2)
+//            [5] sum ia^2 dx, [6] sum ia^2 dy (FP64 mode: [7] sum ln r^2);
+//            sum ib^2 dx = sum ia - sum ia^2 dx, since ia^2 dx + ib^2 dx = ia
+//            (its absolute error stays at the scale of sum |ia|, the scale of
+//            the outputs it enters)
 // The mixed log terms take the product of r^2 instead (P, one log2 per group).
 template <int K, bool MIXED>
 constexpr int mu_moments() {
-  return (K == PFMM_STOKES ? 8 : (K == PFMM_YUKAWA ? 3 : 2)) + ((!MIXED && K != PFMM_YUKAWA) ? 1 : 0);
+  return (K == PFMM_STOKES ? 7 : (K == PFMM_YUKAWA ? 3 : 2)) + ((!MIXED && K != PFMM_YUKAWA) ? 1 : 0);
 }
 
 template <int K, bool MIXED, typename real>
@@ -535,8 +537,8 @@ __device__ __forceinline__ void mutual_image(real dx, real dy, real* m, real& P,
       const real ia = inv * dx, ib = inv * dy;
       m[0] += ia; m[1] += ib;
       m[2] += ia * dx; m[3] += ia * dy; m[4] += ib * dy;
-      const real ia2 = ia * ia, ib2 = ib * ib;
-      m[5] += ia2 * dx; m[6] += ia2 * dy; m[7] += ib2 * dx;
+      const real ia2 = ia * ia;
+      m[5] += ia2 * dx; m[6] += ia2 * dy;
     }
   }
 }
@@ -560,16 +562,17 @@ __device__ __forceinline__ void mutual_combine(const real* m, const real* qi, co
       // (2..7) = sum c dx, sum c dy, sum c, sum c ia dx, sum c ia dy,
       // sum (F2 ia - F1 ib), c = ia F1 + ib F2 (F = 2f as stored)
       const real a1 = qj[2 * v], a2 = qj[2 * v + 1], b1 = qi[2 * v], b2 = qi[2 * v + 1];
+      const real t7 = m[0] - m[5];   // sum ib^2 dx
       if constexpr (!MIXED) {
-        pA[v][0] = m[8] * a1; pA[v][1] = m[8] * a2; pB[v][0] = m[8] * b1; pB[v][1] = m[8] * b2;
+        pA[v][0] = m[7] * a1; pA[v][1] = m[7] * a2; pB[v][0] = m[7] * b1; pB[v][1] = m[7] * b2;
       }
       pA[v][2] = a1 * m[2] + a2 * m[3]; pA[v][3] = a1 * m[3] + a2 * m[4];
       pA[v][4] = a1 * m[0] + a2 * m[1];
-      pA[v][5] = a1 * m[5] + a2 * m[6]; pA[v][6] = a1 * m[6] + a2 * m[7];
+      pA[v][5] = a1 * m[5] + a2 * m[6]; pA[v][6] = a1 * m[6] + a2 * t7;
       pA[v][7] = a2 * m[0] - a1 * m[1];
       pB[v][2] = b1 * m[2] + b2 * m[3]; pB[v][3] = b1 * m[3] + b2 * m[4];
       pB[v][4] = -(b1 * m[0] + b2 * m[1]);
-      pB[v][5] = -(b1 * m[5] + b2 * m[6]); pB[v][6] = -(b1 * m[6] + b2 * m[7]);
+      pB[v][5] = -(b1 * m[5] + b2 * m[6]); pB[v][6] = -(b1 * m[6] + b2 * t7);
       pB[v][7] = b1 * m[1] - b2 * m[0];
     }
   }
