@@ -499,17 +499,18 @@ constexpr int MU_SUB = 64;
 // loop only accumulates density-free moments of the kernel, and the densities
 // multiply them once per pair. Moments (dx, dy = r under one image,
 // inv = 1/r^2, ia = dx inv, ib = dy inv):
-//   Laplace: [0] sum ia, [1] sum ib (FP64 mode: [2] sum ln r^2)
+//   Laplace: [0] sum ia, [1] sum ib
 //   Yukawa:  [0] sum K0(x), [1] sum k dx, [2] sum k dy, k = K1(x)/x
 //   Stokes:  [0] sum ia, [1] sum ib, [2] sum ia dx, [3] sum ia dy, [4] sum ib dy,
-//            [5] sum ia^2 dx, [6] sum ia^2 dy (FP64 mode: [7] sum ln r^2);
+//            [5] sum ia^2 dx, [6] sum ia^2 dy;
 //            sum ib^2 dx = sum ia - sum ia^2 dx, since ia^2 dx + ib^2 dx = ia
 //            (its absolute error stays at the scale of sum |ia|, the scale of
 //            the outputs it enters)
-// The mixed log terms take the product of r^2 instead (P, one log2 per group).
+// The log terms take the product P of r^2 over the images instead: one log
+// per pair (FP64) or per image group (mixed, log2 of an FP32 product).
 template <int K, bool MIXED>
 constexpr int mu_moments() {
-  return (K == PFMM_STOKES ? 7 : (K == PFMM_YUKAWA ? 3 : 2)) + ((!MIXED && K != PFMM_YUKAWA) ? 1 : 0);
+  return K == PFMM_STOKES ? 7 : (K == PFMM_YUKAWA ? 3 : 2);
 }
 
 template <int K, bool MIXED, typename real>
@@ -528,7 +529,7 @@ __device__ __forceinline__ void mutual_image(real dx, real dy, real* m, real& P,
       inv = __builtin_amdgcn_rcpf(r2);
     } else {
       const real r2 = dx * dx + dy * dy;
-      m[mu_moments<K, MIXED>() - 1] += log(r2);
+      P *= r2;
       inv = 1.0 / r2;
     }
     if constexpr (K == PFMM_LAPLACE) {
@@ -545,7 +546,7 @@ __device__ __forceinline__ void mutual_image(real dx, real dy, real* m, real& P,
 
 // pair partials of both points from the moments: pA for i (source j, force
 // f_j), pB for j (source i, displacement -r: odd moments change sign).
-// Mixed Laplace/Stokes log terms [0, NC) are left to the caller.
+// Laplace/Stokes log terms [0, NC) are left to the caller.
 template <int K, bool MIXED, int ND, typename real>
 __device__ __forceinline__ void mutual_combine(const real* m, const real* qi, const real* qj,
                                                real (*pA)[NAcc<K>::v], real (*pB)[NAcc<K>::v]) {
@@ -555,7 +556,6 @@ __device__ __forceinline__ void mutual_combine(const real* m, const real* qi, co
       pA[v][0] = qj[v] * m[0]; pA[v][1] = qj[v] * m[1]; pA[v][2] = qj[v] * m[2];
       pB[v][0] = qi[v] * m[0]; pB[v][1] = -qi[v] * m[1]; pB[v][2] = -qi[v] * m[2];
     } else if constexpr (K == PFMM_LAPLACE) {
-      if constexpr (!MIXED) { pA[v][0] = qj[v] * m[2]; pB[v][0] = qi[v] * m[2]; }
       pA[v][1] = qj[v] * m[0]; pA[v][2] = qj[v] * m[1];
       pB[v][1] = -qi[v] * m[0]; pB[v][2] = -qi[v] * m[1];
     } else {
@@ -563,9 +563,6 @@ __device__ __forceinline__ void mutual_combine(const real* m, const real* qi, co
       // sum (F2 ia - F1 ib), c = ia F1 + ib F2 (F = 2f as stored)
       const real a1 = qj[2 * v], a2 = qj[2 * v + 1], b1 = qi[2 * v], b2 = qi[2 * v + 1];
       const real t7 = m[0] - m[5];   // sum ib^2 dx
-      if constexpr (!MIXED) {
-        pA[v][0] = m[7] * a1; pA[v][1] = m[7] * a2; pB[v][0] = m[7] * b1; pB[v][1] = m[7] * b2;
-      }
       pA[v][2] = a1 * m[2] + a2 * m[3]; pA[v][3] = a1 * m[3] + a2 * m[4];
       pA[v][4] = a1 * m[0] + a2 * m[1];
       pA[v][5] = a1 * m[5] + a2 * m[6]; pA[v][6] = a1 * m[6] + a2 * t7;
@@ -597,7 +594,7 @@ __device__ __forceinline__ void mutual_block(const MutualArgs& a, int64_t tile, 
   constexpr int QN = ND * NC;
   constexpr int NA = NAcc<K>::v;
   constexpr int NO = (K == PFMM_STOKES) ? 6 : 3;
-  constexpr int NLOG = (MIXED && K != PFMM_YUKAWA) ? NC : 0;   // accumulators kept in FP64 pair by pair
+  constexpr int NLOG = (K != PFMM_YUKAWA) ? NC : 0;   // log terms: FP64 density times the pair's log sum
   constexpr int NW = MU_BLOCK / 64;
   double* s_x = (double*)smem;
   double* s_y = s_x + MU_SUB;
@@ -665,8 +662,16 @@ __device__ __forceinline__ void mutual_block(const MutualArgs& a, int64_t tile, 
       real m[mu_moments<K, MIXED>()];
 #pragma unroll
       for (int c = 0; c < mu_moments<K, MIXED>(); ++c) m[c] = 0;
-      double lsum = 0.0;   // mixed Laplace/Stokes: sum of log2 r^2 over the images
-      if constexpr (NLOG > 0) {
+      double lsum = 0.0;   // Laplace/Stokes: sum of log r^2 (mixed: log2) over the images
+      if constexpr (NLOG > 0 && !MIXED) {
+        // FP64: one log of the product of all images' r^2 (no range issue)
+        real P = 1;
+        for (int im = 0; im < a.n_images; ++im) {
+          const real dx = d0x - imx[im], dy = d0y - imy[im];
+          mutual_image<K, MIXED, real>(dx, dy, m, P, beta);
+        }
+        lsum = log(fmin(P, 1.0e300));
+      } else if constexpr (NLOG > 0) {
         // one log2 per image group of the product of its r^2 (FP32)
         int im = 0;
         for (int g = 0; g < a.n_lg; ++g) {
