@@ -142,6 +142,17 @@ int pfmm_plan(int kernel, const double* e1, const double* e2, double tol, const 
 
 }  // extern "C"
 
+// Near-field cutoff of the screened (Yukawa) kernel: a pair beyond r_c with
+// e^{-beta r_c} = eps / 30 is dropped. For sources of uniform density the
+// dropped part of a potential is about 1.25 e^{-beta r_c} of its norm
+// (K0(x) ~ sqrt(pi / 2x) e^{-x}), i.e. 0.04 eps; the far field is truncated
+// at eps the same way. Other kernels: no cutoff.
+static double near_rcut2(const pfmm_plan_s* p) {
+  if (p->kernel != PFMM_YUKAWA || !(p->beta > 0)) return 1.0e308;
+  const double rc = std::log(30.0 / p->eps) / p->beta;
+  return rc * rc;
+}
+
 // image groups of the symmetric mixed near field (one log2 per group)
 static void set_log_groups(MutualArgs& m, const Geometry& g) {
   m.n_lg = g.n_lg;
@@ -325,6 +336,7 @@ static NearArgs cell_near_args(const CellRun& r) {
   na.self = p->self_exclude;
   na.beta = p->beta;
   na.r2min = R2MIN_F32;
+  na.rcut2 = near_rcut2(p);
   na.qsum = L.qsum ? D(L.qsum) : nullptr;
   na.qsum_stride = p->n_dens * (p->kernel == PFMM_STOKES ? 2 : 1);
   na.part = D(L.near_part);
@@ -448,6 +460,7 @@ int pfmm::eval_core(pfmm_plan_t p, int64_t ns, const double* src_xy, const doubl
     ma.n_images = g.n_images;
     ma.imx = p->d_tab + p->tab_img + 2 * g.n_images; ma.imy = ma.imx + g.n_images;
     ma.sigma = g.sigma;
+    ma.rcut2 = near_rcut2(p);
     set_log_groups(ma, g);
     ma.n = ns; ma.chunk_len = r.L.mu_chunk;
     ma.x = nd.sx; ma.y = nd.sy; ma.q64 = nd.q64; ma.q32 = nd.q32;
@@ -718,7 +731,7 @@ static int batch_build(pfmm_batch_s* b, int64_t split, int grid_mult) {
       MutualArgs& m = bc.margs;
       m.n_images = g.n_images;
       m.imx = b->plans[c]->d_tab + b->plans[c]->tab_img + 2 * g.n_images; m.imy = m.imx + g.n_images;
-      m.sigma = g.sigma; set_log_groups(m, g); m.n = r.ns; m.chunk_len = L.mu_chunk; m.beta = b->plans[c]->beta;
+      m.sigma = g.sigma; m.rcut2 = near_rcut2(b->plans[c]); set_log_groups(m, g); m.n = r.ns; m.chunk_len = L.mu_chunk; m.beta = b->plans[c]->beta;
       bc.n_chunks = (int)((r.ns + L.mu_chunk - 1) / L.mu_chunk);
       bc.o_qb64 = B + L.qb64; bc.o_qb32 = mixed ? B + L.qb32 : 0;
       task += bc.n_tiles;

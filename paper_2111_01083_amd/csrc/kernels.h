@@ -58,6 +58,9 @@ struct NearArgs {
   const int* perm;                       // binned position -> original target index
   int self;                              // targets are the sources (same indices)
   double beta, r2min;
+  double rcut2;                          // screened kernel: an image whose source tile lies
+                                         // farther than sqrt(rcut2) from all targets of the
+                                         // block is skipped (scaled units; huge: never)
   const double *imx, *imy;               // image shifts (device, n_images each)
   const double* qsum;                    // mixed Laplace/Stokes: per split, sum of the
                                          // densities [split][qsum_stride] (NULL: no log shift)
@@ -137,6 +140,7 @@ struct MutualArgs {
   int n_images;
   const double *imx, *imy;               // image shifts times sigma (device, n_images each)
   double sigma;                          // coordinate scale (mixed Laplace/Stokes)
+  double rcut2;                          // screened kernel cutoff (as in NearArgs)
   int n_lg;                              // log groups of the images (mixed Laplace/Stokes)
   int lg_end[MAX_IMAGES];                // one past the last image of each group
   float lg_p0[MAX_IMAGES];               // 2^e0: start of each group's r^2 product

@@ -228,6 +228,32 @@ template <> struct NAcc<PFMM_STOKES> { static constexpr int v = 8; };
 
 struct alignas(16) SrcPt { double x, y; };
 
+// Bounding boxes for the screened-kernel cutoff: min/max over a wavefront
+// (every lane gets the result) and the squared gap between two boxes.
+__device__ __forceinline__ void wave_box(double& x0, double& x1, double& y0, double& y1) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    x0 = fmin(x0, __shfl_xor(x0, o)); x1 = fmax(x1, __shfl_xor(x1, o));
+    y0 = fmin(y0, __shfl_xor(y0, o)); y1 = fmax(y1, __shfl_xor(y1, o));
+  }
+}
+
+__device__ __forceinline__ double box_gap2(double ax0, double ax1, double ay0, double ay1, double bx0,
+                                           double bx1, double by0, double by1) {
+  const double gx = fmax(0.0, fmax(bx0 - ax1, ax0 - bx1));
+  const double gy = fmax(0.0, fmax(by0 - ay1, ay0 - by1));
+  return gx * gx + gy * gy;
+}
+constexpr double BOX_EMPTY = 1.0e300;   // min/max start of an empty box
+
+// a wavefront-uniform double moved to scalar registers
+__device__ __forceinline__ double uniform_d(double v) {
+  const unsigned long long b = __double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 template <int K, bool MIXED, int ND, int NA, typename real>
 __device__ __forceinline__ void near_pair(real dx, real dy, const real* qv, const double* qd, real (&p)[ND][NA],
                                           double (&acc)[ND][NA], real beta, real r2min) {
@@ -370,9 +396,27 @@ __device__ __forceinline__ void near_block(const NearArgs& a, int64_t tile, int6
   const real beta = (real)a.beta;
   const real r2min = (real)a.r2min;
   const real qscale = (K == PFMM_STOKES) ? (real)2 : (real)1;
+  // screened kernel: boxes of the block's targets and of each source tile
+  // (scaled coordinates); an image that keeps the tile beyond the cutoff
+  // from every target is skipped (uniform over the block)
+  const bool cut = K == PFMM_YUKAWA && a.rcut2 < 1.0e300;
+  __shared__ double s_box[2][NEAR_BLOCK / 64][4];
+  if (cut) {
+    double x0 = tx * a.geo.sigma, x1 = x0, y0 = ty * a.geo.sigma, y1 = y0;
+    wave_box(x0, x1, y0, y1);
+    if ((tid & 63) == 0) { s_box[0][tid >> 6][0] = x0; s_box[0][tid >> 6][1] = x1; s_box[0][tid >> 6][2] = y0; s_box[0][tid >> 6][3] = y1; }
+  }
   for (int64_t base = s0; base < s1; base += NEAR_TILE) {
     const int nt = (int)min((int64_t)NEAR_TILE, s1 - base);
     __syncthreads();
+    if (cut) {
+      const bool ok = tid < nt;
+      const int64_t j = base + (ok ? tid : 0);
+      double x0 = ok ? a.sx[j] * a.geo.sigma : BOX_EMPTY, x1 = ok ? x0 : -BOX_EMPTY;
+      double y0 = ok ? a.sy[j] * a.geo.sigma : BOX_EMPTY, y1 = ok ? y0 : -BOX_EMPTY;
+      wave_box(x0, x1, y0, y1);
+      if ((tid & 63) == 0) { s_box[1][tid >> 6][0] = x0; s_box[1][tid >> 6][1] = x1; s_box[1][tid >> 6][2] = y0; s_box[1][tid >> 6][3] = y1; }
+    }
     if (tid < nt) {
       const int64_t j = base + tid;
       s_pt[tid] = SrcPt{a.sx[j] * a.geo.sigma, a.sy[j] * a.geo.sigma};   // exact scaling
@@ -391,7 +435,21 @@ __device__ __forceinline__ void near_block(const NearArgs& a, int64_t tile, int6
       }
     }
     __syncthreads();
+    double tb[4] = {BOX_EMPTY, -BOX_EMPTY, BOX_EMPTY, -BOX_EMPTY}, sb[4] = {BOX_EMPTY, -BOX_EMPTY, BOX_EMPTY, -BOX_EMPTY};
+    if (cut) {
+#pragma unroll
+      for (int w = 0; w < NEAR_BLOCK / 64; ++w) {
+        tb[0] = fmin(tb[0], s_box[0][w][0]); tb[1] = fmax(tb[1], s_box[0][w][1]);
+        tb[2] = fmin(tb[2], s_box[0][w][2]); tb[3] = fmax(tb[3], s_box[0][w][3]);
+        sb[0] = fmin(sb[0], s_box[1][w][0]); sb[1] = fmax(sb[1], s_box[1][w][1]);
+        sb[2] = fmin(sb[2], s_box[1][w][2]); sb[3] = fmax(sb[3], s_box[1][w][3]);
+      }
+    }
     for (int im = 0; im < a.geo.n_images; ++im) {
+      if (cut) {
+        const double lx = as_const(a.imx)[im] * a.geo.sigma, ly = as_const(a.imy)[im] * a.geo.sigma;
+        if (box_gap2(tb[0], tb[1], tb[2], tb[3], sb[0] + lx, sb[1] + lx, sb[2] + ly, sb[3] + ly) > a.rcut2) continue;
+      }
       const double txi = (tx - as_const(a.imx)[im]) * a.geo.sigma, tyi = (ty - as_const(a.imy)[im]) * a.geo.sigma;
       for (int jb = 0; jb < nt; jb += NEAR_FLUSH) {
         real p[ND][NA];
@@ -615,6 +673,16 @@ __device__ __forceinline__ void mutual_block(const MutualArgs& a, int64_t tile, 
   const size_t qoff = (size_t)a.dens0 * NC * a.n;
   // an inactive lane sits far from every point with zero density
   const double tx = act ? a.x[k] * sg : 1.0e4, ty = act ? a.y[k] * sg : 1.0e4;
+  // screened kernel: box of this wavefront's points; per source sub-tile an
+  // image mask (images whose shifted sub-tile comes within the cutoff)
+  const bool cut = K == PFMM_YUKAWA && a.rcut2 < 1.0e300;
+  __shared__ double s_box[4];
+  double wx0 = act ? tx : BOX_EMPTY, wx1 = act ? tx : -BOX_EMPTY;
+  double wy0 = act ? ty : BOX_EMPTY, wy1 = act ? ty : -BOX_EMPTY;
+  if (cut) {
+    wave_box(wx0, wx1, wy0, wy1);
+    wx0 = uniform_d(wx0); wx1 = uniform_d(wx1); wy0 = uniform_d(wy0); wy1 = uniform_d(wy1);
+  }
   real qi[QN];
   double qid[QN];
 #pragma unroll
@@ -647,12 +715,27 @@ __device__ __forceinline__ void mutual_block(const MutualArgs& a, int64_t tile, 
         if constexpr (MIXED) s_q[c * MU_SUB + tid] = ok ? (real)(qscale * a.q32[qoff + (size_t)c * a.n + j]) : (real)0;
         else s_q[c * MU_SUB + tid] = qd;
       }
+      if (cut) {   // MU_SUB = one wavefront
+        double x0 = ok ? s_x[tid] : BOX_EMPTY, x1 = ok ? s_x[tid] : -BOX_EMPTY;
+        double y0 = ok ? s_y[tid] : BOX_EMPTY, y1 = ok ? s_y[tid] : -BOX_EMPTY;
+        wave_box(x0, x1, y0, y1);
+        if (tid == 0) { s_box[0] = x0; s_box[1] = x1; s_box[2] = y0; s_box[3] = y1; }
+      }
     }
     double* my_acc = s_acc + (size_t)wv * ND * NA * MU_SUB;
 #pragma unroll
     for (int c = 0; c < ND * NA; ++c) my_acc[c * MU_SUB + lane] = 0.0;
     __syncthreads();
-    for (int st = 0; st < MU_SUB; ++st) {
+    unsigned mask = ~0u;
+    if (cut) {
+      const double bx0 = s_box[0], bx1 = s_box[1], by0 = s_box[2], by1 = s_box[3];
+      mask = 0;
+      for (int im = 0; im < a.n_images; ++im)
+        if (box_gap2(wx0, wx1, wy0, wy1, bx0 + imx[im], bx1 + imx[im], by0 + imy[im], by1 + imy[im]) <= a.rcut2)
+          mask |= 1u << im;
+      mask = __builtin_amdgcn_readfirstlane(mask);
+    }
+    for (int st = 0; st < MU_SUB && mask; ++st) {
       const int b = (lane + st) & (MU_SUB - 1);
       const double d0x = tx - s_x[b], d0y = ty - s_y[b];
       real qj[QN];
@@ -687,6 +770,7 @@ __device__ __forceinline__ void mutual_block(const MutualArgs& a, int64_t tile, 
       } else {
         real P = 1;
         for (int im = 0; im < a.n_images; ++im) {
+          if (!((mask >> im) & 1u)) continue;
           const real dx = (real)(d0x - imx[im]), dy = (real)(d0y - imy[im]);
           mutual_image<K, MIXED, real>(dx, dy, m, P, beta);
         }
