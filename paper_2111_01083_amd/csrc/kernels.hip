@@ -19,6 +19,7 @@ namespace pfmm {
 // read-only tables (plan tables): loads through the constant address space
 // with a uniform index become scalar loads
 typedef const __attribute__((address_space(4))) double cdouble;
+typedef const __attribute__((address_space(4))) BatchCell cBatchCell;
 __device__ __forceinline__ const cdouble* as_const(const double* p) { return (const cdouble*)p; }
 
 __global__ void prep_points_kernel(PrepArgs a) {
@@ -602,33 +603,51 @@ __device__ __forceinline__ void mutual_image(real dx, real dy, real* m, real& P,
   }
 }
 
-// pair partials of both points from the moments: pA for i (source j, force
-// f_j), pB for j (source i, displacement -r: odd moments change sign).
-// Laplace/Stokes log terms [0, NC) are left to the caller.
-template <int K, bool MIXED, int ND, typename real>
-__device__ __forceinline__ void mutual_combine(const real* m, const real* qi, const real* qj,
-                                               real (*pA)[NAcc<K>::v], real (*pB)[NAcc<K>::v]) {
+// Adds a pair's contributions to both points' FP64 sums: pA for i (source j,
+// densities qj), pB for j (source i, displacement -r: odd moments change
+// sign). The moments are converted to FP64 once and multiplied by the FP64
+// densities; lsum is the pair's log sum (Laplace/Stokes).
+template <int K, int ND, typename real>
+__device__ __forceinline__ void mutual_accumulate(const real* m, double lsum, const double* qi, const double* qj,
+                                                  double (*pA)[NAcc<K>::v], double* pB, int pb_stride) {
+  constexpr int NA = NAcc<K>::v;
+  constexpr int NM = K == PFMM_STOKES ? 7 : (K == PFMM_YUKAWA ? 3 : 2);
+  double d[NM];
+#pragma unroll
+  for (int c = 0; c < NM; ++c) d[c] = (double)m[c];
 #pragma unroll
   for (int v = 0; v < ND; ++v) {
+    double* b = pB + (size_t)v * NA * pb_stride;
     if constexpr (K == PFMM_YUKAWA) {
-      pA[v][0] = qj[v] * m[0]; pA[v][1] = qj[v] * m[1]; pA[v][2] = qj[v] * m[2];
-      pB[v][0] = qi[v] * m[0]; pB[v][1] = -qi[v] * m[1]; pB[v][2] = -qi[v] * m[2];
+      pA[v][0] = fma(qj[v], d[0], pA[v][0]); pA[v][1] = fma(qj[v], d[1], pA[v][1]);
+      pA[v][2] = fma(qj[v], d[2], pA[v][2]);
+      b[0] = fma(qi[v], d[0], b[0]); b[pb_stride] = fma(-qi[v], d[1], b[pb_stride]);
+      b[2 * pb_stride] = fma(-qi[v], d[2], b[2 * pb_stride]);
     } else if constexpr (K == PFMM_LAPLACE) {
-      pA[v][1] = qj[v] * m[0]; pA[v][2] = qj[v] * m[1];
-      pB[v][1] = -qi[v] * m[0]; pB[v][2] = -qi[v] * m[1];
+      pA[v][0] = fma(qj[v], lsum, pA[v][0]); pA[v][1] = fma(qj[v], d[0], pA[v][1]);
+      pA[v][2] = fma(qj[v], d[1], pA[v][2]);
+      b[0] = fma(qi[v], lsum, b[0]); b[pb_stride] = fma(-qi[v], d[0], b[pb_stride]);
+      b[2 * pb_stride] = fma(-qi[v], d[1], b[2 * pb_stride]);
     } else {
-      // (2..7) = sum c dx, sum c dy, sum c, sum c ia dx, sum c ia dy,
-      // sum (F2 ia - F1 ib), c = ia F1 + ib F2 (F = 2f as stored)
-      const real a1 = qj[2 * v], a2 = qj[2 * v + 1], b1 = qi[2 * v], b2 = qi[2 * v + 1];
-      const real t7 = m[0] - m[5];   // sum ib^2 dx
-      pA[v][2] = a1 * m[2] + a2 * m[3]; pA[v][3] = a1 * m[3] + a2 * m[4];
-      pA[v][4] = a1 * m[0] + a2 * m[1];
-      pA[v][5] = a1 * m[5] + a2 * m[6]; pA[v][6] = a1 * m[6] + a2 * t7;
-      pA[v][7] = a2 * m[0] - a1 * m[1];
-      pB[v][2] = b1 * m[2] + b2 * m[3]; pB[v][3] = b1 * m[3] + b2 * m[4];
-      pB[v][4] = -(b1 * m[0] + b2 * m[1]);
-      pB[v][5] = -(b1 * m[5] + b2 * m[6]); pB[v][6] = -(b1 * m[6] + b2 * t7);
-      pB[v][7] = b1 * m[1] - b2 * m[0];
+      // (0, 1) = sum lg F; (2..7) = sum c dx, sum c dy, sum c, sum c ia dx,
+      // sum c ia dy, sum (F2 ia - F1 ib), c = ia F1 + ib F2 (F = 2f as stored)
+      const double a1 = qj[2 * v], a2 = qj[2 * v + 1], b1 = qi[2 * v], b2 = qi[2 * v + 1];
+      const double t7 = d[0] - d[5];   // sum ib^2 dx
+      pA[v][0] = fma(a1, lsum, pA[v][0]); pA[v][1] = fma(a2, lsum, pA[v][1]);
+      pA[v][2] = fma(a1, d[2], fma(a2, d[3], pA[v][2]));
+      pA[v][3] = fma(a1, d[3], fma(a2, d[4], pA[v][3]));
+      pA[v][4] = fma(a1, d[0], fma(a2, d[1], pA[v][4]));
+      pA[v][5] = fma(a1, d[5], fma(a2, d[6], pA[v][5]));
+      pA[v][6] = fma(a1, d[6], fma(a2, t7, pA[v][6]));
+      pA[v][7] = fma(a2, d[0], fma(-a1, d[1], pA[v][7]));
+      const int s = pb_stride;
+      b[0] = fma(b1, lsum, b[0]); b[s] = fma(b2, lsum, b[s]);
+      b[2 * s] = fma(b1, d[2], fma(b2, d[3], b[2 * s]));
+      b[3 * s] = fma(b1, d[3], fma(b2, d[4], b[3 * s]));
+      b[4 * s] = fma(-b1, d[0], fma(-b2, d[1], b[4 * s]));
+      b[5 * s] = fma(-b1, d[5], fma(-b2, d[6], b[5 * s]));
+      b[6 * s] = fma(-b1, d[6], fma(-b2, t7, b[6 * s]));
+      b[7 * s] = fma(b1, d[1], fma(-b2, d[0], b[7 * s]));
     }
   }
 }
@@ -638,15 +657,23 @@ template <int K, bool MIXED, int ND>
 constexpr size_t mutual_lds_bytes() {
   using real = typename std::conditional<MIXED, float, double>::type;
   constexpr int QN = ND * ((K == PFMM_STOKES) ? 2 : 1);
-  return 8 * (2 * MU_SUB) + 8 * (size_t)QN * MU_SUB + sizeof(real) * (size_t)QN * MU_SUB +
-         8 * (size_t)(MU_BLOCK / 64) * ND * NAcc<K>::v * MU_SUB;
+  return 8 * (2 * MU_SUB) + 8 * (size_t)QN * MU_SUB + 8 * (size_t)(MU_BLOCK / 64) * ND * NAcc<K>::v * MU_SUB;
 }
 
 // One (tile, chunk) task of the symmetric near field for densities
 // [a.dens0, a.dens0 + ND); smem: mutual_lds_bytes<K, MIXED, ND>() bytes,
 // 16-byte aligned. Every thread of the block must call it.
-template <int K, bool MIXED, int ND>
-__device__ __forceinline__ void mutual_block(const MutualArgs& a, int64_t tile, int64_t chunk, char* smem) {
+// the per-task arrays of a symmetric near-field task (the rest of the
+// arguments come from MutualArgs, in kernel arguments or in a batch record
+// read through the constant address space)
+struct MuTask {
+  const double *x, *y, *q64;
+  double* acc;
+  int dens0;
+};
+
+template <int K, bool MIXED, int ND, typename MA>
+__device__ __forceinline__ void mutual_block(const MA& a, const MuTask& p, int64_t tile, int64_t chunk, char* smem) {
   using real = typename std::conditional<MIXED, float, double>::type;
   constexpr int NC = (K == PFMM_STOKES) ? 2 : 1;
   constexpr int QN = ND * NC;
@@ -658,7 +685,6 @@ __device__ __forceinline__ void mutual_block(const MutualArgs& a, int64_t tile, 
   double* s_y = s_x + MU_SUB;
   double* s_qd = s_y + MU_SUB;                         // [QN][MU_SUB]
   double* s_acc = s_qd + QN * MU_SUB;                  // [NW][ND*NA][MU_SUB]
-  real* s_q = (real*)(s_acc + NW * ND * NA * MU_SUB);  // [QN][MU_SUB]
 
   const int64_t a0 = tile * MU_BLOCK;
   const int64_t a_end = min(a0 + (int64_t)MU_BLOCK, a.n);
@@ -670,9 +696,9 @@ __device__ __forceinline__ void mutual_block(const MutualArgs& a, int64_t tile, 
   const bool act = k < a.n;
   const double sg = a.sigma;
   const double qscale = (K == PFMM_STOKES) ? 2.0 : 1.0;
-  const size_t qoff = (size_t)a.dens0 * NC * a.n;
+  const size_t qoff = (size_t)p.dens0 * NC * a.n;
   // an inactive lane sits far from every point with zero density
-  const double tx = act ? a.x[k] * sg : 1.0e4, ty = act ? a.y[k] * sg : 1.0e4;
+  const double tx = act ? p.x[k] * sg : 1.0e4, ty = act ? p.y[k] * sg : 1.0e4;
   // screened kernel: box of this wavefront's points; per source sub-tile an
   // image mask (images whose shifted sub-tile comes within the cutoff)
   const bool cut = K == PFMM_YUKAWA && a.rcut2 < 1.0e300;
@@ -683,14 +709,9 @@ __device__ __forceinline__ void mutual_block(const MutualArgs& a, int64_t tile, 
     wave_box(wx0, wx1, wy0, wy1);
     wx0 = uniform_d(wx0); wx1 = uniform_d(wx1); wy0 = uniform_d(wy0); wy1 = uniform_d(wy1);
   }
-  real qi[QN];
   double qid[QN];
 #pragma unroll
-  for (int c = 0; c < QN; ++c) {
-    qid[c] = act ? qscale * a.q64[qoff + (size_t)c * a.n + k] : 0.0;
-    if constexpr (MIXED) qi[c] = act ? (real)(qscale * a.q32[qoff + (size_t)c * a.n + k]) : (real)0;
-    else qi[c] = qid[c];
-  }
+  for (int c = 0; c < QN; ++c) qid[c] = act ? qscale * p.q64[qoff + (size_t)c * a.n + k] : 0.0;
   const real beta = (real)a.beta;
   const cdouble* imx = as_const(a.imx);
   const cdouble* imy = as_const(a.imy);
@@ -706,14 +727,11 @@ __device__ __forceinline__ void mutual_block(const MutualArgs& a, int64_t tile, 
     if (tid < MU_SUB) {
       const bool ok = tid < nsb;
       const int64_t j = sb + tid;
-      s_x[tid] = ok ? a.x[j] * sg : -1.0e4;               // padding: far away, zero density
-      s_y[tid] = ok ? a.y[j] * sg : -1.0e4;
+      s_x[tid] = ok ? p.x[j] * sg : -1.0e4;               // padding: far away, zero density
+      s_y[tid] = ok ? p.y[j] * sg : -1.0e4;
 #pragma unroll
       for (int c = 0; c < QN; ++c) {
-        const double qd = ok ? qscale * a.q64[qoff + (size_t)c * a.n + j] : 0.0;
-        s_qd[c * MU_SUB + tid] = qd;
-        if constexpr (MIXED) s_q[c * MU_SUB + tid] = ok ? (real)(qscale * a.q32[qoff + (size_t)c * a.n + j]) : (real)0;
-        else s_q[c * MU_SUB + tid] = qd;
+        s_qd[c * MU_SUB + tid] = ok ? qscale * p.q64[qoff + (size_t)c * a.n + j] : 0.0;
       }
       if (cut) {   // MU_SUB = one wavefront
         double x0 = ok ? s_x[tid] : BOX_EMPTY, x1 = ok ? s_x[tid] : -BOX_EMPTY;
@@ -738,10 +756,9 @@ __device__ __forceinline__ void mutual_block(const MutualArgs& a, int64_t tile, 
     for (int st = 0; st < MU_SUB && mask; ++st) {
       const int b = (lane + st) & (MU_SUB - 1);
       const double d0x = tx - s_x[b], d0y = ty - s_y[b];
-      real qj[QN];
       double qjd[QN];
 #pragma unroll
-      for (int c = 0; c < QN; ++c) { qj[c] = s_q[c * MU_SUB + b]; qjd[c] = s_qd[c * MU_SUB + b]; }
+      for (int c = 0; c < QN; ++c) qjd[c] = s_qd[c * MU_SUB + b];
       real m[mu_moments<K, MIXED>()];
 #pragma unroll
       for (int c = 0; c < mu_moments<K, MIXED>(); ++c) m[c] = 0;
@@ -775,19 +792,7 @@ __device__ __forceinline__ void mutual_block(const MutualArgs& a, int64_t tile, 
           mutual_image<K, MIXED, real>(dx, dy, m, P, beta);
         }
       }
-      real pA[ND][NA], pB[ND][NA];
-      mutual_combine<K, MIXED, ND, real>(m, qi, qj, pA, pB);
-#pragma unroll
-      for (int v = 0; v < ND; ++v) {
-#pragma unroll
-        for (int c = 0; c < NA; ++c) {
-          // log terms with the exact FP64 densities
-          const double ea = c < NLOG ? qjd[v * NC + (c < NC ? c : 0)] * lsum : (double)pA[v][c];
-          const double eb = c < NLOG ? qid[v * NC + (c < NC ? c : 0)] * lsum : (double)pB[v][c];
-          accA[v][c] += ea;
-          my_acc[(v * NA + c) * MU_SUB + b] += eb;
-        }
-      }
+      mutual_accumulate<K, ND, real>(m, lsum, qid, qjd, accA, my_acc + b, MU_SUB);
     }
     __syncthreads();
     if (tid < nsb) {
@@ -804,7 +809,7 @@ __device__ __forceinline__ void mutual_block(const MutualArgs& a, int64_t tile, 
         near_outputs<K, MIXED>(A, o, a.beta, sg);
 #pragma unroll
         for (int c = 0; c < NO; ++c)
-          unsafeAtomicAdd(&a.acc[((size_t)(a.dens0 + v) * NO + c) * a.n + sb + tid], o[c]);
+          unsafeAtomicAdd(&p.acc[((size_t)(p.dens0 + v) * NO + c) * a.n + sb + tid], o[c]);
       }
     }
   }
@@ -814,15 +819,19 @@ __device__ __forceinline__ void mutual_block(const MutualArgs& a, int64_t tile, 
       double o[NO];
       near_outputs<K, MIXED>(accA[v], o, a.beta, sg);
 #pragma unroll
-      for (int c = 0; c < NO; ++c) unsafeAtomicAdd(&a.acc[((size_t)(a.dens0 + v) * NO + c) * a.n + k], o[c]);
+      for (int c = 0; c < NO; ++c) unsafeAtomicAdd(&p.acc[((size_t)(p.dens0 + v) * NO + c) * a.n + k], o[c]);
     }
   }
 }
 
 template <int K, bool MIXED, int ND>
-__global__ __launch_bounds__(MU_BLOCK) void near_mutual_kernel(MutualArgs a) {
+// mixed: at most 6 waves per SIMD, which lets the compiler keep the K0/K1
+// polynomial constants in registers instead of rematerializing them per image
+__global__ __launch_bounds__(MU_BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 4 : 1, MIXED ? 6 : 8)))
+void near_mutual_kernel(MutualArgs a) {
   __shared__ __align__(16) char smem[mutual_lds_bytes<K, MIXED, ND>()];
-  mutual_block<K, MIXED, ND>(a, blockIdx.x, blockIdx.y, smem);
+  const MuTask p{a.x, a.y, a.q64, a.acc, a.dens0};
+  mutual_block<K, MIXED, ND>(a, p, blockIdx.x, blockIdx.y, smem);
 }
 
 // densities per pass of the symmetric kernel (register budget)
@@ -898,14 +907,12 @@ __device__ __forceinline__ void batch_near_task(const BatchCell& r, char* ws, lo
 
 // densities [d0, d1) in groups of ND
 template <int K, bool MIXED, int ND>
-__device__ __forceinline__ void batch_mutual_task(const BatchCell& r, char* ws, long long local, int d0, int d1,
+__device__ __forceinline__ void batch_mutual_task(const cBatchCell& r, char* ws, long long local, int d0, int d1,
                                                   char* smem) {
   const int64_t tile = local % r.n_tiles, chunk = local / r.n_tiles;
-  MutualArgs m = r.margs;
-  m.x = (const double*)(ws + r.o_tx); m.y = (const double*)(ws + r.o_ty);
-  m.q64 = (const double*)(ws + r.o_qb64); m.q32 = (const float*)(ws + r.o_qb32);
-  m.acc = (double*)(ws + r.o_part);
-  for (int v = d0; v + ND <= d1; v += ND) { m.dens0 = v; mutual_block<K, MIXED, ND>(m, tile, chunk, smem); }
+  MuTask p{(const double*)(ws + r.o_tx), (const double*)(ws + r.o_ty), (const double*)(ws + r.o_qb64),
+           (double*)(ws + r.o_part), 0};
+  for (int v = d0; v + ND <= d1; v += ND) { p.dens0 = v; mutual_block<K, MIXED, ND>(r.margs, p, tile, chunk, smem); }
 }
 
 // one launch per kernel type and phase (phase 0: one-sided and diagonal
@@ -921,13 +928,17 @@ __global__ __launch_bounds__(NEAR_BLOCK) void near_batch_kernel(BatchNearArgs b)
     __syncthreads();
     if (threadIdx.x == 0) s_task = (long long)atomicAdd(b.counter, 1ULL);
     __syncthreads();
-    const long long t = s_task;
+    // the task index is uniform: keep it, the cell search and the cell record
+    // in scalar registers (records read through the constant address space)
+    const unsigned long long tu = (unsigned long long)s_task;
+    const long long t = (long long)(((unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)(tu >> 32)) << 32) |
+                                    __builtin_amdgcn_readfirstlane((unsigned)tu));
     if (t >= b.n_tasks) break;
+    const cBatchCell* recs = (const cBatchCell*)b.recs;
     int c = 0;
-    while (c + 1 < b.n_cells && (PHASE ? b.recs[c + 1].task0m : b.recs[c + 1].task0) <= t) ++c;
-    const BatchCell& r = b.recs[c];
-    if constexpr (PHASE) batch_mutual_task<K, MIXED, ND>(r, b.ws, t - r.task0m, b.dens_begin, b.dens_end, smem);
-    else batch_near_task<K, MIXED>(r, b.ws, t - r.task0, smem);
+    while (c + 1 < b.n_cells && (PHASE ? recs[c + 1].task0m : recs[c + 1].task0) <= t) ++c;
+    if constexpr (PHASE) batch_mutual_task<K, MIXED, ND>(recs[c], b.ws, t - recs[c].task0m, b.dens_begin, b.dens_end, smem);
+    else batch_near_task<K, MIXED>(*(const BatchCell*)&recs[c], b.ws, t - recs[c].task0, smem);
   }
 }
 
