@@ -110,7 +110,9 @@ void plan_layout(const pfmm_plan_s* p, int64_t ns, int64_t nt, Layout& L, int64_
     // its chunk once for all modes/nodes of its lanes)
     const int n_w1 = (p->use_nufft ? 0 : p->n_sn) + p->n_ew + 1, lanes = far_r_lanes(n_w1);
     const int64_t wblocks = (n_w1 + lanes - 1) / lanes;
-    const int64_t want = std::max<int64_t>(1, (1024 + wblocks * p->n_dens - 1) / (wblocks * p->n_dens));
+    const int dg = far_r_dgroup(p->kernel, p->n_dens);
+    const int64_t zb = (p->n_dens + dg - 1) / dg;
+    const int64_t want = std::max<int64_t>(1, (1024 + wblocks * zb - 1) / (wblocks * zb));
     int64_t clen = std::max<int64_t>(256, (ns + want - 1) / want);
     clen = (clen + 255) / 256 * 256;
     L.chunk_len = clen;

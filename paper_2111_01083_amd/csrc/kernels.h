@@ -25,6 +25,10 @@ constexpr int FAR_R_BLOCK = 256;  // threads per far_R block: mode lanes x sourc
 // mode lanes of a far_R block for n_w1 modes/nodes (incl. the moment slot):
 // the smallest power of two >= n_w1 in [32, 256]; the other 256/lanes
 // thread slices split the block's sources
+// densities per far_R block (one plane-wave factor serves all of them)
+inline int far_r_dgroup(int kernel, int n_dens) {
+  return n_dens == 1 ? 1 : (kernel == PFMM_STOKES ? 2 : 4);
+}
 inline int far_r_lanes(int n_w1) {
   int l = 32;
   while (l < n_w1 && l < FAR_R_BLOCK) l *= 2;

@@ -1070,9 +1070,12 @@ void launch_near(int kernel, bool mixed, int nd, const NearArgs& a, int n_splits
 //     Laplace/Stokes use e^{...} - 1 (exact for neutral densities, and free of
 //     the O(1) cancellation at small lambda); Stokes also e^W = sum x f e^{...}
 // ---------------------------------------------------------------------------
-constexpr int FAR_R_TILE = 1024;
+constexpr int FAR_R_TILE = 512;
 
 struct cplx { double r, i; };
+typedef const __attribute__((address_space(4))) cplx ccplx;
+// a complex value from a table read through the constant address space
+__device__ __forceinline__ cplx cld(const ccplx* p) { return {p->r, p->i}; }
 __device__ __forceinline__ cplx cmul(cplx a, cplx b) { return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
 __device__ __forceinline__ cplx cadd(cplx a, cplx b) { return {a.r + b.r, a.i + b.i}; }
 __device__ __forceinline__ cplx csub(cplx a, cplx b) { return {a.r - b.r, a.i - b.i}; }
@@ -1087,19 +1090,21 @@ __device__ __forceinline__ cplx cexpm1(double a, double b) {
   return {expm1(a) * c - 2 * sh * sh, exp(a) * s};
 }
 
-// Block (x, y, z) = (mode group, source chunk, density): thread (slice, lane)
-// owns mode/node x * lanes + lane and every slices-th source of each LDS
-// tile; the slices' partial sums are added in a fixed order at the end.
-template <int K>
+// Block (x, y, z) = (mode group, source chunk, density group): thread
+// (slice, lane) owns mode/node x * lanes + lane and every slices-th source of
+// each LDS tile; each plane-wave factor serves the DG densities of the group;
+// the slices' partial sums are added in a fixed order at the end.
+template <int K, int DG>
 __global__ __launch_bounds__(FAR_R_BLOCK) void far_R_kernel(FarRArgs a) {
   constexpr int NC = (K == PFMM_STOKES) ? 2 : 1;
   constexpr int NCW = (K == PFMM_STOKES) ? 8 : 2;
-  constexpr int TILE_D = (2 + NC) * FAR_R_TILE, RED_D = FAR_R_BLOCK * NCW * 2;
+  constexpr int TILE_D = (2 + DG * NC) * FAR_R_TILE, RED_D = FAR_R_BLOCK * NCW * 2;
   __shared__ double smem[TILE_D > RED_D ? TILE_D : RED_D];
   double* s_x = smem;
   double* s_y = smem + FAR_R_TILE;
-  double* s_qb = smem + 2 * FAR_R_TILE;   // [NC][FAR_R_TILE]
-  const int v = blockIdx.z;
+  double* s_qb = smem + 2 * FAR_R_TILE;   // [DG][NC][FAR_R_TILE]
+  const int v0 = blockIdx.z * DG;
+  const int nd = min(DG, a.n_dens - v0);
   const int64_t j0 = (int64_t)blockIdx.y * a.chunk_len;
   const int64_t j1 = min(j0 + a.chunk_len, a.n_src);
   const int lanes = a.lanes, n_slices = FAR_R_BLOCK / lanes;
@@ -1113,17 +1118,22 @@ __global__ __launch_bounds__(FAR_R_BLOCK) void far_R_kernel(FarRArgs a) {
   double par0 = 0, par1 = 0;
   if (is_sn || is_ew) { par0 = a.tab[is_sn ? w * SN_REC : a.n_sn * SN_REC + (w - a.n_sn) * EW_REC];
                         par1 = a.tab[(is_sn ? w * SN_REC : a.n_sn * SN_REC + (w - a.n_sn) * EW_REC) + 1]; }
-  cplx acc[NCW];
+  cplx acc[DG][NCW];
 #pragma unroll
-  for (int c = 0; c < NCW; ++c) acc[c] = {0, 0};
-  const double* dens = a.dens + (size_t)v * NC * a.n_src;
+  for (int d = 0; d < DG; ++d)
+#pragma unroll
+    for (int c = 0; c < NCW; ++c) acc[d][c] = {0, 0};
+  const double* dens = a.dens + (size_t)v0 * NC * a.n_src;
   for (int64_t base = j0; base < j1; base += FAR_R_TILE) {
     const int nt = (int)min((int64_t)FAR_R_TILE, j1 - base);
     __syncthreads();
     for (int t = threadIdx.x; t < nt; t += FAR_R_BLOCK) {
       s_x[t] = a.sx[base + t]; s_y[t] = a.sy[base + t];
 #pragma unroll
-      for (int c = 0; c < NC; ++c) s_qb[c * FAR_R_TILE + t] = dens[(size_t)c * a.n_src + base + t];
+      for (int d = 0; d < DG; ++d)
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+          s_qb[(d * NC + c) * FAR_R_TILE + t] = d < nd ? dens[(size_t)(d * NC + c) * a.n_src + base + t] : 0.0;
     }
     __syncthreads();
     if (is_sn) {
@@ -1135,19 +1145,22 @@ __global__ __launch_bounds__(FAR_R_BLOCK) void far_R_kernel(FarRArgs a) {
         const double ep = exp(aa * y), em = 1.0 / ep;
         const cplx ph = {cs, -sn};
         const cplx ps = cscale(ph, ep), pn = cscale(ph, em);
-        if constexpr (K == PFMM_STOKES) {
 #pragma unroll
-          for (int c = 0; c < 2; ++c) {
-            const double f = s_qb[c * FAR_R_TILE + t];
-            acc[c] = cadd(acc[c], cscale(ps, f));
-            acc[2 + c] = cadd(acc[2 + c], cscale(ps, f * y));
-            acc[4 + c] = cadd(acc[4 + c], cscale(pn, f));
-            acc[6 + c] = cadd(acc[6 + c], cscale(pn, f * y));
+        for (int d = 0; d < DG; ++d) {
+          if constexpr (K == PFMM_STOKES) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+              const double f = s_qb[(d * NC + c) * FAR_R_TILE + t];
+              acc[d][c] = cadd(acc[d][c], cscale(ps, f));
+              acc[d][2 + c] = cadd(acc[d][2 + c], cscale(ps, f * y));
+              acc[d][4 + c] = cadd(acc[d][4 + c], cscale(pn, f));
+              acc[d][6 + c] = cadd(acc[d][6 + c], cscale(pn, f * y));
+            }
+          } else {
+            const double q = s_qb[d * FAR_R_TILE + t];
+            acc[d][0] = cadd(acc[d][0], cscale(ps, q));
+            acc[d][1] = cadd(acc[d][1], cscale(pn, q));
           }
-        } else {
-          const double q = s_qb[t];
-          acc[0] = cadd(acc[0], cscale(ps, q));
-          acc[1] = cadd(acc[1], cscale(pn, q));
         }
       }
     } else if (is_ew) {
@@ -1158,63 +1171,83 @@ __global__ __launch_bounds__(FAR_R_BLOCK) void far_R_kernel(FarRArgs a) {
           double sn, cs;
           sincos(lam * y, &sn, &cs);
           const double ep = exp(kap * x), em = 1.0 / ep;
-          const double q = s_qb[t];
-          acc[0] = cadd(acc[0], cplx{q * ep * cs, -q * ep * sn});
-          acc[1] = cadd(acc[1], cplx{q * em * cs, -q * em * sn});
+          const cplx pw = {ep * cs, -ep * sn}, pe = {em * cs, -em * sn};
+#pragma unroll
+          for (int d = 0; d < DG; ++d) {
+            const double q = s_qb[d * FAR_R_TILE + t];
+            acc[d][0] = cadd(acc[d][0], cscale(pw, q));
+            acc[d][1] = cadd(acc[d][1], cscale(pe, q));
+          }
         } else {
           const cplx wm = cexpm1(lam * x, -lam * y);    // e^{lam(x - i y)} - 1
           const cplx emm = cexpm1(-lam * x, -lam * y);  // e^{-lam(x + i y)} - 1
           if constexpr (K == PFMM_LAPLACE) {
-            const double q = s_qb[t];
-            acc[0] = cadd(acc[0], cscale(wm, q));
-            acc[1] = cadd(acc[1], cscale(emm, q));
+#pragma unroll
+            for (int d = 0; d < DG; ++d) {
+              const double q = s_qb[d * FAR_R_TILE + t];
+              acc[d][0] = cadd(acc[d][0], cscale(wm, q));
+              acc[d][1] = cadd(acc[d][1], cscale(emm, q));
+            }
           } else {
             const cplx wf = {wm.r + 1.0, wm.i}, ef = {emm.r + 1.0, emm.i};
 #pragma unroll
-            for (int c = 0; c < 2; ++c) {
-              const double f = s_qb[c * FAR_R_TILE + t];
-              acc[c] = cadd(acc[c], cscale(wm, f));
-              acc[2 + c] = cadd(acc[2 + c], cscale(wf, f * x));
-              acc[4 + c] = cadd(acc[4 + c], cscale(emm, f));
-              acc[6 + c] = cadd(acc[6 + c], cscale(ef, f * x));
-            }
+            for (int d = 0; d < DG; ++d)
+#pragma unroll
+              for (int c = 0; c < 2; ++c) {
+                const double f = s_qb[(d * NC + c) * FAR_R_TILE + t];
+                acc[d][c] = cadd(acc[d][c], cscale(wm, f));
+                acc[d][2 + c] = cadd(acc[d][2 + c], cscale(wf, f * x));
+                acc[d][4 + c] = cadd(acc[d][4 + c], cscale(emm, f));
+                acc[d][6 + c] = cadd(acc[d][6 + c], cscale(ef, f * x));
+              }
           }
         }
       }
     } else if (is_mom && K != PFMM_YUKAWA) {
       for (int t = slice; t < nt; t += n_slices) {
-        const double y = s_y[t], q = s_qb[t];
-        acc[0].r += q * y;
-        acc[0].i += q * y * y;
+        const double y = s_y[t];
+#pragma unroll
+        for (int d = 0; d < DG; ++d) {
+          const double q = s_qb[d * NC * FAR_R_TILE + t];
+          acc[d][0].r += q * y;
+          acc[d][0].i += q * y * y;
+        }
       }
     }
   }
-  // slice partials -> LDS (reusing the tile), summed by slice 0 in order
-  __syncthreads();
+  // per density: slice partials -> LDS (reusing the tile), summed by slice 0
+  // in a fixed order
   double* red = smem;   // [slice][lane][NCW] complex
 #pragma unroll
-  for (int c = 0; c < NCW; ++c) {
-    red[((size_t)(slice * lanes + lane) * NCW + c) * 2] = acc[c].r;
-    red[((size_t)(slice * lanes + lane) * NCW + c) * 2 + 1] = acc[c].i;
-  }
-  __syncthreads();
-  if (slice != 0) return;
+  for (int d = 0; d < DG; ++d) {
+    if (d >= nd) break;   // uniform over the block
+    __syncthreads();
 #pragma unroll
-  for (int c = 0; c < NCW; ++c) {
-    double sr = 0, si = 0;
-    for (int sl = 0; sl < n_slices; ++sl) {
-      sr += red[((size_t)(sl * lanes + lane) * NCW + c) * 2];
-      si += red[((size_t)(sl * lanes + lane) * NCW + c) * 2 + 1];
+    for (int c = 0; c < NCW; ++c) {
+      red[((size_t)(slice * lanes + lane) * NCW + c) * 2] = acc[d][c].r;
+      red[((size_t)(slice * lanes + lane) * NCW + c) * 2 + 1] = acc[d][c].i;
     }
-    acc[c] = {sr, si};
-  }
-  double* out = a.part + ((size_t)blockIdx.y * a.n_dens + v) * a.n_coef * 2;
-  if (in_sn || is_ew) {
+    __syncthreads();
+    if (slice == 0) {
+      cplx tot[NCW];
 #pragma unroll
-    for (int c = 0; c < NCW; ++c) { out[2 * (w * NCW + c)] = acc[c].r; out[2 * (w * NCW + c) + 1] = acc[c].i; }
-  } else if (is_mom) {
-    out[2 * (n_w * NCW)] = acc[0].r;
-    out[2 * (n_w * NCW) + 1] = acc[0].i;
+      for (int c = 0; c < NCW; ++c) {
+        double sr = 0, si = 0;
+        for (int sl = 0; sl < n_slices; ++sl) {
+          sr += red[((size_t)(sl * lanes + lane) * NCW + c) * 2];
+          si += red[((size_t)(sl * lanes + lane) * NCW + c) * 2 + 1];
+        }
+        tot[c] = {sr, si};
+      }
+      double* out = a.part + ((size_t)blockIdx.y * a.n_dens + v0 + d) * a.n_coef * 2;
+      if (in_sn || is_ew) {
+#pragma unroll
+        for (int c = 0; c < NCW; ++c) { out[2 * (w * NCW + c)] = tot[c].r; out[2 * (w * NCW + c) + 1] = tot[c].i; }
+      } else if (is_mom) {
+        out[2 * (n_w * NCW)] = tot[0].r;
+        out[2 * (n_w * NCW) + 1] = tot[0].i;
+      }
+    }
   }
 }
 
@@ -1246,11 +1279,15 @@ void launch_far_sum(double* part, int n_chunks, int64_t n_cplx, hipStream_t s) {
 
 void launch_far_R(const FarRArgs& a, int n_chunks, hipStream_t s) {
   const int n_w = a.n_sn + a.n_ew + 1 - (a.skip_sn ? a.n_sn : 0);
-  dim3 grid((unsigned)((n_w + a.lanes - 1) / a.lanes), (unsigned)n_chunks, (unsigned)a.n_dens);
-  switch (a.kernel) {
-    case PFMM_LAPLACE: hipLaunchKernelGGL(far_R_kernel<PFMM_LAPLACE>, grid, dim3(FAR_R_BLOCK), 0, s, a); break;
-    case PFMM_YUKAWA: hipLaunchKernelGGL(far_R_kernel<PFMM_YUKAWA>, grid, dim3(FAR_R_BLOCK), 0, s, a); break;
-    default: hipLaunchKernelGGL(far_R_kernel<PFMM_STOKES>, grid, dim3(FAR_R_BLOCK), 0, s, a); break;
+  const int dg = far_r_dgroup(a.kernel, a.n_dens);
+  dim3 grid((unsigned)((n_w + a.lanes - 1) / a.lanes), (unsigned)n_chunks, (unsigned)((a.n_dens + dg - 1) / dg));
+  switch (a.kernel * 8 + dg) {
+    case PFMM_LAPLACE * 8 + 1: hipLaunchKernelGGL((far_R_kernel<PFMM_LAPLACE, 1>), grid, dim3(FAR_R_BLOCK), 0, s, a); break;
+    case PFMM_LAPLACE * 8 + 4: hipLaunchKernelGGL((far_R_kernel<PFMM_LAPLACE, 4>), grid, dim3(FAR_R_BLOCK), 0, s, a); break;
+    case PFMM_YUKAWA * 8 + 1: hipLaunchKernelGGL((far_R_kernel<PFMM_YUKAWA, 1>), grid, dim3(FAR_R_BLOCK), 0, s, a); break;
+    case PFMM_YUKAWA * 8 + 4: hipLaunchKernelGGL((far_R_kernel<PFMM_YUKAWA, 4>), grid, dim3(FAR_R_BLOCK), 0, s, a); break;
+    case PFMM_STOKES * 8 + 1: hipLaunchKernelGGL((far_R_kernel<PFMM_STOKES, 1>), grid, dim3(FAR_R_BLOCK), 0, s, a); break;
+    default: hipLaunchKernelGGL((far_R_kernel<PFMM_STOKES, 2>), grid, dim3(FAR_R_BLOCK), 0, s, a); break;
   }
 }
 
@@ -1404,7 +1441,7 @@ __device__ __forceinline__ void wave_factors(double phase, double expo, double& 
   }
 }
 
-template <int K, bool MIXED>
+template <int K, bool MIXED, int DG>
 __global__ __launch_bounds__(256) void far_L_kernel(FarLArgs a) {
   constexpr int NO = (K == PFMM_STOKES) ? 6 : 3;
   constexpr int NCW = (K == PFMM_STOKES) ? 8 : 2;
@@ -1412,107 +1449,128 @@ __global__ __launch_bounds__(256) void far_L_kernel(FarLArgs a) {
   if (k >= a.n_trg) return;
   const int64_t i = a.perm[k];                                          // original index
   const double x = a.tx[k], y = a.ty[k];
-  const double* sn_tab = a.tab;
-  const double* ew_tab = a.tab + (size_t)a.n_sn * SN_REC;
-  for (int v = 0; v < a.n_dens; ++v) {
-    const cplx* w = reinterpret_cast<const cplx*>(a.w) + (size_t)v * a.n_coef;
-    double o[NO];
+  const cdouble* sn_tab = as_const(a.tab);
+  const cdouble* ew_tab = sn_tab + (size_t)a.n_sn * SN_REC;
+  // densities in groups of DG: every plane-wave factor serves the group
+  for (int v0 = 0; v0 < a.n_dens; v0 += DG) {
+    const int nd = min(DG, a.n_dens - v0);
+    ccplx* w0 = (ccplx*)as_const(a.w) + (size_t)v0 * a.n_coef;
+    double o[DG][NO];
 #pragma unroll
-    for (int c = 0; c < NO; ++c) o[c] = 0;
+    for (int d = 0; d < DG; ++d)
+#pragma unroll
+      for (int c = 0; c < NO; ++c) o[d][c] = 0;
     if (!a.nufft) {
       for (int m = 0; m < a.n_sn; ++m) {
         const double al = sn_tab[m * SN_REC], aa = sn_tab[m * SN_REC + 1];
         double sn, cs, ep, em;
         wave_factors<MIXED>(al * x, aa * y, sn, cs, ep, em);
         const cplx ph = {cs, sn};
-        const cplx* ww = w + m * NCW;
-        if constexpr (K == PFMM_STOKES) {
-          const cplx LS = cscale(ph, em), LN = cscale(ph, ep);
-          for (int k = 0; k < 2; ++k) {
-            const cplx uS = cmul(LS, csub(ww[k], cscale(ww[2 + k], y)));
-            const cplx uN = cmul(LN, csub(ww[4 + k], cscale(ww[6 + k], y)));
-            const cplx u = cadd(uS, uN);
-            o[k] += u.r;
-            o[2 + 2 * k] += -al * u.i;                       // Re(i alpha u)
-            const cplx dy = csub(cscale(uN, aa), cscale(uS, aa));
-            o[3 + 2 * k] += dy.r - cmul(LS, ww[2 + k]).r - cmul(LN, ww[6 + k]).r;
+#pragma unroll
+        for (int d = 0; d < DG; ++d) {
+          if (d >= nd) break;
+          ccplx* ww = w0 + (size_t)d * a.n_coef + m * NCW;
+          if constexpr (K == PFMM_STOKES) {
+            const cplx LS = cscale(ph, em), LN = cscale(ph, ep);
+            for (int q = 0; q < 2; ++q) {
+              const cplx w0q = cld(ww + q), w2q = cld(ww + 2 + q), w4q = cld(ww + 4 + q), w6q = cld(ww + 6 + q);
+              const cplx uS = cmul(LS, csub(w0q, cscale(w2q, y)));
+              const cplx uN = cmul(LN, csub(w4q, cscale(w6q, y)));
+              const cplx u = cadd(uS, uN);
+              o[d][q] += u.r;
+              o[d][2 + 2 * q] += -al * u.i;                       // Re(i alpha u)
+              const cplx dy = csub(cscale(uN, aa), cscale(uS, aa));
+              o[d][3 + 2 * q] += dy.r - cmul(LS, w2q).r - cmul(LN, w6q).r;
+            }
+          } else {
+            const cplx w0v = cld(ww + 0), w1v = cld(ww + 1);
+            const cplx sv = cscale(w0v, em), nv = cscale(w1v, ep);
+            const cplx u = cmul(cadd(sv, nv), ph);
+            o[d][0] += u.r;
+            o[d][1] += -al * u.i;
+            o[d][2] += aa * cmul(csub(nv, sv), ph).r;
           }
-        } else {
-          const cplx s = cscale(ww[0], em), n = cscale(ww[1], ep);
-          const cplx u = cmul(cadd(s, n), ph);
-          o[0] += u.r;
-          o[1] += -al * u.i;
-          o[2] += aa * cmul(csub(n, s), ph).r;
         }
       }
     }
-    for (int k = 0; k < a.n_ew; ++k) {
-      const double lam = ew_tab[k * EW_REC], kap = ew_tab[k * EW_REC + 1];
+    for (int kk = 0; kk < a.n_ew; ++kk) {
+      const double lam = ew_tab[kk * EW_REC], kap = ew_tab[kk * EW_REC + 1];
       double sn, cs, ep, em;
       wave_factors<MIXED>(lam * y, kap * x, sn, cs, ep, em);
       const double ch = 0.5 * (ep + em), sh = 0.5 * (ep - em);
       const cplx ph = {cs, sn};
-      const cplx* ww = w + (a.n_sn + k) * NCW;
-      if constexpr (K == PFMM_STOKES) {
-        for (int c = 0; c < 2; ++c) {
-          const cplx SA = csub(ww[c], cscale(ww[4 + c], x));    // SigmaA - x SigmaX
-          const cplx DA = csub(ww[2 + c], cscale(ww[6 + c], x));// DeltaA - x DeltaX
-          const cplx U = cadd(cscale(SA, ch), cscale(DA, sh));
+#pragma unroll
+      for (int d = 0; d < DG; ++d) {
+        if (d >= nd) break;
+        ccplx* ww = w0 + (size_t)d * a.n_coef + (a.n_sn + kk) * NCW;
+        if constexpr (K == PFMM_STOKES) {
+          for (int c = 0; c < 2; ++c) {
+            const cplx wc = cld(ww + c), w2c = cld(ww + 2 + c), w4c = cld(ww + 4 + c), w6c = cld(ww + 6 + c);
+            const cplx SA = csub(wc, cscale(w4c, x));     // SigmaA - x SigmaX
+            const cplx DA = csub(w2c, cscale(w6c, x));    // DeltaA - x DeltaX
+            const cplx U = cadd(cscale(SA, ch), cscale(DA, sh));
+            const cplx u = cmul(ph, U);
+            o[d][c] += u.r;
+            cplx G = cadd(cscale(SA, kap * sh), cscale(DA, kap * ch));
+            G = csub(G, cadd(cscale(w4c, ch), cscale(w6c, sh)));
+            o[d][2 + 2 * c] += cmul(ph, G).r;
+            o[d][3 + 2 * c] += -lam * u.i;
+          }
+        } else {
+          const cplx w0v = cld(ww + 0), w1v = cld(ww + 1);
+          const cplx U = cadd(cscale(w0v, ch), cscale(w1v, sh));
           const cplx u = cmul(ph, U);
-          o[c] += u.r;
-          cplx G = cadd(cscale(SA, kap * sh), cscale(DA, kap * ch));
-          G = csub(G, cadd(cscale(ww[4 + c], ch), cscale(ww[6 + c], sh)));
-          o[2 + 2 * c] += cmul(ph, G).r;
-          o[3 + 2 * c] += -lam * u.i;
+          o[d][0] += u.r;
+          o[d][1] += kap * cmul(ph, cadd(cscale(w0v, sh), cscale(w1v, ch))).r;
+          o[d][2] += -lam * u.i;
+        }
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < DG; ++d) {
+      if (d >= nd) break;
+      const int v = v0 + d;
+      if constexpr (K != PFMM_YUKAWA) {
+        const cplx mom = cld(w0 + (size_t)d * a.n_coef + (a.n_sn + a.n_ew) * NCW);
+        const double de = a.d * a.eta;
+        o[d][0] += -y * mom.r / de + mom.i / (2 * de);
+        o[d][K == PFMM_STOKES ? 3 : 2] += -mom.r / de;
+      }
+      if (a.nufft) {
+#pragma unroll
+        for (int c = 0; c < NO; ++c) o[d][c] += a.nu_val[((size_t)v * NO + c) * a.n_trg + k];
+      }
+      for (int s = 0; s < a.n_splits; ++s) {
+        const double* p = a.near_part + (size_t)s * a.part_stride;
+#pragma unroll
+        for (int c = 0; c < NO; ++c) o[d][c] += p[((size_t)v * NO + c) * a.n_trg + k];
+      }
+      // back to the user frame: user = R^T canonical
+      const double rc = a.rc, rs = a.rs;
+      if constexpr (K == PFMM_STOKES) {
+        const double u1 = rc * o[d][0] + rs * o[d][1], u2 = -rs * o[d][0] + rc * o[d][1];
+        // J_user = R^T J R,  J = [[o2, o3], [o4, o5]]
+        const double j11 = o[d][2], j12 = o[d][3], j21 = o[d][4], j22 = o[d][5];
+        const double t11 = rc * j11 + rs * j21, t12 = rc * j12 + rs * j22;   // R^T J
+        const double t21 = -rs * j11 + rc * j21, t22 = -rs * j12 + rc * j22;
+        const double g11 = t11 * rc + t12 * rs, g12 = -t11 * rs + t12 * rc; // (R^T J) R
+        const double g21 = t21 * rc + t22 * rs, g22 = -t21 * rs + t22 * rc;
+        const int64_t os = a.out_stride;
+        if (a.out_pot) {
+          a.out_pot[((size_t)v * 2) * os + i] = u1;
+          a.out_pot[((size_t)v * 2 + 1) * os + i] = u2;
+        }
+        if (a.out_grad) {
+          double* g = a.out_grad + (size_t)v * 4 * os;
+          g[i] = g11; g[os + i] = g12; g[2 * os + i] = g21; g[3 * os + i] = g22;
         }
       } else {
-        const cplx U = cadd(cscale(ww[0], ch), cscale(ww[1], sh));
-        const cplx u = cmul(ph, U);
-        o[0] += u.r;
-        o[1] += kap * cmul(ph, cadd(cscale(ww[0], sh), cscale(ww[1], ch))).r;
-        o[2] += -lam * u.i;
-      }
-    }
-    if constexpr (K != PFMM_YUKAWA) {
-      const cplx mom = w[(a.n_sn + a.n_ew) * NCW];
-      const double de = a.d * a.eta;
-      o[0] += -y * mom.r / de + mom.i / (2 * de);
-      o[K == PFMM_STOKES ? 3 : 2] += -mom.r / de;
-    }
-    if (a.nufft) {
-#pragma unroll
-      for (int c = 0; c < NO; ++c) o[c] += a.nu_val[((size_t)v * NO + c) * a.n_trg + k];
-    }
-    for (int s = 0; s < a.n_splits; ++s) {
-      const double* p = a.near_part + (size_t)s * a.part_stride;
-#pragma unroll
-      for (int c = 0; c < NO; ++c) o[c] += p[((size_t)v * NO + c) * a.n_trg + k];
-    }
-    // back to the user frame: user = R^T canonical
-    const double rc = a.rc, rs = a.rs;
-    if constexpr (K == PFMM_STOKES) {
-      const double u1 = rc * o[0] + rs * o[1], u2 = -rs * o[0] + rc * o[1];
-      // J_user = R^T J R,  J = [[o2, o3], [o4, o5]]
-      const double j11 = o[2], j12 = o[3], j21 = o[4], j22 = o[5];
-      const double t11 = rc * j11 + rs * j21, t12 = rc * j12 + rs * j22;   // R^T J
-      const double t21 = -rs * j11 + rc * j21, t22 = -rs * j12 + rc * j22;
-      const double g11 = t11 * rc + t12 * rs, g12 = -t11 * rs + t12 * rc; // (R^T J) R
-      const double g21 = t21 * rc + t22 * rs, g22 = -t21 * rs + t22 * rc;
-      const int64_t os = a.out_stride;
-      if (a.out_pot) {
-        a.out_pot[((size_t)v * 2) * os + i] = u1;
-        a.out_pot[((size_t)v * 2 + 1) * os + i] = u2;
-      }
-      if (a.out_grad) {
-        double* g = a.out_grad + (size_t)v * 4 * os;
-        g[i] = g11; g[os + i] = g12; g[2 * os + i] = g21; g[3 * os + i] = g22;
-      }
-    } else {
-      const int64_t os = a.out_stride;
-      if (a.out_pot) a.out_pot[(size_t)v * os + i] = o[0];
-      if (a.out_grad) {
-        a.out_grad[((size_t)v * 2) * os + i] = rc * o[1] + rs * o[2];
-        a.out_grad[((size_t)v * 2 + 1) * os + i] = -rs * o[1] + rc * o[2];
+        const int64_t os = a.out_stride;
+        if (a.out_pot) a.out_pot[(size_t)v * os + i] = o[d][0];
+        if (a.out_grad) {
+          a.out_grad[((size_t)v * 2) * os + i] = rc * o[d][1] + rs * o[d][2];
+          a.out_grad[((size_t)v * 2 + 1) * os + i] = -rs * o[d][1] + rc * o[d][2];
+        }
       }
     }
   }
@@ -1521,13 +1579,21 @@ __global__ __launch_bounds__(256) void far_L_kernel(FarLArgs a) {
 void launch_far_L(const FarLArgs& a, hipStream_t s) {
   if (a.n_trg <= 0) return;
   dim3 grid((unsigned)((a.n_trg + 255) / 256));
-  switch (a.kernel * 2 + (a.mixed ? 1 : 0)) {
-    case 0: hipLaunchKernelGGL((far_L_kernel<PFMM_LAPLACE, false>), grid, dim3(256), 0, s, a); break;
-    case 1: hipLaunchKernelGGL((far_L_kernel<PFMM_LAPLACE, true>), grid, dim3(256), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((far_L_kernel<PFMM_YUKAWA, false>), grid, dim3(256), 0, s, a); break;
-    case 3: hipLaunchKernelGGL((far_L_kernel<PFMM_YUKAWA, true>), grid, dim3(256), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((far_L_kernel<PFMM_STOKES, false>), grid, dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL((far_L_kernel<PFMM_STOKES, true>), grid, dim3(256), 0, s, a); break;
+  // densities per pass: 1, or a group that shares every plane-wave factor
+  const bool grp = a.n_dens > 1;
+  switch ((a.kernel * 2 + (a.mixed ? 1 : 0)) * 2 + (grp ? 1 : 0)) {
+    case 0: hipLaunchKernelGGL((far_L_kernel<PFMM_LAPLACE, false, 1>), grid, dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((far_L_kernel<PFMM_LAPLACE, false, 4>), grid, dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((far_L_kernel<PFMM_LAPLACE, true, 1>), grid, dim3(256), 0, s, a); break;
+    case 3: hipLaunchKernelGGL((far_L_kernel<PFMM_LAPLACE, true, 4>), grid, dim3(256), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((far_L_kernel<PFMM_YUKAWA, false, 1>), grid, dim3(256), 0, s, a); break;
+    case 5: hipLaunchKernelGGL((far_L_kernel<PFMM_YUKAWA, false, 4>), grid, dim3(256), 0, s, a); break;
+    case 6: hipLaunchKernelGGL((far_L_kernel<PFMM_YUKAWA, true, 1>), grid, dim3(256), 0, s, a); break;
+    case 7: hipLaunchKernelGGL((far_L_kernel<PFMM_YUKAWA, true, 4>), grid, dim3(256), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((far_L_kernel<PFMM_STOKES, false, 1>), grid, dim3(256), 0, s, a); break;
+    case 9: hipLaunchKernelGGL((far_L_kernel<PFMM_STOKES, false, 2>), grid, dim3(256), 0, s, a); break;
+    case 10: hipLaunchKernelGGL((far_L_kernel<PFMM_STOKES, true, 1>), grid, dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL((far_L_kernel<PFMM_STOKES, true, 2>), grid, dim3(256), 0, s, a); break;
   }
 }
 
