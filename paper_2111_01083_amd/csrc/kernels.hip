@@ -572,12 +572,15 @@ constexpr int mu_moments() {
   return K == PFMM_STOKES ? 7 : (K == PFMM_YUKAWA ? 3 : 2);
 }
 
-template <int K, bool MIXED, typename real>
+// LARGE (mixed Yukawa): every lane's beta r exceeds 2, the large-argument
+// K0/K1 formulas suffice (no series branch)
+template <int K, bool MIXED, typename real, bool LARGE = false>
 __device__ __forceinline__ void mutual_image(real dx, real dy, real* m, real& P, real beta) {
   if constexpr (K == PFMM_YUKAWA) {
     const real r2 = dx * dx + dy * dy;
     real k0, k1x;
-    if constexpr (MIXED) bessel_k01_f32_wave(beta * __builtin_amdgcn_sqrtf(r2), k0, k1x);
+    if constexpr (MIXED && LARGE) bessel_k01_f32_large(beta * __builtin_amdgcn_sqrtf(r2), k0, k1x);
+    else if constexpr (MIXED) bessel_k01_f32_wave(beta * __builtin_amdgcn_sqrtf(r2), k0, k1x);
     else bessel_k01_f64(beta * sqrt(r2), k0, k1x);
     m[0] += k0; m[1] += k1x * dx; m[2] += k1x * dy;
   } else {
@@ -744,14 +747,20 @@ __device__ __forceinline__ void mutual_block(const MA& a, const MuTask& p, int64
 #pragma unroll
     for (int c = 0; c < ND * NA; ++c) my_acc[c * MU_SUB + lane] = 0.0;
     __syncthreads();
-    unsigned mask = ~0u;
+    // mask: images within the cutoff; smask: images where some pair may have
+    // beta r <= 2 (K0/K1 series), the others take the large-argument path
+    unsigned mask = ~0u, smask = ~0u;
     if (cut) {
       const double bx0 = s_box[0], bx1 = s_box[1], by0 = s_box[2], by1 = s_box[3];
-      mask = 0;
-      for (int im = 0; im < a.n_images; ++im)
-        if (box_gap2(wx0, wx1, wy0, wy1, bx0 + imx[im], bx1 + imx[im], by0 + imy[im], by1 + imy[im]) <= a.rcut2)
-          mask |= 1u << im;
+      const double small2 = 4.0001 / (a.beta * a.beta);
+      mask = 0; smask = 0;
+      for (int im = 0; im < a.n_images; ++im) {
+        const double g2 = box_gap2(wx0, wx1, wy0, wy1, bx0 + imx[im], bx1 + imx[im], by0 + imy[im], by1 + imy[im]);
+        if (g2 <= a.rcut2) mask |= 1u << im;
+        if (g2 <= small2) smask |= 1u << im;
+      }
       mask = __builtin_amdgcn_readfirstlane(mask);
+      smask = __builtin_amdgcn_readfirstlane(smask);
     }
     for (int st = 0; st < MU_SUB && mask; ++st) {
       const int b = (lane + st) & (MU_SUB - 1);
@@ -786,8 +795,18 @@ __device__ __forceinline__ void mutual_block(const MA& a, const MuTask& p, int64
         }
       } else {
         real P = 1;
-        for (int im = 0; im < a.n_images; ++im) {
-          if (!((mask >> im) & 1u)) continue;
+        // images with only large arguments first (no series branch), then the rest
+        if constexpr (MIXED && K == PFMM_YUKAWA) {
+          const unsigned lmask = mask & ~smask;
+          for (int im = 0; im < a.n_images && lmask; ++im) {
+            if (!((lmask >> im) & 1u)) continue;
+            const real dx = (real)(d0x - imx[im]), dy = (real)(d0y - imy[im]);
+            mutual_image<K, MIXED, real, true>(dx, dy, m, P, beta);
+          }
+        }
+        const unsigned fmask = (MIXED && K == PFMM_YUKAWA) ? (mask & smask) : mask;
+        for (int im = 0; im < a.n_images && fmask; ++im) {
+          if (!((fmask >> im) & 1u)) continue;
           const real dx = (real)(d0x - imx[im]), dy = (real)(d0y - imy[im]);
           mutual_image<K, MIXED, real>(dx, dy, m, P, beta);
         }
