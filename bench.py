@@ -31,7 +31,7 @@ FLOPS_PER_PAIR = {"laplace": 14, "yukawa": 51, "stokes": 30}
 # times moments for both points, the log2 of the images' r^2 product, the
 # additions into both points' sums)
 FLOPS_MUTUAL_PER_IMAGE = {"laplace": 11, "yukawa": 44, "stokes": 22}
-FLOPS_MUTUAL_PER_PAIR = {"laplace": 15, "yukawa": 12, "stokes": 60}
+FLOPS_MUTUAL_PER_PAIR = {"laplace": 15, "yukawa": 12, "stokes": 64}
 TILE = 256    # targets per near-field block (the diagonal tiles are one-sided)
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 
