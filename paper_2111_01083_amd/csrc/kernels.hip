@@ -662,10 +662,10 @@ __device__ __forceinline__ void mutual_accumulate(const real* m, double lsum, do
   }
 }
 
-// LDS bytes of one mutual_block
+// LDS bytes of one mutual_block (the same for both precisions: coordinates,
+// densities and the source-side sums are FP64)
 template <int K, bool MIXED, int ND>
 constexpr size_t mutual_lds_bytes() {
-  using real = typename std::conditional<MIXED, float, double>::type;
   constexpr int QN = ND * ((K == PFMM_STOKES) ? 2 : 1);
   return 8 * (2 * MU_SUB) + 8 * (size_t)QN * MU_SUB + 8 * (size_t)(MU_BLOCK / 64) * ND * NAcc<K>::v * MU_SUB;
 }
