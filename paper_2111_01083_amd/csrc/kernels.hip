@@ -851,9 +851,13 @@ __device__ __forceinline__ void mutual_block(const MA& a, const MuTask& p, int64
 }
 
 template <int K, bool MIXED, int ND>
-// mixed: at most 6 waves per SIMD, which lets the compiler keep the K0/K1
-// polynomial constants in registers instead of rematerializing them per image
-__global__ __launch_bounds__(MU_BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 4 : 1, MIXED ? 6 : 8)))
+// waves per SIMD of the mixed kernels: at most PFMM_MU_WAVES (8). A cap of 6
+// keeps the K0/K1 polynomial constants in registers (no rematerialization
+// per image) but measured no faster for Yukawa and 3 % slower for Laplace
+#ifndef PFMM_MU_WAVES
+#define PFMM_MU_WAVES 8
+#endif
+__global__ __launch_bounds__(MU_BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 4 : 1, MIXED ? PFMM_MU_WAVES : 8)))
 void near_mutual_kernel(MutualArgs a) {
   __shared__ __align__(16) char smem[mutual_lds_bytes<K, MIXED, ND>()];
   const MuTask p{a.x, a.y, a.q64, a.acc, a.dens0};
