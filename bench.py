@@ -85,7 +85,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build evaluates on one GPU only; multi-GPU runs are not supported "
+        print("bench.py: the benchmark evaluates on one GPU only; multi-GPU runs are not supported "
               f"(asked for --gpus {args.gpus}, WORLD_SIZE {world})", file=sys.stderr)
         sys.exit(2)
 
