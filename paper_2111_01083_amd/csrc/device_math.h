@@ -81,6 +81,14 @@ __device__ __forceinline__ void bessel_k01_f32_large(float x, float& k0, float& 
   k1_over_x = e * rx * horner_f(KL1_F32, rx);
 }
 
+// The degree-4 far fits (x >= KF_X for every lane).
+__device__ __forceinline__ void bessel_k01_f32_far(float x, float& k0, float& k1_over_x) {
+  const float rx = __builtin_amdgcn_rcpf(x);
+  const float e = __expf(-x) * __builtin_amdgcn_rsqf(x);
+  k0 = e * horner_f(KF0_F32, rx);
+  k1_over_x = e * rx * horner_f(KF1_F32, rx);
+}
+
 // K0(x) and K1(x)/x for x > 0 in FP64.
 __device__ __forceinline__ void bessel_k01_f64(double x, double& k0, double& k1_over_x) {
   if (x <= 2.0) {

@@ -576,14 +576,16 @@ constexpr int mu_moments() {
   return K == PFMM_STOKES ? 6 : (K == PFMM_YUKAWA ? 3 : 2);
 }
 
-// LARGE (mixed Yukawa): every lane's beta r exceeds 2, the large-argument
-// K0/K1 formulas suffice (no series branch)
-template <int K, bool MIXED, typename real, bool LARGE = false>
+// ARG (mixed Yukawa) tells what every lane's x = beta r is known to be:
+// 0 any (series branch included), 1 x > 2 (large-argument fits), 2 x >= KF_X
+// (the shorter far fits)
+template <int K, bool MIXED, typename real, int ARG = 0>
 __device__ __forceinline__ void mutual_image(real dx, real dy, real* m, real& P, real beta) {
   if constexpr (K == PFMM_YUKAWA) {
     const real r2 = dx * dx + dy * dy;
     real k0, k1x;
-    if constexpr (MIXED && LARGE) bessel_k01_f32_large(beta * __builtin_amdgcn_sqrtf(r2), k0, k1x);
+    if constexpr (MIXED && ARG == 2) bessel_k01_f32_far(beta * __builtin_amdgcn_sqrtf(r2), k0, k1x);
+    else if constexpr (MIXED && ARG == 1) bessel_k01_f32_large(beta * __builtin_amdgcn_sqrtf(r2), k0, k1x);
     else if constexpr (MIXED) bessel_k01_f32_wave(beta * __builtin_amdgcn_sqrtf(r2), k0, k1x);
     else bessel_k01_f64(beta * sqrt(r2), k0, k1x);
     m[0] += k0; m[1] += k1x * dx; m[2] += k1x * dy;
@@ -755,19 +757,24 @@ __device__ __forceinline__ void mutual_block(const MA& a, const MuTask& p, int64
     for (int c = 0; c < ND * NA; ++c) my_acc[c * MU_SUB + lane] = 0.0;
     __syncthreads();
     // mask: images within the cutoff; smask: images where some pair may have
-    // beta r <= 2 (K0/K1 series), the others take the large-argument path
-    unsigned mask = ~0u, smask = ~0u;
+    // beta r <= 2 (K0/K1 series); fmask: images where every pair has
+    // beta r >= KF_X (far fits); the others take the large-argument fits
+    const unsigned all = (1u << a.n_images) - 1u;   // n_images <= MAX_IMAGES < 32
+    unsigned mask = all, smask = all, fmask = 0u;
     if (cut) {
       const double bx0 = s_box[0], bx1 = s_box[1], by0 = s_box[2], by1 = s_box[3];
       const double small2 = 4.0001 / (a.beta * a.beta);
+      const double far2 = (KF_X * KF_X * 1.0001) / (a.beta * a.beta);
       mask = 0; smask = 0;
       for (int im = 0; im < a.n_images; ++im) {
         const double g2 = box_gap2(wx0, wx1, wy0, wy1, bx0 + imx[im], bx1 + imx[im], by0 + imy[im], by1 + imy[im]);
         if (g2 <= a.rcut2) mask |= 1u << im;
         if (g2 <= small2) smask |= 1u << im;
+        if (g2 >= far2) fmask |= 1u << im;
       }
       mask = __builtin_amdgcn_readfirstlane(mask);
       smask = __builtin_amdgcn_readfirstlane(smask);
+      fmask = __builtin_amdgcn_readfirstlane(fmask);
     }
     for (int st = 0; st < MU_SUB && mask; ++st) {
       const int b = (lane + st) & (MU_SUB - 1);
@@ -802,18 +809,24 @@ __device__ __forceinline__ void mutual_block(const MA& a, const MuTask& p, int64
         }
       } else {
         real P = 1;
-        // images with only large arguments first (no series branch), then the rest
+        // images with only far arguments, then only large ones (no series
+        // branch), then the rest
         if constexpr (MIXED && K == PFMM_YUKAWA) {
-          const unsigned lmask = mask & ~smask;
-          for (int im = 0; im < a.n_images && lmask; ++im) {
-            if (!((lmask >> im) & 1u)) continue;
+          // each loop visits only the set bits of its mask
+          for (unsigned mm = mask & fmask; mm; mm &= mm - 1) {
+            const int im = __builtin_ctz(mm);
             const real dx = (real)(d0x - imx[im]), dy = (real)(d0y - imy[im]);
-            mutual_image<K, MIXED, real, true>(dx, dy, m, P, beta);
+            mutual_image<K, MIXED, real, 2>(dx, dy, m, P, beta);
+          }
+          for (unsigned mm = mask & ~smask & ~fmask; mm; mm &= mm - 1) {
+            const int im = __builtin_ctz(mm);
+            const real dx = (real)(d0x - imx[im]), dy = (real)(d0y - imy[im]);
+            mutual_image<K, MIXED, real, 1>(dx, dy, m, P, beta);
           }
         }
-        const unsigned fmask = (MIXED && K == PFMM_YUKAWA) ? (mask & smask) : mask;
-        for (int im = 0; im < a.n_images && fmask; ++im) {
-          if (!((fmask >> im) & 1u)) continue;
+        const unsigned gmask = (MIXED && K == PFMM_YUKAWA) ? (mask & smask) : mask;
+        for (unsigned mm = gmask; mm; mm &= mm - 1) {
+          const int im = __builtin_ctz(mm);
           const real dx = (real)(d0x - imx[im]), dy = (real)(d0y - imy[im]);
           mutual_image<K, MIXED, real>(dx, dy, m, P, beta);
         }
@@ -851,13 +864,12 @@ __device__ __forceinline__ void mutual_block(const MA& a, const MuTask& p, int64
 }
 
 template <int K, bool MIXED, int ND>
-// waves per SIMD of the mixed kernels: at most PFMM_MU_WAVES (8). A cap of 6
-// keeps the K0/K1 polynomial constants in registers (no rematerialization
-// per image) but measured no faster for Yukawa and 3 % slower for Laplace
-#ifndef PFMM_MU_WAVES
-#define PFMM_MU_WAVES 8
-#endif
-__global__ __launch_bounds__(MU_BLOCK) __attribute__((amdgpu_waves_per_eu(MIXED ? 4 : 1, MIXED ? PFMM_MU_WAVES : 8)))
+// waves per SIMD of the mixed Yukawa kernel: at most 6 (its registers allow
+// no more), which lets the compiler keep the K0/K1 polynomial constants in
+// registers instead of rematerializing them per image; the other kernels are
+// not capped (a cap of 6 measured 3 % slower for Laplace)
+__global__ __launch_bounds__(MU_BLOCK)
+__attribute__((amdgpu_waves_per_eu(MIXED ? 4 : 1, (MIXED && K == PFMM_YUKAWA) ? 6 : 8)))
 void near_mutual_kernel(MutualArgs a) {
   __shared__ __align__(16) char smem[mutual_lds_bytes<K, MIXED, ND>()];
   const MuTask p{a.x, a.y, a.q64, a.acc, a.dens0};

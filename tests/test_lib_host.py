@@ -178,6 +178,8 @@ def _tables():
     tabs = {}
     for name, body in re.findall(r"(\w+)\[\d+\] = \{([^}]*)\}", txt):
         tabs[name] = np.array([float(v) for v in body.split(",") if v.strip()])
+    for name, val in re.findall(r"(\w+) = ([0-9.eE+-]+);", txt):
+        tabs[name] = np.array([float(val)])
     return tabs
 
 
@@ -207,6 +209,11 @@ def test_device_bessel_tables_against_scipy(tag, bar):
         k1l = C.chebval(s, t["KL1_F64"])
     assert np.max(np.abs(k0l / (sp.k0e(xl) * np.sqrt(xl)) - 1)) < bar
     assert np.max(np.abs(k1l / (sp.k1e(xl) * np.sqrt(xl)) - 1)) < bar
+    if tag == "F32":
+        # the shorter fits used where every argument is known to be >= KF_X
+        xf = np.linspace(t["KF_X"][0], 200.0, 4001)
+        assert np.max(np.abs(hz(t["KF0_F32"], 1.0 / xf) / (sp.k0e(xf) * np.sqrt(xf)) - 1)) < bar
+        assert np.max(np.abs(hz(t["KF1_F32"], 1.0 / xf) / (sp.k1e(xf) * np.sqrt(xf)) - 1)) < bar
 
 
 @pytest.mark.parametrize("e1,e2,groups", [((1.0, 0.0), (0.0, 1.0), 1), ((1.0, 0.0), (0.5, 0.866), 1),
