@@ -727,6 +727,13 @@ __device__ __forceinline__ void mutual_block(const MA& a, const MuTask& p, int64
   const real beta = (real)a.beta;
   const cdouble* imx = as_const(a.imx);
   const cdouble* imy = as_const(a.imy);
+  // mixed Laplace with the 9 images in one log group (m0 = 1, the common
+  // case): the image loop is unrolled and the shifts stay in scalar registers
+  // for the whole task (6 % faster; Stokes measured 2.5 % slower this way)
+  const bool nine = K == PFMM_LAPLACE && MIXED && a.n_images == 9 && a.n_lg == 1;
+  double i9x[9], i9y[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) { i9x[q] = nine ? imx[q] : 0.0; i9y[q] = nine ? imy[q] : 0.0; }
   double accA[ND][NA];
 #pragma unroll
   for (int v = 0; v < ND; ++v)
@@ -795,6 +802,15 @@ __device__ __forceinline__ void mutual_block(const MA& a, const MuTask& p, int64
         }
         lsum = log(fmin(P, 1.0e300));
       } else if constexpr (NLOG > 0) {
+        if (nine) {
+          real P = a.lg_p0[0];
+#pragma unroll
+          for (int q = 0; q < 9; ++q) {
+            const real dx = (real)(d0x - i9x[q]), dy = (real)(d0y - i9y[q]);
+            mutual_image<K, MIXED, real>(dx, dy, m, P, beta);
+          }
+          lsum = (double)__builtin_amdgcn_logf(__builtin_fminf(P, 3.40282347e38f)) - a.lg_e0[0];
+        } else {
         // one log2 per image group of the product of its r^2 (FP32)
         int im = 0;
         for (int g = 0; g < a.n_lg; ++g) {
@@ -806,6 +822,7 @@ __device__ __forceinline__ void mutual_block(const MA& a, const MuTask& p, int64
           // padding sources (far away, zero density) may overflow P; the clamp
           // keeps 0 * log2(P) finite (valid pairs stay below 2^122)
           lsum += (double)__builtin_amdgcn_logf(__builtin_fminf(P, 3.40282347e38f)) - a.lg_e0[g];
+        }
         }
       } else {
         real P = 1;
