@@ -70,12 +70,16 @@ enum {
 };
 
 typedef struct {
-  double beta;        /* Yukawa parameter (> 0); ignored otherwise              */
+  double beta;        /* Yukawa parameter (> 0); ignored otherwise. Yukawa     */
+                      /* near-field pairs farther apart than r_c, with         */
+                      /* e^{-beta r_c} = eps / 30, are dropped (a truncation   */
+                      /* of the same order as the far field's)                 */
   int precision;      /* pfmm_precision: FP64 everywhere, or MIXED (near-field  */
                       /* pair arithmetic in FP32 on coordinate differences     */
-                      /* taken in FP64; log terms accumulated in FP64 pair by  */
-                      /* pair, other terms in short FP32 blocks flushed to     */
-                      /* FP64; far-field coefficients and weights in FP64,     */
+                      /* taken in FP64, short FP32 sums (over 16 sources or a  */
+                      /* pair's images) combined with the FP64 densities in    */
+                      /* FP64, log terms from FP32 log2 of r^2 products added  */
+                      /* in FP64; far-field coefficients and weights in FP64,  */
                       /* plane waves at the targets in FP32 with phases        */
                       /* reduced in FP64)                                      */
   int far_mode;       /* pfmm_far_mode: AUTO uses the NUFFT when 2M+1 >= 256   */
