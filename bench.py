@@ -46,12 +46,17 @@ HASHED = ["paper_2111_01083_amd/csrc/kernels.hip", "paper_2111_01083_amd/csrc/ke
           "paper_2111_01083_amd/csrc/device_math.h", "paper_2111_01083_amd/csrc/bessel_tables.h"]
 
 
+def code_only(text):
+    """Source text without // comments and blank lines (the hash follows code, not comments)."""
+    return "\n".join(ln.split("//", 1)[0].rstrip() for ln in text.splitlines() if ln.split("//", 1)[0].strip())
+
+
 def measured_traffic():
     import hashlib
     h = hashlib.sha256()
     for f in HASHED:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f)) as fh:
+            h.update(code_only(fh.read()).encode())
     try:
         lines = open(COUNTERS).read().splitlines()
     except OSError:

@@ -541,15 +541,18 @@ __global__ __launch_bounds__(NEAR_BLOCK) void near_kernel(NearArgs a) {
 // lane t pairs its point with source (t + st) mod 64, so within a wavefront
 // every lane works on a different source and the source-side sums go to a
 // per-wavefront LDS row without conflicts or atomics. The 9 (or 15) images of
-// a pair are summed in registers first. Each sub-tile's source-side sums
-// and, at the end, each thread's own sums are converted to outputs and added
-// to acc with FP64 atomics (the order of these adds is not fixed, so repeated
-// runs agree to FP64 rounding). Precision as in the one-sided kernel: MIXED
-// takes the coordinate difference in FP64, the rest in FP32, log terms summed
-// in FP64 with the FP64 densities; the log2 of a group of images is that of
-// the FP32 product of their r^2 (the plan bounds the product's range), which
-// is as accurate as per-image logs and saves a log, a conversion and the FP64
-// fmas per image. No r = 0 guard is needed (no point meets itself here).
+// a pair are summed in registers first (density-free moments, below), then
+// multiplied by both points' densities in FP64. Each sub-tile's source-side
+// sums and, at the end, each thread's own sums are converted to outputs and
+// added to acc with FP64 atomics (the order of these adds is not fixed, so
+// repeated runs agree to FP64 rounding). MIXED takes the coordinate difference
+// in FP64 and the per-image arithmetic in FP32; the log2 of a group of images
+// is that of the FP32 product of their r^2 (the plan bounds the product's
+// range), as accurate as per-image logs and a log, a conversion and the FP64
+// fmas per image cheaper. Yukawa: per (wavefront, source sub-tile) bounding
+// boxes skip the images beyond the screened cutoff and pick the shortest
+// K0/K1 fits that hold for every pair of the image. No r = 0 guard is needed
+// (no point meets itself here).
 // ---------------------------------------------------------------------------
 constexpr int MU_SUB = 64;
 
