@@ -796,6 +796,8 @@ __device__ __forceinline__ void mutual_block(const MA& a, const MuTask& p, int64
 #pragma unroll
       for (int c = 0; c < mu_moments<K, MIXED>(); ++c) m[c] = 0;
       double lsum = 0.0;   // Laplace/Stokes: sum of log r^2 (mixed: log2) over the images
+      double cx = 0.0, cy = 0.0;   // Stokes, several log groups: FP64 sums of m[2], m[3]
+      bool flushed = false;        // uniform
       if constexpr (NLOG > 0 && !MIXED) {
         // FP64: one log of the product of all images' r^2 (no range issue)
         real P = 1;
@@ -814,7 +816,10 @@ __device__ __forceinline__ void mutual_block(const MA& a, const MuTask& p, int64
           }
           lsum = (double)__builtin_amdgcn_logf(__builtin_fminf(P, 3.40282347e38f)) - a.lg_e0[0];
         } else {
-        // one log2 per image group of the product of its r^2 (FP32)
+        // one log2 per image group of the product of its r^2 (FP32); with
+        // several groups (rows of 5 or 7 images) the Stokes sums of order
+        // one (C, sum ia dy) move to FP64 after each group, so none of them
+        // runs over more than a row in FP32 (the 1/r-scale sums stay in FP32)
         int im = 0;
         for (int g = 0; g < a.n_lg; ++g) {
           real P = a.lg_p0[g];
@@ -825,6 +830,11 @@ __device__ __forceinline__ void mutual_block(const MA& a, const MuTask& p, int64
           // padding sources (far away, zero density) may overflow P; the clamp
           // keeps 0 * log2(P) finite (valid pairs stay below 2^122)
           lsum += (double)__builtin_amdgcn_logf(__builtin_fminf(P, 3.40282347e38f)) - a.lg_e0[g];
+          if (K == PFMM_STOKES && a.n_lg > 1) {   // the O(1) sums C and sum ia dy
+            cx += (double)m[2]; cy += (double)m[3];
+            m[2] = 0; m[3] = 0;
+            flushed = true;
+          }
         }
         }
       } else {
@@ -851,7 +861,11 @@ __device__ __forceinline__ void mutual_block(const MA& a, const MuTask& p, int64
           mutual_image<K, MIXED, real>(dx, dy, m, P, beta);
         }
       }
-      mutual_accumulate<K, ND, real>(m, lsum, (double)a.n_images, qid, qjd, accA, my_acc + b, MU_SUB);
+      double md[mu_moments<K, MIXED>()];
+#pragma unroll
+      for (int c = 0; c < mu_moments<K, MIXED>(); ++c) md[c] = (double)m[c];
+      if (K == PFMM_STOKES && flushed) { md[2] += cx; md[3] += cy; }
+      mutual_accumulate<K, ND, double>(md, lsum, (double)a.n_images, qid, qjd, accA, my_acc + b, MU_SUB);
     }
     __syncthreads();
     if (tid < nsb) {

@@ -65,13 +65,16 @@ void reduce_basis(double b1[2], double b2[2]) {
 //   with l* the group image nearest to d0, |d0 - l| >= |l - l*| / 2 for the
 //   others, so the product without l*'s factor is >= prod min(1, |l - l*|^2/4).
 // Starting the product at 2^e0 keeps every partial product below 2^124 and,
-// for the closest image's r^2 down to 2^-100, above 2^-124. The groups tried
-// are all images, the rows of fixed n (images one period d apart), and
-// single images (always valid: the per-image log).
+// for the closest image's r^2 down to 2^-100, above 2^-124; within that range
+// e0 is chosen to bring a typical product near 1 (the FP32 log2 is then most
+// accurate). The groups tried are all images (cells with 9 images), the rows
+// of fixed n (images one period d apart; the kernel also moves its FP32
+// image sums to FP64 after each group, which keeps 15- and 21-image cells
+// accurate), and single images (always valid: the per-image log).
 void plan_log_groups(pfmm::Geometry& g, int per_row) {
   const double s = g.sigma;
   const double dmax = s * std::max(std::hypot(g.d + g.xi, g.eta), std::hypot(g.d - g.xi, g.eta));
-  const int sizes[3] = {g.n_images, per_row, 1};
+  const int sizes[3] = {g.n_images <= 9 ? g.n_images : per_row, per_row, 1};
   for (int gs : sizes) {
     if (gs < 1 || g.n_images % gs) continue;
     bool ok = true;
@@ -94,7 +97,18 @@ void plan_log_groups(pfmm::Geometry& g, int per_row) {
       // need e0 + fmax <= 124 and -100 + e0 + gmin >= -124 (two bits of slack each)
       const double lo = std::ceil(-22 - gmin), hi = std::floor(122 - fmax);
       if (lo > hi) { ok = false; break; }
-      g.lg_e0[n_lg] = (int)std::min(std::max(0.0, lo), hi);
+      // typical log2 of the product: mean over pair differences
+      // d0 = u e1 + v e2, u, v in {-3/4, -1/4, 1/4, 3/4}
+      double typ = 0;
+      for (int iu = 0; iu < 4; ++iu)
+        for (int iv = 0; iv < 4; ++iv) {
+          const double u = -0.75 + 0.5 * iu, v = -0.75 + 0.5 * iv;
+          const double x0 = s * (u * g.d + v * g.xi), y0 = s * (v * g.eta);
+          for (int i = g0; i < g0 + gs; ++i)
+            typ += std::log2(std::pow(x0 - s * g.img_x[i], 2) + std::pow(y0 - s * g.img_y[i], 2));
+        }
+      typ /= 16;
+      g.lg_e0[n_lg] = (int)std::min(std::max(-std::nearbyint(typ), lo), hi);
       g.lg_end[n_lg] = g0 + gs;
       ++n_lg;
     }

@@ -141,3 +141,26 @@ def test_near_coincident_points(env, kernel):
     po, go = oracle.evaluate(kernel, e1, e2, src, dens, None)
     assert np.isfinite(pm).all() and np.isfinite(gm).all()
     assert rel(pm, po) < 1e-6 and rel(gm, go) < 1e-6, (rel(pm, po), rel(gm, go))
+
+
+@pytest.mark.parametrize("kernel,beta", [("laplace", 0.0), ("yukawa", 3.0), ("stokes", 0.0)])
+@pytest.mark.parametrize("prec,tol,bar", [("fp64", 1e-10, 1e-10), ("mixed", 1e-6, 1e-6)])
+def test_widest_near_region(env, kernel, beta, prec, tol, bar):
+    # m0 = 3: 21 images, the most the plan allows (image masks and log groups
+    # at their widest); symmetric and one-sided paths against the oracle
+    P, torch, dev = env
+    n = 700
+    e1, e2 = (1.0, 0.0), (0.3, 1.0)
+    rng = np.random.default_rng(21)
+    src = W.cell_points(rng, e1, e2, n)
+    dens = W.neutral_forces(rng, n) if kernel == "stokes" else W.neutral_charges(rng, n)
+    print(f"case m0=3 {kernel} {prec}", flush=True)
+    outs = []
+    for mode in ("mutual", "one_sided"):
+        plan = P.Plan(kernel, e1, e2, tol, beta=beta, precision=prec, self_exclude=True, near_mode=mode, m0=3)
+        assert plan.info["n_images"] == 21
+        pot, grad = plan(torch.tensor(src, device=dev), torch.tensor(dens, device=dev))
+        outs.append((pot.cpu().numpy(), grad.cpu().numpy()))
+    po, go = oracle.evaluate(kernel, e1, e2, src, dens, None, beta=beta)
+    for pm, gm in outs:
+        assert rel(pm, po) < bar and rel(gm, go) < bar, (rel(pm, po), rel(gm, go))

@@ -216,10 +216,11 @@ def test_device_bessel_tables_against_scipy(tag, bar):
         assert np.max(np.abs(hz(t["KF1_F32"], 1.0 / xf) / (sp.k1e(xf) * np.sqrt(xf)) - 1)) < bar
 
 
-@pytest.mark.parametrize("e1,e2,groups", [((1.0, 0.0), (0.0, 1.0), 1), ((1.0, 0.0), (0.5, 0.866), 1),
+@pytest.mark.parametrize("e1,e2,groups", [((1.0, 0.0), (0.0, 1.0), 1), ((1.0, 0.0), (0.5, 0.866), 3),
                                           ((100.0, 0.0), (0.0, 1.0), 1), ((4000.0, 0.0), (0.0, 1.0), 3)])
 def test_log_groups_of_the_symmetric_mixed_near_field(P, e1, e2, groups):
-    # one group of all images unless the cell is so thin that the product could
-    # leave the FP32 range; then one group per row of images (one period apart)
+    # 9 images: one group unless the cell is so thin that the product could
+    # leave the FP32 range; 15 images (the hexagonal cell, m0 = 2) or such thin
+    # cells: one group per row of images (one period apart)
     inf = P.Plan("laplace", e1, e2, 1e-6, precision="mixed", self_exclude=True).info
     assert inf["n_log_groups"] == groups and inf["n_images"] % groups == 0
