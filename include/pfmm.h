@@ -137,6 +137,14 @@ int pfmm_plan_get_info(pfmm_plan_t plan, pfmm_plan_info_t* info);
  * west_thm_lap / west_thm_s. Either pointer may be NULL. */
 int pfmm_plan_get_quadrature(pfmm_plan_t plan, double* nodes, double* weights);
 
+/* Host: the image groups of the mixed symmetric near field (Def. 1 near
+ * region, images ordered row by row: n = -1, 0, 1 outer, m = -m0..m0
+ * inner): ends[g] is one past the last image of group g and e0[g] the
+ * exponent its FP32 r^2 product starts at (2^e0), for g < n_log_groups
+ * (pfmm_plan_get_info); host int arrays of at least n_log_groups entries.
+ * Either pointer may be NULL. */
+int pfmm_plan_get_log_groups(pfmm_plan_t plan, int* ends, int* e0);
+
 /* Profiling plans only (opts.profile = 1): wait for the events recorded by
  * every pfmm_eval since the last call, and return the summed GPU time of
  * the near-field kernel launches (*near_ms), of whole evaluations

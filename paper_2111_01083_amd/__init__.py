@@ -78,6 +78,13 @@ class Plan:
         _check(L.load().pfmm_plan_get_quadrature(self.handle, _dp(x), _dp(w)), "pfmm_plan_get_quadrature")
         return x, w
 
+    def log_groups(self):
+        """(ends, e0): image groups of the mixed symmetric near field (pfmm_plan_get_log_groups)."""
+        n = self.info["n_log_groups"]
+        ends = (ctypes.c_int * max(n, 1))(); e0 = (ctypes.c_int * max(n, 1))()
+        _check(L.load().pfmm_plan_get_log_groups(self.handle, ends, e0), "pfmm_plan_get_log_groups")
+        return list(ends)[:n], list(e0)[:n]
+
     def stage_times(self):
         """(near-field ms, whole-evaluation ms, evaluations) since the last call
         (profiling plans; waits for the recorded HIP events)."""
@@ -177,6 +184,10 @@ def pfmm_eval(plan, src, dens, trg=None, out_pot=None, out_grad=None, workspace=
         out_pot = None if out_pot is None else out_pot[0]
         out_grad = None if out_grad is None else out_grad[0]
     return out_pot, out_grad
+
+
+def pfmm_plan_get_log_groups(plan):
+    return plan.log_groups()
 
 
 def pfmm_plan_get_tuning(plan):

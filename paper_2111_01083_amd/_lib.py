@@ -18,6 +18,7 @@ ERRORS = {0: "PFMM_OK", -1: "PFMM_EINVAL", -2: "PFMM_EINVAL_LATTICE", -3: "PFMM_
 
 # every function declared in include/pfmm.h
 EXPORTS = ["pfmm_plan", "pfmm_plan_upload", "pfmm_plan_get_info", "pfmm_plan_get_quadrature",
+           "pfmm_plan_get_log_groups",
            "pfmm_plan_stage_times",
            "pfmm_workspace_bytes", "pfmm_eval", "pfmm_workspace_bytes_adjoint", "pfmm_eval_adjoint",
            "pfmm_batch_create", "pfmm_batch_workspace_bytes", "pfmm_eval_batch", "pfmm_batch_destroy",
@@ -71,6 +72,8 @@ def load():
     lib.pfmm_plan_get_info.restype = c_int
     lib.pfmm_plan_get_quadrature.argtypes = [vp, dp, dp]
     lib.pfmm_plan_get_quadrature.restype = c_int
+    lib.pfmm_plan_get_log_groups.argtypes = [vp, ctypes.POINTER(c_int), ctypes.POINTER(c_int)]
+    lib.pfmm_plan_get_log_groups.restype = c_int
     lib.pfmm_plan_stage_times.argtypes = [vp, dp, dp, ctypes.POINTER(c_int)]
     lib.pfmm_plan_stage_times.restype = c_int
     lib.pfmm_workspace_bytes.argtypes = [vp, i64, i64]

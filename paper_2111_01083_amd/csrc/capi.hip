@@ -242,6 +242,15 @@ int pfmm_plan_get_quadrature(pfmm_plan_t p, double* nodes, double* weights) {
   return PFMM_OK;
 }
 
+int pfmm_plan_get_log_groups(pfmm_plan_t p, int* ends, int* e0) {
+  if (!p) return PFMM_EINVAL;
+  for (int g = 0; g < p->geo.n_lg; ++g) {
+    if (ends) ends[g] = p->geo.lg_end[g];
+    if (e0) e0[g] = p->geo.lg_e0[g];
+  }
+  return PFMM_OK;
+}
+
 size_t pfmm_workspace_bytes(pfmm_plan_t p, int64_t ns, int64_t nt) {
   if (!p || ns < 0 || nt < 0) return 0;
   if (p->self_exclude) nt = ns;

@@ -224,3 +224,42 @@ def test_log_groups_of_the_symmetric_mixed_near_field(P, e1, e2, groups):
     # cells: one group per row of images (one period apart)
     inf = P.Plan("laplace", e1, e2, 1e-6, precision="mixed", self_exclude=True).info
     assert inf["n_log_groups"] == groups and inf["n_images"] % groups == 0
+
+
+@pytest.mark.parametrize("e1,e2,m0", [((1.0, 0.0), (0.0, 1.0), 0), ((1.0, 0.0), (0.5, 0.866), 0),
+                                      ((1.0, 0.0), (0.3, 1.0), 3), ((10.0, 0.0), (0.0, 1.0), 0),
+                                      ((2000.0, 0.0), (0.0, 1.0), 0), ((4000.0, 0.0), (0.0, 1.0), 0)])
+def test_log_group_products_stay_in_the_fp32_range(P, e1, e2, m0):
+    # FP32 emulation of the symmetric kernel's image products: for pair
+    # differences across the cell, and for pairs as close as r^2 = 2^-100
+    # under any one image, every partial product of a group (started at
+    # 2^e0) stays a normal FP32 number; in cells of aspect <= 10 the typical
+    # product is also near 1 (in thinner cells the range bound keeps e0 from
+    # centring it: products of 2^80..2^100 there)
+    f32 = np.float32
+    pl = P.Plan("laplace", e1, e2, 1e-6, precision="mixed", self_exclude=True, m0=m0)
+    inf = pl.info
+    ends, e0 = pl.log_groups()
+    assert ends[-1] == inf["n_images"] and len(ends) == inf["n_log_groups"]
+    d, xi, eta, mm = inf["d"], inf["xi"], inf["eta"], (inf["n_images"] // 3 - 1) // 2
+    sg = 2.0 ** round(-0.5 * np.log2(d * eta))
+    imgs = np.array([(sg * (m * d + n * xi), sg * n * eta) for n in (-1, 0, 1) for m in range(-mm, mm + 1)])
+    rng = np.random.default_rng(4)
+    u, v = rng.uniform(-1, 1, (2, 4000))
+    d0 = np.stack([sg * (u * d + v * xi), sg * v * eta], 1)
+    # near-coincident pairs: within 2^-50 of a random image
+    k = rng.integers(0, len(imgs), 400)
+    ang = rng.uniform(0, 2 * np.pi, 400)
+    close = imgs[k] + 2.0 ** -50 * np.stack([np.cos(ang), np.sin(ang)], 1)
+    d0 = np.concatenate([d0, close])
+    g0, logs = 0, []
+    for end, e in zip(ends, e0):
+        p = np.full(len(d0), f32(2.0 ** e))
+        for i in range(g0, end):
+            r2 = ((d0[:, 0] - imgs[i, 0]) ** 2 + (d0[:, 1] - imgs[i, 1]) ** 2).astype(f32)
+            p = (p * r2).astype(f32)
+            assert np.all(np.isfinite(p)) and np.all(p >= np.finfo(f32).tiny), (end, e, i)
+        logs.append(np.log2(p[:4000].astype(np.float64)))
+        g0 = end
+    if max(abs(e1[0]), abs(e2[1])) <= 10:
+        assert np.median(np.abs(np.concatenate(logs))) < 16
