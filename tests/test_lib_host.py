@@ -247,10 +247,13 @@ def test_log_group_products_stay_in_the_fp32_range(P, e1, e2, m0):
     rng = np.random.default_rng(4)
     u, v = rng.uniform(-1, 1, (2, 4000))
     d0 = np.stack([sg * (u * d + v * xi), sg * v * eta], 1)
-    # near-coincident pairs: within 2^-50 of a random image
+    # near-coincident pairs: 2^-50 from a random image, or a few FP64 ulps of
+    # the shift where 2^-50 is not representable next to it (a pair any closer
+    # is coincident in FP64, a singularity on every path)
     k = rng.integers(0, len(imgs), 400)
     ang = rng.uniform(0, 2 * np.pi, 400)
-    close = imgs[k] + 2.0 ** -50 * np.stack([np.cos(ang), np.sin(ang)], 1)
+    off = np.maximum(2.0 ** -50, 8 * np.spacing(np.abs(imgs[k]).max(1)))
+    close = imgs[k] + off[:, None] * np.stack([np.cos(ang), np.sin(ang)], 1)
     d0 = np.concatenate([d0, close])
     g0, logs = 0, []
     for end, e in zip(ends, e0):
