@@ -450,7 +450,10 @@ int pfmm::eval_core(pfmm_plan_t p, int64_t ns, const double* src_xy, const doubl
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
   if (p->profile) {
     for (int k = 0; k < 3; ++k)
-      if (hipEventCreate(&ev[k]) != hipSuccess) return PFMM_EHIP;
+      if (hipEventCreate(&ev[k]) != hipSuccess) {
+        for (int q = 0; q < k; ++q) (void)hipEventDestroy(ev[q]);
+        return PFMM_EHIP;
+      }
     p->prof_events.push_back(ev[0]); p->prof_events.push_back(ev[1]); p->prof_events.push_back(ev[2]);
   }
   cell_prep(r, src_xy, ns, dens, ns, trg_xy, nt, st);
@@ -885,7 +888,8 @@ int pfmm_batch_autotune(pfmm_batch_t b, const double* src_xy, const double* dens
   hipStream_t st = (hipStream_t)hip_stream;
   char* ws = (char*)workspace;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return PFMM_EHIP;
+  if (hipEventCreate(&e0) != hipSuccess) return PFMM_EHIP;
+  if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return PFMM_EHIP; }
   // one warm-up and one timed eager launch sequence
   auto timed = [&](double* ms) -> int {
     int rc = batch_launch(b, src_xy, dens, trg_xy, out_pot, out_grad, ws, st);
