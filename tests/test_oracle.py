@@ -176,6 +176,49 @@ def test_yukawa_tends_to_laplace_quadratically_in_beta():
     assert errs[1] < 0.05 * (np.linalg.norm(pl) + np.linalg.norm(gl))
 
 
+def _yukawa_row_spectral(d, e2, beta, src, q, trg, nrow=40, nk=300):
+    """Periodic Yukawa field for e1 = (d, 0) by Poisson summation along each
+    row of images: the 1D Fourier transform of K0(beta sqrt(x^2 + Y^2)) / (2 pi)
+    is exp(-|Y| s) / (2 s) with s = sqrt(k^2 + beta^2), so a row of images
+    offset by Y sums to (1/d) sum_k exp(-|Y| s_k) cos(k X) / (2 s_k),
+    k = 2 pi j / d. Converges exponentially when every row offset is away
+    from zero; no Bessel function and no image cut-off of the oracle's."""
+    xi, eta = e2
+    pot = np.zeros(trg.shape[1]); grad = np.zeros((2, trg.shape[1]))
+    k = 2 * np.pi * np.arange(-nk, nk + 1) / d
+    s = np.sqrt(k * k + beta * beta)
+    for n in range(-nrow, nrow + 1):
+        X = trg[0][:, None] - src[0][None, :] + n * xi
+        Y = trg[1][:, None] - src[1][None, :] + n * eta
+        e = np.exp(-np.abs(Y)[..., None] * s) / (2 * s * d)
+        ph = k * X[..., None]
+        pot += (np.cos(ph) * e).sum(-1) @ q
+        grad[0] += (-k * np.sin(ph) * e).sum(-1) @ q
+        grad[1] += (-np.sign(Y)[..., None] * s * np.cos(ph) * e).sum(-1) @ q
+    return pot, grad
+
+
+@pytest.mark.parametrize("e1,e2", [SHEARED, GENERAL])
+@pytest.mark.parametrize("beta", [1.5, 4.0])
+def test_yukawa_equals_row_spectral_sum(e1, e2, beta):
+    # Work in the frame where e1 lies on the x axis; sources and targets sit
+    # in separate horizontal bands so that no row offset comes near zero.
+    th = np.arctan2(e1[1], e1[0])
+    R = np.array([[np.cos(th), np.sin(th)], [-np.sin(th), np.cos(th)]])   # rotates e1 onto +x
+    d = np.hypot(*e1)
+    e2r = R @ np.asarray(e2)
+    eta = e2r[1]
+    rng = np.random.default_rng(11)
+    ns, nt = 12, 9
+    src_r = np.vstack([rng.uniform(-d / 2, d / 2, ns), rng.uniform(-0.45, -0.25, ns) * eta])
+    trg_r = np.vstack([rng.uniform(-d / 2, d / 2, nt), rng.uniform(0.05, 0.25, nt) * eta])
+    q = rng.standard_normal(ns)
+    p, g = oracle.yukawa(e1, e2, beta, R.T @ src_r, q, R.T @ trg_r)
+    ps, gs = _yukawa_row_spectral(d, e2r, beta, src_r, q, trg_r)
+    assert np.abs(p - ps).max() < 1e-12 * np.abs(ps).max()
+    assert np.abs(R @ g - gs).max() < 1e-12 * np.abs(gs).max()
+
+
 # --- Stokes -------------------------------------------------------------------
 
 @pytest.mark.parametrize("self_trg", [False, True])
