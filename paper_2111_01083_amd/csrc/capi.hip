@@ -99,7 +99,7 @@ void plan_layout(const pfmm_plan_s* p, int64_t ns, int64_t nt, Layout& L, int64_
     L.qb64 = take(8 * (size_t)p->n_dens * nc * ns);
     L.qb32 = mixed ? take(4 * (size_t)p->n_dens * nc * ns) : 0;
     // about 8192 source chunks x target tiles in total (half of them empty)
-    const int64_t tiles = (ns + MU_BLOCK - 1) / MU_BLOCK;
+    const int64_t tiles = std::max<int64_t>(1, (ns + MU_BLOCK - 1) / MU_BLOCK);
     const int64_t want = std::max<int64_t>(1, ((target ? target : 8192) * 256 / MU_BLOCK + tiles - 1) / tiles);
     int64_t cl = forced_split > 0 ? forced_split : std::max<int64_t>(1024, (ns + want - 1) / want);
     L.mu_chunk = (cl + 63) / 64 * 64;

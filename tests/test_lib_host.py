@@ -141,6 +141,22 @@ def test_workspace_size_grows_with_problem(P):
     assert 0 < a < b and a % 256 == 0
 
 
+@pytest.mark.parametrize("kernel", ["laplace", "yukawa", "stokes"])
+@pytest.mark.parametrize("near_mode", ["one_sided", "mutual"])
+@pytest.mark.parametrize("cell", [((1.1, 0.35), (-0.2, 0.9)), ((100.0, 0.0), (0.0, 1.0))])
+def test_workspace_sizes_of_empty_inputs(P, kernel, near_mode, cell):
+    # sizing for no sources, no targets, or neither is host-only work and must
+    # not fail for any plan shape (symmetric near field, NUFFT far field, adjoint)
+    for prec in ("fp64", "mixed"):
+        kw = dict(beta=3.0 if kernel == "yukawa" else 0.0, precision=prec)
+        plan = P.Plan(kernel, *cell, 1e-6, **kw)
+        for ns, nt in ((0, 37), (50, 0), (0, 0)):
+            assert P.pfmm_workspace_bytes(plan, ns, nt) > 0
+        splan = P.Plan(kernel, *cell, 1e-6, self_exclude=True, near_mode=near_mode, **kw)
+        assert P.pfmm_workspace_bytes(splan, 0, 0) > 0
+        assert P.pfmm_workspace_bytes_adjoint(splan, 0) > 0
+
+
 def test_eval_without_workspace_is_rejected_before_any_launch(P):
     from paper_2111_01083_amd import _lib
     lib = _lib.load()
