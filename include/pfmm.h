@@ -41,6 +41,9 @@
  *  - Evaluation is asynchronous on the caller's HIP stream; nothing is
  *    allocated inside pfmm_eval. Scratch memory comes from `workspace`,
  *    of at least pfmm_workspace_bytes() bytes, 256-byte aligned.
+ *  - n_src and n_trg (per cell in a batch) are at most PFMM_MAX_POINTS
+ *    (point indices are 32-bit inside the kernels); larger sizes are
+ *    PFMM_EINVAL, and pfmm_workspace_bytes* return 0 for them.
  *  - Return value 0 on success, a negative PFMM_E* code otherwise; on an
  *    argument error nothing is launched and outputs are untouched.
  */
@@ -57,6 +60,8 @@ extern "C" {
 typedef enum { PFMM_LAPLACE = 0, PFMM_YUKAWA = 1, PFMM_STOKES = 2 } pfmm_kernel;
 typedef enum { PFMM_FP64 = 0, PFMM_MIXED = 1 } pfmm_precision;
 typedef enum { PFMM_FAR_AUTO = 0, PFMM_FAR_DIRECT = 1, PFMM_FAR_NUFFT = 2 } pfmm_far_mode;
+
+#define PFMM_MAX_POINTS ((int64_t)1 << 30)
 
 enum {
   PFMM_OK = 0,

@@ -13,6 +13,7 @@ PFMM_LAPLACE, PFMM_YUKAWA, PFMM_STOKES = 0, 1, 2
 PFMM_FP64, PFMM_MIXED = 0, 1
 PFMM_FAR_AUTO, PFMM_FAR_DIRECT, PFMM_FAR_NUFFT = 0, 1, 2
 PFMM_NEAR_AUTO, PFMM_NEAR_ONE_SIDED, PFMM_NEAR_MUTUAL = 0, 1, 2
+PFMM_MAX_POINTS = 1 << 30          # largest n_src / n_trg (per cell in a batch)
 ERRORS = {0: "PFMM_OK", -1: "PFMM_EINVAL", -2: "PFMM_EINVAL_LATTICE", -3: "PFMM_EINVAL_TOL",
           -4: "PFMM_EWORKSPACE", -5: "PFMM_EHIP", -6: "PFMM_ENOT_NEUTRAL", -7: "PFMM_ENOMEM"}
 

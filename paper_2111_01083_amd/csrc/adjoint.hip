@@ -100,14 +100,14 @@ using namespace pfmm;
 extern "C" {
 
 size_t pfmm_workspace_bytes_adjoint(pfmm_plan_t p, int64_t ns) {
-  if (!p || ns < 0) return 0;
+  if (!p || ns < 0 || ns > PFMM_MAX_POINTS) return 0;
   return adj_layout(p, ns).total;
 }
 
 int pfmm_eval_adjoint(pfmm_plan_t p, int64_t ns, const double* src_xy, const double* dens,
                       const double* g_pot, double* out_dq, double* out_dxy, void* workspace,
                       size_t ws_bytes, void* hip_stream) {
-  if (!p || ns < 0) return PFMM_EINVAL;
+  if (!p || ns < 0 || ns > PFMM_MAX_POINTS) return PFMM_EINVAL;
   if (!p->self_exclude || p->n_dens != 1) return PFMM_EINVAL;
   if (ns == 0 || (!out_dq && !out_dxy)) return PFMM_OK;
   if (!src_xy || !dens || !g_pot) return PFMM_EINVAL;

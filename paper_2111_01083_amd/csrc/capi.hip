@@ -252,7 +252,7 @@ int pfmm_plan_get_log_groups(pfmm_plan_t p, int* ends, int* e0) {
 }
 
 size_t pfmm_workspace_bytes(pfmm_plan_t p, int64_t ns, int64_t nt) {
-  if (!p || ns < 0 || nt < 0) return 0;
+  if (!p || ns < 0 || nt < 0 || ns > PFMM_MAX_POINTS || nt > PFMM_MAX_POINTS) return 0;
   if (p->self_exclude) nt = ns;
   Layout L;
   plan_layout(p, ns, nt, L);
@@ -425,7 +425,7 @@ int cell_setup(pfmm_plan_s* p, int64_t ns, int64_t nt, char* ws, int64_t forced_
 int pfmm::eval_core(pfmm_plan_t p, int64_t ns, const double* src_xy, const double* dens, int64_t nt,
                     const double* trg_xy, double* out_pot, double* out_grad, void* workspace,
                     size_t ws_bytes, void* hip_stream) {
-  if (!p || ns < 0 || nt < 0) return PFMM_EINVAL;
+  if (!p || ns < 0 || nt < 0 || ns > PFMM_MAX_POINTS || nt > PFMM_MAX_POINTS) return PFMM_EINVAL;
   if (p->self_exclude && nt != ns) return PFMM_EINVAL;
   if (ns > 0 && (!src_xy || !dens)) return PFMM_EINVAL;
   if (nt > 0 && !p->self_exclude && !trg_xy) return PFMM_EINVAL;
@@ -782,8 +782,10 @@ int pfmm_batch_create(int n_cells, const pfmm_plan_t* plans, const int64_t* src_
     if (!p || p->precision != p0->precision || p->n_dens != p0->n_dens || p->self_exclude != p0->self_exclude ||
         (p->kernel == PFMM_STOKES ? 2 : 1) != nc)
       return PFMM_EINVAL;
-    if (src_off[c + 1] < src_off[c]) return PFMM_EINVAL;
-    if (!p0->self_exclude && (!trg_off || trg_off[c + 1] < trg_off[c])) return PFMM_EINVAL;
+    if (src_off[c + 1] < src_off[c] || src_off[c + 1] - src_off[c] > PFMM_MAX_POINTS) return PFMM_EINVAL;
+    if (!p0->self_exclude &&
+        (!trg_off || trg_off[c + 1] < trg_off[c] || trg_off[c + 1] - trg_off[c] > PFMM_MAX_POINTS))
+      return PFMM_EINVAL;
   }
   if (src_off[0] != 0 || (!p0->self_exclude && trg_off[0] != 0)) return PFMM_EINVAL;
   pfmm_batch_s* b = new (std::nothrow) pfmm_batch_s();

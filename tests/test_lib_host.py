@@ -168,6 +168,28 @@ def test_eval_without_workspace_is_rejected_before_any_launch(P):
     assert _lib.ERRORS[rc] == "PFMM_EINVAL"
 
 
+def test_sizes_beyond_the_point_limit_are_rejected_before_any_launch(P):
+    from paper_2111_01083_amd import _lib
+    lib = _lib.load()
+    big = _lib.PFMM_MAX_POINTS + 1
+    plan = P.Plan("laplace", (1.0, 0.0), (0.0, 1.0), 1e-6)
+    assert P.pfmm_workspace_bytes(plan, _lib.PFMM_MAX_POINTS, 10) > 0
+    assert P.pfmm_workspace_bytes(plan, big, 10) == 0 and P.pfmm_workspace_bytes(plan, 10, big) == 0
+    dummy = ctypes.c_void_p(256)   # never dereferenced: the size check fails first
+    for ns, nt in ((big, 10), (10, big)):
+        rc = lib.pfmm_eval(plan.handle, ns, dummy, dummy, nt, dummy, dummy, dummy, dummy, 1 << 62, None)
+        assert _lib.ERRORS[rc] == "PFMM_EINVAL"
+    splan = P.Plan("laplace", (1.0, 0.0), (0.0, 1.0), 1e-6, self_exclude=True)
+    assert P.pfmm_workspace_bytes_adjoint(splan, big) == 0
+    rc = lib.pfmm_eval_adjoint(splan.handle, big, dummy, dummy, dummy, dummy, dummy, dummy, 1 << 62, None)
+    assert _lib.ERRORS[rc] == "PFMM_EINVAL"
+    plans = (ctypes.c_void_p * 2)(splan.handle.value, splan.handle.value)
+    off = (ctypes.c_int64 * 3)(0, 10, 10 + big)
+    out = ctypes.c_void_p()
+    rc = lib.pfmm_batch_create(2, plans, off, None, 0, ctypes.byref(out))
+    assert _lib.ERRORS[rc] == "PFMM_EINVAL" and not out.value
+
+
 def test_tuning_get_set_and_nufft_grid(P):
     plan = P.Plan("laplace", (100.0, 0.0), (0.0, 1.0), 1e-6, far_mode="nufft")
     nf0, w0 = plan.info["nufft_nf"], plan.info["nufft_w"]
