@@ -583,7 +583,10 @@ int pfmm_plan_set_tuning(pfmm_plan_t p, const pfmm_tuning_t* t) {
     int rc = set_nufft_grid(p, t->nufft_grid);
     if (rc) { (void)set_nufft_grid(p, old); return rc; }
     rc = plan_refresh_device(p);
-    if (rc) return rc;
+    if (rc) {   // keep the host tables on the grid the device still holds
+      (void)set_nufft_grid(p, old);
+      return rc;
+    }
   }
   p->tune_near = t->near_blocks;
   return PFMM_OK;
