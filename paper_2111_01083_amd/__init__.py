@@ -144,12 +144,19 @@ def _as_dev(t, name):
     return t.contiguous()
 
 
+def _as_points(t, name):
+    t = _as_dev(t, name)
+    if t.dim() != 2 or t.shape[0] != 2:
+        raise ValueError(f"{name} must have shape (2, n) (x row, then y row), got {tuple(t.shape)}")
+    return t
+
+
 def pfmm_eval(plan, src, dens, trg=None, out_pot=None, out_grad=None, workspace=None, stream=None,
               want_pot=True, want_grad=True):
     """Potentials and gradients at the targets (trg None: targets = sources)."""
     torch = _torch()
     lib = L.load()
-    src = _as_dev(src, "src")
+    src = _as_points(src, "src")
     dens = _as_dev(dens, "dens")
     ns = src.shape[1]
     stokes = plan.kernel == L.PFMM_STOKES
@@ -164,7 +171,7 @@ def pfmm_eval(plan, src, dens, trg=None, out_pot=None, out_grad=None, workspace=
     else:
         if trg is None:
             raise ValueError("plan without self_exclude needs targets")
-        trg_t = _as_dev(trg, "trg")
+        trg_t = _as_points(trg, "trg")
         nt = trg_t.shape[1]
     npot = 2 if stokes else 1
     ngrad = 4 if stokes else 2
@@ -226,11 +233,11 @@ def pfmm_autotune(plan, src, dens, trg=None, out_pot=None, out_grad=None, worksp
     an evaluation with the chosen tuning."""
     torch = _torch()
     lib = L.load()
-    src = _as_dev(src, "src"); dens = _as_dev(dens, "dens")
+    src = _as_points(src, "src"); dens = _as_dev(dens, "dens")
     ns = src.shape[1]
     stokes = plan.kernel == L.PFMM_STOKES
     nd = plan.n_dens
-    trg_t = None if plan.self_exclude else _as_dev(trg, "trg")
+    trg_t = None if plan.self_exclude else _as_points(trg, "trg")
     nt = ns if trg_t is None else trg_t.shape[1]
     if out_pot is None:
         out_pot = torch.empty((nd, 2, nt) if stokes else (nd, nt), dtype=torch.float64, device=src.device)
@@ -255,7 +262,7 @@ def pfmm_eval_adjoint(plan, src, dens, g_pot, workspace=None, stream=None):
     given g_pot = dL/dpot (see pfmm.h)."""
     torch = _torch()
     lib = L.load()
-    src = _as_dev(src, "src"); dens = _as_dev(dens, "dens"); g_pot = _as_dev(g_pot, "g_pot")
+    src = _as_points(src, "src"); dens = _as_dev(dens, "dens"); g_pot = _as_dev(g_pot, "g_pot")
     ns = src.shape[1]
     if g_pot.numel() != dens.numel():
         raise ValueError("g_pot must have the shape of the potential (= shape of dens)")
@@ -345,9 +352,9 @@ def pfmm_eval_batch(batch, src, dens, trg=None, out_pot=None, out_grad=None, wor
     Returns pot (n_dens, T) [Stokes (n_dens, 2, T)] and grad (n_dens, 2|4, T)."""
     torch = _torch()
     lib = L.load()
-    src = _as_dev(src, "src"); dens = _as_dev(dens, "dens")
+    src = _as_points(src, "src"); dens = _as_dev(dens, "dens")
     T = int(batch.src_off[-1] if batch.self_exclude else batch.trg_off[-1])
-    trg_t = None if batch.self_exclude else _as_dev(trg, "trg")
+    trg_t = None if batch.self_exclude else _as_points(trg, "trg")
     nd = batch.n_dens
     if out_pot is None:
         out_pot = torch.empty((nd, 2, T) if batch.stokes else (nd, T), dtype=torch.float64, device=src.device)
@@ -366,9 +373,9 @@ def pfmm_batch_autotune(batch, src, dens, trg=None, out_pot=None, out_grad=None,
     the fastest in the batch; returns (report dict, pot, grad)."""
     torch = _torch()
     lib = L.load()
-    src = _as_dev(src, "src"); dens = _as_dev(dens, "dens")
+    src = _as_points(src, "src"); dens = _as_dev(dens, "dens")
     T = int(batch.src_off[-1] if batch.self_exclude else batch.trg_off[-1])
-    trg_t = None if batch.self_exclude else _as_dev(trg, "trg")
+    trg_t = None if batch.self_exclude else _as_points(trg, "trg")
     nd = batch.n_dens
     if out_pot is None:
         out_pot = torch.empty((nd, 2, T) if batch.stokes else (nd, T), dtype=torch.float64, device=src.device)
