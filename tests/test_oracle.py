@@ -221,6 +221,69 @@ def test_yukawa_equals_row_spectral_sum(e1, e2, beta):
 
 # --- Stokes -------------------------------------------------------------------
 
+def _stokes_row_spectral(d, e2, src, f, trg, nrow=40, nk=300):
+    """Zero-mean periodic Stokeslet velocity and gradient for e1 = (d, 0),
+    from the Fourier symbol T(k) = (I - k k^T / k^2) / k^2 summed over the
+    reciprocal lattice with k = 0 left out. Reciprocal vectors with
+    k_x = 2 pi j / d != 0 are summed over k_y by Poisson summation, which
+    turns them into rows of images offset by n e2 with the 1D transforms
+      int e^{i k_y Y} / k^2   dk_y / 2pi = e^{-a|Y|} / (2a)
+      int e^{i k_y Y} / k^4   dk_y / 2pi = (1 + a|Y|) e^{-a|Y|} / (4a^3),  a = |k_x|;
+    those with k_x = 0 are k = (0, 2 pi l / eta), where T = diag(1/k_y^2, 0)
+    sums to (eta / 2d) B2(t) with B2(t) = t^2 - t + 1/6, t = Y/eta mod 1.
+    No Ewald split, no exponential integral, no real-space image sum."""
+    xi, eta = e2
+    nt = trg.shape[1]
+    u = np.zeros((2, nt)); g = np.zeros((4, nt))     # g: du1/dx, du1/dy, du2/dx, du2/dy
+    a = 2 * np.pi * np.arange(1, nk + 1) / d          # k_x > 0; -k_x is folded in (factor 2)
+    fx = f[0][None, :]; fy = f[1][None, :]
+
+    def add(out, kxx, kxy, kyy):                      # out += sum_src [[xx, xy], [xy, yy]] f
+        out[0] += (kxx.sum(-1) * fx + kxy.sum(-1) * fy).sum(1) / d
+        out[1] += (kxy.sum(-1) * fx + kyy.sum(-1) * fy).sum(1) / d
+
+    for n in range(-nrow, nrow + 1):
+        X = (trg[0][:, None] - src[0][None, :] + n * xi)[..., None]
+        Y = (trg[1][:, None] - src[1][None, :] + n * eta)[..., None]
+        y = np.abs(Y); s = np.sign(Y); E = np.exp(-a * y)
+        F1, dF1 = E / (2 * a), -s * E / 2                                  # 1/k^2 and d/dY
+        G0, dG0 = (1 + a * y) * E / (4 * a), -a * Y * E / 4                # k_x^2 / k^4 and d/dY
+        G1, dG1 = -Y * E / (4 * a), -(1 - a * y) * E / (4 * a)             # d/dY of 1/k^4, and next
+        dG2 = s * (2 - a * y) * E / 4                                      # third derivative of 1/k^4
+        Txx, Tyy, dTxx, dTyy = F1 - G0, F1 + dG1, dF1 - dG0, dF1 + dG2
+        c = np.cos(a * X); sn = np.sin(a * X)
+        vel = np.zeros((2, nt)); gx = np.zeros((2, nt)); gy = np.zeros((2, nt))
+        add(vel, 2 * c * Txx, -2 * a * G1 * sn, 2 * c * Tyy)
+        add(gx, -2 * a * sn * Txx, -2 * a * a * G1 * c, -2 * a * sn * Tyy)
+        add(gy, 2 * c * dTxx, -2 * a * dG1 * sn, 2 * c * dTyy)
+        u += vel; g[0] += gx[0]; g[2] += gx[1]; g[1] += gy[0]; g[3] += gy[1]
+    t = np.mod((trg[1][:, None] - src[1][None, :]) / eta, 1.0)
+    u[0] += ((eta / (2 * d)) * (t * t - t + 1.0 / 6.0) * fx).sum(1)
+    g[1] += (((2 * t - 1) / (2 * d)) * fx).sum(1)
+    return u, g
+
+
+@pytest.mark.parametrize("e1,e2", [SHEARED, GENERAL, ((1.0, 0.0), (0.0, 1.0))])
+def test_stokes_equals_spectral_row_sum(e1, e2):
+    # also fixes the additive constant: the oracle's velocity has zero cell mean
+    th = np.arctan2(e1[1], e1[0])
+    R = np.array([[np.cos(th), np.sin(th)], [-np.sin(th), np.cos(th)]])   # rotates e1 onto +x
+    d = np.hypot(*e1)
+    e2r = R @ np.asarray(e2)
+    eta = e2r[1]
+    rng = np.random.default_rng(11)
+    ns, nt = 12, 9
+    src_r = np.vstack([rng.uniform(-d / 2, d / 2, ns), rng.uniform(-0.45, -0.25, ns) * eta])
+    trg_r = np.vstack([rng.uniform(-d / 2, d / 2, nt), rng.uniform(0.05, 0.25, nt) * eta])
+    f_r = rng.standard_normal((2, ns))
+    f_r -= f_r.mean(1, keepdims=True)
+    u, g = oracle.stokes(e1, e2, R.T @ src_r, R.T @ f_r, R.T @ trg_r)
+    us, gs = _stokes_row_spectral(d, e2r, src_r, f_r, trg_r)
+    gr = np.einsum("ij,jkt,lk->ilt", R, g.reshape(2, 2, nt), R).reshape(4, nt)
+    assert np.abs(R @ u - us).max() < 1e-12 * np.abs(us).max()
+    assert np.abs(gr - gs).max() < 1e-12 * np.abs(gs).max()
+
+
 @pytest.mark.parametrize("self_trg", [False, True])
 def test_stokes_ewald_independent_of_split(self_trg):
     src, f, trg = _setup(*GENERAL, stokes=True)
