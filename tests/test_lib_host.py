@@ -34,6 +34,29 @@ def test_library_exports_every_declared_function(P):
         assert hasattr(lib, name), name
 
 
+def test_header_is_c99_and_the_abi_works_from_c(P, tmp_path):
+    # a plain C program built against include/pfmm.h with warnings as errors,
+    # linked with libpfmm, runs the host-only entry points; the struct sizes it
+    # prints must match the Python binding's ctypes layouts
+    import shutil
+    import subprocess
+    from paper_2111_01083_amd import _lib
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    libdir = os.path.dirname(_lib.LIB_PATH)
+    exe = str(tmp_path / "c_abi_check")
+    subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror",
+                    "-I", os.path.join(ROOT, "include"), os.path.join(ROOT, "tests", "c_abi_check.c"),
+                    "-o", exe, "-L", libdir, "-lpfmm", "-Wl,-rpath," + libdir], check=True)
+    out = subprocess.run([exe], check=True, capture_output=True, text=True, timeout=60).stdout.split("\n")
+    assert out[-2] == "ok", out
+    sizes = dict(line.split()[1:] for line in out if line.startswith("sizeof "))
+    for name, ct in (("pfmm_opts", _lib.pfmm_opts), ("pfmm_plan_info_t", _lib.pfmm_plan_info_t),
+                     ("pfmm_tuning_t", _lib.pfmm_tuning_t), ("pfmm_tune_report_t", _lib.pfmm_tune_report_t)):
+        assert int(sizes[name]) == ctypes.sizeof(ct), name
+
+
 def test_canonical_lattice_of_rotated_unreduced_basis(P):
     # lattice of (3, 0), (0.6, 1), given rotated and as an unreduced basis
     th = 0.7
