@@ -157,6 +157,16 @@ def test_plan_rejects_bad_arguments(P, kw, code):
     assert _lib.ERRORS[e.value.code] == code
 
 
+def test_south_terms_at_double_precision_match_the_papers_estimate(P):
+    rows = [l.split() for l in open(os.path.join(ROOT, "tests", "golden", "south_terms_double_precision.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert rows
+    for A, per_a, band in ((float(a), float(b), float(c)) for a, b, c in rows):
+        for kernel, beta in (("laplace", 0.0), ("yukawa", 1.0)):
+            M = P.Plan(kernel, (A, 0.0), (0.0, 1.0), 1e-14, beta=beta).info["n_modes"]
+            assert abs(M / A - per_a) <= band * per_a, (kernel, A, M)
+
+
 def test_workspace_size_grows_with_problem(P):
     plan = P.Plan("stokes", (1.0, 0.0), (0.0, 1.0), 1e-6, precision="mixed")
     a = P.pfmm_workspace_bytes(plan, 1000, 500)
