@@ -598,7 +598,6 @@ int pfmm_autotune(pfmm_plan_t p, int64_t ns, const double* src_xy, const double*
   if (!p || ns <= 0 || nt <= 0 || (!out_pot && !out_grad)) return PFMM_EINVAL;
   pfmm_tuning_t cur{};
   pfmm_plan_get_tuning(p, &cur);
-  const pfmm_tuning_t start = cur;
   double nm = 0, tm = 0;
   int rc = time_eval(p, ns, src_xy, dens, nt, trg_xy, out_pot, out_grad, ws, ws_bytes, stream, &nm, &tm);
   if (rc) return rc;
@@ -644,7 +643,6 @@ int pfmm_autotune(pfmm_plan_t p, int64_t ns, const double* src_xy, const double*
   double nb, tb;
   if ((rc = time_eval(p, ns, src_xy, dens, nt, trg_xy, out_pot, out_grad, ws, ws_bytes, stream, &nb, &tb))) return rc;
   if (report) { report->n_tried = tried; report->default_ms = start_ms; report->best_ms = tb; }
-  (void)start;
   return PFMM_OK;
 }
 
