@@ -1,0 +1,114 @@
+"""CPU restatement of the periodic scheme for the modified Helmholtz kernel,
+written from the paper's formulas with numpy/scipy, fed with the planner's
+host outputs only (canonical lattice and rotation, near-region width m0,
+south/north truncation M, west/east quadrature nodes and weights), and
+compared with the FP64 oracle (a plain truncated lattice sum).
+
+It checks the host side of the plan end to end, without a GPU: if the
+planner's canonical frame, m0, M or quadrature were wrong, or a reading of
+the paper's theorems were, the scheme would miss the oracle.
+
+  near part:  the 3 (2 m0 + 1) images of Def. 1 (eq. nearfarsplit), summed directly;
+  south/north: Thm. south_thm and its corollary (rows n <= -2 and n >= 2);
+  west/east:   Thm. west_thm (columns |m| > m0 of rows n = -1, 0, 1), through
+               K0(beta r) = int_0^inf cos(lam y) e^{-kappa |x|} / kappa dlam,
+               kappa = sqrt(lam^2 + beta^2).
+"""
+import numpy as np
+import pytest
+import scipy.special as sp
+
+import oracle
+import workloads as W
+
+
+@pytest.fixture(scope="module")
+def P():
+    import os
+    from paper_2111_01083_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2111_01083_amd import build
+        build.build()
+    import paper_2111_01083_amd as P
+    return P
+
+
+def _canonical(info, pts):
+    """User frame -> canonical frame (e1 = (d, 0), e2 = (xi, eta)), wrapped
+    into the cell u1 e1 + u2 e2, u in [-1/2, 1/2)^2."""
+    c, s = info["rot_cos"], info["rot_sin"]
+    R = np.array([[c, -s], [s, c]])
+    p = R @ pts
+    B = np.array([[info["d"], info["xi"]], [0.0, info["eta"]]])
+    u = np.linalg.solve(B, p)
+    u -= np.floor(u + 0.5)
+    return B @ u, R
+
+
+def yukawa_scheme(info, lam, wq, beta, src, q, trg):
+    d, xi, eta, m0, M = info["d"], info["xi"], info["eta"], info["m0"], info["n_modes"]
+    s, R = _canonical(info, src)
+    t, _ = _canonical(info, trg)
+    X = t[0][:, None] - s[0][None, :]           # [nt, ns]
+    Y = t[1][:, None] - s[1][None, :]
+    pot = np.zeros(t.shape[1]); gx = np.zeros_like(pot); gy = np.zeros_like(pot)
+    # near images
+    for n in (-1, 0, 1):
+        for m in range(-m0, m0 + 1):
+            dx = X - m * d - n * xi
+            dy = Y - n * eta
+            r = np.hypot(dx, dy)
+            pot += (sp.k0(beta * r) @ q) / (2 * np.pi)
+            k1r = beta * sp.k1(beta * r) / r
+            gx -= ((k1r * dx) @ q) / (2 * np.pi)
+            gy -= ((k1r * dy) @ q) / (2 * np.pi)
+    # south / north: rows n <= -2 and n >= 2, a geometric sum over the row index
+    m = np.arange(-M, M + 1)
+    al = 2 * np.pi * m / d
+    chi = np.sqrt(al * al + beta * beta)
+    Q = chi * eta - 1j * al * xi
+    DS = np.exp(-2 * Q) / (2 * d * chi * (1 - np.exp(-Q)))
+    Qn = chi * eta + 1j * al * xi
+    DN = np.exp(-2 * Qn) / (2 * d * chi * (1 - np.exp(-Qn)))
+    cS = (np.exp(chi[:, None] * s[1][None, :] - 1j * al[:, None] * s[0][None, :]) * q[None, :]).sum(1)
+    cN = (np.exp(-chi[:, None] * s[1][None, :] - 1j * al[:, None] * s[0][None, :]) * q[None, :]).sum(1)
+    eS = np.exp(-chi[None, :] * t[1][:, None] + 1j * al[None, :] * t[0][:, None]) * (DS * cS)[None, :]
+    eN = np.exp(chi[None, :] * t[1][:, None] + 1j * al[None, :] * t[0][:, None]) * (DN * cN)[None, :]
+    pot += (eS + eN).sum(1).real
+    gx += ((eS + eN) * (1j * al)[None, :]).sum(1).real
+    gy += ((-eS + eN) * chi[None, :]).sum(1).real
+    # west / east: columns m >= m0 + 1 (east) and m <= -(m0 + 1) (west) of rows -1, 0, 1
+    kap = np.sqrt(lam * lam + beta * beta)
+    geo = np.exp(-kap * (m0 + 1) * d) / (1 - np.exp(-kap * d))      # sum over |m| >= m0 + 1
+    for n in (-1, 0, 1):
+        Yn = (Y - n * eta)[..., None]
+        cosl, sinl = np.cos(lam * Yn), np.sin(lam * Yn)
+        east = np.exp(kap * (X[..., None] - n * xi))     # e^{-kappa |x - x_j - m d - n xi|}, m > 0, / e^{-kappa m d}
+        west = np.exp(-kap * (X[..., None] - n * xi))
+        base = wq * geo / kap / (2 * np.pi)
+        pot += (((east + west) * cosl * base).sum(-1)) @ q
+        gx += (((east - west) * kap * cosl * base).sum(-1)) @ q
+        gy += ((-(east + west) * lam * sinl * base).sum(-1)) @ q
+    grad = R.T @ np.vstack([gx, gy])
+    return pot, grad
+
+
+@pytest.mark.parametrize("cell", [((1.0, 0.0), (0.0, 1.0)), ((2.0, 0.0), (0.4, 1.0)),
+                                  ((1.1, 0.35), (-0.2, 0.9)), ((1.0, 0.0), (0.5, np.sqrt(3) / 2)),
+                                  ((10.0, 0.0), (1.5, 1.0))])
+@pytest.mark.parametrize("beta", [0.5, 3.0])
+def test_yukawa_scheme_from_plan_matches_oracle(P, cell, beta):
+    e1, e2 = cell
+    rng = np.random.default_rng(31)
+    src = W.cell_points(rng, e1, e2, 40)
+    trg = W.cell_points(rng, e1, e2, 25)
+    q = rng.standard_normal(40)
+    po, go = oracle.yukawa(e1, e2, beta, src, q, trg)
+    for tol in (1e-6, 1e-10):
+        plan = P.Plan("yukawa", e1, e2, tol, beta=beta)
+        info = plan.info
+        lam, wq = plan.quadrature()
+        pot, grad = yukawa_scheme(info, lam, wq, beta, src, q, trg)
+        ep = np.linalg.norm(pot - po) / np.linalg.norm(po)
+        eg = np.linalg.norm(grad - go) / np.linalg.norm(go)
+        assert ep < tol and eg < tol, (tol, ep, eg, info["m0"], info["n_modes"], len(lam))
