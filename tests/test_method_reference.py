@@ -1,4 +1,4 @@
-"""CPU restatement of the periodic scheme for the modified Helmholtz kernel,
+"""CPU restatement of the periodic scheme for the modified Helmholtz and Laplace kernels,
 written from the paper's formulas with numpy/scipy, fed with the planner's
 host outputs only (canonical lattice and rotation, near-region width m0,
 south/north truncation M, west/east quadrature nodes and weights), and
@@ -13,6 +13,11 @@ the paper's theorems were, the scheme would miss the oracle.
   west/east:   Thm. west_thm (columns |m| > m0 of rows n = -1, 0, 1), through
                K0(beta r) = int_0^inf cos(lam y) e^{-kappa |x|} / kappa dlam,
                kappa = sqrt(lam^2 + beta^2).
+The Laplace version takes the beta -> 0 limits (Thm. south_thm_lap): modes
+m != 0 with |alpha_m|, the m = 0 term -y P_y / (d eta) plus the constant
+sum_j q_j y_j^2 / (2 d eta) of the zero-mean convention, and west and east
+together, each image's constant removed (neutral charges), so that the
+integrand stays regular at lam = 0.
 """
 import numpy as np
 import pytest
@@ -93,6 +98,53 @@ def yukawa_scheme(info, lam, wq, beta, src, q, trg):
     return pot, grad
 
 
+def laplace_scheme(info, lam, wq, src, q, trg):
+    d, xi, eta, m0, M = info["d"], info["xi"], info["eta"], info["m0"], info["n_modes"]
+    s, R = _canonical(info, src)
+    t, _ = _canonical(info, trg)
+    X = t[0][:, None] - s[0][None, :]
+    Y = t[1][:, None] - s[1][None, :]
+    pot = np.zeros(t.shape[1]); gx = np.zeros_like(pot); gy = np.zeros_like(pot)
+    # near images
+    for n in (-1, 0, 1):
+        for m in range(-m0, m0 + 1):
+            dx = X - m * d - n * xi; dy = Y - n * eta
+            r2 = dx * dx + dy * dy
+            pot += (-0.5 * np.log(r2) @ q) / (2 * np.pi)
+            gx -= ((dx / r2) @ q) / (2 * np.pi)
+            gy -= ((dy / r2) @ q) / (2 * np.pi)
+    # south / north, modes m != 0
+    m = np.concatenate([np.arange(-M, 0), np.arange(1, M + 1)])
+    al = 2 * np.pi * m / d
+    chi = np.abs(al)
+    Q = chi * eta - 1j * al * xi
+    DS = np.exp(-2 * Q) / (4 * np.pi * np.abs(m) * (1 - np.exp(-Q)))
+    Qn = chi * eta + 1j * al * xi
+    DN = np.exp(-2 * Qn) / (4 * np.pi * np.abs(m) * (1 - np.exp(-Qn)))
+    cS = (np.exp(chi[:, None] * s[1][None, :] - 1j * al[:, None] * s[0][None, :]) * q[None, :]).sum(1)
+    cN = (np.exp(-chi[:, None] * s[1][None, :] - 1j * al[:, None] * s[0][None, :]) * q[None, :]).sum(1)
+    eS = np.exp(-chi[None, :] * t[1][:, None] + 1j * al[None, :] * t[0][:, None]) * (DS * cS)[None, :]
+    eN = np.exp(chi[None, :] * t[1][:, None] + 1j * al[None, :] * t[0][:, None]) * (DN * cN)[None, :]
+    pot += (eS + eN).sum(1).real
+    gx += ((eS + eN) * (1j * al)[None, :]).sum(1).real
+    gy += ((-eS + eN) * chi[None, :]).sum(1).real
+    # m = 0 south + north and the zero-mean constant
+    Py = (q * s[1]).sum()
+    pot += -t[1] * Py / (d * eta) + (q * s[1] ** 2).sum() / (2 * d * eta)
+    gy += -Py / (d * eta)
+    # west + east together (regular at lam = 0 after removing the constant of each image)
+    geo = np.exp(-lam * (m0 + 1) * d) / (1 - np.exp(-lam * d))
+    base = wq * geo / lam / (2 * np.pi)
+    for n in (-1, 0, 1):
+        Xn = (X - n * xi)[..., None]; Yn = (Y - n * eta)[..., None]
+        ch, sh = np.cosh(lam * Xn), np.sinh(lam * Xn)
+        c, sn = np.cos(lam * Yn), np.sin(lam * Yn)
+        pot += ((2 * (ch * c - 1) * base).sum(-1)) @ q
+        gx += ((2 * lam * sh * c * base).sum(-1)) @ q
+        gy += ((-2 * lam * ch * sn * base).sum(-1)) @ q
+    return pot, R.T @ np.vstack([gx, gy])
+
+
 @pytest.mark.parametrize("cell", [((1.0, 0.0), (0.0, 1.0)), ((2.0, 0.0), (0.4, 1.0)),
                                   ((1.1, 0.35), (-0.2, 0.9)), ((1.0, 0.0), (0.5, np.sqrt(3) / 2)),
                                   ((10.0, 0.0), (1.5, 1.0))])
@@ -109,6 +161,26 @@ def test_yukawa_scheme_from_plan_matches_oracle(P, cell, beta):
         info = plan.info
         lam, wq = plan.quadrature()
         pot, grad = yukawa_scheme(info, lam, wq, beta, src, q, trg)
+        ep = np.linalg.norm(pot - po) / np.linalg.norm(po)
+        eg = np.linalg.norm(grad - go) / np.linalg.norm(go)
+        assert ep < tol and eg < tol, (tol, ep, eg, info["m0"], info["n_modes"], len(lam))
+
+
+@pytest.mark.parametrize("cell", [((1.0, 0.0), (0.0, 1.0)), ((2.0, 0.0), (0.4, 1.0)),
+                                  ((1.1, 0.35), (-0.2, 0.9)), ((1.0, 0.0), (0.5, np.sqrt(3) / 2)),
+                                  ((10.0, 0.0), (1.5, 1.0))])
+def test_laplace_scheme_from_plan_matches_oracle(P, cell):
+    e1, e2 = cell
+    rng = np.random.default_rng(31)
+    src = W.cell_points(rng, e1, e2, 40)
+    trg = W.cell_points(rng, e1, e2, 25)
+    q = W.neutral_charges(rng, 40)
+    po, go = oracle.laplace(e1, e2, src, q, trg)
+    for tol in (1e-6, 1e-10):
+        plan = P.Plan("laplace", e1, e2, tol)
+        info = plan.info
+        lam, wq = plan.quadrature()
+        pot, grad = laplace_scheme(info, lam, wq, src, q, trg)
         ep = np.linalg.norm(pot - po) / np.linalg.norm(po)
         eg = np.linalg.norm(grad - go) / np.linalg.norm(go)
         assert ep < tol and eg < tol, (tol, ep, eg, info["m0"], info["n_modes"], len(lam))
