@@ -1,4 +1,4 @@
-"""CPU restatement of the periodic scheme for the modified Helmholtz and Laplace kernels,
+"""CPU restatement of the periodic scheme for the modified Helmholtz, Laplace and Stokes kernels,
 written from the paper's formulas with numpy/scipy, fed with the planner's
 host outputs only (canonical lattice and rotation, near-region width m0,
 south/north truncation M, west/east quadrature nodes and weights), and
@@ -17,7 +17,11 @@ The Laplace version takes the beta -> 0 limits (Thm. south_thm_lap): modes
 m != 0 with |alpha_m|, the m = 0 term -y P_y / (d eta) plus the constant
 sum_j q_j y_j^2 / (2 d eta) of the zero-mean convention, and west and east
 together, each image's constant removed (neutral charges), so that the
-integrand stays regular at lam = 0.
+integrand stays regular at lam = 0. The Stokes version is derived here from
+the Stokeslet symbol (I - k k^T / k^2) / k^2 rather than transcribed from
+Thms. south_thm_s and west_thm_s: south/north by Poisson summation along the
+rows with a geometric sum over them, the m = 0 term on u1 only, west/east
+from the 1D transforms of the symbol in x.
 """
 import numpy as np
 import pytest
@@ -145,6 +149,92 @@ def laplace_scheme(info, lam, wq, src, q, trg):
     return pot, R.T @ np.vstack([gx, gy])
 
 
+def stokes_scheme(info, lam, wq, src, f, trg):
+    d, xi, eta, m0, M = info["d"], info["xi"], info["eta"], info["m0"], info["n_modes"]
+    s, R = _canonical(info, src)
+    t, _ = _canonical(info, trg)
+    f1, f2 = R @ f                               # forces in the canonical frame
+    X = t[0][:, None] - s[0][None, :]
+    Y = t[1][:, None] - s[1][None, :]
+    nt = t.shape[1]
+    u = np.zeros((2, nt))
+    g = np.zeros((2, 2, nt))                     # g[i, k] = d u_i / d x_k
+
+    def apply(txx, txy, tyy):                    # sum_j T_j f_j for a symmetric 2x2 T
+        return np.array([txx @ f1 + txy @ f2, txy @ f1 + tyy @ f2])
+
+    # near images: G = (1/4pi)(-log r I + r r^T / r^2)
+    c4 = 1 / (4 * np.pi)
+    for n in (-1, 0, 1):
+        for m in range(-m0, m0 + 1):
+            r = (X - m * d - n * xi, Y - n * eta)
+            r2 = r[0] ** 2 + r[1] ** 2
+            L = -0.5 * np.log(r2)
+            u += c4 * apply(L + r[0] ** 2 / r2, r[0] * r[1] / r2, L + r[1] ** 2 / r2)
+            for k in range(2):
+                def dG(i, j):
+                    return c4 * (-(i == j) * r[k] / r2 + ((k == i) * r[j] + (k == j) * r[i]) / r2
+                                 - 2 * r[i] * r[j] * r[k] / (r2 * r2))
+                g[:, k] += apply(dG(0, 0), dG(0, 1), dG(1, 1))
+    # south (rows n <= -2) and north (n >= 2), modes m != 0: Poisson summation
+    # in x turns a row at offset Y_n into (1/d) sum_m T(alpha_m, Y_n) e^{i alpha_m X_n},
+    # with, for a = |alpha|, |Y_n| = y:  T_xx = (1 - a y) e^{-a y} / (4a),
+    # T_yy = (1 + a y) e^{-a y} / (4a), T_xy = -i alpha Y_n e^{-a y} / (4a);
+    # the rows then sum geometrically (S0 = sum_{p>=2} e^{-pQ}, S1 = sum p e^{-pQ})
+    for mm in list(range(-M, 0)) + list(range(1, M + 1)):
+        al = 2 * np.pi * mm / d
+        a = abs(al)
+        for side in (-1, 1):
+            E = np.exp(-(a * eta + side * 1j * al * xi))
+            S0 = E * E / (1 - E)
+            S1 = E * E * (2 - E) / (1 - E) ** 2
+            c = np.exp(side * a * Y + 1j * al * X) / (4 * a * d)
+            xx = c * ((1 + side * a * Y) * S0 - a * eta * S1)
+            yy = c * ((1 - side * a * Y) * S0 + a * eta * S1)
+            xy = c * (1j * al) * (side * eta * S1 - Y * S0)
+            dxx = side * a * xx + side * c * a * S0
+            dyy = side * a * yy - side * c * a * S0
+            dxy = side * a * xy - c * (1j * al) * S0
+            u += apply(xx, xy, yy).real
+            g[:, 0] += apply(1j * al * xx, 1j * al * xy, 1j * al * yy).real
+            g[:, 1] += apply(dxx, dxy, dyy).real
+    # m = 0: u1 only (T_xx(0, k_y) = 1/k_y^2, the Laplace symbol), plus the zero-mean constant
+    P1 = (f1 * s[1]).sum()
+    u[0] += -t[1] * P1 / (d * eta) + (f1 * s[1] ** 2).sum() / (2 * d * eta)
+    g[0, 1] += -P1 / (d * eta)
+    # west + east (rows -1, 0, 1; columns |m| >= p = m0 + 1) from
+    #   G_xx = (1/pi) int cos(lam Y) (1 + lam|X|) e^{-lam|X|} / (4 lam),
+    #   G_yy = (1/pi) int cos(lam Y) (1 - lam|X|) e^{-lam|X|} / (4 lam),
+    #   G_xy = (1/pi) int sin(lam Y) X e^{-lam|X|} / 4,
+    # summed over the columns (A = sum e^{-lam|X|}, B = sum |X| e^{-lam|X|});
+    # the part of G_xx, G_yy that does not depend on the pair is removed (zero net force)
+    p = m0 + 1
+    ed = np.exp(-lam * d)
+    T0 = np.exp(-lam * p * d) / (1 - ed)
+    T1 = np.exp(-lam * p * d) * (p - (p - 1) * ed) / (1 - ed) ** 2
+    w = wq / np.pi
+    xx_ref = (2 * T0 + 2 * lam * d * T1) / (4 * lam)
+    yy_ref = (2 * T0 - 2 * lam * d * T1) / (4 * lam)
+    for n in (-1, 0, 1):
+        X0 = (X - n * xi)[..., None]
+        Yn = (Y - n * eta)[..., None]
+        AE, AW = np.exp(lam * X0) * T0, np.exp(-lam * X0) * T0
+        BE, BW = np.exp(lam * X0) * (d * T1 - X0 * T0), np.exp(-lam * X0) * (X0 * T0 + d * T1)
+        A, B = AE + AW, BE + BW
+        cs, sn = np.cos(lam * Yn), np.sin(lam * Yn)
+        u += apply(((cs * (A + lam * B) / (4 * lam) - xx_ref) * w).sum(-1), ((0.25 * (BW - BE) * sn) * w).sum(-1),
+                   ((cs * (A - lam * B) / (4 * lam) - yy_ref) * w).sum(-1))
+        dA = lam * (AE - AW)
+        dB = lam * (BE - BW) - AE + AW
+        g[:, 0] += apply((cs * (dA + lam * dB) / (4 * lam) * w).sum(-1),
+                         (0.25 * (AW + AE - lam * (BW + BE)) * sn * w).sum(-1),
+                         (cs * (dA - lam * dB) / (4 * lam) * w).sum(-1))
+        g[:, 1] += apply((-sn * (A + lam * B) / 4 * w).sum(-1), (0.25 * (BW - BE) * lam * cs * w).sum(-1),
+                         (-sn * (A - lam * B) / 4 * w).sum(-1))
+    # back to the caller's frame: u -> R^T u, grad u -> R^T (grad u) R
+    return R.T @ u, np.einsum("ji,jkt,kl->ilt", R, g, R).reshape(4, nt)
+
+
 @pytest.mark.parametrize("cell", [((1.0, 0.0), (0.0, 1.0)), ((2.0, 0.0), (0.4, 1.0)),
                                   ((1.1, 0.35), (-0.2, 0.9)), ((1.0, 0.0), (0.5, np.sqrt(3) / 2)),
                                   ((10.0, 0.0), (1.5, 1.0))])
@@ -184,3 +274,23 @@ def test_laplace_scheme_from_plan_matches_oracle(P, cell):
         ep = np.linalg.norm(pot - po) / np.linalg.norm(po)
         eg = np.linalg.norm(grad - go) / np.linalg.norm(go)
         assert ep < tol and eg < tol, (tol, ep, eg, info["m0"], info["n_modes"], len(lam))
+
+
+@pytest.mark.parametrize("cell", [((1.0, 0.0), (0.0, 1.0)), ((2.0, 0.0), (0.4, 1.0)),
+                                  ((1.1, 0.35), (-0.2, 0.9)), ((1.0, 0.0), (0.5, np.sqrt(3) / 2)),
+                                  ((10.0, 0.0), (1.5, 1.0))])
+def test_stokes_scheme_from_plan_matches_oracle(P, cell):
+    e1, e2 = cell
+    rng = np.random.default_rng(31)
+    src = W.cell_points(rng, e1, e2, 40)
+    trg = W.cell_points(rng, e1, e2, 25)
+    f = W.neutral_forces(rng, 40)
+    uo, go = oracle.stokes(e1, e2, src, f, trg)
+    for tol in (1e-6, 1e-10):
+        plan = P.Plan("stokes", e1, e2, tol)
+        info = plan.info
+        lam, wq = plan.quadrature()
+        u, grad = stokes_scheme(info, lam, wq, src, f, trg)
+        eu = np.linalg.norm(u - uo) / np.linalg.norm(uo)
+        eg = np.linalg.norm(grad - go) / np.linalg.norm(go)
+        assert eu < tol and eg < tol, (tol, eu, eg, info["m0"], info["n_modes"], len(lam))
