@@ -1,5 +1,5 @@
 // Device kernels of the periodic evaluator (gfx950):
-//   prep   -- rotate/wrap points into the canonical cell; two-float FP32 copies
+//   prep   -- rotate/wrap points into the canonical cell; FP64 (and, mixed, FP32) densities
 //   near   -- direct sum over the cell and its nearest images (Def. 1)
 //   far_R  -- sources -> plane-wave coefficients (R of P = L D R, Sec. 6)
 //   far_D  -- chunk reduction and the diagonal weights D
@@ -540,7 +540,7 @@ __global__ __launch_bounds__(NEAR_BLOCK) void near_kernel(NearArgs a) {
 // vectors at once. Sources pass through LDS in sub-tiles of 64; in step st
 // lane t pairs its point with source (t + st) mod 64, so within a wavefront
 // every lane works on a different source and the source-side sums go to a
-// per-wavefront LDS row without conflicts or atomics. The 9 (or 15) images of
+// per-wavefront LDS row without conflicts or atomics. The 9, 15 or 21 images of
 // a pair are summed in registers first (density-free moments, below), then
 // multiplied by both points' densities in FP64. Each sub-tile's source-side
 // sums and, at the end, each thread's own sums are converted to outputs and
