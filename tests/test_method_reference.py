@@ -21,7 +21,9 @@ integrand stays regular at lam = 0. The Stokes version is derived here from
 the Stokeslet symbol (I - k k^T / k^2) / k^2 rather than transcribed from
 Thms. south_thm_s and west_thm_s: south/north by Poisson summation along the
 rows with a geometric sum over them, the m = 0 term on u1 only, west/east
-from the 1D transforms of the symbol in x.
+from the 1D transforms of the symbol in x. Last, the NUFFT form of the
+Laplace south/north sums (Sec. 6.1) with the planner's grid, width and line
+count must reproduce the direct sums to well below tol.
 """
 import numpy as np
 import pytest
@@ -294,3 +296,112 @@ def test_stokes_scheme_from_plan_matches_oracle(P, cell):
         eu = np.linalg.norm(u - uo) / np.linalg.norm(uo)
         eg = np.linalg.norm(grad - go) / np.linalg.norm(go)
         assert eu < tol and eg < tol, (tol, eu, eg, info["m0"], info["n_modes"], len(lam))
+
+
+# --- NUFFT form of the south/north sums (Sec. 6.1) --------------------------
+# Sources and targets are interpolated in y onto M_GL Gauss-Legendre lines
+# (Lagrange basis at the lines), and the x sums along each line are type-1 /
+# type-2 NUFFTs with the exponential-of-semicircle kernel
+# phi(z) = exp(b (sqrt(1 - z^2) - 1)), b = 0.97 pi (1 - 1/(2 sigma)) w, on the
+# planner's grid n_f (oversampling sigma = 2, or 4 on the doubled grid) and
+# width w, deconvolved by phi's Fourier transform.
+
+def _es(info, grid):
+    w, nf, d = info["nufft_w"], info["nufft_nf"], info["d"]
+    b = 0.97 * np.pi * (1 - 1 / (2 * (4.0 if grid else 2.0))) * w
+    h = d / nf
+    s = w * h / 2
+
+    def phi(z):
+        return np.where(np.abs(z) <= 1, np.exp(b * (np.sqrt(np.maximum(0.0, 1 - z * z)) - 1)), 0.0)
+
+    z, wz = np.polynomial.legendre.leggauss(4 * w + 60)
+
+    def phihat(al):                              # int phi(x / s) e^{-i al x} dx
+        return s * (wz[None, :] * phi(z)[None, :] * np.cos(np.outer(al, s * z))).sum(1)
+    return phi, phihat, h, s, nf, w
+
+
+def _type1(es, d, x, c, al):
+    """F_m = sum_j c_j e^{-i al_m x_j} (period d): spread, FFT, deconvolve."""
+    phi, phihat, h, s, nf, w = es
+    g = np.zeros(nf)
+    for xj, cj in zip(x, c):
+        ls = np.arange(int(np.floor((xj - s) / h)), int(np.floor((xj - s) / h)) + w + 3)
+        np.add.at(g, np.mod(ls, nf), cj * phi((xj - ls * h) / s))
+    m = np.rint(al * d / (2 * np.pi)).astype(int)
+    return np.fft.fft(g)[np.mod(m, nf)] * h / phihat(al)
+
+
+def _type2(es, d, G, al, x):
+    """v(x) = sum_m G_m e^{i al_m x}: deconvolve, inverse FFT, interpolate."""
+    phi, phihat, h, s, nf, w = es
+    spec = np.zeros(nf, complex)
+    np.add.at(spec, np.mod(np.rint(al * d / (2 * np.pi)).astype(int), nf), G / phihat(al))
+    grid = np.fft.ifft(spec) * nf
+    out = np.zeros(len(x), complex)
+    for i, xt in enumerate(x):
+        ls = np.arange(int(np.floor((xt - s) / h)), int(np.floor((xt - s) / h)) + w + 3)
+        out[i] = (grid[np.mod(ls, nf)] * phi((xt - ls * h) / s)).sum() * h
+    return out
+
+
+def _lagrange(nodes, y):
+    L = np.ones((len(nodes), len(y)))
+    for k in range(len(nodes)):
+        for i in range(len(nodes)):
+            if i != k:
+                L[k] *= (y - nodes[i]) / (nodes[k] - nodes[i])
+    return L
+
+
+def laplace_south_north(info, src, q, trg, grid=None):
+    """The m != 0 south/north field of the Laplace scheme, directly (grid None)
+    or through the NUFFT form on the given grid."""
+    d, xi, eta, M = info["d"], info["xi"], info["eta"], info["n_modes"]
+    s, _ = _canonical(info, src)
+    t, _ = _canonical(info, trg)
+    m = np.concatenate([np.arange(-M, 0), np.arange(1, M + 1)])
+    al = 2 * np.pi * m / d
+    chi = np.abs(al)
+    DS = np.exp(-2 * (chi * eta - 1j * al * xi)) / (4 * np.pi * np.abs(m) * (1 - np.exp(-(chi * eta - 1j * al * xi))))
+    DN = np.exp(-2 * (chi * eta + 1j * al * xi)) / (4 * np.pi * np.abs(m) * (1 - np.exp(-(chi * eta + 1j * al * xi))))
+    if grid is None:
+        cS = (np.exp(chi[:, None] * s[1][None, :] - 1j * al[:, None] * s[0][None, :]) * q[None, :]).sum(1)
+        cN = (np.exp(-chi[:, None] * s[1][None, :] - 1j * al[:, None] * s[0][None, :]) * q[None, :]).sum(1)
+        eS = np.exp(-chi[None, :] * t[1][:, None] + 1j * al[None, :] * t[0][:, None]) * (DS * cS)[None, :]
+        eN = np.exp(chi[None, :] * t[1][:, None] + 1j * al[None, :] * t[0][:, None]) * (DN * cN)[None, :]
+        return (eS + eN).sum(1).real
+    es = _es(info, grid)
+    yb = 0.5 * eta * np.polynomial.legendre.leggauss(info["m_gl"])[0]
+    gs, gt = _lagrange(yb, s[1]), _lagrange(yb, t[1])
+    F = np.array([_type1(es, d, s[0], q * gs[k], al) for k in range(len(yb))])
+    wS = DS * (np.exp(chi[None, :] * yb[:, None]) * F).sum(0)
+    wN = DN * (np.exp(-chi[None, :] * yb[:, None]) * F).sum(0)
+    out = np.zeros(t.shape[1])
+    for k in range(len(yb)):
+        out += (gt[k] * _type2(es, d, wS * np.exp(-chi * yb[k]) + wN * np.exp(chi * yb[k]), al, t[0])).real
+    return out
+
+
+@pytest.mark.parametrize("cell", [((100.0, 0.0), (0.0, 1.0)), ((20.0, 0.0), (3.0, 1.0)),
+                                  ((30.0, 0.0), (7.0, 1.0))])
+@pytest.mark.parametrize("tol", [1e-6, 1e-10])
+def test_nufft_parameters_from_plan_reach_tol(P, cell, tol):
+    # clustered sources (the high-aspect workload's blobs); the NUFFT form with
+    # the planner's n_f, w and M_GL must reproduce the direct south/north
+    # field to well below tol of the whole potential, on both grids
+    e1, e2 = cell
+    rng = np.random.default_rng(5)
+    src = W.blob_points(rng, e1, e2, 300)
+    trg = W.cell_points(rng, e1, e2, 60)
+    q = W.neutral_charges(rng, 300)
+    po, _ = oracle.laplace(e1, e2, src, q, trg)
+    plan = P.Plan("laplace", e1, e2, tol, far_mode="nufft")
+    direct = laplace_south_north(plan.info, src, q, trg)
+    for grid in (0, 1):
+        if grid:
+            plan.set_tuning(nufft_grid=1)
+        info = plan.info
+        err = np.linalg.norm(laplace_south_north(info, src, q, trg, grid) - direct) / np.linalg.norm(po)
+        assert err < 0.1 * tol, (grid, err, info["nufft_nf"], info["nufft_w"], info["m_gl"])
