@@ -13,8 +13,11 @@ are arrays of shape (2, n) (row 0 = x, row 1 = y) in float64.
 
 Parity status: every function here is pinned by ``tests/test_oracle.py``
 (split-parameter independence, agreement of two independent Laplace
-formulas, free-space limits, lattice periodicity, Yukawa -> Laplace limit,
-divergence-free Stokes velocity, library special functions).
+formulas, Yukawa and Stokes against spectral sums by Poisson summation over
+rows of images -- no Ewald split, no Bessel function; the Stokes one also
+fixes the zero-mean constant -- free-space limits, lattice periodicity,
+Yukawa -> Laplace limit, divergence-free Stokes velocity, library special
+functions).
 """
 import ctypes
 import os
