@@ -240,8 +240,11 @@ def stokes_scheme(info, lam, wq, src, f, trg):
 @pytest.mark.parametrize("cell", [((1.0, 0.0), (0.0, 1.0)), ((2.0, 0.0), (0.4, 1.0)),
                                   ((1.1, 0.35), (-0.2, 0.9)), ((1.0, 0.0), (0.5, np.sqrt(3) / 2)),
                                   ((10.0, 0.0), (1.5, 1.0))])
-@pytest.mark.parametrize("beta", [0.5, 3.0])
+@pytest.mark.parametrize("beta", [0.5, 3.0, 10.0])
 def test_yukawa_scheme_from_plan_matches_oracle(P, cell, beta):
+    # beta = 10 on the square cell: the planner drops the west/east part and
+    # all but a few south/north modes as negligible (their whole factor is
+    # below eps); the scheme must still meet tol
     e1, e2 = cell
     rng = np.random.default_rng(31)
     src = W.cell_points(rng, e1, e2, 40)
@@ -405,3 +408,36 @@ def test_nufft_parameters_from_plan_reach_tol(P, cell, tol):
         info = plan.info
         err = np.linalg.norm(laplace_south_north(info, src, q, trg, grid) - direct) / np.linalg.norm(po)
         assert err < 0.1 * tol, (grid, err, info["nufft_nf"], info["nufft_w"], info["m_gl"])
+
+
+@pytest.mark.parametrize("tol", [1e-6, 1e-10])
+def test_yukawa_near_cutoff_drops_less_than_eps(P, tol):
+    # the screened near field leaves out pairs farther apart than r_c with
+    # e^{-beta r_c} = eps / 30; on uniform sources (the benchmark's
+    # distribution, square cell, beta = 10) what is left out stays below eps
+    # of the potential and of the gradient
+    e1, e2 = (1.0, 0.0), (0.0, 1.0)
+    beta = 10.0
+    plan = P.Plan("yukawa", e1, e2, tol, beta=beta)
+    eps = plan.info["eps"]
+    rc = np.log(30.0 / eps) / beta
+    rng = np.random.default_rng(17)
+    n = 1500
+    src = W.cell_points(rng, e1, e2, n)
+    q = W.neutral_charges(rng, n)
+    trg = src[:, :300]
+    pot = np.zeros(300); gx = np.zeros(300); gy = np.zeros(300)
+    dpot = np.zeros(300); dgx = np.zeros(300); dgy = np.zeros(300)
+    for n_ in (-1, 0, 1):
+        for m in (-1, 0, 1):
+            dx = trg[0][:, None] - src[0][None, :] - m
+            dy = trg[1][:, None] - src[1][None, :] - n_
+            r = np.hypot(dx, dy)
+            r = np.where(r == 0, np.inf, r)        # the self pair
+            k0 = sp.k0(beta * r) / (2 * np.pi)
+            k1r = beta * sp.k1(beta * r) / r / (2 * np.pi)
+            far = r > rc
+            pot += k0 @ q; gx -= (k1r * dx) @ q; gy -= (k1r * dy) @ q
+            dpot += (k0 * far) @ q; dgx -= (k1r * dx * far) @ q; dgy -= (k1r * dy * far) @ q
+    assert np.linalg.norm(dpot) < eps * np.linalg.norm(pot)
+    assert np.hypot(np.linalg.norm(dgx), np.linalg.norm(dgy)) < eps * np.hypot(np.linalg.norm(gx), np.linalg.norm(gy))
