@@ -358,17 +358,19 @@ def _lagrange(nodes, y):
     return L
 
 
-def laplace_south_north(info, src, q, trg, grid=None):
-    """The m != 0 south/north field of the Laplace scheme, directly (grid None)
-    or through the NUFFT form on the given grid."""
+def south_north(info, beta, src, q, trg, grid=None):
+    """The south/north field of the scheme (beta = 0: Laplace, modes m != 0;
+    else Yukawa, all modes), directly (grid None) or through the NUFFT form
+    on the given grid."""
     d, xi, eta, M = info["d"], info["xi"], info["eta"], info["n_modes"]
     s, _ = _canonical(info, src)
     t, _ = _canonical(info, trg)
-    m = np.concatenate([np.arange(-M, 0), np.arange(1, M + 1)])
+    m = np.concatenate([np.arange(-M, 0), np.arange(1, M + 1)]) if beta == 0 else np.arange(-M, M + 1)
     al = 2 * np.pi * m / d
-    chi = np.abs(al)
-    DS = np.exp(-2 * (chi * eta - 1j * al * xi)) / (4 * np.pi * np.abs(m) * (1 - np.exp(-(chi * eta - 1j * al * xi))))
-    DN = np.exp(-2 * (chi * eta + 1j * al * xi)) / (4 * np.pi * np.abs(m) * (1 - np.exp(-(chi * eta + 1j * al * xi))))
+    chi = np.sqrt(al * al + beta * beta)
+    Q, Qn = chi * eta - 1j * al * xi, chi * eta + 1j * al * xi
+    DS = np.exp(-2 * Q) / (2 * d * chi * (1 - np.exp(-Q)))      # 1 / (2 d chi) = 1 / (4 pi |m|) for Laplace
+    DN = np.exp(-2 * Qn) / (2 * d * chi * (1 - np.exp(-Qn)))
     if grid is None:
         cS = (np.exp(chi[:, None] * s[1][None, :] - 1j * al[:, None] * s[0][None, :]) * q[None, :]).sum(1)
         cN = (np.exp(-chi[:, None] * s[1][None, :] - 1j * al[:, None] * s[0][None, :]) * q[None, :]).sum(1)
@@ -389,25 +391,31 @@ def laplace_south_north(info, src, q, trg, grid=None):
 
 @pytest.mark.parametrize("cell", [((100.0, 0.0), (0.0, 1.0)), ((20.0, 0.0), (3.0, 1.0)),
                                   ((30.0, 0.0), (7.0, 1.0))])
+@pytest.mark.parametrize("kernel,beta,share", [("laplace", 0.0, 0.1), ("yukawa", 0.5, 0.1), ("yukawa", 5.0, 0.5)])
 @pytest.mark.parametrize("tol", [1e-6, 1e-10])
-def test_nufft_parameters_from_plan_reach_tol(P, cell, tol):
+def test_nufft_parameters_from_plan_reach_tol(P, cell, kernel, beta, share, tol):
     # clustered sources (the high-aspect workload's blobs); the NUFFT form with
     # the planner's n_f, w and M_GL must reproduce the direct south/north
-    # field to well below tol of the whole potential, on both grids
+    # field to below share * tol of the whole potential, on both grids (with
+    # beta = 5 the factors e^{chi y} interpolated across the lines are steeper)
     e1, e2 = cell
     rng = np.random.default_rng(5)
     src = W.blob_points(rng, e1, e2, 300)
     trg = W.cell_points(rng, e1, e2, 60)
-    q = W.neutral_charges(rng, 300)
-    po, _ = oracle.laplace(e1, e2, src, q, trg)
-    plan = P.Plan("laplace", e1, e2, tol, far_mode="nufft")
-    direct = laplace_south_north(plan.info, src, q, trg)
+    if kernel == "laplace":
+        q = W.neutral_charges(rng, 300)
+        po, _ = oracle.laplace(e1, e2, src, q, trg)
+    else:
+        q = rng.standard_normal(300)
+        po, _ = oracle.yukawa(e1, e2, beta, src, q, trg, tol=1e-13)
+    plan = P.Plan(kernel, e1, e2, tol, beta=beta, far_mode="nufft")
+    direct = south_north(plan.info, beta, src, q, trg)
     for grid in (0, 1):
         if grid:
             plan.set_tuning(nufft_grid=1)
         info = plan.info
-        err = np.linalg.norm(laplace_south_north(info, src, q, trg, grid) - direct) / np.linalg.norm(po)
-        assert err < 0.1 * tol, (grid, err, info["nufft_nf"], info["nufft_w"], info["m_gl"])
+        err = np.linalg.norm(south_north(info, beta, src, q, trg, grid) - direct) / np.linalg.norm(po)
+        assert err < share * tol, (grid, err, info["nufft_nf"], info["nufft_w"], info["m_gl"])
 
 
 @pytest.mark.parametrize("tol", [1e-6, 1e-10])
