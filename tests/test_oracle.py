@@ -331,3 +331,24 @@ def test_stokes_periodic_and_tight_pair_free_space():
     u, g = oracle.stokes((1.0, 0.0), (0.0, 1.0), src, f, trg)
     uf, gf = oracle.free_space("stokes", src, f, trg)
     assert np.max(np.abs(u - uf)) < 10 * delta and rel(g, gf) < 10 * delta
+
+
+# --- reciprocity (self targets) ---------------------------------------------
+
+@pytest.mark.parametrize("kernel,beta", [("laplace", 0.0), ("yukawa", 2.5), ("stokes", 0.0)])
+def test_reciprocity_at_the_sources(kernel, beta):
+    # the periodic kernel is symmetric, G(x_i - x_j) = G(x_j - x_i), so with
+    # targets = sources sum_i g_i . u[q](x_i) = sum_j q_j . u[g](x_j); an image
+    # set or reciprocal-space sum that is not symmetric under l -> -l breaks
+    # it (the self term is diagonal and is pinned by the split independence)
+    rng = np.random.default_rng(23)
+    n = 14
+    src = W.cell_points(rng, *GENERAL, n)
+    if kernel == "stokes":
+        q, g = W.neutral_forces(rng, n), W.neutral_forces(rng, n)
+    else:
+        q, g = W.neutral_charges(rng, n), W.neutral_charges(rng, n)
+    uq, _ = oracle.evaluate(kernel, *GENERAL, src, q, None, beta=beta)
+    ug, _ = oracle.evaluate(kernel, *GENERAL, src, g, None, beta=beta)
+    a, b = np.sum(g * uq), np.sum(q * ug)
+    assert abs(a - b) < 1e-12 * (abs(a) + abs(b)), (a, b)
