@@ -162,7 +162,9 @@ size_t pfmm_workspace_bytes(pfmm_plan_t plan, int64_t n_src, int64_t n_trg);
 
 /* Evaluate potentials and gradients (see the conventions above). out_pot
  * or out_grad may be NULL to skip that output. hip_stream: hipStream_t
- * (NULL = default stream). */
+ * (NULL = default stream). n_src = 0 is allowed: the outputs are set to
+ * zero (src_xy and dens may then be NULL). n_trg = 0 (or both outputs NULL)
+ * returns PFMM_OK with nothing launched. */
 int pfmm_eval(pfmm_plan_t plan, int64_t n_src, const double* src_xy, const double* dens,
               int64_t n_trg, const double* trg_xy, double* out_pot, double* out_grad,
               void* workspace, size_t workspace_bytes, void* hip_stream);
