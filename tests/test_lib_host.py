@@ -57,6 +57,27 @@ def test_header_is_c99_and_the_abi_works_from_c(P, tmp_path):
         assert int(sizes[name]) == ctypes.sizeof(ct), name
 
 
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    # with libpfmm.so absent the binding raises; there is no other path
+    import subprocess
+    import sys
+    code = ("import paper_2111_01083_amd._lib as L; L.LIB_PATH = %r\n"
+            "import paper_2111_01083_amd as P\n"
+            "try:\n    P.Plan('laplace', (1.0, 0.0), (0.0, 1.0), 1e-6)\n"
+            "except RuntimeError as e:\n    print('raised:', e)\n") % str(tmp_path / "missing.so")
+    res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT, timeout=120)
+    assert res.returncode == 0 and "raised:" in res.stdout and "no fallback" in res.stdout, res.stdout + res.stderr
+
+
+def test_binding_rejects_host_tensors_before_calling_the_library(P):
+    import torch
+    plan = P.Plan("laplace", (1.0, 0.0), (0.0, 1.0), 1e-6, self_exclude=True)
+    src = torch.zeros((2, 4), dtype=torch.float64)
+    q = torch.zeros(4, dtype=torch.float64)
+    with pytest.raises(TypeError):
+        plan(src, q)
+
+
 def test_canonical_lattice_of_rotated_unreduced_basis(P):
     # lattice of (3, 0), (0.6, 1), given rotated and as an unreduced basis
     th = 0.7
