@@ -188,6 +188,17 @@ def test_south_terms_at_double_precision_match_the_papers_estimate(P):
             assert abs(M / A - per_a) <= band * per_a, (kernel, A, M)
 
 
+def test_west_east_rule_size_against_the_papers_node_counts(P):
+    rows = [l.split() for l in open(os.path.join(ROOT, "tests", "golden", "ggq_node_counts.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert rows
+    for kernel, beta, digits, paper, ratio in rows:
+        # `digits` correct digits = internal eps 10^-digits = tol 10^(1 - digits)
+        plan = P.Plan(kernel, (1.0, 0.0), (0.0, 1.0), 10.0 ** (1 - int(digits)), beta=float(beta))
+        n = plan.info["n_quad"]
+        assert 0 < n <= float(ratio) * int(paper), (kernel, beta, digits, n)
+
+
 def test_workspace_size_grows_with_problem(P):
     plan = P.Plan("stokes", (1.0, 0.0), (0.0, 1.0), 1e-6, precision="mixed")
     a = P.pfmm_workspace_bytes(plan, 1000, 500)
