@@ -449,3 +449,34 @@ def test_yukawa_near_cutoff_drops_less_than_eps(P, tol):
             dpot += (k0 * far) @ q; dgx -= (k1r * dx * far) @ q; dgy -= (k1r * dy * far) @ q
     assert np.linalg.norm(dpot) < eps * np.linalg.norm(pot)
     assert np.hypot(np.linalg.norm(dgx), np.linalg.norm(dgy)) < eps * np.hypot(np.linalg.norm(gx), np.linalg.norm(gy))
+
+
+@pytest.mark.parametrize("kernel", ["laplace", "yukawa", "stokes"])
+def test_wider_near_region_m0_3(P, kernel):
+    # the paper's thin parallelograms use m0 = 3 (21 near images); with the
+    # override the west/east sums start at column p = 4, which the scheme's
+    # geometric factors must follow (for Stokes (p - (p-1) e^{-a}) / (1 - e^{-a})^2)
+    e1, e2 = (1.0, 0.0), (0.3, 1.0)
+    rng = np.random.default_rng(41)
+    src = W.cell_points(rng, e1, e2, 30)
+    trg = W.cell_points(rng, e1, e2, 20)
+    tol = 1e-10
+    plan = P.Plan(kernel, e1, e2, tol, beta=2.0 if kernel == "yukawa" else 0.0, m0=3)
+    info = plan.info
+    assert info["m0"] == 3 and info["n_images"] == 21
+    lam, wq = plan.quadrature()
+    if kernel == "stokes":
+        f = W.neutral_forces(rng, 30)
+        ref, gref = oracle.stokes(e1, e2, src, f, trg)
+        u, g = stokes_scheme(info, lam, wq, src, f, trg)
+    elif kernel == "laplace":
+        q = W.neutral_charges(rng, 30)
+        ref, gref = oracle.laplace(e1, e2, src, q, trg)
+        u, g = laplace_scheme(info, lam, wq, src, q, trg)
+    else:
+        q = rng.standard_normal(30)
+        ref, gref = oracle.yukawa(e1, e2, 2.0, src, q, trg)
+        u, g = yukawa_scheme(info, lam, wq, 2.0, src, q, trg)
+    eu = np.linalg.norm(u - ref) / np.linalg.norm(ref)
+    eg = np.linalg.norm(g - gref) / np.linalg.norm(gref)
+    assert eu < tol and eg < tol, (eu, eg)
