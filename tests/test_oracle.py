@@ -306,6 +306,48 @@ def test_stokes_trace_is_laplace():
     assert rel(np.stack([ga[0] + gb[2], ga[1] + gb[3]]), gl) < 1e-12
 
 
+@pytest.mark.parametrize("e1,e2", [SHEARED, GENERAL])
+def test_stokes_trace_is_laplace_at_the_sources(e1, e2):
+    # the self-excluded sums: tr G_stokeslet(r) = G_laplace(r) + 1/(4 pi), so
+    # with the (j = i, zero shift) term left out on both sides the traces
+    # differ by the left-out constant, -q_i/(4 pi). The velocity gradient
+    # has no such constant. An error in the alpha-independent part of the
+    # Stokes self term (Sec. 5.2 eq. stokeslet at r -> 0) fails this.
+    rng = np.random.default_rng(31)
+    n = 11
+    src = W.cell_points(rng, e1, e2, n)
+    q = W.neutral_charges(rng, n)
+    z = np.zeros_like(q)
+    ua, ga = oracle.stokes(e1, e2, src, np.stack([q, z]), None)
+    ub, gb = oracle.stokes(e1, e2, src, np.stack([z, q]), None)
+    pl, gl = oracle.laplace(e1, e2, src, q, None)
+    assert np.abs(ua[0] + ub[1] - (pl - q / (4 * np.pi))).max() < 1e-12 * np.abs(pl).max()
+    assert rel(np.stack([ga[0] + gb[2], ga[1] + gb[3]]), gl) < 1e-12
+
+
+def test_stokes_self_term_is_the_limit_at_the_source():
+    # u_self(x_i) = lim_{h -> 0} [u(x_i + h) - G_stokeslet(h) f_i]: the
+    # oracle's self term against its own sums at nearby non-self targets
+    # (which never use the self constant). Averaging over +-h along x and
+    # along y cancels the O(h) gradient term, leaving O(h^2).
+    rng = np.random.default_rng(32)
+    n = 9
+    src = W.cell_points(rng, *SHEARED, n)
+    f = W.neutral_forces(rng, n)
+    i = 4
+    u_self, _ = oracle.stokes(*SHEARED, src, f, None)
+    for h in (1e-4, 1e-5, 1e-6):
+        acc = np.zeros(2)
+        for dv in ((h, 0.0), (-h, 0.0), (0.0, h), (0.0, -h)):
+            t = src[:, [i]] + np.array(dv)[:, None]
+            u, _ = oracle.stokes(*SHEARED, src, f, t)
+            r2 = dv[0] ** 2 + dv[1] ** 2
+            G = (-0.5 * np.log(r2) * np.eye(2) + np.outer(dv, dv) / r2) / (4 * np.pi)
+            acc += u[:, 0] - G @ f[:, i]
+        acc /= 4
+        assert np.abs(acc - u_self[:, i]).max() < 1e-9 * np.abs(u_self).max() + 50 * h * h, (h, acc, u_self[:, i])
+
+
 def test_stokes_divergence_free_and_gradient_consistent():
     src, f, trg = _setup(*SHEARED, ns=9, nt=5, seed=9, stokes=True)
     u, g = oracle.stokes(*SHEARED, src, f, trg)
