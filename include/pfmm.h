@@ -38,9 +38,13 @@
  *    same coordinates): the term (j = i, zero lattice vector) is left out.
  *    A target that coincides exactly with another source or source image
  *    is a singularity of the sum; such inputs are not supported.
- *  - Evaluation is asynchronous on the caller's HIP stream; nothing is
- *    allocated inside pfmm_eval. Scratch memory comes from `workspace`,
- *    of at least pfmm_workspace_bytes() bytes, 256-byte aligned.
+ *  - Evaluation is asynchronous on the caller's HIP stream. Scratch memory
+ *    comes from `workspace`, of at least pfmm_workspace_bytes() bytes,
+ *    256-byte aligned. The only device allocation is the plan's small
+ *    table (a few KB): pfmm_plan_upload makes it, and the first pfmm_eval
+ *    on a device calls pfmm_plan_upload itself (hipMalloc plus a
+ *    synchronous copy) when the table is not there yet. After that,
+ *    pfmm_eval allocates nothing.
  *  - n_src and n_trg (per cell in a batch) are at most PFMM_MAX_POINTS
  *    (point indices are 32-bit inside the kernels); larger sizes are
  *    PFMM_EINVAL, and pfmm_workspace_bytes* return 0 for them.
@@ -93,7 +97,9 @@ typedef struct {
   int self_exclude;   /* 1: target i is source i                               */
   int m_gl;           /* Gauss-Legendre lines for the NUFFT path; 0 = automatic*/
   int check_neutral;  /* 1: pfmm_eval syncs the stream and rejects non-neutral */
-                      /*    Laplace/Stokes densities with PFMM_ENOT_NEUTRAL    */
+                      /*    Laplace/Stokes densities with PFMM_ENOT_NEUTRAL;   */
+                      /*    the sync and host copy cannot run under stream     */
+                      /*    capture, and pfmm_batch_create rejects such plans  */
   int profile;        /* 1: record HIP events around the near-field launches   */
                       /*    and the whole evaluation (see pfmm_plan_stage_times)*/
   int near_mode;      /* pfmm_near_mode: AUTO evaluates each pair of a         */
@@ -201,7 +207,14 @@ int pfmm_eval_adjoint(pfmm_plan_t plan, int64_t n_src, const double* src_xy,
  * tables and a task table to the device; use_graph = 1 captures the whole
  * launch sequence into a hipGraph on the first pfmm_eval_batch call (and
  * again whenever a pointer argument changes) and replays it afterwards.
- * The plans must outlive the batch. */
+ * The plans must outlive the batch. Plans with check_neutral set are
+ * rejected (PFMM_EINVAL). Changing the NUFFT grid of a plan held by a batch
+ * (pfmm_plan_set_tuning, pfmm_autotune) changes that cell's workspace: the
+ * next pfmm_batch_workspace_bytes or pfmm_eval_batch call rebuilds the
+ * batch's layout and task table (host work, hipMalloc and a synchronous
+ * copy; not under stream capture) and drops its graph, and pfmm_eval_batch
+ * then returns PFMM_EWORKSPACE if the workspace passed is now too small:
+ * read pfmm_batch_workspace_bytes again after retuning a plan. */
 typedef struct pfmm_batch_s* pfmm_batch_t;
 int pfmm_batch_create(int n_cells, const pfmm_plan_t* plans, const int64_t* src_off,
                       const int64_t* trg_off, int use_graph, pfmm_batch_t* out);

@@ -360,6 +360,8 @@ def pfmm_eval_batch(batch, src, dens, trg=None, out_pot=None, out_grad=None, wor
         out_pot = torch.empty((nd, 2, T) if batch.stokes else (nd, T), dtype=torch.float64, device=src.device)
     if out_grad is None:
         out_grad = torch.empty((nd, 4 if batch.stokes else 2, T), dtype=torch.float64, device=src.device)
+    # re-read: retuning a plan of the batch can change the size
+    batch.workspace_bytes = int(lib.pfmm_batch_workspace_bytes(batch.handle))
     ws, wptr, avail = _workspace(batch.workspace_bytes, src.device, workspace)
     batch._ws_keep = ws
     _check(lib.pfmm_eval_batch(batch.handle, src.data_ptr(), dens.data_ptr(),

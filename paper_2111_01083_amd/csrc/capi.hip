@@ -669,6 +669,7 @@ struct pfmm_batch_s {
   int n_groups;
   int64_t split;                        // sources per near-field task (chunk or split length)
   int grid_mult;                        // persistent blocks per compute unit
+  std::vector<int> nu_grid;             // each plan's NUFFT grid when the layout was built
   BatchCell* d_recs;
   hipStream_t cap_stream;
   hipGraphExec_t exec;
@@ -766,7 +767,18 @@ static int batch_build(pfmm_batch_s* b, int64_t split, int grid_mult) {
   }
   b->n_recs = (int)recs.size();
   b->split = split; b->grid_mult = grid_mult;
+  b->nu_grid.resize(n_cells);
+  for (int c = 0; c < n_cells; ++c) b->nu_grid[c] = b->plans[c]->nu_grid;
   if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }   // task tables changed
+  return PFMM_OK;
+}
+
+// A plan's NUFFT grid (pfmm_plan_set_tuning, pfmm_autotune) sets the size of
+// its cell's NUFFT workspace and the launch shapes of its far field: when one
+// changed since the layout was built, rebuild layout, task records and graph.
+static int batch_refresh(pfmm_batch_s* b) {
+  for (int c = 0; c < b->n_cells; ++c)
+    if (b->plans[c]->nu_grid != b->nu_grid[c]) return batch_build(b, b->split, b->grid_mult);
   return PFMM_OK;
 }
 
@@ -780,8 +792,9 @@ int pfmm_batch_create(int n_cells, const pfmm_plan_t* plans, const int64_t* src_
   const int nc = p0->kernel == PFMM_STOKES ? 2 : 1;
   for (int c = 0; c < n_cells; ++c) {
     pfmm_plan_s* p = plans[c];
+    // check_neutral needs a stream synchronisation, which a batch never does
     if (!p || p->precision != p0->precision || p->n_dens != p0->n_dens || p->self_exclude != p0->self_exclude ||
-        (p->kernel == PFMM_STOKES ? 2 : 1) != nc)
+        (p->kernel == PFMM_STOKES ? 2 : 1) != nc || p->check_neutral)
       return PFMM_EINVAL;
     if (src_off[c + 1] < src_off[c] || src_off[c + 1] - src_off[c] > PFMM_MAX_POINTS) return PFMM_EINVAL;
     if (!p0->self_exclude &&
@@ -809,7 +822,10 @@ int pfmm_batch_create(int n_cells, const pfmm_plan_t* plans, const int64_t* src_
   return PFMM_OK;
 }
 
-size_t pfmm_batch_workspace_bytes(pfmm_batch_t b) { return b ? b->total : 0; }
+size_t pfmm_batch_workspace_bytes(pfmm_batch_t b) {
+  if (!b || batch_refresh(b) != PFMM_OK) return 0;
+  return b->total;
+}
 
 }  // extern "C"
 
@@ -857,6 +873,8 @@ int pfmm_eval_batch(pfmm_batch_t b, const double* src_xy, const double* dens, co
   if (!b) return PFMM_EINVAL;
   if (!src_xy || !dens || (!b->self_exclude && !trg_xy)) return PFMM_EINVAL;
   if (!out_pot && !out_grad) return PFMM_OK;
+  int rc0 = batch_refresh(b);
+  if (rc0) return rc0;
   if (!workspace || ws_bytes < b->total || ((uintptr_t)workspace & 255)) return PFMM_EWORKSPACE;
   hipStream_t st = (hipStream_t)hip_stream;
   char* ws = (char*)workspace;
@@ -888,6 +906,8 @@ int pfmm_batch_autotune(pfmm_batch_t b, const double* src_xy, const double* dens
                         pfmm_tune_report_t* report) {
   if (!b || !src_xy || !dens || (!b->self_exclude && !trg_xy) || (!out_pot && !out_grad)) return PFMM_EINVAL;
   if (!workspace || ((uintptr_t)workspace & 255)) return PFMM_EWORKSPACE;
+  int rc0 = batch_refresh(b);
+  if (rc0) return rc0;
   hipStream_t st = (hipStream_t)hip_stream;
   char* ws = (char*)workspace;
   hipEvent_t e0 = nullptr, e1 = nullptr;

@@ -126,3 +126,49 @@ def test_batched_cells_workload_64_cells_16_densities(env):
                                      beta=beta, tol=1e-10, self_idx=idx)
             sl = offs[c] + idx
             assert rel(pot[v, sl], po) < 1e-6 and rel(grad[v][:, sl], go) < 1e-6, (c, v)
+
+
+def test_batch_follows_a_retuned_plan(env):
+    # a plan of the batch moves to the doubled NUFFT grid after the batch was
+    # built: its cell needs more workspace and other far-field launch shapes,
+    # so the batch must rebuild its layout (and drop its graph) instead of
+    # running the old one; the old workspace size is then refused
+    P, torch, dev = env
+    rng = np.random.default_rng(17)
+    specs = [((1.0, 0.0), (0.0, 1.0), "laplace", 600, "auto"), ((30.0, 0.0), (0.0, 1.0), "laplace", 1500, "nufft"),
+             ((2.0, 0.0), (0.5, 1.0), "yukawa", 400, "auto")]
+    plans, srcs, dens, offs = [], [], [], [0]
+    for e1, e2, k, n, far in specs:
+        plans.append(P.Plan(k, e1, e2, 1e-10, beta=10.0 if k == "yukawa" else 0.0, self_exclude=True,
+                            far_mode=far))
+        srcs.append(W.cell_points(rng, e1, e2, n))
+        dens.append(W.neutral_charges(rng, n))
+        offs.append(offs[-1] + n)
+    batch = P.Batch(plans, offs, use_graph=True)
+    ds = torch.tensor(np.concatenate(srcs, 1), device=dev)
+    dq = torch.tensor(np.concatenate(dens)[None], device=dev)
+    ws_old = batch.workspace_bytes
+    p1, g1 = batch(ds, dq)
+    plans[1].set_tuning(nufft_grid=1)
+    ws_new = int(P._lib.load().pfmm_batch_workspace_bytes(batch.handle))
+    assert ws_new > ws_old
+    small = torch.empty(ws_old + 256, dtype=torch.uint8, device=dev)
+    with pytest.raises(P.PfmmError) as err:
+        batch(ds, dq, workspace=small)
+    assert err.value.code == -4
+    for rep in range(2):                       # captures a new graph, then replays it
+        p2, g2 = batch(ds, dq)
+        torch.cuda.synchronize()
+        p2 = p2.cpu().numpy(); g2 = g2.cpu().numpy()
+        for c, (e1, e2, k, n, far) in enumerate(specs):
+            sl = slice(offs[c], offs[c + 1])
+            po, go = oracle.evaluate(k, e1, e2, srcs[c], dens[c], None, beta=10.0 if k == "yukawa" else 0.0)
+            assert rel(p2[0, sl], po) < 1e-10 and rel(g2[0, :, sl], go) < 1e-10, (rep, c)
+    assert rel(p2, p1.cpu().numpy()) < 1e-10
+
+
+def test_batch_rejects_plans_that_check_neutrality(env):
+    P, torch, dev = env
+    plans = [P.Plan("laplace", (1.0, 0.0), (0.0, 1.0), 1e-6, self_exclude=True, check_neutral=True)]
+    with pytest.raises(P.PfmmError):
+        P.Batch(plans, [0, 100])
