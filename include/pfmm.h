@@ -175,6 +175,26 @@ int pfmm_eval(pfmm_plan_t plan, int64_t n_src, const double* src_xy, const doubl
               int64_t n_trg, const double* trg_xy, double* out_pot, double* out_grad,
               void* workspace, size_t workspace_bytes, void* hip_stream);
 
+/* Allocation-free evaluation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc). Same arguments and results as pfmm_eval, without the
+ * workspace: scratch memory is a fixed device array of
+ * PFMM_STATIC_WORKSPACE_BYTES inside the library, one per device, held
+ * until the process ends. Sizes whose pfmm_workspace_bytes() exceeds it
+ * return PFMM_EWORKSPACE. The plan's table must already be on the current
+ * device (call pfmm_plan_upload at set-up), else PFMM_EINVAL; plans with
+ * check_neutral or profile set are PFMM_EINVAL too (those options copy to
+ * the host or create events). Nothing is allocated and nothing
+ * synchronises. All calls on one device share that device's array and the
+ * array keeps the last call's contents (every evaluation rewrites what it
+ * reads), so calls that overlap in time on one device -- different streams,
+ * or host threads -- race and give wrong results: order them on one
+ * stream. */
+#define PFMM_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+int pfmm_eval_static(pfmm_plan_t plan, int64_t n_src, const double* src_xy, const double* dens,
+                     int64_t n_trg, const double* trg_xy, double* out_pot, double* out_grad,
+                     void* hip_stream);
+
 /* Adjoint for targets == sources (plans with self_exclude = 1 and n_dens = 1,
  * any kernel). With pot = K q the potential at the sources and g = dL/dpot
  * (device, laid out like out_pot: [n_src], Stokes [2][n_src]) for a loss L,

@@ -193,6 +193,31 @@ def pfmm_eval(plan, src, dens, trg=None, out_pot=None, out_grad=None, workspace=
     return out_pot, out_grad
 
 
+def pfmm_eval_static(plan, src, dens, trg=None, out_pot=None, out_grad=None, stream=None):
+    """pfmm_eval without a workspace: the library's fixed device array is
+    used instead (see pfmm.h; the plan must have been uploaded with
+    pfmm_plan_upload). Output tensors are allocated here unless passed."""
+    torch = _torch()
+    lib = L.load()
+    src = _as_points(src, "src")
+    dens = _as_dev(dens, "dens")
+    ns = src.shape[1]
+    stokes = plan.kernel == L.PFMM_STOKES
+    nd = plan.n_dens
+    if dens.numel() != nd * (2 if stokes else 1) * ns:
+        raise ValueError("dens has the wrong size for this plan")
+    trg_t = None if plan.self_exclude else _as_points(trg, "trg")
+    nt = ns if trg_t is None else trg_t.shape[1]
+    if out_pot is None:
+        out_pot = torch.empty((nd, 2, nt) if stokes else (nd, nt), dtype=torch.float64, device=src.device)
+    if out_grad is None:
+        out_grad = torch.empty((nd, 4 if stokes else 2, nt), dtype=torch.float64, device=src.device)
+    _check(lib.pfmm_eval_static(plan.handle, ns, src.data_ptr(), dens.data_ptr(), nt,
+                                None if trg_t is None else trg_t.data_ptr(), out_pot.data_ptr(),
+                                out_grad.data_ptr(), _stream_ptr(stream)), "pfmm_eval_static")
+    return out_pot, out_grad
+
+
 def pfmm_plan_get_log_groups(plan):
     return plan.log_groups()
 

@@ -14,6 +14,7 @@ PFMM_FP64, PFMM_MIXED = 0, 1
 PFMM_FAR_AUTO, PFMM_FAR_DIRECT, PFMM_FAR_NUFFT = 0, 1, 2
 PFMM_NEAR_AUTO, PFMM_NEAR_ONE_SIDED, PFMM_NEAR_MUTUAL = 0, 1, 2
 PFMM_MAX_POINTS = 1 << 30          # largest n_src / n_trg (per cell in a batch)
+PFMM_STATIC_WORKSPACE_BYTES = 64 << 20   # the fixed device workspace of pfmm_eval_static
 ERRORS = {0: "PFMM_OK", -1: "PFMM_EINVAL", -2: "PFMM_EINVAL_LATTICE", -3: "PFMM_EINVAL_TOL",
           -4: "PFMM_EWORKSPACE", -5: "PFMM_EHIP", -6: "PFMM_ENOT_NEUTRAL", -7: "PFMM_ENOMEM"}
 
@@ -21,7 +22,7 @@ ERRORS = {0: "PFMM_OK", -1: "PFMM_EINVAL", -2: "PFMM_EINVAL_LATTICE", -3: "PFMM_
 EXPORTS = ["pfmm_plan", "pfmm_plan_upload", "pfmm_plan_get_info", "pfmm_plan_get_quadrature",
            "pfmm_plan_get_log_groups",
            "pfmm_plan_stage_times",
-           "pfmm_workspace_bytes", "pfmm_eval", "pfmm_workspace_bytes_adjoint", "pfmm_eval_adjoint",
+           "pfmm_workspace_bytes", "pfmm_eval", "pfmm_eval_static", "pfmm_workspace_bytes_adjoint", "pfmm_eval_adjoint",
            "pfmm_batch_create", "pfmm_batch_workspace_bytes", "pfmm_eval_batch", "pfmm_batch_destroy",
            "pfmm_plan_get_tuning", "pfmm_plan_set_tuning", "pfmm_autotune", "pfmm_batch_autotune",
            "pfmm_destroy", "pfmm_strerror"]
@@ -81,6 +82,8 @@ def load():
     lib.pfmm_workspace_bytes.restype = ctypes.c_size_t
     lib.pfmm_eval.argtypes = [vp, i64, vp, vp, i64, vp, vp, vp, vp, ctypes.c_size_t, vp]
     lib.pfmm_eval.restype = c_int
+    lib.pfmm_eval_static.argtypes = [vp, i64, vp, vp, i64, vp, vp, vp, vp]
+    lib.pfmm_eval_static.restype = c_int
     lib.pfmm_workspace_bytes_adjoint.argtypes = [vp, i64]
     lib.pfmm_workspace_bytes_adjoint.restype = ctypes.c_size_t
     lib.pfmm_eval_adjoint.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -195,6 +196,33 @@ static int plan_refresh_device(pfmm_plan_s* p) {
              ? PFMM_OK : PFMM_EHIP;
 }
 
+// Fixed device workspace of pfmm_eval_static. Every device the library runs
+// on holds its own copy for the life of the process. In host code `scratch`
+// only names the symbol: its device address is looked up once per device
+// (hipGetSymbolAddress, with that device current) and only that address is
+// passed to kernels.
+static __device__ __align__(256) char scratch[PFMM_STATIC_WORKSPACE_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// device address of `scratch` on the current device
+int static_workspace(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return PFMM_EHIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return PFMM_EHIP;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return PFMM_OK;
+}
+}  // namespace
+
 extern "C" {
 
 int pfmm_plan_upload(pfmm_plan_t p) {
@@ -213,6 +241,8 @@ int pfmm_plan_upload(pfmm_plan_t p) {
   p->d_tab = d;
   p->dev_id = dev;
   p->tab_doubles = tab.size();
+  void* ws = nullptr;
+  (void)static_workspace(&ws);   // set-up of pfmm_eval_static on this device (it retries and reports)
   return PFMM_OK;
 }
 
@@ -263,6 +293,23 @@ int pfmm_eval(pfmm_plan_t p, int64_t ns, const double* src_xy, const double* den
               const double* trg_xy, double* out_pot, double* out_grad, void* workspace,
               size_t ws_bytes, void* hip_stream) {
   return pfmm::eval_core(p, ns, src_xy, dens, nt, trg_xy, out_pot, out_grad, workspace, ws_bytes, hip_stream);
+}
+
+}  // extern "C"
+
+
+extern "C" {
+
+int pfmm_eval_static(pfmm_plan_t p, int64_t ns, const double* src_xy, const double* dens, int64_t nt,
+                     const double* trg_xy, double* out_pot, double* out_grad, void* hip_stream) {
+  if (!p || ns < 0 || nt < 0 || ns > PFMM_MAX_POINTS || nt > PFMM_MAX_POINTS) return PFMM_EINVAL;
+  const size_t need = cell_workspace(p, ns, nt, 0);
+  if (need > PFMM_STATIC_WORKSPACE_BYTES) return PFMM_EWORKSPACE;
+  void* ws = nullptr;
+  int rc = static_workspace(&ws);
+  if (rc) return rc;
+  return pfmm::eval_core(p, ns, src_xy, dens, nt, trg_xy, out_pot, out_grad, ws, PFMM_STATIC_WORKSPACE_BYTES,
+                         hip_stream, 1);
 }
 
 }  // extern "C"
@@ -424,7 +471,7 @@ int cell_setup(pfmm_plan_s* p, int64_t ns, int64_t nt, char* ws, int64_t forced_
 
 int pfmm::eval_core(pfmm_plan_t p, int64_t ns, const double* src_xy, const double* dens, int64_t nt,
                     const double* trg_xy, double* out_pot, double* out_grad, void* workspace,
-                    size_t ws_bytes, void* hip_stream) {
+                    size_t ws_bytes, void* hip_stream, int no_alloc) {
   if (!p || ns < 0 || nt < 0 || ns > PFMM_MAX_POINTS || nt > PFMM_MAX_POINTS) return PFMM_EINVAL;
   if (p->self_exclude && nt != ns) return PFMM_EINVAL;
   if (ns > 0 && (!src_xy || !dens)) return PFMM_EINVAL;
@@ -434,8 +481,16 @@ int pfmm::eval_core(pfmm_plan_t p, int64_t ns, const double* src_xy, const doubl
   cell_setup(p, ns, nt, (char*)workspace, 0, r);
   if (!workspace || ws_bytes < r.L.total || ((uintptr_t)workspace & 255)) return PFMM_EWORKSPACE;
   hipStream_t st = (hipStream_t)hip_stream;
-  int rc = pfmm_plan_upload(p);
-  if (rc) return rc;
+  int rc = PFMM_OK;
+  if (no_alloc) {
+    // the static-workspace entry point: no upload, no host copy, no events
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return PFMM_EHIP;
+    if (!p->d_tab || p->dev_id != dev || p->check_neutral || p->profile) return PFMM_EINVAL;
+  } else {
+    rc = pfmm_plan_upload(p);
+    if (rc) return rc;
+  }
   const int nc = p->kernel == PFMM_STOKES ? 2 : 1;
   if (p->check_neutral && p->kernel != PFMM_YUKAWA && ns > 0) {
     std::vector<double> h((size_t)p->n_dens * nc * ns);

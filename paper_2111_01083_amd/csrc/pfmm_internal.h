@@ -100,5 +100,5 @@ size_t cell_workspace(pfmm_plan_s* p, int64_t ns, int64_t nt, int64_t forced_spl
 int set_nufft_grid(pfmm_plan_s* p, int grid);
 int eval_core(pfmm_plan_s* p, int64_t ns, const double* src_xy, const double* dens, int64_t nt,
               const double* trg_xy, double* out_pot, double* out_grad, void* workspace,
-              size_t ws_bytes, void* hip_stream);
+              size_t ws_bytes, void* hip_stream, int no_alloc = 0);
 }  // namespace pfmm
