@@ -34,8 +34,20 @@ FLOPS_PER_PAIR = {"laplace": 14, "yukawa": 51, "stokes": 30}
 # bound
 FLOPS_MUTUAL_PER_IMAGE = {"laplace": 11, "yukawa": 36, "stokes": 22}
 FLOPS_MUTUAL_PER_PAIR = {"laplace": 15, "yukawa": 12, "stokes": 64}
+# the FP64 symmetric kernel, same convention (a divide counts as one
+# transcendental). Yukawa per image: coordinate differences 2, r^2 3, sqrt
+# and beta r 2, 2/x, exp(-x)/sqrt(x) 4, 2u - 1 2, two 21-term Chebyshev
+# (Clenshaw) sums of K0 and K1 128, scaling 3, moments 5 (the large-argument
+# branch, which all but ~1 % of the pairs take at beta = 10); per pair the
+# FP64 combination with the densities. Stokes: the same arithmetic as the
+# mixed kernel in FP64. One-sided pairs (diagonal tiles, 0.3 % of the work)
+# are counted at the per-image figure plus the density products.
+FLOPS_FP64_MUTUAL_PER_IMAGE = {"yukawa": 149, "stokes": 22}
+FLOPS_FP64_MUTUAL_PER_PAIR = {"yukawa": 12, "stokes": 64}
+FLOPS_FP64_PER_PAIR = {"yukawa": 155, "stokes": 30}
 TILE = 256    # targets per near-field block (the diagonal tiles are one-sided)
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 
 # HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
@@ -89,6 +101,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 1 GiB elementwise copy (to calibrate HBM byte counters)")
+    ap.add_argument("--nufft-sweep", default="",
+                    help="comma-separated N: instead of the benchmark, time the far part alone (NUFFT "
+                         "spread/FFT/interp) on the A = 100 blob workload at each N, one JSON line each")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -113,6 +128,32 @@ def main():
     import paper_2111_01083_amd as P
 
     dev = torch.device("cuda:0")
+    if args.nufft_sweep:
+        # far part only (near_mode none): the periodizing operator through the
+        # NUFFT, Laplace, mixed, tol 1e-6, targets = sources
+        for n in [int(float(v)) for v in args.nufft_sweep.split(",")]:
+            e1, e2, src, q = W.high_aspect_blobs("a100", "laplace", n)
+            d_src, d_q = torch.tensor(src, device=dev), torch.tensor(q, device=dev)
+            p = P.Plan("laplace", e1, e2, 1e-6, precision="mixed", far_mode="nufft", near_mode="none",
+                       self_exclude=True, profile=True)
+            ws = torch.empty(P.pfmm_workspace_bytes(p, n, n) + 256, dtype=torch.uint8, device=dev)
+            pot = torch.empty((1, n), dtype=torch.float64, device=dev)
+            grad = torch.empty((1, 2, n), dtype=torch.float64, device=dev)
+            for _ in range(max(args.warmup, 1)):
+                P.pfmm_eval(p, d_src, d_q, None, out_pot=pot, out_grad=grad, workspace=ws)
+            torch.cuda.synchronize()
+            p.stage_times()
+            for _ in range(args.steps):
+                P.pfmm_eval(p, d_src, d_q, None, out_pot=pot, out_grad=grad, workspace=ws)
+            torch.cuda.synchronize()
+            _, total_ms, cnt = p.stage_times()
+            ms = total_ms / max(cnt, 1)
+            print(json.dumps({"sweep": "far part alone, A=100 blobs, Laplace mixed tol 1e-6, NUFFT", "n": n,
+                              "eval_ms": round(ms, 4), "targets_per_s": round(n / (ms * 1e-3), 1),
+                              "nufft_nf": p.info["nufft_nf"], "nufft_w": p.info["nufft_w"],
+                              "m_gl": p.info["m_gl"], "steps": args.steps}), flush=True)
+            del ws, pot, grad, d_src, d_q
+        return
     n = args.n
     e1, e2 = (1.0, 0.0), (0.0, 1.0)
     rng = np.random.default_rng(0)
@@ -197,6 +238,20 @@ def main():
                           "pair_evaluations_per_launch": {"one_sided": diag_pairs, "mutual": mutual_pairs}}
     dom = max(roof_all, key=lambda k: roof_all[k]["near_ms_per_launch"])
     roofline = dict(roof_all[dom], kernel=f"near_mutual_kernel<{dom}, mixed> + diagonal near_kernel")
+    # the FP64 path's near field against the FP64 vector peak
+    roof64 = {}
+    for (kern, _, _), (near_ms, total_ms, cnt) in zip(cases, st64):
+        per_launch_ms = near_ms / max(cnt, 1)
+        flops = (FLOPS_FP64_PER_PAIR[kern] * diag_pairs + FLOPS_FP64_MUTUAL_PER_IMAGE[kern] * mutual_pairs
+                 + FLOPS_FP64_MUTUAL_PER_PAIR[kern] * mutual_pairs / images)
+        tflops = flops / (per_launch_ms * 1e-3) / 1e12
+        roof64[kern] = {"bound": "alu", "achieved": round(tflops, 3), "peak": FP64_VECTOR_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(tflops / FP64_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+                        "near_ms_per_launch": round(per_launch_ms, 3), "eval_ms": round(total_ms / max(cnt, 1), 3),
+                        "flops_per_pair": FLOPS_FP64_PER_PAIR[kern],
+                        "flops_per_mutual_image": FLOPS_FP64_MUTUAL_PER_IMAGE[kern],
+                        "flops_per_mutual_pair": FLOPS_FP64_MUTUAL_PER_PAIR[kern],
+                        "kernel": f"near_mutual_kernel<{kern}, fp64> + diagonal near_kernel"}
 
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "targets/s", "n_gpus": 1,
@@ -209,7 +264,8 @@ def main():
                    "targets_per_step": targets_per_step},
         "fp64_gpu": {"value": round(fp64_value, 1), "unit": "targets/s", "ms_per_step": round(ms64_s * 1e3, 3),
                      "steps": args.fp64_steps, "near_ms_per_launch": {k: round(s[0] / max(s[2], 1), 3)
-                                                                      for (k, _, _), s in zip(cases, st64)}},
+                                                                      for (k, _, _), s in zip(cases, st64)},
+                     "roofline": roof64},
         "speedup_mixed_vs_fp64": round(value / fp64_value, 2),
         "roofline": roofline,
         "roofline_all": roof_all,
@@ -218,18 +274,39 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
         idx = np.sort(np.random.default_rng(1).choice(n, args.sample, replace=False))
-        t0 = time.perf_counter()
-        refs = []
+        refs, parts = [], {}
+        cpu_total = 0.0
         for kern, beta, _ in cases:
             dens = f if kern == "stokes" else q
+            # one target first (the per-source setup -- Ewald structure factors
+            # for Stokes, none for the Yukawa lattice sum -- plus one target),
+            # then the whole sample; their difference gives the per-target cost
+            t0 = time.perf_counter()
+            oracle.evaluate(kern, e1, e2, src, dens, src[:, idx[:1]], beta=beta, tol=1e-10, self_idx=idx[:1])
+            t1 = time.perf_counter()
             refs.append(oracle.evaluate(kern, e1, e2, src, dens, src[:, idx], beta=beta, tol=1e-10, self_idx=idx))
-        cpu_s = time.perf_counter() - t0
-        cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
-        out["cpu_baseline"] = {"value": round(len(cases) * args.sample / cpu_s, 3), "unit": "targets/s",
-                               "cores": cores, "kind": "oracle",
-                               "sample": f"{args.sample} sampled targets per kernel (of the {n}), all {n} "
-                                         f"sources, Ewald (Stokes) / truncated lattice sum (Yukawa), "
-                                         f"FP64, {cpu_s:.1f} s"}
+            t2 = time.perf_counter()
+            per_target = max((t2 - t1) - (t1 - t0), 0.0) / max(args.sample - 1, 1)
+            setup = max((t1 - t0) - per_target, 0.0)
+            parts[kern] = {"setup_s": round(setup, 3), "per_target_s": round(per_target, 5),
+                           "sample_s": round(t2 - t1, 3), "full_workload_s_est": round(setup + n * per_target, 1)}
+            cpu_total += setup + n * per_target
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+        model = ""
+        try:
+            with open("/proc/cpuinfo") as fh:
+                model = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
+        except OSError:
+            pass
+        out["cpu_baseline"] = {"value": round(targets_per_step / cpu_total, 3), "unit": "targets/s",
+                               "cores": threads, "kind": "oracle",
+                               "sample": f"{args.sample} sampled targets per kernel (of the {n}) with all {n} "
+                                         f"sources, FP64 Ewald (Stokes) / truncated lattice sum (Yukawa); "
+                                         f"value = 2N targets over the per-source setup plus N times the "
+                                         f"per-target time of each kernel, both measured on the sample",
+                               "per_kernel": parts, "nproc": os.cpu_count(),
+                               "affinity_cpus": len(os.sched_getaffinity(0)), "omp_threads": threads,
+                               "cpu_model": model}
         acc = {}
         for (kern, _, _), (po, go), (pm, gm), (p6, g6) in zip(cases, refs, res_mixed, res64):
             acc[kern] = {"mixed_pot": rel(pm[..., idx], po), "mixed_grad": rel(gm[:, idx], go),

@@ -105,10 +105,27 @@ typedef struct {
   int near_mode;      /* pfmm_near_mode: AUTO evaluates each pair of a         */
                       /* self-target plan once for both of its points (the     */
                       /* kernel is symmetric, Sec. 1 eq. psum); ONE_SIDED      */
-                      /* always sums per target; MUTUAL needs self_exclude     */
+                      /* always sums per target; MUTUAL needs self_exclude;    */
+                      /* NONE leaves the near images out: the outputs are the  */
+                      /* far part alone, the periodizing operator P applied to */
+                      /* the densities (Sec. 1, eq. peropdef; Sec. 6). Batches */
+                      /* reject NONE plans                                     */
+  int periodic;       /* 2 (or 0): doubly periodic in e1 and e2 (operator P2). */
+                      /* 1: singly periodic in e1 alone (operator P1, Sec. 3   */
+                      /* eq. ksplitting1): images m e1 only, near part the     */
+                      /* cell and its 2 neighbours, far part the west/east     */
+                      /* columns (Thm. west_thm and its Laplace/Stokes forms   */
+                      /* with one row). e2 then only sets the strip height:    */
+                      /* points must lie within half of e2's extent across e1 */
+                      /* of the line through the origin along e1 (outside it   */
+                      /* the west/east rule is not accurate). Laplace and      */
+                      /* Stokes sums are the symmetric limits over |m| <= M    */
+                      /* (neutral densities); no additive constant is removed. */
+                      /* Batches reject P1 plans; the NUFFT does not apply     */
 } pfmm_opts;
 
-typedef enum { PFMM_NEAR_AUTO = 0, PFMM_NEAR_ONE_SIDED = 1, PFMM_NEAR_MUTUAL = 2 } pfmm_near_mode;
+typedef enum { PFMM_NEAR_AUTO = 0, PFMM_NEAR_ONE_SIDED = 1, PFMM_NEAR_MUTUAL = 2,
+               PFMM_NEAR_NONE = 3 } pfmm_near_mode;
 
 /* Read-only description of a plan (host struct). */
 typedef struct {
@@ -116,12 +133,17 @@ typedef struct {
   double d, xi, eta;          /* canonical lattice e1 = (d, 0), e2 = (xi, eta) */
   double rot_cos, rot_sin;    /* canonical = R * user, R = [[c, -s], [s, c]]   */
   double eps;                 /* internal truncation tolerance (tol / 10)      */
-  int n_modes;                /* M: south/north modes m = -M..M (eq. mpk0s)    */
+  int n_modes;                /* M: south/north modes m = -M..M (eq. mpk0s);
+                                 0 for singly periodic plans (no rows)        */
   int n_quad;                 /* west/east quadrature nodes                    */
   int m_gl, nufft_nf, nufft_w;/* NUFFT lines, fine grid size, kernel width     */
   int n_images;               /* near images (2 m0 + 1) * 3                    */
   int n_log_groups;           /* mixed symmetric near field: image groups whose
                                  r^2 product shares one log2 (1, 3 or n_images) */
+  int periodic;               /* 2: doubly periodic, 1: singly periodic in e1   */
+  int ew_rotated;             /* 1: west/east waves along e2-perp (Appendix A)  */
+  double ew_cos, ew_sin;      /* canonical -> west/east frame: x' = c x - s y,
+                                 y' = s x + c y (identity when ew_rotated = 0)  */
 } pfmm_plan_info_t;
 
 typedef struct pfmm_plan_s* pfmm_plan_t;
@@ -155,6 +177,14 @@ int pfmm_plan_get_quadrature(pfmm_plan_t plan, double* nodes, double* weights);
  * (pfmm_plan_get_info); host int arrays of at least n_log_groups entries.
  * Either pointer may be NULL. */
 int pfmm_plan_get_log_groups(pfmm_plan_t plan, int* ends, int* e0);
+
+/* Host: the NUFFT spreading kernel as the device evaluates it (Sec. 6.1):
+ * the exponential of semicircle phi(z) = exp(beta_es (sqrt(1 - z^2) - 1))
+ * at the w + 1 taps of a point, each tap t a polynomial
+ * sum_k coef[t * 20 + k] u^k of degree *deg - 1 in u = 2f - 1, where f in
+ * [0, 1) is the offset of the first tap (see the plan's nufft_w). coef: host
+ * array of 17 * 20 doubles (unused entries zero); any pointer may be NULL. */
+int pfmm_plan_get_spread_kernel(pfmm_plan_t plan, double* coef, int* deg, double* beta_es);
 
 /* Profiling plans only (opts.profile = 1): wait for the events recorded by
  * every pfmm_eval since the last call, and return the summed GPU time of
@@ -213,6 +243,22 @@ int pfmm_eval_adjoint(pfmm_plan_t plan, int64_t n_src, const double* src_xy,
                       const double* dens, const double* g_pot, double* out_dq,
                       double* out_dxy, void* workspace, size_t workspace_bytes,
                       void* hip_stream);
+
+/* Pressure of the periodic Stokeslet sum (Stokes plans only): the
+ * Stokeslet's pressure p = (1/2pi) r.f/r^2 (Sec. 5.2, eq. stokeslet; the
+ * pressurelet of Thms. south_thm_stokes_pressure and west_thm_stokes_pressure)
+ * summed over the same images as the velocity, with zero cell mean (doubly
+ * periodic) or as the symmetric limit along e1 (singly periodic). Arguments
+ * as for pfmm_eval with the Stokes plan's forces; out_pres [n_dens][n_trg]
+ * (device) is overwritten. It is evaluated as -div of the periodic Laplace
+ * gradient with the force components as charges (a Laplace plan of the same
+ * lattice and options that every Stokes plan holds), so its cost is that of
+ * one Laplace evaluation with 2 n_dens densities. Workspace: at least
+ * pfmm_workspace_bytes_pressure() bytes. Other plans: PFMM_EINVAL. */
+size_t pfmm_workspace_bytes_pressure(pfmm_plan_t plan, int64_t n_src, int64_t n_trg);
+int pfmm_eval_pressure(pfmm_plan_t plan, int64_t n_src, const double* src_xy, const double* dens,
+                       int64_t n_trg, const double* trg_xy, double* out_pres, void* workspace,
+                       size_t workspace_bytes, void* hip_stream);
 
 /* Batched evaluation of many independent cells. plans[c] (n_cells of them)
  * must share precision, n_dens and self_exclude, and be all scalar kernels

@@ -55,8 +55,12 @@ def _load():
         lib.oracle_yukawa_lattice.argtypes = [_dp, _dp, ctypes.c_double, ctypes.c_double] + common
         lib.oracle_stokes_ewald.argtypes = [_dp, _dp, ctypes.c_double, ctypes.c_double] + common
         lib.oracle_free_space.argtypes = [ctypes.c_int, ctypes.c_double] + common
+        lib.oracle_laplace_p1.argtypes = [ctypes.c_double] + common
+        lib.oracle_yukawa_p1.argtypes = [ctypes.c_double] * 3 + common
+        lib.oracle_stokes_p1.argtypes = [ctypes.c_double] + common
         for f in (lib.oracle_laplace_ewald, lib.oracle_laplace_rowsum, lib.oracle_yukawa_lattice,
-                  lib.oracle_stokes_ewald, lib.oracle_free_space):
+                  lib.oracle_stokes_ewald, lib.oracle_free_space, lib.oracle_laplace_p1,
+                  lib.oracle_yukawa_p1, lib.oracle_stokes_p1):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -170,6 +174,61 @@ def free_space(kernel, src, dens, trg=None, beta=0.0, self_idx=None):
     _check(lib.oracle_free_space(k, beta, ns, _p(src[0]), _p(src[1]), _p(dens), nt,
                                  _p(trg[0]), _p(trg[1]), _p(se), _p(pot), _p(grad)), "oracle_free_space")
     return pot, grad
+
+
+def _p1_frame(e1, pts):
+    """Rotate points so that the period e1 lies along +x: (canonical points, R, d)."""
+    e1 = np.asarray(e1, float)
+    d = float(np.hypot(*e1))
+    c, s = e1[0] / d, e1[1] / d
+    R = np.array([[c, s], [-s, c]])          # canonical = R user
+    return R @ pts, R, d
+
+
+def singly_periodic(kernel, e1, src, dens, trg=None, beta=0.0, tol=1e-15, self_idx=None):
+    """Sums periodic in e1 only (the operator P1, Sec. 3 eq. ksplitting1):
+    u(t) = sum_j sum_{m in Z} G(t - s_j - m e1) dens_j, symmetric in m for
+    Laplace and Stokes (neutral densities). Same layouts as evaluate();
+    gradients and Stokes velocities in the caller's frame."""
+    lib = _load()
+    nc = 2 if kernel == "stokes" else 1
+    src, dens, trg, ns, nt, se = _prep(src, dens, trg, nc, self_idx)
+    sc, R, d = _p1_frame(e1, src)
+    tc = R @ trg
+    dc = R @ dens if kernel == "stokes" else dens
+    sc = np.ascontiguousarray(sc); tc = np.ascontiguousarray(tc); dc = np.ascontiguousarray(dc)
+    if kernel == "stokes":
+        pot = np.empty((2, nt)); grad = np.empty((4, nt))
+        _check(lib.oracle_stokes_p1(d, ns, _p(sc[0]), _p(sc[1]), _p(dc), nt, _p(tc[0]), _p(tc[1]), _p(se),
+                                    _p(pot), _p(grad)), "oracle_stokes_p1")
+        J = grad.reshape(2, 2, nt)
+        return R.T @ pot, np.einsum("ji,jkt,kl->ilt", R, J, R).reshape(4, nt)
+    pot = np.empty(nt); grad = np.empty((2, nt))
+    if kernel == "laplace":
+        _check(lib.oracle_laplace_p1(d, ns, _p(sc[0]), _p(sc[1]), _p(dc), nt, _p(tc[0]), _p(tc[1]), _p(se),
+                                     _p(pot), _p(grad)), "oracle_laplace_p1")
+    elif kernel == "yukawa":
+        _check(lib.oracle_yukawa_p1(d, beta, max(tol, 1e-16), ns, _p(sc[0]), _p(sc[1]), _p(dc), nt, _p(tc[0]),
+                                    _p(tc[1]), _p(se), _p(pot), _p(grad)), "oracle_yukawa_p1")
+    else:
+        raise ValueError(kernel)
+    return pot, R.T @ grad
+
+
+def stokes_pressure(e1, e2, src, f, trg=None, tol=1e-14, self_idx=None, periodic=2):
+    """Pressure of the periodic Stokeslet sum: the Stokeslet's pressure is
+    (1/2pi) r.f/r^2 = -f . grad G_L (G_L = -(1/2pi) log r), so the periodic
+    pressure is -(d/dx u_L[f1] + d/dy u_L[f2]) with u_L the periodic Laplace
+    sum of the force components as charges (zero cell mean for the doubly
+    periodic sum; the symmetric limit along e1 for periodic=1)."""
+    f = _arr(f)
+    if periodic == 1:
+        _, g1 = singly_periodic("laplace", e1, src, f[0], trg, self_idx=self_idx)
+        _, g2 = singly_periodic("laplace", e1, src, f[1], trg, self_idx=self_idx)
+    else:
+        _, g1 = laplace(e1, e2, src, f[0], trg, tol=tol, self_idx=self_idx)
+        _, g2 = laplace(e1, e2, src, f[1], trg, tol=tol, self_idx=self_idx)
+    return -(g1[0] + g2[1])
 
 
 def evaluate(kernel, e1, e2, src, dens, trg=None, beta=0.0, tol=1e-14, self_idx=None):

@@ -43,6 +43,7 @@
 // accumulated. Return 0 on success, negative on bad input.
 
 #include <cmath>
+#include <complex>
 #include <vector>
 #include <algorithm>
 #include <cstdint>
@@ -460,6 +461,150 @@ int oracle_free_space(int kernel, double beta, int64_t ns, const double* sx, con
     } else {
       if (out_pot) out_pot[i] = p0;
       if (out_grad) { out_grad[i] = g[0]; out_grad[nt + i] = g[1]; }
+    }
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Singly periodic sums (Sec. 1, the operator P1: periodic in e1 = (d, 0)
+// only, images m e1 for m in Z; Sec. 3 eq. ksplitting1). Canonical frame:
+// the period is along x; y is unbounded. The Laplace and Stokes sums need
+// neutral densities and are taken as the limit of symmetric partial sums
+// over |m| <= M (the form the paper's west + east split produces).
+// ---------------------------------------------------------------------------
+
+// Laplace, P1: the symmetric row sum in closed form (sine product):
+//   sum_m -(1/2pi) log|w - m d| = -(1/2pi) log|2 sin(pi w / d)| + const
+//                               = -|y|/(2d) - (1/2pi) log|1 - e^{i kap sg w}| + const,
+// kap = 2 pi/d, sg = sign(y), w = x + i y; the constants cancel for neutral
+// q. A target on its own source takes the row without m = 0:
+// lim_{w->0} (log|2 sin(pi w/d)| - log|w|) = log(2 pi/d).
+int oracle_laplace_p1(double d, int64_t ns, const double* sx, const double* sy, const double* q,
+                      int64_t nt, const double* tx, const double* ty, const int64_t* self_idx,
+                      double* out_pot, double* out_grad) {
+  if (!(d > 0)) return -1;
+  const double kap = 2 * PI / d;
+#pragma omp parallel for schedule(dynamic, 8)
+  for (int64_t i = 0; i < nt; ++i) {
+    double pot = 0, gx = 0, gy = 0;
+    for (int64_t j = 0; j < ns; ++j) {
+      if (self_idx && j == self_idx[i]) {
+        pot += -q[j] * std::log(kap) / (2 * PI);
+        continue;
+      }
+      const double wx = tx[i] - sx[j], wy = ty[i] - sy[j];
+      const double sg = (wy >= 0) ? 1.0 : -1.0;
+      const double rho = std::exp(-kap * std::fabs(wy));
+      const double c = std::cos(kap * sg * wx), s = std::sin(kap * sg * wx);
+      // |1 - rho e^{i phi}|^2 = (1 - rho)^2 + 4 rho sin^2(phi/2) (no cancellation)
+      const double sh = std::sin(0.5 * kap * sg * wx);
+      const double mod2 = (1 - rho) * (1 - rho) + 4 * rho * sh * sh;
+      pot += q[j] * (-std::fabs(wy) / (2 * d) - std::log(mod2) / (4 * PI));
+      // gradient of log|g|, g = 1 - e^{i kap sg w}: (Re g'/g, -Im g'/g)
+      const double gre = 1 - rho * c, gim = -rho * s;
+      const double dre = kap * sg * rho * s, dim = -kap * sg * rho * c;
+      const double fre = (dre * gre + dim * gim) / mod2;
+      const double fim = (dim * gre - dre * gim) / mod2;
+      gx += q[j] * (-fre / (2 * PI));
+      gy += q[j] * (fim / (2 * PI) - sg / (2 * d));
+    }
+    if (out_pot) out_pot[i] = pot;
+    if (out_grad) { out_grad[i] = gx; out_grad[nt + i] = gy; }
+  }
+  return 0;
+}
+
+// Yukawa, P1: direct sum over the images m d, |m| <= M, with M grown until
+// the dropped tail, at most 2 sum_{m > M} K0(beta (m - 1) d) <= 2 K0(beta (M - 1) d)
+// / (1 - e^{-beta d}), is below tol (all points have |x| <= d/2 after
+// wrapping, so an image m is at least (|m| - 1) d away).
+int oracle_yukawa_p1(double d, double beta, double tol, int64_t ns, const double* sx, const double* sy,
+                     const double* q, int64_t nt, const double* tx, const double* ty, const int64_t* self_idx,
+                     double* out_pot, double* out_grad) {
+  if (!(d > 0) || !(beta > 0) || !(tol > 0 && tol < 1)) return -1;
+  int M = 2;
+  while (2 * std::cyl_bessel_k(0.0, beta * (M - 1) * d) / (-std::expm1(-beta * d)) > tol) ++M;
+  int bad = 0;
+#pragma omp parallel for schedule(dynamic, 8) reduction(| : bad)
+  for (int64_t i = 0; i < nt; ++i) {
+    double pot = 0, gx = 0, gy = 0;
+    for (int64_t j = 0; j < ns; ++j) {
+      double bx = tx[i] - sx[j];
+      bx -= d * std::nearbyint(bx / d);
+      const double by = ty[i] - sy[j];
+      for (int m = -M; m <= M; ++m) {
+        const double rx = bx - m * d, ry = by, r2 = rx * rx + ry * ry;
+        if (r2 == 0) {
+          if (!(self_idx && j == self_idx[i])) bad = 1;
+          continue;
+        }
+        const double r = std::sqrt(r2);
+        pot += q[j] * std::cyl_bessel_k(0.0, beta * r) / (2 * PI);
+        const double g = -q[j] * beta * std::cyl_bessel_k(1.0, beta * r) / (2 * PI * r);
+        gx += g * rx; gy += g * ry;
+      }
+    }
+    if (out_pot) out_pot[i] = pot;
+    if (out_grad) { out_grad[i] = gx; out_grad[nt + i] = gy; }
+  }
+  return bad ? -4 : 0;
+}
+
+// Stokeslet, P1, in complex form: with w = x + i y, F = f1 + i f2 and
+// u = u1 + i u2, the free-space Stokeslet reads
+//   u = (1/4pi) [ -log|w| F + (F + conj F)/2 + i y conj(F) / conj(w) ]
+// (r r^T f / r^2 = (F + (w / conj w) conj F)/2 and w / conj w = 1 + 2 i y / conj w).
+// Summed symmetrically over the images w - m d: log|w| gives the sine
+// product as for Laplace, sum_m 1/(conj w - m d) = (pi/d) cot(pi conj(w)/d),
+// and the constant terms vanish for sum F = 0, so
+//   u = (1/4pi) sum_j [ -log|2 sin(pi w_j / d)| F_j + i y_j (pi/d) cot(pi conj(w_j)/d) conj(F_j) ]
+// with w_j = t - s_j. A target on its own source takes the images m != 0:
+// (1/4pi)(-log(2 pi/d) F_i - Re F_i) (the x-directed images give r r^T f / r^2
+// = (f1, 0)), and no gradient (the images pair up as m, -m).
+int oracle_stokes_p1(double d, int64_t ns, const double* sx, const double* sy, const double* f,
+                     int64_t nt, const double* tx, const double* ty, const int64_t* self_idx,
+                     double* out_vel, double* out_grad) {
+  if (!(d > 0)) return -1;
+  typedef std::complex<double> cd;
+  const double kap = 2 * PI / d, pd = PI / d;
+  const double* f1 = f;
+  const double* f2 = f + ns;
+#pragma omp parallel for schedule(dynamic, 8)
+  for (int64_t i = 0; i < nt; ++i) {
+    cd u(0, 0), ux(0, 0), uy(0, 0);
+    for (int64_t j = 0; j < ns; ++j) {
+      const cd F(f1[j], f2[j]);
+      if (self_idx && j == self_idx[i]) {
+        u += (-std::log(kap) * F - F.real()) / (4 * PI);
+        continue;
+      }
+      const double wx = tx[i] - sx[j], wy = ty[i] - sy[j];
+      const double sg = (wy >= 0) ? 1.0 : -1.0;
+      // log|2 sin(pi w/d)| = |y| pi/d + log|1 - E|, E = e^{i kap sg w}, |E| <= 1
+      const double rho = std::exp(-kap * std::fabs(wy));
+      const double sh = std::sin(0.5 * kap * sg * wx);
+      const double mod2 = (1 - rho) * (1 - rho) + 4 * rho * sh * sh;
+      const double lsin = std::fabs(wy) * pd + 0.5 * std::log(mod2);
+      const cd E = rho * cd(std::cos(kap * sg * wx), std::sin(kap * sg * wx));
+      // cot(pi w/d) = i (E + 1)/(E - 1) for y >= 0; for y < 0 with E = e^{-i kap w}:
+      // cot = -i (E + 1)/(E - 1)
+      const cd cotw = sg * cd(0, 1) * (E + 1.0) / (E - 1.0);
+      // cot(pi conj(w)/d) = conj(cot(pi w/d)); 1/sin^2 = 1 + cot^2
+      const cd cotc = std::conj(cotw);
+      const cd csc2c = 1.0 + cotc * cotc;
+      const cd Fc = std::conj(F);
+      u += (-lsin * F + cd(0, 1) * wy * pd * cotc * Fc) / (4 * PI);
+      // d/dx log|2 sin| = Re(pd cot w), d/dy = -Im(pd cot w)
+      const double lx = (pd * cotw).real(), ly = -(pd * cotw).imag();
+      // d/dx cot(pi conj w/d) = -pd csc^2, d/dy = +i pd csc^2
+      ux += (-lx * F + cd(0, 1) * wy * pd * (-pd * csc2c) * Fc) / (4 * PI);
+      uy += (-ly * F + cd(0, 1) * pd * cotc * Fc + cd(0, 1) * wy * pd * (cd(0, 1) * pd * csc2c) * Fc) / (4 * PI);
+    }
+    if (out_vel) { out_vel[i] = u.real(); out_vel[nt + i] = u.imag(); }
+    if (out_grad) {
+      out_grad[i] = ux.real(); out_grad[nt + i] = uy.real();
+      out_grad[2 * nt + i] = ux.imag(); out_grad[3 * nt + i] = uy.imag();
     }
   }
   return 0;

@@ -20,7 +20,8 @@ from . import _lib as L
 KERNELS = {"laplace": L.PFMM_LAPLACE, "yukawa": L.PFMM_YUKAWA, "stokes": L.PFMM_STOKES}
 PRECISIONS = {"fp64": L.PFMM_FP64, "mixed": L.PFMM_MIXED}
 FAR_MODES = {"auto": L.PFMM_FAR_AUTO, "direct": L.PFMM_FAR_DIRECT, "nufft": L.PFMM_FAR_NUFFT}
-NEAR_MODES = {"auto": L.PFMM_NEAR_AUTO, "one_sided": L.PFMM_NEAR_ONE_SIDED, "mutual": L.PFMM_NEAR_MUTUAL}
+NEAR_MODES = {"auto": L.PFMM_NEAR_AUTO, "one_sided": L.PFMM_NEAR_ONE_SIDED, "mutual": L.PFMM_NEAR_MUTUAL,
+              "none": L.PFMM_NEAR_NONE}
 
 
 class PfmmError(RuntimeError):
@@ -43,13 +44,14 @@ class Plan:
     """Owner of a pfmm_plan_t (see pfmm_plan)."""
 
     def __init__(self, kernel, e1, e2, tol, beta=0.0, precision="fp64", far_mode="auto", m0=0,
-                 n_dens=1, self_exclude=False, m_gl=0, check_neutral=False, profile=False, near_mode="auto"):
+                 n_dens=1, self_exclude=False, m_gl=0, check_neutral=False, profile=False, near_mode="auto",
+                 periodic=2):
         lib = L.load()
         self.kernel_name = kernel
         self.kernel = KERNELS[kernel]
         opts = L.pfmm_opts(float(beta), PRECISIONS[precision], FAR_MODES[far_mode], int(m0), int(n_dens),
                            int(bool(self_exclude)), int(m_gl), int(bool(check_neutral)), int(bool(profile)),
-                           NEAR_MODES[near_mode])
+                           NEAR_MODES[near_mode], int(periodic))
         e1 = np.ascontiguousarray(e1, dtype=np.float64)
         e2 = np.ascontiguousarray(e2, dtype=np.float64)
         h = ctypes.c_void_p()
@@ -84,6 +86,14 @@ class Plan:
         ends = (ctypes.c_int * max(n, 1))(); e0 = (ctypes.c_int * max(n, 1))()
         _check(L.load().pfmm_plan_get_log_groups(self.handle, ends, e0), "pfmm_plan_get_log_groups")
         return list(ends)[:n], list(e0)[:n]
+
+    def spread_kernel(self):
+        """(coef (17, 20), deg, beta_es): the NUFFT kernel's tap polynomials (pfmm_plan_get_spread_kernel)."""
+        coef = np.zeros(17 * 20)
+        deg, b = ctypes.c_int(), ctypes.c_double()
+        _check(L.load().pfmm_plan_get_spread_kernel(self.handle, _dp(coef), ctypes.byref(deg), ctypes.byref(b)),
+               "pfmm_plan_get_spread_kernel")
+        return coef.reshape(17, 20), deg.value, b.value
 
     def stage_times(self):
         """(near-field ms, whole-evaluation ms, evaluations) since the last call
@@ -276,6 +286,35 @@ def pfmm_autotune(plan, src, dens, trg=None, out_pot=None, out_grad=None, worksp
     report = {"n_tried": rep.n_tried, "default_ms": rep.default_ms, "best_ms": rep.best_ms,
               **pfmm_plan_get_tuning(plan)}
     return report, out_pot, out_grad
+
+
+def pfmm_workspace_bytes_pressure(plan, n_src, n_trg):
+    return int(L.load().pfmm_workspace_bytes_pressure(plan.handle, int(n_src), int(n_trg)))
+
+
+def pfmm_eval_pressure(plan, src, dens, trg=None, out_pres=None, workspace=None, stream=None):
+    """Stokes pressure at the targets (trg None: targets = sources), shape
+    (n_trg,) or (n_dens, n_trg) like the potential of a scalar plan."""
+    torch = _torch()
+    lib = L.load()
+    src = _as_points(src, "src")
+    dens = _as_dev(dens, "dens")
+    ns = src.shape[1]
+    nd = plan.n_dens
+    if plan.kernel != L.PFMM_STOKES:
+        raise ValueError("pfmm_eval_pressure needs a Stokes plan")
+    if dens.numel() != nd * 2 * ns:
+        raise ValueError("dens has the wrong size for this plan")
+    squeeze = dens.dim() == 2
+    trg_t = None if plan.self_exclude else _as_points(trg, "trg")
+    nt = ns if trg_t is None else trg_t.shape[1]
+    if out_pres is None:
+        out_pres = torch.empty((nd, nt), dtype=torch.float64, device=src.device)
+    ws, wptr, avail = _workspace(pfmm_workspace_bytes_pressure(plan, ns, nt), src.device, workspace)
+    _check(lib.pfmm_eval_pressure(plan.handle, ns, src.data_ptr(), dens.data_ptr(), nt,
+                                  None if trg_t is None else trg_t.data_ptr(), out_pres.data_ptr(), wptr, avail,
+                                  _stream_ptr(stream)), "pfmm_eval_pressure")
+    return out_pres[0] if squeeze else out_pres
 
 
 def pfmm_workspace_bytes_adjoint(plan, n_src):

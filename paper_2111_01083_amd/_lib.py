@@ -12,7 +12,7 @@ LIB_PATH = os.path.join(_PKG, "libpfmm.so")
 PFMM_LAPLACE, PFMM_YUKAWA, PFMM_STOKES = 0, 1, 2
 PFMM_FP64, PFMM_MIXED = 0, 1
 PFMM_FAR_AUTO, PFMM_FAR_DIRECT, PFMM_FAR_NUFFT = 0, 1, 2
-PFMM_NEAR_AUTO, PFMM_NEAR_ONE_SIDED, PFMM_NEAR_MUTUAL = 0, 1, 2
+PFMM_NEAR_AUTO, PFMM_NEAR_ONE_SIDED, PFMM_NEAR_MUTUAL, PFMM_NEAR_NONE = 0, 1, 2, 3
 PFMM_MAX_POINTS = 1 << 30          # largest n_src / n_trg (per cell in a batch)
 PFMM_STATIC_WORKSPACE_BYTES = 64 << 20   # the fixed device workspace of pfmm_eval_static
 ERRORS = {0: "PFMM_OK", -1: "PFMM_EINVAL", -2: "PFMM_EINVAL_LATTICE", -3: "PFMM_EINVAL_TOL",
@@ -20,9 +20,10 @@ ERRORS = {0: "PFMM_OK", -1: "PFMM_EINVAL", -2: "PFMM_EINVAL_LATTICE", -3: "PFMM_
 
 # every function declared in include/pfmm.h
 EXPORTS = ["pfmm_plan", "pfmm_plan_upload", "pfmm_plan_get_info", "pfmm_plan_get_quadrature",
-           "pfmm_plan_get_log_groups",
+           "pfmm_plan_get_log_groups", "pfmm_plan_get_spread_kernel",
            "pfmm_plan_stage_times",
            "pfmm_workspace_bytes", "pfmm_eval", "pfmm_eval_static", "pfmm_workspace_bytes_adjoint", "pfmm_eval_adjoint",
+           "pfmm_workspace_bytes_pressure", "pfmm_eval_pressure",
            "pfmm_batch_create", "pfmm_batch_workspace_bytes", "pfmm_eval_batch", "pfmm_batch_destroy",
            "pfmm_plan_get_tuning", "pfmm_plan_set_tuning", "pfmm_autotune", "pfmm_batch_autotune",
            "pfmm_destroy", "pfmm_strerror"]
@@ -32,7 +33,7 @@ class pfmm_opts(ctypes.Structure):
     _fields_ = [("beta", ctypes.c_double), ("precision", ctypes.c_int), ("far_mode", ctypes.c_int),
                 ("m0", ctypes.c_int), ("n_dens", ctypes.c_int), ("self_exclude", ctypes.c_int),
                 ("m_gl", ctypes.c_int), ("check_neutral", ctypes.c_int), ("profile", ctypes.c_int),
-                ("near_mode", ctypes.c_int)]
+                ("near_mode", ctypes.c_int), ("periodic", ctypes.c_int)]
 
 
 class pfmm_plan_info_t(ctypes.Structure):
@@ -42,7 +43,9 @@ class pfmm_plan_info_t(ctypes.Structure):
                 ("rot_cos", ctypes.c_double), ("rot_sin", ctypes.c_double), ("eps", ctypes.c_double),
                 ("n_modes", ctypes.c_int), ("n_quad", ctypes.c_int), ("m_gl", ctypes.c_int),
                 ("nufft_nf", ctypes.c_int), ("nufft_w", ctypes.c_int), ("n_images", ctypes.c_int),
-                ("n_log_groups", ctypes.c_int)]
+                ("n_log_groups", ctypes.c_int), ("periodic", ctypes.c_int), ("ew_rotated", ctypes.c_int),
+                ("ew_cos", ctypes.c_double),
+                ("ew_sin", ctypes.c_double)]
 
 
 class pfmm_tuning_t(ctypes.Structure):
@@ -76,6 +79,8 @@ def load():
     lib.pfmm_plan_get_quadrature.restype = c_int
     lib.pfmm_plan_get_log_groups.argtypes = [vp, ctypes.POINTER(c_int), ctypes.POINTER(c_int)]
     lib.pfmm_plan_get_log_groups.restype = c_int
+    lib.pfmm_plan_get_spread_kernel.argtypes = [vp, dp, ctypes.POINTER(c_int), dp]
+    lib.pfmm_plan_get_spread_kernel.restype = c_int
     lib.pfmm_plan_stage_times.argtypes = [vp, dp, dp, ctypes.POINTER(c_int)]
     lib.pfmm_plan_stage_times.restype = c_int
     lib.pfmm_workspace_bytes.argtypes = [vp, i64, i64]
@@ -88,6 +93,10 @@ def load():
     lib.pfmm_workspace_bytes_adjoint.restype = ctypes.c_size_t
     lib.pfmm_eval_adjoint.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
     lib.pfmm_eval_adjoint.restype = c_int
+    lib.pfmm_workspace_bytes_pressure.argtypes = [vp, i64, i64]
+    lib.pfmm_workspace_bytes_pressure.restype = ctypes.c_size_t
+    lib.pfmm_eval_pressure.argtypes = [vp, i64, vp, vp, i64, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.pfmm_eval_pressure.restype = c_int
     lib.pfmm_batch_create.argtypes = [c_int, ctypes.POINTER(vp), ctypes.POINTER(i64), ctypes.POINTER(i64),
                                       c_int, ctypes.POINTER(vp)]
     lib.pfmm_batch_create.restype = c_int

@@ -86,7 +86,7 @@ void plan_layout(const pfmm_plan_s* p, int64_t ns, int64_t nt, Layout& L, int64_
   // writes a single partial row
   // (forced_split > 0: batched cell; its symmetric tasks use chunks of that length)
   L.mutual = (p->mutual && p->self_exclude && ns == nt) ? 1 : 0;
-  if (L.mutual) per = std::max<int64_t>(ns, 1);
+  if (L.mutual || p->near_none) per = std::max<int64_t>(ns, 1);
   per = std::max<int64_t>(NEAR_TILE, (per + NEAR_TILE - 1) / NEAR_TILE * NEAR_TILE);
   L.split_len = per;
   L.n_splits = (int)std::max<int64_t>(1, (ns + per - 1) / per);
@@ -139,6 +139,22 @@ int pfmm_plan(int kernel, const double* e1, const double* e2, double tol, const 
   if (!p) return PFMM_ENOMEM;
   int rc = build_plan(kernel, e1, e2, tol, opts, p);
   if (rc != PFMM_OK) { delete p; return rc; }
+  if (kernel == PFMM_STOKES) {
+    // the pressure's Laplace plan: same lattice and options, the force
+    // components as 2 n_dens charge vectors, no checks or events of its own
+    pfmm_opts lo{};
+    lo.n_dens = 1;
+    if (opts) lo = *opts;
+    lo.n_dens = 2 * p->n_dens;
+    lo.beta = 0.0;
+    lo.check_neutral = 0;
+    lo.profile = 0;
+    pfmm_plan_s* lap = new (std::nothrow) pfmm_plan_s();
+    if (!lap) { delete p; return PFMM_ENOMEM; }
+    rc = build_plan(PFMM_LAPLACE, e1, e2, tol, &lo, lap);
+    if (rc != PFMM_OK) { delete lap; delete p; return rc; }
+    p->lap = lap;
+  }
   *out = p;
   return PFMM_OK;
 }
@@ -167,7 +183,7 @@ static void set_log_groups(MutualArgs& m, const Geometry& g) {
 }
 
 // the plan's device table: sn | ew | GL nodes | barycentric weights |
-// NUFFT deconvolution | images (plain, then times sigma)
+// NUFFT deconvolution | kernel polynomials | images (plain, then times sigma)
 static std::vector<double> plan_table(pfmm_plan_s* p) {
   std::vector<double> tab;
   tab.insert(tab.end(), p->sn_tab.begin(), p->sn_tab.end());
@@ -175,6 +191,7 @@ static std::vector<double> plan_table(pfmm_plan_s* p) {
   tab.insert(tab.end(), p->gl_nodes.begin(), p->gl_nodes.end());
   tab.insert(tab.end(), p->gl_bary.begin(), p->gl_bary.end());
   tab.insert(tab.end(), p->nu_deconv.begin(), p->nu_deconv.end());
+  tab.insert(tab.end(), p->nu_poly.begin(), p->nu_poly.end());
   p->tab_img = tab.size();
   const Geometry& g = p->geo;
   for (int s = 0; s < 2; ++s) {
@@ -257,8 +274,10 @@ int pfmm_plan_get_info(pfmm_plan_t p, pfmm_plan_info_t* info) {
   info->d = p->geo.d; info->xi = p->geo.xi; info->eta = p->geo.eta;
   info->rot_cos = p->geo.rc; info->rot_sin = p->geo.rs;
   info->eps = p->eps;
-  info->n_modes = p->M;
+  info->n_modes = p->n_sn > 0 ? p->M : 0;
   info->n_quad = p->n_ew;
+  info->periodic = p->periodic;
+  info->ew_rotated = p->ew_rotated; info->ew_cos = p->ew_c; info->ew_sin = p->ew_s;
   info->m_gl = p->nu.m_gl; info->nufft_nf = p->nu.nf; info->nufft_w = p->nu.w;
   info->n_images = p->geo.n_images;
   info->n_log_groups = p->geo.n_lg;
@@ -269,6 +288,14 @@ int pfmm_plan_get_quadrature(pfmm_plan_t p, double* nodes, double* weights) {
   if (!p) return PFMM_EINVAL;
   if (nodes) std::copy(p->ew_nodes.begin(), p->ew_nodes.end(), nodes);
   if (weights) std::copy(p->ew_weights.begin(), p->ew_weights.end(), weights);
+  return PFMM_OK;
+}
+
+int pfmm_plan_get_spread_kernel(pfmm_plan_t p, double* coef, int* deg, double* beta_es) {
+  if (!p) return PFMM_EINVAL;
+  if (coef) std::copy(p->nu_poly.begin(), p->nu_poly.end(), coef);
+  if (deg) *deg = p->nu.es_deg;
+  if (beta_es) *beta_es = p->nu.es_beta;
   return PFMM_OK;
 }
 
@@ -341,7 +368,7 @@ static void cell_prep(CellRun& r, const double* src_xy, int64_t src_stride, cons
   const Geometry& g = p->geo;
   const bool mixed = p->precision == PFMM_MIXED;
   PrepArgs pa{};
-  pa.rc = g.rc; pa.rs = g.rs; pa.d = g.d; pa.xi = g.xi; pa.eta = g.eta;
+  pa.rc = g.rc; pa.rs = g.rs; pa.d = g.d; pa.xi = g.xi; pa.eta = g.eta; pa.wrap_y = p->periodic == 2;
   pa.n = r.ns; pa.ystride = src_stride; pa.xy = src_xy; pa.cx = D(L.scx); pa.cy = D(L.scy);
   launch_prep_points(pa, st);
   if (!p->self_exclude) {
@@ -414,6 +441,7 @@ static int cell_far(CellRun& r, double* out_pot, double* out_grad, int64_t out_s
   FarRArgs fr{};
   fr.kernel = K; fr.n_sn = p->n_sn; fr.n_ew = p->n_ew; fr.ncw = coef_per_wave(K);
   fr.n_coef = L.n_coef; fr.n_dens = p->n_dens; fr.n_src = ns; fr.tab = p->d_tab;
+  fr.ew_c = p->ew_c; fr.ew_s = p->ew_s;
   fr.sx = D(L.scx); fr.sy = D(L.scy); fr.dens = dens_c; fr.part = D(L.far_part);
   fr.skip_sn = p->use_nufft; fr.chunk_len = L.chunk_len;
   fr.lanes = far_r_lanes((p->use_nufft ? 0 : p->n_sn) + p->n_ew + 1);
@@ -435,7 +463,8 @@ static int cell_far(CellRun& r, double* out_pot, double* out_grad, int64_t out_s
   }
   FarDArgs fd{};
   fd.kernel = K; fd.n_sn = p->n_sn; fd.n_ew = p->n_ew; fd.ncw = fr.ncw; fd.n_coef = L.n_coef;
-  fd.n_dens = p->n_dens; fd.n_chunks = d_chunks; fd.eta = g.eta; fd.xi = g.xi;
+  fd.n_dens = p->n_dens; fd.n_chunks = d_chunks; fd.eta = g.eta; fd.xi = p->ew_xi;
+  fd.ew_c = p->ew_c; fd.ew_s = p->ew_s;
   fd.tab = p->d_tab; fd.part = fr.part; fd.extra = csn; fd.w = D(L.w);
   launch_far_D(fd, st);
   const double* nu_val = nullptr;
@@ -448,6 +477,8 @@ static int cell_far(CellRun& r, double* out_pot, double* out_grad, int64_t out_s
   fl.n_dens = p->n_dens; fl.n_splits = ns > 0 ? L.n_splits : 1; fl.nufft = p->use_nufft; fl.n_trg = nt;
   fl.mixed = p->precision == PFMM_MIXED;
   fl.d = g.d; fl.eta = g.eta; fl.rc = g.rc; fl.rs = g.rs; fl.tab = p->d_tab; fl.w = D(L.w);
+  fl.ew_c = p->ew_c; fl.ew_s = p->ew_s;
+  fl.m0term = p->periodic == 2;
   fl.tx = D(L.stx); fl.ty = D(L.sty); fl.perm = (const int*)(ws + L.perm);
   fl.near_part = D(L.near_part); fl.part_stride = L.part_stride;
   fl.nu_val = nu_val; fl.out_pot = out_pot; fl.out_grad = out_grad; fl.out_stride = out_stride;
@@ -514,7 +545,9 @@ int pfmm::eval_core(pfmm_plan_t p, int64_t ns, const double* src_xy, const doubl
   cell_prep(r, src_xy, ns, dens, ns, trg_xy, nt, st);
   NearArgs na = cell_near_args(r);
   if (p->profile) (void)hipEventRecord(ev[0], st);
-  if (ns > 0 && r.L.mutual) {
+  if (p->near_none) {
+    launch_fill_zero(na.part, (int64_t)r.L.part_stride, st);   // far part alone
+  } else if (ns > 0 && r.L.mutual) {
     // diagonal tiles (one-sided, writes the partial row), then every other
     // pair once for both of its points (atomic adds into the same row)
     const bool mixed = p->precision == PFMM_MIXED;
@@ -573,6 +606,7 @@ int pfmm_plan_stage_times(pfmm_plan_t p, double* near_ms, double* total_ms, int*
 
 void pfmm_destroy(pfmm_plan_t p) {
   if (!p) return;
+  if (p->lap) pfmm_destroy(p->lap);
   for (void* e : p->prof_events) (void)hipEventDestroy((hipEvent_t)e);
   if (p->d_tab) (void)hipFree(p->d_tab);
   delete p;
@@ -847,9 +881,10 @@ int pfmm_batch_create(int n_cells, const pfmm_plan_t* plans, const int64_t* src_
   const int nc = p0->kernel == PFMM_STOKES ? 2 : 1;
   for (int c = 0; c < n_cells; ++c) {
     pfmm_plan_s* p = plans[c];
-    // check_neutral needs a stream synchronisation, which a batch never does
+    // check_neutral needs a stream synchronisation, which a batch never does;
+    // far-only plans have no near tasks; singly periodic cells are not batched
     if (!p || p->precision != p0->precision || p->n_dens != p0->n_dens || p->self_exclude != p0->self_exclude ||
-        (p->kernel == PFMM_STOKES ? 2 : 1) != nc || p->check_neutral)
+        (p->kernel == PFMM_STOKES ? 2 : 1) != nc || p->check_neutral || p->near_none || p->periodic != 2)
       return PFMM_EINVAL;
     if (src_off[c + 1] < src_off[c] || src_off[c + 1] - src_off[c] > PFMM_MAX_POINTS) return PFMM_EINVAL;
     if (!p0->self_exclude &&

@@ -39,6 +39,7 @@ struct PrepArgs {
   int64_t n, ystride;        // y coordinates at xy[ystride + i]
   const double* xy;          // [2][*] user frame
   double rc, rs, d, xi, eta;
+  int wrap_y;                // 0: singly periodic (wrap along e1 only)
   double *cx, *cy;           // canonical FP64
 };
 
@@ -106,6 +107,7 @@ struct FarRArgs {
   int64_t n_src, chunk_len;  // sources per block (grid y = source chunks)
   int lanes;                 // far_r_lanes(n_sn + n_ew + 1)
   const double* tab;         // sn records | ew records
+  double ew_c, ew_s;         // canonical -> west/east frame rotation
   const double *sx, *sy;     // canonical sources
   const double* dens;        // canonical densities [n_dens][nc][n_src]
   double* part;              // [chunk][n_dens][n_coef] complex (2 doubles)
@@ -113,7 +115,9 @@ struct FarRArgs {
 
 struct FarDArgs {
   int kernel, n_sn, n_ew, ncw, n_coef, n_dens, n_chunks;
-  double eta, xi;
+  double eta;                // canonical eta (south/north)
+  double xi;                 // xi' of the west/east frame
+  double ew_c, ew_s;         // canonical -> west/east frame rotation
   const double* tab;
   const double* part;
   const double* extra;       // NUFFT south/north coefficients [n_dens][n_sn][ncw] or NULL
@@ -125,6 +129,8 @@ struct FarLArgs {
   int mixed;                 // plane-wave factors in FP32 (phases reduced in FP64)
   int64_t n_trg;
   double d, eta, rc, rs;
+  double ew_c, ew_s;         // canonical -> west/east frame rotation
+  int m0term;                // Laplace/Stokes m = 0 south/north term (doubly periodic only)
   const double* tab;
   const double* w;
   const double *tx, *ty;     // canonical targets in binned order

@@ -28,7 +28,8 @@ __global__ void prep_points_kernel(PrepArgs a) {
   double x = a.xy[i], y = a.xy[a.ystride + i];
   double xc = a.rc * x - a.rs * y, yc = a.rs * x + a.rc * y;
   // lattice coordinates u2 = y/eta, u1 = (x - u2 xi)/d, then u <- u - rint(u)
-  double k2 = rint(yc / a.eta);
+  // (singly periodic: u1 only)
+  double k2 = a.wrap_y ? rint(yc / a.eta) : 0.0;
   yc -= k2 * a.eta;
   xc -= k2 * a.xi;
   double k1 = rint((xc - (yc / a.eta) * a.xi) / a.d);
@@ -95,7 +96,22 @@ __global__ void bin_count_kernel(SortArgs a) {
   int key = by * a.nbx + ((by & 1) ? (a.nbx - 1 - bx) : bx);   // boustrophedon rows
   if (!PFMM_NEAR_BIN) key = 0;
   a.key[i] = key;
-  atomicAdd(&a.cnt[(int64_t)key * a.nblk + i / a.bp], 1);
+  // lanes with equal (key, block) add once for all of them: clustered points
+  // put most of a wavefront in one bin, whose counter would otherwise take
+  // up to 64 serialized atomics (a few rounds, then one add per lane)
+  const int64_t slot = (int64_t)key * a.nblk + i / a.bp;
+  bool done = false;
+  for (int round = 0; round < 4; ++round) {
+    const unsigned long long pending = __ballot(!done);
+    if (!pending) break;
+    const int lead = __ffsll((long long)pending) - 1;
+    const int64_t lead_slot = __shfl(slot, lead);
+    const bool mine = !done && slot == lead_slot;
+    const unsigned long long same = __ballot(mine);
+    if (mine && (threadIdx.x & 63) == lead) atomicAdd(&a.cnt[slot], __popcll(same));
+    done = done || mine;
+  }
+  if (!done) atomicAdd(&a.cnt[slot], 1);
 }
 // In-place exclusive scan of cnt[bin][block] in three passes: segment sums
 // (one block per SCAN_SEG entries), a scan of the segment sums (one block),
@@ -1141,10 +1157,12 @@ void launch_near(int kernel, bool mixed, int nd, const NearArgs& a, int n_splits
 //   south/north (Thm. south_thm, south_thm_lap, south_thm_s):
 //     c^S = sum q e^{a y - i alpha x},  c^N = sum q e^{-a y - i alpha x}
 //     Stokes also e^S = sum y f e^{a y - i alpha x} (and north alike)
-//   west/east (Thm. west_thm, west_thm_lap, west_thm_s):
+//   west/east (Thm. west_thm, west_thm_lap, west_thm_s; Appendix A), with
+//   (x, y) the source in the west/east frame:
 //     c^W = sum q e^{kappa x - i lambda y}, c^E = sum q e^{-kappa x - i lambda y}
 //     Laplace/Stokes use e^{...} - 1 (exact for neutral densities, and free of
 //     the O(1) cancellation at small lambda); Stokes also e^W = sum x f e^{...}
+//     (force components stay canonical; far_D rotates them)
 // ---------------------------------------------------------------------------
 constexpr int FAR_R_TILE = 512;
 
@@ -1158,12 +1176,16 @@ __device__ __forceinline__ cplx csub(cplx a, cplx b) { return {a.r - b.r, a.i - 
 __device__ __forceinline__ cplx cscale(cplx a, double s) { return {a.r * s, a.i * s}; }
 __device__ __forceinline__ cplx cconj(cplx a) { return {a.r, -a.i}; }
 __device__ __forceinline__ cplx cmuli(cplx a) { return {-a.i, a.r}; }  // i*a
-// e^{a + i b} - 1 without cancellation for small |a|, |b|
-__device__ __forceinline__ cplx cexpm1(double a, double b) {
+// e^{a + i b} - 1 and e^{-a + i b} - 1 without cancellation for small |a|,
+// |b|, sharing their transcendentals (e^{-a} - 1 = -(e^a - 1) e^{-a})
+__device__ __forceinline__ void cexpm1_pair(double a, double b, cplx& plus, cplx& minus) {
   double s, c;
   sincos(b, &s, &c);
-  double sh = sin(0.5 * b);
-  return {expm1(a) * c - 2 * sh * sh, exp(a) * s};
+  const double sh = sin(0.5 * b);
+  const double cm1 = -2 * sh * sh;            // cos b - 1
+  const double em = expm1(a), e = em + 1.0, ie = 1.0 / e;
+  plus = {em * c + cm1, e * s};
+  minus = {-em * ie * c + cm1, ie * s};
 }
 
 // Block (x, y, z) = (mode group, source chunk, density group): thread
@@ -1242,7 +1264,8 @@ __global__ __launch_bounds__(FAR_R_BLOCK) void far_R_kernel(FarRArgs a) {
     } else if (is_ew) {
       const double lam = par0, kap = par1;
       for (int t = slice; t < nt; t += n_slices) {
-        const double x = s_x[t], y = s_y[t];
+        // west/east frame coordinates
+        const double x = a.ew_c * s_x[t] - a.ew_s * s_y[t], y = a.ew_s * s_x[t] + a.ew_c * s_y[t];
         if constexpr (K == PFMM_YUKAWA) {
           double sn, cs;
           sincos(lam * y, &sn, &cs);
@@ -1255,8 +1278,8 @@ __global__ __launch_bounds__(FAR_R_BLOCK) void far_R_kernel(FarRArgs a) {
             acc[d][1] = cadd(acc[d][1], cscale(pe, q));
           }
         } else {
-          const cplx wm = cexpm1(lam * x, -lam * y);    // e^{lam(x - i y)} - 1
-          const cplx emm = cexpm1(-lam * x, -lam * y);  // e^{-lam(x + i y)} - 1
+          cplx wm, emm;                                 // e^{lam(x - i y)} - 1, e^{-lam(x + i y)} - 1
+          cexpm1_pair(lam * x, -lam * y, wm, emm);
           if constexpr (K == PFMM_LAPLACE) {
 #pragma unroll
             for (int d = 0; d < DG; ++d) {
@@ -1375,11 +1398,12 @@ void launch_far_R(const FarRArgs& a, int n_chunks, hipStream_t s) {
 //     M_N = [[-1,i],[i,1]], D = fac T/(4d)):
 //     A_S = D (c^S/a - eta tau M_S c^S + M_S e^S), B_S = D M_S c^S
 //     A_N = conj(D)(c^N/a + eta conj(tau) M_N c^N + M_N e^N), B_N = conj(D) M_N c^N
-//   Stokes west/east (Thm. west_thm_s, re-derived; M_W = [[-1,i],[i,1]],
-//     M_E = [[1,i],[i,-1]], pre = w R/(4 pi)):
-//     A_W = pre((B/lam) c^W - dP B M_W c^W + B M_W e^W + xi B' M_W c^W), X_W = pre B M_W c^W
-//     A_E = pre((conj B/lam) c^E + dP conj(B) M_E c^E + conj(B) M_E e^E
-//               - xi conj(B') M_E c^E),  X_E = pre conj(B) M_E c^E
+//   Stokes west/east (Thm. west_thm_s, re-derived; in the west/east frame,
+//     force components rotated into it first and the results rotated back;
+//     M_W = [[-1,i],[i,1]], M_E = [[1,i],[i,-1]], pre = w R/(4 pi)):
+//     A_W = pre((B/lam) c^W - dP B M_W c^W + B M_W e^W + xi' B' M_W c^W), X_W = pre B M_W c^W
+//     A_E = conj(pre)((conj B/lam) c^E + conj(dP) conj(B) M_E c^E + conj(B) M_E e^E
+//               - xi' conj(B') M_E c^E),  X_E = conj(pre) conj(B) M_E c^E
 //     stored as (A_W + A_E, A_E - A_W, X_W + X_E, X_E - X_W)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void mat_s(cplx c1, cplx c2, cplx& o1, cplx& o2) {  // [[1,i],[i,-1]]
@@ -1451,32 +1475,45 @@ __global__ void far_D_kernel(FarDArgs a) {
       o[0] = cadd(tW, tE);
       o[1] = csub(tE, tW);
     } else {
-      const double lam = r[0], pre = r[2], dP = r[7];
-      const cplx B = {r[3], r[4]}, Bp = {r[5], r[6]};
-      const cplx Bc = cconj(B), Bpc = cconj(Bp);
+      const double lam = r[0];
+      const cplx pre = {r[2], r[3]}, B = {r[4], r[5]}, Bp = {r[6], r[7]}, dP = {r[8], r[9]};
+      const cplx Bc = cconj(B), Bpc = cconj(Bp), prec = cconj(pre), dPc = cconj(dP);
+      // force components of the coefficients into the west/east frame
+      const double ec = a.ew_c, es = a.ew_s;
+      cplx cc[8];
+      for (int q = 0; q < 8; q += 2) {
+        cc[q] = csub(cscale(c[q], ec), cscale(c[q + 1], es));
+        cc[q + 1] = cadd(cscale(c[q], es), cscale(c[q + 1], ec));
+      }
       cplx mw1, mw2, ew1, ew2, me1, me2, ee1, ee2;
-      mat_n(c[0], c[1], mw1, mw2);        // M_W c^W  (M_W = [[-1,i],[i,1]])
-      mat_n(c[2], c[3], ew1, ew2);        // M_W e^W
-      mat_s(c[4], c[5], me1, me2);        // M_E c^E  (M_E = [[1,i],[i,-1]])
-      mat_s(c[6], c[7], ee1, ee2);        // M_E e^E
+      mat_n(cc[0], cc[1], mw1, mw2);      // M_W c^W  (M_W = [[-1,i],[i,1]])
+      mat_n(cc[2], cc[3], ew1, ew2);      // M_W e^W
+      mat_s(cc[4], cc[5], me1, me2);      // M_E c^E  (M_E = [[1,i],[i,-1]])
+      mat_s(cc[6], cc[7], ee1, ee2);      // M_E e^E
       const cplx mw[2] = {mw1, mw2}, ew[2] = {ew1, ew2}, me[2] = {me1, me2}, ee[2] = {ee1, ee2};
       for (int k = 0; k < 2; ++k) {
-        cplx AW = cmul(B, cscale(c[k], 1.0 / lam));
-        AW = csub(AW, cscale(cmul(B, mw[k]), dP));
+        cplx AW = cmul(B, cscale(cc[k], 1.0 / lam));
+        AW = csub(AW, cmul(dP, cmul(B, mw[k])));
         AW = cadd(AW, cmul(B, ew[k]));
         AW = cadd(AW, cscale(cmul(Bp, mw[k]), a.xi));
-        AW = cscale(AW, pre);
-        const cplx XW = cscale(cmul(B, mw[k]), pre);
-        cplx AE = cmul(Bc, cscale(c[4 + k], 1.0 / lam));
-        AE = cadd(AE, cscale(cmul(Bc, me[k]), dP));
+        AW = cmul(AW, pre);
+        const cplx XW = cmul(cmul(B, mw[k]), pre);
+        cplx AE = cmul(Bc, cscale(cc[4 + k], 1.0 / lam));
+        AE = cadd(AE, cmul(dPc, cmul(Bc, me[k])));
         AE = cadd(AE, cmul(Bc, ee[k]));
         AE = csub(AE, cscale(cmul(Bpc, me[k]), a.xi));
-        AE = cscale(AE, pre);
-        const cplx XE = cscale(cmul(Bc, me[k]), pre);
+        AE = cmul(AE, prec);
+        const cplx XE = cmul(cmul(Bc, me[k]), prec);
         o[k] = cadd(AW, AE);
         o[2 + k] = csub(AE, AW);
         o[4 + k] = cadd(XW, XE);
         o[6 + k] = csub(XE, XW);
+      }
+      // velocity components back to the canonical frame
+      for (int q = 0; q < 8; q += 2) {
+        const cplx v1 = o[q], v2 = o[q + 1];
+        o[q] = cadd(cscale(v1, ec), cscale(v2, es));
+        o[q + 1] = csub(cscale(v2, ec), cscale(v1, es));
       }
     }
   }
@@ -1495,6 +1532,7 @@ void launch_far_D(const FarDArgs& a, hipStream_t s) {
 // rotate back to the user frame and write at the target's original index.
 //   scalar south/north: u += Re[(w^S e^{-a y} + w^N e^{a y}) e^{i alpha x}]
 //   scalar west/east:   u += Re[e^{i lam y}(cosh(kap x) S + sinh(kap x) D)]
+//                       with (x, y) the target in the west/east frame
 //   Laplace m = 0 (Thm. south_thm_lap and corollary, plus the zero-mean
 //   constant):          u += -y P_y/(d eta) + sum q y^2/(2 d eta)
 //   Stokes: the same waves times (A - y B) (south/north) or (A - x X)
@@ -1569,10 +1607,18 @@ __global__ __launch_bounds__(256) void far_L_kernel(FarLArgs a) {
         }
       }
     }
+    // west/east waves in the west/east frame: the target's coordinates there,
+    // and gradients taken along that frame's axes (rotated back below)
+    const double xe = a.ew_c * x - a.ew_s * y, ye = a.ew_s * x + a.ew_c * y;
+    double ge[DG][K == PFMM_STOKES ? 4 : 2];
+#pragma unroll
+    for (int d = 0; d < DG; ++d)
+#pragma unroll
+      for (int c = 0; c < (K == PFMM_STOKES ? 4 : 2); ++c) ge[d][c] = 0;
     for (int kk = 0; kk < a.n_ew; ++kk) {
       const double lam = ew_tab[kk * EW_REC], kap = ew_tab[kk * EW_REC + 1];
       double sn, cs, ep, em;
-      wave_factors<MIXED>(lam * y, kap * x, sn, cs, ep, em);
+      wave_factors<MIXED>(lam * ye, kap * xe, sn, cs, ep, em);
       const double ch = 0.5 * (ep + em), sh = 0.5 * (ep - em);
       const cplx ph = {cs, sn};
 #pragma unroll
@@ -1582,31 +1628,45 @@ __global__ __launch_bounds__(256) void far_L_kernel(FarLArgs a) {
         if constexpr (K == PFMM_STOKES) {
           for (int c = 0; c < 2; ++c) {
             const cplx wc = cld(ww + c), w2c = cld(ww + 2 + c), w4c = cld(ww + 4 + c), w6c = cld(ww + 6 + c);
-            const cplx SA = csub(wc, cscale(w4c, x));     // SigmaA - x SigmaX
-            const cplx DA = csub(w2c, cscale(w6c, x));    // DeltaA - x DeltaX
+            const cplx SA = csub(wc, cscale(w4c, xe));    // SigmaA - x SigmaX
+            const cplx DA = csub(w2c, cscale(w6c, xe));   // DeltaA - x DeltaX
             const cplx U = cadd(cscale(SA, ch), cscale(DA, sh));
             const cplx u = cmul(ph, U);
             o[d][c] += u.r;
             cplx G = cadd(cscale(SA, kap * sh), cscale(DA, kap * ch));
             G = csub(G, cadd(cscale(w4c, ch), cscale(w6c, sh)));
-            o[d][2 + 2 * c] += cmul(ph, G).r;
-            o[d][3 + 2 * c] += -lam * u.i;
+            ge[d][2 * c] += cmul(ph, G).r;
+            ge[d][2 * c + 1] += -lam * u.i;
           }
         } else {
           const cplx w0v = cld(ww + 0), w1v = cld(ww + 1);
           const cplx U = cadd(cscale(w0v, ch), cscale(w1v, sh));
           const cplx u = cmul(ph, U);
           o[d][0] += u.r;
-          o[d][1] += kap * cmul(ph, cadd(cscale(w0v, sh), cscale(w1v, ch))).r;
-          o[d][2] += -lam * u.i;
+          ge[d][0] += kap * cmul(ph, cadd(cscale(w0v, sh), cscale(w1v, ch))).r;
+          ge[d][1] += -lam * u.i;
         }
+      }
+    }
+    // d/dx = c d/dx' + s d/dy', d/dy = -s d/dx' + c d/dy'
+#pragma unroll
+    for (int d = 0; d < DG; ++d) {
+      if constexpr (K == PFMM_STOKES) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          o[d][2 + 2 * c] += a.ew_c * ge[d][2 * c] + a.ew_s * ge[d][2 * c + 1];
+          o[d][3 + 2 * c] += -a.ew_s * ge[d][2 * c] + a.ew_c * ge[d][2 * c + 1];
+        }
+      } else {
+        o[d][1] += a.ew_c * ge[d][0] + a.ew_s * ge[d][1];
+        o[d][2] += -a.ew_s * ge[d][0] + a.ew_c * ge[d][1];
       }
     }
 #pragma unroll
     for (int d = 0; d < DG; ++d) {
       if (d >= nd) break;
       const int v = v0 + d;
-      if constexpr (K != PFMM_YUKAWA) {
+      if (K != PFMM_YUKAWA && a.m0term) {
         const cplx mom = cld(w0 + (size_t)d * a.n_coef + (a.n_sn + a.n_ew) * NCW);
         const double de = a.d * a.eta;
         o[d][0] += -y * mom.r / de + mom.i / (2 * de);

@@ -19,6 +19,7 @@
 // west/east part and the Laplace/Stokes m = 0 terms stay on the direct path.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "kernels.h"
@@ -28,15 +29,19 @@ namespace pfmm {
 
 namespace {
 
+typedef const __attribute__((address_space(4))) double cdouble;   // tables: scalar loads
+
 constexpr int NU_BLOCK = 256;
-constexpr int NU_SPREAD_CHUNK = 4096;   // sources per spreading block
-constexpr int NU_LDS_DOUBLES = 8192;    // LDS sub-grid budget (64 KB)
+constexpr int SP_BLOCK = 512;           // spreading block (8 wavefronts)
+constexpr int SP_WAVES = SP_BLOCK / 64;
+constexpr int NU_LDS_BYTES = 65536;     // LDS sub-grid budget of a spreading block
 
 struct NuTabs {
   const double* sn;      // south/north records
   const double* ybar;    // [m_gl]
   const double* bary;    // [m_gl]
   const double* deconv;  // [M + 1]
+  const double* poly;    // [ES_TAPS][ES_COEF] kernel polynomials
 };
 
 NuTabs tabs_of(const pfmm_plan_s* p) {
@@ -45,6 +50,7 @@ NuTabs tabs_of(const pfmm_plan_s* p) {
   t.ybar = p->d_tab + (size_t)p->n_sn * SN_REC + (size_t)p->n_ew * EW_REC;
   t.bary = t.ybar + p->nu.m_gl;
   t.deconv = t.bary + p->nu.m_gl;
+  t.poly = t.deconv + (p->M + 1);
   return t;
 }
 
@@ -53,7 +59,7 @@ int r_fields(int kernel) { return kernel == PFMM_STOKES ? 2 : 1; }
 int l_fields(int kernel) { return kernel == PFMM_STOKES ? 12 : 3; }
 
 struct NuLayout {
-  size_t grid_r, spec, csn, grid_l, total;
+  size_t grid_r, spec, csn, grid_l, real_l, total;
   int lines_per_group, n_groups;
 };
 
@@ -67,7 +73,10 @@ NuLayout nu_layout(const pfmm_plan_s* p, int64_t ns, int64_t nt) {
   L.spec = take(16 * (size_t)nd * r_fields(p->kernel) * mgl * nf);               // complex FFT buffers
   L.csn = take(16 * (size_t)nd * p->n_sn * coef_per_wave(p->kernel));            // south/north coefficients
   L.grid_l = take(16 * (size_t)nd * l_fields(p->kernel) * mgl * nf);             // L-side line buffers
-  L.lines_per_group = std::max(1, std::min(mgl, NU_LDS_DOUBLES / nf));
+  L.real_l = take(8 * (size_t)nd * l_fields(p->kernel) * mgl * nf);              // their real parts, [dens][line][nf][field]
+  // spreading sub-grid in LDS (FP64: the deconvolution amplifies the
+  // rounding of the grid's high frequencies, so the sums stay in FP64)
+  L.lines_per_group = std::max(1, std::min(mgl, (int)(NU_LDS_BYTES / 8) / nf));
   L.n_groups = (mgl + L.lines_per_group - 1) / L.lines_per_group;
   L.total = off;
   return L;
@@ -75,10 +84,36 @@ NuLayout nu_layout(const pfmm_plan_s* p, int64_t ns, int64_t nt) {
 
 struct c2 { double r, i; };
 
-// exponential of semicircle, phi(z) = exp(b (sqrt(1 - z^2) - 1)) on |z| <= 1
-__device__ __forceinline__ double es_kernel(double z, double b) {
-  const double t = 1.0 - z * z;
-  return t > 0.0 ? exp(b * (sqrt(t) - 1.0)) : 0.0;
+// Kernel values at the taps of a point at grid coordinate g: l0 = ceil(g -
+// w/2) is the first tap, and tap t (0..w) has value p_t(u), u = 2(l0 - g +
+// w/2) - 1 (polynomials fitted by the planner to the exponential of
+// semicircle exp(b (sqrt(1 - z^2) - 1)), z = (l0 + t - g)/(w/2)). Taps t > w
+// are zero.
+template <int NP>
+__device__ __forceinline__ void es_taps(double g, int w, int deg, const double* poly, int& l0, double* ph) {
+  const double half_w = 0.5 * w;
+  const double l0d = ceil(g - half_w);
+  l0 = (int)l0d;
+  const double u = 2.0 * (l0d - g + half_w) - 1.0;
+  const cdouble* c = (const cdouble*)poly;
+#pragma unroll
+  for (int t = 0; t < NP; ++t) ph[t] = c[t * ES_COEF + deg - 1];
+  for (int k = deg - 2; k >= 0; --k) {
+#pragma unroll
+    for (int t = 0; t < NP; ++t) ph[t] = fma(ph[t], u, c[t * ES_COEF + k]);
+  }
+#pragma unroll
+  for (int t = 0; t < NP; ++t)
+    if (t > w) ph[t] = 0.0;
+}
+
+// 1/x in FP64 from the hardware estimate and two Newton steps
+__device__ __forceinline__ double rcp64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
 }
 
 // barycentric weights gamma(y, k) for all lines (second form, eq. baryweights);
@@ -87,18 +122,20 @@ template <int MG>
 __device__ __forceinline__ void bary_weights(double y, const double* ybar, const double* sig, int n, double* g) {
   constexpr int NA = MG > 0 ? MG : 32;
   const int m = MG > 0 ? MG : n;
+  const cdouble* yb = (const cdouble*)ybar;
+  const cdouble* sg = (const cdouble*)sig;
   int hit = -1;
   double s = 0.0;
 #pragma unroll
   for (int k = 0; k < NA; ++k) {
     if (k < m) {
-      const double dy = y - ybar[k];
+      const double dy = y - yb[k];
       if (dy == 0.0) hit = k;
-      g[k] = sig[k] / (dy == 0.0 ? 1.0 : dy);
+      g[k] = sg[k] * rcp64(dy == 0.0 ? 1.0 : dy);
       s += g[k];
     }
   }
-  const double is = 1.0 / s;
+  const double is = rcp64(s);
 #pragma unroll
   for (int k = 0; k < NA; ++k)
     if (k < m) g[k] = hit >= 0 ? (k == hit ? 1.0 : 0.0) : g[k] * is;
@@ -111,54 +148,66 @@ inline int np_class(int w) { return w + 1 <= 9 ? 9 : (w + 1 <= 13 ? 13 : 17); }
 
 struct SpreadArgs {
   int64_t ns;
-  int nf, w, mgl, nfield, lines_per_group, n_dens;
-  double d, b, inv_h;
+  int nf, w, deg, mgl, nfield, lines_per_group, n_dens;
+  double d, inv_h;
   const double *sx, *sy, *dens;
-  const double *ybar, *bary;
+  const double *ybar, *bary, *poly;
   double* grid;          // [dens][field][mgl][nf]
 };
 
-// grid (x: source chunk, y: line group, z: dens * field)
-template <int MG, int NP>
-__global__ __launch_bounds__(NU_BLOCK) void spread_kernel(SpreadArgs a) {
+// grid (x: source slice, y: line group, z: dens * field). Lane l of every
+// wavefront works in segment l of the source array (64 segments of
+// S = ceil(n/64) sources): global wavefront gw of GW takes offsets gw,
+// gw + GW, ... of each segment, so the 64 lanes of a wavefront hold points
+// far apart in the input order (inputs stored cluster by cluster would
+// otherwise put a wavefront's 64 LDS atomic adds on the same few grid
+// cells), while the SP_WAVES wavefronts of a block read neighbouring words
+// of the same cache lines. Each block accumulates its lines in LDS (FP64)
+// and adds them to the global grid once.
+template <int MG, int NP, typename acc_t>
+__global__ __launch_bounds__(SP_BLOCK) void spread_kernel(SpreadArgs a) {
   constexpr int NA = MG > 0 ? MG : 32;
-  __shared__ double sg[NU_LDS_DOUBLES];
+  extern __shared__ __align__(16) char sp_smem[];
+  acc_t* sg = (acc_t*)sp_smem;
   const int vf = blockIdx.z;
   const int v = vf / a.nfield, fld = vf % a.nfield;
   const int k0 = blockIdx.y * a.lines_per_group;
   const int nk = min(a.lines_per_group, a.mgl - k0);
   const int nf = a.nf;
-  for (int t = threadIdx.x; t < nk * nf; t += NU_BLOCK) sg[t] = 0.0;
+  for (int t = threadIdx.x; t < nk * nf; t += SP_BLOCK) sg[t] = (acc_t)0;
   __syncthreads();
   const double* q = a.dens + ((size_t)v * a.nfield + fld) * a.ns;
-  const int64_t j0 = (int64_t)blockIdx.x * NU_SPREAD_CHUNK;
-  const int64_t j1 = min(j0 + NU_SPREAD_CHUNK, a.ns);
-  const double half_w = 0.5 * a.w;
-  for (int64_t j = j0 + threadIdx.x; j < j1; j += NU_BLOCK) {
-    double gam[NA];
-    bary_weights<MG>(a.sy[j], a.ybar, a.bary, a.mgl, gam);
-    double x = a.sx[j];
-    x -= a.d * rint(x / a.d);                       // wrap into [-d/2, d/2]
-    const double g = (x + 0.5 * a.d) * a.inv_h;      // grid coordinate
-    const int l0 = (int)ceil(g - half_w);
-    const double qj = q[j];
+  const int lane = threadIdx.x & 63;
+  const int64_t gw = (int64_t)blockIdx.x * SP_WAVES + (threadIdx.x >> 6);
+  const int64_t GW = (int64_t)gridDim.x * SP_WAVES;
+  const int64_t seg = (a.ns + 63) / 64;
+  for (int64_t c = gw; c < seg; c += GW) {   // uniform over the wavefront
+    const int64_t j = lane * seg + c;
+    if (j < a.ns) {
+      double gam[NA];
+      bary_weights<MG>(a.sy[j], a.ybar, a.bary, a.mgl, gam);
+      double x = a.sx[j];
+      x -= a.d * rint(x / a.d);                       // wrap into [-d/2, d/2]
+      const double g = (x + 0.5 * a.d) * a.inv_h;      // grid coordinate
+      int l0;
+      double ph[NP];
+      es_taps<NP>(g, a.w, a.deg, a.poly, l0, ph);
+      const double qj = q[j];
+      int lw = ((l0 % nf) + nf) % nf;
 #pragma unroll
-    for (int t = 0; t < NP; ++t) {
-      if (t > a.w) break;
-      const int l = l0 + t;
-      const double ph = es_kernel((l - g) / half_w, a.b);
-      if (ph == 0.0) continue;
-      const int lw = ((l % nf) + nf) % nf;
-      const double val = qj * ph;
+      for (int t = 0; t < NP; ++t) {
+        const double val = qj * ph[t];
 #pragma unroll
-      for (int kk = 0; kk < NA; ++kk)
-        if (kk >= k0 && kk < k0 + nk) atomicAdd(&sg[(kk - k0) * nf + lw], val * gam[kk]);
+        for (int kk = 0; kk < NA; ++kk)
+          if (kk >= k0 && kk < k0 + nk) atomicAdd(&sg[(kk - k0) * nf + lw], (acc_t)(val * gam[kk]));
+        lw = lw + 1 == nf ? 0 : lw + 1;
+      }
     }
   }
   __syncthreads();
   double* out = a.grid + ((size_t)vf * a.mgl + k0) * nf;
-  for (int t = threadIdx.x; t < nk * nf; t += NU_BLOCK) {
-    const double val = sg[t];
+  for (int t = threadIdx.x; t < nk * nf; t += SP_BLOCK) {
+    const double val = (double)sg[t];
     if (val != 0.0) atomicAdd(&out[t], val);
   }
 }
@@ -166,8 +215,12 @@ __global__ __launch_bounds__(NU_BLOCK) void spread_kernel(SpreadArgs a) {
 // In-LDS radix-2 FFT of length n (power of two), one transform per block.
 // dir = -1: sum_l x_l e^{-2 pi i m l/n}; dir = +1: e^{+...} (no scaling).
 // real_in: input is a real array [n] per transform (imaginary part zero).
+// real_out (optional): the real parts of transform b = (v * nfl + f) * mgl + k
+// go to real_out[((v * mgl + k) * n + i) * nfl + f] (fields of a grid point
+// side by side; FP32 when real32 is set), and out is not written.
 __global__ __launch_bounds__(NU_BLOCK) void fft_kernel(const double* in_real, const c2* in_cplx, c2* out,
-                                                       int n, int log2n, int dir) {
+                                                       int n, int log2n, int dir, double* real_out, int nfl,
+                                                       int mgl, int real32) {
   extern __shared__ c2 buf[];
   const size_t off = (size_t)blockIdx.x * n;
   for (int i = threadIdx.x; i < n; i += NU_BLOCK) {
@@ -189,7 +242,19 @@ __global__ __launch_bounds__(NU_BLOCK) void fft_kernel(const double* in_real, co
     }
     __syncthreads();
   }
-  for (int i = threadIdx.x; i < n; i += NU_BLOCK) out[off + i] = buf[i];
+  if (real_out) {
+    const int b = blockIdx.x, k = b % mgl, vf = b / mgl, f = vf % nfl, v = vf / nfl;
+    const size_t o0 = (((size_t)v * mgl + k) * n) * nfl + f;
+    if (real32) {
+      float* o = (float*)real_out + o0;
+      for (int i = threadIdx.x; i < n; i += NU_BLOCK) o[(size_t)i * nfl] = (float)buf[i].r;
+    } else {
+      double* o = real_out + o0;
+      for (int i = threadIdx.x; i < n; i += NU_BLOCK) o[(size_t)i * nfl] = buf[i].r;
+    }
+  } else {
+    for (int i = threadIdx.x; i < n; i += NU_BLOCK) out[off + i] = buf[i];
+  }
 }
 
 struct CombineArgs {
@@ -274,110 +339,124 @@ __global__ void lines_kernel(LinesArgs a) {
 
 struct InterpArgs {
   int64_t nt;
-  int kernel, mgl, nf, w, n_dens;
-  double d, b, inv_h;
+  int kernel, mgl, nf, w, deg, n_dens;
+  double d, inv_h;
   NuTabs t;
   const double *tx, *ty;
-  const c2* grid;        // [dens][lfield][mgl][nf] after the inverse FFT
+  const void* grid;      // real line fields [dens][mgl][nf][lfield] after the inverse FFT (FP32 or FP64)
   double* val;           // [dens][NOUT][nt]
 };
 
-// One target per thread. The barycentric weight of line k is formed inside
-// the line loop from the normalising sum (no per-thread weight array), the
-// NP kernel values stay in registers, and the line fields go through LDS.
-template <int NP, bool STOKES>
+// One target per thread (targets in binned order, so a wavefront's taps fall
+// on nearby grid points): line weights and kernel taps in registers, then
+// for every line the NLF fields of its w + 1 taps (side by side in memory;
+// FP32 for mixed plans, whose line fields follow the inverse FFT with no
+// further amplification, FP64 otherwise).
+template <int MG, int NP, bool STOKES, typename gr_t>
 __global__ __launch_bounds__(NU_BLOCK) void interp_kernel(InterpArgs a) {
   constexpr int NLF = STOKES ? 12 : 3, NO = STOKES ? 6 : 3;
-  __shared__ double sF[NLF][NU_BLOCK];
+  constexpr int NA = MG > 0 ? MG : 32;
   const int64_t l = (int64_t)blockIdx.x * NU_BLOCK + threadIdx.x;
   if (l >= a.nt) return;                 // no block-wide barrier below
-  const int tid = threadIdx.x;
   const double y = a.ty[l];
-  // barycentric weights (second form): g_k = (sig_k / (y - ybar_k)) / sum_j sig_j / (y - ybar_j)
-  int hit = -1;
-  double ssum = 0.0;
-  for (int k = 0; k < a.mgl; ++k) {
-    const double dy = y - a.t.ybar[k];
-    if (dy == 0.0) hit = k;
-    ssum += a.t.bary[k] / (dy == 0.0 ? 1.0 : dy);
-  }
-  const double inv_s = 1.0 / ssum;
+  double gam[NA];
+  bary_weights<MG>(y, a.t.ybar, a.t.bary, a.mgl, gam);
   double x = a.tx[l];
   x -= a.d * rint(x / a.d);
   const double g = (x + 0.5 * a.d) * a.inv_h;
-  const double half_w = 0.5 * a.w;
-  const int l0 = (int)ceil(g - half_w);
+  int l0;
   double ph[NP];
-  int idx[NP];
-#pragma unroll
-  for (int t = 0; t < NP; ++t) {
-    const int li = l0 + t;
-    ph[t] = t <= a.w ? es_kernel((li - g) / half_w, a.b) : 0.0;
-    idx[t] = ((li % a.nf) + a.nf) % a.nf;
-  }
+  es_taps<NP>(g, a.w, a.deg, a.t.poly, l0, ph);
+  const int nf = a.nf;
+  const int lw0 = ((l0 % nf) + nf) % nf;
+  const int mgl = MG > 0 ? MG : a.mgl;
   for (int v = 0; v < a.n_dens; ++v) {
-    for (int f = 0; f < NLF; ++f) {
-      double s = 0.0;
-      for (int k = 0; k < a.mgl; ++k) {
-        const double gk = hit >= 0 ? (k == hit ? 1.0 : 0.0) : a.t.bary[k] / (y - a.t.ybar[k]) * inv_s;
-        const c2* row = a.grid + (((size_t)v * NLF + f) * a.mgl + k) * a.nf;
-        double r = 0.0;
+    double F[NLF];
 #pragma unroll
-        for (int t = 0; t < NP; ++t)
-          if (t <= a.w) r += ph[t] * row[idx[t]].r;
-        s += gk * r;
+    for (int f = 0; f < NLF; ++f) F[f] = 0.0;
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+      if (k >= mgl) break;
+      const gr_t* row = (const gr_t*)a.grid + (((size_t)v * mgl + k) * nf) * NLF;
+      double S[NLF];
+#pragma unroll
+      for (int f = 0; f < NLF; ++f) S[f] = 0.0;
+      int lw = lw0;
+#pragma unroll
+      for (int t = 0; t < NP; ++t) {
+        const gr_t* pt = row + (size_t)lw * NLF;
+#pragma unroll
+        for (int f = 0; f < NLF; ++f) S[f] = fma(ph[t], (double)pt[f], S[f]);
+        lw = lw + 1 == nf ? 0 : lw + 1;
       }
-      sF[f][tid] = s;
+#pragma unroll
+      for (int f = 0; f < NLF; ++f) F[f] = fma(gam[k], S[f], F[f]);
     }
     double* o = a.val + (size_t)v * NO * a.nt;
     if constexpr (STOKES) {
       // u = P - y Q; du/dx = P_x - y Q_x; du/dy = P_y - y Q_y - Q
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
-        o[(size_t)c * a.nt + l] = sF[c][tid] - y * sF[2 + c][tid];
-        o[(size_t)(2 + 2 * c) * a.nt + l] = sF[4 + c][tid] - y * sF[6 + c][tid];
-        o[(size_t)(3 + 2 * c) * a.nt + l] = sF[8 + c][tid] - y * sF[10 + c][tid] - sF[2 + c][tid];
+        o[(size_t)c * a.nt + l] = F[c] - y * F[2 + c];
+        o[(size_t)(2 + 2 * c) * a.nt + l] = F[4 + c] - y * F[6 + c];
+        o[(size_t)(3 + 2 * c) * a.nt + l] = F[8 + c] - y * F[10 + c] - F[2 + c];
       }
     } else {
-      o[l] = sF[0][tid];
-      o[a.nt + l] = sF[1][tid];
-      o[2 * a.nt + l] = sF[2][tid];
+      o[l] = F[0];
+      o[a.nt + l] = F[1];
+      o[2 * a.nt + l] = F[2];
     }
   }
 }
 
 // dispatch over the compile-time classes
 template <int MG, int NP>
-void launch_spread_np(dim3 g, const SpreadArgs& sa, hipStream_t st) {
-  hipLaunchKernelGGL((spread_kernel<MG, NP>), g, dim3(NU_BLOCK), 0, st, sa);
+void launch_spread_np(dim3 g, const SpreadArgs& sa, bool mixed, hipStream_t st) {
+  (void)mixed;
+  const size_t lds = (size_t)sa.lines_per_group * sa.nf * 8;
+  hipLaunchKernelGGL((spread_kernel<MG, NP, double>), g, dim3(SP_BLOCK), lds, st, sa);
 }
 template <int MG>
-void launch_spread_mg(dim3 g, const SpreadArgs& sa, hipStream_t st) {
+void launch_spread_mg(dim3 g, const SpreadArgs& sa, bool mixed, hipStream_t st) {
   switch (np_class(sa.w)) {
-    case 9: launch_spread_np<MG, 9>(g, sa, st); break;
-    case 13: launch_spread_np<MG, 13>(g, sa, st); break;
-    default: launch_spread_np<MG, 17>(g, sa, st); break;
+    case 9: launch_spread_np<MG, 9>(g, sa, mixed, st); break;
+    case 13: launch_spread_np<MG, 13>(g, sa, mixed, st); break;
+    default: launch_spread_np<MG, 17>(g, sa, mixed, st); break;
   }
 }
-void launch_spread(dim3 g, const SpreadArgs& sa, hipStream_t st) {
+void launch_spread(dim3 g, const SpreadArgs& sa, bool mixed, hipStream_t st) {
   switch (mg_class(sa.mgl)) {
-    case 8: launch_spread_mg<8>(g, sa, st); break;
-    case 12: launch_spread_mg<12>(g, sa, st); break;
-    case 16: launch_spread_mg<16>(g, sa, st); break;
-    default: launch_spread_mg<0>(g, sa, st); break;
+    case 8: launch_spread_mg<8>(g, sa, mixed, st); break;
+    case 12: launch_spread_mg<12>(g, sa, mixed, st); break;
+    case 16: launch_spread_mg<16>(g, sa, mixed, st); break;
+    default: launch_spread_mg<0>(g, sa, mixed, st); break;
   }
 }
-template <int NP>
+template <int MG, int NP, typename gr_t>
 void launch_interp_np(dim3 g, const InterpArgs& ia, hipStream_t st) {
-  if (ia.kernel == PFMM_STOKES) hipLaunchKernelGGL((interp_kernel<NP, true>), g, dim3(NU_BLOCK), 0, st, ia);
-  else hipLaunchKernelGGL((interp_kernel<NP, false>), g, dim3(NU_BLOCK), 0, st, ia);
+  if (ia.kernel == PFMM_STOKES) hipLaunchKernelGGL((interp_kernel<MG, NP, true, gr_t>), g, dim3(NU_BLOCK), 0, st, ia);
+  else hipLaunchKernelGGL((interp_kernel<MG, NP, false, gr_t>), g, dim3(NU_BLOCK), 0, st, ia);
 }
-void launch_interp(dim3 g, const InterpArgs& ia, hipStream_t st) {
+template <int MG, typename gr_t>
+void launch_interp_mg(dim3 g, const InterpArgs& ia, hipStream_t st) {
   switch (np_class(ia.w)) {
-    case 9: launch_interp_np<9>(g, ia, st); break;
-    case 13: launch_interp_np<13>(g, ia, st); break;
-    default: launch_interp_np<17>(g, ia, st); break;
+    case 9: launch_interp_np<MG, 9, gr_t>(g, ia, st); break;
+    case 13: launch_interp_np<MG, 13, gr_t>(g, ia, st); break;
+    default: launch_interp_np<MG, 17, gr_t>(g, ia, st); break;
   }
+}
+template <typename gr_t>
+void launch_interp_t(dim3 g, const InterpArgs& ia, hipStream_t st) {
+  switch (mg_class(ia.mgl)) {
+    case 8: launch_interp_mg<8, gr_t>(g, ia, st); break;
+    case 12: launch_interp_mg<12, gr_t>(g, ia, st); break;
+    case 16: launch_interp_mg<16, gr_t>(g, ia, st); break;
+    default: launch_interp_mg<0, gr_t>(g, ia, st); break;
+  }
+}
+void launch_interp(dim3 g, const InterpArgs& ia, bool mixed, hipStream_t st) {
+  if (mixed) launch_interp_t<float>(g, ia, st);
+  else launch_interp_t<double>(g, ia, st);
 }
 
 __global__ void zero_kernel(double* p, int64_t n) {
@@ -409,16 +488,22 @@ int nufft_R(const pfmm_plan_s* p, int64_t ns, const double* sx, const double* sy
   zero(grid, (int64_t)nd * nfr * mgl * nf, st);
   if (ns > 0) {
     SpreadArgs sa{};
-    sa.ns = ns; sa.nf = nf; sa.w = p->nu.w; sa.mgl = mgl; sa.nfield = nfr;
+    sa.ns = ns; sa.nf = nf; sa.w = p->nu.w; sa.deg = p->nu.es_deg; sa.mgl = mgl; sa.nfield = nfr;
     sa.lines_per_group = L.lines_per_group; sa.n_dens = nd;
-    sa.d = p->geo.d; sa.b = p->nu.es_beta; sa.inv_h = nf / p->geo.d;
-    sa.sx = sx; sa.sy = sy; sa.dens = dens; sa.ybar = t.ybar; sa.bary = t.bary; sa.grid = grid;
-    dim3 g((unsigned)((ns + NU_SPREAD_CHUNK - 1) / NU_SPREAD_CHUNK), (unsigned)L.n_groups, (unsigned)(nd * nfr));
-    launch_spread(g, sa, st);
+    sa.d = p->geo.d; sa.inv_h = nf / p->geo.d;
+    sa.sx = sx; sa.sy = sy; sa.dens = dens; sa.ybar = t.ybar; sa.bary = t.bary; sa.poly = t.poly;
+    sa.grid = grid;
+    // about two blocks per compute unit in all, each slice of at least 4
+    // sources per thread
+    const int64_t yz = (int64_t)L.n_groups * nd * nfr;
+    const int64_t by_work = (ns + 4 * SP_BLOCK - 1) / (4 * SP_BLOCK);
+    const int64_t bx = std::max<int64_t>(1, std::min<int64_t>(by_work, (512 + yz - 1) / yz));
+    dim3 g((unsigned)bx, (unsigned)L.n_groups, (unsigned)(nd * nfr));
+    launch_spread(g, sa, p->precision == PFMM_MIXED, st);
   }
   const int nfft = nd * nfr * mgl;
   hipLaunchKernelGGL(fft_kernel, dim3(nfft), dim3(NU_BLOCK), nf * sizeof(c2), st, (const double*)grid,
-                     (const c2*)nullptr, spec, nf, ilog2(nf), -1);
+                     (const c2*)nullptr, spec, nf, ilog2(nf), -1, (double*)nullptr, 1, 1, 0);
   CombineArgs ca{};
   ca.kernel = p->kernel; ca.n_sn = p->n_sn; ca.m_lo = p->m_lo; ca.mgl = mgl; ca.nf = nf; ca.n_dens = nd;
   ca.ncw = coef_per_wave(p->kernel); ca.nfield = nfr; ca.t = t; ca.spec = spec; ca.csn = csn;
@@ -439,14 +524,16 @@ int nufft_L(const pfmm_plan_s* p, int64_t nt, const double* tx, const double* ty
   la.ncw = coef_per_wave(p->kernel); la.n_coef = n_coef; la.t = t; la.w = (const c2*)w; la.grid = grid;
   hipLaunchKernelGGL(lines_kernel, dim3((p->n_sn + 127) / 128, mgl, nd), dim3(128), 0, st, la);
   const int nfft = nd * nlf * mgl;
+  double* real_l = (double*)(ws + L.real_l);
+  const bool mixed = p->precision == PFMM_MIXED;   // FP32 line fields (no deconvolution follows)
   hipLaunchKernelGGL(fft_kernel, dim3(nfft), dim3(NU_BLOCK), nf * sizeof(c2), st, (const double*)nullptr,
-                     (const c2*)grid, grid, nf, ilog2(nf), +1);
+                     (const c2*)grid, grid, nf, ilog2(nf), +1, real_l, nlf, mgl, mixed ? 1 : 0);
   if (nt > 0) {
     InterpArgs ia{};
-    ia.nt = nt; ia.kernel = p->kernel; ia.mgl = mgl; ia.nf = nf; ia.w = p->nu.w; ia.n_dens = nd;
-    ia.d = p->geo.d; ia.b = p->nu.es_beta; ia.inv_h = nf / p->geo.d; ia.t = t; ia.tx = tx; ia.ty = ty;
-    ia.grid = grid; ia.val = val;
-    launch_interp(dim3((unsigned)((nt + NU_BLOCK - 1) / NU_BLOCK)), ia, st);
+    ia.nt = nt; ia.kernel = p->kernel; ia.mgl = mgl; ia.nf = nf; ia.w = p->nu.w; ia.deg = p->nu.es_deg;
+    ia.n_dens = nd; ia.d = p->geo.d; ia.inv_h = nf / p->geo.d; ia.t = t; ia.tx = tx; ia.ty = ty;
+    ia.grid = real_l; ia.val = val;
+    launch_interp(dim3((unsigned)((nt + NU_BLOCK - 1) / NU_BLOCK)), ia, mixed, st);
   }
   *val_out = val;
   return PFMM_OK;

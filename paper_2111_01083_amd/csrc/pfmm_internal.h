@@ -39,15 +39,18 @@ struct Geometry {
 //   [4] tau_r [5] tau_i : Stokes (2 - e^{-Q})/(1 - e^{-Q}); unused otherwise
 //   fac = 1 for m = 0, 2 otherwise (modes -m are conjugates for real densities)
 constexpr int SN_REC = 6;
-// Per west/east node record (doubles):
+// Per west/east node record (doubles). The west/east waves live in the
+// west/east frame: canonical coordinates rotated by (ew_c, ew_s), in which
+// e1 = (dx', dy') and e2 = (xi', eta') (Appendix A; the identity frame has
+// dx' = d, dy' = 0, xi' = xi, eta' = eta):
 //   [0] lambda  [1] kappa (sqrt(lambda^2+beta^2) for Yukawa, lambda otherwise)
-//   scalar kernels: [2..3] DW = w R B/(2 pi kappa)  [4..5] DE = w R conj(B)/(2 pi kappa)
-//   Stokes:         [2] pre = w R/(4 pi)  [3..4] B  [5..6] B' [7] d P
-//   R = e^{-p kappa d}/(1-e^{-kappa d}), p = m0+1,
-//   B = e^{-kappa xi + i lambda eta} + e^{kappa xi - i lambda eta} + 1,
-//   B' = -e^{-lambda xi + i lambda eta} + e^{lambda xi - i lambda eta},
-//   P = (p - (p-1) e^{-lambda d})/(1 - e^{-lambda d})
-constexpr int EW_REC = 8;
+//   scalar kernels: [2..3] DW = w R B/(2 pi kappa)  [4..5] DE = w conj(R B)/(2 pi kappa)
+//   Stokes:         [2..3] pre = w R/(4 pi)  [4..5] B  [6..7] B'  [8..9] dx' P
+//   a = kappa dx' - i lambda dy',  R = e^{-p a}/(1-e^{-a}), p = m0+1,
+//   B = e^{-kappa xi' + i lambda eta'} + e^{kappa xi' - i lambda eta'} + 1,
+//   B' = -e^{-lambda xi' + i lambda eta'} + e^{lambda xi' - i lambda eta'},
+//   P = (p - (p-1) e^{-a})/(1 - e^{-a})
+constexpr int EW_REC = 12;
 
 // complex coefficients per wave (mode or node) and density:
 //   scalar kernels: 2 (south|west, north|east)
@@ -59,17 +62,32 @@ struct NufftParams {
   int nf;          // fine grid points per period d
   int w;           // spreading kernel width (grid points)
   double es_beta;  // exponential-of-semicircle kernel shape parameter
+  int es_deg;      // degree of the per-tap polynomials of the kernel
 };
+
+// Spreading kernel as polynomials: tap t (0..w) of a point whose grid offset
+// is f = l0 - g + w/2 in [0, 1) has value sum_k c[t][k] u^k, u = 2f - 1;
+// stored as ES_TAPS x ES_COEF doubles (fixed size, zero-padded)
+constexpr int ES_TAPS = 17;
+constexpr int ES_COEF = 20;
 
 }  // namespace pfmm
 
 struct pfmm_plan_s {
   int kernel, precision, far_mode, m0, n_dens, self_exclude, check_neutral, profile;
   int mutual;                  // near field by symmetric pair evaluation (self targets)
+  int near_none;               // far part only (near images left out)
   double beta, tol, eps;
   pfmm::Geometry geo;
   int M, m_lo, n_sn;           // south/north modes m = m_lo..M
   int n_ew;                    // west/east nodes
+  // west/east frame (Appendix A): canonical -> [[ew_c, -ew_s], [ew_s, ew_c]];
+  // rotated so that e2 is vertical (xi' = 0) when the canonical frame would
+  // need a wider near region, else the identity
+  int ew_rotated;
+  double ew_c, ew_s, ew_dx, ew_dy, ew_xi, ew_eta;
+  int ew_rows;                 // west/east rows: 3 (n = -1, 0, 1) or 1 (singly periodic)
+  int periodic;                // 2: doubly periodic (P2), 1: singly periodic in e1 (P1)
   std::vector<double> sn_tab;  // n_sn * SN_REC
   std::vector<double> ew_tab;  // n_ew * EW_REC
   std::vector<double> ew_nodes, ew_weights;
@@ -81,13 +99,17 @@ struct pfmm_plan_s {
   std::vector<double> gl_nodes;    // ybar_k on [-eta/2, eta/2]
   std::vector<double> gl_bary;     // barycentric weights sigma_k
   std::vector<double> nu_deconv;   // 1/phihat(m) for m = 0..M (real, even kernel)
+  std::vector<double> nu_poly;     // ES_TAPS * ES_COEF kernel polynomial coefficients
   // device copies (per device, uploaded lazily)
   int dev_id;
-  double* d_tab;               // sn_tab | ew_tab | gl_nodes | gl_bary | nu_deconv | images
+  double* d_tab;               // sn_tab | ew_tab | gl_nodes | gl_bary | nu_deconv | nu_poly | images
   size_t tab_img;              // offset in d_tab of img_x, img_y, then both times sigma
   size_t tab_doubles;
   // profiling: event triples (start, near done, end) of evaluations not yet read
   std::vector<void*> prof_events;
+  // Stokes plans: a Laplace plan of the same lattice and options with 2 n_dens
+  // density vectors, whose gradients give the pressure (pressure.hip)
+  pfmm_plan_s* lap = nullptr;
 };
 
 namespace pfmm {

@@ -43,6 +43,13 @@ void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
 
 namespace {
 
+// 1 - e^{-a} for complex a, without cancellation for small |a|
+cd one_minus_exp(cd a) {
+  const double sh = std::sin(0.5 * a.imag());
+  const cd em1(std::expm1(-a.real()) * std::cos(a.imag()) - 2 * sh * sh, -std::exp(-a.real()) * std::sin(a.imag()));
+  return -em1;
+}
+
 // Gauss-Lagrange reduction of a 2D lattice basis; returns b1 (shortest) and
 // b2 with |b1| <= |b2| and |b1.b2| <= |b1|^2/2.
 void reduce_basis(double b1[2], double b2[2]) {
@@ -164,6 +171,98 @@ void ew_rule(int kernel, double beta, double d, double xi, double eta, int m0, d
   }
 }
 
+// West/east rule in a rotated frame (Appendix A, eq. k0west2): with e2
+// vertical the closest west/east image is a full column dx' away, but the
+// integrand e^{-kappa X} e^{i lambda Y} B R, R = e^{-p a}/(1 - e^{-a}),
+// a = kappa dx' - i lambda dy', oscillates with |Y| up to |dy'| + eta' plus
+// the frequencies of R (multiples of dy'), and R has near-poles where
+// lambda dy' ~ 2 pi k while kappa dx' is small. The rule is built by
+// adaptive bisection of Gauss-Legendre panels on [0, L]: a panel is kept
+// when its np- and 2np-point sums of every sampled integrand (X and Y over
+// their ranges) agree within eps times that sample's integral of |f|,
+// prorated by the panel's length. Laplace/Stokes samples are multiplied by
+// lambda/(1+lambda) (the combined west+east integrand is smooth at 0).
+// rows = 3: the rows n = -1, 0, 1 of the doubly periodic split, |y
+// offsets| up to Ym = |dy'| + eta'; rows = 1: the singly periodic split (one
+// row, B = 1), |y offsets| up to the strip height Ym.
+void ew_rule_adaptive(int kernel, double beta, double dx, double dy, double xi2, double eta2, int rows, double Ym,
+                      int m0, double eps, std::vector<double>& nodes, std::vector<double>& wts) {
+  nodes.clear(); wts.clear();
+  const double Xmin = m0 * dx;
+  const double lk = (std::log(1.0 / eps) + 2.0) / Xmin;
+  double L;
+  if (kernel == PFMM_YUKAWA) {
+    if (lk <= beta) return;
+    L = std::sqrt(lk * lk - beta * beta);
+  } else {
+    L = lk;
+  }
+  const int p0 = m0 + 1;
+  std::vector<double> sx, sy;
+  for (int i = 0; i < 5; ++i)
+    for (int j = 0; j < 9; ++j) {
+      sx.push_back(dx * (-0.999 + 0.4995 * i));
+      sy.push_back(Ym * (-1.0 + 0.25 * j));
+    }
+  const size_t ns = sx.size();
+  auto f = [&](double lam, std::vector<cd>& out) {
+    const double kap = kernel == PFMM_YUKAWA ? std::sqrt(lam * lam + beta * beta) : lam;
+    const cd a(kap * dx, -lam * dy);
+    const cd R = std::exp(-double(p0) * a) / one_minus_exp(a);
+    const cd B = rows == 1 ? cd(1.0) : std::exp(cd(-kap * xi2, lam * eta2)) + std::exp(cd(kap * xi2, -lam * eta2)) + 1.0;
+    const double s = kernel == PFMM_YUKAWA ? 1.0 / kap : lam / (1.0 + lam);
+    for (size_t k = 0; k < ns; ++k) out[k] = s * std::exp(cd(-kap * sx[k], lam * sy[k])) * R * B;
+  };
+  const int np = eps >= 1e-8 ? 12 : (eps >= 1e-12 ? 16 : 20);
+  std::vector<double> g1x, g1w, g2x, g2w;
+  gauss_legendre(np, g1x, g1w);
+  gauss_legendre(2 * np, g2x, g2w);
+  std::vector<cd> val(ns);
+  auto panel = [&](double a0, double b0, int n, const std::vector<double>& gx, const std::vector<double>& gw,
+                   std::vector<cd>& I, std::vector<double>* A) {
+    I.assign(ns, cd(0.0));
+    if (A) A->assign(ns, 0.0);
+    for (int i = 0; i < n; ++i) {
+      const double lam = 0.5 * (b0 - a0) * (gx[i] + 1) + a0, w = 0.5 * (b0 - a0) * gw[i];
+      f(lam, val);
+      for (size_t k = 0; k < ns; ++k) {
+        I[k] += w * val[k];
+        if (A) (*A)[k] += w * std::abs(val[k]);
+      }
+    }
+  };
+  // scale of each sample: integral of |f| on a fine uniform composite rule
+  const double h0 = std::min(L, 2 * PI / (Ym + 2 * std::fabs(dy) + eta2));
+  const int n0 = std::max(1, (int)std::ceil(L / h0));
+  std::vector<double> scale(ns, 0.0), tmpA;
+  std::vector<cd> I1, I2;
+  for (int e = 0; e < n0; ++e) {
+    panel(L * e / n0, L * (e + 1) / n0, 2 * np, g2x, g2w, I2, &tmpA);
+    for (size_t k = 0; k < ns; ++k) scale[k] += tmpA[k];
+  }
+  std::vector<std::pair<double, double>> todo;
+  for (int e = n0 - 1; e >= 0; --e) todo.push_back({L * e / n0, L * (e + 1) / n0});
+  std::vector<std::pair<double, double>> done;
+  while (!todo.empty() && done.size() + todo.size() < 4096) {
+    auto [a0, b0] = todo.back();
+    todo.pop_back();
+    panel(a0, b0, np, g1x, g1w, I1, nullptr);
+    panel(a0, b0, 2 * np, g2x, g2w, I2, nullptr);
+    bool ok = true;
+    for (size_t k = 0; k < ns && ok; ++k)
+      ok = std::abs(I1[k] - I2[k]) <= 0.25 * eps * scale[k] * (b0 - a0) / L;
+    if (ok || b0 - a0 < 1e-9 * L) done.push_back({a0, b0});
+    else { todo.push_back({0.5 * (a0 + b0), b0}); todo.push_back({a0, 0.5 * (a0 + b0)}); }
+  }
+  for (auto& pr : todo) done.push_back(pr);
+  std::sort(done.begin(), done.end());
+  for (auto [a0, b0] : done)
+    for (int i = 0; i < np; ++i) {
+      nodes.push_back(0.5 * (b0 - a0) * (g1x[i] + 1) + a0);
+      wts.push_back(0.5 * (b0 - a0) * g1w[i]);
+    }
+}
+
 }  // namespace
 
 // NUFFT grid and kernel (Sec. 6.1). grid 0: the smallest power of two
@@ -193,6 +292,56 @@ int set_nufft_grid(pfmm_plan_s* p, int grid) {
   const double so = grid == 1 ? 4.0 : 2.0;
   p->nu.es_beta = 0.97 * PI * (1 - 1 / (2 * so)) * w;
   p->nu_grid = grid;
+  // the kernel's taps as polynomials in u = 2f - 1 (least squares on 4x
+  // oversampled Chebyshev points, Householder QR), so that a point's w + 1
+  // kernel values cost one Horner pass instead of w + 1 exp and sqrt
+  {
+    const int D = std::min(ES_COEF, w + 4);
+    p->nu.es_deg = D;
+    p->nu_poly.assign((size_t)ES_TAPS * ES_COEF, 0.0);
+    const int K = 4 * D;
+    const double bb = p->nu.es_beta;
+    for (int t = 0; t <= w; ++t) {
+      std::vector<double> A((size_t)K * D), y(K);
+      for (int i = 0; i < K; ++i) {
+        const double u = std::cos(PI * (i + 0.5) / K), f = 0.5 * (u + 1);
+        const double z = (t + f - 0.5 * w) / (0.5 * w);
+        y[i] = std::fabs(z) < 1 ? std::exp(bb * (std::sqrt(1 - z * z) - 1)) : 0.0;
+        double pw = 1;
+        for (int k = 0; k < D; ++k) { A[(size_t)i * D + k] = pw; pw *= u; }
+      }
+      // Householder QR of A (K x D), then R c = Q^T y
+      for (int k = 0; k < D; ++k) {
+        double nrm = 0;
+        for (int i = k; i < K; ++i) nrm += A[(size_t)i * D + k] * A[(size_t)i * D + k];
+        nrm = std::sqrt(nrm);
+        const double a0 = A[(size_t)k * D + k];
+        const double alpha = a0 > 0 ? -nrm : nrm;
+        std::vector<double> v(K, 0.0);
+        v[k] = a0 - alpha;
+        for (int i = k + 1; i < K; ++i) v[i] = A[(size_t)i * D + k];
+        double vv = 0;
+        for (int i = k; i < K; ++i) vv += v[i] * v[i];
+        if (vv == 0) continue;
+        for (int j = k; j < D; ++j) {
+          double s2 = 0;
+          for (int i = k; i < K; ++i) s2 += v[i] * A[(size_t)i * D + j];
+          s2 *= 2 / vv;
+          for (int i = k; i < K; ++i) A[(size_t)i * D + j] -= s2 * v[i];
+        }
+        double s2 = 0;
+        for (int i = k; i < K; ++i) s2 += v[i] * y[i];
+        s2 *= 2 / vv;
+        for (int i = k; i < K; ++i) y[i] -= s2 * v[i];
+      }
+      double* c = &p->nu_poly[(size_t)t * ES_COEF];
+      for (int k = D - 1; k >= 0; --k) {
+        double s2 = y[k];
+        for (int j = k + 1; j < D; ++j) s2 -= A[(size_t)k * D + j] * c[j];
+        c[k] = s2 / A[(size_t)k * D + k];
+      }
+    }
+  }
   p->nu_deconv.assign(M + 1, 0.0);
   std::vector<double> qx, qw;
   gauss_legendre(2 * w + 40, qx, qw);
@@ -226,6 +375,7 @@ int build_plan(int kernel, const double* e1, const double* e2, double tol, const
   if (o.precision != PFMM_FP64 && o.precision != PFMM_MIXED) return PFMM_EINVAL;
   if (o.far_mode < 0 || o.far_mode > 2) return PFMM_EINVAL;
   if (o.m0 < 0 || o.m0 > 3 || o.m_gl < 0 || o.m_gl > 32) return PFMM_EINVAL;
+  if (o.periodic != 0 && o.periodic != 1 && o.periodic != 2) return PFMM_EINVAL;
 
   p->kernel = kernel;
   p->precision = o.precision;
@@ -233,23 +383,30 @@ int build_plan(int kernel, const double* e1, const double* e2, double tol, const
   p->self_exclude = o.self_exclude ? 1 : 0;
   p->check_neutral = o.check_neutral ? 1 : 0;
   p->profile = o.profile ? 1 : 0;
-  if (o.near_mode < 0 || o.near_mode > 2) return PFMM_EINVAL;
+  if (o.near_mode < 0 || o.near_mode > 3) return PFMM_EINVAL;
   if (o.near_mode == PFMM_NEAR_MUTUAL && !o.self_exclude) return PFMM_EINVAL;
-  p->mutual = (o.near_mode != PFMM_NEAR_ONE_SIDED && o.self_exclude) ? 1 : 0;
+  p->near_none = o.near_mode == PFMM_NEAR_NONE ? 1 : 0;
+  p->mutual = (o.near_mode != PFMM_NEAR_ONE_SIDED && !p->near_none && o.self_exclude) ? 1 : 0;
   p->beta = kernel == PFMM_YUKAWA ? o.beta : 0.0;
   p->tol = tol;
   p->eps = tol / 10;
 
   // --- canonical lattice (Sec. 1): e1 = (d, 0) the longer reduced vector,
-  // e2 = (xi, eta) with eta > 0 and |xi| <= d/2.
+  // e2 = (xi, eta) with eta > 0 and |xi| <= d/2. Singly periodic (P1):
+  // e1 is the period and is not reduced; the cell is the strip of width d
+  // and height eta (the part of e2 across e1), xi = 0.
+  const bool p1 = o.periodic == 1;
   double b1[2] = {e1[0], e1[1]}, b2[2] = {e2[0], e2[1]};
-  reduce_basis(b1, b2);
+  if (!p1) reduce_basis(b1, b2);
+  else { std::swap(b1[0], b2[0]); std::swap(b1[1], b2[1]); }
   const double d = std::hypot(b2[0], b2[1]);
   const double rc = b2[0] / d, rs = -b2[1] / d;  // R rotates b2 onto +x
   double xi = rc * b1[0] - rs * b1[1];
   double eta = rs * b1[0] + rc * b1[1];
   if (eta < 0) { xi = -xi; eta = -eta; }
   xi -= d * std::nearbyint(xi / d);
+  if (p1) xi = 0.0;
+  p->periodic = p1 ? 1 : 2;
   pfmm::Geometry& g = p->geo;
   g.d = d; g.xi = xi; g.eta = eta; g.rc = rc; g.rs = rs;
 
@@ -262,11 +419,33 @@ int build_plan(int kernel, const double* e1, const double* e2, double tol, const
     g.sigma = std::ldexp(1.0, k);
     g.lg_shift = 2 * k;
   }
-  int m0 = std::fabs(xi) <= 0.25 * d ? 1 : 2;
-  if (o.m0 > 0) m0 = std::max(m0, o.m0);
+  // west/east frame: the canonical one keeps the closest west/east image at
+  // x-distance m0 d - 2|xi|, enough with m0 = 1 while |xi| <= d/4. Beyond
+  // that the waves are taken along e2-perp instead (Appendix A): the closest
+  // west/east image is then one full column, dx' = d eta/|e2|, away, and
+  // m0 = 1 (9 near images) holds for every shear. An explicit m0 >= 2 keeps
+  // the canonical frame.
+  int m0 = 1;
+  p->ew_rotated = 0;
+  if (o.m0 > 0) m0 = o.m0;
+  else if (!p1 && std::fabs(xi) > 0.25 * d) p->ew_rotated = 1;
+  if (!p1 && o.m0 == 1 && std::fabs(xi) > 0.25 * d) p->ew_rotated = 1;
   p->m0 = m0;
+  {
+    const double l2 = std::hypot(xi, eta);
+    if (p->ew_rotated) {
+      p->ew_c = eta / l2; p->ew_s = xi / l2;
+      p->ew_dx = d * eta / l2; p->ew_dy = d * xi / l2; p->ew_xi = 0.0; p->ew_eta = l2;
+    } else {
+      p->ew_c = 1.0; p->ew_s = 0.0;
+      p->ew_dx = d; p->ew_dy = 0.0; p->ew_xi = xi; p->ew_eta = eta;
+    }
+    // the west/east rows: n = -1, 0, 1 (P2) or n = 0 alone (P1)
+    p->ew_rows = p1 ? 1 : 3;
+    if (p1) p->ew_eta = 0.0;
+  }
   g.n_images = 0;
-  for (int n = -1; n <= 1; ++n)
+  for (int n = p1 ? 0 : -1; n <= (p1 ? 0 : 1); ++n)
     for (int m = -m0; m <= m0; ++m) {
       g.img_x[g.n_images] = m * d + n * xi;
       g.img_y[g.n_images] = n * eta;
@@ -280,6 +459,7 @@ int build_plan(int kernel, const double* e1, const double* e2, double tol, const
   int M = (int)std::ceil(d / (2 * PI * eta) * std::log(1.0 / ((1 - std::exp(-2 * PI * eta / d)) * eps)));
   M = std::max(M, 1);
   p->m_lo = kernel == PFMM_YUKAWA ? 0 : 1;
+  if (p1) M = p->m_lo - 1;   // no south/north rows
   // for Yukawa, drop modes whose whole contribution e^{-chi_m eta} is below eps
   if (kernel == PFMM_YUKAWA) {
     while (M > 0) {
@@ -304,26 +484,35 @@ int build_plan(int kernel, const double* e1, const double* e2, double tol, const
     r[0] = al; r[1] = a; r[2] = D.real(); r[3] = D.imag(); r[4] = tau.real(); r[5] = tau.imag();
   }
 
-  // --- west/east rule and weights
-  ew_rule(kernel, beta, d, xi, eta, m0, eps, p->ew_nodes, p->ew_weights);
+  // --- west/east rule and weights (in the west/east frame)
+  if (p1)
+    ew_rule_adaptive(kernel, beta, d, 0.0, 0.0, 0.0, 1, eta, m0, eps, p->ew_nodes, p->ew_weights);
+  else if (p->ew_rotated)
+    ew_rule_adaptive(kernel, beta, p->ew_dx, p->ew_dy, p->ew_xi, p->ew_eta, 3, std::fabs(p->ew_dy) + p->ew_eta, m0,
+                     eps, p->ew_nodes, p->ew_weights);
+  else
+    ew_rule(kernel, beta, d, xi, eta, m0, eps, p->ew_nodes, p->ew_weights);
   p->n_ew = (int)p->ew_nodes.size();
   p->ew_tab.assign((size_t)p->n_ew * EW_REC, 0.0);
   const int pp = m0 + 1;
   for (int k = 0; k < p->n_ew; ++k) {
     double lam = p->ew_nodes[k], w = p->ew_weights[k];
     double kap = kernel == PFMM_YUKAWA ? std::sqrt(lam * lam + beta * beta) : lam;
-    double R = std::exp(-pp * kap * d) / (-std::expm1(-kap * d));
-    cd B = std::exp(cd(-kap * xi, lam * eta)) + std::exp(cd(kap * xi, -lam * eta)) + 1.0;
+    const cd a(kap * p->ew_dx, -lam * p->ew_dy);
+    const cd ea = std::exp(-a), om = one_minus_exp(a);
+    const cd R = std::exp(-double(pp) * a) / om;
+    const double x2 = p->ew_xi, y2 = p->ew_eta;
+    cd B = p1 ? cd(1.0) : std::exp(cd(-kap * x2, lam * y2)) + std::exp(cd(kap * x2, -lam * y2)) + 1.0;
     double* r = &p->ew_tab[(size_t)k * EW_REC];
     r[0] = lam; r[1] = kap;
     if (kernel == PFMM_STOKES) {
-      cd Bp = -std::exp(cd(-lam * xi, lam * eta)) + std::exp(cd(lam * xi, -lam * eta));
-      double e = std::exp(-lam * d);
-      double P = (pp - (pp - 1) * e) / (-std::expm1(-lam * d));
-      r[2] = w * R / (4 * PI); r[3] = B.real(); r[4] = B.imag(); r[5] = Bp.real(); r[6] = Bp.imag();
-      r[7] = d * P;
+      cd Bp = p1 ? cd(0.0) : -std::exp(cd(-lam * x2, lam * y2)) + std::exp(cd(lam * x2, -lam * y2));
+      cd P = (double(pp) - double(pp - 1) * ea) / om;
+      cd pre = w * R / (4 * PI), dP = p->ew_dx * P;
+      r[2] = pre.real(); r[3] = pre.imag(); r[4] = B.real(); r[5] = B.imag();
+      r[6] = Bp.real(); r[7] = Bp.imag(); r[8] = dP.real(); r[9] = dP.imag();
     } else {
-      cd DW = w * R * B / (2 * PI * kap), DE = w * R * std::conj(B) / (2 * PI * kap);
+      cd DW = w * R * B / (2 * PI * kap), DE = std::conj(DW);
       r[2] = DW.real(); r[3] = DW.imag(); r[4] = DE.real(); r[5] = DE.imag();
     }
   }
@@ -333,6 +522,8 @@ int build_plan(int kernel, const double* e1, const double* e2, double tol, const
   // of at least twice the 2M+1 modes
   const bool nufft_fits = 2 * (2 * M + 1) <= 4096;
   int far = o.far_mode;
+  if (p1 && far == PFMM_FAR_NUFFT) return PFMM_EINVAL;   // no south/north part to accelerate
+  if (p1) far = PFMM_FAR_DIRECT;
   if (far == PFMM_FAR_AUTO) far = (2 * M + 1 >= 256 && nufft_fits) ? PFMM_FAR_NUFFT : PFMM_FAR_DIRECT;
   if (far == PFMM_FAR_NUFFT && !nufft_fits) return PFMM_EINVAL;
   p->far_mode = far;

@@ -6,6 +6,7 @@ import pytest
 
 import oracle
 import workloads as W
+from parity import check, golden
 
 pytestmark = pytest.mark.gpu
 
@@ -15,10 +16,6 @@ def env():
     import torch
     import paper_2111_01083_amd as P
     return P, torch, torch.device("cuda:0")
-
-
-def rel(a, b):
-    return np.linalg.norm((np.asarray(a) - np.asarray(b)).ravel()) / np.linalg.norm(np.asarray(b).ravel())
 
 
 def energy_grads(env, kernel, e1, e2, src, dens, prec, tol, beta=0.0):
@@ -88,7 +85,7 @@ def test_forces_match_oracle(env, kernel, prec, bar):
         ref_dx = dens * grad
         ref_dq = pot - pot.mean()
         dq = dq - dq.mean()
-    assert rel(dx, ref_dx) < bar and rel(dq, ref_dq) < bar
+    check(bar, (dx, ref_dx), (dq, ref_dq), label=f"forces {kernel} {prec}")
 
 
 def test_general_loss_vs_gpu_finite_differences(env):
@@ -133,18 +130,32 @@ def test_general_loss_vs_gpu_finite_differences(env):
 @pytest.mark.parametrize("kernel", ["laplace", "stokes"])
 def test_differentiation_workload_n50k(env, kernel):
     # cell e1 = (10, 0), e2 = (0, 1); N = 5e4 uniform sources, neutral N(0,1)
-    # densities; forward in mixed precision, adjoint backward; forces checked
-    # against the oracle's q_i grad phi(x_i) on sampled particles.
-    e1, e2 = (10.0, 0.0), (0.0, 1.0)
-    n = 50_000
-    rng = np.random.default_rng(0)
-    src = W.cell_points(rng, e1, e2, n)
-    dens = W.neutral_forces(rng, n) if kernel == "stokes" else W.neutral_charges(rng, n)
+    # densities; forward in mixed precision, adjoint backward. Against stored
+    # oracle values: forces dE/dx and dE/dq (on the neutral subspace) at 1024
+    # particles, and differences of the energy in x at 64 particles.
+    e1, e2, src, dens = W.energy_uniform(kernel)
+    ref = golden(f"energy_n50k_{kernel}", src, dens)
+    print(f"energy n50k {kernel}", flush=True)
     _, dx, dq = energy_grads(env, kernel, e1, e2, src, dens, "mixed", 1e-6)
-    idx = np.sort(np.random.default_rng(1).choice(n, 24, replace=False))
-    pot, grad = oracle.evaluate(kernel, e1, e2, src, dens, src[:, idx], tol=1e-10, self_idx=idx)
+    idx = ref["idx"]
+    pot, grad = ref["pot"], ref["grad"]
     if kernel == "stokes":
-        ref = np.stack([dens[0, idx] * grad[c] + dens[1, idx] * grad[2 + c] for c in range(2)])
+        ref_dx = np.stack([dens[0, idx] * grad[c] + dens[1, idx] * grad[2 + c] for c in range(2)])
     else:
-        ref = dens[idx] * grad
-    assert rel(dx[:, idx], ref) < 1e-6
+        ref_dx = dens[idx] * grad
+    # dE/dq = pot; compare differences between particles (the neutral
+    # directions e_j - e_k: a central difference of the quadratic energy along
+    # them is exactly pot_j - pot_k)
+    sel = np.arange(0, len(idx) - 1, 2)
+    dq_s = dq[..., idx]
+    check(1e-6, (dx[:, idx], ref_dx), (dq_s[..., sel] - dq_s[..., sel + 1], pot[..., sel] - pot[..., sel + 1]),
+          label=f"energy n50k {kernel}")
+    # fourth-order difference quotient of the energy in x_j from the stored
+    # potentials at x_j + t e_c, t = h, -h, 2h, -2h
+    fd_idx, fp, h = ref["fd_idx"], ref["fd_pot"], float(ref["fd_steps"][0])
+    fd = np.empty((2, len(fd_idx)))
+    for c in range(2):
+        up, um, u2p, u2m = fp[c]
+        dphi = (8 * (up - um) - (u2p - u2m)) / (12 * h)
+        fd[c] = (dens[:, fd_idx] * dphi).sum(axis=0) if kernel == "stokes" else dens[fd_idx] * dphi
+    check(1e-6, (dx[:, fd_idx], fd), label=f"energy n50k {kernel} differences")

@@ -8,6 +8,7 @@ import pytest
 
 import oracle
 import workloads as W
+from parity import check, golden, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -20,10 +21,6 @@ def env():
     import torch
     import paper_2111_01083_amd as P
     return P, torch, torch.device("cuda:0")
-
-
-def rel(a, b):
-    return np.linalg.norm((np.asarray(a) - np.asarray(b)).ravel()) / np.linalg.norm(np.asarray(b).ravel())
 
 
 def run(env, kernel, e1, e2, src, dens, prec, tol, beta, mode):
@@ -55,9 +52,10 @@ def test_mutual_matches_oracle_and_one_sided(env, n, cell, kernel, beta, prec, t
     agree = 1e-12 if prec == "fp64" else 1e-6
     if n == 1:
         # one charge and its images: the field at the charge vanishes by symmetry
-        assert rel(pm, po) < bar and np.abs(gm).max() < 1e-2 * bar * np.abs(pm).max()
+        check(bar, (pm, po), label=f"mutual {kernel} {cell} n=1 {prec}")
+        assert np.abs(gm).max() < 1e-2 * bar * np.abs(pm).max()
         return
-    assert rel(pm, po) < bar and rel(gm, go) < bar, (rel(pm, po), rel(gm, go))
+    check(bar, (pm, po), (gm, go), label=f"mutual {kernel} {cell} n={n} {prec}")
     assert rel(pm, p1) < agree and rel(gm, g1) < agree, (rel(pm, p1), rel(gm, g1))
 
 
@@ -65,18 +63,14 @@ def test_auto_uses_the_symmetric_path_and_full_size_is_accurate(env):
     # square cell, N = 2e5 uniform, Yukawa beta = 10, mixed, tol 1e-6: AUTO takes
     # the symmetric path; sampled outputs against the oracle
     P, torch, dev = env
-    n = 200_000
-    rng = np.random.default_rng(0)
-    e1, e2 = CELLS["square"]
-    src = W.cell_points(rng, e1, e2, n)
-    q = W.neutral_charges(rng, n)
+    e1, e2, src, q = W.square_uniform("yukawa")
     print("mutual full size", flush=True)
     pa, ga = run(env, "yukawa", e1, e2, src, q, "mixed", 1e-6, 10.0, "auto")
     pm, gm = run(env, "yukawa", e1, e2, src, q, "mixed", 1e-6, 10.0, "mutual")
     assert rel(pa, pm) < 1e-12 and rel(ga, gm) < 1e-12
-    idx = np.sort(np.random.default_rng(1).choice(n, 16, replace=False))
-    po, go = oracle.evaluate("yukawa", e1, e2, src, q, src[:, idx], beta=10.0, tol=1e-10, self_idx=idx)
-    assert rel(pa[idx], po) < 1e-6 and rel(ga[:, idx], go) < 1e-6
+    ref = golden("square_n200k_yukawa", src, q)
+    idx = ref["idx"]
+    check(1e-6, (pa[idx], ref["pot"]), (ga[:, idx], ref["grad"]), label="mutual full size")
 
 
 @pytest.mark.parametrize("kernel,beta", [("laplace", 0.0), ("yukawa", 10.0), ("stokes", 0.0)])
@@ -114,7 +108,7 @@ def test_thin_cells_share_logs_across_images(env, a_ratio, groups, kernel):
     pm, gm = run(env, kernel, e1, e2, src, dens, "mixed", 1e-6, 0.0, "mutual")
     p1, g1 = run(env, kernel, e1, e2, src, dens, "mixed", 1e-6, 0.0, "one_sided")
     po, go = oracle.evaluate(kernel, e1, e2, src, dens, None)
-    assert rel(pm, po) < 1e-6 and rel(gm, go) < 1e-6, (rel(pm, po), rel(gm, go))
+    check(1e-6, (pm, po), (gm, go), label=f"thin {kernel} A={a_ratio}")
     assert rel(pm, p1) < 1e-6 and rel(gm, g1) < 1e-6, (rel(pm, p1), rel(gm, g1))
 
 
@@ -140,7 +134,7 @@ def test_near_coincident_points(env, kernel):
     pm, gm = run(env, kernel, e1, e2, src, dens, "mixed", 1e-6, 0.0, "mutual")
     po, go = oracle.evaluate(kernel, e1, e2, src, dens, None)
     assert np.isfinite(pm).all() and np.isfinite(gm).all()
-    assert rel(pm, po) < 1e-6 and rel(gm, go) < 1e-6, (rel(pm, po), rel(gm, go))
+    check(1e-6, (pm, po), (gm, go), label=f"coincident {kernel}")
 
 
 @pytest.mark.parametrize("kernel,beta", [("laplace", 0.0), ("yukawa", 3.0), ("stokes", 0.0)])
@@ -162,5 +156,5 @@ def test_widest_near_region(env, kernel, beta, prec, tol, bar):
         pot, grad = plan(torch.tensor(src, device=dev), torch.tensor(dens, device=dev))
         outs.append((pot.cpu().numpy(), grad.cpu().numpy()))
     po, go = oracle.evaluate(kernel, e1, e2, src, dens, None, beta=beta)
-    for pm, gm in outs:
-        assert rel(pm, po) < bar and rel(gm, go) < bar, (rel(pm, po), rel(gm, go))
+    for mode, (pm, gm) in zip(("mutual", "one_sided"), outs):
+        check(bar, (pm, po), (gm, go), label=f"m0=3 {kernel} {prec} {mode}")

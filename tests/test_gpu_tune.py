@@ -7,6 +7,7 @@ import pytest
 
 import oracle
 import workloads as W
+from parity import check, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -16,10 +17,6 @@ def env():
     import torch
     import paper_2111_01083_amd as P
     return P, torch, torch.device("cuda:0")
-
-
-def rel(a, b):
-    return np.linalg.norm((np.asarray(a) - np.asarray(b)).ravel()) / np.linalg.norm(np.asarray(b).ravel())
 
 
 @pytest.mark.parametrize("kernel", ["laplace", "stokes"])
@@ -39,7 +36,7 @@ def test_nufft_doubled_grid_keeps_accuracy(env, kernel, prec, tol, bar):
     assert plan.info["nufft_nf"] == 2 * nf0
     print(f"case doubled grid {kernel} {prec}", flush=True)
     pot, grad = plan(torch.tensor(src, device=dev), torch.tensor(dens, device=dev), torch.tensor(trg, device=dev))
-    assert rel(pot.cpu().numpy(), po) < bar and rel(grad.cpu().numpy(), go) < bar
+    check(bar, (pot.cpu().numpy(), po), (grad.cpu().numpy(), go), label=f"doubled grid {kernel} {prec}")
 
 
 @pytest.mark.parametrize("cell,kernel,beta,far", [(((1.0, 0.0), (0.0, 1.0)), "yukawa", 10.0, "auto"),
@@ -63,7 +60,7 @@ def test_autotune_result_and_reuse(env, cell, kernel, beta, far):
     assert rel(p2.cpu().numpy(), pot) < 1e-12 and rel(g2.cpu().numpy(), grad) < 1e-12
     idx = np.sort(rng.choice(n, 12, replace=False))
     po, go = oracle.evaluate(kernel, e1, e2, src, q, src[:, idx], beta=beta, tol=1e-10, self_idx=idx)
-    assert rel(pot[idx], po) < 1e-6 and rel(grad[:, idx], go) < 1e-6
+    check(1e-6, (pot[idx], po), (grad[:, idx], go), label=f"autotune {kernel} {far}")
 
 
 def test_batch_autotune(env):
@@ -91,4 +88,4 @@ def test_batch_autotune(env):
         beta = 10.0 if cell["kernel"] == "yukawa" else 0.0
         po, go = oracle.evaluate(cell["kernel"], cell["e1"], cell["e2"], srcs[c], dens[c][nd - 1], None, beta=beta)
         sl = slice(offs[c], offs[c + 1])
-        assert rel(pot[nd - 1, sl], po) < 1e-6 and rel(grad[nd - 1, :, sl], go) < 1e-6, c
+        check(1e-6, (pot[nd - 1, sl], po), (grad[nd - 1, :, sl], go), label=f"batch autotune cell {c}")

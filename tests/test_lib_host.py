@@ -102,10 +102,50 @@ def test_canonical_lattice_of_rotated_unreduced_basis(P):
     assert inf["m0"] == 1 and inf["n_images"] == 9
 
 
-def test_hexagonal_cell_needs_wider_near_region(P):
+def test_hexagonal_cell_keeps_nine_images_with_rotated_west_east_waves(P):
+    # with the west/east waves along the x axis the hexagonal cell needs m0 = 2
+    # (Sec. 7 uses it for theta = pi/3); taken along e2-perp instead (Appendix
+    # A) the closest west/east image is a full column away and m0 = 1 holds
     plan = P.Plan("stokes", (1.0, 0.0), (0.5, np.sqrt(3) / 2), 1e-6)
     inf = plan.info
-    assert inf["m0"] == 2 and inf["n_images"] == 15        # Sec. 7: m0 = 2 for theta = pi/3
+    assert inf["m0"] == 1 and inf["n_images"] == 9 and inf["ew_rotated"] == 1
+    c, s = inf["ew_cos"], inf["ew_sin"]
+    assert abs(c * c + s * s - 1) < 1e-15
+    assert abs(c * inf["xi"] - s * inf["eta"]) < 1e-14        # e2 on the frame's y axis
+    assert s * inf["xi"] + c * inf["eta"] > 0
+    # an explicit m0 = 2 keeps the canonical frame (15 images)
+    inf2 = P.Plan("stokes", (1.0, 0.0), (0.5, np.sqrt(3) / 2), 1e-6, m0=2).info
+    assert inf2["m0"] == 2 and inf2["n_images"] == 15 and inf2["ew_rotated"] == 0
+    assert inf2["ew_cos"] == 1.0 and inf2["ew_sin"] == 0.0
+
+
+@pytest.mark.parametrize("cell", [((1.0, 0.0), (0.5, np.sqrt(3) / 2)), ((3.0, 0.0), (1.2, 1.0)),
+                                  ((40.0, 0.0), (17.0, 1.0))])
+@pytest.mark.parametrize("beta,tol", [(0.3, 1e-6), (3.0, 1e-10), (0.3, 1e-10)])
+def test_rotated_west_east_rule_sums_the_columns(P, cell, beta, tol):
+    # eq. k0west2: in the rotated frame the west columns p >= 2 of rows
+    # n = -1, 0, 1 sum to Re int_0^inf e^{-kappa X} e^{i lam Y} R B / kappa,
+    # R = sum_p e^{-p (kappa dx - i lam dy)}, B = sum_n e^{-i n lam eta'};
+    # against the direct sum of K0 over those images
+    plan = P.Plan("yukawa", *cell, tol, beta=beta)
+    inf = plan.info
+    assert inf["ew_rotated"] == 1 and inf["m0"] == 1
+    lam, w = plan.quadrature()
+    c, s = inf["ew_cos"], inf["ew_sin"]
+    dx, dy = c * inf["d"], s * inf["d"]
+    eta2 = s * inf["xi"] + c * inf["eta"]
+    kap = np.sqrt(lam ** 2 + beta ** 2)
+    a = kap * dx - 1j * lam * dy
+    R = np.exp(-2 * a) / (1 - np.exp(-a))
+    B = 1 + 2 * np.cos(lam * eta2)
+    pmax = int(np.ceil(60.0 / (beta * dx))) + 3
+    for X in np.linspace(-0.99 * dx, 0.99 * dx, 5):
+        for Y in np.linspace(-(abs(dy) + eta2), abs(dy) + eta2, 7):
+            approx = np.sum(w * (np.exp(-kap * X + 1j * lam * Y) * R * B).real / kap)
+            exact = sum(sp.k0(beta * np.hypot(X + p * dx, Y + p * dy - n * eta2))
+                        for p in range(2, pmax) for n in (-1, 0, 1))
+            scale = sp.k0(beta * dx)
+            assert abs(approx - exact) < 10 * inf["eps"] * scale + 1e-13, (X, Y, approx, exact)
 
 
 @pytest.mark.parametrize("d,eta,tol", [(1.0, 1.0, 1e-10), (100.0, 1.0, 1e-6), (20.0, 1.0, 1e-6), (10.0, 1.0, 1e-6)])
@@ -122,9 +162,10 @@ def test_mode_count_follows_truncation_formula(P, d, eta, tol):
 
 
 @pytest.mark.parametrize("cell", [((1.0, 0.0), (0.0, 1.0)), ((2.0, 0.0), (0.4, 1.0)),
-                                  ((1.0, 0.0), (0.5, np.sqrt(3) / 2)), ((100.0, 0.0), (0.0, 1.0))])
+                                  ((10.0, 0.0), (1.5, 1.0)), ((100.0, 0.0), (0.0, 1.0))])
 @pytest.mark.parametrize("tol", [1e-6, 1e-10])
 def test_west_east_rule_integrates_laplace_plane_waves(P, cell, tol):
+    # (canonical west/east frame; the rotated one is checked below)
     # int_0^inf e^{-lam X} e^{i lam Y} dlam = 1/(X - iY) over the X, Y range
     # the rule is used on (closest west/east image and beyond, |Y| <= 2 eta)
     plan = P.Plan("laplace", *cell, tol)
@@ -319,13 +360,14 @@ def test_device_bessel_tables_against_scipy(tag, bar):
         assert np.max(np.abs(hz(t["KF1_F32"], 1.0 / xf) / (sp.k1e(xf) * np.sqrt(xf)) - 1)) < bar
 
 
-@pytest.mark.parametrize("e1,e2,groups", [((1.0, 0.0), (0.0, 1.0), 1), ((1.0, 0.0), (0.5, 0.866), 3),
-                                          ((100.0, 0.0), (0.0, 1.0), 1), ((4000.0, 0.0), (0.0, 1.0), 3)])
-def test_log_groups_of_the_symmetric_mixed_near_field(P, e1, e2, groups):
+@pytest.mark.parametrize("e1,e2,m0,groups", [((1.0, 0.0), (0.0, 1.0), 0, 1), ((1.0, 0.0), (0.5, 0.866), 0, 1),
+                                             ((1.0, 0.0), (0.5, 0.866), 2, 3), ((100.0, 0.0), (0.0, 1.0), 0, 1),
+                                             ((4000.0, 0.0), (0.0, 1.0), 0, 3)])
+def test_log_groups_of_the_symmetric_mixed_near_field(P, e1, e2, m0, groups):
     # 9 images: one group unless the cell is so thin that the product could
-    # leave the FP32 range; 15 images (the hexagonal cell, m0 = 2) or such thin
-    # cells: one group per row of images (one period apart)
-    inf = P.Plan("laplace", e1, e2, 1e-6, precision="mixed", self_exclude=True).info
+    # leave the FP32 range; 15 images (the hexagonal cell with m0 = 2) or such
+    # thin cells: one group per row of images (one period apart)
+    inf = P.Plan("laplace", e1, e2, 1e-6, precision="mixed", self_exclude=True, m0=m0).info
     assert inf["n_log_groups"] == groups and inf["n_images"] % groups == 0
 
 
@@ -369,3 +411,25 @@ def test_log_group_products_stay_in_the_fp32_range(P, e1, e2, m0):
         g0 = end
     if max(abs(e1[0]), abs(e2[1])) <= 10:
         assert np.median(np.abs(np.concatenate(logs))) < 16
+
+
+@pytest.mark.parametrize("cell,tol,grid", [(((100.0, 0.0), (0.0, 1.0)), 1e-6, 0), (((100.0, 0.0), (0.0, 1.0)), 1e-6, 1),
+                                           (((100.0, 0.0), (0.0, 1.0)), 1e-10, 0), (((30.0, 0.0), (0.0, 1.0)), 1e-12, 0)])
+def test_spread_kernel_polynomials_match_the_kernel(P, cell, tol, grid):
+    # the device evaluates the w + 1 taps of the exponential-of-semicircle
+    # kernel (Sec. 6.1) as the planner's polynomials in the grid offset; they
+    # must reproduce exp(b (sqrt(1 - z^2) - 1)) on |z| < 1 (0 outside) to a
+    # fraction of eps at every offset
+    plan = P.Plan("laplace", *cell, tol, far_mode="nufft")
+    if grid:
+        plan.set_tuning(nufft_grid=1)
+    coef, deg, b = plan.spread_kernel()
+    w, eps = plan.info["nufft_w"], plan.info["eps"]
+    assert deg == min(20, w + 4) and np.all(coef[w + 1:] == 0) and np.all(coef[:, deg:] == 0)
+    f = np.linspace(0.0, 1.0, 4001, endpoint=False)
+    u = 2 * f - 1
+    for t in range(w + 1):
+        z = (t + f - w / 2) / (w / 2)
+        exact = np.where(np.abs(z) < 1, np.exp(b * (np.sqrt(np.clip(1 - z * z, 0, None)) - 1)), 0.0)
+        approx = np.polynomial.polynomial.polyval(u, coef[t, :deg])
+        assert np.abs(approx - exact).max() < 0.5 * eps, (t, np.abs(approx - exact).max())

@@ -56,6 +56,59 @@ def _canonical(info, pts):
     return B @ u, R
 
 
+# the last four have |xi| > d/4 after reduction: their west/east waves run
+# along e2-perp (Appendix A) with m0 = 1
+SCHEME_CELLS = [((1.0, 0.0), (0.0, 1.0)), ((2.0, 0.0), (0.4, 1.0)), ((1.1, 0.35), (-0.2, 0.9)),
+                ((10.0, 0.0), (1.5, 1.0)), ((1.0, 0.0), (0.5, np.sqrt(3) / 2)), ((1.0, 0.0), (0.4, 1.0)),
+                ((3.0, 0.0), (1.2, 1.0)), ((40.0, 0.0), (17.0, 1.0))]
+
+
+def _ew_frame(info, s, t):
+    """West/east frame of the plan (Appendix A; the identity unless the waves
+    run along e2-perp): pair differences X, Y in it, e1 = (dx, dy) and
+    e2 = (xi2, eta2) there, and the rotation (c, sn) from the canonical frame."""
+    c, sn = info["ew_cos"], info["ew_sin"]
+    Rb = np.array([[c, -sn], [sn, c]])
+    sb, tb = Rb @ s, Rb @ t
+    e1 = Rb @ np.array([info["d"], 0.0])
+    e2 = Rb @ np.array([info["xi"], info["eta"]])
+    X = tb[0][:, None] - sb[0][None, :]
+    Y = tb[1][:, None] - sb[1][None, :]
+    return X, Y, e1[0], e1[1], e2[0], e2[1], Rb
+
+
+def _columns(kap, lam, dx, dy, p):
+    """sum_{q >= p} e^{-q a} and sum_{q >= p} q e^{-q a}, a = kappa dx - i lambda dy
+    (the west columns; the east ones are the conjugates)."""
+    a = kap * dx - 1j * lam * dy
+    ea = np.exp(-a)
+    T0 = np.exp(-p * a) / (1 - ea)
+    T1 = np.exp(-p * a) * (p - (p - 1) * ea) / (1 - ea) ** 2
+    return T0, T1
+
+
+def _scalar_ew(info, lam, wq, kap, s, t, q, laplace):
+    """West + east columns (|m| >= m0 + 1 of rows -1, 0, 1) of a scalar kernel
+    in the plan's west/east frame; returns pot and the canonical gradient.
+    Laplace drops each image's pair-independent constant (neutral charges)."""
+    X, Y, dx, dy, xi2, eta2, Rb = _ew_frame(info, s, t)
+    T0, _ = _columns(kap, lam, dx, dy, info["m0"] + 1)
+    base = wq / kap / (2 * np.pi)
+    pot = np.zeros(t.shape[1]); gx = np.zeros_like(pot); gy = np.zeros_like(pot)
+    for n in ((0,) if info["periodic"] == 1 else (-1, 0, 1)):
+        Xn = (X - n * xi2)[..., None]; Yn = (Y - n * eta2)[..., None]
+        ph = np.exp(1j * lam * Yn)
+        west = np.exp(-kap * Xn) * T0
+        east = np.exp(kap * Xn) * np.conj(T0)
+        tot = ph * (west + east)
+        if laplace:
+            tot = tot - 2 * T0.real
+        pot += ((tot.real * base).sum(-1)) @ q
+        gx += (((ph * kap * (east - west)).real * base).sum(-1)) @ q
+        gy += (((1j * lam * ph * (west + east)).real * base).sum(-1)) @ q
+    return pot, Rb.T @ np.vstack([gx, gy])
+
+
 def yukawa_scheme(info, lam, wq, beta, src, q, trg):
     d, xi, eta, m0, M = info["d"], info["xi"], info["eta"], info["m0"], info["n_modes"]
     s, R = _canonical(info, src)
@@ -90,18 +143,9 @@ def yukawa_scheme(info, lam, wq, beta, src, q, trg):
     gy += ((-eS + eN) * chi[None, :]).sum(1).real
     # west / east: columns m >= m0 + 1 (east) and m <= -(m0 + 1) (west) of rows -1, 0, 1
     kap = np.sqrt(lam * lam + beta * beta)
-    geo = np.exp(-kap * (m0 + 1) * d) / (1 - np.exp(-kap * d))      # sum over |m| >= m0 + 1
-    for n in (-1, 0, 1):
-        Yn = (Y - n * eta)[..., None]
-        cosl, sinl = np.cos(lam * Yn), np.sin(lam * Yn)
-        east = np.exp(kap * (X[..., None] - n * xi))     # e^{-kappa |x - x_j - m d - n xi|}, m > 0, / e^{-kappa m d}
-        west = np.exp(-kap * (X[..., None] - n * xi))
-        base = wq * geo / kap / (2 * np.pi)
-        pot += (((east + west) * cosl * base).sum(-1)) @ q
-        gx += (((east - west) * kap * cosl * base).sum(-1)) @ q
-        gy += ((-(east + west) * lam * sinl * base).sum(-1)) @ q
-    grad = R.T @ np.vstack([gx, gy])
-    return pot, grad
+    pe, ge = _scalar_ew(info, lam, wq, kap, s, t, q, laplace=False)
+    grad = R.T @ (np.vstack([gx, gy]) + ge)
+    return pot + pe, grad
 
 
 def laplace_scheme(info, lam, wq, src, q, trg):
@@ -139,16 +183,51 @@ def laplace_scheme(info, lam, wq, src, q, trg):
     pot += -t[1] * Py / (d * eta) + (q * s[1] ** 2).sum() / (2 * d * eta)
     gy += -Py / (d * eta)
     # west + east together (regular at lam = 0 after removing the constant of each image)
-    geo = np.exp(-lam * (m0 + 1) * d) / (1 - np.exp(-lam * d))
-    base = wq * geo / lam / (2 * np.pi)
-    for n in (-1, 0, 1):
-        Xn = (X - n * xi)[..., None]; Yn = (Y - n * eta)[..., None]
-        ch, sh = np.cosh(lam * Xn), np.sinh(lam * Xn)
-        c, sn = np.cos(lam * Yn), np.sin(lam * Yn)
-        pot += ((2 * (ch * c - 1) * base).sum(-1)) @ q
-        gx += ((2 * lam * sh * c * base).sum(-1)) @ q
-        gy += ((-2 * lam * ch * sn * base).sum(-1)) @ q
-    return pot, R.T @ np.vstack([gx, gy])
+    pe, ge = _scalar_ew(info, lam, wq, lam, s, t, q, laplace=True)
+    return pot + pe, R.T @ (np.vstack([gx, gy]) + ge)
+
+
+def _stokes_ew(info, lam, wq, s, t, f1, f2):
+    """West + east columns of the Stokeslet in the plan's west/east frame
+    (canonical force components f1, f2; canonical velocity and gradient out)."""
+    nt = t.shape[1]
+    m0 = info["m0"]
+    u = np.zeros((2, nt))
+    g = np.zeros((2, 2, nt))
+    Xb, Yb, dxb, dyb, xi2, eta2, Rb = _ew_frame(info, s, t)
+    fb1, fb2 = Rb @ np.vstack([f1, f2])
+    ub = np.zeros((2, nt))
+    gb = np.zeros((2, 2, nt))
+
+    def applyb(txx, txy, tyy):
+        return np.array([txx @ fb1 + txy @ fb2, txy @ fb1 + tyy @ fb2])
+
+    T0, T1 = _columns(lam, lam, dxb, dyb, m0 + 1)
+    w = wq / np.pi
+    xx_ref = (2 * T0.real + 2 * lam * dxb * T1.real) / (4 * lam)
+    yy_ref = (2 * T0.real - 2 * lam * dxb * T1.real) / (4 * lam)
+    for n in ((0,) if info["periodic"] == 1 else (-1, 0, 1)):
+        X0 = (Xb - n * xi2)[..., None]
+        Yn = (Yb - n * eta2)[..., None]
+        ph = np.exp(1j * lam * Yn)
+        AE, AW = np.exp(lam * X0) * np.conj(T0), np.exp(-lam * X0) * T0
+        BE = np.exp(lam * X0) * (dxb * np.conj(T1) - X0 * np.conj(T0))
+        BW = np.exp(-lam * X0) * (X0 * T0 + dxb * T1)
+        A, B = AE + AW, BE + BW
+        ub += applyb((((ph * (A + lam * B)).real / (4 * lam) - xx_ref) * w).sum(-1),
+                     ((0.25 * (ph * (BW - BE)).imag) * w).sum(-1),
+                     (((ph * (A - lam * B)).real / (4 * lam) - yy_ref) * w).sum(-1))
+        dA = lam * (AE - AW)
+        dB = lam * (BE - BW) - AE + AW
+        gb[:, 0] += applyb(((ph * (dA + lam * dB)).real / (4 * lam) * w).sum(-1),
+                           (0.25 * (ph * (AW + AE - lam * (BW + BE))).imag * w).sum(-1),
+                           ((ph * (dA - lam * dB)).real / (4 * lam) * w).sum(-1))
+        gb[:, 1] += applyb((-(ph * (A + lam * B)).imag / 4 * w).sum(-1),
+                           (0.25 * (ph * (BW - BE)).real * lam * w).sum(-1),
+                           (-(ph * (A - lam * B)).imag / 4 * w).sum(-1))
+    u += Rb.T @ ub
+    g += np.einsum("ji,jkt,kl->ilt", Rb, gb, Rb)
+    return u, g
 
 
 def stokes_scheme(info, lam, wq, src, f, trg):
@@ -208,38 +287,19 @@ def stokes_scheme(info, lam, wq, src, f, trg):
     #   G_xx = (1/pi) int cos(lam Y) (1 + lam|X|) e^{-lam|X|} / (4 lam),
     #   G_yy = (1/pi) int cos(lam Y) (1 - lam|X|) e^{-lam|X|} / (4 lam),
     #   G_xy = (1/pi) int sin(lam Y) X e^{-lam|X|} / 4,
-    # summed over the columns (A = sum e^{-lam|X|}, B = sum |X| e^{-lam|X|});
-    # the part of G_xx, G_yy that does not depend on the pair is removed (zero net force)
-    p = m0 + 1
-    ed = np.exp(-lam * d)
-    T0 = np.exp(-lam * p * d) / (1 - ed)
-    T1 = np.exp(-lam * p * d) * (p - (p - 1) * ed) / (1 - ed) ** 2
-    w = wq / np.pi
-    xx_ref = (2 * T0 + 2 * lam * d * T1) / (4 * lam)
-    yy_ref = (2 * T0 - 2 * lam * d * T1) / (4 * lam)
-    for n in (-1, 0, 1):
-        X0 = (X - n * xi)[..., None]
-        Yn = (Y - n * eta)[..., None]
-        AE, AW = np.exp(lam * X0) * T0, np.exp(-lam * X0) * T0
-        BE, BW = np.exp(lam * X0) * (d * T1 - X0 * T0), np.exp(-lam * X0) * (X0 * T0 + d * T1)
-        A, B = AE + AW, BE + BW
-        cs, sn = np.cos(lam * Yn), np.sin(lam * Yn)
-        u += apply(((cs * (A + lam * B) / (4 * lam) - xx_ref) * w).sum(-1), ((0.25 * (BW - BE) * sn) * w).sum(-1),
-                   ((cs * (A - lam * B) / (4 * lam) - yy_ref) * w).sum(-1))
-        dA = lam * (AE - AW)
-        dB = lam * (BE - BW) - AE + AW
-        g[:, 0] += apply((cs * (dA + lam * dB) / (4 * lam) * w).sum(-1),
-                         (0.25 * (AW + AE - lam * (BW + BE)) * sn * w).sum(-1),
-                         (cs * (dA - lam * dB) / (4 * lam) * w).sum(-1))
-        g[:, 1] += apply((-sn * (A + lam * B) / 4 * w).sum(-1), (0.25 * (BW - BE) * lam * cs * w).sum(-1),
-                         (-sn * (A - lam * B) / 4 * w).sum(-1))
+    # in the plan's west/east frame (forces rotated into it, results rotated
+    # back), summed over the columns (A = sum e^{-lam|X|}, B = sum |X| e^{-lam|X|},
+    # complex geometric sums when e1 is not along the frame's x axis; cos and
+    # sin become real and imaginary parts of e^{i lam Y}); the part of G_xx,
+    # G_yy that does not depend on the pair is removed (zero net force)
+    ue, ge = _stokes_ew(info, lam, wq, s, t, f1, f2)
+    u += ue
+    g += ge
     # back to the caller's frame: u -> R^T u, grad u -> R^T (grad u) R
     return R.T @ u, np.einsum("ji,jkt,kl->ilt", R, g, R).reshape(4, nt)
 
 
-@pytest.mark.parametrize("cell", [((1.0, 0.0), (0.0, 1.0)), ((2.0, 0.0), (0.4, 1.0)),
-                                  ((1.1, 0.35), (-0.2, 0.9)), ((1.0, 0.0), (0.5, np.sqrt(3) / 2)),
-                                  ((10.0, 0.0), (1.5, 1.0))])
+@pytest.mark.parametrize("cell", SCHEME_CELLS)
 @pytest.mark.parametrize("beta", [0.5, 3.0, 10.0])
 def test_yukawa_scheme_from_plan_matches_oracle(P, cell, beta):
     # beta = 10 on the square cell: the planner drops the west/east part and
@@ -261,9 +321,7 @@ def test_yukawa_scheme_from_plan_matches_oracle(P, cell, beta):
         assert ep < tol and eg < tol, (tol, ep, eg, info["m0"], info["n_modes"], len(lam))
 
 
-@pytest.mark.parametrize("cell", [((1.0, 0.0), (0.0, 1.0)), ((2.0, 0.0), (0.4, 1.0)),
-                                  ((1.1, 0.35), (-0.2, 0.9)), ((1.0, 0.0), (0.5, np.sqrt(3) / 2)),
-                                  ((10.0, 0.0), (1.5, 1.0))])
+@pytest.mark.parametrize("cell", SCHEME_CELLS)
 def test_laplace_scheme_from_plan_matches_oracle(P, cell):
     e1, e2 = cell
     rng = np.random.default_rng(31)
@@ -281,9 +339,7 @@ def test_laplace_scheme_from_plan_matches_oracle(P, cell):
         assert ep < tol and eg < tol, (tol, ep, eg, info["m0"], info["n_modes"], len(lam))
 
 
-@pytest.mark.parametrize("cell", [((1.0, 0.0), (0.0, 1.0)), ((2.0, 0.0), (0.4, 1.0)),
-                                  ((1.1, 0.35), (-0.2, 0.9)), ((1.0, 0.0), (0.5, np.sqrt(3) / 2)),
-                                  ((10.0, 0.0), (1.5, 1.0))])
+@pytest.mark.parametrize("cell", SCHEME_CELLS)
 def test_stokes_scheme_from_plan_matches_oracle(P, cell):
     e1, e2 = cell
     rng = np.random.default_rng(31)
@@ -480,3 +536,56 @@ def test_wider_near_region_m0_3(P, kernel):
     eu = np.linalg.norm(u - ref) / np.linalg.norm(ref)
     eg = np.linalg.norm(g - gref) / np.linalg.norm(gref)
     assert eu < tol and eg < tol, (eu, eg)
+
+
+# --- singly periodic plans (P1, Sec. 3 eq. ksplitting1) ----------------------
+# Near part: the cell and its two neighbours along e1 (direct sums); far
+# part: the west/east columns |m| >= 2 of the single row, from the planner's
+# nodes and weights (Thm. west_thm with B = 1 and its Laplace/Stokes forms).
+
+def p1_scheme(info, lam, wq, kernel, beta, src, dens, trg):
+    c, s_ = info["rot_cos"], info["rot_sin"]
+    R = np.array([[c, -s_], [s_, c]])
+    d = info["d"]
+
+    def canon(p):
+        q = R @ p
+        q[0] -= d * np.round(q[0] / d)
+        return q
+    sc, tc = canon(src), canon(trg)
+    dc = R @ dens if kernel == "stokes" else dens
+    s_img = np.concatenate([sc + np.array([[m * d], [0.0]]) for m in (-1, 0, 1)], axis=1)
+    d_img = np.concatenate([dc] * 3, axis=-1)
+    pot, grad = oracle.free_space(kernel, s_img, d_img, tc, beta=beta)
+    if kernel == "stokes":
+        ue, ge = _stokes_ew(info, lam, wq, sc, tc, dc[0], dc[1])
+        u = pot + ue
+        J = grad.reshape(2, 2, -1) + ge
+        return R.T @ u, np.einsum("ji,jkt,kl->ilt", R, J, R).reshape(4, -1)
+    kap = np.sqrt(lam * lam + beta * beta) if kernel == "yukawa" else lam
+    pe, ge = _scalar_ew(info, lam, wq, kap, sc, tc, dc, laplace=kernel == "laplace")
+    return pot + pe, R.T @ (grad + ge)
+
+
+@pytest.mark.parametrize("e1,e2", [((1.0, 0.0), (0.0, 1.0)), ((1.3, 0.4), (0.2, 2.0)), ((1.0, 0.0), (0.0, 8.0)),
+                                   ((6.0, 0.0), (0.0, 1.0))])
+@pytest.mark.parametrize("kernel,beta", [("laplace", 0.0), ("yukawa", 0.5), ("yukawa", 4.0), ("stokes", 0.0)])
+def test_p1_scheme_from_plan_matches_oracle(P, e1, e2, kernel, beta):
+    rng = np.random.default_rng(37)
+    n, nt = 40, 25
+    # points in the strip: anywhere along e1, within half the height across it
+    e1a = np.array(e1); dd = np.hypot(*e1a); along = e1a / dd; perp = np.array([-along[1], along[0]])
+    H = abs(np.dot(np.array(e2), perp))
+    src = np.outer(along, dd * (rng.random(n) - 0.5) + 3 * dd) + np.outer(perp, H * (rng.random(n) - 0.5))
+    trg = np.outer(along, dd * (rng.random(nt) - 0.5)) + np.outer(perp, H * (rng.random(nt) - 0.5))
+    dens = W.neutral_forces(rng, n) if kernel == "stokes" else W.neutral_charges(rng, n)
+    po, go = oracle.singly_periodic(kernel, e1, src, dens, trg, beta=beta)
+    for tol in (1e-6, 1e-10):
+        plan = P.Plan(kernel, e1, e2, tol, beta=beta, periodic=1)
+        info = plan.info
+        assert info["periodic"] == 1 and info["n_images"] == 3 and info["n_modes"] == 0
+        lam, wq = plan.quadrature()
+        pot, grad = p1_scheme(info, lam, wq, kernel, beta, src, dens, trg)
+        ep = np.linalg.norm(pot - po) / np.linalg.norm(po)
+        eg = np.linalg.norm(grad - go) / np.linalg.norm(go)
+        assert ep < tol and eg < tol, (tol, ep, eg, len(lam))

@@ -394,3 +394,182 @@ def test_reciprocity_at_the_sources(kernel, beta):
     ug, _ = oracle.evaluate(kernel, *GENERAL, src, g, None, beta=beta)
     a, b = np.sum(g * uq), np.sum(q * ug)
     assert abs(a - b) < 1e-12 * (abs(a) + abs(b)), (a, b)
+
+
+# --- singly periodic sums (P1, periodic in e1 only) --------------------------
+
+P1_E1 = (1.3, 0.4)          # period vector, not along x
+
+
+def _p1_points(n, nt, seed, stokes=False, height=2.0):
+    rng = np.random.default_rng(seed)
+    e1 = np.array(P1_E1)
+    d = np.hypot(*e1)
+    perp = np.array([-e1[1], e1[0]]) / d
+    u = rng.random(n) - 0.5; v = (rng.random(n) - 0.5) * height
+    src = np.outer(e1, u) + np.outer(perp, v)
+    ut = rng.random(nt) - 0.5; vt = (rng.random(nt) - 0.5) * height
+    trg = np.outer(e1, ut) + np.outer(perp, vt)
+    dens = W.neutral_forces(rng, n) if stokes else W.neutral_charges(rng, n)
+    return src, dens, trg
+
+
+def _p1_brute(kernel, src, dens, trg, beta=0.0, M0=64, levels=5):
+    """Symmetric partial sums over |m| <= M of the free-space kernel over the
+    images s_j + m e1, for M = M0 2^k, extrapolated to M -> infinity by fitting
+    a polynomial in 1/M through all levels (the neutral sums' tails have an
+    expansion in powers of 1/M); Yukawa needs no extrapolation."""
+    e1 = np.array(P1_E1)
+    vals = []
+    Ms = [M0 * 2 ** k for k in range(levels)]
+    for M in Ms:
+        m = np.arange(-M, M + 1)
+        s_img = (src[:, None, :] + np.outer(e1, m)[:, :, None]).reshape(2, -1)
+        d_img = np.repeat(dens[..., None, :], len(m), axis=-2).reshape(dens.shape[:-1] + (-1,))
+        p, g = oracle.free_space(kernel, s_img, d_img, trg, beta=beta)
+        vals.append(np.concatenate([np.ravel(p), np.ravel(g)]))
+        if kernel == "yukawa":
+            return vals[-1]
+    h = 1.0 / np.array(Ms, float)
+    V = np.vander(h, levels, increasing=True)
+    coef = np.linalg.solve(V, np.array(vals))
+    return coef[0]
+
+
+@pytest.mark.parametrize("kernel", ["laplace", "stokes"])
+def test_p1_closed_forms_equal_extrapolated_direct_sums(kernel):
+    # the sine-product (Laplace) and complex cotangent (Stokes) forms of the
+    # symmetric image sums against brute force over up to 2 x 1024 images
+    src, dens, trg = _p1_points(7, 5, seed=41, stokes=kernel == "stokes")
+    p, g = oracle.singly_periodic(kernel, P1_E1, src, dens, trg)
+    ref = _p1_brute(kernel, src, dens, trg)
+    got = np.concatenate([np.ravel(p), np.ravel(g)])
+    assert np.abs(got - ref).max() < 1e-9 * np.abs(ref).max(), np.abs(got - ref).max()
+
+
+def test_p1_yukawa_equals_direct_sum_and_row_spectral_sum():
+    beta = 1.7
+    src, q, trg = _p1_points(8, 6, seed=42)
+    p, g = oracle.singly_periodic("yukawa", P1_E1, src, q, trg, beta=beta)
+    ref = _p1_brute("yukawa", src, q, trg, beta=beta, M0=80, levels=1)
+    got = np.concatenate([p, np.ravel(g)])
+    assert np.abs(got - ref).max() < 1e-13 * np.abs(ref).max()
+    # one row of the Poisson-summation form (no Bessel function), in the frame
+    # where the period lies along x
+    e1 = np.array(P1_E1); d = np.hypot(*e1)
+    R = np.array([[e1[0], e1[1]], [-e1[1], e1[0]]]) / d
+    ps, gs = _yukawa_row_spectral(d, (0.0, 1e6), beta, R @ src, q, R @ trg, nrow=0, nk=600)
+    assert rel(p, ps) < 1e-12 and rel(g, R.T @ gs) < 1e-12
+
+
+def test_p1_stokes_trace_is_laplace_and_divergence_free():
+    src, q, trg = _p1_points(9, 7, seed=43)
+    lp, lg = oracle.singly_periodic("laplace", P1_E1, src, q, trg)
+    ua, ga = oracle.singly_periodic("stokes", P1_E1, src, np.stack([q, 0 * q]), trg)
+    ub, gb = oracle.singly_periodic("stokes", P1_E1, src, np.stack([0 * q, q]), trg)
+    # trace of the Stokeslet = Laplace kernel + 1/(4 pi); the constant drops for neutral q
+    assert rel(ua[0] + ub[1], lp) < 1e-13
+    assert rel(ga[0:2] + gb[2:4], lg) < 1e-13
+    src, f, trg = _p1_points(9, 7, seed=44, stokes=True)
+    u, g = oracle.singly_periodic("stokes", P1_E1, src, f, trg)
+    assert np.abs(g[0] + g[3]).max() < 1e-12 * np.abs(g).max()
+
+
+@pytest.mark.parametrize("kernel,beta", [("laplace", 0.0), ("yukawa", 2.0), ("stokes", 0.0)])
+def test_p1_periodic_along_e1_and_gradient_is_derivative(kernel, beta):
+    src, dens, trg = _p1_points(8, 5, seed=45, stokes=kernel == "stokes")
+    e1 = np.array(P1_E1)[:, None]
+    p0, g0 = oracle.singly_periodic(kernel, P1_E1, src, dens, trg, beta=beta)
+    p1, g1 = oracle.singly_periodic(kernel, P1_E1, src, dens, trg + 3 * e1, beta=beta)
+    assert rel(p1, p0) < 1e-12 and rel(g1, g0) < 1e-12
+    h = 1e-6
+    for c in range(2):
+        dv = np.zeros((2, 1)); dv[c] = h
+        pp, _ = oracle.singly_periodic(kernel, P1_E1, src, dens, trg + dv, beta=beta)
+        pm, _ = oracle.singly_periodic(kernel, P1_E1, src, dens, trg - dv, beta=beta)
+        fd = (pp - pm) / (2 * h)
+        an = g0[c::2] if kernel == "stokes" else g0[c]
+        assert rel(an, fd) < 1e-7, (c, rel(an, fd))
+
+
+@pytest.mark.parametrize("kernel", ["laplace", "stokes"])
+def test_p1_self_term_is_the_limit_at_the_source(kernel):
+    # value at a source with its own m = 0 term left out = lim_{h->0} of the
+    # full sum at x_i + h minus the free-space kernel at h
+    src, dens, _ = _p1_points(7, 1, seed=46, stokes=kernel == "stokes")
+    i = 3
+    u_self, _ = oracle.singly_periodic(kernel, P1_E1, src, dens, None)
+    for h in (1e-4, 1e-5):
+        acc = 0
+        for dv in ((h, 0.0), (-h, 0.0), (0.0, h), (0.0, -h)):
+            t = src[:, [i]] + np.array(dv)[:, None]
+            u, _ = oracle.singly_periodic(kernel, P1_E1, src, dens, t)
+            r2 = dv[0] ** 2 + dv[1] ** 2
+            if kernel == "stokes":
+                G = (-0.5 * np.log(r2) * np.eye(2) + np.outer(dv, dv) / r2) / (4 * np.pi)
+                acc = acc + (u[:, 0] - G @ dens[:, i])
+            else:
+                acc = acc + (u[0] + 0.25 * np.log(r2) / np.pi * dens[i])
+        acc = acc / 4
+        ref = u_self[:, i] if kernel == "stokes" else u_self[i]
+        assert np.abs(acc - ref).max() < 1e-8 * np.abs(u_self).max() + 50 * h * h, (h, acc, ref)
+
+
+def test_p1_yukawa_tends_to_laplace():
+    # neutral charges: the row sum of K0(beta r)/(2 pi) differs from the
+    # Laplace one by O(beta) (its zero mode is (1/(2 beta d)) e^{-beta |y|})
+    src, q, trg = _p1_points(8, 6, seed=47)
+    lp, lg = oracle.singly_periodic("laplace", P1_E1, src, q, trg)
+    errs = []
+    for beta in (1e-2, 5e-3):
+        yp, yg = oracle.singly_periodic("yukawa", P1_E1, src, q, trg, beta=beta, tol=1e-15)
+        errs.append(rel(yp, lp))
+    assert errs[0] < 0.05 and 1.6 < errs[0] / errs[1] < 2.4, errs
+
+
+# --- Stokes pressure ----------------------------------------------------------
+
+@pytest.mark.parametrize("periodic", [2, 1])
+def test_stokes_pressure_satisfies_the_momentum_equation(periodic):
+    # away from the forces the Stokes equations (mu = 1) give grad p = lap u;
+    # the velocity comes from the Stokes oracle (Ewald, or the singly periodic
+    # closed form), the pressure from the Laplace one: central differences
+    # of the analytic velocity gradient against differences of the pressure
+    rng = np.random.default_rng(61)
+    if periodic == 2:
+        e1, e2 = SHEARED
+        src, f, trg = _setup(e1, e2, ns=10, nt=6, seed=62, stokes=True)
+        vel = lambda t: oracle.stokes(e1, e2, src, f, t)
+    else:
+        e1, e2 = P1_E1, None
+        src, f, trg = _p1_points(10, 6, seed=62, stokes=True)
+        vel = lambda t: oracle.singly_periodic("stokes", e1, src, f, t)
+    pres = lambda t: oracle.stokes_pressure(e1, e2, src, f, t, periodic=periodic)
+    h = 2e-4
+
+    def d4(fun, k):
+        # fourth-order central difference along x_k
+        dv = np.zeros((2, 1)); dv[k] = h
+        return (8 * (fun(trg + dv) - fun(trg - dv)) - (fun(trg + 2 * dv) - fun(trg - 2 * dv))) / (12 * h)
+    lap_u = np.zeros((2, trg.shape[1])); grad_p = np.zeros((2, trg.shape[1]))
+    for k in range(2):
+        dj = d4(lambda t: vel(t)[1], k)
+        # d/dx_k of du_i/dx_k (gradient rows: du1/dx, du1/dy, du2/dx, du2/dy)
+        lap_u[0] += dj[k]
+        lap_u[1] += dj[2 + k]
+        grad_p[k] = d4(pres, k)
+    assert rel(grad_p, lap_u) < 1e-7, rel(grad_p, lap_u)
+
+
+def test_stokes_pressure_of_a_tight_pair_is_free_space():
+    # a force dipole much smaller than the cell: the periodic pressure near it
+    # is the free-space pressurelet sum (1/2pi) r.f/r^2 up to the images' smooth part
+    e1, e2 = SHEARED
+    c = np.array([[0.1], [0.05]])
+    src = c + 1e-3 * np.array([[1.0, -1.0], [0.5, -0.5]])
+    f = np.array([[1.0, -1.0], [-0.3, 0.3]])
+    trg = c + np.array([[0.02, -0.015, 0.0], [0.01, 0.02, -0.025]])
+    p = oracle.stokes_pressure(e1, e2, src, f, trg)
+    r = trg[:, :, None] - src[:, None, :]
+    ref = (np.einsum("ktj,kj->tj", r, f) / (r[0] ** 2 + r[1] ** 2)).sum(1) / (2 * np.pi)
+    assert rel(p, ref) < 1e-3

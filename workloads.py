@@ -69,3 +69,63 @@ def batched_cells(seed=0, ncells=64, nmin=1000, nmax=50000, amax=50.0, smax=0.5)
         out.append(dict(e1=(A, 0.0), e2=(s * A, 1.0), n=n,
                         kernel="laplace" if c % 2 == 0 else "yukawa", rng=rng))
     return out
+
+
+# --- full-size workloads, as the tests and the stored oracle samples draw them ---
+
+SQUARE = ((1.0, 0.0), (0.0, 1.0))
+HIGH_ASPECT = {"a100": ((100.0, 0.0), (0.0, 1.0)), "sheared20": ((20.0, 0.0), (3.0, 1.0))}
+ENERGY_CELL = ((10.0, 0.0), (0.0, 1.0))
+
+
+def densities(rng, kernel, n, ndens=1):
+    """Neutral N(0,1) densities for a kernel: forces (2, n) for Stokes, charges (n,) otherwise."""
+    return neutral_forces(rng, n, ndens) if kernel == "stokes" else neutral_charges(rng, n, ndens)
+
+
+def square_uniform(kernel, n=200_000, seed=0):
+    """Square cell, n uniform sources, neutral densities: (e1, e2, src, dens)."""
+    rng = np.random.default_rng(seed)
+    src = cell_points(rng, *SQUARE, n)
+    return SQUARE[0], SQUARE[1], src, densities(rng, kernel, n)
+
+
+def high_aspect_blobs(cell, kernel, n=200_000, seed=0):
+    """Cell (100,0),(0,1) or (20,0),(3,1), n sources in 50 Gaussian blobs: (e1, e2, src, dens)."""
+    e1, e2 = HIGH_ASPECT[cell]
+    rng = np.random.default_rng(seed)
+    src = blob_points(rng, e1, e2, n)
+    return e1, e2, src, densities(rng, kernel, n)
+
+
+def energy_uniform(kernel, n=50_000, seed=0):
+    """Cell (10,0),(0,1), n uniform sources, neutral densities: (e1, e2, src, dens)."""
+    rng = np.random.default_rng(seed)
+    src = cell_points(rng, *ENERGY_CELL, n)
+    return ENERGY_CELL[0], ENERGY_CELL[1], src, densities(rng, kernel, n)
+
+
+def batched_inputs(nd=16, seed=0):
+    """The 64-cell workload with nd neutral charge vectors per cell: a list of
+    dicts (e1, e2, n, kernel, beta, src (2, n), dens (nd, n))."""
+    out = []
+    for c in batched_cells(seed=seed):
+        src = cell_points(c["rng"], c["e1"], c["e2"], c["n"])
+        dens = neutral_charges(c["rng"], c["n"], nd).reshape(nd, c["n"])
+        out.append(dict(e1=c["e1"], e2=c["e2"], n=c["n"], kernel=c["kernel"],
+                        beta=10.0 if c["kernel"] == "yukawa" else 0.0, src=src, dens=dens))
+    return out
+
+
+def sample_indices(n, k, seed=1):
+    """k distinct indices out of n, sorted (the sampled targets of a full-size check)."""
+    return np.sort(np.random.default_rng(seed).choice(n, k, replace=False))
+
+
+def checksum(*arrays):
+    """sha256 (hex, 16 digits) of the float64 bytes of the arrays, in order."""
+    import hashlib
+    h = hashlib.sha256()
+    for a in arrays:
+        h.update(np.ascontiguousarray(a, dtype=np.float64).tobytes())
+    return h.hexdigest()[:16]
