@@ -122,6 +122,11 @@ typedef struct {
                       /* Stokes sums are the symmetric limits over |m| <= M    */
                       /* (neutral densities); no additive constant is removed. */
                       /* Batches reject P1 plans; the NUFFT does not apply     */
+  int ew_rule;        /* west/east quadrature in the canonical frame: 0 = the  */
+                      /* Gauss-Legendre panel rule compressed by pivoted QR    */
+                      /* node selection and least-squares weights (kept only   */
+                      /* if it reproduces the panel rule to eps on a check     */
+                      /* set), 1 = the panel rule as built                     */
 } pfmm_opts;
 
 typedef enum { PFMM_NEAR_AUTO = 0, PFMM_NEAR_ONE_SIDED = 1, PFMM_NEAR_MUTUAL = 2,
@@ -301,7 +306,7 @@ typedef struct {
 } pfmm_tuning_t;
 
 /* Host: read or set a plan's tuning. nufft_grid = 1 is rejected (PFMM_EINVAL)
- * when the doubled grid would exceed 4096 points. Not while an evaluation with
+ * when the doubled grid would exceed 2^20 points per line. Not while an evaluation with
  * this plan is being captured into a graph. */
 int pfmm_plan_get_tuning(pfmm_plan_t plan, pfmm_tuning_t* tuning);
 int pfmm_plan_set_tuning(pfmm_plan_t plan, const pfmm_tuning_t* tuning);

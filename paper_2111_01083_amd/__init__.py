@@ -45,13 +45,13 @@ class Plan:
 
     def __init__(self, kernel, e1, e2, tol, beta=0.0, precision="fp64", far_mode="auto", m0=0,
                  n_dens=1, self_exclude=False, m_gl=0, check_neutral=False, profile=False, near_mode="auto",
-                 periodic=2):
+                 periodic=2, ew_rule="compressed"):
         lib = L.load()
         self.kernel_name = kernel
         self.kernel = KERNELS[kernel]
         opts = L.pfmm_opts(float(beta), PRECISIONS[precision], FAR_MODES[far_mode], int(m0), int(n_dens),
                            int(bool(self_exclude)), int(m_gl), int(bool(check_neutral)), int(bool(profile)),
-                           NEAR_MODES[near_mode], int(periodic))
+                           NEAR_MODES[near_mode], int(periodic), {"compressed": 0, "panels": 1}[ew_rule])
         e1 = np.ascontiguousarray(e1, dtype=np.float64)
         e2 = np.ascontiguousarray(e2, dtype=np.float64)
         h = ctypes.c_void_p()

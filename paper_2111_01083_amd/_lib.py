@@ -33,7 +33,7 @@ class pfmm_opts(ctypes.Structure):
     _fields_ = [("beta", ctypes.c_double), ("precision", ctypes.c_int), ("far_mode", ctypes.c_int),
                 ("m0", ctypes.c_int), ("n_dens", ctypes.c_int), ("self_exclude", ctypes.c_int),
                 ("m_gl", ctypes.c_int), ("check_neutral", ctypes.c_int), ("profile", ctypes.c_int),
-                ("near_mode", ctypes.c_int), ("periodic", ctypes.c_int)]
+                ("near_mode", ctypes.c_int), ("periodic", ctypes.c_int), ("ew_rule", ctypes.c_int)]
 
 
 class pfmm_plan_info_t(ctypes.Structure):

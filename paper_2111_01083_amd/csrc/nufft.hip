@@ -35,6 +35,7 @@ constexpr int NU_BLOCK = 256;
 constexpr int SP_BLOCK = 512;           // spreading block (8 wavefronts)
 constexpr int SP_WAVES = SP_BLOCK / 64;
 constexpr int NU_LDS_BYTES = 65536;     // LDS sub-grid budget of a spreading block
+constexpr int FFT_LDS_MAX = 4096;       // longest line transformed inside one block's LDS
 
 struct NuTabs {
   const double* sn;      // south/north records
@@ -59,8 +60,9 @@ int r_fields(int kernel) { return kernel == PFMM_STOKES ? 2 : 1; }
 int l_fields(int kernel) { return kernel == PFMM_STOKES ? 12 : 3; }
 
 struct NuLayout {
-  size_t grid_r, spec, csn, grid_l, real_l, total;
+  size_t grid_r, spec, csn, grid_l, real_l, fft_tmp, total;
   int lines_per_group, n_groups;
+  bool spread_direct;
 };
 
 NuLayout nu_layout(const pfmm_plan_s* p, int64_t ns, int64_t nt) {
@@ -74,9 +76,14 @@ NuLayout nu_layout(const pfmm_plan_s* p, int64_t ns, int64_t nt) {
   L.csn = take(16 * (size_t)nd * p->n_sn * coef_per_wave(p->kernel));            // south/north coefficients
   L.grid_l = take(16 * (size_t)nd * l_fields(p->kernel) * mgl * nf);             // L-side line buffers
   L.real_l = take(8 * (size_t)nd * l_fields(p->kernel) * mgl * nf);              // their real parts, [dens][line][nf][field]
+  // four-step transforms of lines longer than one block's LDS: a scratch copy
+  L.fft_tmp = nf > FFT_LDS_MAX ? take(16 * (size_t)nd * l_fields(p->kernel) * mgl * nf) : 0;
   // spreading sub-grid in LDS (FP64: the deconvolution amplifies the
   // rounding of the grid's high frequencies, so the sums stay in FP64)
   L.lines_per_group = std::max(1, std::min(mgl, (int)(NU_LDS_BYTES / 8) / nf));
+  // a line longer than the LDS budget: spread straight into the global grid
+  L.spread_direct = (size_t)nf * 8 > (size_t)NU_LDS_BYTES;
+  if (L.spread_direct) L.lines_per_group = mgl;
   L.n_groups = (mgl + L.lines_per_group - 1) / L.lines_per_group;
   L.total = off;
   return L;
@@ -163,19 +170,24 @@ struct SpreadArgs {
 // otherwise put a wavefront's 64 LDS atomic adds on the same few grid
 // cells), while the SP_WAVES wavefronts of a block read neighbouring words
 // of the same cache lines. Each block accumulates its lines in LDS (FP64)
-// and adds them to the global grid once.
-template <int MG, int NP, typename acc_t>
+// and adds them to the global grid once (lines too long for the LDS budget:
+// straight into the global grid).
+template <int MG, int NP, bool DIRECT>
 __global__ __launch_bounds__(SP_BLOCK) void spread_kernel(SpreadArgs a) {
   constexpr int NA = MG > 0 ? MG : 32;
   extern __shared__ __align__(16) char sp_smem[];
-  acc_t* sg = (acc_t*)sp_smem;
   const int vf = blockIdx.z;
   const int v = vf / a.nfield, fld = vf % a.nfield;
   const int k0 = blockIdx.y * a.lines_per_group;
   const int nk = min(a.lines_per_group, a.mgl - k0);
   const int nf = a.nf;
-  for (int t = threadIdx.x; t < nk * nf; t += SP_BLOCK) sg[t] = (acc_t)0;
-  __syncthreads();
+  double* out = a.grid + ((size_t)vf * a.mgl + k0) * nf;
+  // DIRECT (lines longer than the LDS budget): atomics straight into the grid
+  double* sg = DIRECT ? out : (double*)sp_smem;
+  if (!DIRECT) {
+    for (int t = threadIdx.x; t < nk * nf; t += SP_BLOCK) sg[t] = 0.0;
+    __syncthreads();
+  }
   const double* q = a.dens + ((size_t)v * a.nfield + fld) * a.ns;
   const int lane = threadIdx.x & 63;
   const int64_t gw = (int64_t)blockIdx.x * SP_WAVES + (threadIdx.x >> 6);
@@ -199,15 +211,15 @@ __global__ __launch_bounds__(SP_BLOCK) void spread_kernel(SpreadArgs a) {
         const double val = qj * ph[t];
 #pragma unroll
         for (int kk = 0; kk < NA; ++kk)
-          if (kk >= k0 && kk < k0 + nk) atomicAdd(&sg[(kk - k0) * nf + lw], (acc_t)(val * gam[kk]));
+          if (kk >= k0 && kk < k0 + nk) atomicAdd(&sg[(kk - k0) * nf + lw], val * gam[kk]);
         lw = lw + 1 == nf ? 0 : lw + 1;
       }
     }
   }
+  if (DIRECT) return;
   __syncthreads();
-  double* out = a.grid + ((size_t)vf * a.mgl + k0) * nf;
   for (int t = threadIdx.x; t < nk * nf; t += SP_BLOCK) {
-    const double val = (double)sg[t];
+    const double val = sg[t];
     if (val != 0.0) atomicAdd(&out[t], val);
   }
 }
@@ -255,6 +267,86 @@ __global__ __launch_bounds__(NU_BLOCK) void fft_kernel(const double* in_real, co
   } else {
     for (int i = threadIdx.x; i < n; i += NU_BLOCK) out[off + i] = buf[i];
   }
+}
+
+// Longer lines (n > FFT_LDS_MAX points): four-step transform n = n1 n2. With
+// l = l1 + n1 l2 and k = k2 + n2 k1,
+//   X[k] = sum_l1 w_n^{l1 k2} w_n1^{l1 k1} (sum_l2 x[l1 + n1 l2] w_n2^{l2 k2}),
+// so pass 1 takes n1 transforms of length n2 (stride n1) and multiplies by
+// the twiddles w_n^{l1 k2}, and pass 2 takes n2 transforms of length n1.
+// One block per (transform, line): element i of transform b of line y is read
+// at y * n + b * in_bs + i * in_es and written at y * n + b * out_bs + i * out_es;
+// tw_n > 0 multiplies output k of transform b by e^{dir 2 pi i b k / tw_n}.
+// real_out as in fft_kernel (pass 2 of the L side only).
+__global__ __launch_bounds__(NU_BLOCK) void fft_pass_kernel(const double* in_real, const c2* in_cplx, c2* out,
+                                                            int64_t n, int ns, int log2ns, int dir, int64_t in_bs,
+                                                            int64_t in_es, int64_t out_bs, int64_t out_es,
+                                                            int64_t tw_n, double* real_out, int nfl, int mgl,
+                                                            int real32) {
+  extern __shared__ c2 buf[];
+  const int64_t b = blockIdx.x, y = blockIdx.y;
+  const size_t line = (size_t)y * n;
+  for (int i = threadIdx.x; i < ns; i += NU_BLOCK) {
+    const int r = (int)(__brev((unsigned)i) >> (32 - log2ns));
+    const size_t at = line + b * in_bs + (size_t)i * in_es;
+    buf[r] = in_real ? c2{in_real[at], 0.0} : in_cplx[at];
+  }
+  __syncthreads();
+  for (int s = 1; s <= log2ns; ++s) {
+    const int m = 1 << s, half = m >> 1;
+    for (int q = threadIdx.x; q < ns / 2; q += NU_BLOCK) {
+      const int grp = q / half, j = q - grp * half;
+      const int i0 = grp * m + j, i1 = i0 + half;
+      double sn, cs;
+      sincospi((double)(dir * 2 * j) / (double)m, &sn, &cs);
+      const c2 u = buf[i0], v = buf[i1];
+      const c2 t = {cs * v.r - sn * v.i, cs * v.i + sn * v.r};
+      buf[i0] = {u.r + t.r, u.i + t.i};
+      buf[i1] = {u.r - t.r, u.i - t.i};
+    }
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < ns; i += NU_BLOCK) {
+    c2 v = buf[i];
+    if (tw_n > 0) {
+      const int64_t e = (b * (int64_t)i) % tw_n;          // exact phase index
+      double sn, cs;
+      sincospi((double)(dir * 2) * (double)e / (double)tw_n, &sn, &cs);
+      v = {cs * v.r - sn * v.i, cs * v.i + sn * v.r};
+    }
+    const int64_t pos = b * out_bs + (int64_t)i * out_es;   // position within the line
+    if (real_out) {
+      const int k = (int)(y % mgl), vf = (int)(y / mgl), f = vf % nfl, vv = vf / nfl;
+      const size_t o0 = ((((size_t)vv * mgl + k) * n) + pos) * nfl + f;
+      if (real32) ((float*)real_out)[o0] = (float)v.r;
+      else real_out[o0] = v.r;
+    } else {
+      out[line + pos] = v;
+    }
+  }
+}
+
+int ilog2i(int64_t n) { int l = 0; while (((int64_t)1 << l) < n) ++l; return l; }
+
+// n-point transform of `lines` lines: in-LDS for n <= FFT_LDS_MAX, else the
+// four-step form through tmp (lines * n complex). Output as for fft_kernel.
+void line_fft(const double* in_real, const c2* in_cplx, c2* out, c2* tmp, int64_t n, int lines, int dir,
+              double* real_out, int nfl, int mgl, int real32, hipStream_t st) {
+  if (n <= FFT_LDS_MAX) {
+    hipLaunchKernelGGL(fft_kernel, dim3(lines), dim3(NU_BLOCK), n * sizeof(c2), st, in_real, in_cplx, out, (int)n,
+                       ilog2i(n), dir, real_out, nfl, mgl, real32);
+    return;
+  }
+  const int L = ilog2i(n);
+  const int64_t n2 = (int64_t)1 << (L / 2), n1 = n / n2;    // n1 >= n2, both <= FFT_LDS_MAX
+  // pass 1: n1 transforms (l1) of length n2 over l2 (stride n1); tmp[l1 n2 + k2]
+  hipLaunchKernelGGL(fft_pass_kernel, dim3((unsigned)n1, lines), dim3(NU_BLOCK), n2 * sizeof(c2), st, in_real,
+                     in_cplx, tmp, n, (int)n2, ilog2i(n2), dir, (int64_t)1, n1, n2, (int64_t)1, n, (double*)nullptr,
+                     1, 1, 0);
+  // pass 2: n2 transforms (k2) of length n1 over l1 (stride n2); X[k2 + n2 k1]
+  hipLaunchKernelGGL(fft_pass_kernel, dim3((unsigned)n2, lines), dim3(NU_BLOCK), n1 * sizeof(c2), st,
+                     (const double*)nullptr, (const c2*)tmp, out, n, (int)n1, ilog2i(n1), dir, (int64_t)1, n2,
+                     (int64_t)1, n2, (int64_t)0, real_out, nfl, mgl, real32);
 }
 
 struct CombineArgs {
@@ -411,25 +503,28 @@ __global__ __launch_bounds__(NU_BLOCK) void interp_kernel(InterpArgs a) {
 
 // dispatch over the compile-time classes
 template <int MG, int NP>
-void launch_spread_np(dim3 g, const SpreadArgs& sa, bool mixed, hipStream_t st) {
-  (void)mixed;
-  const size_t lds = (size_t)sa.lines_per_group * sa.nf * 8;
-  hipLaunchKernelGGL((spread_kernel<MG, NP, double>), g, dim3(SP_BLOCK), lds, st, sa);
-}
-template <int MG>
-void launch_spread_mg(dim3 g, const SpreadArgs& sa, bool mixed, hipStream_t st) {
-  switch (np_class(sa.w)) {
-    case 9: launch_spread_np<MG, 9>(g, sa, mixed, st); break;
-    case 13: launch_spread_np<MG, 13>(g, sa, mixed, st); break;
-    default: launch_spread_np<MG, 17>(g, sa, mixed, st); break;
+void launch_spread_np(dim3 g, const SpreadArgs& sa, bool direct, hipStream_t st) {
+  if (direct) {
+    hipLaunchKernelGGL((spread_kernel<MG, NP, true>), g, dim3(SP_BLOCK), 0, st, sa);
+  } else {
+    const size_t lds = (size_t)sa.lines_per_group * sa.nf * 8;
+    hipLaunchKernelGGL((spread_kernel<MG, NP, false>), g, dim3(SP_BLOCK), lds, st, sa);
   }
 }
-void launch_spread(dim3 g, const SpreadArgs& sa, bool mixed, hipStream_t st) {
+template <int MG>
+void launch_spread_mg(dim3 g, const SpreadArgs& sa, bool direct, hipStream_t st) {
+  switch (np_class(sa.w)) {
+    case 9: launch_spread_np<MG, 9>(g, sa, direct, st); break;
+    case 13: launch_spread_np<MG, 13>(g, sa, direct, st); break;
+    default: launch_spread_np<MG, 17>(g, sa, direct, st); break;
+  }
+}
+void launch_spread(dim3 g, const SpreadArgs& sa, bool direct, hipStream_t st) {
   switch (mg_class(sa.mgl)) {
-    case 8: launch_spread_mg<8>(g, sa, mixed, st); break;
-    case 12: launch_spread_mg<12>(g, sa, mixed, st); break;
-    case 16: launch_spread_mg<16>(g, sa, mixed, st); break;
-    default: launch_spread_mg<0>(g, sa, mixed, st); break;
+    case 8: launch_spread_mg<8>(g, sa, direct, st); break;
+    case 12: launch_spread_mg<12>(g, sa, direct, st); break;
+    case 16: launch_spread_mg<16>(g, sa, direct, st); break;
+    default: launch_spread_mg<0>(g, sa, direct, st); break;
   }
 }
 template <int MG, int NP, typename gr_t>
@@ -499,11 +594,11 @@ int nufft_R(const pfmm_plan_s* p, int64_t ns, const double* sx, const double* sy
     const int64_t by_work = (ns + 4 * SP_BLOCK - 1) / (4 * SP_BLOCK);
     const int64_t bx = std::max<int64_t>(1, std::min<int64_t>(by_work, (512 + yz - 1) / yz));
     dim3 g((unsigned)bx, (unsigned)L.n_groups, (unsigned)(nd * nfr));
-    launch_spread(g, sa, p->precision == PFMM_MIXED, st);
+    launch_spread(g, sa, L.spread_direct, st);
   }
   const int nfft = nd * nfr * mgl;
-  hipLaunchKernelGGL(fft_kernel, dim3(nfft), dim3(NU_BLOCK), nf * sizeof(c2), st, (const double*)grid,
-                     (const c2*)nullptr, spec, nf, ilog2(nf), -1, (double*)nullptr, 1, 1, 0);
+  line_fft((const double*)grid, (const c2*)nullptr, spec, (c2*)(ws + L.fft_tmp), nf, nfft, -1, (double*)nullptr,
+           1, 1, 0, st);
   CombineArgs ca{};
   ca.kernel = p->kernel; ca.n_sn = p->n_sn; ca.m_lo = p->m_lo; ca.mgl = mgl; ca.nf = nf; ca.n_dens = nd;
   ca.ncw = coef_per_wave(p->kernel); ca.nfield = nfr; ca.t = t; ca.spec = spec; ca.csn = csn;
@@ -526,8 +621,8 @@ int nufft_L(const pfmm_plan_s* p, int64_t nt, const double* tx, const double* ty
   const int nfft = nd * nlf * mgl;
   double* real_l = (double*)(ws + L.real_l);
   const bool mixed = p->precision == PFMM_MIXED;   // FP32 line fields (no deconvolution follows)
-  hipLaunchKernelGGL(fft_kernel, dim3(nfft), dim3(NU_BLOCK), nf * sizeof(c2), st, (const double*)nullptr,
-                     (const c2*)grid, grid, nf, ilog2(nf), +1, real_l, nlf, mgl, mixed ? 1 : 0);
+  line_fft((const double*)nullptr, (const c2*)grid, grid, (c2*)(ws + L.fft_tmp), nf, nfft, +1, real_l, nlf, mgl,
+           mixed ? 1 : 0, st);
   if (nt > 0) {
     InterpArgs ia{};
     ia.nt = nt; ia.kernel = p->kernel; ia.mgl = mgl; ia.nf = nf; ia.w = p->nu.w; ia.deg = p->nu.es_deg;

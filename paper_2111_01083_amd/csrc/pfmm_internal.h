@@ -68,6 +68,7 @@ struct NufftParams {
 // Spreading kernel as polynomials: tap t (0..w) of a point whose grid offset
 // is f = l0 - g + w/2 in [0, 1) has value sum_k c[t][k] u^k, u = 2f - 1;
 // stored as ES_TAPS x ES_COEF doubles (fixed size, zero-padded)
+constexpr int NUFFT_MAX_GRID = 1 << 20;   // NUFFT fine-grid points per line (two passes of <= 1024-point FFTs)
 constexpr int ES_TAPS = 17;
 constexpr int ES_COEF = 20;
 

@@ -263,6 +263,162 @@ void ew_rule_adaptive(int kernel, double beta, double dx, double dy, double xi2,
     }
 }
 
+// Least-squares solve min ||A x - b|| (A m x n, m >= n, row-major, full
+// column rank) by Householder QR; A and b are overwritten.
+bool lstsq(std::vector<double>& A, std::vector<double>& b, int m, int n, std::vector<double>& x) {
+  for (int k = 0; k < n; ++k) {
+    double nrm = 0;
+    for (int i = k; i < m; ++i) nrm += A[(size_t)i * n + k] * A[(size_t)i * n + k];
+    nrm = std::sqrt(nrm);
+    if (nrm == 0) return false;
+    const double a0 = A[(size_t)k * n + k], alpha = a0 > 0 ? -nrm : nrm;
+    std::vector<double> v(m, 0.0);
+    v[k] = a0 - alpha;
+    for (int i = k + 1; i < m; ++i) v[i] = A[(size_t)i * n + k];
+    double vv = 0;
+    for (int i = k; i < m; ++i) vv += v[i] * v[i];
+    for (int j = k; j < n; ++j) {
+      double t = 0;
+      for (int i = k; i < m; ++i) t += v[i] * A[(size_t)i * n + j];
+      t *= 2 / vv;
+      for (int i = k; i < m; ++i) A[(size_t)i * n + j] -= t * v[i];
+    }
+    double t = 0;
+    for (int i = k; i < m; ++i) t += v[i] * b[i];
+    t *= 2 / vv;
+    for (int i = k; i < m; ++i) b[i] -= t * v[i];
+  }
+  x.assign(n, 0.0);
+  for (int k = n - 1; k >= 0; --k) {
+    double t = b[k];
+    for (int j = k + 1; j < n; ++j) t -= A[(size_t)k * n + j] * x[j];
+    if (A[(size_t)k * n + k] == 0) return false;
+    x[k] = t / A[(size_t)k * n + k];
+  }
+  return true;
+}
+
+// Compressed west/east rule (canonical frame). The rule only ever integrates
+// combinations of the plane waves f(lambda) = e^{-kappa X} e^{i lambda Y}
+// (times 1/kappa for Yukawa) with X >= Xmin and |Y| <= 2 eta (every west/east
+// image of every pair, Thm. west_thm; the Laplace/Stokes forms are
+// superpositions of these over X). Sampling that family on the panel rule's
+// nodes, a column-pivoted QR of the weighted samples picks the nodes that
+// span it to eps, and least squares fits their weights to reproduce the panel
+// rule's integrals of every sample; the result is kept only if it also
+// reproduces them on a second, interleaved sample set to eps/4 of the
+// largest integral, else the panel rule stays. This is the node selection step of generalized Gaussian
+// quadrature, without its final Newton refinement of the nodes.
+void compress_rule(int kernel, double beta, double Xmin, double Ymax, double eps, std::vector<double>& nodes,
+                   std::vector<double>& wts) {
+  const int n = (int)nodes.size();
+  if (n < 8) return;
+  auto kap = [&](double lam) { return kernel == PFMM_YUKAWA ? std::sqrt(lam * lam + beta * beta) : lam; };
+  auto family = [&](double xs0, double ys0, std::vector<double>& X, std::vector<double>& Y) {
+    X.clear(); Y.clear();
+    const double span = (std::log(1.0 / eps) + 4.0) / std::max(kap(nodes[0] > 0 ? nodes[0] : 1e-3), 1e-300);
+    const double xmax = Xmin + std::min(span, 60.0 * Xmin + 60.0);
+    for (int i = 0; i < 24; ++i) {
+      const double t = (i + xs0) / 24.0;
+      X.push_back(Xmin * std::pow(xmax / Xmin, t * t));   // denser near Xmin
+    }
+    for (int j = 0; j <= 32; ++j) Y.push_back(Ymax * (-1.0 + 2.0 * (j + ys0) / 32.5));
+  };
+  auto fill = [&](const std::vector<double>& X, const std::vector<double>& Y, const std::vector<int>& cols,
+                  const std::vector<double>* w, std::vector<double>& M, std::vector<double>* ref) {
+    const int m = 2 * (int)(X.size() * Y.size()), nc = (int)cols.size();
+    M.assign((size_t)m * nc, 0.0);
+    if (ref) ref->assign(m, 0.0);
+    int r = 0;
+    for (double x : X)
+      for (double y : Y) {
+        double sr = 0, si = 0;
+        for (int c = 0; c < nc; ++c) {
+          const double lam = nodes[cols[c]], k = kap(lam);
+          const double a = std::exp(-k * x) / (kernel == PFMM_YUKAWA ? k : 1.0);
+          const double fr = a * std::cos(lam * y), fi = a * std::sin(lam * y);
+          const double sc = w ? (*w)[c] : 1.0;
+          M[(size_t)r * nc + c] = fr * sc;
+          M[(size_t)(r + 1) * nc + c] = fi * sc;
+          if (ref) { sr += wts[cols[c]] * fr; si += wts[cols[c]] * fi; }
+        }
+        if (ref) { (*ref)[r] = sr; (*ref)[r + 1] = si; }
+        r += 2;
+      }
+  };
+  std::vector<int> all(n);
+  for (int i = 0; i < n; ++i) all[i] = i;
+  std::vector<double> X, Y, F, ref;
+  family(0.0, 0.0, X, Y);
+  std::vector<double> sw(n);
+  for (int i = 0; i < n; ++i) sw[i] = std::sqrt(std::fabs(wts[i]));
+  fill(X, Y, all, &sw, F, &ref);
+  const int m = 2 * (int)(X.size() * Y.size());
+  // column-pivoted Householder QR of F until the largest remaining column
+  // norm drops below eps/20 of the largest initial one
+  std::vector<double> cn(n, 0.0);
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < m; ++i) cn[j] += F[(size_t)i * n + j] * F[(size_t)i * n + j];
+  const double c0 = std::sqrt(*std::max_element(cn.begin(), cn.end()));
+  std::vector<int> perm = all;
+  int r = 0;
+  for (; r < std::min(m, n); ++r) {
+    int jm = r;
+    for (int j = r; j < n; ++j) if (cn[j] > cn[jm]) jm = j;
+    if (std::sqrt(cn[jm]) < 0.05 * eps * c0) break;
+    if (jm != r) {
+      std::swap(perm[r], perm[jm]); std::swap(cn[r], cn[jm]);
+      for (int i = 0; i < m; ++i) std::swap(F[(size_t)i * n + r], F[(size_t)i * n + jm]);
+    }
+    double nrm = 0;
+    for (int i = r; i < m; ++i) nrm += F[(size_t)i * n + r] * F[(size_t)i * n + r];
+    nrm = std::sqrt(nrm);
+    const double a0 = F[(size_t)r * n + r], alpha = a0 > 0 ? -nrm : nrm;
+    std::vector<double> v(m, 0.0);
+    v[r] = a0 - alpha;
+    for (int i = r + 1; i < m; ++i) v[i] = F[(size_t)i * n + r];
+    double vv = 0;
+    for (int i = r; i < m; ++i) vv += v[i] * v[i];
+    if (vv == 0) break;
+    for (int j = r; j < n; ++j) {
+      double t = 0;
+      for (int i = r; i < m; ++i) t += v[i] * F[(size_t)i * n + j];
+      t *= 2 / vv;
+      for (int i = r; i < m; ++i) F[(size_t)i * n + j] -= t * v[i];
+    }
+    for (int j = r + 1; j < n; ++j) {
+      double t = 0;
+      for (int i = r + 1; i < m; ++i) t += F[(size_t)i * n + j] * F[(size_t)i * n + j];
+      cn[j] = t;
+    }
+  }
+  if (r >= n) return;
+  std::vector<int> sel(perm.begin(), perm.begin() + r);
+  std::sort(sel.begin(), sel.end());
+  // weights: least squares against the panel rule's integrals of the samples
+  std::vector<double> A, b = ref, w;
+  fill(X, Y, sel, nullptr, A, nullptr);
+  if (!lstsq(A, b, m, r, w)) return;
+  // check on an interleaved sample set
+  std::vector<double> X2, Y2, A2, ref2;
+  family(0.5, 0.5, X2, Y2);
+  fill(X2, Y2, sel, nullptr, A2, nullptr);
+  fill(X2, Y2, all, nullptr, F, &ref2);
+  const int m2 = 2 * (int)(X2.size() * Y2.size());
+  double scale = 0, err = 0;
+  for (int i = 0; i < m2; i += 2) {
+    double sr = 0, si = 0;
+    for (int c = 0; c < r; ++c) { sr += A2[(size_t)i * r + c] * w[c]; si += A2[(size_t)(i + 1) * r + c] * w[c]; }
+    err = std::max(err, std::hypot(sr - ref2[i], si - ref2[i + 1]));
+    scale = std::max(scale, std::hypot(ref2[i], ref2[i + 1]));
+  }
+  if (!(err <= 0.25 * eps * scale)) return;
+  std::vector<double> nn(r), ww(r);
+  for (int c = 0; c < r; ++c) { nn[c] = nodes[sel[c]]; ww[c] = w[c]; }
+  nodes.swap(nn);
+  wts.swap(ww);
+}
+
 }  // namespace
 
 // NUFFT grid and kernel (Sec. 6.1). grid 0: the smallest power of two
@@ -281,7 +437,7 @@ int set_nufft_grid(pfmm_plan_s* p, int grid) {
   int nf = 16;
   while (nf < 2 * (2 * M + 1) || nf < 2 * w) nf *= 2;
   if (grid == 1) {
-    if (2 * nf > 4096) return PFMM_EINVAL;   // the in-LDS line FFT holds 4096 points
+    if (2 * nf > NUFFT_MAX_GRID) return PFMM_EINVAL;
     nf *= 2;
     w = std::max(4, w - 1);
   } else if (grid != 0) {
@@ -490,8 +646,10 @@ int build_plan(int kernel, const double* e1, const double* e2, double tol, const
   else if (p->ew_rotated)
     ew_rule_adaptive(kernel, beta, p->ew_dx, p->ew_dy, p->ew_xi, p->ew_eta, 3, std::fabs(p->ew_dy) + p->ew_eta, m0,
                      eps, p->ew_nodes, p->ew_weights);
-  else
+  else {
     ew_rule(kernel, beta, d, xi, eta, m0, eps, p->ew_nodes, p->ew_weights);
+    if (o.ew_rule != 1) compress_rule(kernel, beta, m0 * d - 2 * std::fabs(xi), 2 * eta, eps, p->ew_nodes, p->ew_weights);
+  }
   p->n_ew = (int)p->ew_nodes.size();
   p->ew_tab.assign((size_t)p->n_ew * EW_REC, 0.0);
   const int pp = m0 + 1;
@@ -518,9 +676,9 @@ int build_plan(int kernel, const double* e1, const double* e2, double tol, const
   }
 
   // --- far mode and NUFFT parameters (Sec. 6.1)
-  // the in-LDS line FFT holds at most 4096 complex points; NUFFT needs a grid
-  // of at least twice the 2M+1 modes
-  const bool nufft_fits = 2 * (2 * M + 1) <= 4096;
+  // NUFFT needs a grid of at least twice the 2M+1 modes; lines up to 4096
+  // points are transformed in one block's LDS, longer ones in two passes
+  const bool nufft_fits = 2 * (2 * M + 1) <= NUFFT_MAX_GRID;
   int far = o.far_mode;
   if (p1 && far == PFMM_FAR_NUFFT) return PFMM_EINVAL;   // no south/north part to accelerate
   if (p1) far = PFMM_FAR_DIRECT;

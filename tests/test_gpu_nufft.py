@@ -132,3 +132,20 @@ def test_far_part_alone(env, cell, kernel, beta, far, prec, tol, bar):
     pn, gn = near_images_free_space(info, kernel, src, dens, trg, beta)
     po, go = oracle.evaluate(kernel, e1, e2, src, dens, trg, beta=beta)
     check(bar, (pf + pn, po), (gf + gn, go), label=f"far only {kernel} {far} {prec}")
+
+
+@pytest.mark.parametrize("kernel,beta", [("laplace", 0.0), ("stokes", 0.0), ("yukawa", 1.0)])
+@pytest.mark.parametrize("prec,tol,bar", [("fp64", 1e-10, 1e-10), ("mixed", 1e-6, 1e-6)])
+def test_aspect_ratio_1000_takes_the_nufft(env, kernel, beta, prec, tol, bar):
+    # A = 1000 (the paper's longest cells, Sec. 7 Tables 1-3): 2M + 1 = 6747
+    # modes at tol 1e-6 (9679 at 1e-10), fine grids of 16384 / 32768 points,
+    # whose line FFTs take two passes; auto mode picks the NUFFT
+    e1, e2 = (1000.0, 0.0), (0.0, 1.0)
+    src, dens, trg = blob_inputs(kernel, e1, e2, 3000, 700, seed=29)
+    print(f"case A=1000 {kernel} {prec}", flush=True)
+    pn, gn, info = run(env, kernel, e1, e2, src, dens, trg, "auto", prec, tol, beta)
+    assert info["far_mode_used"] == 2 and info["nufft_nf"] > 4096
+    pd, gd, _ = run(env, kernel, e1, e2, src, dens, trg, "direct", prec, tol, beta)
+    po, go = oracle.evaluate(kernel, e1, e2, src, dens, trg, beta=beta)
+    check(bar, (pn, po), (gn, go), label=f"A=1000 nufft {kernel} {prec}")
+    check(bar, (pn, pd), (gn, gd), label=f"A=1000 nufft vs direct {kernel} {prec}")

@@ -306,12 +306,12 @@ def test_tuning_get_set_and_nufft_grid(P):
     assert plan.info["nufft_nf"] == 2 * nf0 and plan.info["nufft_w"] == max(4, w0 - 1)
     plan.set_tuning(nufft_grid=0)
     assert plan.info["nufft_nf"] == nf0 and plan.info["nufft_w"] == w0
-    # a doubled grid beyond the 4096-point line FFT is refused and nothing changes
-    big = P.Plan("laplace", (200.0, 0.0), (0.0, 1.0), 1e-6, far_mode="nufft")
-    assert big.info["nufft_nf"] == 4096
+    # a doubled grid beyond the largest line (2^20 points) is refused and nothing changes
+    big = P.Plan("laplace", (60000.0, 0.0), (0.0, 1.0), 1e-6, far_mode="nufft")
+    assert big.info["nufft_nf"] == 1 << 20
     with pytest.raises(P.PfmmError):
         big.set_tuning(nufft_grid=1)
-    assert big.tuning["nufft_grid"] == 0 and big.info["nufft_nf"] <= 4096
+    assert big.tuning["nufft_grid"] == 0 and big.info["nufft_nf"] == 1 << 20
     with pytest.raises(P.PfmmError):
         plan.set_tuning(near_blocks=-1)
 
