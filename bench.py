@@ -90,6 +90,58 @@ def rel(a, b):
     return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
 
 
+def batch_workload(P, W, torch, dev, np):
+    """The batched form: 64 cells (N log-uniform in [1e3, 5e4], aspect ratio
+    log-uniform in [1, 50], shear in [0, 0.5]|e1|, even cells Laplace, odd
+    Yukawa beta = 10), 16 neutral density vectors per cell, pot + grad at all
+    sources, one hipGraph per batch, tol 1e-6; mixed (autotuned task shape)
+    against the plain FP64 path, each checked on the stored oracle samples
+    (32 targets of every cell, all 16 densities)."""
+    cells = W.batched_inputs(nd=16)
+    offs = [0]
+    for c in cells:
+        offs.append(offs[-1] + c["n"])
+    src = torch.tensor(np.concatenate([c["src"] for c in cells], axis=1), device=dev)
+    q = torch.tensor(np.concatenate([c["dens"] for c in cells], axis=1), device=dev)
+    ref = None
+    gpath = os.path.join(ROOT, "tests", "golden", "batch64_nd16.npz")
+    if os.path.exists(gpath):
+        z = np.load(gpath)
+        if str(z["inputs"]) == W.checksum(*([c["src"] for c in cells] + [c["dens"] for c in cells])):
+            ref = {k: z[k] for k in z.files}
+    res = {"workload": "64 cells, 16 density vectors each, sum N = %d, tol 1e-6, hipGraph" % offs[-1]}
+    for prec in ("mixed", "fp64"):
+        plans = [P.Plan(c["kernel"], c["e1"], c["e2"], 1e-6, beta=c["beta"], precision=prec, n_dens=16,
+                        self_exclude=True) for c in cells]
+        batch = P.Batch(plans, offs, use_graph=True)
+        if prec == "mixed":
+            batch.autotune(src, q)
+        ws = torch.empty(batch.workspace_bytes + 256, dtype=torch.uint8, device=dev)
+        pot = torch.empty((16, offs[-1]), dtype=torch.float64, device=dev)
+        grad = torch.empty((16, 2, offs[-1]), dtype=torch.float64, device=dev)
+        batch(src, q, out_pot=pot, out_grad=grad, workspace=ws)      # captures the graph
+        torch.cuda.synchronize()
+        steps = 3 if prec == "mixed" else 2
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            batch(src, q, out_pot=pot, out_grad=grad, workspace=ws)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / steps * 1e3
+        entry = {"ms_per_eval": round(ms, 3), "target_densities_per_s": round(16 * offs[-1] / (ms * 1e-3), 1),
+                 "steps": steps}
+        if ref is not None:
+            p_h = pot.cpu().numpy(); g_h = grad.cpu().numpy()
+            worst = 0.0
+            for c in range(len(cells)):
+                sl = offs[c] + ref[f"c{c}_idx"]
+                worst = max(worst, rel(p_h[:, sl], ref[f"c{c}_pot"]), rel(g_h[:, :, sl], ref[f"c{c}_grad"]))
+            entry["max_rel_err_vs_oracle_per_cell"] = worst
+        res[prec] = entry
+        del batch, plans, ws
+    res["speedup_mixed_vs_fp64"] = round(res["fp64"]["ms_per_eval"] / res["mixed"]["ms_per_eval"], 2)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,6 +151,8 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--sample", type=int, default=16, help="oracle targets per kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 64-cell batched workload (mixed and FP64) reported beside the headline")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 1 GiB elementwise copy (to calibrate HBM byte counters)")
     ap.add_argument("--nufft-sweep", default="",
@@ -270,6 +324,9 @@ def main():
         "roofline": roofline,
         "roofline_all": roof_all,
     }
+
+    if not args.no_batch:
+        out["batch"] = batch_workload(P, W, torch, dev, np)
 
     if not args.no_cpu_baseline:
         import oracle
