@@ -21,31 +21,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "targets/sec (pot+grad) at 1e-6 rel err, mixed vs FP64 GPU path; % FP32/HBM roofline"
-# algorithmic flops per target/source/image pair of the near-field kernels
-# (add/mul = 1, fma = 2, transcendental = 1; counted from the kernel source,
-# large-argument branch for K0/K1; FP64/FP32 conversions and the r = 0
-# guards are not counted)
+# algorithmic flops of one kernel sample (a target-source pair of the
+# leaves' direct sums, or a node pair of an interaction list) in the FMM
+# kernels: add/mul = 1, fma = 2, transcendental = 1 (a divide, and every FP64
+# log, exp, sqrt or Bessel sequence, counts as its one transcendental plus
+# its polynomial arithmetic), counted from the kernel source;
+# FP64/FP32 conversions, the r = 0 guards and the log-shift bookkeeping are
+# not counted. FP32 Yukawa: the large-argument K0/K1 branch. FP64 Yukawa:
+# coordinate differences 2, r^2 3, sqrt and beta r 2, 2/x, exp(-x)/sqrt(x) 4,
+# 2u - 1 2, two 21-term Clenshaw sums 128, scaling 3, accumulation 7.
 FLOPS_PER_PAIR = {"laplace": 14, "yukawa": 51, "stokes": 30}
-# symmetric kernel (targets == sources, a pair and its mirror at once): per
-# image of a pair (kernel moments without densities) and per pair (densities
-# times moments for both points, the log2 of the images' r^2 product, the
-# additions into both points' sums). Yukawa: 36 on the far-argument fits that
-# most images take, 44 on the large-argument fits; 36 makes the count a lower
-# bound
-FLOPS_MUTUAL_PER_IMAGE = {"laplace": 11, "yukawa": 36, "stokes": 22}
-FLOPS_MUTUAL_PER_PAIR = {"laplace": 15, "yukawa": 12, "stokes": 64}
-# the FP64 symmetric kernel, same convention (a divide counts as one
-# transcendental). Yukawa per image: coordinate differences 2, r^2 3, sqrt
-# and beta r 2, 2/x, exp(-x)/sqrt(x) 4, 2u - 1 2, two 21-term Chebyshev
-# (Clenshaw) sums of K0 and K1 128, scaling 3, moments 5 (the large-argument
-# branch, which all but ~1 % of the pairs take at beta = 10); per pair the
-# FP64 combination with the densities. Stokes: the same arithmetic as the
-# mixed kernel in FP64. One-sided pairs (diagonal tiles, 0.3 % of the work)
-# are counted at the per-image figure plus the density products.
-FLOPS_FP64_MUTUAL_PER_IMAGE = {"yukawa": 149, "stokes": 22}
-FLOPS_FP64_MUTUAL_PER_PAIR = {"yukawa": 12, "stokes": 64}
-FLOPS_FP64_PER_PAIR = {"yukawa": 155, "stokes": 30}
-TILE = 256    # targets per near-field block (the diagonal tiles are one-sided)
+FLOPS_FP64_PER_PAIR = {"laplace": 14, "yukawa": 155, "stokes": 30}
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
@@ -54,7 +40,8 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 # summary (scaled by a plain-copy calibration); used only while the kernel
 # sources still hash to the value recorded with the counters
 COUNTERS = os.path.join(ROOT, "profiles", "hbm_counters_square_n200k.md")
-HASHED = ["paper_2111_01083_amd/csrc/kernels.hip", "paper_2111_01083_amd/csrc/kernels.h",
+HASHED = ["paper_2111_01083_amd/csrc/fmm.hip", "paper_2111_01083_amd/csrc/fmm.h",
+          "paper_2111_01083_amd/csrc/kernels.hip", "paper_2111_01083_amd/csrc/kernels.h",
           "paper_2111_01083_amd/csrc/device_math.h", "paper_2111_01083_amd/csrc/bessel_tables.h"]
 
 
@@ -82,6 +69,83 @@ def measured_traffic():
             name, val = l[len("traffic:"):].strip().rsplit(" ", 1)
             out[name] = float(val)
     return out
+
+
+def fmm_work(plan, src, n_trg):
+    """Algorithmic work of the FMM near part of one evaluation with targets =
+    sources src (user frame, [2][n]): the leaves' direct pairs and the
+    interaction lists' kernel samples (node pairs) on the FP32 and FP64
+    levels, counted on the host from the same tree (the plan's lattice, leaf
+    boxes in lattice coordinates, empty boxes and the screened cutoff as in
+    the kernels). None if the evaluation's near part is direct."""
+    import numpy as np
+    t = plan.fmm_tree(src.shape[1], n_trg)
+    if t is None:
+        return None
+    inf = plan.info
+    d, xi, eta, rc, rs = inf["d"], inf["xi"], inf["eta"], inf["rot_cos"], inf["rot_sin"]
+    x = rc * src[0] - rs * src[1]
+    y = rs * src[0] + rc * src[1]
+    u2 = y / eta
+    u2 -= np.rint(u2)
+    u1 = (x - xi * (y / eta)) / d
+    u1 -= np.rint(u1)
+    L, k1, k2, P = t["level"], t["k1"], t["k2"], t["order"]
+    n1, n2 = k1 << L, k2 << L
+    i = np.clip(np.floor((u1 + 0.5) * n1).astype(np.int64), 0, n1 - 1)
+    j = np.clip(np.floor((u2 + 0.5) * n2).astype(np.int64), 0, n2 - 1)
+    leaf = np.zeros((n2, n1))
+    np.add.at(leaf, (j, i), 1.0)
+    # leaves: every target against the 3 x 3 neighbouring leaves (periodic
+    # neighbours are the images' boxes), less the self pairs
+    nb = sum(np.roll(np.roll(leaf, a, 0), b, 1) for a in (-1, 0, 1) for b in (-1, 0, 1))
+    p2p = float((leaf * nb).sum()) - src.shape[1]
+    m0 = inf["m0"]
+    beta = plan.beta if plan.kernel == 1 else 0.0
+    rcut = np.log(30.0 / inf["eps"]) / beta if beta > 0 else np.inf
+    f32_from = max(0, L - 1) if plan.precision == 1 else L + 1
+    pairs = {"fp32": 0.0, "fp64": 0.0}
+    cnt = leaf
+    for lev in range(L, -1, -1):
+        m1, m2 = k1 << lev, k2 << lev
+        h1, h2 = 0.5 / m1, 0.5 / m2
+        rad = 0.5 * max(np.hypot(2 * d * h1 + 2 * xi * h2, 2 * eta * h2), np.hypot(-2 * d * h1 + 2 * xi * h2, 2 * eta * h2))
+        ne = cnt > 0
+        visits = 0.0
+        if lev == 0:
+            offs = [(I, J) for J in range(-m2, 2 * m2) for I in range(-m0 * m1, (m0 + 1) * m1)]
+            for jj in range(m2):
+                for ii in range(m1):
+                    for I, J in offs:
+                        if abs(I - ii) <= 1 and abs(J - jj) <= 1:
+                            continue
+                        Dx = d * (ii - I) / m1 + xi * (jj - J) / m2
+                        Dy = eta * (jj - J) / m2
+                        if np.hypot(Dx, Dy) - 2 * rad > rcut or not ne[J % m2, I % m1]:
+                            continue
+                        visits += 1
+        else:
+            # offsets of the interaction list by the target's position in its parent
+            for pj in (0, 1):
+                for pi in (0, 1):
+                    tj, ti = np.meshgrid(np.arange(pj, m2, 2), np.arange(pi, m1, 2), indexing="ij")
+                    for dJ in range(-3, 4):
+                        for dI in range(-3, 4):
+                            if abs(dI) <= 1 and abs(dJ) <= 1:
+                                continue
+                            # children of the parent's neighbours: offsets from the target
+                            if not (-2 - pi <= dI <= 3 - pi and -2 - pj <= dJ <= 3 - pj):
+                                continue
+                            Dx = -(d * dI / m1 + xi * dJ / m2)
+                            Dy = -(eta * dJ / m2)
+                            if np.hypot(Dx, Dy) - 2 * rad > rcut:
+                                continue
+                            visits += float(ne[(tj + dJ) % m2, (ti + dI) % m1].sum())
+        pairs["fp32" if lev >= f32_from else "fp64"] += visits * P ** 4
+        if lev > 0:
+            cnt = cnt.reshape(m2 // 2, 2, m1 // 2, 2).sum(axis=(1, 3))
+    return {"level": L, "k1": k1, "k2": k2, "order": P, "p2p_pairs": p2p,
+            "m2l_node_pairs_fp32": pairs["fp32"], "m2l_node_pairs_fp64": pairs["fp64"]}
 
 
 def rel(a, b):
@@ -151,6 +215,8 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--sample", type=int, default=16, help="oracle targets per kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-direct", action="store_true",
+                    help="skip the one-step context run of the direct near-image sum")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 64-cell batched workload (mixed and FP64) reported beside the headline")
     ap.add_argument("--copy-calib", action="store_true",
@@ -246,66 +312,67 @@ def main():
             step(plans, outs, wss)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        stages = [p.stage_times() for p in plans]
+        stages = [p.stage_times() + p.fmm_stage_times() for p in plans]
         res = [(o[0].cpu().numpy()[0], o[1].cpu().numpy()[0]) for o in outs]
-        return (t1 - t0) / steps, stages, res
+        works = [fmm_work(p, src, n) for p in plans]
+        return (t1 - t0) / steps, stages, res, works
 
     print(f"bench: N={n} mixed steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
-    ms_mixed_s, st_mixed, res_mixed = timed("mixed", args.steps, args.warmup)
+    ms_mixed_s, st_mixed, res_mixed, work_mixed = timed("mixed", args.steps, args.warmup)
     print(f"bench: mixed {ms_mixed_s * 1e3:.1f} ms/step", file=sys.stderr, flush=True)
-    ms64_s, st64, res64 = timed("fp64", args.fp64_steps, 1)
+    ms64_s, st64, res64, work64 = timed("fp64", args.fp64_steps, 1)
     print(f"bench: fp64 {ms64_s * 1e3:.1f} ms/step", file=sys.stderr, flush=True)
 
     targets_per_step = 2 * n
     value = targets_per_step / ms_mixed_s
     fp64_value = targets_per_step / ms64_s
 
-    # near-field rooflines (HIP events on the evaluation stream)
-    images = 9
-    # pair evaluations of one launch: each target tile against itself
-    # one-sided, every other pair once for both points
-    tiles = [min(TILE, n - t0) for t0 in range(0, n, TILE)]
-    diag_pairs = images * sum(float(t) * t for t in tiles)
-    mutual_pairs = images * (float(n) * n - sum(float(t) * t for t in tiles)) / 2
-    roof_all = {}
+    # rooflines of the FMM near part's kernels (HIP events on the evaluation
+    # stream between its launches) against the algorithmic work of the same
+    # tree counted on the host
     traffic = measured_traffic()
-    for (kern, _, _), (near_ms, total_ms, cnt) in zip(cases, st_mixed):
-        per_launch_ms = near_ms / max(cnt, 1)
-        flops = (FLOPS_PER_PAIR[kern] * diag_pairs + FLOPS_MUTUAL_PER_IMAGE[kern] * mutual_pairs
-                 + FLOPS_MUTUAL_PER_PAIR[kern] * mutual_pairs / images)
-        tflops = flops / (per_launch_ms * 1e-3) / 1e12
-        # the plain one-sided direct sum's flops over the same time (context only)
-        direct = FLOPS_PER_PAIR[kern] * images * float(n) * n / (per_launch_ms * 1e-3) / 1e12
-        roof_all[kern] = {"bound": "alu", "achieved": round(tflops, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
-                          "unit": "TFLOP/s", "frac": round(tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
-                          "traffic": (traffic[f"near_mutual_kernel<{kern}, mixed, nd=1>"]
-                                      + traffic[f"near_kernel<{kern}, mixed, nd=1>"])
-                          if f"near_mutual_kernel<{kern}, mixed, nd=1>" in traffic
-                          and f"near_kernel<{kern}, mixed, nd=1>" in traffic else None,
-                          "near_ms_per_launch": round(per_launch_ms, 3),
-                          "eval_ms": round(total_ms / max(cnt, 1), 3),
-                          "flops_per_pair": FLOPS_PER_PAIR[kern],
-                          "flops_per_mutual_image": FLOPS_MUTUAL_PER_IMAGE[kern],
-                          "flops_per_mutual_pair": FLOPS_MUTUAL_PER_PAIR[kern],
-                          "direct_sum_equivalent_tflops": round(direct, 3),
-                          "pairs_per_launch": images * n * n,
-                          "pair_evaluations_per_launch": {"one_sided": diag_pairs, "mutual": mutual_pairs}}
-    dom = max(roof_all, key=lambda k: roof_all[k]["near_ms_per_launch"])
-    roofline = dict(roof_all[dom], kernel=f"near_mutual_kernel<{dom}, mixed> + diagonal near_kernel")
-    # the FP64 path's near field against the FP64 vector peak
-    roof64 = {}
-    for (kern, _, _), (near_ms, total_ms, cnt) in zip(cases, st64):
-        per_launch_ms = near_ms / max(cnt, 1)
-        flops = (FLOPS_FP64_PER_PAIR[kern] * diag_pairs + FLOPS_FP64_MUTUAL_PER_IMAGE[kern] * mutual_pairs
-                 + FLOPS_FP64_MUTUAL_PER_PAIR[kern] * mutual_pairs / images)
-        tflops = flops / (per_launch_ms * 1e-3) / 1e12
-        roof64[kern] = {"bound": "alu", "achieved": round(tflops, 3), "peak": FP64_VECTOR_PEAK_TFLOPS,
-                        "unit": "TFLOP/s", "frac": round(tflops / FP64_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
-                        "near_ms_per_launch": round(per_launch_ms, 3), "eval_ms": round(total_ms / max(cnt, 1), 3),
-                        "flops_per_pair": FLOPS_FP64_PER_PAIR[kern],
-                        "flops_per_mutual_image": FLOPS_FP64_MUTUAL_PER_IMAGE[kern],
-                        "flops_per_mutual_pair": FLOPS_FP64_MUTUAL_PER_PAIR[kern],
-                        "kernel": f"near_mutual_kernel<{kern}, fp64> + diagonal near_kernel"}
+
+    def stage_roofs(prec, stages, works):
+        peak = FP32_VECTOR_PEAK_TFLOPS if prec == "mixed" else FP64_VECTOR_PEAK_TFLOPS
+        pair32, pair64 = FLOPS_PER_PAIR, FLOPS_FP64_PER_PAIR
+        out_k = {}
+        for (kern, _, _), st, w in zip(cases, stages, works):
+            near_ms, total_ms, cnt, fst, fcnt = st
+            per = {k: v / max(fcnt, 1) for k, v in fst.items()}
+            pw = pair32 if prec == "mixed" else pair64
+            nout = 6 if kern == "stokes" else 3
+            # leaves: direct pairs, plus per target the interpolation of NOUT
+            # fields (P^2 fma each) and the two 1D bases (about 6 P)
+            leaf_flops = pw[kern] * w["p2p_pairs"] + n * (2 * nout * w["order"] ** 2 + 6 * w["order"])
+            kname = f"{kern}, {'mixed' if prec == 'mixed' else 'fp64'}"
+            rows = {"m2l_fp32": (FLOPS_PER_PAIR[kern] * w["m2l_node_pairs_fp32"], FP32_VECTOR_PEAK_TFLOPS,
+                                 f"fmm_m2l_kernel<{kern}, mixed>"),
+                    "m2l_fp64": (FLOPS_FP64_PER_PAIR[kern] * w["m2l_node_pairs_fp64"], FP64_VECTOR_PEAK_TFLOPS,
+                                 f"fmm_m2l_kernel<{kern}, fp64>"),
+                    "leaves": (leaf_flops, peak, f"fmm_leaf_kernel<{kname}>")}
+            ent = {}
+            for stg, (fl, pk, kn) in rows.items():
+                ms = per[stg]
+                if fl <= 0 or ms <= 0:
+                    continue
+                tf = fl / (ms * 1e-3) / 1e12
+                ent[stg] = {"bound": "alu", "achieved": round(tf, 3), "peak": pk, "unit": "TFLOP/s",
+                            "frac": round(tf / pk, 4), "traffic": traffic.get(kn), "ms_per_launch": round(ms, 4),
+                            "flops_per_launch": fl, "kernel": kn}
+            out_k[kern] = {"stages_ms_per_eval": {k: round(v, 4) for k, v in per.items()},
+                           "near_ms_per_eval": round(near_ms / max(cnt, 1), 3),
+                           "eval_ms": round(total_ms / max(cnt, 1), 3), "tree": w, "rooflines": ent}
+        return out_k
+
+    roof_all = stage_roofs("mixed", st_mixed, work_mixed)
+    roof64 = stage_roofs("fp64", st64, work64)
+    # the dominant kernel: the longest FMM stage over both kernels of a step
+    dom_k, dom_s = max(((k, s_) for k in roof_all for s_ in roof_all[k]["rooflines"]),
+                       key=lambda ks: roof_all[ks[0]]["rooflines"][ks[1]]["ms_per_launch"])
+    roofline = dict(roof_all[dom_k]["rooflines"][dom_s])
+    d64_k, d64_s = max(((k, s_) for k in roof64 for s_ in roof64[k]["rooflines"]),
+                       key=lambda ks: roof64[ks[0]]["rooflines"][ks[1]]["ms_per_launch"])
+    roofline64 = dict(roof64[d64_k]["rooflines"][d64_s])
 
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "targets/s", "n_gpus": 1,
@@ -317,13 +384,27 @@ def main():
                    "n": n, "tol": 1e-6, "precision": "mixed (FP32 pairs, FP64 accumulation and far field)",
                    "targets_per_step": targets_per_step},
         "fp64_gpu": {"value": round(fp64_value, 1), "unit": "targets/s", "ms_per_step": round(ms64_s * 1e3, 3),
-                     "steps": args.fp64_steps, "near_ms_per_launch": {k: round(s[0] / max(s[2], 1), 3)
-                                                                      for (k, _, _), s in zip(cases, st64)},
-                     "roofline": roof64},
+                     "steps": args.fp64_steps, "roofline": roofline64, "kernels": roof64},
         "speedup_mixed_vs_fp64": round(value / fp64_value, 2),
         "roofline": roofline,
         "roofline_all": roof_all,
     }
+    if not args.no_direct:
+        # context: the same mixed step with the near part as the direct sum
+        # over the near images (symmetric pair evaluation), one step
+        plans_d = [P.Plan(kern, e1, e2, 1e-6, beta=beta, precision="mixed", self_exclude=True, near_mode="mutual")
+                   for kern, beta, _ in cases]
+        outs_d = [o for o in make("mixed")[1]]
+        wss_d = [torch.empty(P.pfmm_workspace_bytes(p_, n, n) + 256, dtype=torch.uint8, device=dev) for p_ in plans_d]
+        step(plans_d, outs_d, wss_d)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        step(plans_d, outs_d, wss_d)
+        torch.cuda.synchronize()
+        ms_d = (time.perf_counter() - t0) * 1e3
+        out["direct_near_mixed"] = {"ms_per_step": round(ms_d, 3), "value": round(targets_per_step / (ms_d * 1e-3), 1),
+                                    "speedup_fmm_vs_direct": round(ms_d / (ms_mixed_s * 1e3), 2)}
+        del plans_d, wss_d
 
     if not args.no_batch:
         out["batch"] = batch_workload(P, W, torch, dev, np)

@@ -88,9 +88,10 @@ typedef struct {
                       /* taken in FP64, short FP32 sums (over 16 sources or a  */
                       /* pair's images) combined with the FP64 densities in    */
                       /* FP64, log terms from FP32 log2 of r^2 products added  */
-                      /* in FP64; far-field coefficients and weights in FP64,  */
-                      /* plane waves at the targets in FP32 with phases        */
-                      /* reduced in FP64)                                      */
+                      /* in FP64; FMM near part: kernel samples in FP32 on the */
+                      /* two finest levels, every expansion and sum in FP64;   */
+                      /* the far field (coefficients, weights, plane waves at  */
+                      /* the targets) in FP64)                                 */
   int far_mode;       /* pfmm_far_mode: AUTO uses the NUFFT when 2M+1 >= 256   */
   int m0;             /* near-region half width in e1 (Def. 1); 0 = automatic  */
   int n_dens;         /* number of density vectors evaluated together (>= 1)   */
@@ -109,7 +110,19 @@ typedef struct {
                       /* NONE leaves the near images out: the outputs are the  */
                       /* far part alone, the periodizing operator P applied to */
                       /* the densities (Sec. 1, eq. peropdef; Sec. 6). Batches */
-                      /* reject NONE plans                                     */
+                      /* reject NONE plans. FMM evaluates the near images by a */
+                      /* fast multipole method on a tree of boxes in lattice   */
+                      /* coordinates whose image boxes share the cell boxes'   */
+                      /* expansions (the remark of Sec. 7): Chebyshev          */
+                      /* interpolants of P x P points per box (P from tol and  */
+                      /* the kernel, see pfmm_plan_info_t.fmm_order), direct   */
+                      /* sums over neighbouring leaf boxes; O(N) work instead  */
+                      /* of the direct sum's 3 (2 m0 + 1) N_S N_T. Doubly      */
+                      /* periodic plans only; batches evaluate the near part  */
+                      /* directly and reject FMM plans. AUTO takes the FMM for */
+                      /* doubly periodic evaluations with N_S N_T >= 2^32      */
+                      /* (its error is then that of the interpolation, kept   */
+                      /* below tol / 10, instead of rounding alone)            */
   int periodic;       /* 2 (or 0): doubly periodic in e1 and e2 (operator P2). */
                       /* 1: singly periodic in e1 alone (operator P1, Sec. 3   */
                       /* eq. ksplitting1): images m e1 only, near part the     */
@@ -130,7 +143,7 @@ typedef struct {
 } pfmm_opts;
 
 typedef enum { PFMM_NEAR_AUTO = 0, PFMM_NEAR_ONE_SIDED = 1, PFMM_NEAR_MUTUAL = 2,
-               PFMM_NEAR_NONE = 3 } pfmm_near_mode;
+               PFMM_NEAR_NONE = 3, PFMM_NEAR_FMM = 4 } pfmm_near_mode;
 
 /* Read-only description of a plan (host struct). */
 typedef struct {
@@ -149,6 +162,8 @@ typedef struct {
   int ew_rotated;             /* 1: west/east waves along e2-perp (Appendix A)  */
   double ew_cos, ew_sin;      /* canonical -> west/east frame: x' = c x - s y,
                                  y' = s x + c y (identity when ew_rotated = 0)  */
+  int fmm_order;              /* Chebyshev points per box dimension of the FMM
+                                 near part (0: the plan never takes it)        */
 } pfmm_plan_info_t;
 
 typedef struct pfmm_plan_s* pfmm_plan_t;
@@ -197,6 +212,24 @@ int pfmm_plan_get_spread_kernel(pfmm_plan_t plan, double* coef, int* deg, double
  * (*total_ms) and the number of evaluations (*n_evals); then forget them.
  * Host pointers; any may be NULL. */
 int pfmm_plan_stage_times(pfmm_plan_t plan, double* near_ms, double* total_ms, int* n_evals);
+
+/* Profiling plans only: the same for the stages of the FMM near part of
+ * every pfmm_eval that took it since the last call (events on the
+ * evaluation's stream between the launches): stage_ms[0] upward pass
+ * (equivalent densities of the leaves and of every coarser level),
+ * [1] interaction lists whose kernel samples are FP64, [2] those sampled in
+ * FP32 (mixed plans: the two finest levels), [3] downward pass (local fields
+ * interpolated level to level), [4] leaves (local fields at the targets plus
+ * the neighbouring leaves' direct sums). Host pointers; stage_ms holds 5
+ * doubles; either may be NULL. */
+int pfmm_plan_fmm_stage_times(pfmm_plan_t plan, double* stage_ms, int* n_evals);
+
+/* Host: whether an evaluation with these sizes takes the FMM near part, and
+ * its tree: out[0] = 1 if so (else 0 and the rest 0), out[1] = leaf level
+ * L, out[2], out[3] = top boxes k1 x k2 (level l has (k1 2^l) x (k2 2^l)
+ * boxes over the cell in lattice coordinates), out[4] = Chebyshev points per
+ * box dimension. out: host int[5]. */
+int pfmm_fmm_tree(pfmm_plan_t plan, int64_t n_src, int64_t n_trg, int* out);
 
 /* Workspace size in bytes for pfmm_eval with these sizes. */
 size_t pfmm_workspace_bytes(pfmm_plan_t plan, int64_t n_src, int64_t n_trg);
@@ -303,6 +336,9 @@ typedef struct {
                            one-sided sum, 8192 for the symmetric one) */
   int nufft_grid;       /* NUFFT path: 0 = smallest power-of-two grid >= 2(2M+1) with width
                            ceil(log10(1/eps)) + 1; 1 = twice that grid, one point narrower */
+  int fmm_level;        /* FMM near part: leaf level of the tree, 1..11 (its leaves are the
+                           k1 x k2 top boxes split 4^level times); 0 = from a cost model of
+                           neighbour pairs against interaction-list node pairs */
 } pfmm_tuning_t;
 
 /* Host: read or set a plan's tuning. nufft_grid = 1 is rejected (PFMM_EINVAL)
@@ -317,8 +353,9 @@ typedef struct {
   double best_ms;       /* the same for the chosen tuning */
 } pfmm_tune_report_t;
 
-/* Autotuner: times candidate tunings (near_blocks; for NUFFT plans both
- * grids) on the caller's inputs with HIP events, keeps the fastest in the
+/* Autotuner: times candidate tunings (near_blocks, or for an FMM near part
+ * the leaf levels next to the cost model's; for NUFFT plans both grids) on
+ * the caller's inputs with HIP events, keeps the fastest in the
  * plan and leaves the result of an evaluation with it in out_pot/out_grad.
  * Arguments as for pfmm_eval; candidates that would need more than
  * workspace_bytes are skipped. Synchronises hip_stream; not for use under

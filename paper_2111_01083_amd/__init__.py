@@ -21,7 +21,7 @@ KERNELS = {"laplace": L.PFMM_LAPLACE, "yukawa": L.PFMM_YUKAWA, "stokes": L.PFMM_
 PRECISIONS = {"fp64": L.PFMM_FP64, "mixed": L.PFMM_MIXED}
 FAR_MODES = {"auto": L.PFMM_FAR_AUTO, "direct": L.PFMM_FAR_DIRECT, "nufft": L.PFMM_FAR_NUFFT}
 NEAR_MODES = {"auto": L.PFMM_NEAR_AUTO, "one_sided": L.PFMM_NEAR_ONE_SIDED, "mutual": L.PFMM_NEAR_MUTUAL,
-              "none": L.PFMM_NEAR_NONE}
+              "none": L.PFMM_NEAR_NONE, "fmm": L.PFMM_NEAR_FMM}
 
 
 class PfmmError(RuntimeError):
@@ -60,6 +60,8 @@ class Plan:
         self.handle = h
         self.n_dens = int(n_dens)
         self.self_exclude = bool(self_exclude)
+        self.beta = float(beta)
+        self.precision = PRECISIONS[precision]
         self._ws = None
 
     def __del__(self):
@@ -103,12 +105,29 @@ class Plan:
                "pfmm_plan_stage_times")
         return a.value, b.value, n.value
 
+    def fmm_stage_times(self):
+        """FMM near part of the evaluations since the last call (profiling
+        plans): ({stage: ms summed}, evaluations) for the stages upward,
+        m2l_fp64, m2l_fp32, downward, leaves."""
+        ms = (ctypes.c_double * 5)()
+        n = ctypes.c_int()
+        _check(L.load().pfmm_plan_fmm_stage_times(self.handle, ms, ctypes.byref(n)), "pfmm_plan_fmm_stage_times")
+        return dict(zip(("upward", "m2l_fp64", "m2l_fp32", "downward", "leaves"), list(ms))), n.value
+
+    def fmm_tree(self, n_src, n_trg=None):
+        """The FMM tree an evaluation with these sizes takes, or None if its
+        near part is direct: dict(level, k1, k2, order)."""
+        out = (ctypes.c_int * 5)()
+        _check(L.load().pfmm_fmm_tree(self.handle, int(n_src), int(n_src if n_trg is None else n_trg), out),
+               "pfmm_fmm_tree")
+        return dict(level=out[1], k1=out[2], k2=out[3], order=out[4]) if out[0] else None
+
     @property
     def tuning(self):
         return pfmm_plan_get_tuning(self)
 
-    def set_tuning(self, near_blocks=None, nufft_grid=None):
-        pfmm_plan_set_tuning(self, near_blocks, nufft_grid)
+    def set_tuning(self, near_blocks=None, nufft_grid=None, fmm_level=None):
+        pfmm_plan_set_tuning(self, near_blocks, nufft_grid, fmm_level)
 
     def __call__(self, src, dens, trg=None, **kw):
         return pfmm_eval(self, src, dens, trg, **kw)
@@ -235,13 +254,14 @@ def pfmm_plan_get_log_groups(plan):
 def pfmm_plan_get_tuning(plan):
     t = L.pfmm_tuning_t()
     _check(L.load().pfmm_plan_get_tuning(plan.handle, ctypes.byref(t)), "pfmm_plan_get_tuning")
-    return {"near_blocks": int(t.near_blocks), "nufft_grid": int(t.nufft_grid)}
+    return {"near_blocks": int(t.near_blocks), "nufft_grid": int(t.nufft_grid), "fmm_level": int(t.fmm_level)}
 
 
-def pfmm_plan_set_tuning(plan, near_blocks=None, nufft_grid=None):
+def pfmm_plan_set_tuning(plan, near_blocks=None, nufft_grid=None, fmm_level=None):
     cur = pfmm_plan_get_tuning(plan)
     t = L.pfmm_tuning_t(int(cur["near_blocks"] if near_blocks is None else near_blocks),
-                        int(cur["nufft_grid"] if nufft_grid is None else nufft_grid))
+                        int(cur["nufft_grid"] if nufft_grid is None else nufft_grid),
+                        int(cur["fmm_level"] if fmm_level is None else fmm_level))
     _check(L.load().pfmm_plan_set_tuning(plan.handle, ctypes.byref(t)), "pfmm_plan_set_tuning")
 
 
@@ -252,13 +272,14 @@ def _tuning_workspace_bytes(plan, ns, nt):
     try:
         for nb in (4096, 16384):
             for g in (0, 1):
-                try:
-                    pfmm_plan_set_tuning(plan, nb, g)
-                except PfmmError:
-                    continue
-                best = max(best, pfmm_workspace_bytes(plan, ns, nt))
+                for lv in range(0, 12):   # FMM leaf levels (only the tree's neighbours are tried)
+                    try:
+                        pfmm_plan_set_tuning(plan, nb, g, lv)
+                    except PfmmError:
+                        continue
+                    best = max(best, pfmm_workspace_bytes(plan, ns, nt))
     finally:
-        pfmm_plan_set_tuning(plan, start["near_blocks"], start["nufft_grid"])
+        pfmm_plan_set_tuning(plan, start["near_blocks"], start["nufft_grid"], start["fmm_level"])
     return best
 
 

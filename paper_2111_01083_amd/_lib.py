@@ -12,7 +12,7 @@ LIB_PATH = os.path.join(_PKG, "libpfmm.so")
 PFMM_LAPLACE, PFMM_YUKAWA, PFMM_STOKES = 0, 1, 2
 PFMM_FP64, PFMM_MIXED = 0, 1
 PFMM_FAR_AUTO, PFMM_FAR_DIRECT, PFMM_FAR_NUFFT = 0, 1, 2
-PFMM_NEAR_AUTO, PFMM_NEAR_ONE_SIDED, PFMM_NEAR_MUTUAL, PFMM_NEAR_NONE = 0, 1, 2, 3
+PFMM_NEAR_AUTO, PFMM_NEAR_ONE_SIDED, PFMM_NEAR_MUTUAL, PFMM_NEAR_NONE, PFMM_NEAR_FMM = 0, 1, 2, 3, 4
 PFMM_MAX_POINTS = 1 << 30          # largest n_src / n_trg (per cell in a batch)
 PFMM_STATIC_WORKSPACE_BYTES = 64 << 20   # the fixed device workspace of pfmm_eval_static
 ERRORS = {0: "PFMM_OK", -1: "PFMM_EINVAL", -2: "PFMM_EINVAL_LATTICE", -3: "PFMM_EINVAL_TOL",
@@ -21,7 +21,7 @@ ERRORS = {0: "PFMM_OK", -1: "PFMM_EINVAL", -2: "PFMM_EINVAL_LATTICE", -3: "PFMM_
 # every function declared in include/pfmm.h
 EXPORTS = ["pfmm_plan", "pfmm_plan_upload", "pfmm_plan_get_info", "pfmm_plan_get_quadrature",
            "pfmm_plan_get_log_groups", "pfmm_plan_get_spread_kernel",
-           "pfmm_plan_stage_times",
+           "pfmm_plan_stage_times", "pfmm_plan_fmm_stage_times", "pfmm_fmm_tree",
            "pfmm_workspace_bytes", "pfmm_eval", "pfmm_eval_static", "pfmm_workspace_bytes_adjoint", "pfmm_eval_adjoint",
            "pfmm_workspace_bytes_pressure", "pfmm_eval_pressure",
            "pfmm_batch_create", "pfmm_batch_workspace_bytes", "pfmm_eval_batch", "pfmm_batch_destroy",
@@ -45,11 +45,11 @@ class pfmm_plan_info_t(ctypes.Structure):
                 ("nufft_nf", ctypes.c_int), ("nufft_w", ctypes.c_int), ("n_images", ctypes.c_int),
                 ("n_log_groups", ctypes.c_int), ("periodic", ctypes.c_int), ("ew_rotated", ctypes.c_int),
                 ("ew_cos", ctypes.c_double),
-                ("ew_sin", ctypes.c_double)]
+                ("ew_sin", ctypes.c_double), ("fmm_order", ctypes.c_int)]
 
 
 class pfmm_tuning_t(ctypes.Structure):
-    _fields_ = [("near_blocks", ctypes.c_int64), ("nufft_grid", ctypes.c_int)]
+    _fields_ = [("near_blocks", ctypes.c_int64), ("nufft_grid", ctypes.c_int), ("fmm_level", ctypes.c_int)]
 
 
 class pfmm_tune_report_t(ctypes.Structure):
@@ -83,6 +83,10 @@ def load():
     lib.pfmm_plan_get_spread_kernel.restype = c_int
     lib.pfmm_plan_stage_times.argtypes = [vp, dp, dp, ctypes.POINTER(c_int)]
     lib.pfmm_plan_stage_times.restype = c_int
+    lib.pfmm_plan_fmm_stage_times.argtypes = [vp, dp, ctypes.POINTER(c_int)]
+    lib.pfmm_plan_fmm_stage_times.restype = c_int
+    lib.pfmm_fmm_tree.argtypes = [vp, i64, i64, ctypes.POINTER(c_int)]
+    lib.pfmm_fmm_tree.restype = c_int
     lib.pfmm_workspace_bytes.argtypes = [vp, i64, i64]
     lib.pfmm_workspace_bytes.restype = ctypes.c_size_t
     lib.pfmm_eval.argtypes = [vp, i64, vp, vp, i64, vp, vp, vp, vp, ctypes.c_size_t, vp]

@@ -7,7 +7,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpfmm.so")
-SOURCES = ["plan.cpp", "kernels.hip", "nufft.hip", "capi.hip", "adjoint.hip", "pressure.hip"]
+SOURCES = ["plan.cpp", "kernels.hip", "nufft.hip", "fmm.hip", "capi.hip", "adjoint.hip", "pressure.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

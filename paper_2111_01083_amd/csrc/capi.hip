@@ -9,6 +9,7 @@
 #include <new>
 #include <vector>
 
+#include "fmm.h"
 #include "kernels.h"
 #include "nufft.h"
 #include "pfmm.h"
@@ -37,6 +38,14 @@ struct Layout {
   int64_t chunk_len;
   int64_t split_len;
   size_t part_stride;  // doubles per split
+  // near part by the FMM: the tree, leaf-box order of the sources (their own
+  // sort unless they are the targets), expansions and per-box source counts
+  int fmm;
+  FmmTree ft;
+  size_t skey, sperm, scnt, sseg, ssx, ssy;
+  int snblk;
+  int64_t sbp;
+  size_t fW, fF, fcount;
 };
 
 void plan_layout(const pfmm_plan_s* p, int64_t ns, int64_t nt, Layout& L, int64_t forced_split = 0) {
@@ -55,13 +64,25 @@ void plan_layout(const pfmm_plan_s* p, int64_t ns, int64_t nt, Layout& L, int64_
     L.q32 = 0;
   }
   L.dens_c = take(8 * (size_t)p->n_dens * nc * ns);   // contiguous FP64 densities (Stokes: rotated)
+  // FMM near part: explicit, or AUTO for doubly periodic single cells with
+  // many pairs (batched cells take the direct near field)
+  L.fmm = (!p->near_none && p->periodic == 2 && forced_split == 0 && ns > 0 && nt > 0 &&
+           (p->near_fmm == 1 || (p->near_fmm == 2 && (double)ns * (double)nt >= FMM_AUTO_PAIRS))) ? 1 : 0;
+  if (L.fmm) {
+    fmm_tree(p, ns, nt, L.ft);
+    // AUTO: not for cells whose top grid needs many boxes (their level-0
+    // interaction lists span the whole super-grid)
+    if (p->near_fmm == 2 && L.ft.k1 * L.ft.k2 > FMM_AUTO_TOP) L.fmm = 0;
+  }
   // target bins of about 64 points over the canonical cell's bounding box
+  // (FMM: the leaf boxes, in lattice coordinates)
   {
     const double W = p->geo.d + std::fabs(p->geo.xi), H = p->geo.eta;
     const double nb = std::max(1.0, std::min((double)nt / 64.0, 4.0e6));
     const double h = std::sqrt(W * H / nb);
     L.nbx = std::max(1, (int)std::ceil(W / h));
     L.nby = std::max(1, (int)std::ceil(H / h));
+    if (L.fmm) { L.nbx = L.ft.k1 << L.ft.L; L.nby = L.ft.k2 << L.ft.L; }
     L.bin_w = W / L.nbx;
     L.bin_h = H / L.nby;
     L.key = take(4 * nt); L.perm = take(4 * nt); L.stx = take(8 * nt); L.sty = take(8 * nt);
@@ -85,17 +106,37 @@ void plan_layout(const pfmm_plan_s* p, int64_t ns, int64_t nt, Layout& L, int64_
   // the symmetric near field needs targets == sources; its diagonal pass
   // writes a single partial row
   // (forced_split > 0: batched cell; its symmetric tasks use chunks of that length)
-  L.mutual = (p->mutual && p->self_exclude && ns == nt) ? 1 : 0;
-  if (L.mutual || p->near_none) per = std::max<int64_t>(ns, 1);
+  L.mutual = (p->mutual && p->self_exclude && ns == nt && !L.fmm) ? 1 : 0;
+  if (L.mutual || p->near_none || L.fmm) per = std::max<int64_t>(ns, 1);
   per = std::max<int64_t>(NEAR_TILE, (per + NEAR_TILE - 1) / NEAR_TILE * NEAR_TILE);
   L.split_len = per;
   L.n_splits = (int)std::max<int64_t>(1, (ns + per - 1) / per);
   L.part_stride = (size_t)p->n_dens * no * nt;
-  L.qsum = (mixed && p->kernel != PFMM_YUKAWA) ? take(8 * (size_t)L.n_splits * p->n_dens * nc) : 0;
+  L.qsum = (mixed && p->kernel != PFMM_YUKAWA && !L.fmm) ? take(8 * (size_t)L.n_splits * p->n_dens * nc) : 0;
   L.qpart = L.qsum ? take(8 * (size_t)L.n_splits * QSUM_PARTS * p->n_dens * nc) : 0;
   L.near_part = take(8 * L.part_stride * L.n_splits);
   L.qb64 = L.qb32 = 0;
   L.mu_chunk = 0;
+  L.skey = L.sperm = L.scnt = L.sseg = L.ssx = L.ssy = L.fW = L.fF = L.fcount = 0;
+  L.snblk = 0;
+  L.sbp = 0;
+  if (L.fmm) {
+    // sources in leaf-box order: the sorted targets when they are the sources
+    if (!p->self_exclude) {
+      const int64_t nbins = (int64_t)L.nbx * L.nby;
+      L.snblk = (int)std::min<int64_t>(std::min<int64_t>(256, std::max<int64_t>(1, (1 << 26) / nbins)),
+                                       std::max<int64_t>(1, (ns + 1023) / 1024));
+      L.sbp = std::max<int64_t>(1, (ns + L.snblk - 1) / L.snblk);
+      L.skey = take(4 * ns); L.sperm = take(4 * ns); L.ssx = take(8 * ns); L.ssy = take(8 * ns);
+      L.scnt = take(4 * (size_t)nbins * L.snblk);
+      L.sseg = take(4 * (((size_t)nbins * L.snblk + SCAN_SEG - 1) / SCAN_SEG));
+    }
+    L.qb64 = take(8 * (size_t)p->n_dens * nc * ns);
+    const size_t nbox = (size_t)fmm_boxes(L.ft), P2 = (size_t)L.ft.P * L.ft.P;
+    L.fW = take(8 * nbox * p->n_dens * nc * P2);
+    L.fF = take(8 * nbox * p->n_dens * no * P2);
+    L.fcount = take(4 * nbox);
+  }
   if (L.mutual) {
     L.qb64 = take(8 * (size_t)p->n_dens * nc * ns);
     L.qb32 = mixed ? take(4 * (size_t)p->n_dens * nc * ns) : 0;
@@ -281,6 +322,7 @@ int pfmm_plan_get_info(pfmm_plan_t p, pfmm_plan_info_t* info) {
   info->m_gl = p->nu.m_gl; info->nufft_nf = p->nu.nf; info->nufft_w = p->nu.w;
   info->n_images = p->geo.n_images;
   info->n_log_groups = p->geo.n_lg;
+  info->fmm_order = (p->near_fmm && p->periodic == 2 && !p->near_none) ? p->fmm_order : 0;
   return PFMM_OK;
 }
 
@@ -395,11 +437,25 @@ static void cell_prep(CellRun& r, const double* src_xy, int64_t src_stride, cons
   sa.key = (int*)(ws + L.key); sa.perm = (int*)(ws + L.perm);
   sa.cnt = (int*)(ws + L.cnt); sa.nblk = L.nblk; sa.bp = L.bp; sa.seg = (int*)(ws + L.seg);
   sa.sx = D(L.stx); sa.sy = D(L.sty);
+  sa.lattice = L.fmm; sa.d = g.d; sa.xi = g.xi; sa.eta = g.eta;
   launch_sort_targets(sa, st);
   r.perm = sa.perm;
+  const int ncomp = p->n_dens * (p->kernel == PFMM_STOKES ? 2 : 1);
   if (L.mutual)
-    launch_gather_dens(D(L.dens_c), sa.perm, r.ns, p->n_dens * (p->kernel == PFMM_STOKES ? 2 : 1), D(L.qb64),
-                       mixed ? F(L.qb32) : nullptr, st);
+    launch_gather_dens(D(L.dens_c), sa.perm, r.ns, ncomp, D(L.qb64), mixed ? F(L.qb32) : nullptr, st);
+  if (L.fmm) {
+    const int* sperm = sa.perm;
+    if (!p->self_exclude) {
+      SortArgs ss = sa;
+      ss.n = r.ns; ss.x = D(L.scx); ss.y = D(L.scy);
+      ss.key = (int*)(ws + L.skey); ss.perm = (int*)(ws + L.sperm);
+      ss.cnt = (int*)(ws + L.scnt); ss.nblk = L.snblk; ss.bp = L.sbp; ss.seg = (int*)(ws + L.sseg);
+      ss.sx = D(L.ssx); ss.sy = D(L.ssy);
+      launch_sort_targets(ss, st);
+      sperm = ss.perm;
+    }
+    launch_gather_dens(D(L.dens_c), sperm, r.ns, ncomp, D(L.qb64), nullptr, st);
+  }
 }
 
 static NearArgs cell_near_args(const CellRun& r) {
@@ -475,7 +531,6 @@ static int cell_far(CellRun& r, double* out_pot, double* out_grad, int64_t out_s
   FarLArgs fl{};
   fl.kernel = K; fl.n_sn = p->n_sn; fl.n_ew = p->n_ew; fl.ncw = fr.ncw; fl.n_coef = L.n_coef;
   fl.n_dens = p->n_dens; fl.n_splits = ns > 0 ? L.n_splits : 1; fl.nufft = p->use_nufft; fl.n_trg = nt;
-  fl.mixed = p->precision == PFMM_MIXED;
   fl.d = g.d; fl.eta = g.eta; fl.rc = g.rc; fl.rs = g.rs; fl.tab = p->d_tab; fl.w = D(L.w);
   fl.ew_c = p->ew_c; fl.ew_s = p->ew_s;
   fl.m0term = p->periodic == 2;
@@ -547,6 +602,39 @@ int pfmm::eval_core(pfmm_plan_t p, int64_t ns, const double* src_xy, const doubl
   if (p->profile) (void)hipEventRecord(ev[0], st);
   if (p->near_none) {
     launch_fill_zero(na.part, (int64_t)r.L.part_stride, st);   // far part alone
+  } else if (r.L.fmm) {
+    const Layout& L = r.L;
+    FmmArgs fa{};
+    fa.t = L.ft;
+    fa.n_dens = p->n_dens;
+    fa.beta = p->beta;
+    fa.rcut = p->kernel == PFMM_YUKAWA ? std::sqrt(near_rcut2(p)) : 1.0e300;
+    fa.n_src = ns; fa.n_trg = nt;
+    fa.tx = D_(r, L.stx); fa.ty = D_(r, L.sty);
+    fa.tcnt = (const int*)(r.ws + L.cnt); fa.tnblk = L.nblk;
+    if (p->self_exclude) {
+      fa.sx = fa.tx; fa.sy = fa.ty; fa.scnt = fa.tcnt; fa.snblk = fa.tnblk;
+    } else {
+      fa.sx = D_(r, L.ssx); fa.sy = D_(r, L.ssy);
+      fa.scnt = (const int*)(r.ws + L.scnt); fa.snblk = L.snblk;
+    }
+    fa.sq = D_(r, L.qb64);
+    fa.scount = (int*)(r.ws + L.fcount);
+    fa.W = D_(r, L.fW); fa.F = D_(r, L.fF);
+    fa.part = na.part;
+    hipEvent_t fev[6] = {};
+    bool timed = false;
+    if (p->profile) {
+      timed = true;
+      for (int k = 0; k < 6 && timed; ++k)
+        if (hipEventCreate(&fev[k]) != hipSuccess) {
+          for (int q = 0; q < k; ++q) (void)hipEventDestroy(fev[q]);
+          timed = false;
+        }
+      if (timed)
+        for (int k = 0; k < 6; ++k) p->prof_fmm_events.push_back(fev[k]);
+    }
+    launch_fmm(p->kernel, p->precision == PFMM_MIXED, fa, st, timed ? fev : nullptr);
   } else if (ns > 0 && r.L.mutual) {
     // diagonal tiles (one-sided, writes the partial row), then every other
     // pair once for both of its points (atomic adds into the same row)
@@ -604,10 +692,44 @@ int pfmm_plan_stage_times(pfmm_plan_t p, double* near_ms, double* total_ms, int*
   return rc;
 }
 
+int pfmm_plan_fmm_stage_times(pfmm_plan_t p, double* stage_ms, int* n_evals) {
+  if (!p) return PFMM_EINVAL;
+  double acc[5] = {0, 0, 0, 0, 0};
+  int n = 0, rc = PFMM_OK;
+  for (size_t k = 0; k + 5 < p->prof_fmm_events.size(); k += 6) {
+    hipEvent_t* e = (hipEvent_t*)&p->prof_fmm_events[k];
+    if (hipEventSynchronize(e[5]) != hipSuccess) rc = PFMM_EHIP;
+    for (int q = 0; q < 5; ++q) {
+      float t = 0;
+      if (hipEventElapsedTime(&t, e[q], e[q + 1]) != hipSuccess) rc = PFMM_EHIP;
+      acc[q] += t;
+    }
+    for (int q = 0; q < 6; ++q) (void)hipEventDestroy(e[q]);
+    ++n;
+  }
+  p->prof_fmm_events.clear();
+  if (stage_ms) std::copy(acc, acc + 5, stage_ms);
+  if (n_evals) *n_evals = n;
+  return rc;
+}
+
+int pfmm_fmm_tree(pfmm_plan_t p, int64_t ns, int64_t nt, int* out) {
+  if (!p || !out || ns < 0 || nt < 0 || ns > PFMM_MAX_POINTS || nt > PFMM_MAX_POINTS) return PFMM_EINVAL;
+  Layout L;
+  plan_layout(p, ns, p->self_exclude ? ns : nt, L);
+  out[0] = L.fmm;
+  out[1] = L.fmm ? L.ft.L : 0;
+  out[2] = L.fmm ? L.ft.k1 : 0;
+  out[3] = L.fmm ? L.ft.k2 : 0;
+  out[4] = L.fmm ? L.ft.P : 0;
+  return PFMM_OK;
+}
+
 void pfmm_destroy(pfmm_plan_t p) {
   if (!p) return;
   if (p->lap) pfmm_destroy(p->lap);
   for (void* e : p->prof_events) (void)hipEventDestroy((hipEvent_t)e);
+  for (void* e : p->prof_fmm_events) (void)hipEventDestroy((hipEvent_t)e);
   if (p->d_tab) (void)hipFree(p->d_tab);
   delete p;
 }
@@ -662,11 +784,13 @@ int pfmm_plan_get_tuning(pfmm_plan_t p, pfmm_tuning_t* t) {
   if (!p || !t) return PFMM_EINVAL;
   t->near_blocks = p->tune_near;
   t->nufft_grid = p->nu_grid;
+  t->fmm_level = p->tune_fmm_level;
   return PFMM_OK;
 }
 
 int pfmm_plan_set_tuning(pfmm_plan_t p, const pfmm_tuning_t* t) {
   if (!p || !t || t->near_blocks < 0 || t->near_blocks > (1LL << 24)) return PFMM_EINVAL;
+  if (t->fmm_level < 0 || t->fmm_level > FMM_MAX_LEVEL) return PFMM_EINVAL;
   if (t->nufft_grid != p->nu_grid) {
     const int old = p->nu_grid;
     int rc = set_nufft_grid(p, t->nufft_grid);
@@ -678,6 +802,7 @@ int pfmm_plan_set_tuning(pfmm_plan_t p, const pfmm_tuning_t* t) {
     }
   }
   p->tune_near = t->near_blocks;
+  p->tune_fmm_level = t->fmm_level;
   return PFMM_OK;
 }
 
@@ -692,15 +817,23 @@ int pfmm_autotune(pfmm_plan_t p, int64_t ns, const double* src_xy, const double*
   if (rc) return rc;
   const double start_ms = tm;
   int tried = 1;
-  // near field: blocks in flight
+  // near field: blocks in flight, or the FMM tree's leaf level
+  Layout L0;
+  plan_layout(p, ns, nt, L0);
   const bool mutual = p->mutual && p->self_exclude && ns == nt;
   const int64_t near_c[3] = {mutual ? 4096 : 1024, mutual ? 8192 : 2048, mutual ? 16384 : 4096};
   pfmm_tuning_t best = cur;
   double best_near = nm;
-  for (int64_t c : near_c) {
+  for (int k = 0; k < 3; ++k) {
     pfmm_tuning_t t = cur;
-    t.near_blocks = c;
-    if (t.near_blocks == cur.near_blocks) continue;
+    if (L0.fmm) {
+      if (k == 2) break;
+      t.fmm_level = L0.ft.L + (k ? 1 : -1);
+      if (t.fmm_level < 1 || t.fmm_level > FMM_MAX_LEVEL) continue;
+    } else {
+      t.near_blocks = near_c[k];
+      if (t.near_blocks == cur.near_blocks) continue;
+    }
     if ((rc = pfmm_plan_set_tuning(p, &t))) return rc;
     if (cell_workspace(p, ns, nt, 0) > ws_bytes) continue;
     double n1, t1;
@@ -884,7 +1017,8 @@ int pfmm_batch_create(int n_cells, const pfmm_plan_t* plans, const int64_t* src_
     // check_neutral needs a stream synchronisation, which a batch never does;
     // far-only plans have no near tasks; singly periodic cells are not batched
     if (!p || p->precision != p0->precision || p->n_dens != p0->n_dens || p->self_exclude != p0->self_exclude ||
-        (p->kernel == PFMM_STOKES ? 2 : 1) != nc || p->check_neutral || p->near_none || p->periodic != 2)
+        (p->kernel == PFMM_STOKES ? 2 : 1) != nc || p->check_neutral || p->near_none || p->periodic != 2 ||
+        p->near_fmm == 1)
       return PFMM_EINVAL;
     if (src_off[c + 1] < src_off[c] || src_off[c + 1] - src_off[c] > PFMM_MAX_POINTS) return PFMM_EINVAL;
     if (!p0->self_exclude &&

@@ -1,0 +1,60 @@
+// Interpolation FMM for the near part (internal; fmm.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "pfmm_internal.h"
+
+namespace pfmm {
+
+constexpr int FMM_PMAX = 20;          // Chebyshev points per dimension, at most
+constexpr int FMM_MAX_LEVEL = 11;     // deepest leaf level
+constexpr int FMM_CHUNK = 128;        // points per LDS chunk (P2M, leaf kernel)
+#ifndef PFMM_FMM_F32_LEVELS
+#define PFMM_FMM_F32_LEVELS 2
+#endif
+constexpr int FMM_F32_LEVELS = PFMM_FMM_F32_LEVELS;   // mixed: levels (the finest) whose M2L samples the kernel in FP32
+constexpr double FMM_AUTO_PAIRS = 4294967296.0;   // AUTO near mode: FMM from N_S N_T >= 2^32
+constexpr int FMM_AUTO_TOP = 16;      // ... and top grids of at most this many boxes
+
+// The tree: level l has (k1 << l) x (k2 << l) boxes over the cell in lattice
+// coordinates u = (u1, u2) in [-1/2, 1/2)^2 (x = u1 e1 + u2 e2), stored row by
+// row (box = j n1 + i) after the boxes of the coarser levels. The boxes of
+// the image cells m e1 + n e2 are those of the cell shifted by whole cells,
+// so only the cell's own boxes carry expansions.
+struct FmmTree {
+  int P, L, k1, k2, m0;
+  double d, xi, eta;                  // canonical lattice e1 = (d, 0), e2 = (xi, eta)
+  int64_t box_off[FMM_MAX_LEVEL + 2]; // first box of each level; box_off[L + 1] = total
+};
+
+struct FmmArgs {
+  FmmTree t;
+  int n_dens;
+  double beta;
+  double rcut;                        // screened kernel: box pairs farther apart are skipped
+  int64_t n_src, n_trg;
+  const double *sx, *sy;              // sources in leaf-box order (canonical)
+  const double* sq;                   // their densities [n_dens][nc][n_src]
+  const double *tx, *ty;              // targets in leaf-box order
+  const int *scnt, *tcnt;             // sort tables: leaf box k ends at cnt[(k + 1) nblk - 1]
+  int snblk, tnblk;
+  int* scount;                        // sources per box, every level [n_box]
+  double* W;                          // equivalent densities [n_box][n_dens * nc][P^2]
+  double* F;                          // local fields [n_box][n_dens * NOUT][P^2]
+  double* part;                       // near part [n_dens * NOUT][n_trg], leaf-box target order
+};
+
+// the tree for n points: k1 x k2 top boxes and the leaf level from a cost
+// model (pairs of the leaf neighbour sums against the node pairs of the
+// interaction lists)
+void fmm_tree(const pfmm_plan_s* p, int64_t n_src, int64_t n_trg, FmmTree& t);
+inline int64_t fmm_boxes(const FmmTree& t) { return t.box_off[t.L + 1]; }
+// Chebyshev points per dimension for a kernel, precision and tolerance
+int fmm_order(int kernel, int precision, double tol);
+// ev: NULL, or 6 events recorded on s at the stage boundaries (start,
+// upward done, FP64 interaction lists done, FP32 ones done, downward done,
+// leaves done)
+void launch_fmm(int kernel, bool mixed, const FmmArgs& a, hipStream_t s, hipEvent_t* ev = nullptr);
+
+}  // namespace pfmm

@@ -1,0 +1,740 @@
+// Near part by a fast multipole method whose expansions are Chebyshev
+// interpolants, on a tree of boxes in lattice coordinates.
+//
+// The near part of the splitting (Sec. 1, Def. 1) is the free-space sum of
+// the kernel over the sources of the cell and of its images m e1 + n e2,
+// |m| <= m0, |n| <= 1, at targets in the cell. Sec. 7 evaluates it with a
+// free-space FMM over all those sources and notes that the image cells hold
+// the same sources, hence the same hierarchy of expansions. Here that is
+// built in: the tree lives in lattice coordinates u (x = u1 e1 + u2 e2), so a
+// box of an image cell is a box of the cell moved by whole lattice vectors and
+// carries the cell box's expansion unchanged; only the cell's own boxes are
+// stored, and the near region is a (2 m0 + 1) x 3 super-grid of them.
+//
+// Expansions: on a box with local coordinates s in [-1, 1]^2, P x P tensor
+// Chebyshev points s_ab. The far field of the box's sources is represented by
+// equivalent densities W_ab = sum_j q_j l_a(s1_j) l_b(s2_j) at those points
+// (l_a: Lagrange basis), the field of distant boxes at a target box by its
+// samples F_ab at the points, interpolated at the targets. Upward: W of a
+// parent from its children by exact polynomial transfer (M2M); across: F of
+// a box += kernel(point_ab - point_cd) W_cd over its interaction list (the
+// children of the parent's neighbours that are not neighbours, M2L, the
+// kernel sampled on the fly); downward: F of a child += the parent's F
+// interpolated at the child's points (L2L); at the leaves: interpolation of
+// F at every target plus the direct sum over the 3 x 3 neighbouring leaf
+// boxes, images included (P2P). Each of the potential and the gradient
+// components is interpolated as its own field, so the gradient needs no
+// differentiation of an interpolant.
+//
+// Precision: W, F and every sum over boxes in FP64. MIXED: kernel samples in
+// FP32 (M2L on displacements box centre to box centre taken in FP64 plus node
+// offsets, partial sums over one row of P source points flushed to FP64; P2P
+// on displacements taken in FP64 and rounded once, log terms added in FP64
+// pair by pair, the others in FP32 over 16 sources).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <type_traits>
+
+#include "device_math.h"
+#include "fmm.h"
+#include "kernels.h"
+
+namespace pfmm {
+
+namespace {
+
+struct Lvl {
+  int n1, n2;       // boxes along e1, e2
+  double h1, h2;    // lattice half-widths of a box
+};
+__device__ __forceinline__ Lvl level_of(const FmmTree& t, int l) {
+  Lvl v;
+  v.n1 = t.k1 << l;
+  v.n2 = t.k2 << l;
+  v.h1 = 0.5 / v.n1;
+  v.h2 = 0.5 / v.n2;
+  return v;
+}
+__device__ __forceinline__ int floordiv(int a, int b) { return a >= 0 ? a / b : -((b - 1 - a) / b); }
+__device__ __forceinline__ int posmod(int a, int b) { const int r = a % b; return r < 0 ? r + b : r; }
+
+// first and one-past-last sorted index of leaf box k
+__device__ __forceinline__ int64_t leaf_begin(const int* cnt, int nblk, int64_t k) {
+  return k ? cnt[k * nblk - 1] : 0;
+}
+__device__ __forceinline__ int64_t leaf_end(const int* cnt, int nblk, int64_t k) { return cnt[(k + 1) * nblk - 1]; }
+
+// Chebyshev points of the first kind s_a = cos((2a+1) pi / 2P) and their
+// barycentric weights (-1)^a sin((2a+1) pi / 2P)
+__device__ void cheb_init(int P, double* s, double* w) {
+  for (int a = threadIdx.x; a < P; a += blockDim.x) {
+    const double th = (2 * a + 1) * PI / (2 * P);
+    s[a] = cos(th);
+    if (w) w[a] = (a & 1) ? -sin(th) : sin(th);
+  }
+}
+
+// Lagrange basis of the P points at x (barycentric form): out[a * stride]
+__device__ void lagrange(int P, const double* s, const double* w, double x, double* out, int stride) {
+  double sum = 0.0;
+  int hit = -1;
+  for (int a = 0; a < P; ++a) {
+    const double dd = x - s[a];
+    if (dd == 0.0) hit = a;
+    const double t = dd == 0.0 ? 0.0 : w[a] / dd;
+    out[a * stride] = t;
+    sum += t;
+  }
+  const double inv = 1.0 / sum;
+  for (int a = 0; a < P; ++a) out[a * stride] = hit >= 0 ? (a == hit ? 1.0 : 0.0) : out[a * stride] * inv;
+}
+
+// transfer matrices T[h][a][a'] = l_a'((s_a + 2h - 1) / 2): parent basis at
+// the points of child half h (0 lower, 1 upper) of each dimension
+__device__ void transfer_init(int P, const double* s, const double* w, double* T) {
+  for (int r = threadIdx.x; r < 2 * P; r += blockDim.x) {
+    const int h = r / P, a = r % P;
+    lagrange(P, s, w, 0.5 * (s[a] + 2 * h - 1), T + (size_t)r * P, 1);
+  }
+}
+
+// Lagrange basis of the P points at x into registers (entries P.. are zero)
+__device__ __forceinline__ void basis_regs(int P, const double* s, const double* w, double x,
+                                           double (&l)[FMM_PMAX]) {
+  double sum = 0.0;
+  int hit = -1;
+#pragma unroll
+  for (int a = 0; a < FMM_PMAX; ++a) {
+    double t = 0.0;
+    if (a < P) {
+      const double dd = x - s[a];
+      if (dd == 0.0) hit = a;
+      t = dd == 0.0 ? 0.0 : w[a] / dd;
+    }
+    l[a] = t;
+    sum += t;
+  }
+  const double inv = 1.0 / sum;
+#pragma unroll
+  for (int a = 0; a < FMM_PMAX; ++a) l[a] = hit >= 0 ? (a == hit ? 1.0 : 0.0) : l[a] * inv;
+}
+
+template <int K> struct Fk {
+  static constexpr int NC = K == PFMM_STOKES ? 2 : 1;    // density components
+  static constexpr int NO = K == PFMM_STOKES ? 6 : 3;    // outputs
+  static constexpr int NA = K == PFMM_STOKES ? 8 : 3;    // pair accumulators
+};
+
+// One kernel sample (pair displacement dx, dy = target - source) with
+// weights w0 (w1: second Stokes component) into the accumulators:
+//   Laplace: sum w lg, sum w dx/r^2, sum w dy/r^2           (lg = log r^2; log2 in FP32)
+//   Yukawa:  sum w K0(beta r), sum w K1(beta r)/(beta r) dx, ... dy
+//   Stokes:  sum lg w1, sum lg w2, sum c dx, sum c dy, sum c, sum c ia dx,
+//            sum c ia dy, sum (w2 ia - w1 ib);  ia = dx/r^2, ib = dy/r^2,
+//            c = ia w1 + ib w2
+// GUARD: r = 0 contributes nothing (the self pair).
+// LOG64: the log terms are left out of acc and lg is returned instead (the
+// caller adds them in FP64).
+// r2_self replaces r^2 of a guarded pair (its log then equals the caller's
+// log shift, and the shifted log term vanishes).
+template <int K, bool GUARD, bool LOG64, typename real>
+__device__ __forceinline__ void fmm_pair(real dx, real dy, real w0, real w1, real* acc, real beta, real& lg_out,
+                                         real r2_self = (real)1) {
+  constexpr bool F32 = std::is_same<real, float>::value;
+  real r2 = F32 ? __builtin_fmaf(dx, dx, dy * dy) : dx * dx + dy * dy;
+  if constexpr (GUARD) {
+    const bool ok = r2 > (real)0;
+    r2 = ok ? r2 : r2_self;
+    w0 = ok ? w0 : (real)0;
+    w1 = ok ? w1 : (real)0;
+  }
+  if constexpr (K == PFMM_YUKAWA) {
+    lg_out = (real)0;
+    real k0, k1x;
+    if constexpr (F32) bessel_k01_f32_wave(beta * __builtin_amdgcn_sqrtf(r2), k0, k1x);
+    else bessel_k01_f64(beta * sqrt(r2), k0, k1x);
+    acc[0] += w0 * k0;
+    const real g = w0 * k1x;
+    acc[1] += g * dx;
+    acc[2] += g * dy;
+  } else {
+    real lg, inv;
+    if constexpr (F32) {
+      lg = __builtin_amdgcn_logf(r2);
+      inv = __builtin_amdgcn_rcpf(r2);
+    } else {
+      lg = log(r2);
+      inv = 1.0 / r2;
+    }
+    lg_out = lg;
+    if constexpr (K == PFMM_LAPLACE) {
+      if constexpr (!LOG64) acc[0] += w0 * lg;
+      const real g = w0 * inv;
+      acc[1] += g * dx;
+      acc[2] += g * dy;
+    } else {
+      const real ia = inv * dx, ib = inv * dy;
+      const real c = ia * w0 + ib * w1;
+      const real ca = c * ia;
+      if constexpr (!LOG64) { acc[0] += lg * w0; acc[1] += lg * w1; }
+      acc[2] += c * dx; acc[3] += c * dy; acc[4] += c;
+      acc[5] += ca * dx; acc[6] += ca * dy;
+      acc[7] += w1 * ia - w0 * ib;
+    }
+  }
+}
+
+// accumulators -> outputs (potential, gradient; Stokes u1, u2, du1/dx,
+// du1/dy, du2/dx, du2/dy); lscale converts the log base to natural logs
+template <int K>
+__device__ __forceinline__ void fmm_outputs(const double* A, double* o, double beta, double lscale) {
+  const double inv4pi = 1.0 / (4 * PI), inv2pi = 1.0 / (2 * PI);
+  if constexpr (K == PFMM_LAPLACE) {
+    o[0] = -inv4pi * lscale * A[0];
+    o[1] = -inv2pi * A[1];
+    o[2] = -inv2pi * A[2];
+  } else if constexpr (K == PFMM_YUKAWA) {
+    o[0] = inv2pi * A[0];
+    o[1] = -beta * beta * inv2pi * A[1];
+    o[2] = -beta * beta * inv2pi * A[2];
+  } else {
+    // u_i = (1/4pi) sum [-(1/2) log r^2 f_i + (r.f) r_i / r^2]
+    o[0] = inv4pi * (-0.5 * lscale * A[0] + A[2]);
+    o[1] = inv4pi * (-0.5 * lscale * A[1] + A[3]);
+    o[2] = inv4pi * (A[4] - 2 * A[5]);
+    o[3] = inv4pi * (A[7] - 2 * A[6]);
+    o[4] = inv4pi * (-A[7] - 2 * A[6]);
+    o[5] = -o[2];
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// P2M: equivalent densities of each leaf box (grid: leaf boxes x densities)
+// ---------------------------------------------------------------------------
+template <int NC>
+__global__ __launch_bounds__(FMM_CHUNK) void fmm_p2m_kernel(FmmArgs a) {
+  const FmmTree& t = a.t;
+  const int P = t.P, P2 = P * P;
+  const int box = blockIdx.x, v = blockIdx.y, tid = threadIdx.x;
+  const Lvl lv = level_of(t, t.L);
+  const int i = box % lv.n1, j = box / lv.n1;
+  __shared__ double s_s[FMM_PMAX], s_w[FMM_PMAX];
+  __shared__ double s_l1[FMM_PMAX * FMM_CHUNK], s_l2[FMM_PMAX * FMM_CHUNK];
+  __shared__ double s_q[NC][FMM_CHUNK];
+  cheb_init(P, s_s, s_w);
+  const int64_t b0 = leaf_begin(a.scnt, a.snblk, box), b1 = leaf_end(a.scnt, a.snblk, box);
+  double acc[4][NC];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[r][c] = 0.0;
+  __syncthreads();
+  for (int64_t c0 = b0; c0 < b1; c0 += FMM_CHUNK) {
+    const int nch = (int)min((int64_t)FMM_CHUNK, b1 - c0);
+    if (tid < nch) {
+      const int64_t k = c0 + tid;
+      const double u2 = a.sy[k] / t.eta, u1 = (a.sx[k] - t.xi * u2) / t.d;
+      lagrange(P, s_s, s_w, 2.0 * ((u1 + 0.5) * lv.n1 - i) - 1.0, s_l1 + tid, FMM_CHUNK);
+      lagrange(P, s_s, s_w, 2.0 * ((u2 + 0.5) * lv.n2 - j) - 1.0, s_l2 + tid, FMM_CHUNK);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) s_q[c][tid] = a.sq[((size_t)v * NC + c) * a.n_src + k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int node = tid + r * FMM_CHUNK;
+      if (node < P2) {
+        const double* l1 = s_l1 + (node / P) * FMM_CHUNK;
+        const double* l2 = s_l2 + (node % P) * FMM_CHUNK;
+        for (int jj = 0; jj < nch; ++jj) {
+          const double g = l1[jj] * l2[jj];
+#pragma unroll
+          for (int c = 0; c < NC; ++c) acc[r][c] = fma(s_q[c][jj], g, acc[r][c]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  const int64_t gb = t.box_off[t.L] + box;
+  const int qn = a.n_dens * NC;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int node = tid + r * FMM_CHUNK;
+    if (node < P2)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) a.W[((size_t)gb * qn + v * NC + c) * P2 + node] = acc[r][c];
+  }
+  if (tid == 0 && v == 0) a.scount[gb] = (int)(b1 - b0);
+}
+
+// ---------------------------------------------------------------------------
+// M2M: equivalent densities of the boxes of level l from their children
+// (grid: boxes of level l x density components)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void fmm_m2m_kernel(FmmArgs a, int l, int qn) {
+  const FmmTree& t = a.t;
+  const int P = t.P, P2 = P * P;
+  const int box = blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
+  const Lvl lv = level_of(t, l), lc = level_of(t, l + 1);
+  const int i = box % lv.n1, j = box / lv.n1;
+  __shared__ double s_s[FMM_PMAX], s_w[FMM_PMAX];
+  __shared__ double s_T[2 * FMM_PMAX * FMM_PMAX], s_c[FMM_PMAX * FMM_PMAX], s_t[FMM_PMAX * FMM_PMAX];
+  cheb_init(P, s_s, s_w);
+  __syncthreads();
+  transfer_init(P, s_s, s_w, s_T);
+  double acc[2] = {0.0, 0.0};
+  int cnt = 0;
+  for (int h = 0; h < 4; ++h) {
+    const int hi = h & 1, hj = h >> 1;
+    const int64_t cb = t.box_off[l + 1] + (int64_t)(2 * j + hj) * lc.n1 + 2 * i + hi;
+    __syncthreads();
+    for (int n = tid; n < P2; n += 256) s_c[n] = a.W[((size_t)cb * qn + c) * P2 + n];
+    if (tid == 0) cnt += a.scount[cb];
+    __syncthreads();
+    // s_t[a][b'] = sum_b W_child[a][b] T[hj][b][b']
+    for (int n = tid; n < P2; n += 256) {
+      const int ra = n / P, bp = n % P;
+      double s = 0.0;
+      for (int b = 0; b < P; ++b) s = fma(s_c[ra * P + b], s_T[(hj * P + b) * P + bp], s);
+      s_t[n] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int n = tid + 256 * r;
+      if (n < P2) {
+        const int ap = n / P, bp = n % P;
+        double s = 0.0;
+        for (int ra = 0; ra < P; ++ra) s = fma(s_T[(hi * P + ra) * P + ap], s_t[ra * P + bp], s);
+        acc[r] += s;
+      }
+    }
+  }
+  const int64_t gb = t.box_off[l] + box;
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const int n = tid + 256 * r;
+    if (n < P2) a.W[((size_t)gb * qn + c) * P2 + n] = acc[r];
+  }
+  if (tid == 0 && c == 0) a.scount[gb] = cnt;
+}
+
+// ---------------------------------------------------------------------------
+// M2L: local fields of every box of every level from its interaction list
+// (grid: all boxes x densities; block: one thread per Chebyshev point).
+// Level 0 has no parent: its list is every non-neighbouring box of the
+// super-grid.
+// ---------------------------------------------------------------------------
+template <typename real> struct alignas(4 * sizeof(real)) SrcNode { real ox, oy, w0, w1; };
+
+// 2^k with 2^k times a box's width about 1/2 at level l: coordinate
+// differences are scaled by it (exactly) so that the log2 of a typical M2L or
+// neighbour pair's r^2 is near zero, and its FP32 value carries an absolute
+// error of an ulp of a small number; the shift 2k is removed in FP64
+__device__ __forceinline__ int level_shift(const FmmTree& t, int l) {
+  const double h = sqrt(t.d * t.eta / ((double)(t.k1 << l) * (double)(t.k2 << l)));
+  return -(int)lround(log2(2.0 * h));
+}
+
+// MIXED: the FP32 kernel samples (the finest levels); FP64: the coarse levels
+// of a mixed evaluation (their equivalent densities are sums over many
+// sources, too large for FP32 log terms) and every level in FP64 mode. Boxes
+// gb0 + blockIdx.x.
+template <int K, bool MIXED>
+__global__ __launch_bounds__(512) void fmm_m2l_kernel(FmmArgs a, int64_t gb0) {
+  using real = typename std::conditional<MIXED, float, double>::type;
+  constexpr int NC = Fk<K>::NC, NO = Fk<K>::NO, NA = Fk<K>::NA;
+  constexpr bool SHIFT = MIXED && K != PFMM_YUKAWA;     // scaled coordinates, log2 shifted
+  const FmmTree& t = a.t;
+  const int P = t.P, P2 = P * P;
+  const int64_t gb = gb0 + blockIdx.x;
+  const int v = blockIdx.y, tid = threadIdx.x;
+  int l = 0;
+  while (l < t.L && gb >= t.box_off[l + 1]) ++l;
+  const Lvl lv = level_of(t, l);
+  const int box = (int)(gb - t.box_off[l]);
+  const int i = box % lv.n1, j = box / lv.n1;
+  __shared__ double s_s[FMM_PMAX];
+  __shared__ SrcNode<real> s_src[FMM_PMAX * FMM_PMAX];
+  __shared__ double s_wsum[8][NC];
+  cheb_init(P, s_s, nullptr);
+  __syncthreads();
+  const bool act = tid < P2;
+  const int na = act ? tid / P : 0, nb = act ? tid % P : 0;
+  const int ksh = SHIFT ? level_shift(t, l) : 0;
+  const double sc = ldexp(1.0, ksh);
+  // the point's offset from its box centre (the same for every box of the
+  // level), scaled
+  const double ox = sc * (t.d * lv.h1 * s_s[na] + t.xi * lv.h2 * s_s[nb]);
+  const double oy = sc * (t.eta * lv.h2 * s_s[nb]);
+  // circumradius of a box: half its longer diagonal
+  const double rad = 0.5 * fmax(hypot(2 * t.d * lv.h1 + 2 * t.xi * lv.h2, 2 * t.eta * lv.h2),
+                                hypot(-2 * t.d * lv.h1 + 2 * t.xi * lv.h2, 2 * t.eta * lv.h2));
+  const int qn = a.n_dens * NC;
+  const real beta = (real)(a.beta / sc);
+  double acc[NA];
+#pragma unroll
+  for (int c = 0; c < NA; ++c) acc[c] = 0.0;
+  double wtot[NC];                                      // sum of the visited equivalent densities
+#pragma unroll
+  for (int c = 0; c < NC; ++c) wtot[c] = 0.0;
+  const int I0 = -t.m0 * lv.n1, I1 = (t.m0 + 1) * lv.n1, J0 = -lv.n2, J1 = 2 * lv.n2;
+
+  auto visit = [&](int I, int J) {
+    const int64_t sg = t.box_off[l] + (int64_t)posmod(J, lv.n2) * lv.n1 + posmod(I, lv.n1);
+    if (a.scount[sg] == 0) return;                      // uniform over the block
+    // target centre minus source centre (lattice difference of the super-grid)
+    const double du1 = (double)(i - I) / lv.n1, du2 = (double)(j - J) / lv.n2;
+    const double Dx = t.d * du1 + t.xi * du2, Dy = t.eta * du2;
+    if (sqrt(Dx * Dx + Dy * Dy) - 2 * rad > a.rcut) return;
+    __syncthreads();
+    double w[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) w[c] = act ? a.W[((size_t)sg * qn + v * NC + c) * P2 + tid] : 0.0;
+    if (act) {
+      SrcNode<real> sn;
+      sn.ox = (real)ox;
+      sn.oy = (real)oy;
+      sn.w0 = (real)w[0];
+      sn.w1 = NC > 1 ? (real)w[NC - 1] : (real)0;
+      s_src[tid] = sn;
+    }
+    if constexpr (SHIFT) {
+      // the box's total equivalent density (FP64), for the log shift
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        double x = w[c];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+        if ((tid & 63) == 0) s_wsum[tid >> 6][c] = x;
+      }
+    }
+    __syncthreads();
+    if constexpr (SHIFT) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) wtot[c] += s_wsum[q][c];
+    }
+    if (act) {
+      const real ex = (real)(sc * Dx + ox), ey = (real)(sc * Dy + oy);
+      for (int r = 0; r < P; ++r) {
+        real p[NA];
+#pragma unroll
+        for (int c = 0; c < NA; ++c) p[c] = (real)0;
+        for (int c = 0; c < P; ++c) {
+          const SrcNode<real> sn = s_src[r * P + c];
+          real lg;
+          fmm_pair<K, false, false, real>(ex - sn.ox, ey - sn.oy, sn.w0, sn.w1, p, beta, lg);
+        }
+#pragma unroll
+        for (int c = 0; c < NA; ++c) acc[c] += (double)p[c];
+      }
+    }
+  };
+
+  if (l == 0) {
+    for (int J = J0; J < J1; ++J)
+      for (int I = I0; I < I1; ++I)
+        if (abs(I - i) > 1 || abs(J - j) > 1) visit(I, J);
+  } else {
+    const int pi = i >> 1, pj = j >> 1;
+    for (int qj = pj - 1; qj <= pj + 1; ++qj)
+      for (int qi = pi - 1; qi <= pi + 1; ++qi)
+        for (int h = 0; h < 4; ++h) {
+          const int I = 2 * qi + (h & 1), J = 2 * qj + (h >> 1);
+          if (I < I0 || I >= I1 || J < J0 || J >= J1) continue;
+          if (abs(I - i) > 1 || abs(J - j) > 1) visit(I, J);
+        }
+  }
+  if (act) {
+    if constexpr (SHIFT) {
+      // log2 of scaled r^2 = log2 r^2 + 2k; scaled gradient sums carry 2^-k
+#pragma unroll
+      for (int c = 0; c < NC; ++c) acc[c] -= 2.0 * ksh * wtot[c];
+      if constexpr (K == PFMM_LAPLACE) { acc[1] *= sc; acc[2] *= sc; }
+      else { acc[4] *= sc; acc[5] *= sc; acc[6] *= sc; acc[7] *= sc; }
+    }
+    double o[NO];
+    fmm_outputs<K>(acc, o, a.beta, MIXED ? 0.69314718055994530942 : 1.0);
+#pragma unroll
+    for (int c = 0; c < NO; ++c) a.F[((size_t)gb * a.n_dens * NO + v * NO + c) * P2 + tid] = o[c];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// L2L: local fields of the boxes of level l + 1 += their parent's,
+// interpolated (grid: boxes of level l + 1 x output components)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void fmm_l2l_kernel(FmmArgs a, int l, int no_total) {
+  const FmmTree& t = a.t;
+  const int P = t.P, P2 = P * P;
+  const int box = blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
+  const Lvl lc = level_of(t, l + 1), lp = level_of(t, l);
+  const int i = box % lc.n1, j = box / lc.n1;
+  const int hi = i & 1, hj = j & 1;
+  __shared__ double s_s[FMM_PMAX], s_w[FMM_PMAX];
+  __shared__ double s_T[2 * FMM_PMAX * FMM_PMAX], s_p[FMM_PMAX * FMM_PMAX], s_t[FMM_PMAX * FMM_PMAX];
+  cheb_init(P, s_s, s_w);
+  __syncthreads();
+  transfer_init(P, s_s, s_w, s_T);
+  const int64_t pg = t.box_off[l] + (int64_t)(j >> 1) * lp.n1 + (i >> 1);
+  const int64_t cg = t.box_off[l + 1] + box;
+  for (int n = tid; n < P2; n += 256) s_p[n] = a.F[((size_t)pg * no_total + c) * P2 + n];
+  __syncthreads();
+  // s_t[a'][b] = sum_b' F_parent[a'][b'] T[hj][b][b']
+  for (int n = tid; n < P2; n += 256) {
+    const int ap = n / P, b = n % P;
+    double s = 0.0;
+    for (int bp = 0; bp < P; ++bp) s = fma(s_p[ap * P + bp], s_T[(hj * P + b) * P + bp], s);
+    s_t[n] = s;
+  }
+  __syncthreads();
+  for (int n = tid; n < P2; n += 256) {
+    const int ra = n / P, b = n % P;
+    double s = 0.0;
+    for (int ap = 0; ap < P; ++ap) s = fma(s_T[(hi * P + ra) * P + ap], s_t[ap * P + b], s);
+    a.F[((size_t)cg * no_total + c) * P2 + n] += s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Leaves: the local field interpolated at each target plus the direct sum over
+// the 3 x 3 neighbouring leaf boxes with their image shifts (grid: leaf boxes
+// x densities; targets of a box in chunks of FMM_CHUNK)
+// ---------------------------------------------------------------------------
+template <int K, bool MIXED>
+__global__ __launch_bounds__(FMM_CHUNK) void fmm_leaf_kernel(FmmArgs a) {
+  using real = typename std::conditional<MIXED, float, double>::type;
+  constexpr int NC = Fk<K>::NC, NO = Fk<K>::NO, NA = Fk<K>::NA;
+  constexpr int NLOG = (K != PFMM_YUKAWA && MIXED) ? NC : 0;   // log terms summed in FP64 per pair
+  const FmmTree& t = a.t;
+  const int P = t.P, P2 = P * P;
+  const int box = blockIdx.x, v = blockIdx.y, tid = threadIdx.x;
+  const Lvl lv = level_of(t, t.L);
+  const int i = box % lv.n1, j = box / lv.n1;
+  const int64_t gb = t.box_off[t.L] + box;
+  const int64_t t0 = leaf_begin(a.tcnt, a.tnblk, box), t1 = leaf_end(a.tcnt, a.tnblk, box);
+  if (t0 >= t1) return;                                   // uniform over the block
+  __shared__ double s_s[FMM_PMAX], s_w[FMM_PMAX];
+  __shared__ double s_F[6 * FMM_PMAX * FMM_PMAX];
+  __shared__ double s_x[FMM_CHUNK], s_y[FMM_CHUNK], s_q[NC][FMM_CHUNK];
+  cheb_init(P, s_s, s_w);
+  for (int n = tid; n < NO * P2; n += FMM_CHUNK)
+    s_F[n] = a.F[((size_t)gb * a.n_dens * NO + v * NO) * P2 + n];
+  __syncthreads();
+  const real beta = (real)a.beta;
+  // mixed Laplace/Stokes: differences scaled by 2^k (as in the M2L) so that
+  // the FP32 log2 of r^2 is near zero; its shift 2k is removed in FP64
+  const int ksh = NLOG > 0 ? level_shift(t, t.L) : 0;
+  const double sc = ldexp(1.0, ksh);
+  const real r2_self = (real)ldexp(1.0, 2 * ksh);
+  for (int64_t tc = t0; tc < t1; tc += FMM_CHUNK) {
+    const int64_t k = tc + tid;
+    const bool act = k < t1;
+    const double tx = act ? a.tx[k] : 0.0, ty = act ? a.ty[k] : 0.0;
+    // interpolated local field
+    double o[NO];
+#pragma unroll
+    for (int c = 0; c < NO; ++c) o[c] = 0.0;
+    if (act) {
+      const double u2 = ty / t.eta, u1 = (tx - t.xi * u2) / t.d;
+      const double x1 = 2.0 * ((u1 + 0.5) * lv.n1 - i) - 1.0, x2 = 2.0 * ((u2 + 0.5) * lv.n2 - j) - 1.0;
+      // basis in the second dimension in registers, the first on the fly
+      double l2[FMM_PMAX];
+      basis_regs(P, s_s, s_w, x2, l2);
+      double sum1 = 0.0;
+      int hit1 = -1;
+      for (int ra = 0; ra < P; ++ra) {
+        const double dd = x1 - s_s[ra];
+        if (dd == 0.0) hit1 = ra;
+        sum1 += dd == 0.0 ? 0.0 : s_w[ra] / dd;
+      }
+      const double inv1 = 1.0 / sum1;
+      for (int ra = 0; ra < P; ++ra) {
+        double row[NO];
+#pragma unroll
+        for (int c = 0; c < NO; ++c) row[c] = 0.0;
+#pragma unroll
+        for (int b = 0; b < FMM_PMAX; ++b)
+          if (b < P)
+#pragma unroll
+            for (int c = 0; c < NO; ++c) row[c] = fma(l2[b], s_F[c * P2 + ra * P + b], row[c]);
+        const double dd = x1 - s_s[ra];
+        const double la = hit1 >= 0 ? (ra == hit1 ? 1.0 : 0.0) : s_w[ra] / dd * inv1;
+#pragma unroll
+        for (int c = 0; c < NO; ++c) o[c] = fma(la, row[c], o[c]);
+      }
+    }
+    // direct sum over the neighbouring leaf boxes
+    double acc[NA];
+#pragma unroll
+    for (int c = 0; c < NA; ++c) acc[c] = 0.0;
+    for (int nbh = 0; nbh < 9; ++nbh) {
+      const int I = i + nbh % 3 - 1, J = j + nbh / 3 - 1;
+      const int m = floordiv(I, lv.n1), n = floordiv(J, lv.n2);
+      const int64_t sb = (int64_t)posmod(J, lv.n2) * lv.n1 + posmod(I, lv.n1);
+      const double shx = m * t.d + n * t.xi, shy = n * t.eta;
+      const int64_t s0 = leaf_begin(a.scnt, a.snblk, sb), s1 = leaf_end(a.scnt, a.snblk, sb);
+      for (int64_t c0 = s0; c0 < s1; c0 += FMM_CHUNK) {
+        const int nch = (int)min((int64_t)FMM_CHUNK, s1 - c0);
+        __syncthreads();
+        if (tid < nch) {
+          s_x[tid] = a.sx[c0 + tid] + shx;
+          s_y[tid] = a.sy[c0 + tid] + shy;
+#pragma unroll
+          for (int c = 0; c < NC; ++c) s_q[c][tid] = a.sq[((size_t)v * NC + c) * a.n_src + c0 + tid];
+        }
+        __syncthreads();
+        for (int j0 = 0; j0 < nch; j0 += 16) {
+          const int j1 = min(nch, j0 + 16);
+          real p[NA];
+#pragma unroll
+          for (int c = 0; c < NA; ++c) p[c] = (real)0;
+          for (int jj = j0; jj < j1; ++jj) {
+            const real dx = (real)(sc * (tx - s_x[jj])), dy = (real)(sc * (ty - s_y[jj]));
+            const real w0 = (real)s_q[0][jj], w1 = NC > 1 ? (real)s_q[NC - 1][jj] : (real)0;
+            real lg;
+            fmm_pair<K, true, (NLOG > 0), real>(dx, dy, w0, w1, p, beta, lg, r2_self);
+            if constexpr (NLOG > 0) {   // log terms straight into FP64 (the self pair gives 0)
+              const double lgs = (double)lg - 2.0 * ksh;
+              acc[0] = fma(s_q[0][jj], lgs, acc[0]);
+              if constexpr (NC > 1) acc[1] = fma(s_q[NC - 1][jj], lgs, acc[1]);
+            }
+          }
+#pragma unroll
+          for (int c = NLOG; c < NA; ++c) acc[c] += (double)p[c];
+        }
+      }
+    }
+    if (act) {
+      if constexpr (NLOG > 0) {
+        if constexpr (K == PFMM_LAPLACE) { acc[1] *= sc; acc[2] *= sc; }
+        else { acc[4] *= sc; acc[5] *= sc; acc[6] *= sc; acc[7] *= sc; }
+      }
+      double d[NO];
+      fmm_outputs<K>(acc, d, a.beta, MIXED ? 0.69314718055994530942 : 1.0);
+#pragma unroll
+      for (int c = 0; c < NO; ++c) a.part[((size_t)v * NO + c) * a.n_trg + k] = o[c] + d[c];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+int fmm_order(int kernel, int precision, double tol) {
+  // interpolation error of the near part measured against its direct sum
+  // (uniform points, hexagonal cell, the worst of the cells tried): about
+  // 1.5e-6 (Laplace, Yukawa) and 1e-5 (Stokes) at P = 8, falling by 4.5 and
+  // 3.7 per added point; P is taken so that it stays below tol / 10
+  (void)precision;
+  const double e8 = kernel == PFMM_STOKES ? 1.0e-5 : 1.5e-6;
+  const double rate = kernel == PFMM_STOKES ? 3.7 : 4.5;
+  const double need = std::log(e8 / (0.1 * tol)) / std::log(rate);
+  int P = 8 + (int)std::ceil(std::max(need, -4.0));
+  return std::min(std::max(P, 4), FMM_PMAX);
+}
+
+void fmm_tree(const pfmm_plan_s* p, int64_t ns, int64_t nt, FmmTree& t) {
+  const Geometry& g = p->geo;
+  t.P = p->fmm_order;
+  t.d = g.d; t.xi = g.xi; t.eta = g.eta;
+  t.m0 = p->m0;
+  // top grid k1 x k2 with boxes about as long along e1 as along e2 (the
+  // interpolation error grows with the boxes' aspect ratio): the fewest top
+  // boxes whose sides differ by at most 10 %, else the closest with at most
+  // 128 of them
+  const double r = g.d / std::hypot(g.xi, g.eta);
+  double best_dev = 1e300;
+  t.k1 = t.k2 = 1;
+  for (int n = 1; n <= 128; ++n)
+    for (int k2 = 1; k2 <= n; ++k2) {
+      if (n % k2) continue;
+      const int k1 = n / k2;
+      const double dev = std::fabs(std::log(r * k2 / k1));
+      if (dev < best_dev - 1e-12) { best_dev = dev; t.k1 = k1; t.k2 = k2; }
+    }
+  for (int n = 1; n <= 128; ++n) {
+    bool found = false;
+    for (int k2 = 1; k2 <= n && !found; ++k2) {
+      if (n % k2) continue;
+      const int k1 = n / k2;
+      if (std::fabs(std::log(r * k2 / k1)) <= std::log(1.1)) { t.k1 = k1; t.k2 = k2; found = true; }
+    }
+    if (found) break;
+  }
+  // leaf level: neighbour pairs 9 ns nt / boxes against node pairs 27 P^4
+  // per box (level 0: every non-neighbour of the super-grid)
+  const double P4 = std::pow((double)t.P, 4);
+  const double top = (double)t.k1 * t.k2;
+  const double lvl0 = top * std::max(0.0, 3.0 * (2 * t.m0 + 1) * top - 9.0) * P4;
+  double best = 0;
+  int bestL = 0;
+  for (int L = 0; L <= FMM_MAX_LEVEL; ++L) {
+    const double leaves = top * std::pow(4.0, L);
+    if (leaves > 4.0e6) break;
+    double m2l = lvl0;
+    for (int l = 1; l <= L; ++l) m2l += 27.0 * top * std::pow(4.0, l) * P4;
+    const double cost = 9.0 * (double)ns * (double)nt / leaves + m2l;
+    if (L == 0 || cost < best) { best = cost; bestL = L; }
+  }
+  t.L = bestL;
+  if (p->tune_fmm_level > 0) {
+    t.L = p->tune_fmm_level;
+    while (t.L > 0 && top * std::pow(4.0, t.L) > 4.0e6) --t.L;
+  }
+  int64_t off = 0;
+  for (int l = 0; l <= t.L; ++l) {
+    t.box_off[l] = off;
+    off += ((int64_t)t.k1 << l) * ((int64_t)t.k2 << l);
+  }
+  t.box_off[t.L + 1] = off;
+}
+
+template <int K, bool MIXED>
+static void launch_fmm_t(const FmmArgs& a, hipStream_t s, hipEvent_t* ev) {
+  constexpr int NC = Fk<K>::NC, NO = Fk<K>::NO;
+  const FmmTree& t = a.t;
+  const int64_t nleaf = t.box_off[t.L + 1] - t.box_off[t.L];
+  auto mark = [&](int k) { if (ev) (void)hipEventRecord(ev[k], s); };
+  mark(0);
+  hipLaunchKernelGGL(fmm_p2m_kernel<NC>, dim3((unsigned)nleaf, a.n_dens), dim3(FMM_CHUNK), 0, s, a);
+  for (int l = t.L - 1; l >= 0; --l) {
+    const int64_t nb = t.box_off[l + 1] - t.box_off[l];
+    hipLaunchKernelGGL(fmm_m2m_kernel, dim3((unsigned)nb, a.n_dens * NC), dim3(256), 0, s, a, l, a.n_dens * NC);
+  }
+  mark(1);
+  const int threads = (t.P * t.P + 63) / 64 * 64;
+  // mixed: FP32 kernel samples on the two finest levels, FP64 above them
+  const int64_t split = MIXED ? t.box_off[std::max(0, t.L - FMM_F32_LEVELS + 1)] : fmm_boxes(t);
+  if (split > 0)
+    hipLaunchKernelGGL((fmm_m2l_kernel<K, false>), dim3((unsigned)split, a.n_dens), dim3(threads), 0, s, a,
+                       (int64_t)0);
+  mark(2);
+  if (fmm_boxes(t) > split)
+    hipLaunchKernelGGL((fmm_m2l_kernel<K, true>), dim3((unsigned)(fmm_boxes(t) - split), a.n_dens), dim3(threads), 0,
+                       s, a, split);
+  mark(3);
+  for (int l = 0; l < t.L; ++l) {
+    const int64_t nb = t.box_off[l + 2] - t.box_off[l + 1];
+    hipLaunchKernelGGL(fmm_l2l_kernel, dim3((unsigned)nb, a.n_dens * NO), dim3(256), 0, s, a, l, a.n_dens * NO);
+  }
+  mark(4);
+  hipLaunchKernelGGL((fmm_leaf_kernel<K, MIXED>), dim3((unsigned)nleaf, a.n_dens), dim3(FMM_CHUNK), 0, s, a);
+  mark(5);
+}
+
+void launch_fmm(int kernel, bool mixed, const FmmArgs& a, hipStream_t s, hipEvent_t* ev) {
+  if (a.n_trg <= 0) return;
+  if (kernel == PFMM_LAPLACE)
+    mixed ? launch_fmm_t<PFMM_LAPLACE, true>(a, s, ev) : launch_fmm_t<PFMM_LAPLACE, false>(a, s, ev);
+  else if (kernel == PFMM_YUKAWA)
+    mixed ? launch_fmm_t<PFMM_YUKAWA, true>(a, s, ev) : launch_fmm_t<PFMM_YUKAWA, false>(a, s, ev);
+  else mixed ? launch_fmm_t<PFMM_STOKES, true>(a, s, ev) : launch_fmm_t<PFMM_STOKES, false>(a, s, ev);
+}
+
+}  // namespace pfmm

@@ -97,6 +97,8 @@ struct SortArgs {
   int *key, *cnt, *perm;     // cnt: [bin][block] counts, then their exclusive prefix
   int* seg;                  // scratch: one int per SCAN_SEG entries of cnt
   double *sx, *sy;           // binned copies
+  int lattice;               // 1: bins are nbx x nby boxes in lattice coordinates of the
+  double d, xi, eta;         //    canonical cell (u2 = y / eta, u1 = (x - xi u2) / d), row by row
 };
 
 constexpr int SCAN_SEG = 4096;   // entries of the bin-count table per scan block
@@ -126,7 +128,6 @@ struct FarDArgs {
 
 struct FarLArgs {
   int kernel, n_sn, n_ew, ncw, n_coef, n_dens, n_splits, nufft;
-  int mixed;                 // plane-wave factors in FP32 (phases reduced in FP64)
   int64_t n_trg;
   double d, eta, rc, rs;
   double ew_c, ew_s;         // canonical -> west/east frame rotation

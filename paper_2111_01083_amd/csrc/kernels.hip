@@ -90,10 +90,19 @@ __global__ void fill_double_kernel(double* p, int64_t n) {
 __global__ void bin_count_kernel(SortArgs a) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
-  int bx = (int)floor((a.x[i] - a.x0) * a.inv_w), by = (int)floor((a.y[i] - a.y0) * a.inv_h);
+  int bx, by;
+  if (a.lattice) {
+    const double u2 = a.y[i] / a.eta, u1 = (a.x[i] - a.xi * u2) / a.d;
+    bx = (int)floor((u1 + 0.5) * a.nbx);
+    by = (int)floor((u2 + 0.5) * a.nby);
+  } else {
+    bx = (int)floor((a.x[i] - a.x0) * a.inv_w);
+    by = (int)floor((a.y[i] - a.y0) * a.inv_h);
+  }
   bx = min(max(bx, 0), a.nbx - 1);
   by = min(max(by, 0), a.nby - 1);
-  int key = by * a.nbx + ((by & 1) ? (a.nbx - 1 - bx) : bx);   // boustrophedon rows
+  // boustrophedon rows (lattice boxes: plain rows)
+  int key = by * a.nbx + ((by & 1) && !a.lattice ? (a.nbx - 1 - bx) : bx);
   if (!PFMM_NEAR_BIN) key = 0;
   a.key[i] = key;
   // lanes with equal (key, block) add once for all of them: clustered points
@@ -1538,24 +1547,17 @@ void launch_far_D(const FarDArgs& a, hipStream_t s) {
 //   Stokes: the same waves times (A - y B) (south/north) or (A - x X)
 //   (west/east); m = 0 acts on u1 only, like Laplace with q = f1.
 // ---------------------------------------------------------------------------
-// e^{i phase} and e^{+-expo} of one plane wave: in FP64, or (MIXED) in FP32
-// after reducing the phase modulo 2 pi in FP64
-template <bool MIXED>
+// e^{i phase} and e^{+-expo} of one plane wave, in FP64 in both precisions:
+// the far field is a sum of such waves that cancels much of the near part,
+// so FP32 factors (about 1e-7 each) would show as a 1e-6 relative error of a
+// Laplace or Stokes potential, at about 1 % of an evaluation's time
 __device__ __forceinline__ void wave_factors(double phase, double expo, double& sn, double& cs, double& ep, double& em) {
-  if constexpr (MIXED) {
-    const double r = phase - 2 * PI * rint(phase * (0.5 / PI));
-    float sf, cf;
-    sincosf((float)r, &sf, &cf);
-    const float e = expf((float)expo);
-    sn = sf; cs = cf; ep = e; em = 1.0f / e;
-  } else {
-    sincos(phase, &sn, &cs);
-    ep = exp(expo);
-    em = 1.0 / ep;
-  }
+  sincos(phase, &sn, &cs);
+  ep = exp(expo);
+  em = 1.0 / ep;
 }
 
-template <int K, bool MIXED, int DG>
+template <int K, int DG>
 __global__ __launch_bounds__(256) void far_L_kernel(FarLArgs a) {
   constexpr int NO = (K == PFMM_STOKES) ? 6 : 3;
   constexpr int NCW = (K == PFMM_STOKES) ? 8 : 2;
@@ -1578,7 +1580,7 @@ __global__ __launch_bounds__(256) void far_L_kernel(FarLArgs a) {
       for (int m = 0; m < a.n_sn; ++m) {
         const double al = sn_tab[m * SN_REC], aa = sn_tab[m * SN_REC + 1];
         double sn, cs, ep, em;
-        wave_factors<MIXED>(al * x, aa * y, sn, cs, ep, em);
+        wave_factors(al * x, aa * y, sn, cs, ep, em);
         const cplx ph = {cs, sn};
 #pragma unroll
         for (int d = 0; d < DG; ++d) {
@@ -1618,7 +1620,7 @@ __global__ __launch_bounds__(256) void far_L_kernel(FarLArgs a) {
     for (int kk = 0; kk < a.n_ew; ++kk) {
       const double lam = ew_tab[kk * EW_REC], kap = ew_tab[kk * EW_REC + 1];
       double sn, cs, ep, em;
-      wave_factors<MIXED>(lam * ye, kap * xe, sn, cs, ep, em);
+      wave_factors(lam * ye, kap * xe, sn, cs, ep, em);
       const double ch = 0.5 * (ep + em), sh = 0.5 * (ep - em);
       const cplx ph = {cs, sn};
 #pragma unroll
@@ -1717,19 +1719,13 @@ void launch_far_L(const FarLArgs& a, hipStream_t s) {
   dim3 grid((unsigned)((a.n_trg + 255) / 256));
   // densities per pass: 1, or a group that shares every plane-wave factor
   const bool grp = a.n_dens > 1;
-  switch ((a.kernel * 2 + (a.mixed ? 1 : 0)) * 2 + (grp ? 1 : 0)) {
-    case 0: hipLaunchKernelGGL((far_L_kernel<PFMM_LAPLACE, false, 1>), grid, dim3(256), 0, s, a); break;
-    case 1: hipLaunchKernelGGL((far_L_kernel<PFMM_LAPLACE, false, 4>), grid, dim3(256), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((far_L_kernel<PFMM_LAPLACE, true, 1>), grid, dim3(256), 0, s, a); break;
-    case 3: hipLaunchKernelGGL((far_L_kernel<PFMM_LAPLACE, true, 4>), grid, dim3(256), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((far_L_kernel<PFMM_YUKAWA, false, 1>), grid, dim3(256), 0, s, a); break;
-    case 5: hipLaunchKernelGGL((far_L_kernel<PFMM_YUKAWA, false, 4>), grid, dim3(256), 0, s, a); break;
-    case 6: hipLaunchKernelGGL((far_L_kernel<PFMM_YUKAWA, true, 1>), grid, dim3(256), 0, s, a); break;
-    case 7: hipLaunchKernelGGL((far_L_kernel<PFMM_YUKAWA, true, 4>), grid, dim3(256), 0, s, a); break;
-    case 8: hipLaunchKernelGGL((far_L_kernel<PFMM_STOKES, false, 1>), grid, dim3(256), 0, s, a); break;
-    case 9: hipLaunchKernelGGL((far_L_kernel<PFMM_STOKES, false, 2>), grid, dim3(256), 0, s, a); break;
-    case 10: hipLaunchKernelGGL((far_L_kernel<PFMM_STOKES, true, 1>), grid, dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL((far_L_kernel<PFMM_STOKES, true, 2>), grid, dim3(256), 0, s, a); break;
+  switch (a.kernel * 2 + (grp ? 1 : 0)) {
+    case 0: hipLaunchKernelGGL((far_L_kernel<PFMM_LAPLACE, 1>), grid, dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((far_L_kernel<PFMM_LAPLACE, 4>), grid, dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((far_L_kernel<PFMM_YUKAWA, 1>), grid, dim3(256), 0, s, a); break;
+    case 3: hipLaunchKernelGGL((far_L_kernel<PFMM_YUKAWA, 4>), grid, dim3(256), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((far_L_kernel<PFMM_STOKES, 1>), grid, dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL((far_L_kernel<PFMM_STOKES, 2>), grid, dim3(256), 0, s, a); break;
   }
 }
 

@@ -78,6 +78,9 @@ struct pfmm_plan_s {
   int kernel, precision, far_mode, m0, n_dens, self_exclude, check_neutral, profile;
   int mutual;                  // near field by symmetric pair evaluation (self targets)
   int near_none;               // far part only (near images left out)
+  int near_fmm;                // near part by the FMM: 0 never, 1 always (P2), 2 for large N (AUTO)
+  int fmm_order;               // its Chebyshev points per box dimension
+  int tune_fmm_level;          // its leaf level (0: cost model)
   double beta, tol, eps;
   pfmm::Geometry geo;
   int M, m_lo, n_sn;           // south/north modes m = m_lo..M
@@ -108,6 +111,7 @@ struct pfmm_plan_s {
   size_t tab_doubles;
   // profiling: event triples (start, near done, end) of evaluations not yet read
   std::vector<void*> prof_events;
+  std::vector<void*> prof_fmm_events;   // FMM near part: 6 events per evaluation (stage boundaries)
   // Stokes plans: a Laplace plan of the same lattice and options with 2 n_dens
   // density vectors, whose gradients give the pressure (pressure.hip)
   pfmm_plan_s* lap = nullptr;

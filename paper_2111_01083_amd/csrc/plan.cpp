@@ -7,6 +7,7 @@
 #include <cstring>
 
 #include "pfmm_internal.h"
+#include "fmm.h"
 
 namespace pfmm {
 
@@ -539,10 +540,13 @@ int build_plan(int kernel, const double* e1, const double* e2, double tol, const
   p->self_exclude = o.self_exclude ? 1 : 0;
   p->check_neutral = o.check_neutral ? 1 : 0;
   p->profile = o.profile ? 1 : 0;
-  if (o.near_mode < 0 || o.near_mode > 3) return PFMM_EINVAL;
+  if (o.near_mode < 0 || o.near_mode > 4) return PFMM_EINVAL;
   if (o.near_mode == PFMM_NEAR_MUTUAL && !o.self_exclude) return PFMM_EINVAL;
+  if (o.near_mode == PFMM_NEAR_FMM && o.periodic == 1) return PFMM_EINVAL;   // the FMM tree needs both periods
   p->near_none = o.near_mode == PFMM_NEAR_NONE ? 1 : 0;
   p->mutual = (o.near_mode != PFMM_NEAR_ONE_SIDED && !p->near_none && o.self_exclude) ? 1 : 0;
+  p->near_fmm = o.near_mode == PFMM_NEAR_FMM ? 1 : (o.near_mode == PFMM_NEAR_AUTO ? 2 : 0);
+  p->fmm_order = fmm_order(kernel, o.precision, tol);
   p->beta = kernel == PFMM_YUKAWA ? o.beta : 0.0;
   p->tol = tol;
   p->eps = tol / 10;

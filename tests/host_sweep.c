@@ -59,6 +59,7 @@ int main(void) {
     o.self_exclude = (it / 7) % 2;
     o.m_gl = ((it / 11) % 3) * 8;
     o.near_mode = o.self_exclude ? (it / 13) % 3 : (it / 13) % 2;
+    if ((it / 5) % 4 == 0) o.near_mode = PFMM_NEAR_FMM;
     tol = pow(10.0, -2.0 - 12.0 * urand(&seed));
     if (it % 97 == 0) tol = 0.5;
 
@@ -73,6 +74,7 @@ int main(void) {
     if (pfmm_plan_get_info(p, &inf)) FAIL("info");
     if (!(inf.d > 0 && inf.eta > 0 && fabs(inf.xi) <= 0.5 * inf.d * (1 + 1e-12))) FAIL("canonical lattice");
     if (inf.n_images != 3 * (2 * inf.m0 + 1)) FAIL("image count");
+    if (o.near_mode == PFMM_NEAR_FMM && (inf.fmm_order < 4 || inf.fmm_order > 20)) FAIL("fmm order");
     x = malloc(sizeof(double) * (inf.n_quad + 1));
     w = malloc(sizeof(double) * (inf.n_quad + 1));
     if (pfmm_plan_get_quadrature(p, x, w)) FAIL("quadrature");

@@ -39,22 +39,26 @@ def test_nufft_doubled_grid_keeps_accuracy(env, kernel, prec, tol, bar):
     check(bar, (pot.cpu().numpy(), po), (grad.cpu().numpy(), go), label=f"doubled grid {kernel} {prec}")
 
 
-@pytest.mark.parametrize("cell,kernel,beta,far", [(((1.0, 0.0), (0.0, 1.0)), "yukawa", 10.0, "auto"),
-                                                  (((100.0, 0.0), (0.0, 1.0)), "laplace", 0.0, "nufft")])
-def test_autotune_result_and_reuse(env, cell, kernel, beta, far):
+@pytest.mark.parametrize("cell,kernel,beta,far,near,n", [
+    (((1.0, 0.0), (0.0, 1.0)), "yukawa", 10.0, "auto", "auto", 20000),
+    (((100.0, 0.0), (0.0, 1.0)), "laplace", 0.0, "nufft", "auto", 20000),
+    (((1.0, 0.0), (0.3, 1.0)), "yukawa", 10.0, "auto", "fmm", 100000)])
+def test_autotune_result_and_reuse(env, cell, kernel, beta, far, near, n):
+    # the FMM plan: the candidates are the leaf levels next to the cost model's
     P, torch, dev = env
     e1, e2 = cell
-    n = 20000
     rng = np.random.default_rng(2)
     src = W.blob_points(rng, e1, e2, n) if far == "nufft" else W.cell_points(rng, e1, e2, n)
     q = W.neutral_charges(rng, n)
-    plan = P.Plan(kernel, e1, e2, 1e-6, beta=beta, precision="mixed", far_mode=far, self_exclude=True)
+    plan = P.Plan(kernel, e1, e2, 1e-6, beta=beta, precision="mixed", far_mode=far, self_exclude=True,
+                  near_mode=near)
     ds, dq = torch.tensor(src, device=dev), torch.tensor(q, device=dev)
-    print(f"case autotune {kernel} {far}", flush=True)
+    print(f"case autotune {kernel} {far} {near}", flush=True)
     rep, pot, grad = P.pfmm_autotune(plan, ds, dq)
     assert rep["n_tried"] >= 3 and rep["best_ms"] > 0
     assert rep["best_ms"] <= 1.10 * rep["default_ms"]
     assert rep["near_blocks"] in (4096, 8192, 16384, 0)
+    assert 0 <= rep["fmm_level"] <= 11 and (near == "fmm" or rep["fmm_level"] == 0)
     pot = pot[0].cpu().numpy(); grad = grad[0].cpu().numpy()
     p2, g2 = plan(ds, dq)
     assert rel(p2.cpu().numpy(), pot) < 1e-12 and rel(g2.cpu().numpy(), grad) < 1e-12

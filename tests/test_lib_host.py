@@ -299,10 +299,10 @@ def test_sizes_beyond_the_point_limit_are_rejected_before_any_launch(P):
 def test_tuning_get_set_and_nufft_grid(P):
     plan = P.Plan("laplace", (100.0, 0.0), (0.0, 1.0), 1e-6, far_mode="nufft")
     nf0, w0 = plan.info["nufft_nf"], plan.info["nufft_w"]
-    assert plan.tuning == {"near_blocks": 0, "nufft_grid": 0}
+    assert plan.tuning == {"near_blocks": 0, "nufft_grid": 0, "fmm_level": 0}
     assert nf0 >= 2 * (2 * plan.info["n_modes"] + 1) and nf0 & (nf0 - 1) == 0
     plan.set_tuning(near_blocks=4096, nufft_grid=1)
-    assert plan.tuning == {"near_blocks": 4096, "nufft_grid": 1}
+    assert plan.tuning == {"near_blocks": 4096, "nufft_grid": 1, "fmm_level": 0}
     assert plan.info["nufft_nf"] == 2 * nf0 and plan.info["nufft_w"] == max(4, w0 - 1)
     plan.set_tuning(nufft_grid=0)
     assert plan.info["nufft_nf"] == nf0 and plan.info["nufft_w"] == w0
@@ -433,3 +433,55 @@ def test_spread_kernel_polynomials_match_the_kernel(P, cell, tol, grid):
         exact = np.where(np.abs(z) < 1, np.exp(b * (np.sqrt(np.clip(1 - z * z, 0, None)) - 1)), 0.0)
         approx = np.polynomial.polynomial.polyval(u, coef[t, :deg])
         assert np.abs(approx - exact).max() < 0.5 * eps, (t, np.abs(approx - exact).max())
+
+
+def test_fmm_plan_options_and_workspace(P):
+    # the FMM near part: Chebyshev order from the kernel and tolerance, only
+    # for doubly periodic plans, leaf level as a tuning with its workspace
+    cell = ((1.0, 0.0), (0.3, 1.0))
+    orders = {}
+    for k in ("laplace", "yukawa", "stokes"):
+        for tol in (1e-3, 1e-6, 1e-10):
+            orders[k, tol] = P.Plan(k, *cell, tol, beta=2.0, near_mode="fmm").info["fmm_order"]
+    for k in ("laplace", "yukawa", "stokes"):
+        assert 4 <= orders[k, 1e-3] < orders[k, 1e-6] < orders[k, 1e-10] <= 20
+    assert orders["stokes", 1e-6] > orders["laplace", 1e-6] == orders["yukawa", 1e-6]
+    assert P.Plan("laplace", *cell, 1e-6, near_mode="one_sided").info["fmm_order"] == 0
+    with pytest.raises(P.PfmmError):
+        P.Plan("laplace", *cell, 1e-6, near_mode="fmm", periodic=1)
+    plan = P.Plan("stokes", *cell, 1e-6, near_mode="fmm", self_exclude=True, precision="mixed")
+    n = 50000
+    ws = {}
+    for lv in (2, 4, 6):
+        plan.set_tuning(fmm_level=lv)
+        assert plan.tuning["fmm_level"] == lv
+        ws[lv] = P.pfmm_workspace_bytes(plan, n, n)
+    # expansions: P^2 (2 + 6) doubles per box, (4^(L+1) - 1) / 3 boxes
+    P2 = plan.info["fmm_order"] ** 2
+    assert ws[6] - ws[4] >= 8 * P2 * 8 * ((4 ** 7 - 4 ** 5) // 3)
+    assert ws[2] < ws[4] < ws[6]
+    with pytest.raises(P.PfmmError):
+        plan.set_tuning(fmm_level=12)
+    plan.set_tuning(fmm_level=0)
+    # forced levels deeper than the cap (4e6 leaves) are cut back, not refused
+    plan.set_tuning(fmm_level=11)
+    assert P.pfmm_workspace_bytes(plan, 10, 10) > 0
+    assert plan.fmm_tree(10)["level"] <= 10
+    plan.set_tuning(fmm_level=0)
+    # the cost model deepens the tree with N; AUTO takes the FMM from
+    # N_S N_T >= 2^32 on cells with at most 16 top boxes, never for P1
+    t1, t2 = plan.fmm_tree(20000), plan.fmm_tree(2000000)
+    assert t2["level"] > t1["level"] and t1["order"] == plan.info["fmm_order"]
+    auto = P.Plan("laplace", *cell, 1e-6, self_exclude=True)
+    assert auto.fmm_tree(60000) is None and auto.fmm_tree(70000) is not None
+    assert P.Plan("laplace", (100.0, 0.0), (0.0, 1.0), 1e-6, self_exclude=True).fmm_tree(200000) is None
+    assert P.Plan("laplace", (10.0, 0.0), (0.0, 1.0), 1e-6, self_exclude=True).fmm_tree(200000)["k1"] == 10
+    assert P.Plan("laplace", *cell, 1e-6, self_exclude=True, periodic=1).fmm_tree(200000) is None
+    assert P.Plan("laplace", *cell, 1e-6, self_exclude=True, near_mode="mutual").fmm_tree(200000) is None
+    # top grid: boxes within 10 % of square where 128 top boxes allow it
+    for e1, e2 in (((3.0, 0.0), (1.2, 1.0)), ((1.0, 0.0), (0.5, 0.8660254)), ((7.3, 0.0), (0.2, 1.0))):
+        p = P.Plan("stokes", e1, e2, 1e-6, near_mode="fmm")
+        t = p.fmm_tree(100000, 100000)
+        inf = p.info
+        r = inf["d"] / np.hypot(inf["xi"], inf["eta"])
+        assert abs(np.log(r * t["k2"] / t["k1"])) <= np.log(1.1) + 1e-12, (e1, e2, t)

@@ -35,15 +35,19 @@ CASES = [
     ("laplace", 0.0, (1.0, 0.0), (0.0, 1.0), "mixed", True, "auto", (3000, 1100)),
     ("yukawa", 10.0, (1.0, 0.0), (0.3, 1.0), "fp64", False, "auto", (2500, 700)),
     ("stokes", 0.0, (100.0, 0.0), (0.0, 1.0), "mixed", True, "nufft", (4000, 1500)),
+    ("stokes", 0.0, (1.0, 0.0), (0.4, 1.0), "mixed", False, "fmm", (6000, 2500)),
 ]
 
 
-@pytest.mark.parametrize("case", CASES, ids=[c[0] + "-" + c[4] for c in CASES])
+@pytest.mark.parametrize("case", CASES, ids=[c[0] + "-" + c[4] + "-" + c[6] for c in CASES])
 def test_static_matches_eval_twice(env, case):
     P, torch, dev = env
     kernel, beta, e1, e2, prec, self_trg, far, sizes = case
     tol = 1e-10 if prec == "fp64" else 1e-6
-    plan = P.Plan(kernel, e1, e2, tol, beta=beta, precision=prec, self_exclude=self_trg, far_mode=far)
+    near = "fmm" if far == "fmm" else "auto"   # the last case: near part by the FMM
+    far = "auto" if far == "fmm" else far
+    plan = P.Plan(kernel, e1, e2, tol, beta=beta, precision=prec, self_exclude=self_trg, far_mode=far,
+                  near_mode=near)
     P.pfmm_plan_upload(plan)
     for call, n in enumerate(sizes):
         print(f"static {kernel} {prec} call {call} n={n}", flush=True)
