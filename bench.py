@@ -103,7 +103,8 @@ def fmm_work(plan, src, n_trg):
     m0 = inf["m0"]
     beta = plan.beta if plan.kernel == 1 else 0.0
     rcut = np.log(30.0 / inf["eps"]) / beta if beta > 0 else np.inf
-    f32_from = max(0, L - 1) if plan.precision == 1 else L + 1
+    # mixed: FP32 kernel samples on the two finest levels (every level for Yukawa)
+    f32_from = (0 if plan.kernel == 1 else max(0, L - 1)) if plan.precision == 1 else L + 1
     pairs = {"fp32": 0.0, "fp64": 0.0}
     cnt = leaf
     for lev in range(L, -1, -1):

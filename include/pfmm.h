@@ -89,7 +89,8 @@ typedef struct {
                       /* pair's images) combined with the FP64 densities in    */
                       /* FP64, log terms from FP32 log2 of r^2 products added  */
                       /* in FP64; FMM near part: kernel samples in FP32 on the */
-                      /* two finest levels, every expansion and sum in FP64;   */
+                      /* two finest levels (every level for Yukawa), every     */
+                      /* expansion and sum in FP64;                            */
                       /* the far field (coefficients, weights, plane waves at  */
                       /* the targets) in FP64)                                 */
   int far_mode;       /* pfmm_far_mode: AUTO uses the NUFFT when 2M+1 >= 256   */

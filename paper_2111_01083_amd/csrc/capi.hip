@@ -45,7 +45,7 @@ struct Layout {
   size_t skey, sperm, scnt, sseg, ssx, ssy;
   int snblk;
   int64_t sbp;
-  size_t fW, fF, fcount;
+  size_t fW, fF, fcount, fFp;
 };
 
 void plan_layout(const pfmm_plan_s* p, int64_t ns, int64_t nt, Layout& L, int64_t forced_split = 0) {
@@ -117,7 +117,7 @@ void plan_layout(const pfmm_plan_s* p, int64_t ns, int64_t nt, Layout& L, int64_
   L.near_part = take(8 * L.part_stride * L.n_splits);
   L.qb64 = L.qb32 = 0;
   L.mu_chunk = 0;
-  L.skey = L.sperm = L.scnt = L.sseg = L.ssx = L.ssy = L.fW = L.fF = L.fcount = 0;
+  L.skey = L.sperm = L.scnt = L.sseg = L.ssx = L.ssy = L.fW = L.fF = L.fcount = L.fFp = 0;
   L.snblk = 0;
   L.sbp = 0;
   if (L.fmm) {
@@ -136,6 +136,7 @@ void plan_layout(const pfmm_plan_s* p, int64_t ns, int64_t nt, Layout& L, int64_
     L.fW = take(8 * nbox * p->n_dens * nc * P2);
     L.fF = take(8 * nbox * p->n_dens * no * P2);
     L.fcount = take(4 * nbox);
+    L.fFp = take(8 * (size_t)fmm_slice_doubles(L.ft, p->kernel, mixed, p->n_dens));
   }
   if (L.mutual) {
     L.qb64 = take(8 * (size_t)p->n_dens * nc * ns);
@@ -620,7 +621,7 @@ int pfmm::eval_core(pfmm_plan_t p, int64_t ns, const double* src_xy, const doubl
     }
     fa.sq = D_(r, L.qb64);
     fa.scount = (int*)(r.ws + L.fcount);
-    fa.W = D_(r, L.fW); fa.F = D_(r, L.fF);
+    fa.W = D_(r, L.fW); fa.F = D_(r, L.fF); fa.Fp = D_(r, L.fFp);
     fa.part = na.part;
     hipEvent_t fev[6] = {};
     bool timed = false;

@@ -33,11 +33,15 @@ __device__ __forceinline__ double clenshaw_d(const double (&c)[N], double s) {
   return __builtin_fma(s, b1, c[0] - b2);
 }
 
+// ln t for normal t > 0 from the hardware log2 (one instruction; the
+// library logf adds denormal scaling and an extra-precise product by ln 2)
+__device__ __forceinline__ float ln_f32(float t) { return __builtin_amdgcn_logf(t) * 0.693147180559945f; }
+
 // K0(x) and K1(x)/x for x > 0 in FP32.
 __device__ __forceinline__ void bessel_k01_f32(float x, float& k0, float& k1_over_x) {
   if (x <= 2.0f) {
     float t = 0.25f * x * x;
-    float lt = __logf(t);
+    float lt = ln_f32(t);
     float i0 = horner_f(KS_I0_F32, t), p0 = horner_f(KS_P0_F32, t);
     float j1 = horner_f(KS_J1_F32, t), p1 = horner_f(KS_P1_F32, t);
     k0 = p0 - 0.5f * lt * i0;
@@ -63,7 +67,33 @@ __device__ __forceinline__ void bessel_k01_f32_wave(float x, float& k0, float& k
   const bool small = x <= 2.0f;
   if (__any(small)) {
     const float t = 0.25f * x * x;
-    const float lt = __logf(t);
+    const float lt = ln_f32(t);
+    const float i0 = horner_f(KS_I0_F32, t), p0 = horner_f(KS_P0_F32, t);
+    const float j1 = horner_f(KS_J1_F32, t), p1 = horner_f(KS_P1_F32, t);
+    const float k0s = p0 - 0.5f * lt * i0;
+    const float k1s = (1.0f + t * (lt * j1 - p1)) * __builtin_amdgcn_rcpf(x * x);
+    k0 = small ? k0s : k0;
+    k1_over_x = small ? k1s : k1_over_x;
+  }
+}
+
+// Same, each of the two forms evaluated only when some lane of the wavefront
+// needs it (both wave-uniform branches): for pair sets where most or all
+// lanes share the small-argument series (close pairs at large beta r
+// scales) as well as the large-argument fits.
+__device__ __forceinline__ void bessel_k01_f32_split(float x, float& k0, float& k1_over_x) {
+  const bool small = x <= 2.0f;
+  k0 = 0.0f;
+  k1_over_x = 0.0f;
+  if (__any(!small)) {
+    const float rx = __builtin_amdgcn_rcpf(x);
+    const float e = __expf(-x) * __builtin_amdgcn_rsqf(x);
+    k0 = e * horner_f(KL0_F32, rx);
+    k1_over_x = e * rx * horner_f(KL1_F32, rx);
+  }
+  if (__any(small)) {
+    const float t = 0.25f * x * x;
+    const float lt = ln_f32(t);
     const float i0 = horner_f(KS_I0_F32, t), p0 = horner_f(KS_P0_F32, t);
     const float j1 = horner_f(KS_J1_F32, t), p1 = horner_f(KS_P1_F32, t);
     const float k0s = p0 - 0.5f * lt * i0;

@@ -9,11 +9,13 @@ namespace pfmm {
 
 constexpr int FMM_PMAX = 20;          // Chebyshev points per dimension, at most
 constexpr int FMM_MAX_LEVEL = 11;     // deepest leaf level
-constexpr int FMM_CHUNK = 128;        // points per LDS chunk (P2M, leaf kernel)
+constexpr int FMM_CHUNK = 128;        // points per LDS chunk (P2M)
+constexpr int FMM_LEAF = 256;         // threads (targets) and LDS sources per chunk of the leaf kernel
 #ifndef PFMM_FMM_F32_LEVELS
 #define PFMM_FMM_F32_LEVELS 2
 #endif
 constexpr int FMM_F32_LEVELS = PFMM_FMM_F32_LEVELS;   // mixed: levels (the finest) whose M2L samples the kernel in FP32
+constexpr int64_t FMM_M2L_BLOCKS = 8192;  // M2L blocks per density aimed at by splitting interaction lists
 constexpr double FMM_AUTO_PAIRS = 4294967296.0;   // AUTO near mode: FMM from N_S N_T >= 2^32
 constexpr int FMM_AUTO_TOP = 16;      // ... and top grids of at most this many boxes
 
@@ -42,6 +44,7 @@ struct FmmArgs {
   int* scount;                        // sources per box, every level [n_box]
   double* W;                          // equivalent densities [n_box][n_dens * nc][P^2]
   double* F;                          // local fields [n_box][n_dens * NOUT][P^2]
+  double* Fp;                         // M2L partial fields of list slices (fmm_slice_doubles)
   double* part;                       // near part [n_dens * NOUT][n_trg], leaf-box target order
 };
 
@@ -52,6 +55,8 @@ void fmm_tree(const pfmm_plan_s* p, int64_t n_src, int64_t n_trg, FmmTree& t);
 inline int64_t fmm_boxes(const FmmTree& t) { return t.box_off[t.L + 1]; }
 // Chebyshev points per dimension for a kernel, precision and tolerance
 int fmm_order(int kernel, int precision, double tol);
+// doubles of M2L slice scratch (partial local fields) an evaluation needs
+int64_t fmm_slice_doubles(const FmmTree& t, int kernel, bool mixed, int n_dens);
 // ev: NULL, or 6 events recorded on s at the stage boundaries (start,
 // upward done, FP64 interaction lists done, FP32 ones done, downward done,
 // leaves done)

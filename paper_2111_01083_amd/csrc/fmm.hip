@@ -153,7 +153,7 @@ __device__ __forceinline__ void fmm_pair(real dx, real dy, real w0, real w1, rea
   if constexpr (K == PFMM_YUKAWA) {
     lg_out = (real)0;
     real k0, k1x;
-    if constexpr (F32) bessel_k01_f32_wave(beta * __builtin_amdgcn_sqrtf(r2), k0, k1x);
+    if constexpr (F32) bessel_k01_f32_split(beta * __builtin_amdgcn_sqrtf(r2), k0, k1x);
     else bessel_k01_f64(beta * sqrt(r2), k0, k1x);
     acc[0] += w0 * k0;
     const real g = w0 * k1x;
@@ -343,9 +343,12 @@ __device__ __forceinline__ int level_shift(const FmmTree& t, int l) {
 // MIXED: the FP32 kernel samples (the finest levels); FP64: the coarse levels
 // of a mixed evaluation (their equivalent densities are sums over many
 // sources, too large for FP32 log terms) and every level in FP64 mode. Boxes
-// gb0 + blockIdx.x.
+// gb0 + blockIdx.x. Slices: block z = blockIdx.z takes the entries
+// [z per, (z + 1) per) of its box's interaction list (listed in a fixed
+// order); with one slice it writes F, else its partial field to
+// Fp[z][box - gb0], summed in slice order by fmm_slice_sum_kernel.
 template <int K, bool MIXED>
-__global__ __launch_bounds__(512) void fmm_m2l_kernel(FmmArgs a, int64_t gb0) {
+__global__ __launch_bounds__(512) void fmm_m2l_kernel(FmmArgs a, int64_t gb0, int64_t nbox, int per) {
   using real = typename std::conditional<MIXED, float, double>::type;
   constexpr int NC = Fk<K>::NC, NO = Fk<K>::NO, NA = Fk<K>::NA;
   constexpr bool SHIFT = MIXED && K != PFMM_YUKAWA;     // scaled coordinates, log2 shifted
@@ -384,7 +387,11 @@ __global__ __launch_bounds__(512) void fmm_m2l_kernel(FmmArgs a, int64_t gb0) {
   for (int c = 0; c < NC; ++c) wtot[c] = 0.0;
   const int I0 = -t.m0 * lv.n1, I1 = (t.m0 + 1) * lv.n1, J0 = -lv.n2, J1 = 2 * lv.n2;
 
+  const int e0 = (int)blockIdx.z * per, e1 = e0 + per;
+  int e = 0;                                            // list position (uniform over the block)
   auto visit = [&](int I, int J) {
+    const int pos = e++;
+    if (pos < e0 || pos >= e1) return;
     const int64_t sg = t.box_off[l] + (int64_t)posmod(J, lv.n2) * lv.n1 + posmod(I, lv.n1);
     if (a.scount[sg] == 0) return;                      // uniform over the block
     // target centre minus source centre (lattice difference of the super-grid)
@@ -461,8 +468,21 @@ __global__ __launch_bounds__(512) void fmm_m2l_kernel(FmmArgs a, int64_t gb0) {
     double o[NO];
     fmm_outputs<K>(acc, o, a.beta, MIXED ? 0.69314718055994530942 : 1.0);
 #pragma unroll
-    for (int c = 0; c < NO; ++c) a.F[((size_t)gb * a.n_dens * NO + v * NO + c) * P2 + tid] = o[c];
+    for (int c = 0; c < NO; ++c) {
+      if (gridDim.z == 1) a.F[((size_t)gb * a.n_dens * NO + v * NO + c) * P2 + tid] = o[c];
+      else a.Fp[(((size_t)blockIdx.z * nbox + (gb - gb0)) * a.n_dens * NO + v * NO + c) * P2 + tid] = o[c];
+    }
   }
+}
+
+// F[f0 + k] = sum over slices z (in order) of Fp[z n + k], k < n (the
+// local fields of a range of boxes, n doubles from element f0)
+__global__ __launch_bounds__(256) void fmm_slice_sum_kernel(FmmArgs a, int64_t f0, int64_t n, int n_slices) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double s = 0.0;
+  for (int z = 0; z < n_slices; ++z) s += a.Fp[(size_t)z * n + k];
+  a.F[f0 + k] = s;
 }
 
 // ---------------------------------------------------------------------------
@@ -504,10 +524,49 @@ __global__ __launch_bounds__(256) void fmm_l2l_kernel(FmmArgs a, int l, int no_t
 // ---------------------------------------------------------------------------
 // Leaves: the local field interpolated at each target plus the direct sum over
 // the 3 x 3 neighbouring leaf boxes with their image shifts (grid: leaf boxes
-// x densities; targets of a box in chunks of FMM_CHUNK)
+// x densities; a box's targets in chunks of FMM_LEAF, one per thread). The
+// three boxes of a neighbour row are consecutive in leaf-box order, so a row
+// is one range of sources (two where it crosses the cell's edge, whose
+// parts carry different image shifts), streamed through LDS.
 // ---------------------------------------------------------------------------
+// The direct pairs of one LDS chunk of nch sources against this thread's
+// target, 16 sources per FP32 partial sum (log terms pair by pair in FP64)
+template <int K, bool MIXED, bool GUARD>
+__device__ __forceinline__ void leaf_pairs(int nch, double tx, double ty, const double* s_x, const double* s_y,
+                                           const double (*s_q)[FMM_LEAF], const float (*s_q32)[FMM_LEAF],
+                                           double sc, int ksh,
+                                           typename std::conditional<MIXED, float, double>::type beta,
+                                           typename std::conditional<MIXED, float, double>::type r2_self,
+                                           double* acc) {
+  using real = typename std::conditional<MIXED, float, double>::type;
+  constexpr int NC = Fk<K>::NC, NA = Fk<K>::NA;
+  constexpr int NLOG = (K != PFMM_YUKAWA && MIXED) ? NC : 0;
+  for (int j0 = 0; j0 < nch; j0 += 16) {
+    const int j1 = min(nch, j0 + 16);
+    real p[NA];
+#pragma unroll
+    for (int c = 0; c < NA; ++c) p[c] = (real)0;
+    for (int jj = j0; jj < j1; ++jj) {
+      const real dx = NLOG > 0 ? (real)(sc * (tx - s_x[jj])) : (real)(tx - s_x[jj]);
+      const real dy = NLOG > 0 ? (real)(sc * (ty - s_y[jj])) : (real)(ty - s_y[jj]);
+      real w0, w1;
+      if constexpr (MIXED) { w0 = s_q32[0][jj]; w1 = NC > 1 ? s_q32[NC - 1][jj] : 0.0f; }
+      else { w0 = s_q[0][jj]; w1 = NC > 1 ? s_q[NC - 1][jj] : 0.0; }
+      real lg;
+      fmm_pair<K, GUARD, (NLOG > 0), real>(dx, dy, w0, w1, p, beta, lg, r2_self);
+      if constexpr (NLOG > 0) {   // log terms straight into FP64 (a guarded pair gives 0)
+        const double lgs = (double)lg - 2.0 * ksh;
+        acc[0] = fma(s_q[0][jj], lgs, acc[0]);
+        if constexpr (NC > 1) acc[1] = fma(s_q[NC - 1][jj], lgs, acc[1]);
+      }
+    }
+#pragma unroll
+    for (int c = NLOG; c < NA; ++c) acc[c] += (double)p[c];
+  }
+}
+
 template <int K, bool MIXED>
-__global__ __launch_bounds__(FMM_CHUNK) void fmm_leaf_kernel(FmmArgs a) {
+__global__ __launch_bounds__(FMM_LEAF) void fmm_leaf_kernel(FmmArgs a) {
   using real = typename std::conditional<MIXED, float, double>::type;
   constexpr int NC = Fk<K>::NC, NO = Fk<K>::NO, NA = Fk<K>::NA;
   constexpr int NLOG = (K != PFMM_YUKAWA && MIXED) ? NC : 0;   // log terms summed in FP64 per pair
@@ -521,9 +580,10 @@ __global__ __launch_bounds__(FMM_CHUNK) void fmm_leaf_kernel(FmmArgs a) {
   if (t0 >= t1) return;                                   // uniform over the block
   __shared__ double s_s[FMM_PMAX], s_w[FMM_PMAX];
   __shared__ double s_F[6 * FMM_PMAX * FMM_PMAX];
-  __shared__ double s_x[FMM_CHUNK], s_y[FMM_CHUNK], s_q[NC][FMM_CHUNK];
+  __shared__ double s_x[FMM_LEAF], s_y[FMM_LEAF], s_q[NC][FMM_LEAF];
+  __shared__ float s_q32[NC][FMM_LEAF];
   cheb_init(P, s_s, s_w);
-  for (int n = tid; n < NO * P2; n += FMM_CHUNK)
+  for (int n = tid; n < NO * P2; n += FMM_LEAF)
     s_F[n] = a.F[((size_t)gb * a.n_dens * NO + v * NO) * P2 + n];
   __syncthreads();
   const real beta = (real)a.beta;
@@ -532,7 +592,7 @@ __global__ __launch_bounds__(FMM_CHUNK) void fmm_leaf_kernel(FmmArgs a) {
   const int ksh = NLOG > 0 ? level_shift(t, t.L) : 0;
   const double sc = ldexp(1.0, ksh);
   const real r2_self = (real)ldexp(1.0, 2 * ksh);
-  for (int64_t tc = t0; tc < t1; tc += FMM_CHUNK) {
+  for (int64_t tc = t0; tc < t1; tc += FMM_LEAF) {
     const int64_t k = tc + tid;
     const bool act = k < t1;
     const double tx = act ? a.tx[k] : 0.0, ty = act ? a.ty[k] : 0.0;
@@ -569,44 +629,41 @@ __global__ __launch_bounds__(FMM_CHUNK) void fmm_leaf_kernel(FmmArgs a) {
         for (int c = 0; c < NO; ++c) o[c] = fma(la, row[c], o[c]);
       }
     }
-    // direct sum over the neighbouring leaf boxes
+    // direct sum over the neighbouring leaf boxes, one row at a time
     double acc[NA];
 #pragma unroll
     for (int c = 0; c < NA; ++c) acc[c] = 0.0;
-    for (int nbh = 0; nbh < 9; ++nbh) {
-      const int I = i + nbh % 3 - 1, J = j + nbh / 3 - 1;
-      const int m = floordiv(I, lv.n1), n = floordiv(J, lv.n2);
-      const int64_t sb = (int64_t)posmod(J, lv.n2) * lv.n1 + posmod(I, lv.n1);
-      const double shx = m * t.d + n * t.xi, shy = n * t.eta;
-      const int64_t s0 = leaf_begin(a.scnt, a.snblk, sb), s1 = leaf_end(a.scnt, a.snblk, sb);
-      for (int64_t c0 = s0; c0 < s1; c0 += FMM_CHUNK) {
-        const int nch = (int)min((int64_t)FMM_CHUNK, s1 - c0);
-        __syncthreads();
-        if (tid < nch) {
-          s_x[tid] = a.sx[c0 + tid] + shx;
-          s_y[tid] = a.sy[c0 + tid] + shy;
+    for (int dj = -1; dj <= 1; ++dj) {
+      const int J = j + dj, n = floordiv(J, lv.n2), row = posmod(J, lv.n2);
+      for (int q = 0; q < 3;) {
+        // boxes I = i - 1 + q .. i - 1 + last of one image column m
+        const int m = floordiv(i - 1 + q, lv.n1);
+        int last = q;
+        while (last < 2 && floordiv(i + last, lv.n1) == m) ++last;
+        const int64_t kb0 = (int64_t)row * lv.n1 + posmod(i - 1 + q, lv.n1);
+        const int64_t kb1 = (int64_t)row * lv.n1 + posmod(i - 1 + last, lv.n1);
+        const bool own = dj == 0 && m == 0 && q <= 1 && last >= 1;
+        q = last + 1;
+        const double shx = m * t.d + n * t.xi, shy = n * t.eta;
+        const int64_t s0 = leaf_begin(a.scnt, a.snblk, kb0), s1 = leaf_end(a.scnt, a.snblk, kb1);
+        for (int64_t c0 = s0; c0 < s1; c0 += FMM_LEAF) {
+          const int nch = (int)min((int64_t)FMM_LEAF, s1 - c0);
+          __syncthreads();
+          if (tid < nch) {
+            s_x[tid] = a.sx[c0 + tid] + shx;
+            s_y[tid] = a.sy[c0 + tid] + shy;
 #pragma unroll
-          for (int c = 0; c < NC; ++c) s_q[c][tid] = a.sq[((size_t)v * NC + c) * a.n_src + c0 + tid];
-        }
-        __syncthreads();
-        for (int j0 = 0; j0 < nch; j0 += 16) {
-          const int j1 = min(nch, j0 + 16);
-          real p[NA];
-#pragma unroll
-          for (int c = 0; c < NA; ++c) p[c] = (real)0;
-          for (int jj = j0; jj < j1; ++jj) {
-            const real dx = (real)(sc * (tx - s_x[jj])), dy = (real)(sc * (ty - s_y[jj]));
-            const real w0 = (real)s_q[0][jj], w1 = NC > 1 ? (real)s_q[NC - 1][jj] : (real)0;
-            real lg;
-            fmm_pair<K, true, (NLOG > 0), real>(dx, dy, w0, w1, p, beta, lg, r2_self);
-            if constexpr (NLOG > 0) {   // log terms straight into FP64 (the self pair gives 0)
-              const double lgs = (double)lg - 2.0 * ksh;
-              acc[0] = fma(s_q[0][jj], lgs, acc[0]);
-              if constexpr (NC > 1) acc[1] = fma(s_q[NC - 1][jj], lgs, acc[1]);
+            for (int c = 0; c < NC; ++c) {
+              const double q = a.sq[((size_t)v * NC + c) * a.n_src + c0 + tid];
+              s_q[c][tid] = q;
+              s_q32[c][tid] = (float)q;
             }
           }
-#pragma unroll
-          for (int c = NLOG; c < NA; ++c) acc[c] += (double)p[c];
+          __syncthreads();
+          // r = 0 (a target that is a source) can only occur in the piece
+          // that holds the target's own box, unshifted
+          if (own) leaf_pairs<K, MIXED, true>(nch, tx, ty, s_x, s_y, s_q, s_q32, sc, ksh, beta, r2_self, acc);
+          else leaf_pairs<K, MIXED, false>(nch, tx, ty, s_x, s_y, s_q, s_q32, sc, ksh, beta, r2_self, acc);
         }
       }
     }
@@ -695,6 +752,67 @@ void fmm_tree(const pfmm_plan_s* p, int64_t ns, int64_t nt, FmmTree& t) {
   t.box_off[t.L + 1] = off;
 }
 
+// The M2L launches: box ranges (level 0 apart from the others, whose lists
+// are longer; FP64 levels apart from FP32 ones) and for each the number of
+// slices its interaction lists are split into, so that a launch has about
+// FMM_M2L_BLOCKS blocks per density. Level 0 of a 1 x 1 top grid has an
+// empty list.
+struct M2lPart {
+  int64_t lo, hi;
+  int maxlist, S, per;
+  bool f32;
+};
+static int m2l_parts(const FmmTree& t, int kernel, bool mixed, M2lPart* out) {
+  // mixed: FP32 samples on every level for Yukawa (no log terms: its coarse
+  // levels measured the same error in FP32), the two finest otherwise
+  const int64_t split = !mixed ? fmm_boxes(t)
+                        : kernel == PFMM_YUKAWA ? 0 : t.box_off[std::max(0, t.L - FMM_F32_LEVELS + 1)];
+  const int64_t top = t.box_off[1];
+  const int list0 = (t.k1 * t.k2 > 1) ? 3 * (2 * t.m0 + 1) * t.k1 * t.k2 : 1;
+  int n = 0;
+  for (int f32 = 0; f32 < 2; ++f32) {
+    const int64_t b0 = f32 ? split : 0, b1 = f32 ? fmm_boxes(t) : split;
+    for (int part = 0; part < 2; ++part) {
+      const int64_t lo = part == 0 ? b0 : std::max(b0, top), hi = part == 0 ? std::min(b1, top) : b1;
+      if (hi <= lo) continue;
+      M2lPart& m = out[n++];
+      m.lo = lo; m.hi = hi; m.f32 = f32;
+      m.maxlist = part == 0 ? list0 : 27;
+      const int64_t nbox = hi - lo;
+      m.S = (int)std::min<int64_t>(m.maxlist, std::max<int64_t>(1, FMM_M2L_BLOCKS / nbox));
+      m.per = (m.maxlist + m.S - 1) / m.S;
+      m.S = (m.maxlist + m.per - 1) / m.per;
+    }
+  }
+  return n;
+}
+
+int64_t fmm_slice_doubles(const FmmTree& t, int kernel, bool mixed, int n_dens) {
+  const int64_t per_box = (int64_t)n_dens * (kernel == PFMM_STOKES ? 6 : 3) * t.P * t.P;
+  M2lPart parts[4];
+  const int n = m2l_parts(t, kernel, mixed, parts);
+  int64_t need = 0;
+  for (int k = 0; k < n; ++k)
+    if (parts[k].S > 1) need = std::max(need, (int64_t)parts[k].S * (parts[k].hi - parts[k].lo) * per_box);
+  return need;
+}
+
+template <int K, bool MIXED>
+static void m2l_launch(const FmmArgs& a, hipStream_t s, const M2lPart& m) {
+  constexpr int NO = Fk<K>::NO;
+  const FmmTree& t = a.t;
+  const int threads = (t.P * t.P + 63) / 64 * 64;
+  const int64_t per_box = (int64_t)a.n_dens * NO * t.P * t.P;
+  const int64_t nbox = m.hi - m.lo;
+  hipLaunchKernelGGL((fmm_m2l_kernel<K, MIXED>), dim3((unsigned)nbox, a.n_dens, m.S), dim3(threads), 0, s, a, m.lo,
+                     nbox, m.per);
+  if (m.S > 1) {
+    const int64_t n = nbox * per_box;
+    hipLaunchKernelGGL(fmm_slice_sum_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, m.lo * per_box, n,
+                       m.S);
+  }
+}
+
 template <int K, bool MIXED>
 static void launch_fmm_t(const FmmArgs& a, hipStream_t s, hipEvent_t* ev) {
   constexpr int NC = Fk<K>::NC, NO = Fk<K>::NO;
@@ -708,23 +826,20 @@ static void launch_fmm_t(const FmmArgs& a, hipStream_t s, hipEvent_t* ev) {
     hipLaunchKernelGGL(fmm_m2m_kernel, dim3((unsigned)nb, a.n_dens * NC), dim3(256), 0, s, a, l, a.n_dens * NC);
   }
   mark(1);
-  const int threads = (t.P * t.P + 63) / 64 * 64;
-  // mixed: FP32 kernel samples on the two finest levels, FP64 above them
-  const int64_t split = MIXED ? t.box_off[std::max(0, t.L - FMM_F32_LEVELS + 1)] : fmm_boxes(t);
-  if (split > 0)
-    hipLaunchKernelGGL((fmm_m2l_kernel<K, false>), dim3((unsigned)split, a.n_dens), dim3(threads), 0, s, a,
-                       (int64_t)0);
+  M2lPart parts[4];
+  const int np = m2l_parts(t, K, MIXED, parts);
+  for (int k = 0; k < np; ++k)
+    if (!parts[k].f32) m2l_launch<K, false>(a, s, parts[k]);
   mark(2);
-  if (fmm_boxes(t) > split)
-    hipLaunchKernelGGL((fmm_m2l_kernel<K, true>), dim3((unsigned)(fmm_boxes(t) - split), a.n_dens), dim3(threads), 0,
-                       s, a, split);
+  for (int k = 0; k < np; ++k)
+    if (parts[k].f32) m2l_launch<K, true>(a, s, parts[k]);
   mark(3);
   for (int l = 0; l < t.L; ++l) {
     const int64_t nb = t.box_off[l + 2] - t.box_off[l + 1];
     hipLaunchKernelGGL(fmm_l2l_kernel, dim3((unsigned)nb, a.n_dens * NO), dim3(256), 0, s, a, l, a.n_dens * NO);
   }
   mark(4);
-  hipLaunchKernelGGL((fmm_leaf_kernel<K, MIXED>), dim3((unsigned)nleaf, a.n_dens), dim3(FMM_CHUNK), 0, s, a);
+  hipLaunchKernelGGL((fmm_leaf_kernel<K, MIXED>), dim3((unsigned)nleaf, a.n_dens), dim3(FMM_LEAF), 0, s, a);
   mark(5);
 }
 
