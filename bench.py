@@ -105,7 +105,20 @@ def fmm_work(plan, src, n_trg):
     rcut = np.log(30.0 / inf["eps"]) / beta if beta > 0 else np.inf
     # mixed: FP32 kernel samples on the two finest levels (every level for Yukawa)
     f32_from = (0 if plan.kernel == 1 else max(0, L - 1)) if plan.precision == 1 else L + 1
-    pairs = {"fp32": 0.0, "fp64": 0.0}
+    # tabulated levels (Laplace, Yukawa): from the finest down while a level
+    # has >= 64 boxes and the tables fit 1 GiB (49 classes x 3 P^4 entries)
+    tab = set()
+    if plan.kernel != 2:
+        total = 0
+        for lev in range(L, 0, -1):
+            if (k1 << lev) * (k2 << lev) < 64:
+                break
+            b = 49 * 3 * P ** 4 * (4 if lev >= f32_from else 8)
+            if total + b > 1 << 30:
+                break
+            total += b
+            tab.add(lev)
+    pairs = {"fp32": 0.0, "fp64": 0.0, "tab_fp32": 0.0, "tab_fp64": 0.0}
     cnt = leaf
     for lev in range(L, -1, -1):
         m1, m2 = k1 << lev, k2 << lev
@@ -142,11 +155,12 @@ def fmm_work(plan, src, n_trg):
                             if np.hypot(Dx, Dy) - 2 * rad > rcut:
                                 continue
                             visits += float(ne[(tj + dJ) % m2, (ti + dI) % m1].sum())
-        pairs["fp32" if lev >= f32_from else "fp64"] += visits * P ** 4
+        pairs[("tab_" if lev in tab else "") + ("fp32" if lev >= f32_from else "fp64")] += visits * P ** 4
         if lev > 0:
             cnt = cnt.reshape(m2 // 2, 2, m1 // 2, 2).sum(axis=(1, 3))
-    return {"level": L, "k1": k1, "k2": k2, "order": P, "p2p_pairs": p2p,
-            "m2l_node_pairs_fp32": pairs["fp32"], "m2l_node_pairs_fp64": pairs["fp64"]}
+    return {"level": L, "k1": k1, "k2": k2, "order": P, "p2p_pairs": p2p, "tabulated_levels": sorted(tab),
+            "m2l_node_pairs_fp32": pairs["fp32"], "m2l_node_pairs_fp64": pairs["fp64"],
+            "m2l_table_pairs_fp32": pairs["tab_fp32"], "m2l_table_pairs_fp64": pairs["tab_fp64"]}
 
 
 def rel(a, b):
@@ -346,10 +360,16 @@ def main():
             # fields (P^2 fma each) and the two 1D bases (about 6 P)
             leaf_flops = pw[kern] * w["p2p_pairs"] + n * (2 * nout * w["order"] ** 2 + 6 * w["order"])
             kname = f"{kern}, {'mixed' if prec == 'mixed' else 'fp64'}"
-            rows = {"m2l_fp32": (FLOPS_PER_PAIR[kern] * w["m2l_node_pairs_fp32"], FP32_VECTOR_PEAK_TFLOPS,
-                                 f"fmm_m2l_kernel<{kern}, mixed>"),
-                    "m2l_fp64": (FLOPS_FP64_PER_PAIR[kern] * w["m2l_node_pairs_fp64"], FP64_VECTOR_PEAK_TFLOPS,
-                                 f"fmm_m2l_kernel<{kern}, fp64>"),
+            # list stages: sampled point pairs at the sample's flops, tabulated
+            # ones at 2 NOUT flops (one fma per output); the kernel named is
+            # the one with the most flops in the stage
+            tabf = 2 * nout
+            f32s, f32t = FLOPS_PER_PAIR[kern] * w["m2l_node_pairs_fp32"], tabf * w["m2l_table_pairs_fp32"]
+            f64s, f64t = FLOPS_FP64_PER_PAIR[kern] * w["m2l_node_pairs_fp64"], tabf * w["m2l_table_pairs_fp64"]
+            rows = {"m2l_fp32": (f32s + f32t, FP32_VECTOR_PEAK_TFLOPS,
+                                 f"fmm_m2l_table_kernel<{kern}, fp32>" if f32t > f32s else f"fmm_m2l_kernel<{kern}, mixed>"),
+                    "m2l_fp64": (f64s + f64t, FP64_VECTOR_PEAK_TFLOPS,
+                                 f"fmm_m2l_table_kernel<{kern}, fp64>" if f64t > f64s else f"fmm_m2l_kernel<{kern}, fp64>"),
                     "leaves": (leaf_flops, peak, f"fmm_leaf_kernel<{kname}>")}
             ent = {}
             for stg, (fl, pk, kn) in rows.items():

@@ -40,11 +40,16 @@
  *    is a singularity of the sum; such inputs are not supported.
  *  - Evaluation is asynchronous on the caller's HIP stream. Scratch memory
  *    comes from `workspace`, of at least pfmm_workspace_bytes() bytes,
- *    256-byte aligned. The only device allocation is the plan's small
- *    table (a few KB): pfmm_plan_upload makes it, and the first pfmm_eval
- *    on a device calls pfmm_plan_upload itself (hipMalloc plus a
- *    synchronous copy) when the table is not there yet. After that,
- *    pfmm_eval allocates nothing.
+ *    256-byte aligned. Device allocations: the plan's small table (a few
+ *    KB): pfmm_plan_upload makes it, and the first pfmm_eval on a device
+ *    calls pfmm_plan_upload itself (hipMalloc plus a synchronous copy) when
+ *    the table is not there yet; and, for Laplace/Yukawa evaluations whose
+ *    near part takes the FMM, its interaction-list tables (MB to at most
+ *    1 GiB, one per plan): the first evaluation of a tree size allocates
+ *    them and builds them on its stream, a later evaluation with another
+ *    tree (see pfmm_fmm_tree) frees and rebuilds them. Other evaluations
+ *    allocate nothing. A plan must not be evaluated on two streams at once
+ *    with sizes that give different FMM trees.
  *  - n_src and n_trg (per cell in a batch) are at most PFMM_MAX_POINTS
  *    (point indices are 32-bit inside the kernels); larger sizes are
  *    PFMM_EINVAL, and pfmm_workspace_bytes* return 0 for them.
@@ -254,7 +259,10 @@ int pfmm_eval(pfmm_plan_t plan, int64_t n_src, const double* src_xy, const doubl
  * device (call pfmm_plan_upload at set-up), else PFMM_EINVAL; plans with
  * check_neutral or profile set are PFMM_EINVAL too (those options copy to
  * the host or create events). Nothing is allocated and nothing
- * synchronises. All calls on one device share that device's array and the
+ * synchronises: an FMM near part uses the plan's interaction-list tables
+ * when they were built for this tree size (by a pfmm_eval of the same
+ * sizes), else samples the kernel for every level (same results to
+ * rounding, slower). All calls on one device share that device's array and the
  * array keeps the last call's contents (every evaluation rewrites what it
  * reads), so calls that overlap in time on one device -- different streams,
  * or host threads -- race and give wrong results: order them on one

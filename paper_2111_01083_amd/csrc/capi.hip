@@ -45,7 +45,7 @@ struct Layout {
   size_t skey, sperm, scnt, sseg, ssx, ssy;
   int snblk;
   int64_t sbp;
-  size_t fW, fF, fcount, fFp;
+  size_t fW, fF, fcount, fFp, fQ;
 };
 
 void plan_layout(const pfmm_plan_s* p, int64_t ns, int64_t nt, Layout& L, int64_t forced_split = 0) {
@@ -117,7 +117,7 @@ void plan_layout(const pfmm_plan_s* p, int64_t ns, int64_t nt, Layout& L, int64_
   L.near_part = take(8 * L.part_stride * L.n_splits);
   L.qb64 = L.qb32 = 0;
   L.mu_chunk = 0;
-  L.skey = L.sperm = L.scnt = L.sseg = L.ssx = L.ssy = L.fW = L.fF = L.fcount = L.fFp = 0;
+  L.skey = L.sperm = L.scnt = L.sseg = L.ssx = L.ssy = L.fW = L.fF = L.fcount = L.fFp = L.fQ = 0;
   L.snblk = 0;
   L.sbp = 0;
   if (L.fmm) {
@@ -137,6 +137,7 @@ void plan_layout(const pfmm_plan_s* p, int64_t ns, int64_t nt, Layout& L, int64_
     L.fF = take(8 * nbox * p->n_dens * no * P2);
     L.fcount = take(4 * nbox);
     L.fFp = take(8 * (size_t)fmm_slice_doubles(L.ft, p->kernel, mixed, p->n_dens));
+    L.fQ = take(8 * nbox * p->n_dens * nc);
   }
   if (L.mutual) {
     L.qb64 = take(8 * (size_t)p->n_dens * nc * ns);
@@ -621,7 +622,36 @@ int pfmm::eval_core(pfmm_plan_t p, int64_t ns, const double* src_xy, const doubl
     }
     fa.sq = D_(r, L.qb64);
     fa.scount = (int*)(r.ws + L.fcount);
-    fa.W = D_(r, L.fW); fa.F = D_(r, L.fF); fa.Fp = D_(r, L.fFp);
+    fa.W = D_(r, L.fW); fa.F = D_(r, L.fF); fa.Fp = D_(r, L.fFp); fa.Q = D_(r, L.fQ);
+    // tabulated M2L: the plan keeps the tables of its last tree; another
+    // tree rebuilds them (allocating: not in the allocation-free entry
+    // point, which then samples every level)
+    {
+      const bool mixed = p->precision == PFMM_MIXED;
+      const size_t tb = fmm_table_layout(L.ft, p->kernel, mixed, fa.tab_off, fa.tab_f32);
+      int dev = 0;
+      (void)hipGetDevice(&dev);
+      const int key[4] = {L.ft.L, L.ft.k1, L.ft.k2, dev};
+      const bool have = p->fmm_tab && std::equal(key, key + 4, p->fmm_tab_key);
+      if (tb > 0 && (have || !no_alloc)) {
+        if (!have) {
+          if (p->fmm_tab_bytes < tb || p->fmm_tab_key[3] != dev) {
+            if (p->fmm_tab) (void)hipFree(p->fmm_tab);
+            p->fmm_tab = nullptr;
+            p->fmm_tab_bytes = 0;
+            if (hipMalloc(&p->fmm_tab, tb) != hipSuccess) { p->fmm_tab = nullptr; return PFMM_EHIP; }
+            p->fmm_tab_bytes = tb;
+          }
+          fa.tab = (const char*)p->fmm_tab;
+          fmm_build_tables(p->kernel, mixed, fa, (char*)p->fmm_tab, st);
+          std::copy(key, key + 4, p->fmm_tab_key);
+        }
+        fa.tab = (const char*)p->fmm_tab;
+      } else {
+        for (int l = 0; l <= FMM_MAX_LEVEL; ++l) fa.tab_off[l] = -1;
+        fa.tab = nullptr;
+      }
+    }
     fa.part = na.part;
     hipEvent_t fev[6] = {};
     bool timed = false;
@@ -731,6 +761,7 @@ void pfmm_destroy(pfmm_plan_t p) {
   if (p->lap) pfmm_destroy(p->lap);
   for (void* e : p->prof_events) (void)hipEventDestroy((hipEvent_t)e);
   for (void* e : p->prof_fmm_events) (void)hipEventDestroy((hipEvent_t)e);
+  if (p->fmm_tab) (void)hipFree(p->fmm_tab);
   if (p->d_tab) (void)hipFree(p->d_tab);
   delete p;
 }

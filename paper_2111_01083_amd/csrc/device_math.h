@@ -14,6 +14,15 @@ __device__ __forceinline__ float horner_f(const double (&c)[N], float t) {
   for (int k = N - 2; k >= 0; --k) r = __builtin_fmaf(r, t, (float)c[k]);
   return r;
 }
+// the first NT coefficients of c only (a truncated series)
+template <int NT, int N>
+__device__ __forceinline__ float horner_fn(const double (&c)[N], float t) {
+  static_assert(NT <= N, "truncation longer than the series");
+  float r = (float)c[NT - 1];
+#pragma unroll
+  for (int k = NT - 2; k >= 0; --k) r = __builtin_fmaf(r, t, (float)c[k]);
+  return r;
+}
 template <int N>
 __device__ __forceinline__ double horner_d(const double (&c)[N], double t) {
   double r = c[N - 1];
@@ -68,8 +77,16 @@ __device__ __forceinline__ void bessel_k01_f32_wave(float x, float& k0, float& k
   if (__any(small)) {
     const float t = 0.25f * x * x;
     const float lt = ln_f32(t);
-    const float i0 = horner_f(KS_I0_F32, t), p0 = horner_f(KS_P0_F32, t);
-    const float j1 = horner_f(KS_J1_F32, t), p1 = horner_f(KS_P1_F32, t);
+    float i0, p0, j1, p1;
+    if (__all(t <= 0.25f)) {
+      // x <= 1 on every lane: the terms beyond t^5 add less than 2e-9
+      // relative to each sum (their coefficients fall like 1/(k!)^2)
+      i0 = horner_fn<6>(KS_I0_F32, t); p0 = horner_fn<6>(KS_P0_F32, t);
+      j1 = horner_fn<6>(KS_J1_F32, t); p1 = horner_fn<6>(KS_P1_F32, t);
+    } else {
+      i0 = horner_f(KS_I0_F32, t); p0 = horner_f(KS_P0_F32, t);
+      j1 = horner_f(KS_J1_F32, t); p1 = horner_f(KS_P1_F32, t);
+    }
     const float k0s = p0 - 0.5f * lt * i0;
     const float k1s = (1.0f + t * (lt * j1 - p1)) * __builtin_amdgcn_rcpf(x * x);
     k0 = small ? k0s : k0;
@@ -94,8 +111,16 @@ __device__ __forceinline__ void bessel_k01_f32_split(float x, float& k0, float& 
   if (__any(small)) {
     const float t = 0.25f * x * x;
     const float lt = ln_f32(t);
-    const float i0 = horner_f(KS_I0_F32, t), p0 = horner_f(KS_P0_F32, t);
-    const float j1 = horner_f(KS_J1_F32, t), p1 = horner_f(KS_P1_F32, t);
+    float i0, p0, j1, p1;
+    if (__all(t <= 0.25f)) {
+      // x <= 1 on every lane: the terms beyond t^5 add less than 2e-9
+      // relative to each sum (their coefficients fall like 1/(k!)^2)
+      i0 = horner_fn<6>(KS_I0_F32, t); p0 = horner_fn<6>(KS_P0_F32, t);
+      j1 = horner_fn<6>(KS_J1_F32, t); p1 = horner_fn<6>(KS_P1_F32, t);
+    } else {
+      i0 = horner_f(KS_I0_F32, t); p0 = horner_f(KS_P0_F32, t);
+      j1 = horner_f(KS_J1_F32, t); p1 = horner_f(KS_P1_F32, t);
+    }
     const float k0s = p0 - 0.5f * lt * i0;
     const float k1s = (1.0f + t * (lt * j1 - p1)) * __builtin_amdgcn_rcpf(x * x);
     k0 = small ? k0s : k0;

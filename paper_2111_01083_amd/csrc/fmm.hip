@@ -269,6 +269,23 @@ __global__ __launch_bounds__(FMM_CHUNK) void fmm_p2m_kernel(FmmArgs a) {
       for (int c = 0; c < NC; ++c) a.W[((size_t)gb * qn + v * NC + c) * P2 + node] = acc[r][c];
   }
   if (tid == 0 && v == 0) a.scount[gb] = (int)(b1 - b0);
+  // the box's total density per component (the W sum over its points)
+  __shared__ double s_red[FMM_CHUNK];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    double x = 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (tid + r * FMM_CHUNK < P2) x += acc[r][c];
+    s_red[tid] = x;
+    __syncthreads();
+    for (int o = FMM_CHUNK / 2; o > 0; o >>= 1) {
+      if (tid < o) s_red[tid] += s_red[tid + o];
+      __syncthreads();
+    }
+    if (tid == 0) a.Q[(size_t)gb * qn + v * NC + c] = s_red[0];
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -321,6 +338,14 @@ __global__ __launch_bounds__(256) void fmm_m2m_kernel(FmmArgs a, int l, int qn) 
     if (n < P2) a.W[((size_t)gb * qn + c) * P2 + n] = acc[r];
   }
   if (tid == 0 && c == 0) a.scount[gb] = cnt;
+  if (tid == 0) {
+    double q = 0.0;
+    for (int h = 0; h < 4; ++h) {
+      const int64_t cb = t.box_off[l + 1] + (int64_t)(2 * j + (h >> 1)) * lc.n1 + 2 * i + (h & 1);
+      q += a.Q[(size_t)cb * qn + c];
+    }
+    a.Q[(size_t)gb * qn + c] = q;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -335,7 +360,7 @@ template <typename real> struct alignas(4 * sizeof(real)) SrcNode { real ox, oy,
 // differences are scaled by it (exactly) so that the log2 of a typical M2L or
 // neighbour pair's r^2 is near zero, and its FP32 value carries an absolute
 // error of an ulp of a small number; the shift 2k is removed in FP64
-__device__ __forceinline__ int level_shift(const FmmTree& t, int l) {
+__host__ __device__ inline int level_shift(const FmmTree& t, int l) {
   const double h = sqrt(t.d * t.eta / ((double)(t.k1 << l) * (double)(t.k2 << l)));
   return -(int)lround(log2(2.0 * h));
 }
@@ -486,6 +511,165 @@ __global__ __launch_bounds__(256) void fmm_slice_sum_kernel(FmmArgs a, int64_t f
 }
 
 // ---------------------------------------------------------------------------
+// Tabulated M2L (Laplace, Yukawa). Table of level l, class cls = (dJ + 3) 7 +
+// dI + 3 (source box = target box + (dI, dJ)): entry [cls][sc][o][t] = output
+// o at target point t of unit density on source point-component sc, in TT.
+// FP32 tables of Laplace store the potential with log r^2 shifted by the
+// level's 2k ln 2 (as the sampled M2L does; the shift times the box's total
+// density is added back in FP64).
+// ---------------------------------------------------------------------------
+template <int K, typename TT>
+__global__ __launch_bounds__(512) void fmm_table_build_kernel(FmmArgs a, int l, TT* tab, int ksh) {
+  constexpr int NC = Fk<K>::NC, NO = Fk<K>::NO, NA = Fk<K>::NA;
+  const FmmTree& t = a.t;
+  const int P = t.P, P2 = P * P;
+  const int cls = blockIdx.x, sc = blockIdx.y, tp = threadIdx.x;
+  const int dI = cls % 7 - 3, dJ = cls / 7 - 3;
+  if ((abs(dI) <= 1 && abs(dJ) <= 1) || tp >= P2) return;
+  const Lvl lv = level_of(t, l);
+  const int c = sc / P2, sn = sc % P2;
+  auto node = [&](int a_) { return cos((2 * a_ + 1) * PI / (2 * P)); };
+  const double ta = node(tp / P), tb = node(tp % P), sa = node(sn / P), sb = node(sn % P);
+  // target point minus source point: -(box offset) + the two points' offsets
+  const double dx = -(t.d * dI / lv.n1 + t.xi * dJ / lv.n2) + t.d * lv.h1 * (ta - sa) + t.xi * lv.h2 * (tb - sb);
+  const double dy = -(t.eta * dJ / lv.n2) + t.eta * lv.h2 * (tb - sb);
+  double acc[NA];
+#pragma unroll
+  for (int k = 0; k < NA; ++k) acc[k] = 0.0;
+  double lg;
+  fmm_pair<K, false, false, double>(dx, dy, c == 0 ? 1.0 : 0.0, c == 1 ? 1.0 : 0.0, acc, a.beta, lg);
+  double o[NO];
+  fmm_outputs<K>(acc, o, a.beta, 1.0);
+  if (K == PFMM_LAPLACE && ksh != 0) o[0] -= 2.0 * ksh * 0.69314718055994530942 / (4 * PI);
+#pragma unroll
+  for (int k = 0; k < NO; ++k)
+    tab[(((size_t)cls * NC * P2 + sc) * NO + k) * P2 + tp] = (TT)o[k];
+}
+
+// One block per tile of T target boxes of one parity (so that they share
+// their 27 list classes) of level l and one density; a thread per target
+// point. Per class: the T source boxes' equivalent densities in LDS, the
+// class's table rows streamed from memory (L2-resident across tiles),
+// partial sums in TT over one row of P source points, then FP64.
+template <int K, typename TT, int T>
+__global__ __launch_bounds__(512) void fmm_m2l_table_kernel(FmmArgs a, int l, int ksh, int per) {
+  constexpr int NC = Fk<K>::NC, NO = Fk<K>::NO;
+  const FmmTree& t = a.t;
+  const int P = t.P, P2 = P * P;
+  const Lvl lv = level_of(t, l);
+  const int hn1 = lv.n1 / 2, hn2 = lv.n2 / 2;
+  const int tpp = (hn1 * hn2 + T - 1) / T;             // tiles per parity
+  const int g = blockIdx.x / tpp, tile = blockIdx.x % tpp;
+  const int pi = g & 1, pj = g >> 1, v = blockIdx.y, tid = threadIdx.x;
+  const int qn = a.n_dens * NC;
+  __shared__ __align__(16) TT s_w[T][NC * FMM_PMAX * FMM_PMAX];   // rows padded with zeros to a multiple of 4
+  __shared__ double s_q[T][NC];
+  const int NS = NC * P2, NSP = (NS + 3) & ~3;
+  int bi[T], bj[T];
+  bool bv[T];
+#pragma unroll
+  for (int b = 0; b < T; ++b) {
+    const int idx = tile * T + b;
+    bv[b] = idx < hn1 * hn2;
+    bi[b] = 2 * (bv[b] ? idx % hn1 : 0) + pi;
+    bj[b] = 2 * (bv[b] ? idx / hn1 : 0) + pj;
+  }
+  const double rad = 0.5 * fmax(hypot(2 * t.d * lv.h1 + 2 * t.xi * lv.h2, 2 * t.eta * lv.h2),
+                                hypot(-2 * t.d * lv.h1 + 2 * t.xi * lv.h2, 2 * t.eta * lv.h2));
+  const TT* tab = (const TT*)(a.tab + a.tab_off[l]);
+  const bool act = tid < P2;
+  double acc[T][NO];
+#pragma unroll
+  for (int b = 0; b < T; ++b)
+#pragma unroll
+    for (int k = 0; k < NO; ++k) acc[b][k] = 0.0;
+  double qsum[T];
+#pragma unroll
+  for (int b = 0; b < T; ++b) qsum[b] = 0.0;
+  // slice blockIdx.z: list entries [z per, (z + 1) per) in this fixed order
+  const int e0 = (int)blockIdx.z * per, e1 = e0 + per;
+  int e = 0;
+  for (int dJ = -2 - pj; dJ <= 3 - pj; ++dJ)
+    for (int dI = -2 - pi; dI <= 3 - pi; ++dI) {
+      if (abs(dI) <= 1 && abs(dJ) <= 1) continue;
+      const int pos = e++;
+      if (pos < e0 || pos >= e1) continue;
+      const double Dx = -(t.d * dI / lv.n1 + t.xi * dJ / lv.n2), Dy = -(t.eta * dJ / lv.n2);
+      if (sqrt(Dx * Dx + Dy * Dy) - 2 * rad > a.rcut) continue;   // uniform over the block
+      const int cls = (dJ + 3) * 7 + dI + 3;
+      __syncthreads();
+      for (int e = tid; e < T * NSP; e += blockDim.x) {
+        const int b = e / NSP, r = e % NSP;
+        const int64_t sg = t.box_off[l] + (int64_t)posmod(bj[b] + dJ, lv.n2) * lv.n1 + posmod(bi[b] + dI, lv.n1);
+        s_w[b][r] = (TT)((bv[b] && r < NS) ? a.W[((size_t)sg * qn + v * NC + r / P2) * P2 + r % P2] : 0.0);
+      }
+      if (tid < T * NC) {
+        const int b = tid / NC, c = tid % NC;
+        const int64_t sg = t.box_off[l] + (int64_t)posmod(bj[b] + dJ, lv.n2) * lv.n1 + posmod(bi[b] + dI, lv.n1);
+        s_q[b][c] = bv[b] ? a.Q[(size_t)sg * qn + v * NC + c] : 0.0;
+      }
+      __syncthreads();
+      if (act) {
+        const TT* kc = tab + (size_t)cls * NC * P2 * NO * P2 + tid;
+        // 4 source points per step (one 16-byte LDS read per box for FP32),
+        // TT partial sums over 20 of them
+        for (int s0 = 0; s0 < NSP; s0 += 20) {
+          TT p[T][NO];
+#pragma unroll
+          for (int b = 0; b < T; ++b)
+#pragma unroll
+            for (int k = 0; k < NO; ++k) p[b][k] = (TT)0;
+          const int s1 = min(s0 + 20, NSP);
+          for (int sc = s0; sc < s1; sc += 4) {
+            TT kv[4][NO];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+              for (int k = 0; k < NO; ++k) kv[u][k] = sc + u < NS ? kc[((size_t)(sc + u) * NO + k) * P2] : (TT)0;
+#pragma unroll
+            for (int b = 0; b < T; ++b) {
+              TT w[4];
+              if constexpr (std::is_same<TT, float>::value) {
+                const float4 w4 = *reinterpret_cast<const float4*>(&s_w[b][sc]);
+                w[0] = w4.x; w[1] = w4.y; w[2] = w4.z; w[3] = w4.w;
+              } else {
+                const double2 w01 = *reinterpret_cast<const double2*>(&s_w[b][sc]);
+                const double2 w23 = *reinterpret_cast<const double2*>(&s_w[b][sc + 2]);
+                w[0] = w01.x; w[1] = w01.y; w[2] = w23.x; w[3] = w23.y;
+              }
+#pragma unroll
+              for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int k = 0; k < NO; ++k) p[b][k] += kv[u][k] * w[u];
+            }
+          }
+#pragma unroll
+          for (int b = 0; b < T; ++b)
+#pragma unroll
+            for (int k = 0; k < NO; ++k) acc[b][k] += (double)p[b][k];
+        }
+#pragma unroll
+        for (int b = 0; b < T; ++b) qsum[b] += s_q[b][0];
+      }
+    }
+  if (!act) return;
+  const double shift = (K == PFMM_LAPLACE && ksh != 0) ? 2.0 * ksh * 0.69314718055994530942 / (4 * PI) : 0.0;
+#pragma unroll
+  for (int b = 0; b < T; ++b) {
+    if (!bv[b]) continue;
+    const int64_t gb = t.box_off[l] + (int64_t)bj[b] * lv.n1 + bi[b];
+    acc[b][0] += shift * qsum[b];
+#pragma unroll
+    for (int k = 0; k < NO; ++k) {
+      if (gridDim.z == 1) a.F[((size_t)gb * a.n_dens * NO + v * NO + k) * P2 + tid] = acc[b][k];
+      else
+        a.Fp[(((size_t)blockIdx.z * (lv.n1 * lv.n2) + (gb - t.box_off[l])) * a.n_dens * NO + v * NO + k) * P2 + tid] =
+            acc[b][k];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // L2L: local fields of the boxes of level l + 1 += their parent's,
 // interpolated (grid: boxes of level l + 1 x output components)
 // ---------------------------------------------------------------------------
@@ -531,9 +715,9 @@ __global__ __launch_bounds__(256) void fmm_l2l_kernel(FmmArgs a, int l, int no_t
 // ---------------------------------------------------------------------------
 // The direct pairs of one LDS chunk of nch sources against this thread's
 // target, 16 sources per FP32 partial sum (log terms pair by pair in FP64)
-template <int K, bool MIXED, bool GUARD>
+template <int K, bool MIXED, bool GUARD, int BS>
 __device__ __forceinline__ void leaf_pairs(int nch, double tx, double ty, const double* s_x, const double* s_y,
-                                           const double (*s_q)[FMM_LEAF], const float (*s_q32)[FMM_LEAF],
+                                           const double (*s_q)[BS], const float (*s_q32)[BS],
                                            double sc, int ksh,
                                            typename std::conditional<MIXED, float, double>::type beta,
                                            typename std::conditional<MIXED, float, double>::type r2_self,
@@ -565,8 +749,8 @@ __device__ __forceinline__ void leaf_pairs(int nch, double tx, double ty, const 
   }
 }
 
-template <int K, bool MIXED>
-__global__ __launch_bounds__(FMM_LEAF) void fmm_leaf_kernel(FmmArgs a) {
+template <int K, bool MIXED, int BS>
+__global__ __launch_bounds__(BS) void fmm_leaf_kernel(FmmArgs a) {
   using real = typename std::conditional<MIXED, float, double>::type;
   constexpr int NC = Fk<K>::NC, NO = Fk<K>::NO, NA = Fk<K>::NA;
   constexpr int NLOG = (K != PFMM_YUKAWA && MIXED) ? NC : 0;   // log terms summed in FP64 per pair
@@ -580,10 +764,10 @@ __global__ __launch_bounds__(FMM_LEAF) void fmm_leaf_kernel(FmmArgs a) {
   if (t0 >= t1) return;                                   // uniform over the block
   __shared__ double s_s[FMM_PMAX], s_w[FMM_PMAX];
   __shared__ double s_F[6 * FMM_PMAX * FMM_PMAX];
-  __shared__ double s_x[FMM_LEAF], s_y[FMM_LEAF], s_q[NC][FMM_LEAF];
-  __shared__ float s_q32[NC][FMM_LEAF];
+  __shared__ double s_x[BS], s_y[BS], s_q[NC][BS];
+  __shared__ float s_q32[NC][BS];
   cheb_init(P, s_s, s_w);
-  for (int n = tid; n < NO * P2; n += FMM_LEAF)
+  for (int n = tid; n < NO * P2; n += BS)
     s_F[n] = a.F[((size_t)gb * a.n_dens * NO + v * NO) * P2 + n];
   __syncthreads();
   const real beta = (real)a.beta;
@@ -592,7 +776,7 @@ __global__ __launch_bounds__(FMM_LEAF) void fmm_leaf_kernel(FmmArgs a) {
   const int ksh = NLOG > 0 ? level_shift(t, t.L) : 0;
   const double sc = ldexp(1.0, ksh);
   const real r2_self = (real)ldexp(1.0, 2 * ksh);
-  for (int64_t tc = t0; tc < t1; tc += FMM_LEAF) {
+  for (int64_t tc = t0; tc < t1; tc += BS) {
     const int64_t k = tc + tid;
     const bool act = k < t1;
     const double tx = act ? a.tx[k] : 0.0, ty = act ? a.ty[k] : 0.0;
@@ -646,8 +830,8 @@ __global__ __launch_bounds__(FMM_LEAF) void fmm_leaf_kernel(FmmArgs a) {
         q = last + 1;
         const double shx = m * t.d + n * t.xi, shy = n * t.eta;
         const int64_t s0 = leaf_begin(a.scnt, a.snblk, kb0), s1 = leaf_end(a.scnt, a.snblk, kb1);
-        for (int64_t c0 = s0; c0 < s1; c0 += FMM_LEAF) {
-          const int nch = (int)min((int64_t)FMM_LEAF, s1 - c0);
+        for (int64_t c0 = s0; c0 < s1; c0 += BS) {
+          const int nch = (int)min((int64_t)BS, s1 - c0);
           __syncthreads();
           if (tid < nch) {
             s_x[tid] = a.sx[c0 + tid] + shx;
@@ -662,8 +846,8 @@ __global__ __launch_bounds__(FMM_LEAF) void fmm_leaf_kernel(FmmArgs a) {
           __syncthreads();
           // r = 0 (a target that is a source) can only occur in the piece
           // that holds the target's own box, unshifted
-          if (own) leaf_pairs<K, MIXED, true>(nch, tx, ty, s_x, s_y, s_q, s_q32, sc, ksh, beta, r2_self, acc);
-          else leaf_pairs<K, MIXED, false>(nch, tx, ty, s_x, s_y, s_q, s_q32, sc, ksh, beta, r2_self, acc);
+          if (own) leaf_pairs<K, MIXED, true, BS>(nch, tx, ty, s_x, s_y, s_q, s_q32, sc, ksh, beta, r2_self, acc);
+          else leaf_pairs<K, MIXED, false, BS>(nch, tx, ty, s_x, s_y, s_q, s_q32, sc, ksh, beta, r2_self, acc);
         }
       }
     }
@@ -725,8 +909,16 @@ void fmm_tree(const pfmm_plan_s* p, int64_t ns, int64_t nt, FmmTree& t) {
     if (found) break;
   }
   // leaf level: neighbour pairs 9 ns nt / boxes against node pairs 27 P^4
-  // per box (level 0: every non-neighbour of the super-grid)
-  const double P4 = std::pow((double)t.P, 4);
+  // per box (level 0: every non-neighbour of the super-grid), a list point
+  // pair weighted by its cost relative to a leaf pair, measured on MI355X at
+  // N = 2e5: tabulated lists (Laplace, Yukawa) cost 0.24 (Laplace FP64),
+  // 0.36 (Yukawa mixed) and 0.08 (Yukawa FP64, whose leaf pairs take the
+  // FP64 Bessel sequences) of a leaf pair; sampled lists (Stokes, and mixed
+  // Laplace with its FP64 coarse levels) about one
+  const bool mixed = p->precision == PFMM_MIXED;
+  const double wm = p->kernel == PFMM_YUKAWA ? (mixed ? 0.36 : 0.08)
+                    : (p->kernel == PFMM_LAPLACE && !mixed) ? 0.24 : 1.0;
+  const double P4 = wm * std::pow((double)t.P, 4);
   const double top = (double)t.k1 * t.k2;
   const double lvl0 = top * std::max(0.0, 3.0 * (2 * t.m0 + 1) * top - 9.0) * P4;
   double best = 0;
@@ -762,16 +954,22 @@ struct M2lPart {
   int maxlist, S, per;
   bool f32;
 };
-static int m2l_parts(const FmmTree& t, int kernel, bool mixed, M2lPart* out) {
-  // mixed: FP32 samples on every level for Yukawa (no log terms: its coarse
-  // levels measured the same error in FP32), the two finest otherwise
-  const int64_t split = !mixed ? fmm_boxes(t)
-                        : kernel == PFMM_YUKAWA ? 0 : t.box_off[std::max(0, t.L - FMM_F32_LEVELS + 1)];
+// mixed: FP32 samples on every level for Yukawa (no log terms: its coarse
+// levels measured the same error in FP32), the two finest otherwise
+static bool level_f32(const FmmTree& t, int kernel, bool mixed, int l) {
+  return mixed && (kernel == PFMM_YUKAWA || l >= t.L - FMM_F32_LEVELS + 1);
+}
+
+// the sampled (not tabulated) M2L of boxes below b_end
+static int m2l_parts(const FmmTree& t, int kernel, bool mixed, M2lPart* out, int64_t b_end) {
+  int l32 = 0;
+  while (l32 <= t.L && !level_f32(t, kernel, mixed, l32)) ++l32;
+  const int64_t split = std::min(t.box_off[l32], b_end);
   const int64_t top = t.box_off[1];
   const int list0 = (t.k1 * t.k2 > 1) ? 3 * (2 * t.m0 + 1) * t.k1 * t.k2 : 1;
   int n = 0;
   for (int f32 = 0; f32 < 2; ++f32) {
-    const int64_t b0 = f32 ? split : 0, b1 = f32 ? fmm_boxes(t) : split;
+    const int64_t b0 = f32 ? split : 0, b1 = f32 ? b_end : split;
     for (int part = 0; part < 2; ++part) {
       const int64_t lo = part == 0 ? b0 : std::max(b0, top), hi = part == 0 ? std::min(b1, top) : b1;
       if (hi <= lo) continue;
@@ -790,10 +988,16 @@ static int m2l_parts(const FmmTree& t, int kernel, bool mixed, M2lPart* out) {
 int64_t fmm_slice_doubles(const FmmTree& t, int kernel, bool mixed, int n_dens) {
   const int64_t per_box = (int64_t)n_dens * (kernel == PFMM_STOKES ? 6 : 3) * t.P * t.P;
   M2lPart parts[4];
-  const int n = m2l_parts(t, kernel, mixed, parts);
+  const int n = m2l_parts(t, kernel, mixed, parts, fmm_boxes(t));
   int64_t need = 0;
   for (int k = 0; k < n; ++k)
     if (parts[k].S > 1) need = std::max(need, (int64_t)parts[k].S * (parts[k].hi - parts[k].lo) * per_box);
+  // tabulated levels (fmm_table_layout's choice) write FMM_TAB_SLICES partial fields
+  int64_t off[FMM_MAX_LEVEL + 1];
+  int f32[FMM_MAX_LEVEL + 1];
+  if (fmm_table_layout(t, kernel, mixed, off, f32) > 0)
+    for (int l = 0; l <= t.L; ++l)
+      if (off[l] >= 0) need = std::max(need, (int64_t)FMM_TAB_SLICES * (t.box_off[l + 1] - t.box_off[l]) * per_box);
   return need;
 }
 
@@ -813,6 +1017,66 @@ static void m2l_launch(const FmmArgs& a, hipStream_t s, const M2lPart& m) {
   }
 }
 
+template <int K, bool F32>
+static void m2l_table_launch(const FmmArgs& a, hipStream_t s, int l) {
+  if constexpr (K == PFMM_STOKES) {
+    (void)a; (void)s; (void)l;
+  } else {
+    constexpr int T = F32 ? 8 : 4;
+    const FmmTree& t = a.t;
+    const int hn = (t.k1 << l) / 2 * ((t.k2 << l) / 2);
+    const int tiles = 4 * ((hn + T - 1) / T);
+    const int threads = (t.P * t.P + 63) / 64 * 64;
+    const int ksh = (F32 && K == PFMM_LAPLACE) ? level_shift(t, l) : 0;
+    using TT = typename std::conditional<F32, float, double>::type;
+    const int per = 27 / FMM_TAB_SLICES, S = FMM_TAB_SLICES;
+    hipLaunchKernelGGL((fmm_m2l_table_kernel<K, TT, T>), dim3((unsigned)tiles, a.n_dens, S), dim3(threads), 0, s, a,
+                       l, ksh, per);
+    const int64_t per_box = (int64_t)a.n_dens * Fk<K>::NO * t.P * t.P;
+    const int64_t n = (t.box_off[l + 1] - t.box_off[l]) * per_box;
+    hipLaunchKernelGGL(fmm_slice_sum_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a,
+                       t.box_off[l] * per_box, n, S);
+  }
+}
+
+size_t fmm_table_layout(const FmmTree& t, int kernel, bool mixed, int64_t* off, int* f32) {
+  for (int l = 0; l <= FMM_MAX_LEVEL; ++l) { off[l] = -1; f32[l] = 0; }
+  if (kernel == PFMM_STOKES) return 0;     // its 12 samples per point pair cost more to stream than to compute
+  const size_t P2 = (size_t)t.P * t.P;
+  size_t total = 0;
+  for (int l = t.L; l >= 1; --l) {
+    const int64_t boxes = ((int64_t)t.k1 << l) * ((int64_t)t.k2 << l);
+    if (boxes < FMM_TAB_MIN_BOXES) break;
+    const bool is32 = level_f32(t, kernel, mixed, l);
+    const size_t bytes = (FMM_CLASSES * P2 * 3 * P2 * (is32 ? 4 : 8) + 255) & ~(size_t)255;
+    if (total + bytes > FMM_TAB_MAX_BYTES) break;
+    off[l] = (int64_t)total;
+    f32[l] = is32;
+    total += bytes;
+  }
+  return total;
+}
+
+void fmm_build_tables(int kernel, bool mixed, const FmmArgs& a, char* tab, hipStream_t s) {
+  (void)mixed;
+  const FmmTree& t = a.t;
+  const int threads = (t.P * t.P + 63) / 64 * 64;
+  for (int l = 0; l <= t.L; ++l) {
+    if (a.tab_off[l] < 0) continue;
+    const dim3 grid(FMM_CLASSES, t.P * t.P);
+    const bool f32 = a.tab_f32[l];
+    const int ksh = (f32 && kernel == PFMM_LAPLACE) ? level_shift(t, l) : 0;
+    char* base = tab + a.tab_off[l];
+    if (kernel == PFMM_LAPLACE) {
+      if (f32) hipLaunchKernelGGL((fmm_table_build_kernel<PFMM_LAPLACE, float>), grid, dim3(threads), 0, s, a, l, (float*)base, ksh);
+      else hipLaunchKernelGGL((fmm_table_build_kernel<PFMM_LAPLACE, double>), grid, dim3(threads), 0, s, a, l, (double*)base, ksh);
+    } else if (kernel == PFMM_YUKAWA) {
+      if (f32) hipLaunchKernelGGL((fmm_table_build_kernel<PFMM_YUKAWA, float>), grid, dim3(threads), 0, s, a, l, (float*)base, ksh);
+      else hipLaunchKernelGGL((fmm_table_build_kernel<PFMM_YUKAWA, double>), grid, dim3(threads), 0, s, a, l, (double*)base, ksh);
+    }
+  }
+}
+
 template <int K, bool MIXED>
 static void launch_fmm_t(const FmmArgs& a, hipStream_t s, hipEvent_t* ev) {
   constexpr int NC = Fk<K>::NC, NO = Fk<K>::NO;
@@ -826,20 +1090,36 @@ static void launch_fmm_t(const FmmArgs& a, hipStream_t s, hipEvent_t* ev) {
     hipLaunchKernelGGL(fmm_m2m_kernel, dim3((unsigned)nb, a.n_dens * NC), dim3(256), 0, s, a, l, a.n_dens * NC);
   }
   mark(1);
+  // tabulated levels: a suffix lt..L; the others sampled
+  int lt = t.L + 1;
+  while (lt > 0 && a.tab && a.tab_off[lt - 1] >= 0) --lt;
   M2lPart parts[4];
-  const int np = m2l_parts(t, K, MIXED, parts);
+  const int np = m2l_parts(t, K, MIXED, parts, t.box_off[lt]);
   for (int k = 0; k < np; ++k)
     if (!parts[k].f32) m2l_launch<K, false>(a, s, parts[k]);
+  for (int l = lt; l <= t.L; ++l)
+    if (!a.tab_f32[l]) m2l_table_launch<K, false>(a, s, l);
   mark(2);
   for (int k = 0; k < np; ++k)
     if (parts[k].f32) m2l_launch<K, true>(a, s, parts[k]);
+  for (int l = lt; l <= t.L; ++l)
+    if (a.tab_f32[l]) m2l_table_launch<K, true>(a, s, l);
   mark(3);
   for (int l = 0; l < t.L; ++l) {
     const int64_t nb = t.box_off[l + 2] - t.box_off[l + 1];
     hipLaunchKernelGGL(fmm_l2l_kernel, dim3((unsigned)nb, a.n_dens * NO), dim3(256), 0, s, a, l, a.n_dens * NO);
   }
   mark(4);
-  hipLaunchKernelGGL((fmm_leaf_kernel<K, MIXED>), dim3((unsigned)nleaf, a.n_dens), dim3(FMM_LEAF), 0, s, a);
+  // one thread per target: blocks sized to the mean leaf occupancy (a
+  // leaf's targets beyond the block loop in further chunks)
+  const double mean = (double)a.n_trg / (double)nleaf;
+  if (mean <= 56)
+    hipLaunchKernelGGL((fmm_leaf_kernel<K, MIXED, 64>), dim3((unsigned)nleaf, a.n_dens), dim3(64), 0, s, a);
+  else if (mean <= 112)
+    hipLaunchKernelGGL((fmm_leaf_kernel<K, MIXED, 128>), dim3((unsigned)nleaf, a.n_dens), dim3(128), 0, s, a);
+  else
+    hipLaunchKernelGGL((fmm_leaf_kernel<K, MIXED, FMM_LEAF>), dim3((unsigned)nleaf, a.n_dens), dim3(FMM_LEAF), 0, s,
+                       a);
   mark(5);
 }
 

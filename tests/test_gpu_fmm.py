@@ -54,7 +54,7 @@ def inputs(kernel, e1, e2, ns, nt, seed, nd=1):
 
 
 @pytest.mark.parametrize("cell", list(CELLS))
-@pytest.mark.parametrize("kernel,beta", [("laplace", 0.0), ("yukawa", 3.0), ("stokes", 0.0)])
+@pytest.mark.parametrize("kernel,beta", [("laplace", 0.0), ("yukawa", 6.0), ("stokes", 0.0)])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 @pytest.mark.parametrize("self_trg", [True, False])
 def test_fmm_matches_oracle(env, cell, kernel, beta, prec, self_trg):
@@ -137,9 +137,9 @@ def test_fmm_multiple_density_vectors(env, kernel):
     e1, e2 = CELLS["hexagonal"]
     src, dens, trg = inputs(kernel, e1, e2, 2000, 900, seed=35, nd=3)
     print(f"case nd=3 {kernel}", flush=True)
-    pot, grad, _ = run(env, kernel, e1, e2, src, dens, trg, 2.0, "mixed", level=3, n_dens=3)
+    pot, grad, _ = run(env, kernel, e1, e2, src, dens, trg, 6.0, "mixed", level=3, n_dens=3)
     for v in range(3):
-        po, go = oracle.evaluate(kernel, e1, e2, src, dens[v], trg, beta=2.0)
+        po, go = oracle.evaluate(kernel, e1, e2, src, dens[v], trg, beta=6.0)
         check(1e-6, (pot[v], po), (grad[v], go), label=f"fmm {kernel} nd=3 v={v}")
 
 
