@@ -224,8 +224,8 @@ def batch_workload(P, W, torch, dev, np):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=200000, help="sources (= targets) per cell")
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--sample", type=int, default=16, help="oracle targets per kernel")
