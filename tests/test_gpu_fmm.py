@@ -135,7 +135,7 @@ def test_fmm_points_on_the_cell_edges_and_tiny_sizes(env, kernel):
 @pytest.mark.parametrize("kernel", ["laplace", "yukawa", "stokes"])
 def test_fmm_multiple_density_vectors(env, kernel):
     e1, e2 = CELLS["hexagonal"]
-    src, dens, trg = inputs(kernel, e1, e2, 2000, 900, seed=35, nd=3)
+    src, dens, trg = inputs(kernel, e1, e2, 2000, 300, seed=35, nd=3)
     print(f"case nd=3 {kernel}", flush=True)
     pot, grad, _ = run(env, kernel, e1, e2, src, dens, trg, 6.0, "mixed", level=3, n_dens=3)
     for v in range(3):
