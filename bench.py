@@ -32,6 +32,9 @@ METRIC = "targets/sec (pot+grad) at 1e-6 rel err, mixed vs FP64 GPU path; % FP32
 # 2u - 1 2, two 21-term Clenshaw sums 128, scaling 3, accumulation 7.
 FLOPS_PER_PAIR = {"laplace": 14, "yukawa": 51, "stokes": 30}
 FLOPS_FP64_PER_PAIR = {"laplace": 14, "yukawa": 155, "stokes": 30}
+# symmetric leaves: the terms at the source end of a pair (same kernel values,
+# the target's density as weight)
+FLOPS_REVERSE_PER_PAIR = {"laplace": 7, "yukawa": 7, "stokes": 19}
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
@@ -100,6 +103,12 @@ def fmm_work(plan, src, n_trg):
     # neighbours are the images' boxes), less the self pairs
     nb = sum(np.roll(np.roll(leaf, a, 0), b, 1) for a in (-1, 0, 1) for b in (-1, 0, 1))
     p2p = float((leaf * nb).sum()) - src.shape[1]
+    # symmetric leaves (targets are the sources): the own box one-sided, the
+    # forward boxes (the row above, the box to the right) once per pair
+    sym = plan.fmm_symmetric
+    own = float((leaf * leaf).sum()) - src.shape[1]
+    fwd = sum(np.roll(np.roll(leaf, -dj, 0), -di, 1) for di, dj in ((-1, 1), (0, 1), (1, 1), (1, 0)))
+    fwd = float((leaf * fwd).sum())
     m0 = inf["m0"]
     beta = plan.beta if plan.kernel == 1 else 0.0
     rcut = np.log(30.0 / inf["eps"]) / beta if beta > 0 else np.inf
@@ -158,7 +167,8 @@ def fmm_work(plan, src, n_trg):
         pairs[("tab_" if lev in tab else "") + ("fp32" if lev >= f32_from else "fp64")] += visits * P ** 4
         if lev > 0:
             cnt = cnt.reshape(m2 // 2, 2, m1 // 2, 2).sum(axis=(1, 3))
-    return {"level": L, "k1": k1, "k2": k2, "order": P, "p2p_pairs": p2p, "tabulated_levels": sorted(tab),
+    return {"level": L, "k1": k1, "k2": k2, "order": P, "p2p_pairs": p2p, "symmetric_leaves": bool(sym),
+            "p2p_own_pairs": own, "p2p_forward_pairs": fwd, "tabulated_levels": sorted(tab),
             "m2l_node_pairs_fp32": pairs["fp32"], "m2l_node_pairs_fp64": pairs["fp64"],
             "m2l_table_pairs_fp32": pairs["tab_fp32"], "m2l_table_pairs_fp64": pairs["tab_fp64"]}
 
@@ -358,7 +368,11 @@ def main():
             nout = 6 if kern == "stokes" else 3
             # leaves: direct pairs, plus per target the interpolation of NOUT
             # fields (P^2 fma each) and the two 1D bases (about 6 P)
-            leaf_flops = pw[kern] * w["p2p_pairs"] + n * (2 * nout * w["order"] ** 2 + 6 * w["order"])
+            if w["symmetric_leaves"]:
+                pairs_fl = pw[kern] * w["p2p_own_pairs"] + (pw[kern] + FLOPS_REVERSE_PER_PAIR[kern]) * w["p2p_forward_pairs"]
+            else:
+                pairs_fl = pw[kern] * w["p2p_pairs"]
+            leaf_flops = pairs_fl + n * (2 * nout * w["order"] ** 2 + 6 * w["order"])
             kname = f"{kern}, {'mixed' if prec == 'mixed' else 'fp64'}"
             # list stages: sampled point pairs at the sample's flops, tabulated
             # ones at 2 NOUT flops (one fma per output); the kernel named is
@@ -370,7 +384,8 @@ def main():
                                  f"fmm_m2l_table_kernel<{kern}, fp32>" if f32t > f32s else f"fmm_m2l_kernel<{kern}, mixed>"),
                     "m2l_fp64": (f64s + f64t, FP64_VECTOR_PEAK_TFLOPS,
                                  f"fmm_m2l_table_kernel<{kern}, fp64>" if f64t > f64s else f"fmm_m2l_kernel<{kern}, fp64>"),
-                    "leaves": (leaf_flops, peak, f"fmm_leaf_kernel<{kname}>")}
+                    "leaves": (leaf_flops, peak,
+                               f"fmm_leaf_sym_kernel<{kname}>" if w["symmetric_leaves"] else f"fmm_leaf_kernel<{kname}>")}
             ent = {}
             for stg, (fl, pk, kn) in rows.items():
                 ms = per[stg]

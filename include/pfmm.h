@@ -170,6 +170,9 @@ typedef struct {
                                  y' = s x + c y (identity when ew_rotated = 0)  */
   int fmm_order;              /* Chebyshev points per box dimension of the FMM
                                  near part (0: the plan never takes it)        */
+  int fmm_symmetric;          /* 1: its leaves evaluate each pair of
+                                 neighbouring boxes once for both (targets =
+                                 sources; pfmm_tuning_t.fmm_leaves)             */
 } pfmm_plan_info_t;
 
 typedef struct pfmm_plan_s* pfmm_plan_t;
@@ -348,6 +351,14 @@ typedef struct {
   int fmm_level;        /* FMM near part: leaf level of the tree, 1..11 (its leaves are the
                            k1 x k2 top boxes split 4^level times); 0 = from a cost model of
                            neighbour pairs against interaction-list node pairs */
+  int fmm_leaves;       /* FMM near part with targets = sources (self_exclude): 2 = symmetric
+                           leaves, each pair of a leaf box and one of its four forward
+                           neighbours (the row above, the box to the right) evaluated once
+                           for the points of both boxes; 1 = one-sided, every box against
+                           its 3 x 3 neighbours; 0 = symmetric except for mixed Stokes
+                           (whose FP32 pair costs less than the extra terms). Same results
+                           to rounding; symmetric leaves need 4 n_dens NOUT n doubles more
+                           workspace */
 } pfmm_tuning_t;
 
 /* Host: read or set a plan's tuning. nufft_grid = 1 is rejected (PFMM_EINVAL)

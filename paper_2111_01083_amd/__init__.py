@@ -76,6 +76,11 @@ class Plan:
         _check(L.load().pfmm_plan_get_info(self.handle, ctypes.byref(inf)), "pfmm_plan_get_info")
         return {f: getattr(inf, f) for f, _ in inf._fields_}
 
+    @property
+    def fmm_symmetric(self):
+        """True if an FMM near part of this plan takes symmetric leaves."""
+        return bool(self.info["fmm_symmetric"])
+
     def quadrature(self):
         n = self.info["n_quad"]
         x = np.zeros(n); w = np.zeros(n)
@@ -126,8 +131,8 @@ class Plan:
     def tuning(self):
         return pfmm_plan_get_tuning(self)
 
-    def set_tuning(self, near_blocks=None, nufft_grid=None, fmm_level=None):
-        pfmm_plan_set_tuning(self, near_blocks, nufft_grid, fmm_level)
+    def set_tuning(self, near_blocks=None, nufft_grid=None, fmm_level=None, fmm_leaves=None):
+        pfmm_plan_set_tuning(self, near_blocks, nufft_grid, fmm_level, fmm_leaves)
 
     def __call__(self, src, dens, trg=None, **kw):
         return pfmm_eval(self, src, dens, trg, **kw)
@@ -254,14 +259,16 @@ def pfmm_plan_get_log_groups(plan):
 def pfmm_plan_get_tuning(plan):
     t = L.pfmm_tuning_t()
     _check(L.load().pfmm_plan_get_tuning(plan.handle, ctypes.byref(t)), "pfmm_plan_get_tuning")
-    return {"near_blocks": int(t.near_blocks), "nufft_grid": int(t.nufft_grid), "fmm_level": int(t.fmm_level)}
+    return {"near_blocks": int(t.near_blocks), "nufft_grid": int(t.nufft_grid), "fmm_level": int(t.fmm_level),
+            "fmm_leaves": int(t.fmm_leaves)}
 
 
-def pfmm_plan_set_tuning(plan, near_blocks=None, nufft_grid=None, fmm_level=None):
+def pfmm_plan_set_tuning(plan, near_blocks=None, nufft_grid=None, fmm_level=None, fmm_leaves=None):
     cur = pfmm_plan_get_tuning(plan)
     t = L.pfmm_tuning_t(int(cur["near_blocks"] if near_blocks is None else near_blocks),
                         int(cur["nufft_grid"] if nufft_grid is None else nufft_grid),
-                        int(cur["fmm_level"] if fmm_level is None else fmm_level))
+                        int(cur["fmm_level"] if fmm_level is None else fmm_level),
+                        int(cur["fmm_leaves"] if fmm_leaves is None else fmm_leaves))
     _check(L.load().pfmm_plan_set_tuning(plan.handle, ctypes.byref(t)), "pfmm_plan_set_tuning")
 
 
@@ -279,7 +286,7 @@ def _tuning_workspace_bytes(plan, ns, nt):
                         continue
                     best = max(best, pfmm_workspace_bytes(plan, ns, nt))
     finally:
-        pfmm_plan_set_tuning(plan, start["near_blocks"], start["nufft_grid"], start["fmm_level"])
+        pfmm_plan_set_tuning(plan, start["near_blocks"], start["nufft_grid"], start["fmm_level"], start["fmm_leaves"])
     return best
 
 

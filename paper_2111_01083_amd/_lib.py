@@ -45,11 +45,12 @@ class pfmm_plan_info_t(ctypes.Structure):
                 ("nufft_nf", ctypes.c_int), ("nufft_w", ctypes.c_int), ("n_images", ctypes.c_int),
                 ("n_log_groups", ctypes.c_int), ("periodic", ctypes.c_int), ("ew_rotated", ctypes.c_int),
                 ("ew_cos", ctypes.c_double),
-                ("ew_sin", ctypes.c_double), ("fmm_order", ctypes.c_int)]
+                ("ew_sin", ctypes.c_double), ("fmm_order", ctypes.c_int), ("fmm_symmetric", ctypes.c_int)]
 
 
 class pfmm_tuning_t(ctypes.Structure):
-    _fields_ = [("near_blocks", ctypes.c_int64), ("nufft_grid", ctypes.c_int), ("fmm_level", ctypes.c_int)]
+    _fields_ = [("near_blocks", ctypes.c_int64), ("nufft_grid", ctypes.c_int), ("fmm_level", ctypes.c_int),
+                ("fmm_leaves", ctypes.c_int)]
 
 
 class pfmm_tune_report_t(ctypes.Structure):

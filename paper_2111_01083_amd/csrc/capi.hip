@@ -45,7 +45,7 @@ struct Layout {
   size_t skey, sperm, scnt, sseg, ssx, ssy;
   int snblk;
   int64_t sbp;
-  size_t fW, fF, fcount, fFp, fQ;
+  size_t fW, fF, fcount, fFp, fQ, fM;
 };
 
 void plan_layout(const pfmm_plan_s* p, int64_t ns, int64_t nt, Layout& L, int64_t forced_split = 0) {
@@ -117,7 +117,7 @@ void plan_layout(const pfmm_plan_s* p, int64_t ns, int64_t nt, Layout& L, int64_
   L.near_part = take(8 * L.part_stride * L.n_splits);
   L.qb64 = L.qb32 = 0;
   L.mu_chunk = 0;
-  L.skey = L.sperm = L.scnt = L.sseg = L.ssx = L.ssy = L.fW = L.fF = L.fcount = L.fFp = L.fQ = 0;
+  L.skey = L.sperm = L.scnt = L.sseg = L.ssx = L.ssy = L.fW = L.fF = L.fcount = L.fFp = L.fQ = L.fM = 0;
   L.snblk = 0;
   L.sbp = 0;
   if (L.fmm) {
@@ -138,6 +138,7 @@ void plan_layout(const pfmm_plan_s* p, int64_t ns, int64_t nt, Layout& L, int64_
     L.fcount = take(4 * nbox);
     L.fFp = take(8 * (size_t)fmm_slice_doubles(L.ft, p->kernel, mixed, p->n_dens));
     L.fQ = take(8 * nbox * p->n_dens * nc);
+    if (fmm_symmetric_leaves(p)) L.fM = take(8 * (size_t)FMM_SLOTS * p->n_dens * no * nt);
   }
   if (L.mutual) {
     L.qb64 = take(8 * (size_t)p->n_dens * nc * ns);
@@ -325,6 +326,7 @@ int pfmm_plan_get_info(pfmm_plan_t p, pfmm_plan_info_t* info) {
   info->n_images = p->geo.n_images;
   info->n_log_groups = p->geo.n_lg;
   info->fmm_order = (p->near_fmm && p->periodic == 2 && !p->near_none) ? p->fmm_order : 0;
+  info->fmm_symmetric = (info->fmm_order > 0 && fmm_symmetric_leaves(p)) ? 1 : 0;
   return PFMM_OK;
 }
 
@@ -653,6 +655,7 @@ int pfmm::eval_core(pfmm_plan_t p, int64_t ns, const double* src_xy, const doubl
       }
     }
     fa.part = na.part;
+    fa.M = L.fM ? D_(r, L.fM) : nullptr;
     hipEvent_t fev[6] = {};
     bool timed = false;
     if (p->profile) {
@@ -817,12 +820,14 @@ int pfmm_plan_get_tuning(pfmm_plan_t p, pfmm_tuning_t* t) {
   t->near_blocks = p->tune_near;
   t->nufft_grid = p->nu_grid;
   t->fmm_level = p->tune_fmm_level;
+  t->fmm_leaves = p->tune_fmm_leaves;
   return PFMM_OK;
 }
 
 int pfmm_plan_set_tuning(pfmm_plan_t p, const pfmm_tuning_t* t) {
   if (!p || !t || t->near_blocks < 0 || t->near_blocks > (1LL << 24)) return PFMM_EINVAL;
   if (t->fmm_level < 0 || t->fmm_level > FMM_MAX_LEVEL) return PFMM_EINVAL;
+  if (t->fmm_leaves < 0 || t->fmm_leaves > 2) return PFMM_EINVAL;
   if (t->nufft_grid != p->nu_grid) {
     const int old = p->nu_grid;
     int rc = set_nufft_grid(p, t->nufft_grid);
@@ -835,6 +840,7 @@ int pfmm_plan_set_tuning(pfmm_plan_t p, const pfmm_tuning_t* t) {
   }
   p->tune_near = t->near_blocks;
   p->tune_fmm_level = t->fmm_level;
+  p->tune_fmm_leaves = t->fmm_leaves;
   return PFMM_OK;
 }
 

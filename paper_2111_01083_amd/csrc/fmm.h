@@ -52,13 +52,26 @@ struct FmmArgs {
   int64_t tab_off[FMM_MAX_LEVEL + 1];
   int tab_f32[FMM_MAX_LEVEL + 1];
   double* part;                       // near part [n_dens * NOUT][n_trg], leaf-box target order
+  // symmetric leaves (targets are the sources): the sums at the points of a
+  // box's forward neighbours, [FMM_SLOTS][n_dens * NOUT][n_trg]; NULL: one-sided
+  double* M;
 };
+
+constexpr int FMM_SLOTS = 4;          // directions of the backward neighbours of a leaf box
 
 // the tree for n points: k1 x k2 top boxes and the leaf level from a cost
 // model (pairs of the leaf neighbour sums against the node pairs of the
 // interaction lists)
 void fmm_tree(const pfmm_plan_s* p, int64_t n_src, int64_t n_trg, FmmTree& t);
 inline int64_t fmm_boxes(const FmmTree& t) { return t.box_off[t.L + 1]; }
+// leaves evaluated symmetrically (targets are the sources): by default for
+// every kernel but mixed Stokes, whose FP32 pair costs less than the terms of
+// its reverse and their lane moves (measured on MI355X at N = 2e5: 1.16x the
+// one-sided time; 0.56..0.84x for the others), or as the tuning asks
+inline bool fmm_symmetric_leaves(const pfmm_plan_s* p) {
+  if (!p->self_exclude || p->tune_fmm_leaves == 1) return false;
+  return p->tune_fmm_leaves == 2 || p->kernel != PFMM_STOKES || p->precision != PFMM_MIXED;
+}
 // Chebyshev points per dimension for a kernel, precision and tolerance
 int fmm_order(int kernel, int precision, double tol);
 // doubles of M2L slice scratch (partial local fields) an evaluation needs

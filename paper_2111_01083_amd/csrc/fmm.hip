@@ -127,6 +127,44 @@ template <int K> struct Fk {
   static constexpr int NA = K == PFMM_STOKES ? 8 : 3;    // pair accumulators
 };
 
+// The kernel values of one pair from r^2: Yukawa K0(beta r) and
+// K1(beta r)/(beta r); Laplace and Stokes log r^2 (log2 in FP32) and 1/r^2.
+template <int K, typename real>
+__device__ __forceinline__ void pair_vals(real r2, real beta, real& va, real& vb) {
+  constexpr bool F32 = std::is_same<real, float>::value;
+  if constexpr (K == PFMM_YUKAWA) {
+    if constexpr (F32) bessel_k01_f32_split(beta * __builtin_amdgcn_sqrtf(r2), va, vb);
+    else bessel_k01_f64(beta * sqrt(r2), va, vb);
+  } else if constexpr (F32) {
+    va = __builtin_amdgcn_logf(r2);
+    vb = __builtin_amdgcn_rcpf(r2);
+  } else {
+    va = log(r2);
+    vb = 1.0 / r2;
+  }
+}
+
+// The terms of one pair (values va, vb from pair_vals, displacement dx, dy =
+// target - source, weights w0, w1) added to the accumulators; LOG64: without
+// the log terms.
+template <int K, bool LOG64, typename real>
+__device__ __forceinline__ void pair_acc(real va, real vb, real dx, real dy, real w0, real w1, real* acc) {
+  if constexpr (K == PFMM_STOKES) {
+    const real ia = vb * dx, ib = vb * dy;
+    const real c = ia * w0 + ib * w1;
+    const real ca = c * ia;
+    if constexpr (!LOG64) { acc[0] += va * w0; acc[1] += va * w1; }
+    acc[2] += c * dx; acc[3] += c * dy; acc[4] += c;
+    acc[5] += ca * dx; acc[6] += ca * dy;
+    acc[7] += w1 * ia - w0 * ib;
+  } else {
+    if constexpr (K == PFMM_YUKAWA || !LOG64) acc[0] += w0 * va;
+    const real g = w0 * vb;
+    acc[1] += g * dx;
+    acc[2] += g * dy;
+  }
+}
+
 // One kernel sample (pair displacement dx, dy = target - source) with
 // weights w0 (w1: second Stokes component) into the accumulators:
 //   Laplace: sum w lg, sum w dx/r^2, sum w dy/r^2           (lg = log r^2; log2 in FP32)
@@ -150,40 +188,10 @@ __device__ __forceinline__ void fmm_pair(real dx, real dy, real w0, real w1, rea
     w0 = ok ? w0 : (real)0;
     w1 = ok ? w1 : (real)0;
   }
-  if constexpr (K == PFMM_YUKAWA) {
-    lg_out = (real)0;
-    real k0, k1x;
-    if constexpr (F32) bessel_k01_f32_split(beta * __builtin_amdgcn_sqrtf(r2), k0, k1x);
-    else bessel_k01_f64(beta * sqrt(r2), k0, k1x);
-    acc[0] += w0 * k0;
-    const real g = w0 * k1x;
-    acc[1] += g * dx;
-    acc[2] += g * dy;
-  } else {
-    real lg, inv;
-    if constexpr (F32) {
-      lg = __builtin_amdgcn_logf(r2);
-      inv = __builtin_amdgcn_rcpf(r2);
-    } else {
-      lg = log(r2);
-      inv = 1.0 / r2;
-    }
-    lg_out = lg;
-    if constexpr (K == PFMM_LAPLACE) {
-      if constexpr (!LOG64) acc[0] += w0 * lg;
-      const real g = w0 * inv;
-      acc[1] += g * dx;
-      acc[2] += g * dy;
-    } else {
-      const real ia = inv * dx, ib = inv * dy;
-      const real c = ia * w0 + ib * w1;
-      const real ca = c * ia;
-      if constexpr (!LOG64) { acc[0] += lg * w0; acc[1] += lg * w1; }
-      acc[2] += c * dx; acc[3] += c * dy; acc[4] += c;
-      acc[5] += ca * dx; acc[6] += ca * dy;
-      acc[7] += w1 * ia - w0 * ib;
-    }
-  }
+  real va, vb;
+  pair_vals<K, real>(r2, beta, va, vb);
+  lg_out = K == PFMM_YUKAWA ? (real)0 : va;
+  pair_acc<K, LOG64, real>(va, vb, dx, dy, w0, w1, acc);
 }
 
 // accumulators -> outputs (potential, gradient; Stokes u1, u2, du1/dx,
@@ -713,6 +721,41 @@ __global__ __launch_bounds__(256) void fmm_l2l_kernel(FmmArgs a, int l, int no_t
 // is one range of sources (two where it crosses the cell's edge, whose
 // parts carry different image shifts), streamed through LDS.
 // ---------------------------------------------------------------------------
+// The local field F of leaf box (i, j) (LDS, [NO][P^2]) interpolated at the
+// target (tx, ty): o[c] = sum_ab l_a(x1) l_b(x2) F[c][a P + b]
+template <int NO>
+__device__ __forceinline__ void leaf_local(const FmmTree& t, const Lvl& lv, int i, int j, const double* s_s,
+                                           const double* s_w, const double* s_F, double tx, double ty, double* o) {
+  const int P = t.P, P2 = P * P;
+  const double u2 = ty / t.eta, u1 = (tx - t.xi * u2) / t.d;
+  const double x1 = 2.0 * ((u1 + 0.5) * lv.n1 - i) - 1.0, x2 = 2.0 * ((u2 + 0.5) * lv.n2 - j) - 1.0;
+  // basis in the second dimension in registers, the first on the fly
+  double l2[FMM_PMAX];
+  basis_regs(P, s_s, s_w, x2, l2);
+  double sum1 = 0.0;
+  int hit1 = -1;
+  for (int ra = 0; ra < P; ++ra) {
+    const double dd = x1 - s_s[ra];
+    if (dd == 0.0) hit1 = ra;
+    sum1 += dd == 0.0 ? 0.0 : s_w[ra] / dd;
+  }
+  const double inv1 = 1.0 / sum1;
+  for (int ra = 0; ra < P; ++ra) {
+    double row[NO];
+#pragma unroll
+    for (int c = 0; c < NO; ++c) row[c] = 0.0;
+#pragma unroll
+    for (int b = 0; b < FMM_PMAX; ++b)
+      if (b < P)
+#pragma unroll
+        for (int c = 0; c < NO; ++c) row[c] = fma(l2[b], s_F[c * P2 + ra * P + b], row[c]);
+    const double dd = x1 - s_s[ra];
+    const double la = hit1 >= 0 ? (ra == hit1 ? 1.0 : 0.0) : s_w[ra] / dd * inv1;
+#pragma unroll
+    for (int c = 0; c < NO; ++c) o[c] = fma(la, row[c], o[c]);
+  }
+}
+
 // The direct pairs of one LDS chunk of nch sources against this thread's
 // target, 16 sources per FP32 partial sum (log terms pair by pair in FP64)
 template <int K, bool MIXED, bool GUARD, int BS>
@@ -784,35 +827,7 @@ __global__ __launch_bounds__(BS) void fmm_leaf_kernel(FmmArgs a) {
     double o[NO];
 #pragma unroll
     for (int c = 0; c < NO; ++c) o[c] = 0.0;
-    if (act) {
-      const double u2 = ty / t.eta, u1 = (tx - t.xi * u2) / t.d;
-      const double x1 = 2.0 * ((u1 + 0.5) * lv.n1 - i) - 1.0, x2 = 2.0 * ((u2 + 0.5) * lv.n2 - j) - 1.0;
-      // basis in the second dimension in registers, the first on the fly
-      double l2[FMM_PMAX];
-      basis_regs(P, s_s, s_w, x2, l2);
-      double sum1 = 0.0;
-      int hit1 = -1;
-      for (int ra = 0; ra < P; ++ra) {
-        const double dd = x1 - s_s[ra];
-        if (dd == 0.0) hit1 = ra;
-        sum1 += dd == 0.0 ? 0.0 : s_w[ra] / dd;
-      }
-      const double inv1 = 1.0 / sum1;
-      for (int ra = 0; ra < P; ++ra) {
-        double row[NO];
-#pragma unroll
-        for (int c = 0; c < NO; ++c) row[c] = 0.0;
-#pragma unroll
-        for (int b = 0; b < FMM_PMAX; ++b)
-          if (b < P)
-#pragma unroll
-            for (int c = 0; c < NO; ++c) row[c] = fma(l2[b], s_F[c * P2 + ra * P + b], row[c]);
-        const double dd = x1 - s_s[ra];
-        const double la = hit1 >= 0 ? (ra == hit1 ? 1.0 : 0.0) : s_w[ra] / dd * inv1;
-#pragma unroll
-        for (int c = 0; c < NO; ++c) o[c] = fma(la, row[c], o[c]);
-      }
-    }
+    if (act) leaf_local<NO>(t, lv, i, j, s_s, s_w, s_F, tx, ty, o);
     // direct sum over the neighbouring leaf boxes, one row at a time
     double acc[NA];
 #pragma unroll
@@ -860,6 +875,311 @@ __global__ __launch_bounds__(BS) void fmm_leaf_kernel(FmmArgs a) {
       fmm_outputs<K>(acc, d, a.beta, MIXED ? 0.69314718055994530942 : 1.0);
 #pragma unroll
       for (int c = 0; c < NO; ++c) a.part[((size_t)v * NO + c) * a.n_trg + k] = o[c] + d[c];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Symmetric leaves, for targets that are the sources (one array, one order).
+// A box's direct sum is split into its own box (one-sided, as above) and its
+// four forward neighbours: the row above (i - 1 .. i + 1) and the box to the
+// right. A pair of the box and a forward neighbour is evaluated once for both
+// ends: the sums at the box's points go into its result, the sums at the
+// neighbour's points into M, one slot per direction in which a point sees
+// the box (slots 0..2: the row below, i - 1 .. i + 1; slot 3: the box to the
+// left), and fmm_leaf_sym_add adds a point's slots to its result in that
+// order. Each point is written to one slot by one block, so no atomics are
+// needed and the result is deterministic.
+//
+// The four forward boxes form one stream of sources (each with its image
+// shift), cut into tiles of 64. A wavefront takes its 64 points against a tile
+// in 64 steps, lane l pairing its point with source (l + s) mod 64 at step s:
+// its own sums stay in the lane, the sums at the sources move one lane down
+// per step (a wavefront rotation), so that source b's sum is always in the
+// lane that pairs with b next, and after 64 steps it is back in lane b.
+// Mixed: the moving sums are FP32 over 16 steps, then added to FP64 sums in
+// lane b (one cross-lane read per 16 steps); the log terms move in FP64.
+// ---------------------------------------------------------------------------
+// the value held by lane l + 1 (lane 0's for lane 63): DPP wave_rol:1, every
+// lane of the wavefront active
+__device__ __forceinline__ float rot_next(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0x134, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double rot_next(double x) {
+  const long long u = __builtin_bit_cast(long long, x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(u & 0xffffffffll), 0x134, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(u >> 32), 0x134, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, (long long)(unsigned)lo | ((long long)hi << 32));
+}
+
+// forward box f (0..2: the row above, i - 1 .. i + 1; 3: the box to the
+// right): its lattice offset and the slot in which its points see this box
+__device__ __forceinline__ void fwd_offset(int f, int& di, int& dj) {
+  di = f < 3 ? f - 1 : 1;
+  dj = f < 3 ? 1 : 0;
+}
+__device__ __forceinline__ int fwd_slot(int f) { return f < 3 ? 2 - f : 3; }
+
+template <int K, bool MIXED, int BS>
+__global__ __launch_bounds__(BS) void fmm_leaf_sym_kernel(FmmArgs a) {
+  using real = typename std::conditional<MIXED, float, double>::type;
+  constexpr int NC = Fk<K>::NC, NO = Fk<K>::NO, NA = Fk<K>::NA;
+  constexpr int NLOG = (K != PFMM_YUKAWA && MIXED) ? NC : 0;   // log terms summed in FP64 per pair
+  constexpr int NW = BS / 64;
+  const FmmTree& t = a.t;
+  const int P = t.P, P2 = P * P;
+  const int box = blockIdx.x, v = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const Lvl lv = level_of(t, t.L);
+  const int i = box % lv.n1, j = box / lv.n1;
+  const int64_t gb = t.box_off[t.L] + box;
+  const int64_t t0 = leaf_begin(a.tcnt, a.tnblk, box), t1 = leaf_end(a.tcnt, a.tnblk, box);
+  if (t0 >= t1) return;                                   // uniform over the block
+  __shared__ double s_s[FMM_PMAX], s_w[FMM_PMAX];
+  __shared__ double s_F[NO * FMM_PMAX * FMM_PMAX];
+  __shared__ double s_x[BS], s_y[BS], s_q[NC][BS];
+  __shared__ float s_q32[NC][BS];
+  __shared__ double s_col[NW][NA][64];
+  __shared__ int64_t s_g0[FMM_SLOTS], s_len[FMM_SLOTS];
+  __shared__ double s_shx[FMM_SLOTS], s_shy[FMM_SLOTS];
+  cheb_init(P, s_s, s_w);
+  for (int n = tid; n < NO * P2; n += BS)
+    s_F[n] = a.F[((size_t)gb * a.n_dens * NO + v * NO) * P2 + n];
+  if (tid < FMM_SLOTS) {
+    int di, dj;
+    fwd_offset(tid, di, dj);
+    const int I = i + di, J = j + dj;
+    const int m = floordiv(I, lv.n1), n = floordiv(J, lv.n2);
+    const int64_t B = (int64_t)posmod(J, lv.n2) * lv.n1 + posmod(I, lv.n1);
+    s_g0[tid] = leaf_begin(a.scnt, a.snblk, B);
+    s_len[tid] = leaf_end(a.scnt, a.snblk, B) - s_g0[tid];
+    s_shx[tid] = m * t.d + n * t.xi;
+    s_shy[tid] = n * t.eta;
+  }
+  __syncthreads();
+  // the forward stream: boxes f = 0..3 one after the other
+  int64_t b0[FMM_SLOTS + 1];
+  b0[0] = 0;
+#pragma unroll
+  for (int f = 0; f < FMM_SLOTS; ++f) b0[f + 1] = b0[f] + s_len[f];
+  const int64_t nf = b0[FMM_SLOTS];
+  const real beta = (real)a.beta;
+  const int ksh = NLOG > 0 ? level_shift(t, t.L) : 0;
+  const double sc = ldexp(1.0, ksh);
+  const real r2_self = (real)ldexp(1.0, 2 * ksh);
+  const size_t qv = (size_t)v * NC * a.n_src;
+  const double far = 1.0e3 * (t.d + fabs(t.xi) + t.eta);
+  // pairs farther apart than a quarter of that involve padding (r^2 in the
+  // scaled units of the differences); their stand-in r^2: the log shift's
+  // (Laplace, Stokes) or (1 / beta)^2 (Yukawa: K0(1), K1(1))
+  const real dead2 = (real)((0.25 * far * sc) * (0.25 * far * sc));
+  const real r2_dead = K == PFMM_YUKAWA ? (real)(1.0 / (a.beta * a.beta)) : r2_self;
+  for (int64_t tc = t0; tc < t1; tc += BS) {
+    const int64_t k = tc + tid;
+    const bool act = k < t1;
+    // a wavefront with no point of the box skips the pairs (its column sums
+    // are zero)
+    const bool idle = tc + 64 * wv >= t1;
+    // an inactive lane sits far from every source (the forward stream lies
+    // within two cells of the origin), with zero density
+    const double tx = act ? a.tx[k] : far, ty = act ? a.ty[k] : far;
+    double qa[NC];
+    real qr[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      qa[c] = act ? a.sq[qv + (size_t)c * a.n_src + k] : 0.0;
+      qr[c] = (real)qa[c];
+    }
+    double acc[NA];
+#pragma unroll
+    for (int c = 0; c < NA; ++c) acc[c] = 0.0;
+    // own box, one-sided (r = 0 guarded)
+    for (int64_t c0 = t0; c0 < t1; c0 += BS) {
+      const int nch = (int)min((int64_t)BS, t1 - c0);
+      __syncthreads();
+      if (tid < nch) {
+        s_x[tid] = a.sx[c0 + tid];
+        s_y[tid] = a.sy[c0 + tid];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          const double q = a.sq[qv + (size_t)c * a.n_src + c0 + tid];
+          s_q[c][tid] = q;
+          s_q32[c][tid] = (float)q;
+        }
+      }
+      __syncthreads();
+      if (!idle) leaf_pairs<K, MIXED, true, BS>(nch, tx, ty, s_x, s_y, s_q, s_q32, sc, ksh, beta, r2_self, acc);
+    }
+    // forward stream, both ends of every pair
+    for (int64_t c0 = 0; c0 < nf; c0 += BS) {
+      const int nch = (int)min((int64_t)BS, nf - c0);
+      const int nsub = (nch + 63) >> 6;
+      __syncthreads();
+      if (tid < nsub * 64) {
+        const int64_t p = c0 + tid;
+        const bool ok = tid < nch;
+        const int f = (p >= b0[1]) + (p >= b0[2]) + (p >= b0[3]);
+        const int64_t g = s_g0[f] + (p - b0[f]);
+        // padding: far from every point (and from the inactive lanes), zero density
+        s_x[tid] = ok ? a.sx[g] + s_shx[f] : -far;
+        s_y[tid] = ok ? a.sy[g] + s_shy[f] : -far;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          const double q = ok ? a.sq[qv + (size_t)c * a.n_src + g] : 0.0;
+          s_q[c][tid] = q;
+          s_q32[c][tid] = (float)q;
+        }
+      }
+      __syncthreads();
+      for (int sub = 0; sub < nsub; ++sub) {
+        const int base = sub * 64;
+        double D[NA];                                      // sums at source base + lane (FP64)
+#pragma unroll
+        for (int c = 0; c < NA; ++c) D[c] = 0.0;
+        if (!idle) {
+          // lane l meets source (l + s) mod 64 of the tile at step s: it
+          // holds that source's coordinates and densities, which move one
+          // lane down per step together with the sums at the sources
+          double xs = s_x[base + lane], ys = s_y[base + lane];
+          real ws[NC];
+          double wl[NC];
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            ws[c] = MIXED ? (real)s_q32[c][base + lane] : (real)s_q[c][base + lane];
+            wl[c] = s_q[c][base + lane];
+          }
+          real pc[NA];                                     // moving sums at the sources
+#pragma unroll
+          for (int c = 0; c < NA; ++c) pc[c] = (real)0;
+          for (int s16 = 0; s16 < 64; s16 += 16) {
+            real pr[NA];                                   // this lane's sums over 16 sources
+#pragma unroll
+            for (int c = 0; c < NA; ++c) pr[c] = (real)0;
+#pragma unroll 2
+            for (int st = s16; st < s16 + 16; ++st) {
+              const real dx = NLOG > 0 ? (real)(sc * (tx - xs)) : (real)(tx - xs);
+              const real dy = NLOG > 0 ? (real)(sc * (ty - ys)) : (real)(ty - ys);
+              real r2 = MIXED ? __builtin_fmaf(dx, dx, dy * dy) : dx * dx + dy * dy;
+              // a pair with a padding source or an inactive lane (weight
+              // zero, far away) is evaluated at a harmless r^2 instead (the
+              // small-argument branch, log shift cancelled)
+              r2 = r2 > dead2 ? r2_dead : r2;
+              real va, vb;
+              pair_vals<K, real>(r2, beta, va, vb);
+              pair_acc<K, (NLOG > 0), real>(va, vb, dx, dy, ws[0], ws[NC - 1], pr);
+              pair_acc<K, (NLOG > 0), real>(va, vb, -dx, -dy, qr[0], qr[NC - 1], pc);
+              if constexpr (NLOG > 0) {
+                const double lgs = (double)va - 2.0 * ksh;
+                acc[0] = fma(wl[0], lgs, acc[0]);
+                D[0] = fma(qa[0], lgs, D[0]);
+                if constexpr (NC > 1) {
+                  acc[1] = fma(wl[NC - 1], lgs, acc[1]);
+                  D[1] = fma(qa[NC - 1], lgs, D[1]);
+                }
+#pragma unroll
+                for (int c = 0; c < NLOG; ++c) D[c] = rot_next(D[c]);
+              }
+#pragma unroll
+              for (int c = NLOG; c < NA; ++c) pc[c] = rot_next(pc[c]);
+              xs = rot_next(xs);
+              ys = rot_next(ys);
+#pragma unroll
+              for (int c = 0; c < NC; ++c) {
+                ws[c] = rot_next(ws[c]);
+                if constexpr (NLOG > 0) wl[c] = rot_next(wl[c]);
+              }
+            }
+#pragma unroll
+            for (int c = NLOG; c < NA; ++c) acc[c] += (double)pr[c];
+            if constexpr (MIXED) {
+              // the moving sum of source base + lane sits in lane - s16 - 16
+              const int from = (lane - s16 - 16) & 63;
+#pragma unroll
+              for (int c = NLOG; c < NA; ++c) {
+                D[c] += (double)__shfl(pc[c], from);
+                pc[c] = 0.0f;
+              }
+            }
+          }
+          if constexpr (!MIXED) {
+#pragma unroll
+            for (int c = 0; c < NA; ++c) D[c] = (double)pc[c];
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < NA; ++c) s_col[wv][c][lane] = D[c];
+        __syncthreads();
+        if (tid < 64 && base + tid < nch) {
+          double A[NA];
+#pragma unroll
+          for (int c = 0; c < NA; ++c) {
+            double x = 0.0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) x += s_col[w][c][tid];
+            A[c] = x;
+          }
+          if constexpr (NLOG > 0) {
+            if constexpr (K == PFMM_LAPLACE) { A[1] *= sc; A[2] *= sc; }
+            else { A[4] *= sc; A[5] *= sc; A[6] *= sc; A[7] *= sc; }
+          }
+          double d[NO];
+          fmm_outputs<K>(A, d, a.beta, MIXED ? 0.69314718055994530942 : 1.0);
+          const int64_t p = c0 + base + tid;
+          const int f = (p >= b0[1]) + (p >= b0[2]) + (p >= b0[3]);
+          const int64_t g = s_g0[f] + (p - b0[f]);
+          double* m = a.M + ((size_t)(fwd_slot(f) * a.n_dens + v) * NO) * a.n_trg + g;
+          // a box with more points than the block visits the stream once per
+          // chunk of them: the same thread adds to what it wrote before
+#pragma unroll
+          for (int c = 0; c < NO; ++c) m[(size_t)c * a.n_trg] = (tc == t0 ? 0.0 : m[(size_t)c * a.n_trg]) + d[c];
+        }
+        __syncthreads();
+      }
+    }
+    if (act) {
+      if constexpr (NLOG > 0) {
+        if constexpr (K == PFMM_LAPLACE) { acc[1] *= sc; acc[2] *= sc; }
+        else { acc[4] *= sc; acc[5] *= sc; acc[6] *= sc; acc[7] *= sc; }
+      }
+      double o[NO], d[NO];
+#pragma unroll
+      for (int c = 0; c < NO; ++c) o[c] = 0.0;
+      leaf_local<NO>(t, lv, i, j, s_s, s_w, s_F, tx, ty, o);
+      fmm_outputs<K>(acc, d, a.beta, MIXED ? 0.69314718055994530942 : 1.0);
+#pragma unroll
+      for (int c = 0; c < NO; ++c) a.part[((size_t)v * NO + c) * a.n_trg + k] = o[c] + d[c];
+    }
+  }
+}
+
+// adds to each point of a leaf box the slots written by its backward
+// neighbours (grid: leaf boxes x densities); a slot whose neighbour box is
+// empty was not written and is skipped
+template <int NO>
+__global__ __launch_bounds__(256) void fmm_leaf_sym_add(FmmArgs a) {
+  const FmmTree& t = a.t;
+  const int box = blockIdx.x, v = blockIdx.y;
+  const Lvl lv = level_of(t, t.L);
+  const int i = box % lv.n1, j = box / lv.n1;
+  const int64_t t0 = leaf_begin(a.tcnt, a.tnblk, box), t1 = leaf_end(a.tcnt, a.tnblk, box);
+  if (t0 >= t1) return;
+  bool use[FMM_SLOTS];
+#pragma unroll
+  for (int f = 0; f < FMM_SLOTS; ++f) {
+    // the box that sees this one in slot fwd_slot(f) lies at minus forward offset f
+    int di, dj;
+    fwd_offset(f, di, dj);
+    const int64_t A = (int64_t)posmod(j - dj, lv.n2) * lv.n1 + posmod(i - di, lv.n1);
+    use[fwd_slot(f)] = leaf_end(a.scnt, a.snblk, A) > leaf_begin(a.scnt, a.snblk, A);
+  }
+  for (int64_t k = t0 + threadIdx.x; k < t1; k += 256) {
+#pragma unroll
+    for (int c = 0; c < NO; ++c) {
+      double* out = a.part + ((size_t)v * NO + c) * a.n_trg + k;
+      double x = *out;
+#pragma unroll
+      for (int sl = 0; sl < FMM_SLOTS; ++sl)
+        if (use[sl]) x += a.M[((size_t)(sl * a.n_dens + v) * NO + c) * a.n_trg + k];
+      *out = x;
     }
   }
 }
@@ -918,7 +1238,12 @@ void fmm_tree(const pfmm_plan_s* p, int64_t ns, int64_t nt, FmmTree& t) {
   const bool mixed = p->precision == PFMM_MIXED;
   const double wm = p->kernel == PFMM_YUKAWA ? (mixed ? 0.36 : 0.08)
                     : (p->kernel == PFMM_LAPLACE && !mixed) ? 0.24 : 1.0;
-  const double P4 = wm * std::pow((double)t.P, 4);
+  // symmetric leaves: the own box one-sided, the four forward boxes once for
+  // both ends; their time relative to one-sided leaves, measured the same way
+  const double wl = !fmm_symmetric_leaves(p) ? 1.0
+                    : p->kernel == PFMM_YUKAWA ? (mixed ? 0.70 : 0.56)
+                    : p->kernel == PFMM_LAPLACE ? (mixed ? 0.84 : 0.59) : (mixed ? 1.16 : 0.66);
+  const double P4 = wm / wl * std::pow((double)t.P, 4);
   const double top = (double)t.k1 * t.k2;
   const double lvl0 = top * std::max(0.0, 3.0 * (2 * t.m0 + 1) * top - 9.0) * P4;
   double best = 0;
@@ -1113,7 +1438,13 @@ static void launch_fmm_t(const FmmArgs& a, hipStream_t s, hipEvent_t* ev) {
   // one thread per target: blocks sized to the mean leaf occupancy (a
   // leaf's targets beyond the block loop in further chunks)
   const double mean = (double)a.n_trg / (double)nleaf;
-  if (mean <= 56)
+  const dim3 lg((unsigned)nleaf, a.n_dens);
+  if (a.M) {
+    if (mean <= 56) hipLaunchKernelGGL((fmm_leaf_sym_kernel<K, MIXED, 64>), lg, dim3(64), 0, s, a);
+    else if (mean <= 112) hipLaunchKernelGGL((fmm_leaf_sym_kernel<K, MIXED, 128>), lg, dim3(128), 0, s, a);
+    else hipLaunchKernelGGL((fmm_leaf_sym_kernel<K, MIXED, FMM_LEAF>), lg, dim3(FMM_LEAF), 0, s, a);
+    hipLaunchKernelGGL((fmm_leaf_sym_add<Fk<K>::NO>), lg, dim3(256), 0, s, a);
+  } else if (mean <= 56)
     hipLaunchKernelGGL((fmm_leaf_kernel<K, MIXED, 64>), dim3((unsigned)nleaf, a.n_dens), dim3(64), 0, s, a);
   else if (mean <= 112)
     hipLaunchKernelGGL((fmm_leaf_kernel<K, MIXED, 128>), dim3((unsigned)nleaf, a.n_dens), dim3(128), 0, s, a);

@@ -81,6 +81,7 @@ struct pfmm_plan_s {
   int near_fmm;                // near part by the FMM: 0 never, 1 always (P2), 2 for large N (AUTO)
   int fmm_order;               // its Chebyshev points per box dimension
   int tune_fmm_level;          // its leaf level (0: cost model)
+  int tune_fmm_leaves;         // targets = sources: 0 symmetric leaves where they pay, 1 one-sided, 2 symmetric
   // tabulated M2L kernel samples of the FMM (device), built for the tree
   // fmm_tab_key = {L, k1, k2, device}; rebuilt when an evaluation's tree differs
   void* fmm_tab = nullptr;

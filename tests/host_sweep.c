@@ -96,6 +96,7 @@ int main(int argc, char** argv) {
     t.near_blocks = 4096;
     (void)pfmm_plan_set_tuning(p, &t);   /* the doubled grid may be refused */
     t.nufft_grid = 0;
+    t.fmm_leaves = (it / 3) % 3;
     if (pfmm_plan_set_tuning(p, &t)) FAIL("set tuning back");
     if (pfmm_workspace_bytes(p, 5000, 5000) == 0) FAIL("workspace after tuning");
     if (pfmm_eval(p, -1, NULL, NULL, 0, NULL, NULL, NULL, NULL, 0, NULL) != PFMM_EINVAL) FAIL("eval argument check");

@@ -143,6 +143,59 @@ def test_fmm_multiple_density_vectors(env, kernel):
         check(1e-6, (pot[v], po), (grad[v], go), label=f"fmm {kernel} nd=3 v={v}")
 
 
+@pytest.mark.parametrize("kernel,beta", [("laplace", 0.0), ("yukawa", 10.0), ("stokes", 0.0)])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_symmetric_leaves_match_one_sided_leaves(env, kernel, beta, prec):
+    # targets = sources: each forward pair of leaf boxes evaluated once for
+    # both against the same plan and tree with one-sided leaves; equal up to
+    # the order of the sums (FP64) and the grouping of the FP32 partial sums
+    # (mixed); three density vectors. First the square cell with 300 points:
+    # the cost model's tree is the single leaf of the 1 x 1 top grid, which is
+    # its own forward neighbour four times (shifted) and has more points than
+    # a block (the stream is visited once per chunk of them); its 3 x 3
+    # super-grid has no interaction list, so the FMM near part is the direct
+    # near sum. Then the sheared cell at leaf levels 1, 2, 5 and 7 (about one
+    # point per box at 7, most neighbours empty).
+    P, torch, dev = env
+    tol = 2e-14 if prec == "fp64" else 3e-7
+
+    def run3(cell, src, dens, mode, level=0, leaves=0):
+        e1, e2 = CELLS[cell]
+        plan = P.Plan(kernel, e1, e2, BAR[prec][0], beta=beta, precision=prec, self_exclude=True,
+                      near_mode=mode, n_dens=3)
+        if mode == "fmm":
+            plan.set_tuning(fmm_level=level, fmm_leaves=leaves)
+            assert plan.fmm_symmetric == (leaves == 2)
+        tree = plan.fmm_tree(src.shape[1])
+        pot, grad = plan(torch.tensor(src, device=dev), torch.tensor(dens, device=dev), None)
+        torch.cuda.synchronize()
+        return pot.cpu().numpy(), grad.cpu().numpy(), tree
+
+    def same(a, b, label, bar=None):
+        for v in range(3):
+            ep, eg = rel(a[0][v], b[0][v]), rel(a[1][v], b[1][v])
+            assert ep < (bar or tol) and eg < (bar or tol), (label, v, ep, eg)
+
+    e1, e2 = CELLS["square"]
+    src, dens, _ = inputs(kernel, e1, e2, 300, 1, seed=37, nd=3)
+    print(f"case symmetric leaves {kernel} {prec} square n=300", flush=True)
+    sym = run3("square", src, dens, "fmm", 0, 2)
+    assert sym[2]["level"] == 0 and sym[2]["k1"] * sym[2]["k2"] == 1
+    # (the direct sum drops screened pairs beyond its cutoff and groups its
+    # FP32 sums its own way: agreement to a tenth of the plan's bar in FP64,
+    # to the bar in mixed precision, where each path is within about 1e-7)
+    same(sym, run3("square", src, dens, "one_sided"), "square L=0",
+         BAR[prec][0] if prec == "mixed" else 0.1 * BAR[prec][0])
+    e1, e2 = CELLS["sheared"]
+    src, dens, _ = inputs(kernel, e1, e2, 20000, 1, seed=38, nd=3)
+    for level in (1, 2, 5, 7):
+        print(f"case symmetric leaves {kernel} {prec} sheared n=20000 L={level}", flush=True)
+        sym = run3("sheared", src, dens, "fmm", level, 2)
+        one = run3("sheared", src, dens, "fmm", level, 1)
+        assert sym[2] == one[2] and sym[2]["level"] == level
+        same(sym, one, f"sheared L={level}")
+
+
 def test_fmm_repeated_evaluations_are_identical(env):
     # no atomics: the FMM near part is deterministic
     e1, e2 = CELLS["sheared"]

@@ -299,10 +299,10 @@ def test_sizes_beyond_the_point_limit_are_rejected_before_any_launch(P):
 def test_tuning_get_set_and_nufft_grid(P):
     plan = P.Plan("laplace", (100.0, 0.0), (0.0, 1.0), 1e-6, far_mode="nufft")
     nf0, w0 = plan.info["nufft_nf"], plan.info["nufft_w"]
-    assert plan.tuning == {"near_blocks": 0, "nufft_grid": 0, "fmm_level": 0}
+    assert plan.tuning == {"near_blocks": 0, "nufft_grid": 0, "fmm_level": 0, "fmm_leaves": 0}
     assert nf0 >= 2 * (2 * plan.info["n_modes"] + 1) and nf0 & (nf0 - 1) == 0
     plan.set_tuning(near_blocks=4096, nufft_grid=1)
-    assert plan.tuning == {"near_blocks": 4096, "nufft_grid": 1, "fmm_level": 0}
+    assert plan.tuning == {"near_blocks": 4096, "nufft_grid": 1, "fmm_level": 0, "fmm_leaves": 0}
     assert plan.info["nufft_nf"] == 2 * nf0 and plan.info["nufft_w"] == max(4, w0 - 1)
     plan.set_tuning(nufft_grid=0)
     assert plan.info["nufft_nf"] == nf0 and plan.info["nufft_w"] == w0
@@ -462,6 +462,29 @@ def test_fmm_plan_options_and_workspace(P):
     assert ws[2] < ws[4] < ws[6]
     with pytest.raises(P.PfmmError):
         plan.set_tuning(fmm_level=12)
+    # symmetric leaves (targets are the sources) keep 4 slots of the 6
+    # Stokes outputs per point; one-sided leaves need none; by default
+    # mixed Stokes is one-sided, FP64 Stokes symmetric
+    plan.set_tuning(fmm_level=4)
+    one = P.pfmm_workspace_bytes(plan, n, n)
+    plan.set_tuning(fmm_leaves=2)
+    assert plan.tuning["fmm_leaves"] == 2
+    assert P.pfmm_workspace_bytes(plan, n, n) - one == 8 * 4 * 6 * n
+    plan.set_tuning(fmm_leaves=1)
+    assert P.pfmm_workspace_bytes(plan, n, n) == one
+    with pytest.raises(P.PfmmError):
+        plan.set_tuning(fmm_leaves=3)
+    plan.set_tuning(fmm_leaves=0)
+    f64 = P.Plan("stokes", *cell, 1e-10, near_mode="fmm", self_exclude=True)
+    f64.set_tuning(fmm_level=4)
+    sym = P.pfmm_workspace_bytes(f64, n, n)
+    f64.set_tuning(fmm_leaves=1)
+    assert sym - P.pfmm_workspace_bytes(f64, n, n) == 8 * 4 * 6 * n
+    other = P.Plan("stokes", *cell, 1e-6, near_mode="fmm", precision="mixed")
+    other.set_tuning(fmm_level=4)
+    one = P.pfmm_workspace_bytes(other, n, n)
+    other.set_tuning(fmm_leaves=2)
+    assert P.pfmm_workspace_bytes(other, n, n) == one
     plan.set_tuning(fmm_level=0)
     # forced levels deeper than the cap (4e6 leaves) are cut back, not refused
     plan.set_tuning(fmm_level=11)
