@@ -114,19 +114,21 @@ def fmm_work(plan, src, n_trg):
     rcut = np.log(30.0 / inf["eps"]) / beta if beta > 0 else np.inf
     # mixed: FP32 kernel samples on the two finest levels (every level for Yukawa)
     f32_from = (0 if plan.kernel == 1 else max(0, L - 1)) if plan.precision == 1 else L + 1
-    # tabulated levels (Laplace, Yukawa): from the finest down while a level
-    # has >= 64 boxes and the tables fit 1 GiB (49 classes x 3 P^4 entries)
+    # tabulated levels (FP64 tables and products): from the finest down (for
+    # mixed Stokes from the finest level it samples in FP64) while a level has
+    # >= 64 boxes and the tables fit 1 GiB (49 classes x nc NOUT P^4 entries)
     tab = set()
-    if plan.kernel != 2:
-        total = 0
-        for lev in range(L, 0, -1):
-            if (k1 << lev) * (k2 << lev) < 64:
-                break
-            b = 49 * 3 * P ** 4 * (4 if lev >= f32_from else 8)
-            if total + b > 1 << 30:
-                break
-            total += b
-            tab.add(lev)
+    nc, no = (2, 6) if plan.kernel == 2 else (1, 3)
+    total = 0
+    top = min(L, f32_from - 1) if (plan.kernel == 2 and plan.precision == 1) else L
+    for lev in range(top, 0, -1):
+        if (k1 << lev) * (k2 << lev) < 64:
+            break
+        b = 49 * nc * no * P ** 4 * 8
+        if total + b > 1 << 30:
+            break
+        total += b
+        tab.add(lev)
     pairs = {"fp32": 0.0, "fp64": 0.0, "tab_fp32": 0.0, "tab_fp64": 0.0}
     cnt = leaf
     for lev in range(L, -1, -1):
@@ -164,7 +166,7 @@ def fmm_work(plan, src, n_trg):
                             if np.hypot(Dx, Dy) - 2 * rad > rcut:
                                 continue
                             visits += float(ne[(tj + dJ) % m2, (ti + dI) % m1].sum())
-        pairs[("tab_" if lev in tab else "") + ("fp32" if lev >= f32_from else "fp64")] += visits * P ** 4
+        pairs["tab_fp64" if lev in tab else ("fp32" if lev >= f32_from else "fp64")] += visits * P ** 4
         if lev > 0:
             cnt = cnt.reshape(m2 // 2, 2, m1 // 2, 2).sum(axis=(1, 3))
     return {"level": L, "k1": k1, "k2": k2, "order": P, "p2p_pairs": p2p, "symmetric_leaves": bool(sym),
@@ -375,15 +377,15 @@ def main():
             leaf_flops = pairs_fl + n * (2 * nout * w["order"] ** 2 + 6 * w["order"])
             kname = f"{kern}, {'mixed' if prec == 'mixed' else 'fp64'}"
             # list stages: sampled point pairs at the sample's flops, tabulated
-            # ones at 2 NOUT flops (one fma per output); the kernel named is
-            # the one with the most flops in the stage
-            tabf = 2 * nout
+            # ones at 2 nc NOUT flops (one fma per table entry); the kernel
+            # named is the one with the most flops in the stage
+            tabf = 2 * nout * (2 if kern == "stokes" else 1)
             f32s, f32t = FLOPS_PER_PAIR[kern] * w["m2l_node_pairs_fp32"], tabf * w["m2l_table_pairs_fp32"]
             f64s, f64t = FLOPS_FP64_PER_PAIR[kern] * w["m2l_node_pairs_fp64"], tabf * w["m2l_table_pairs_fp64"]
             rows = {"m2l_fp32": (f32s + f32t, FP32_VECTOR_PEAK_TFLOPS,
-                                 f"fmm_m2l_table_kernel<{kern}, fp32>" if f32t > f32s else f"fmm_m2l_kernel<{kern}, mixed>"),
+                                 f"fmm_m2l_kernel<{kern}, mixed>"),
                     "m2l_fp64": (f64s + f64t, FP64_VECTOR_PEAK_TFLOPS,
-                                 f"fmm_m2l_table_kernel<{kern}, fp64>" if f64t > f64s else f"fmm_m2l_kernel<{kern}, fp64>"),
+                                 f"fmm_m2l_mfma_kernel<{kern}>" if f64t > f64s else f"fmm_m2l_kernel<{kern}, fp64>"),
                     "leaves": (leaf_flops, peak,
                                f"fmm_leaf_sym_kernel<{kname}>" if w["symmetric_leaves"] else f"fmm_leaf_kernel<{kname}>")}
             ent = {}

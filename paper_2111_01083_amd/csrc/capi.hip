@@ -630,7 +630,7 @@ int pfmm::eval_core(pfmm_plan_t p, int64_t ns, const double* src_xy, const doubl
     // point, which then samples every level)
     {
       const bool mixed = p->precision == PFMM_MIXED;
-      const size_t tb = fmm_table_layout(L.ft, p->kernel, mixed, fa.tab_off, fa.tab_f32);
+      const size_t tb = fmm_table_layout(L.ft, p->kernel, mixed, fa.tab_off);
       int dev = 0;
       (void)hipGetDevice(&dev);
       const int key[4] = {L.ft.L, L.ft.k1, L.ft.k2, dev};

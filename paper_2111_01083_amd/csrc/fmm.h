@@ -46,11 +46,10 @@ struct FmmArgs {
   double* F;                          // local fields [n_box][n_dens * NOUT][P^2]
   double* Fp;                         // M2L partial fields of list slices (fmm_slice_doubles)
   double* Q;                          // total density of each box [n_box][n_dens * nc]
-  // tabulated M2L: per level, byte offset into tab of its kernel samples
-  // (-1: sampled on the fly) and their type (1: FP32, 0: FP64)
+  // tabulated M2L: per level, byte offset into tab of its FP64 kernel
+  // samples (-1: sampled on the fly)
   const char* tab;
   int64_t tab_off[FMM_MAX_LEVEL + 1];
-  int tab_f32[FMM_MAX_LEVEL + 1];
   double* part;                       // near part [n_dens * NOUT][n_trg], leaf-box target order
   // symmetric leaves (targets are the sources): the sums at the points of a
   // box's forward neighbours, [FMM_SLOTS][n_dens * NOUT][n_trg]; NULL: one-sided
@@ -79,16 +78,20 @@ int64_t fmm_slice_doubles(const FmmTree& t, int kernel, bool mixed, int n_dens);
 
 // Tabulated M2L: the kernel samples between the Chebyshev points of two
 // boxes of one level depend only on their offset class (dI, dJ) in
-// [-3, 3]^2 minus [-1, 1]^2, so a level with enough boxes keeps them in a
-// table of FMM_CLASSES x (nc P^2) x NOUT x P^2 entries built once per plan
-// and tree. fmm_table_layout fills off/f32 (bytes per level, -1: not
-// tabulated) and returns the total bytes (0: none); fmm_build_tables
-// launches the builds on s.
+// [-3, 3]^2 minus [-1, 1]^2, so a level with enough boxes keeps them in an
+// FP64 table of FMM_CLASSES x (nc P^2) x NOUT x P^2 entries built once per
+// plan and tree, and its lists become FP64 matrix products on the matrix
+// cores. fmm_table_layout fills off (bytes per level, -1: not tabulated) and
+// returns the total bytes (0: none); fmm_build_tables launches the builds on
+// s.
 constexpr int FMM_CLASSES = 49;            // 7 x 7 offsets (the inner 3 x 3 unused)
 constexpr int64_t FMM_TAB_MIN_BOXES = 64;  // levels with fewer boxes sample on the fly
 constexpr size_t FMM_TAB_MAX_BYTES = (size_t)1 << 30;
-constexpr int FMM_TAB_SLICES = 9;          // blocks per tile, 3 of its 27 classes each
-size_t fmm_table_layout(const FmmTree& t, int kernel, bool mixed, int64_t* off, int* f32);
+constexpr int FMM_TAB_SLICES = 9;          // slices of the 27 classes (3 each), summed in order
+#ifndef PFMM_FMM_TABLE_STOKES
+#define PFMM_FMM_TABLE_STOKES 1
+#endif
+size_t fmm_table_layout(const FmmTree& t, int kernel, bool mixed, int64_t* off);
 void fmm_build_tables(int kernel, bool mixed, const FmmArgs& a, char* tab, hipStream_t s);
 // ev: NULL, or 6 events recorded on s at the stage boundaries (start,
 // upward done, FP64 interaction lists done, FP32 ones done, downward done,

@@ -508,6 +508,114 @@ __global__ __launch_bounds__(512) void fmm_m2l_kernel(FmmArgs a, int64_t gb0, in
   }
 }
 
+// ---------------------------------------------------------------------------
+// Tabulated M2L on the matrix cores. For one level and one parity group of
+// target boxes (boxes whose parents sit alike share their 27 list classes)
+// the lists are a matrix product: F[:, b] += sum over classes c of
+// T_c W[:, b + offset_c], with T_c the class's FP64 table (rows: output
+// component and target point, NO P^2; columns: source point and component,
+// NC P^2) and W the source boxes' equivalent densities. A block takes 64 rows
+// (16 per wavefront) by 32 target boxes over the classes of one slice; per
+// class it gathers the 32 source boxes' W columns into LDS, and each
+// wavefront streams its 16 table rows from memory into FP64 MFMA 16x16x4
+// products (two per step, 16 boxes each). Inputs, products and sums are
+// FP64 throughout.
+// ---------------------------------------------------------------------------
+typedef double fmm_v4d __attribute__((ext_vector_type(4)));
+constexpr int MM_ROWS = 64, MM_BOXES = 32;   // block tile: 4 wavefronts x 16 rows, 2 x 16 boxes
+constexpr int MM_KC = 128;                   // source columns per LDS stage
+constexpr int MM_LD = MM_KC + 1;             // LDS row of one box (odd: the 16 boxes of a read hit distinct banks)
+constexpr int MM_KSTEP = 16;                 // table values in flight per lane (16 products of K = 4)
+
+template <int K>
+__global__ __launch_bounds__(256) void fmm_m2l_mfma_kernel(FmmArgs a, int l, int per, int n_nt) {
+  constexpr int NC = Fk<K>::NC, NO = Fk<K>::NO;
+  const FmmTree& t = a.t;
+  const int P = t.P, P2 = P * P;
+  const int NS = NC * P2, NSP = (NS + 3) & ~3, M = NO * P2;
+  const Lvl lv = level_of(t, l);
+  const int hn1 = lv.n1 / 2, hn2 = lv.n2 / 2, hn = hn1 * hn2;
+  const int g = blockIdx.x / n_nt, nt = blockIdx.x % n_nt;
+  const int pi = g & 1, pj = g >> 1;
+  const int v = (int)blockIdx.z / FMM_TAB_SLICES, z = (int)blockIdx.z % FMM_TAB_SLICES;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int m0 = (int)blockIdx.y * MM_ROWS + wv * 16;
+  const int qn = a.n_dens * NC;
+  __shared__ double s_wm[MM_BOXES * MM_LD];
+  const double rad = 0.5 * fmax(hypot(2 * t.d * lv.h1 + 2 * t.xi * lv.h2, 2 * t.eta * lv.h2),
+                                hypot(-2 * t.d * lv.h1 + 2 * t.xi * lv.h2, 2 * t.eta * lv.h2));
+  const double* tab = (const double*)(a.tab + a.tab_off[l]);
+  // this lane's row of the table tile (A) and its step within K = 4
+  const int arow = m0 + (lane & 15), kq = lane >> 4;
+  const bool arow_ok = arow < M;
+  fmm_v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+  const int e0 = z * per, e1 = e0 + per;
+  int e = 0;
+  for (int dJ = -2 - pj; dJ <= 3 - pj; ++dJ)
+    for (int dI = -2 - pi; dI <= 3 - pi; ++dI) {
+      if (abs(dI) <= 1 && abs(dJ) <= 1) continue;
+      const int pos = e++;
+      if (pos < e0 || pos >= e1) continue;
+      const double Dx = -(t.d * dI / lv.n1 + t.xi * dJ / lv.n2), Dy = -(t.eta * dJ / lv.n2);
+      if (sqrt(Dx * Dx + Dy * Dy) - 2 * rad > a.rcut) continue;   // uniform over the block
+      const int cls = (dJ + 3) * 7 + dI + 3;
+      const double* tc = tab + (size_t)cls * NS * M;     // [source column][row]
+      for (int c0 = 0; c0 < NSP; c0 += MM_KC) {
+        const int kc = min(MM_KC, NSP - c0);             // a multiple of 4
+        __syncthreads();
+        // gather: the source box of target box j, columns c0 .. c0 + kc
+        // (zero past NC P^2 and for boxes beyond the group)
+        for (int q = tid; q < MM_BOXES * kc; q += 256) {
+          const int j = q / kc, r = c0 + q % kc;
+          const int idx = nt * MM_BOXES + j;
+          double w = 0.0;
+          if (idx < hn && r < NS) {
+            const int bi = 2 * (idx % hn1) + pi, bj = 2 * (idx / hn1) + pj;
+            const int64_t sg = t.box_off[l] + (int64_t)posmod(bj + dJ, lv.n2) * lv.n1 + posmod(bi + dI, lv.n1);
+            w = a.W[((size_t)sg * qn + v * NC + r / P2) * P2 + r % P2];
+          }
+          s_wm[j * MM_LD + q % kc] = w;
+        }
+        __syncthreads();
+        for (int k0 = 0; k0 < kc; k0 += 4 * MM_KSTEP) {
+          double av[MM_KSTEP];
+#pragma unroll
+          for (int u = 0; u < MM_KSTEP; ++u) {
+            const int col = c0 + k0 + 4 * u + kq;
+            av[u] = (arow_ok && col < NS) ? tc[(size_t)col * M + arow] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < MM_KSTEP; ++u) {
+            if (k0 + 4 * u < kc) {                         // uniform
+              const int cl = k0 + 4 * u + kq;
+              const double b0 = s_wm[(lane & 15) * MM_LD + cl];
+              const double b1 = s_wm[(16 + (lane & 15)) * MM_LD + cl];
+              acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], b0, acc0, 0, 0, 0);
+              acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], b1, acc1, 0, 0, 0);
+            }
+          }
+        }
+      }
+    }
+  // the lane holds rows m0 + lane / 16 + 4 r of boxes lane % 16 (acc0) and
+  // 16 + lane % 16 (acc1), the output layout of the 16x16x4 FP64 product
+  // (checked on the GPU against a host product): slice z's partial fields
+  const int64_t nbox = t.box_off[l + 1] - t.box_off[l];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int idx = nt * MM_BOXES + h * 16 + (lane & 15);
+    if (idx >= hn) continue;
+    const int bi = 2 * (idx % hn1) + pi, bj = 2 * (idx / hn1) + pj;
+    const int64_t lb = (int64_t)bj * lv.n1 + bi;
+    const fmm_v4d& ac = h ? acc1 : acc0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = m0 + kq + 4 * r;
+      if (row < M) a.Fp[(((size_t)z * nbox + lb) * a.n_dens + v) * NO * P2 + row] = ac[r];
+    }
+  }
+}
+
 // F[f0 + k] = sum over slices z (in order) of Fp[z n + k], k < n (the
 // local fields of a range of boxes, n doubles from element f0)
 __global__ __launch_bounds__(256) void fmm_slice_sum_kernel(FmmArgs a, int64_t f0, int64_t n, int n_slices) {
@@ -519,15 +627,13 @@ __global__ __launch_bounds__(256) void fmm_slice_sum_kernel(FmmArgs a, int64_t f
 }
 
 // ---------------------------------------------------------------------------
-// Tabulated M2L (Laplace, Yukawa). Table of level l, class cls = (dJ + 3) 7 +
-// dI + 3 (source box = target box + (dI, dJ)): entry [cls][sc][o][t] = output
-// o at target point t of unit density on source point-component sc, in TT.
-// FP32 tables of Laplace store the potential with log r^2 shifted by the
-// level's 2k ln 2 (as the sampled M2L does; the shift times the box's total
-// density is added back in FP64).
+// M2L tables. Table of level l, class cls = (dJ + 3) 7 + dI + 3 (source box =
+// target box + (dI, dJ)): entry [cls][sc][o][t] = output o at target point t
+// of unit density on source point-component sc, FP64 (grid: classes x
+// source point-components; a thread per target point).
 // ---------------------------------------------------------------------------
-template <int K, typename TT>
-__global__ __launch_bounds__(512) void fmm_table_build_kernel(FmmArgs a, int l, TT* tab, int ksh) {
+template <int K>
+__global__ __launch_bounds__(512) void fmm_table_build_kernel(FmmArgs a, int l, double* tab) {
   constexpr int NC = Fk<K>::NC, NO = Fk<K>::NO, NA = Fk<K>::NA;
   const FmmTree& t = a.t;
   const int P = t.P, P2 = P * P;
@@ -548,133 +654,9 @@ __global__ __launch_bounds__(512) void fmm_table_build_kernel(FmmArgs a, int l, 
   fmm_pair<K, false, false, double>(dx, dy, c == 0 ? 1.0 : 0.0, c == 1 ? 1.0 : 0.0, acc, a.beta, lg);
   double o[NO];
   fmm_outputs<K>(acc, o, a.beta, 1.0);
-  if (K == PFMM_LAPLACE && ksh != 0) o[0] -= 2.0 * ksh * 0.69314718055994530942 / (4 * PI);
 #pragma unroll
   for (int k = 0; k < NO; ++k)
-    tab[(((size_t)cls * NC * P2 + sc) * NO + k) * P2 + tp] = (TT)o[k];
-}
-
-// One block per tile of T target boxes of one parity (so that they share
-// their 27 list classes) of level l and one density; a thread per target
-// point. Per class: the T source boxes' equivalent densities in LDS, the
-// class's table rows streamed from memory (L2-resident across tiles),
-// partial sums in TT over one row of P source points, then FP64.
-template <int K, typename TT, int T>
-__global__ __launch_bounds__(512) void fmm_m2l_table_kernel(FmmArgs a, int l, int ksh, int per) {
-  constexpr int NC = Fk<K>::NC, NO = Fk<K>::NO;
-  const FmmTree& t = a.t;
-  const int P = t.P, P2 = P * P;
-  const Lvl lv = level_of(t, l);
-  const int hn1 = lv.n1 / 2, hn2 = lv.n2 / 2;
-  const int tpp = (hn1 * hn2 + T - 1) / T;             // tiles per parity
-  const int g = blockIdx.x / tpp, tile = blockIdx.x % tpp;
-  const int pi = g & 1, pj = g >> 1, v = blockIdx.y, tid = threadIdx.x;
-  const int qn = a.n_dens * NC;
-  __shared__ __align__(16) TT s_w[T][NC * FMM_PMAX * FMM_PMAX];   // rows padded with zeros to a multiple of 4
-  __shared__ double s_q[T][NC];
-  const int NS = NC * P2, NSP = (NS + 3) & ~3;
-  int bi[T], bj[T];
-  bool bv[T];
-#pragma unroll
-  for (int b = 0; b < T; ++b) {
-    const int idx = tile * T + b;
-    bv[b] = idx < hn1 * hn2;
-    bi[b] = 2 * (bv[b] ? idx % hn1 : 0) + pi;
-    bj[b] = 2 * (bv[b] ? idx / hn1 : 0) + pj;
-  }
-  const double rad = 0.5 * fmax(hypot(2 * t.d * lv.h1 + 2 * t.xi * lv.h2, 2 * t.eta * lv.h2),
-                                hypot(-2 * t.d * lv.h1 + 2 * t.xi * lv.h2, 2 * t.eta * lv.h2));
-  const TT* tab = (const TT*)(a.tab + a.tab_off[l]);
-  const bool act = tid < P2;
-  double acc[T][NO];
-#pragma unroll
-  for (int b = 0; b < T; ++b)
-#pragma unroll
-    for (int k = 0; k < NO; ++k) acc[b][k] = 0.0;
-  double qsum[T];
-#pragma unroll
-  for (int b = 0; b < T; ++b) qsum[b] = 0.0;
-  // slice blockIdx.z: list entries [z per, (z + 1) per) in this fixed order
-  const int e0 = (int)blockIdx.z * per, e1 = e0 + per;
-  int e = 0;
-  for (int dJ = -2 - pj; dJ <= 3 - pj; ++dJ)
-    for (int dI = -2 - pi; dI <= 3 - pi; ++dI) {
-      if (abs(dI) <= 1 && abs(dJ) <= 1) continue;
-      const int pos = e++;
-      if (pos < e0 || pos >= e1) continue;
-      const double Dx = -(t.d * dI / lv.n1 + t.xi * dJ / lv.n2), Dy = -(t.eta * dJ / lv.n2);
-      if (sqrt(Dx * Dx + Dy * Dy) - 2 * rad > a.rcut) continue;   // uniform over the block
-      const int cls = (dJ + 3) * 7 + dI + 3;
-      __syncthreads();
-      for (int e = tid; e < T * NSP; e += blockDim.x) {
-        const int b = e / NSP, r = e % NSP;
-        const int64_t sg = t.box_off[l] + (int64_t)posmod(bj[b] + dJ, lv.n2) * lv.n1 + posmod(bi[b] + dI, lv.n1);
-        s_w[b][r] = (TT)((bv[b] && r < NS) ? a.W[((size_t)sg * qn + v * NC + r / P2) * P2 + r % P2] : 0.0);
-      }
-      if (tid < T * NC) {
-        const int b = tid / NC, c = tid % NC;
-        const int64_t sg = t.box_off[l] + (int64_t)posmod(bj[b] + dJ, lv.n2) * lv.n1 + posmod(bi[b] + dI, lv.n1);
-        s_q[b][c] = bv[b] ? a.Q[(size_t)sg * qn + v * NC + c] : 0.0;
-      }
-      __syncthreads();
-      if (act) {
-        const TT* kc = tab + (size_t)cls * NC * P2 * NO * P2 + tid;
-        // 4 source points per step (one 16-byte LDS read per box for FP32),
-        // TT partial sums over 20 of them
-        for (int s0 = 0; s0 < NSP; s0 += 20) {
-          TT p[T][NO];
-#pragma unroll
-          for (int b = 0; b < T; ++b)
-#pragma unroll
-            for (int k = 0; k < NO; ++k) p[b][k] = (TT)0;
-          const int s1 = min(s0 + 20, NSP);
-          for (int sc = s0; sc < s1; sc += 4) {
-            TT kv[4][NO];
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-              for (int k = 0; k < NO; ++k) kv[u][k] = sc + u < NS ? kc[((size_t)(sc + u) * NO + k) * P2] : (TT)0;
-#pragma unroll
-            for (int b = 0; b < T; ++b) {
-              TT w[4];
-              if constexpr (std::is_same<TT, float>::value) {
-                const float4 w4 = *reinterpret_cast<const float4*>(&s_w[b][sc]);
-                w[0] = w4.x; w[1] = w4.y; w[2] = w4.z; w[3] = w4.w;
-              } else {
-                const double2 w01 = *reinterpret_cast<const double2*>(&s_w[b][sc]);
-                const double2 w23 = *reinterpret_cast<const double2*>(&s_w[b][sc + 2]);
-                w[0] = w01.x; w[1] = w01.y; w[2] = w23.x; w[3] = w23.y;
-              }
-#pragma unroll
-              for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int k = 0; k < NO; ++k) p[b][k] += kv[u][k] * w[u];
-            }
-          }
-#pragma unroll
-          for (int b = 0; b < T; ++b)
-#pragma unroll
-            for (int k = 0; k < NO; ++k) acc[b][k] += (double)p[b][k];
-        }
-#pragma unroll
-        for (int b = 0; b < T; ++b) qsum[b] += s_q[b][0];
-      }
-    }
-  if (!act) return;
-  const double shift = (K == PFMM_LAPLACE && ksh != 0) ? 2.0 * ksh * 0.69314718055994530942 / (4 * PI) : 0.0;
-#pragma unroll
-  for (int b = 0; b < T; ++b) {
-    if (!bv[b]) continue;
-    const int64_t gb = t.box_off[l] + (int64_t)bj[b] * lv.n1 + bi[b];
-    acc[b][0] += shift * qsum[b];
-#pragma unroll
-    for (int k = 0; k < NO; ++k) {
-      if (gridDim.z == 1) a.F[((size_t)gb * a.n_dens * NO + v * NO + k) * P2 + tid] = acc[b][k];
-      else
-        a.Fp[(((size_t)blockIdx.z * (lv.n1 * lv.n2) + (gb - t.box_off[l])) * a.n_dens * NO + v * NO + k) * P2 + tid] =
-            acc[b][k];
-    }
-  }
+    tab[(((size_t)cls * NC * P2 + sc) * NO + k) * P2 + tp] = o[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -1286,16 +1268,28 @@ static bool level_f32(const FmmTree& t, int kernel, bool mixed, int l) {
 }
 
 // the sampled (not tabulated) M2L of boxes below b_end
-static int m2l_parts(const FmmTree& t, int kernel, bool mixed, M2lPart* out, int64_t b_end) {
+// The sampled boxes are every box outside the tabulated range [t_lo, t_hi)
+// (out: at most M2L_MAX_PARTS parts).
+constexpr int M2L_MAX_PARTS = 8;
+static int m2l_parts(const FmmTree& t, int kernel, bool mixed, M2lPart* out, int64_t t_lo, int64_t t_hi) {
   int l32 = 0;
   while (l32 <= t.L && !level_f32(t, kernel, mixed, l32)) ++l32;
-  const int64_t split = std::min(t.box_off[l32], b_end);
+  const int64_t end = fmm_boxes(t), split = t.box_off[l32];
   const int64_t top = t.box_off[1];
   const int list0 = (t.k1 * t.k2 > 1) ? 3 * (2 * t.m0 + 1) * t.k1 * t.k2 : 1;
   int n = 0;
   for (int f32 = 0; f32 < 2; ++f32) {
-    const int64_t b0 = f32 ? split : 0, b1 = f32 ? b_end : split;
-    for (int part = 0; part < 2; ++part) {
+    const int64_t r0 = f32 ? split : 0, r1 = f32 ? end : split;
+    // the range less the tabulated boxes: up to two pieces
+    int64_t pc[2][2] = {{r0, r1}, {0, 0}};
+    if (t_hi > t_lo && t_lo < r1 && t_hi > r0) {
+      pc[0][1] = std::max(r0, t_lo);
+      pc[1][0] = std::min(r1, t_hi);
+      pc[1][1] = r1;
+    }
+    for (int q = 0; q < 4; ++q) {
+      const int64_t b0 = pc[q >> 1][0], b1 = pc[q >> 1][1];
+      const int part = q & 1;
       const int64_t lo = part == 0 ? b0 : std::max(b0, top), hi = part == 0 ? std::min(b1, top) : b1;
       if (hi <= lo) continue;
       M2lPart& m = out[n++];
@@ -1312,15 +1306,14 @@ static int m2l_parts(const FmmTree& t, int kernel, bool mixed, M2lPart* out, int
 
 int64_t fmm_slice_doubles(const FmmTree& t, int kernel, bool mixed, int n_dens) {
   const int64_t per_box = (int64_t)n_dens * (kernel == PFMM_STOKES ? 6 : 3) * t.P * t.P;
-  M2lPart parts[4];
-  const int n = m2l_parts(t, kernel, mixed, parts, fmm_boxes(t));
+  M2lPart parts[M2L_MAX_PARTS];
+  const int n = m2l_parts(t, kernel, mixed, parts, 0, 0);
   int64_t need = 0;
   for (int k = 0; k < n; ++k)
     if (parts[k].S > 1) need = std::max(need, (int64_t)parts[k].S * (parts[k].hi - parts[k].lo) * per_box);
   // tabulated levels (fmm_table_layout's choice) write FMM_TAB_SLICES partial fields
   int64_t off[FMM_MAX_LEVEL + 1];
-  int f32[FMM_MAX_LEVEL + 1];
-  if (fmm_table_layout(t, kernel, mixed, off, f32) > 0)
+  if (fmm_table_layout(t, kernel, mixed, off) > 0)
     for (int l = 0; l <= t.L; ++l)
       if (off[l] >= 0) need = std::max(need, (int64_t)FMM_TAB_SLICES * (t.box_off[l + 1] - t.box_off[l]) * per_box);
   return need;
@@ -1342,41 +1335,40 @@ static void m2l_launch(const FmmArgs& a, hipStream_t s, const M2lPart& m) {
   }
 }
 
-template <int K, bool F32>
+template <int K>
 static void m2l_table_launch(const FmmArgs& a, hipStream_t s, int l) {
-  if constexpr (K == PFMM_STOKES) {
-    (void)a; (void)s; (void)l;
-  } else {
-    constexpr int T = F32 ? 8 : 4;
-    const FmmTree& t = a.t;
-    const int hn = (t.k1 << l) / 2 * ((t.k2 << l) / 2);
-    const int tiles = 4 * ((hn + T - 1) / T);
-    const int threads = (t.P * t.P + 63) / 64 * 64;
-    const int ksh = (F32 && K == PFMM_LAPLACE) ? level_shift(t, l) : 0;
-    using TT = typename std::conditional<F32, float, double>::type;
-    const int per = 27 / FMM_TAB_SLICES, S = FMM_TAB_SLICES;
-    hipLaunchKernelGGL((fmm_m2l_table_kernel<K, TT, T>), dim3((unsigned)tiles, a.n_dens, S), dim3(threads), 0, s, a,
-                       l, ksh, per);
-    const int64_t per_box = (int64_t)a.n_dens * Fk<K>::NO * t.P * t.P;
-    const int64_t n = (t.box_off[l + 1] - t.box_off[l]) * per_box;
-    hipLaunchKernelGGL(fmm_slice_sum_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a,
-                       t.box_off[l] * per_box, n, S);
-  }
+  constexpr int NO = Fk<K>::NO;
+  const FmmTree& t = a.t;
+  const int P2 = t.P * t.P;
+  const int hn = (t.k1 << l) / 2 * ((t.k2 << l) / 2);
+  const int n_nt = (hn + MM_BOXES - 1) / MM_BOXES, n_mt = (NO * P2 + MM_ROWS - 1) / MM_ROWS;
+  const int per = 27 / FMM_TAB_SLICES;
+  hipLaunchKernelGGL((fmm_m2l_mfma_kernel<K>), dim3(4 * n_nt, n_mt, FMM_TAB_SLICES * a.n_dens), dim3(256), 0, s, a, l,
+                     per, n_nt);
+  const int64_t per_box = (int64_t)a.n_dens * NO * P2;
+  const int64_t n = (t.box_off[l + 1] - t.box_off[l]) * per_box;
+  hipLaunchKernelGGL(fmm_slice_sum_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a,
+                     t.box_off[l] * per_box, n, FMM_TAB_SLICES);
 }
 
-size_t fmm_table_layout(const FmmTree& t, int kernel, bool mixed, int64_t* off, int* f32) {
-  for (int l = 0; l <= FMM_MAX_LEVEL; ++l) { off[l] = -1; f32[l] = 0; }
-  if (kernel == PFMM_STOKES) return 0;     // its 12 samples per point pair cost more to stream than to compute
+size_t fmm_table_layout(const FmmTree& t, int kernel, bool mixed, int64_t* off) {
+  for (int l = 0; l <= FMM_MAX_LEVEL; ++l) off[l] = -1;
   const size_t P2 = (size_t)t.P * t.P;
+  const size_t nc = kernel == PFMM_STOKES ? 2 : 1, no = kernel == PFMM_STOKES ? 6 : 3;
   size_t total = 0;
-  for (int l = t.L; l >= 1; --l) {
+  // a contiguous range of levels, finest first; mixed Stokes keeps sampling
+  // its FP32 levels (measured at N = 2e5: FP32 samples 0.55 ms for the two
+  // finest levels against 0.95 ms of FP64 products), and tabulates the FP64
+  // ones below them
+  int top = t.L;
+  if (kernel == PFMM_STOKES && mixed)
+    while (top >= 1 && level_f32(t, kernel, mixed, top)) --top;
+  for (int l = top; l >= 1; --l) {
     const int64_t boxes = ((int64_t)t.k1 << l) * ((int64_t)t.k2 << l);
     if (boxes < FMM_TAB_MIN_BOXES) break;
-    const bool is32 = level_f32(t, kernel, mixed, l);
-    const size_t bytes = (FMM_CLASSES * P2 * 3 * P2 * (is32 ? 4 : 8) + 255) & ~(size_t)255;
+    const size_t bytes = (FMM_CLASSES * nc * P2 * no * P2 * 8 + 255) & ~(size_t)255;
     if (total + bytes > FMM_TAB_MAX_BYTES) break;
     off[l] = (int64_t)total;
-    f32[l] = is32;
     total += bytes;
   }
   return total;
@@ -1386,19 +1378,17 @@ void fmm_build_tables(int kernel, bool mixed, const FmmArgs& a, char* tab, hipSt
   (void)mixed;
   const FmmTree& t = a.t;
   const int threads = (t.P * t.P + 63) / 64 * 64;
+  const int nc = kernel == PFMM_STOKES ? 2 : 1;
   for (int l = 0; l <= t.L; ++l) {
     if (a.tab_off[l] < 0) continue;
-    const dim3 grid(FMM_CLASSES, t.P * t.P);
-    const bool f32 = a.tab_f32[l];
-    const int ksh = (f32 && kernel == PFMM_LAPLACE) ? level_shift(t, l) : 0;
-    char* base = tab + a.tab_off[l];
-    if (kernel == PFMM_LAPLACE) {
-      if (f32) hipLaunchKernelGGL((fmm_table_build_kernel<PFMM_LAPLACE, float>), grid, dim3(threads), 0, s, a, l, (float*)base, ksh);
-      else hipLaunchKernelGGL((fmm_table_build_kernel<PFMM_LAPLACE, double>), grid, dim3(threads), 0, s, a, l, (double*)base, ksh);
-    } else if (kernel == PFMM_YUKAWA) {
-      if (f32) hipLaunchKernelGGL((fmm_table_build_kernel<PFMM_YUKAWA, float>), grid, dim3(threads), 0, s, a, l, (float*)base, ksh);
-      else hipLaunchKernelGGL((fmm_table_build_kernel<PFMM_YUKAWA, double>), grid, dim3(threads), 0, s, a, l, (double*)base, ksh);
-    }
+    const dim3 grid(FMM_CLASSES, nc * t.P * t.P);
+    double* base = (double*)(tab + a.tab_off[l]);
+    if (kernel == PFMM_LAPLACE)
+      hipLaunchKernelGGL((fmm_table_build_kernel<PFMM_LAPLACE>), grid, dim3(threads), 0, s, a, l, base);
+    else if (kernel == PFMM_YUKAWA)
+      hipLaunchKernelGGL((fmm_table_build_kernel<PFMM_YUKAWA>), grid, dim3(threads), 0, s, a, l, base);
+    else
+      hipLaunchKernelGGL((fmm_table_build_kernel<PFMM_STOKES>), grid, dim3(threads), 0, s, a, l, base);
   }
 }
 
@@ -1415,20 +1405,22 @@ static void launch_fmm_t(const FmmArgs& a, hipStream_t s, hipEvent_t* ev) {
     hipLaunchKernelGGL(fmm_m2m_kernel, dim3((unsigned)nb, a.n_dens * NC), dim3(256), 0, s, a, l, a.n_dens * NC);
   }
   mark(1);
-  // tabulated levels: a suffix lt..L; the others sampled
-  int lt = t.L + 1;
-  while (lt > 0 && a.tab && a.tab_off[lt - 1] >= 0) --lt;
-  M2lPart parts[4];
-  const int np = m2l_parts(t, K, MIXED, parts, t.box_off[lt]);
+  // tabulated levels: one contiguous range lt..lt1 - 1 (FP64 tables and
+  // products); the others sampled
+  int lt = 0, lt1 = 0;
+  if (a.tab) {
+    while (lt <= t.L && a.tab_off[lt] < 0) ++lt;
+    lt1 = lt;
+    while (lt1 <= t.L && a.tab_off[lt1] >= 0) ++lt1;
+  }
+  M2lPart parts[M2L_MAX_PARTS];
+  const int np = m2l_parts(t, K, MIXED, parts, t.box_off[lt], t.box_off[lt1]);
   for (int k = 0; k < np; ++k)
     if (!parts[k].f32) m2l_launch<K, false>(a, s, parts[k]);
-  for (int l = lt; l <= t.L; ++l)
-    if (!a.tab_f32[l]) m2l_table_launch<K, false>(a, s, l);
+  for (int l = lt; l < lt1; ++l) m2l_table_launch<K>(a, s, l);
   mark(2);
   for (int k = 0; k < np; ++k)
     if (parts[k].f32) m2l_launch<K, true>(a, s, parts[k]);
-  for (int l = lt; l <= t.L; ++l)
-    if (a.tab_f32[l]) m2l_table_launch<K, true>(a, s, l);
   mark(3);
   for (int l = 0; l < t.L; ++l) {
     const int64_t nb = t.box_off[l + 2] - t.box_off[l + 1];

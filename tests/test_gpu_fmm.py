@@ -149,13 +149,13 @@ def test_symmetric_leaves_match_one_sided_leaves(env, kernel, beta, prec):
     # targets = sources: each forward pair of leaf boxes evaluated once for
     # both against the same plan and tree with one-sided leaves; equal up to
     # the order of the sums (FP64) and the grouping of the FP32 partial sums
-    # (mixed); three density vectors. First the square cell with 300 points:
+    # (mixed); three density vectors. First the square cell with 100 points:
     # the cost model's tree is the single leaf of the 1 x 1 top grid, which is
-    # its own forward neighbour four times (shifted) and has more points than
-    # a block (the stream is visited once per chunk of them); its 3 x 3
-    # super-grid has no interaction list, so the FMM near part is the direct
-    # near sum. Then the sheared cell at leaf levels 1, 2, 5 and 7 (about one
-    # point per box at 7, most neighbours empty).
+    # its own forward neighbour four times (shifted); its 3 x 3 super-grid
+    # has no interaction list, so the FMM near part is the direct near sum.
+    # Then the sheared cell at leaf levels 1 (thousands of points per box:
+    # the stream is visited once per chunk of a block's points), 2, 5 and 7
+    # (about one point per box, most neighbours empty).
     P, torch, dev = env
     tol = 2e-14 if prec == "fp64" else 3e-7
 
@@ -177,8 +177,8 @@ def test_symmetric_leaves_match_one_sided_leaves(env, kernel, beta, prec):
             assert ep < (bar or tol) and eg < (bar or tol), (label, v, ep, eg)
 
     e1, e2 = CELLS["square"]
-    src, dens, _ = inputs(kernel, e1, e2, 300, 1, seed=37, nd=3)
-    print(f"case symmetric leaves {kernel} {prec} square n=300", flush=True)
+    src, dens, _ = inputs(kernel, e1, e2, 100, 1, seed=37, nd=3)
+    print(f"case symmetric leaves {kernel} {prec} square n=100", flush=True)
     sym = run3("square", src, dens, "fmm", 0, 2)
     assert sym[2]["level"] == 0 and sym[2]["k1"] * sym[2]["k2"] == 1
     # (the direct sum drops screened pairs beyond its cutoff and groups its
