@@ -30,6 +30,15 @@ __device__ __forceinline__ double horner_d(const double (&c)[N], double t) {
   for (int k = N - 2; k >= 0; --k) r = __builtin_fma(r, t, c[k]);
   return r;
 }
+// the first NT coefficients of c, each times s (folded at compile time)
+template <int NT, int N>
+__device__ __forceinline__ float horner_fns(const double (&c)[N], double s, float t) {
+  static_assert(NT <= N, "truncation longer than the series");
+  float r = (float)(c[NT - 1] * s);
+#pragma unroll
+  for (int k = NT - 2; k >= 0; --k) r = __builtin_fmaf(r, t, (float)(c[k] * s));
+  return r;
+}
 // Clenshaw recurrence for a Chebyshev series sum c_k T_k(s)
 template <int N>
 __device__ __forceinline__ double clenshaw_d(const double (&c)[N], double s) {
@@ -126,6 +135,26 @@ __device__ __forceinline__ void bessel_k01_f32_split(float x, float& k0, float& 
     k0 = small ? k0s : k0;
     k1_over_x = small ? k1s : k1_over_x;
   }
+}
+
+// K0(x) and K1(x)/x in FP32 from t = (x / 2)^2 when x <= 2 on every lane of
+// the wavefront (the caller checks that, wave-uniformly): the series of
+// bessel_k01_f32 with ln t = ln 2 log2 t, and K1(x)/x = (1/4 + t (...)) / t,
+// the factors ln 2, -1/2 and 1/4 folded into the coefficients; truncated
+// after t^5 when every lane has t <= 1/4 (as bessel_k01_f32_split)
+__device__ __forceinline__ void bessel_k01_f32_series_t(float t, float& k0, float& k1_over_x) {
+  constexpr double LN2 = 0.69314718055994530942;
+  const float l2 = __builtin_amdgcn_logf(t), it = __builtin_amdgcn_rcpf(t);
+  float i0, p0, j1, p1;
+  if (__all(t <= 0.25f)) {
+    i0 = horner_fns<6>(KS_I0_F32, -0.5 * LN2, t); p0 = horner_fns<6>(KS_P0_F32, 1.0, t);
+    j1 = horner_fns<6>(KS_J1_F32, 0.25 * LN2, t); p1 = horner_fns<6>(KS_P1_F32, 0.25, t);
+  } else {
+    i0 = horner_fns<9>(KS_I0_F32, -0.5 * LN2, t); p0 = horner_fns<9>(KS_P0_F32, 1.0, t);
+    j1 = horner_fns<9>(KS_J1_F32, 0.25 * LN2, t); p1 = horner_fns<9>(KS_P1_F32, 0.25, t);
+  }
+  k0 = __builtin_fmaf(l2, i0, p0);
+  k1_over_x = __builtin_fmaf(t, __builtin_fmaf(l2, j1, -p1), 0.25f) * it;
 }
 
 // The large-argument formulas alone (x > 2 for every lane).

@@ -133,8 +133,15 @@ template <int K, typename real>
 __device__ __forceinline__ void pair_vals(real r2, real beta, real& va, real& vb) {
   constexpr bool F32 = std::is_same<real, float>::value;
   if constexpr (K == PFMM_YUKAWA) {
-    if constexpr (F32) bessel_k01_f32_split(beta * __builtin_amdgcn_sqrtf(r2), va, vb);
-    else bessel_k01_f64(beta * sqrt(r2), va, vb);
+    if constexpr (F32) {
+      // t = (beta r / 2)^2: when every lane is on the series (x <= 2, the
+      // common case of leaf pairs), no square root
+      const float t = r2 * (0.25f * beta * beta);
+      if (__all(t <= 1.0f)) bessel_k01_f32_series_t(t, va, vb);
+      else bessel_k01_f32_split(beta * __builtin_amdgcn_sqrtf(r2), va, vb);
+    } else {
+      bessel_k01_f64(beta * sqrt(r2), va, vb);
+    }
   } else if constexpr (F32) {
     va = __builtin_amdgcn_logf(r2);
     vb = __builtin_amdgcn_rcpf(r2);
@@ -800,7 +807,10 @@ __global__ __launch_bounds__(BS) void fmm_leaf_kernel(FmmArgs a) {
   // the FP32 log2 of r^2 is near zero; its shift 2k is removed in FP64
   const int ksh = NLOG > 0 ? level_shift(t, t.L) : 0;
   const double sc = ldexp(1.0, ksh);
-  const real r2_self = (real)ldexp(1.0, 2 * ksh);
+  // stand-in r^2 of a guarded (r = 0) pair: the log shift's (Laplace, Stokes),
+  // or x = beta r = 1 (Yukawa: the series branch, as the other pairs of a
+  // fine leaf)
+  const real r2_self = K == PFMM_YUKAWA ? (real)(1.0 / (a.beta * a.beta)) : (real)ldexp(1.0, 2 * ksh);
   for (int64_t tc = t0; tc < t1; tc += BS) {
     const int64_t k = tc + tid;
     const bool act = k < t1;
@@ -947,14 +957,17 @@ __global__ __launch_bounds__(BS) void fmm_leaf_sym_kernel(FmmArgs a) {
   const real beta = (real)a.beta;
   const int ksh = NLOG > 0 ? level_shift(t, t.L) : 0;
   const double sc = ldexp(1.0, ksh);
-  const real r2_self = (real)ldexp(1.0, 2 * ksh);
+  // stand-in r^2 of a guarded (r = 0) pair: the log shift's (Laplace, Stokes),
+  // or x = beta r = 1 (Yukawa: the series branch, as the other pairs of a
+  // fine leaf)
+  const real r2_self = K == PFMM_YUKAWA ? (real)(1.0 / (a.beta * a.beta)) : (real)ldexp(1.0, 2 * ksh);
   const size_t qv = (size_t)v * NC * a.n_src;
   const double far = 1.0e3 * (t.d + fabs(t.xi) + t.eta);
   // pairs farther apart than a quarter of that involve padding (r^2 in the
   // scaled units of the differences); their stand-in r^2: the log shift's
   // (Laplace, Stokes) or (1 / beta)^2 (Yukawa: K0(1), K1(1))
   const real dead2 = (real)((0.25 * far * sc) * (0.25 * far * sc));
-  const real r2_dead = K == PFMM_YUKAWA ? (real)(1.0 / (a.beta * a.beta)) : r2_self;
+  const real r2_dead = r2_self;
   for (int64_t tc = t0; tc < t1; tc += BS) {
     const int64_t k = tc + tid;
     const bool act = k < t1;
