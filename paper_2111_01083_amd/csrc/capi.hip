@@ -48,6 +48,15 @@ struct Layout {
   size_t fW, fF, fcount, fFp, fQ, fM;
 };
 
+// point blocks of the counting sort for n points in nbins bins
+static int64_t sort_blocks(int64_t nbins, int64_t n) {
+  const int64_t base = std::min<int64_t>(std::min<int64_t>(256, std::max<int64_t>(1, (1 << 26) / nbins)),
+                                         std::max<int64_t>(1, (n + 1023) / 1024));
+  const int64_t one_pass = std::min<int64_t>(std::max<int64_t>(1, (n + 255) / 256),
+                                             std::max<int64_t>(1, (1 << 21) / nbins));
+  return std::max(base, one_pass);
+}
+
 void plan_layout(const pfmm_plan_s* p, int64_t ns, int64_t nt, Layout& L, int64_t forced_split = 0) {
   const bool mixed = p->precision == PFMM_MIXED;
   const int nc = p->kernel == PFMM_STOKES ? 2 : 1;
@@ -86,10 +95,11 @@ void plan_layout(const pfmm_plan_s* p, int64_t ns, int64_t nt, Layout& L, int64_
     L.bin_w = W / L.nbx;
     L.bin_h = H / L.nby;
     L.key = take(4 * nt); L.perm = take(4 * nt); L.stx = take(8 * nt); L.sty = take(8 * nt);
-    // stable placement in blocks of bp consecutive points (at most 256 blocks)
+    // stable placement in blocks of bp consecutive points: at most 256
+    // blocks, or more, down to one rank pass of 256 points per block, while
+    // the count table stays within 2^21 entries
     const int64_t nbins = (int64_t)L.nbx * L.nby;
-    L.nblk = (int)std::min<int64_t>(std::min<int64_t>(256, std::max<int64_t>(1, (1 << 26) / nbins)),
-                                    std::max<int64_t>(1, (nt + 1023) / 1024));
+    L.nblk = (int)sort_blocks(nbins, nt);
     L.bp = std::max<int64_t>(1, (nt + L.nblk - 1) / L.nblk);
     L.cnt = take(4 * (size_t)L.nbx * L.nby * L.nblk);
     L.seg = take(4 * (((size_t)L.nbx * L.nby * L.nblk + SCAN_SEG - 1) / SCAN_SEG));
@@ -124,8 +134,7 @@ void plan_layout(const pfmm_plan_s* p, int64_t ns, int64_t nt, Layout& L, int64_
     // sources in leaf-box order: the sorted targets when they are the sources
     if (!p->self_exclude) {
       const int64_t nbins = (int64_t)L.nbx * L.nby;
-      L.snblk = (int)std::min<int64_t>(std::min<int64_t>(256, std::max<int64_t>(1, (1 << 26) / nbins)),
-                                       std::max<int64_t>(1, (ns + 1023) / 1024));
+      L.snblk = (int)sort_blocks(nbins, ns);
       L.sbp = std::max<int64_t>(1, (ns + L.snblk - 1) / L.snblk);
       L.skey = take(4 * ns); L.sperm = take(4 * ns); L.ssx = take(8 * ns); L.ssy = take(8 * ns);
       L.scnt = take(4 * (size_t)nbins * L.snblk);
@@ -594,8 +603,10 @@ int pfmm::eval_core(pfmm_plan_t p, int64_t ns, const double* src_xy, const doubl
   }
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
   if (p->profile) {
+    // timing only (read after a synchronisation): no system-scope fence,
+    // which would write back and invalidate the caches the next kernels use
     for (int k = 0; k < 3; ++k)
-      if (hipEventCreate(&ev[k]) != hipSuccess) {
+      if (hipEventCreateWithFlags(&ev[k], hipEventDisableSystemFence) != hipSuccess) {
         for (int q = 0; q < k; ++q) (void)hipEventDestroy(ev[q]);
         return PFMM_EHIP;
       }
@@ -661,7 +672,7 @@ int pfmm::eval_core(pfmm_plan_t p, int64_t ns, const double* src_xy, const doubl
     if (p->profile) {
       timed = true;
       for (int k = 0; k < 6 && timed; ++k)
-        if (hipEventCreate(&fev[k]) != hipSuccess) {
+        if (hipEventCreateWithFlags(&fev[k], hipEventDisableSystemFence) != hipSuccess) {
           for (int q = 0; q < k; ++q) (void)hipEventDestroy(fev[q]);
           timed = false;
         }
