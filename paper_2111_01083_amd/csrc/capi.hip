@@ -45,7 +45,7 @@ struct Layout {
   size_t skey, sperm, scnt, sseg, ssx, ssy;
   int snblk;
   int64_t sbp;
-  size_t fW, fF, fcount, fFp, fQ, fM;
+  size_t fW, fF, fcount, fFp, fQ, fM, fcheb;
 };
 
 // point blocks of the counting sort for n points in nbins bins
@@ -127,7 +127,7 @@ void plan_layout(const pfmm_plan_s* p, int64_t ns, int64_t nt, Layout& L, int64_
   L.near_part = take(8 * L.part_stride * L.n_splits);
   L.qb64 = L.qb32 = 0;
   L.mu_chunk = 0;
-  L.skey = L.sperm = L.scnt = L.sseg = L.ssx = L.ssy = L.fW = L.fF = L.fcount = L.fFp = L.fQ = L.fM = 0;
+  L.skey = L.sperm = L.scnt = L.sseg = L.ssx = L.ssy = L.fW = L.fF = L.fcount = L.fFp = L.fQ = L.fM = L.fcheb = 0;
   L.snblk = 0;
   L.sbp = 0;
   if (L.fmm) {
@@ -148,6 +148,7 @@ void plan_layout(const pfmm_plan_s* p, int64_t ns, int64_t nt, Layout& L, int64_
     L.fFp = take(8 * (size_t)fmm_slice_doubles(L.ft, p->kernel, mixed, p->n_dens));
     L.fQ = take(8 * nbox * p->n_dens * nc);
     if (fmm_symmetric_leaves(p)) L.fM = take(8 * (size_t)FMM_SLOTS * p->n_dens * no * nt);
+    L.fcheb = take(8 * (size_t)FMM_CHEB_DOUBLES);
   }
   if (L.mutual) {
     L.qb64 = take(8 * (size_t)p->n_dens * nc * ns);
@@ -667,6 +668,7 @@ int pfmm::eval_core(pfmm_plan_t p, int64_t ns, const double* src_xy, const doubl
     }
     fa.part = na.part;
     fa.M = L.fM ? D_(r, L.fM) : nullptr;
+    fa.cheb = D_(r, L.fcheb);
     hipEvent_t fev[6] = {};
     bool timed = false;
     if (p->profile) {

@@ -51,12 +51,16 @@ struct FmmArgs {
   const char* tab;
   int64_t tab_off[FMM_MAX_LEVEL + 1];
   double* part;                       // near part [n_dens * NOUT][n_trg], leaf-box target order
+  // Chebyshev points, barycentric weights and transfer matrices of order P
+  // (FMM_CHEB_DOUBLES), computed once per evaluation by the first launch
+  double* cheb;
   // symmetric leaves (targets are the sources): the sums at the points of a
   // box's forward neighbours, [FMM_SLOTS][n_dens * NOUT][n_trg]; NULL: one-sided
   double* M;
 };
 
 constexpr int FMM_SLOTS = 4;          // directions of the backward neighbours of a leaf box
+constexpr int FMM_CHEB_DOUBLES = 2 * FMM_PMAX + 2 * FMM_PMAX * FMM_PMAX;
 
 // the tree for n points: k1 x k2 top boxes and the leaf level from a cost
 // model (pairs of the leaf neighbour sums against the node pairs of the

@@ -100,6 +100,17 @@ __device__ void transfer_init(int P, const double* s, const double* w, double* T
   }
 }
 
+// a.cheb holds s [FMM_PMAX], w [FMM_PMAX] and T [2 P][P] (transfer_init's
+// layout); each block copies what it needs into LDS (s, w, T may be null)
+__device__ void cheb_load(const FmmArgs& a, int P, double* s, double* w, double* T) {
+  for (int k = threadIdx.x; k < P; k += blockDim.x) {
+    s[k] = a.cheb[k];
+    if (w) w[k] = a.cheb[FMM_PMAX + k];
+  }
+  if (T)
+    for (int k = threadIdx.x; k < 2 * P * P; k += blockDim.x) T[k] = a.cheb[2 * FMM_PMAX + k];
+}
+
 // Lagrange basis of the P points at x into registers (entries P.. are zero)
 __device__ __forceinline__ void basis_regs(int P, const double* s, const double* w, double x,
                                            double (&l)[FMM_PMAX]) {
@@ -227,6 +238,16 @@ __device__ __forceinline__ void fmm_outputs(const double* A, double* o, double b
 
 }  // namespace
 
+// the tables of cheb_load, once per evaluation (one block)
+__global__ __launch_bounds__(64) void fmm_cheb_kernel(FmmArgs a) {
+  const int P = a.t.P;
+  __shared__ double s_s[FMM_PMAX], s_w[FMM_PMAX];
+  cheb_init(P, s_s, s_w);
+  __syncthreads();
+  for (int k = threadIdx.x; k < P; k += blockDim.x) { a.cheb[k] = s_s[k]; a.cheb[FMM_PMAX + k] = s_w[k]; }
+  transfer_init(P, s_s, s_w, a.cheb + 2 * FMM_PMAX);
+}
+
 // ---------------------------------------------------------------------------
 // P2M: equivalent densities of each leaf box (grid: leaf boxes x densities)
 // ---------------------------------------------------------------------------
@@ -237,10 +258,13 @@ __global__ __launch_bounds__(FMM_CHUNK) void fmm_p2m_kernel(FmmArgs a) {
   const int box = blockIdx.x, v = blockIdx.y, tid = threadIdx.x;
   const Lvl lv = level_of(t, t.L);
   const int i = box % lv.n1, j = box / lv.n1;
+  // basis values [a][point], rows FMM_CHUNK + 1 apart (odd: the rows that
+  // the threads of a wavefront read at one point fall in distinct banks)
+  constexpr int LDL = FMM_CHUNK + 1;
   __shared__ double s_s[FMM_PMAX], s_w[FMM_PMAX];
-  __shared__ double s_l1[FMM_PMAX * FMM_CHUNK], s_l2[FMM_PMAX * FMM_CHUNK];
+  __shared__ double s_l1[FMM_PMAX * LDL], s_l2[FMM_PMAX * LDL];
   __shared__ double s_q[NC][FMM_CHUNK];
-  cheb_init(P, s_s, s_w);
+  cheb_load(a, P, s_s, s_w, nullptr);
   const int64_t b0 = leaf_begin(a.scnt, a.snblk, box), b1 = leaf_end(a.scnt, a.snblk, box);
   double acc[4][NC];
 #pragma unroll
@@ -253,8 +277,8 @@ __global__ __launch_bounds__(FMM_CHUNK) void fmm_p2m_kernel(FmmArgs a) {
     if (tid < nch) {
       const int64_t k = c0 + tid;
       const double u2 = a.sy[k] / t.eta, u1 = (a.sx[k] - t.xi * u2) / t.d;
-      lagrange(P, s_s, s_w, 2.0 * ((u1 + 0.5) * lv.n1 - i) - 1.0, s_l1 + tid, FMM_CHUNK);
-      lagrange(P, s_s, s_w, 2.0 * ((u2 + 0.5) * lv.n2 - j) - 1.0, s_l2 + tid, FMM_CHUNK);
+      lagrange(P, s_s, s_w, 2.0 * ((u1 + 0.5) * lv.n1 - i) - 1.0, s_l1 + tid, LDL);
+      lagrange(P, s_s, s_w, 2.0 * ((u2 + 0.5) * lv.n2 - j) - 1.0, s_l2 + tid, LDL);
 #pragma unroll
       for (int c = 0; c < NC; ++c) s_q[c][tid] = a.sq[((size_t)v * NC + c) * a.n_src + k];
     }
@@ -263,8 +287,8 @@ __global__ __launch_bounds__(FMM_CHUNK) void fmm_p2m_kernel(FmmArgs a) {
     for (int r = 0; r < 4; ++r) {
       const int node = tid + r * FMM_CHUNK;
       if (node < P2) {
-        const double* l1 = s_l1 + (node / P) * FMM_CHUNK;
-        const double* l2 = s_l2 + (node % P) * FMM_CHUNK;
+        const double* l1 = s_l1 + (node / P) * LDL;
+        const double* l2 = s_l2 + (node % P) * LDL;
         for (int jj = 0; jj < nch; ++jj) {
           const double g = l1[jj] * l2[jj];
 #pragma unroll
@@ -315,9 +339,7 @@ __global__ __launch_bounds__(256) void fmm_m2m_kernel(FmmArgs a, int l, int qn) 
   const int i = box % lv.n1, j = box / lv.n1;
   __shared__ double s_s[FMM_PMAX], s_w[FMM_PMAX];
   __shared__ double s_T[2 * FMM_PMAX * FMM_PMAX], s_c[FMM_PMAX * FMM_PMAX], s_t[FMM_PMAX * FMM_PMAX];
-  cheb_init(P, s_s, s_w);
-  __syncthreads();
-  transfer_init(P, s_s, s_w, s_T);
+  cheb_load(a, P, s_s, s_w, s_T);
   double acc[2] = {0.0, 0.0};
   int cnt = 0;
   for (int h = 0; h < 4; ++h) {
@@ -404,7 +426,7 @@ __global__ __launch_bounds__(512) void fmm_m2l_kernel(FmmArgs a, int64_t gb0, in
   __shared__ double s_s[FMM_PMAX];
   __shared__ SrcNode<real> s_src[FMM_PMAX * FMM_PMAX];
   __shared__ double s_wsum[8][NC];
-  cheb_init(P, s_s, nullptr);
+  cheb_load(a, P, s_s, nullptr, nullptr);
   __syncthreads();
   const bool act = tid < P2;
   const int na = act ? tid / P : 0, nb = act ? tid % P : 0;
@@ -679,9 +701,7 @@ __global__ __launch_bounds__(256) void fmm_l2l_kernel(FmmArgs a, int l, int no_t
   const int hi = i & 1, hj = j & 1;
   __shared__ double s_s[FMM_PMAX], s_w[FMM_PMAX];
   __shared__ double s_T[2 * FMM_PMAX * FMM_PMAX], s_p[FMM_PMAX * FMM_PMAX], s_t[FMM_PMAX * FMM_PMAX];
-  cheb_init(P, s_s, s_w);
-  __syncthreads();
-  transfer_init(P, s_s, s_w, s_T);
+  cheb_load(a, P, s_s, s_w, s_T);
   const int64_t pg = t.box_off[l] + (int64_t)(j >> 1) * lp.n1 + (i >> 1);
   const int64_t cg = t.box_off[l + 1] + box;
   for (int n = tid; n < P2; n += 256) s_p[n] = a.F[((size_t)pg * no_total + c) * P2 + n];
@@ -798,7 +818,7 @@ __global__ __launch_bounds__(BS) void fmm_leaf_kernel(FmmArgs a) {
   __shared__ double s_F[6 * FMM_PMAX * FMM_PMAX];
   __shared__ double s_x[BS], s_y[BS], s_q[NC][BS];
   __shared__ float s_q32[NC][BS];
-  cheb_init(P, s_s, s_w);
+  cheb_load(a, P, s_s, s_w, nullptr);
   for (int n = tid; n < NO * P2; n += BS)
     s_F[n] = a.F[((size_t)gb * a.n_dens * NO + v * NO) * P2 + n];
   __syncthreads();
@@ -933,7 +953,7 @@ __global__ __launch_bounds__(BS) void fmm_leaf_sym_kernel(FmmArgs a) {
   __shared__ double s_col[NW][NA][64];
   __shared__ int64_t s_g0[FMM_SLOTS], s_len[FMM_SLOTS];
   __shared__ double s_shx[FMM_SLOTS], s_shy[FMM_SLOTS];
-  cheb_init(P, s_s, s_w);
+  cheb_load(a, P, s_s, s_w, nullptr);
   for (int n = tid; n < NO * P2; n += BS)
     s_F[n] = a.F[((size_t)gb * a.n_dens * NO + v * NO) * P2 + n];
   if (tid < FMM_SLOTS) {
@@ -1412,6 +1432,7 @@ static void launch_fmm_t(const FmmArgs& a, hipStream_t s, hipEvent_t* ev) {
   const int64_t nleaf = t.box_off[t.L + 1] - t.box_off[t.L];
   auto mark = [&](int k) { if (ev) (void)hipEventRecord(ev[k], s); };
   mark(0);
+  hipLaunchKernelGGL(fmm_cheb_kernel, dim3(1), dim3(64), 0, s, a);
   hipLaunchKernelGGL(fmm_p2m_kernel<NC>, dim3((unsigned)nleaf, a.n_dens), dim3(FMM_CHUNK), 0, s, a);
   for (int l = t.L - 1; l >= 0; --l) {
     const int64_t nb = t.box_off[l + 1] - t.box_off[l];
