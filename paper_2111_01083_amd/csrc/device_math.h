@@ -173,6 +173,88 @@ __device__ __forceinline__ void bessel_k01_f32_far(float x, float& k0, float& k1
   k1_over_x = e * rx * horner_f(KF1_F32, rx);
 }
 
+// FP64 plane-wave factors (far part). The arguments are phases and
+// exponents of plane waves over one cell: moderate, so a short argument
+// reduction is exact and the polynomials are the Taylor series of the
+// functions on the reduced interval (coefficients 1/n!, to the first term
+// below 2^-60 relative).
+//
+// sin and cos: x = k pi/2 + r, pi/2 in three parts (Cody-Waite), the first
+// two with 33 significant bits so that k times them is exact for |k| < 2^20;
+// |r| <= pi/4, sin to r^17 and cos to r^16; the quadrant is k mod 4.
+// |x| > 1e5 takes the library routine.
+__device__ __forceinline__ void sincos_pw(double x, double& s, double& c) {
+  if (fabs(x) > 1.0e5) { sincos(x, &s, &c); return; }
+  const double k = rint(x * 0.6366197723675814);          // 2/pi
+  double r = fma(-k, 1.5707963267341256, x);
+  r = fma(-k, 6.077100506303966e-11, r);
+  r = fma(-k, 2.0222662487959506e-21, r);
+  const double r2 = r * r;
+  double ps = 1.0 / 355687428096000.0;                    // 1/17!
+  ps = fma(ps, r2, -1.0 / 1307674368000.0);               // -1/15!
+  ps = fma(ps, r2, 1.0 / 6227020800.0);
+  ps = fma(ps, r2, -1.0 / 39916800.0);
+  ps = fma(ps, r2, 1.0 / 362880.0);
+  ps = fma(ps, r2, -1.0 / 5040.0);
+  ps = fma(ps, r2, 1.0 / 120.0);
+  ps = fma(ps, r2, -1.0 / 6.0);
+  const double sr = fma(r * r2, ps, r);
+  double pc = 1.0 / 20922789888000.0;                     // 1/16!
+  pc = fma(pc, r2, -1.0 / 87178291200.0);                 // -1/14!
+  pc = fma(pc, r2, 1.0 / 479001600.0);
+  pc = fma(pc, r2, -1.0 / 3628800.0);
+  pc = fma(pc, r2, 1.0 / 40320.0);
+  pc = fma(pc, r2, -1.0 / 720.0);
+  pc = fma(pc, r2, 1.0 / 24.0);
+  pc = fma(pc, r2, -0.5);
+  const double cr = fma(r2, pc, 1.0);
+  const int q = (int)(int64_t)k & 3;
+  s = q == 0 ? sr : q == 1 ? cr : q == 2 ? -sr : -cr;
+  c = q == 0 ? cr : q == 1 ? -sr : q == 2 ? -cr : sr;
+}
+
+// e^r - 1 for |r| <= ln 2 / 2: the Taylor series without its constant term,
+// to r^13
+__device__ __forceinline__ double expm1_taylor(double r) {
+  double p = 1.0 / 6227020800.0;                          // 1/13!
+  p = fma(p, r, 1.0 / 479001600.0);
+  p = fma(p, r, 1.0 / 39916800.0);
+  p = fma(p, r, 1.0 / 3628800.0);
+  p = fma(p, r, 1.0 / 362880.0);
+  p = fma(p, r, 1.0 / 40320.0);
+  p = fma(p, r, 1.0 / 5040.0);
+  p = fma(p, r, 1.0 / 720.0);
+  p = fma(p, r, 1.0 / 120.0);
+  p = fma(p, r, 1.0 / 24.0);
+  p = fma(p, r, 1.0 / 6.0);
+  p = fma(p, r, 0.5);
+  return fma(p, r * r, r);
+}
+
+// e^x: x = k ln 2 + r, ln 2 in two parts (the first with 32 significant
+// bits), |r| <= ln 2 / 2, e^r from its series, times 2^k; |x| > 700 takes the
+// library routine
+__device__ __forceinline__ double exp_pw(double x) {
+  if (fabs(x) > 700.0) return exp(x);
+  const double k = rint(x * 1.4426950408889634);          // 1/ln 2
+  double r = fma(-k, 0.6931471806019545, x);
+  r = fma(-k, -4.2009150726810846e-11, r);
+  return ldexp(1.0 + expm1_taylor(r), (int)k);
+}
+
+// e^x - 1 without cancellation near 0
+__device__ __forceinline__ double expm1_pw(double x) {
+  return fabs(x) <= 0.34657359027997264 ? expm1_taylor(x) : exp_pw(x) - 1.0;
+}
+
+// 1/x for normal x: the hardware estimate and two Newton steps (each squares
+// the relative error)
+__device__ __forceinline__ double recip_pw(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(fma(-x, y, 1.0), y, y);
+  return fma(fma(-x, y, 1.0), y, y);
+}
+
 // K0(x) and K1(x)/x for x > 0 in FP64.
 __device__ __forceinline__ void bessel_k01_f64(double x, double& k0, double& k1_over_x) {
   if (x <= 2.0) {

@@ -1188,11 +1188,11 @@ __device__ __forceinline__ cplx cmuli(cplx a) { return {-a.i, a.r}; }  // i*a
 // e^{a + i b} - 1 and e^{-a + i b} - 1 without cancellation for small |a|,
 // |b|, sharing their transcendentals (e^{-a} - 1 = -(e^a - 1) e^{-a})
 __device__ __forceinline__ void cexpm1_pair(double a, double b, cplx& plus, cplx& minus) {
-  double s, c;
-  sincos(b, &s, &c);
-  const double sh = sin(0.5 * b);
-  const double cm1 = -2 * sh * sh;            // cos b - 1
-  const double em = expm1(a), e = em + 1.0, ie = 1.0 / e;
+  double sh, ch;
+  sincos_pw(0.5 * b, sh, ch);
+  const double s = 2.0 * sh * ch, cm1 = -2.0 * sh * sh;   // sin b, cos b - 1
+  const double c = 1.0 + cm1;
+  const double em = expm1_pw(a), e = em + 1.0, ie = recip_pw(e);
   plus = {em * c + cm1, e * s};
   minus = {-em * ie * c + cm1, ie * s};
 }
@@ -1248,8 +1248,8 @@ __global__ __launch_bounds__(FAR_R_BLOCK) void far_R_kernel(FarRArgs a) {
       for (int t = slice; t < nt; t += n_slices) {
         const double x = s_x[t], y = s_y[t];
         double sn, cs;
-        sincos(al * x, &sn, &cs);
-        const double ep = exp(aa * y), em = 1.0 / ep;
+        sincos_pw(al * x, sn, cs);
+        const double ep = exp_pw(aa * y), em = recip_pw(ep);
         const cplx ph = {cs, -sn};
         const cplx ps = cscale(ph, ep), pn = cscale(ph, em);
 #pragma unroll
@@ -1277,8 +1277,8 @@ __global__ __launch_bounds__(FAR_R_BLOCK) void far_R_kernel(FarRArgs a) {
         const double x = a.ew_c * s_x[t] - a.ew_s * s_y[t], y = a.ew_s * s_x[t] + a.ew_c * s_y[t];
         if constexpr (K == PFMM_YUKAWA) {
           double sn, cs;
-          sincos(lam * y, &sn, &cs);
-          const double ep = exp(kap * x), em = 1.0 / ep;
+          sincos_pw(lam * y, sn, cs);
+          const double ep = exp_pw(kap * x), em = recip_pw(ep);
           const cplx pw = {ep * cs, -ep * sn}, pe = {em * cs, -em * sn};
 #pragma unroll
           for (int d = 0; d < DG; ++d) {
@@ -1552,9 +1552,9 @@ void launch_far_D(const FarDArgs& a, hipStream_t s) {
 // so FP32 factors (about 1e-7 each) would show as a 1e-6 relative error of a
 // Laplace or Stokes potential, at about 1 % of an evaluation's time
 __device__ __forceinline__ void wave_factors(double phase, double expo, double& sn, double& cs, double& ep, double& em) {
-  sincos(phase, &sn, &cs);
-  ep = exp(expo);
-  em = 1.0 / ep;
+  sincos_pw(phase, sn, cs);
+  ep = exp_pw(expo);
+  em = recip_pw(ep);
 }
 
 template <int K, int DG>
