@@ -241,6 +241,10 @@ def main():
     ap.add_argument("--n", type=int, default=200000, help="sources (= targets) per cell")
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--sample", type=int, default=16, help="oracle targets per kernel")
+    ap.add_argument("--streams", type=int, default=2, choices=(1, 2),
+                    help="HIP streams of a step: 2 = the Yukawa and Stokes evaluations run concurrently")
+    ap.add_argument("--no-one-stream", action="store_true",
+                    help="skip the comparison pass with both evaluations on one stream")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-direct", action="store_true",
                     help="skip the one-step context run of the direct near-image sum")
@@ -323,20 +327,37 @@ def main():
             plans.append(p); outs.append((pot, grad)); wss.append(ws)
         return plans, outs, wss
 
-    def step(plans, outs, wss):
-        for (kern, beta, dens), p, (pot, grad), ws in zip(cases, plans, outs, wss):
-            P.pfmm_eval(p, d_src, dens, None, out_pot=pot, out_grad=grad, workspace=ws)
+    # two streams (default priority): the step's two evaluations are
+    # independent, and each has phases that do not fill the GPU (binning,
+    # the coarse levels of the tree, the far part), which the other's
+    # kernels fill; the step starts after, and ends with, the main stream
+    side = [torch.cuda.Stream(), torch.cuda.Stream()]
 
-    def timed(prec, steps, warmup):
+    def step(plans, outs, wss, nstreams=1):
+        if nstreams == 1:
+            for (kern, beta, dens), p, (pot, grad), ws in zip(cases, plans, outs, wss):
+                P.pfmm_eval(p, d_src, dens, None, out_pot=pot, out_grad=grad, workspace=ws)
+            return
+        main = torch.cuda.current_stream()
+        ev = torch.cuda.Event()
+        ev.record(main)
+        for (kern, beta, dens), p, (pot, grad), ws, st in zip(cases, plans, outs, wss, side):
+            st.wait_event(ev)
+            with torch.cuda.stream(st):
+                P.pfmm_eval(p, d_src, dens, None, out_pot=pot, out_grad=grad, workspace=ws, stream=st)
+        for st in side:
+            main.wait_stream(st)
+
+    def timed(prec, steps, warmup, nstreams=1):
         plans, outs, wss = make(prec)
         for _ in range(warmup):
-            step(plans, outs, wss)
+            step(plans, outs, wss, nstreams)
         torch.cuda.synchronize()
         for p in plans:
             p.stage_times()      # drop warm-up events
         t0 = time.perf_counter()
         for _ in range(steps):
-            step(plans, outs, wss)
+            step(plans, outs, wss, nstreams)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         stages = [p.stage_times() + p.fmm_stage_times() for p in plans]
@@ -344,11 +365,21 @@ def main():
         works = [fmm_work(p, src, n) for p in plans]
         return (t1 - t0) / steps, stages, res, works
 
-    print(f"bench: N={n} mixed steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
-    ms_mixed_s, st_mixed, res_mixed, work_mixed = timed("mixed", args.steps, args.warmup)
-    print(f"bench: mixed {ms_mixed_s * 1e3:.1f} ms/step", file=sys.stderr, flush=True)
-    ms64_s, st64, res64, work64 = timed("fp64", args.fp64_steps, 1)
-    print(f"bench: fp64 {ms64_s * 1e3:.1f} ms/step", file=sys.stderr, flush=True)
+    print(f"bench: N={n} mixed steps={args.steps} warmup={args.warmup} streams={args.streams}", file=sys.stderr,
+          flush=True)
+    ms_mixed_s, st_mixed, res_mixed, work_mixed = timed("mixed", args.steps, args.warmup, args.streams)
+    print(f"bench: mixed {ms_mixed_s * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
+    ms64_s, st64, res64, work64 = timed("fp64", args.fp64_steps, 1, args.streams)
+    print(f"bench: fp64 {ms64_s * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
+    one = one64 = None
+    if args.streams == 2 and not args.no_one_stream:
+        # the same steps with both evaluations on one stream: every kernel
+        # alone on the GPU, so that the HIP events between its launches time
+        # the kernels themselves (with two streams they also hold the waits
+        # for the other stream's kernels); the rooflines come from these
+        one = timed("mixed", args.steps, args.warmup, 1)
+        print(f"bench: mixed, one stream {one[0] * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
+        one64 = timed("fp64", args.fp64_steps, 1, 1)
 
     targets_per_step = 2 * n
     value = targets_per_step / ms_mixed_s
@@ -402,8 +433,11 @@ def main():
                            "eval_ms": round(total_ms / max(cnt, 1), 3), "tree": w, "rooflines": ent}
         return out_k
 
-    roof_all = stage_roofs("mixed", st_mixed, work_mixed)
-    roof64 = stage_roofs("fp64", st64, work64)
+    roof_main = stage_roofs("mixed", st_mixed, work_mixed)
+    roof64_main = stage_roofs("fp64", st64, work64)
+    # rooflines from the one-stream passes when the timed steps overlap
+    roof_all = stage_roofs("mixed", one[1], one[3]) if one is not None else roof_main
+    roof64 = stage_roofs("fp64", one64[1], one64[3]) if one64 is not None else roof64_main
     # the dominant kernel: the longest FMM stage over both kernels of a step
     dom_k, dom_s = max(((k, s_) for k in roof_all for s_ in roof_all[k]["rooflines"]),
                        key=lambda ks: roof_all[ks[0]]["rooflines"][ks[1]]["ms_per_launch"])
@@ -411,6 +445,16 @@ def main():
     d64_k, d64_s = max(((k, s_) for k in roof64 for s_ in roof64[k]["rooflines"]),
                        key=lambda ks: roof64[ks[0]]["rooflines"][ks[1]]["ms_per_launch"])
     roofline64 = dict(roof64[d64_k]["rooflines"][d64_s])
+    one_stream = None
+    if one is not None:
+        # context: the step on one stream, and the stage times of the timed
+        # (overlapped) steps, which include the waits for the other stream
+        one_stream = {"value": round(targets_per_step / one[0], 1), "ms_per_step": round(one[0] * 1e3, 3),
+                      "fp64_value": round(targets_per_step / one64[0], 1),
+                      "fp64_ms_per_step": round(one64[0] * 1e3, 3),
+                      "rooflines_from": "these one-stream passes (roofline, roofline_all, fp64_gpu.roofline)"}
+        one_stream["stages_two_streams"] = {k: v["stages_ms_per_eval"] for k, v in roof_main.items()}
+        one_stream["fp64_stages_two_streams"] = {k: v["stages_ms_per_eval"] for k, v in roof64_main.items()}
 
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "targets/s", "n_gpus": 1,
@@ -420,13 +464,15 @@ def main():
         "config": {"workload": "square cell, N=200000 uniform sources = targets, modified Helmholtz "
                                "beta=10 + Stokes, pot+grad, tol 1e-6",
                    "n": n, "tol": 1e-6, "precision": "mixed (FP32 pairs, FP64 accumulation and far field)",
-                   "targets_per_step": targets_per_step},
+                   "targets_per_step": targets_per_step, "streams": args.streams},
         "fp64_gpu": {"value": round(fp64_value, 1), "unit": "targets/s", "ms_per_step": round(ms64_s * 1e3, 3),
                      "steps": args.fp64_steps, "roofline": roofline64, "kernels": roof64},
         "speedup_mixed_vs_fp64": round(value / fp64_value, 2),
         "roofline": roofline,
         "roofline_all": roof_all,
     }
+    if one_stream is not None:
+        out["one_stream"] = one_stream
     if not args.no_direct:
         # context: the same mixed step with the near part as the direct sum
         # over the near images (symmetric pair evaluation), one step
