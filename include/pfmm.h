@@ -43,12 +43,14 @@
  *    256-byte aligned. Device allocations: the plan's small table (a few
  *    KB): pfmm_plan_upload makes it, and the first pfmm_eval on a device
  *    calls pfmm_plan_upload itself (hipMalloc plus a synchronous copy) when
- *    the table is not there yet; and, for Laplace/Yukawa evaluations whose
- *    near part takes the FMM, its interaction-list tables (MB to at most
- *    1 GiB, one per plan): the first evaluation of a tree size allocates
- *    them and builds them on its stream, a later evaluation with another
- *    tree (see pfmm_fmm_tree) frees and rebuilds them. Other evaluations
- *    allocate nothing. A plan must not be evaluated on two streams at once
+ *    the table is not there yet; and, for evaluations whose near part takes
+ *    the FMM, its interaction-list tables (FP64 kernel samples per level and
+ *    box-offset class: every Laplace and Yukawa level with at least 64
+ *    boxes, the FP64-sampled Stokes levels; MB to at most 1 GiB, one set per
+ *    plan): the first evaluation of a tree size allocates them and builds
+ *    them on its stream, a later evaluation with another tree (see
+ *    pfmm_fmm_tree) frees and rebuilds them. Other evaluations allocate
+ *    nothing. A plan must not be evaluated on two streams at once
  *    with sizes that give different FMM trees.
  *  - n_src and n_trg (per cell in a batch) are at most PFMM_MAX_POINTS
  *    (point indices are 32-bit inside the kernels); larger sizes are

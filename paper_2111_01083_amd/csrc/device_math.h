@@ -255,6 +255,36 @@ __device__ __forceinline__ double recip_pw(double x) {
   return fma(fma(-x, y, 1.0), y, y);
 }
 
+// the first NT coefficients of c, each times s (FP64)
+template <int NT, int N>
+__device__ __forceinline__ double horner_dns(const double (&c)[N], double s, double t) {
+  static_assert(NT <= N, "truncation longer than the series");
+  double r = c[NT - 1] * s;
+#pragma unroll
+  for (int k = NT - 2; k >= 0; --k) r = fma(r, t, c[k] * s);
+  return r;
+}
+
+// K0(x) and K1(x)/x in FP64 from t = (x / 2)^2 when x <= 2 on every lane of
+// the wavefront (the caller checks that, wave-uniformly): the series of
+// bessel_k01_f64 with K1(x)/x = (1/4 + t (...)) / t, the factors -1/2 and
+// 1/4 folded into the coefficients, 1/t by Newton steps; the first 10 terms
+// when every lane has t <= 1/4 (the next is below 2e-19 relative: the
+// coefficients fall like 1/(k!)^2)
+__device__ __forceinline__ void bessel_k01_f64_series_t(double t, double& k0, double& k1_over_x) {
+  const double lt = log(t), it = recip_pw(t);
+  double i0, p0, j1, p1;
+  if (__all(t <= 0.25)) {
+    i0 = horner_dns<10>(KS_I0_F64, -0.5, t); p0 = horner_dns<10>(KS_P0_F64, 1.0, t);
+    j1 = horner_dns<10>(KS_J1_F64, 0.25, t); p1 = horner_dns<10>(KS_P1_F64, 0.25, t);
+  } else {
+    i0 = horner_dns<13>(KS_I0_F64, -0.5, t); p0 = horner_dns<13>(KS_P0_F64, 1.0, t);
+    j1 = horner_dns<13>(KS_J1_F64, 0.25, t); p1 = horner_dns<13>(KS_P1_F64, 0.25, t);
+  }
+  k0 = fma(lt, i0, p0);
+  k1_over_x = fma(t, fma(lt, j1, -p1), 0.25) * it;
+}
+
 // K0(x) and K1(x)/x for x > 0 in FP64.
 __device__ __forceinline__ void bessel_k01_f64(double x, double& k0, double& k1_over_x) {
   if (x <= 2.0) {

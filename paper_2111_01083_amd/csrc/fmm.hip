@@ -151,7 +151,9 @@ __device__ __forceinline__ void pair_vals(real r2, real beta, real& va, real& vb
       if (__all(t <= 1.0f)) bessel_k01_f32_series_t(t, va, vb);
       else bessel_k01_f32_split(beta * __builtin_amdgcn_sqrtf(r2), va, vb);
     } else {
-      bessel_k01_f64(beta * sqrt(r2), va, vb);
+      const double t = r2 * (0.25 * beta * beta);
+      if (__all(t <= 1.0)) bessel_k01_f64_series_t(t, va, vb);
+      else bessel_k01_f64(beta * sqrt(r2), va, vb);
     }
   } else if constexpr (F32) {
     va = __builtin_amdgcn_logf(r2);
