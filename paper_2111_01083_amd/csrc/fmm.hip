@@ -160,7 +160,7 @@ __device__ __forceinline__ void pair_vals(real r2, real beta, real& va, real& vb
     vb = __builtin_amdgcn_rcpf(r2);
   } else {
     va = log(r2);
-    vb = 1.0 / r2;
+    vb = recip_pw(r2);
   }
 }
 
