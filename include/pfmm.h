@@ -376,7 +376,8 @@ typedef struct {
 } pfmm_tune_report_t;
 
 /* Autotuner: times candidate tunings (near_blocks, or for an FMM near part
- * the leaf levels next to the cost model's; for NUFFT plans both grids) on
+ * the leaf levels next to the cost model's and, when the targets are the
+ * sources, the other leaf form; for NUFFT plans both grids) on
  * the caller's inputs with HIP events, keeps the fastest in the
  * plan and leaves the result of an evaluation with it in out_pot/out_grad.
  * Arguments as for pfmm_eval; candidates that would need more than

@@ -280,11 +280,12 @@ def _tuning_workspace_bytes(plan, ns, nt):
         for nb in (4096, 16384):
             for g in (0, 1):
                 for lv in range(0, 12):   # FMM leaf levels (only the tree's neighbours are tried)
-                    try:
-                        pfmm_plan_set_tuning(plan, nb, g, lv)
-                    except PfmmError:
-                        continue
-                    best = max(best, pfmm_workspace_bytes(plan, ns, nt))
+                    for leaves in (0, 1, 2):
+                        try:
+                            pfmm_plan_set_tuning(plan, nb, g, lv, leaves)
+                        except PfmmError:
+                            continue
+                        best = max(best, pfmm_workspace_bytes(plan, ns, nt))
     finally:
         pfmm_plan_set_tuning(plan, start["near_blocks"], start["nufft_grid"], start["fmm_level"], start["fmm_leaves"])
     return best

@@ -875,12 +875,18 @@ int pfmm_autotune(pfmm_plan_t p, int64_t ns, const double* src_xy, const double*
   const int64_t near_c[3] = {mutual ? 4096 : 1024, mutual ? 8192 : 2048, mutual ? 16384 : 4096};
   pfmm_tuning_t best = cur;
   double best_near = nm;
+  const bool sym0 = fmm_symmetric_leaves(p);
   for (int k = 0; k < 3; ++k) {
     pfmm_tuning_t t = cur;
     if (L0.fmm) {
-      if (k == 2) break;
-      t.fmm_level = L0.ft.L + (k ? 1 : -1);
-      if (t.fmm_level < 1 || t.fmm_level > FMM_MAX_LEVEL) continue;
+      if (k < 2) {
+        t.fmm_level = L0.ft.L + (k ? 1 : -1);
+        if (t.fmm_level < 1 || t.fmm_level > FMM_MAX_LEVEL) continue;
+      } else {
+        // targets = sources: the other leaf form (symmetric or one-sided)
+        if (!p->self_exclude) break;
+        t.fmm_leaves = sym0 ? 1 : 2;
+      }
     } else {
       t.near_blocks = near_c[k];
       if (t.near_blocks == cur.near_blocks) continue;

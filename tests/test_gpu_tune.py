@@ -44,7 +44,8 @@ def test_nufft_doubled_grid_keeps_accuracy(env, kernel, prec, tol, bar):
     (((100.0, 0.0), (0.0, 1.0)), "laplace", 0.0, "nufft", "auto", 20000),
     (((1.0, 0.0), (0.3, 1.0)), "yukawa", 10.0, "auto", "fmm", 100000)])
 def test_autotune_result_and_reuse(env, cell, kernel, beta, far, near, n):
-    # the FMM plan: the candidates are the leaf levels next to the cost model's
+    # the FMM plan: the candidates are the leaf levels next to the cost
+    # model's and the other leaf form (symmetric / one-sided)
     P, torch, dev = env
     e1, e2 = cell
     rng = np.random.default_rng(2)
@@ -59,6 +60,9 @@ def test_autotune_result_and_reuse(env, cell, kernel, beta, far, near, n):
     assert rep["best_ms"] <= 1.10 * rep["default_ms"]
     assert rep["near_blocks"] in (4096, 8192, 16384, 0)
     assert 0 <= rep["fmm_level"] <= 11 and (near == "fmm" or rep["fmm_level"] == 0)
+    assert rep["fmm_leaves"] in (0, 1, 2) and (near == "fmm" or rep["fmm_leaves"] == 0)
+    if near == "fmm":
+        assert rep["n_tried"] >= 4   # the reference, two leaf levels, the other leaf form
     pot = pot[0].cpu().numpy(); grad = grad[0].cpu().numpy()
     p2, g2 = plan(ds, dq)
     assert rel(p2.cpu().numpy(), pot) < 1e-12 and rel(g2.cpu().numpy(), grad) < 1e-12
