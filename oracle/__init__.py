@@ -54,12 +54,13 @@ def _load():
         lib.oracle_laplace_rowsum.argtypes = [ctypes.c_double] * 3 + [ctypes.c_int] + common
         lib.oracle_yukawa_lattice.argtypes = [_dp, _dp, ctypes.c_double, ctypes.c_double] + common
         lib.oracle_stokes_ewald.argtypes = [_dp, _dp, ctypes.c_double, ctypes.c_double] + common
+        lib.oracle_mstokes.argtypes = [_dp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_double] + common
         lib.oracle_free_space.argtypes = [ctypes.c_int, ctypes.c_double] + common
         lib.oracle_laplace_p1.argtypes = [ctypes.c_double] + common
         lib.oracle_yukawa_p1.argtypes = [ctypes.c_double] * 3 + common
         lib.oracle_stokes_p1.argtypes = [ctypes.c_double] + common
         for f in (lib.oracle_laplace_ewald, lib.oracle_laplace_rowsum, lib.oracle_yukawa_lattice,
-                  lib.oracle_stokes_ewald, lib.oracle_free_space, lib.oracle_laplace_p1,
+                  lib.oracle_stokes_ewald, lib.oracle_mstokes, lib.oracle_free_space, lib.oracle_laplace_p1,
                   lib.oracle_yukawa_p1, lib.oracle_stokes_p1):
             f.restype = ctypes.c_int
         _lib = lib
@@ -164,13 +165,28 @@ def stokes(e1, e2, src, f, trg=None, tol=1e-14, alpha=0.0, self_idx=None):
     return vel, grad
 
 
-def free_space(kernel, src, dens, trg=None, beta=0.0, self_idx=None):
-    """Non-periodic direct sums ('laplace' | 'yukawa' | 'stokes'), same layouts."""
+def mstokes(e1, e2, beta, src, f, trg=None, tol=1e-14, alpha=0.0, self_idx=None):
+    """Periodic modified Stokeslet (Sec. 5, eq. msgreen) velocity u[2, nt]
+    and gradient g[4, nt] (du1/dx, du1/dy, du2/dx, du2/dy); f has shape
+    (2, ns), any net force: the cell mean of u is sum(f)/(beta^2 |C|)."""
     lib = _load()
-    k = {"laplace": 0, "yukawa": 1, "stokes": 2}[kernel]
-    src, dens, trg, ns, nt, se = _prep(src, dens, trg, 2 if k == 2 else 1, self_idx)
-    pot = np.empty((2, nt)) if k == 2 else np.empty(nt)
-    grad = np.empty((4, nt)) if k == 2 else np.empty((2, nt))
+    src, f, trg, ns, nt, se = _prep(src, f, trg, 2, self_idx)
+    e1 = _arr(e1); e2 = _arr(e2)
+    vel = np.empty((2, nt)); grad = np.empty((4, nt))
+    _check(lib.oracle_mstokes(_p(e1), _p(e2), beta, alpha, tol, ns, _p(src[0]), _p(src[1]), _p(f),
+                              nt, _p(trg[0]), _p(trg[1]), _p(se), _p(vel), _p(grad)),
+           "oracle_mstokes")
+    return vel, grad
+
+
+def free_space(kernel, src, dens, trg=None, beta=0.0, self_idx=None):
+    """Non-periodic direct sums ('laplace' | 'yukawa' | 'stokes' | 'mstokes'),
+    same layouts."""
+    lib = _load()
+    k = {"laplace": 0, "yukawa": 1, "stokes": 2, "mstokes": 3}[kernel]
+    src, dens, trg, ns, nt, se = _prep(src, dens, trg, 2 if k >= 2 else 1, self_idx)
+    pot = np.empty((2, nt)) if k >= 2 else np.empty(nt)
+    grad = np.empty((4, nt)) if k >= 2 else np.empty((2, nt))
     _check(lib.oracle_free_space(k, beta, ns, _p(src[0]), _p(src[1]), _p(dens), nt,
                                  _p(trg[0]), _p(trg[1]), _p(se), _p(pot), _p(grad)), "oracle_free_space")
     return pot, grad

@@ -14,6 +14,8 @@
 //     Laplace:   G = -(1/2pi) log r                       (Sec. 1)
 //     Yukawa:    G = (1/2pi) K0(beta r)                   (Sec. 1)
 //     Stokeslet: G = -(1/4pi)(log r I - r r^T / r^2)      (Sec. 5.2, eq. stokeslet)
+//     modified Stokeslet (Brinkman): the operator of Sec. 5 eq. msgreen on
+//                G_MB = -(K0(beta r) + log r)/(2 pi beta^2)
 // The Laplace and Stokes sums converge only conditionally; they need
 // sum_j q_j = 0 (Sec. 1 eq. chargeneutral) and are defined here as the
 // periodic ("tin-foil") solution with zero mean over the cell, which is
@@ -36,6 +38,10 @@
 //     real space (1/4pi)[(E1(x)/2 - e^{-x}) I + e^{-x} r r^T/r^2], x = a^2 r^2;
 //     reciprocal (1/|C|) sum_{k!=0} (I - k k^T/k^2) phi(k)/k^2 e^{ik.t} F(k);
 //     self term -(1/4pi)((gamma + 2 ln a)/2 + 1) f_i.
+//   * modified Stokes: G = [G_Y I - Hess G_Y / beta^2] + Hess G_L / beta^2
+//     (G_L, G_Y the Laplace and Yukawa kernels above); the bracket by a
+//     direct lattice sum, Hess G_L by an Ewald split (k != 0), so the cell
+//     mean of u is the net force / (beta^2 |C|) and no neutrality is needed.
 // Special functions come from the C++17 standard library (std::expint,
 // std::cyl_bessel_k).
 //
@@ -121,6 +127,26 @@ double max_extent(const Lattice& L, const double* x, const double* y, int64_t n)
     m = std::max(m, std::hypot(rx, ry));
   }
   return m;
+}
+
+// Second and third derivatives of a radial function g(|x|) at x = (rx, ry),
+// from the first three radial derivatives d1, d2, d3 of g at r = |x|:
+//   H_ij  = b x_i x_j + a delta_ij,
+//   T_ijk = c x_i x_j x_k + b (delta_ij x_k + delta_ik x_j + delta_jk x_i),
+//   a = d1/r, b = (d2 - d1/r)/r^2, c = (d3 - 3 d2/r + 3 d1/r^2)/r^3.
+void radial_derivs(double rx, double ry, double d1, double d2, double d3,
+                   double H[2][2], double T[2][2][2]) {
+  const double r2 = rx * rx + ry * ry, r = std::sqrt(r2);
+  const double a = d1 / r, b = (d2 - d1 / r) / r2;
+  const double c = (d3 - 3 * d2 / r + 3 * d1 / r2) / (r2 * r);
+  const double x[2] = {rx, ry};
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      H[i][j] = b * x[i] * x[j] + (i == j ? a : 0.0);
+      for (int k = 0; k < 2; ++k)
+        T[i][j][k] = c * x[i] * x[j] * x[k] +
+                     b * ((i == j ? x[k] : 0.0) + (i == k ? x[j] : 0.0) + (j == k ? x[i] : 0.0));
+    }
 }
 
 }  // namespace
@@ -423,9 +449,150 @@ int oracle_stokes_ewald(const double* e1, const double* e2, double alpha, double
   return bad ? -4 : 0;
 }
 
+// Modified Stokeslet (Sec. 5, eq. msgreen): the fundamental solution of
+// (beta^2 - Laplacian) u + grad p = f delta, div u = 0, built from the
+// modified biharmonic Green's function G_MB = -(K0(beta r) + log r)/(2 pi beta^2).
+// With G_L = -(1/2pi) log r and G_Y = (1/2pi) K0(beta r), G_MB = (G_L - G_Y)/beta^2
+// and Laplacian G_MB = -G_Y, so the Stokeslet splits as
+//     G_MS = [G_Y I - (1/beta^2) Hess G_Y] + (1/beta^2) Hess G_L.
+// The bracket decays like K0 and is summed directly over the lattice (as
+// the Yukawa sum); the Hessian of G_L is summed by an Ewald split of G_L
+// (real space (1/4pi) E1(alpha^2 r^2), reciprocal e^{-k^2/4alpha^2}/k^2,
+// k != 0), i.e. it is the Hessian of the zero-mean periodic Laplace
+// Green's function. Hence the cell mean of u is (sum_j f_j)/(beta^2 |C|),
+// Brinkman flow with a periodic pressure; no neutrality is needed.
+// dens f[2][ns]; out_vel[2][nt], out_grad[4][nt] = (du1/dx, du1/dy,
+// du2/dx, du2/dy). A target on its own source leaves out that whole term.
+int oracle_mstokes(const double* e1, const double* e2, double beta, double alpha, double tol,
+                   int64_t ns, const double* sx, const double* sy, const double* f,
+                   int64_t nt, const double* tx, const double* ty, const int64_t* self_idx,
+                   double* out_vel, double* out_grad) {
+  Lattice L;
+  if (make_lattice(e1, e2, &L)) return -1;
+  if (!(beta > 0) || !(tol > 0 && tol < 1)) return -3;
+  if (alpha <= 0) {
+    double nn = std::max<double>(1.0, (double)ns * nt / (double)(ns + nt));
+    alpha = std::sqrt(PI * std::sqrt(nn) / L.area);
+    alpha = std::max(alpha, 4.0 / std::sqrt(L.area));
+  }
+  const double* f1 = f;
+  const double* f2 = f + ns;
+  const double ib2 = 1.0 / (beta * beta);
+  // screened part: every term is bounded by a multiple of K0(beta r) + K1(beta r)
+  double R = 1.0 / beta;
+  while ((1 + 2 * PI * R / (beta * L.area)) *
+             (std::cyl_bessel_k(0.0, beta * R) + std::cyl_bessel_k(1.0, beta * R)) > tol)
+    R *= 1.1;
+  // Laplace Hessian: Ewald cut-offs as for the Stokes sum
+  const double lt = std::log(1.0 / tol);
+  const double rc = std::sqrt(lt + 3.0) / alpha;
+  const double kc = 2.0 * alpha * std::sqrt(lt + std::log(2.0 + lt) + 3.0);
+  double ext = std::max(max_extent(L, sx, sy, ns), max_extent(L, tx, ty, nt));
+  std::vector<double> img = lattice_ball(L, std::max(R, rc) + 2 * ext + 1e-12);
+  std::vector<double> kv = reciprocal_ball(L, kc);
+  const size_t nimg = img.size() / 2, nk = kv.size() / 2;
+  const double a2 = alpha * alpha;
+
+  // reciprocal part: V_i(k) = (1/|C|) (-k_i k_j) e^{-k^2/4a^2}/k^2 F_j(k),
+  // F(k) = sum_s f_s e^{-i k.s}
+  std::vector<double> Vr(2 * nk), Vi(2 * nk);
+#pragma omp parallel for schedule(dynamic, 4)
+  for (long a = 0; a < (long)nk; ++a) {
+    double kx = kv[2 * a], ky = kv[2 * a + 1];
+    double F1r = 0, F1i = 0, F2r = 0, F2i = 0;
+    for (int64_t j = 0; j < ns; ++j) {
+      double ph = kx * sx[j] + ky * sy[j];
+      double c = std::cos(ph), s = std::sin(ph);
+      F1r += f1[j] * c; F1i -= f1[j] * s;
+      F2r += f2[j] * c; F2i -= f2[j] * s;
+    }
+    double k2 = kx * kx + ky * ky;
+    double w = -std::exp(-k2 / (4 * a2)) / (k2 * L.area);
+    double kFr = kx * F1r + ky * F2r, kFi = kx * F1i + ky * F2i;
+    Vr[2 * a] = w * kx * kFr; Vi[2 * a] = w * kx * kFi;
+    Vr[2 * a + 1] = w * ky * kFr; Vi[2 * a + 1] = w * ky * kFi;
+  }
+  int bad = 0;
+#pragma omp parallel for schedule(dynamic, 8) reduction(| : bad)
+  for (int64_t i = 0; i < nt; ++i) {
+    double u[2] = {0, 0}, g[2][2] = {{0, 0}, {0, 0}};   // g[i][k] = d u_i / d x_k
+    for (int64_t j = 0; j < ns; ++j) {
+      double bx = tx[i] - sx[j], by = ty[i] - sy[j];
+      lattice_reduce(L, bx, by);
+      const double ff[2] = {f1[j], f2[j]};
+      for (size_t l = 0; l < nimg; ++l) {
+        double rx = bx - img[2 * l], ry = by - img[2 * l + 1];
+        double r2 = rx * rx + ry * ry;
+        if (r2 > R * R && r2 > rc * rc) continue;
+        if (r2 == 0) {
+          if (!(self_idx && j == self_idx[i])) bad = 1;
+          continue;
+        }
+        double r = std::sqrt(r2);
+        double H[2][2], T[2][2][2];
+        if (r2 <= R * R) {
+          // G_Y I - Hess G_Y / beta^2 with the radial derivatives of
+          // G_Y = K0(beta r)/2pi: d1 = -beta K1, d2 = beta^2 (K0 + K1/(beta r)),
+          // d3 = -beta^3 K1 - beta^2 K0/r - 2 beta K1/r^2 (all over 2pi)
+          double k0 = std::cyl_bessel_k(0.0, beta * r), k1 = std::cyl_bessel_k(1.0, beta * r);
+          double d0 = k0 / (2 * PI), d1 = -beta * k1 / (2 * PI);
+          double d2 = beta * beta * (k0 + k1 / (beta * r)) / (2 * PI);
+          double d3 = (-beta * beta * beta * k1 - beta * beta * k0 / r - 2 * beta * k1 / r2) / (2 * PI);
+          radial_derivs(rx, ry, d1, d2, d3, H, T);
+          const double x[2] = {rx, ry};
+          for (int p = 0; p < 2; ++p) {
+            u[p] += d0 * ff[p] - ib2 * (H[p][0] * ff[0] + H[p][1] * ff[1]);
+            for (int k = 0; k < 2; ++k)
+              g[p][k] += d1 * x[k] / r * ff[p] - ib2 * (T[p][0][k] * ff[0] + T[p][1][k] * ff[1]);
+          }
+        }
+        if (r2 <= rc * rc) {
+          // Hess of (1/4pi) E1(a^2 r^2) / beta^2: d1 = -e^{-x}/(2pi r),
+          // d2 = e^{-x} (2a^2 + 1/r^2)/2pi, d3 = -e^{-x} (4a^4 r + 2a^2/r + 2/r^3)/2pi
+          double ex = std::exp(-a2 * r2);
+          double d1 = -ex / (2 * PI * r);
+          double d2 = ex * (2 * a2 + 1 / r2) / (2 * PI);
+          double d3 = -ex * (4 * a2 * a2 * r + 2 * a2 / r + 2 / (r2 * r)) / (2 * PI);
+          radial_derivs(rx, ry, d1, d2, d3, H, T);
+          for (int p = 0; p < 2; ++p) {
+            u[p] += ib2 * (H[p][0] * ff[0] + H[p][1] * ff[1]);
+            for (int k = 0; k < 2; ++k) g[p][k] += ib2 * (T[p][0][k] * ff[0] + T[p][1][k] * ff[1]);
+          }
+        }
+      }
+    }
+    for (size_t a = 0; a < nk; ++a) {
+      double kx = kv[2 * a], ky = kv[2 * a + 1];
+      double ph = kx * tx[i] + ky * ty[i];
+      double c = std::cos(ph), s = std::sin(ph);
+      for (int p = 0; p < 2; ++p) {
+        double re = c * Vr[2 * a + p] - s * Vi[2 * a + p], im = c * Vi[2 * a + p] + s * Vr[2 * a + p];
+        u[p] += ib2 * re;
+        // d/dx_k of Re(e^{ik.t} V) = -k_k Im(e^{ik.t} V)
+        g[p][0] -= ib2 * kx * im; g[p][1] -= ib2 * ky * im;
+      }
+    }
+    if (self_idx && self_idx[i] >= 0) {
+      // the reciprocal sum holds the smooth part of the left-out term:
+      // G_L - (1/4pi) E1(a^2 r^2) = const - a^2 r^2/(4pi) + O(r^4), whose
+      // Hessian at 0 is -(a^2/2pi) I (odd third derivatives vanish)
+      const int64_t s = self_idx[i];
+      u[0] += ib2 * a2 / (2 * PI) * f1[s];
+      u[1] += ib2 * a2 / (2 * PI) * f2[s];
+    }
+    if (out_vel) { out_vel[i] = u[0]; out_vel[nt + i] = u[1]; }
+    if (out_grad) {
+      out_grad[i] = g[0][0]; out_grad[nt + i] = g[0][1];
+      out_grad[2 * nt + i] = g[1][0]; out_grad[3 * nt + i] = g[1][1];
+    }
+  }
+  return bad ? -4 : 0;
+}
+
 // Free-space (non-periodic) direct sums, used by tests that pin the
 // oracle's periodic sums in limits where images do not matter.
-// kernel: 0 Laplace, 1 Yukawa (beta), 2 Stokes. Same layouts as above.
+// kernel: 0 Laplace, 1 Yukawa (beta), 2 Stokes, 3 modified Stokes (beta).
+// Same layouts as above.
 int oracle_free_space(int kernel, double beta, int64_t ns, const double* sx, const double* sy,
                       const double* dens, int64_t nt, const double* tx, const double* ty,
                       const int64_t* self_idx, double* out_pot, double* out_grad) {
@@ -443,6 +610,23 @@ int oracle_free_space(int kernel, double beta, int64_t ns, const double* sx, con
         p0 += dens[j] * std::cyl_bessel_k(0.0, beta * r) / (2 * PI);
         double gg = -dens[j] * beta * std::cyl_bessel_k(1.0, beta * r) / (2 * PI * r);
         g[0] += gg * rx; g[1] += gg * ry;
+      } else if (kernel == 3) {
+        // modified Stokeslet as the operator of eq. msgreen on
+        // G_MB = -(K0(beta r) + log r)/(2 pi beta^2): [[-d_yy, d_xy], [d_xy, -d_xx]] G_MB
+        double br = beta * r, k0 = std::cyl_bessel_k(0.0, br), k1 = std::cyl_bessel_k(1.0, br);
+        double cm = -1.0 / (2 * PI * beta * beta);
+        double d1 = cm * (-beta * k1 + 1 / r);
+        double d2 = cm * (beta * beta * (k0 + k1 / br) - 1 / r2);
+        double d3 = cm * (-beta * beta * beta * k1 - beta * beta * k0 / r - 2 * beta * k1 / r2 + 2 / (r2 * r));
+        double H[2][2], T[2][2][2];
+        radial_derivs(rx, ry, d1, d2, d3, H, T);
+        double fx = dens[j], fy = dens[ns + j];
+        p0 += -H[1][1] * fx + H[0][1] * fy;
+        p1 += H[0][1] * fx - H[0][0] * fy;
+        for (int k = 0; k < 2; ++k) {
+          g[k] += -T[1][1][k] * fx + T[0][1][k] * fy;
+          g[2 + k] += T[0][1][k] * fx - T[0][0][k] * fy;
+        }
       } else {
         double fx = dens[j], fy = dens[ns + j], rf = rx * fx + ry * fy;
         double lr = std::log(r);
@@ -455,7 +639,7 @@ int oracle_free_space(int kernel, double beta, int64_t ns, const double* sx, con
                              - 2 * rf * rr[a] * rr[k] / (r2 * r2)) / (4 * PI);
       }
     }
-    if (kernel == 2) {
+    if (kernel >= 2) {
       if (out_pot) { out_pot[i] = p0; out_pot[nt + i] = p1; }
       if (out_grad) for (int c = 0; c < 4; ++c) out_grad[c * nt + i] = g[c];
     } else {

@@ -573,3 +573,163 @@ def test_stokes_pressure_of_a_tight_pair_is_free_space():
     r = trg[:, :, None] - src[:, None, :]
     ref = (np.einsum("ktj,kj->tj", r, f) / (r[0] ** 2 + r[1] ** 2)).sum(1) / (2 * np.pi)
     assert rel(p, ref) < 1e-3
+
+
+# --- modified Stokeslet (Sec. 5, eq. msgreen) --------------------------------
+
+def _g_mb(beta, x, y):
+    # G_MB = -(K0(beta r) + log r)/(2 pi beta^2), the paper's modified
+    # biharmonic Green's function, from scipy
+    r = np.hypot(x, y)
+    return -(sp.k0(beta * r) + np.log(r)) / (2 * np.pi * beta ** 2)
+
+
+def test_free_space_mstokes_is_the_operator_on_g_mb():
+    # the oracle's free-space modified Stokeslet against the operator
+    # [[-d_yy, d_xy], [d_xy, -d_xx]] applied to G_MB by fourth-order differences
+    rng = np.random.default_rng(40)
+    beta = 2.5
+    src = rng.uniform(-0.5, 0.5, (2, 3))
+    f = rng.standard_normal((2, 3))
+    trg = rng.uniform(-0.5, 0.5, (2, 4)) + np.array([[1.5], [0.0]])
+    u, g = oracle.free_space("mstokes", src, f, trg, beta=beta)
+    h = 2e-3
+    w = {-2: 1 / 12, -1: -2 / 3, 1: 2 / 3, 2: -1 / 12}
+
+    def d(fun, kx, ky):
+        # fourth-order difference: kx, ky derivative orders (0..2 in sum)
+        if kx == 2 or ky == 2:
+            c = {-2: -1 / 12, -1: 4 / 3, 0: -5 / 2, 1: 4 / 3, 2: -1 / 12}
+            return lambda x, y: sum(c[a] * (fun(x + a * h, y) if kx == 2 else fun(x, y + a * h))
+                                    for a in c) / h ** 2
+        if kx == 1 and ky == 1:
+            return lambda x, y: sum(w[a] * w[b] * fun(x + a * h, y + b * h) for a in w for b in w) / h ** 2
+        raise ValueError
+
+    ref = np.zeros((2, trg.shape[1]))
+    for j in range(3):
+        x = trg[0] - src[0, j]; y = trg[1] - src[1, j]
+        gm = lambda x, y: _g_mb(beta, x, y)
+        gxx, gyy, gxy = d(gm, 2, 0)(x, y), d(gm, 0, 2)(x, y), d(gm, 1, 1)(x, y)
+        ref[0] += -gyy * f[0, j] + gxy * f[1, j]
+        ref[1] += gxy * f[0, j] - gxx * f[1, j]
+    assert rel(u, ref) < 1e-7
+    # gradient of the free-space velocity by differences
+    for k in range(2):
+        dp = np.zeros((2, 1)); dp[k] = 1e-5
+        fd = (oracle.free_space("mstokes", src, f, trg + dp, beta=beta)[0]
+              - oracle.free_space("mstokes", src, f, trg - dp, beta=beta)[0]) / 2e-5
+        assert rel(np.stack([g[k], g[2 + k]]), fd) < 1e-7
+
+
+@pytest.mark.parametrize("self_trg", [False, True])
+def test_mstokes_independent_of_split(self_trg):
+    rng = np.random.default_rng(41)
+    src = W.cell_points(rng, *GENERAL, 8)
+    trg = None if self_trg else W.cell_points(rng, *GENERAL, 6)
+    f = rng.standard_normal((2, 8))          # net force allowed
+    a = oracle.mstokes(*GENERAL, 3.0, src, f, trg, alpha=2.5)
+    b = oracle.mstokes(*GENERAL, 3.0, src, f, trg, alpha=8.0)
+    assert rel(a[0], b[0]) < 1e-12 and rel(a[1], b[1]) < 1e-12
+
+
+def test_mstokes_periodic_divergence_free_and_gradient_is_derivative():
+    rng = np.random.default_rng(42)
+    src = W.cell_points(rng, *SHEARED, 7)
+    trg = W.cell_points(rng, *SHEARED, 5)
+    f = rng.standard_normal((2, 7))
+    u, g = oracle.mstokes(*SHEARED, 1.7, src, f, trg)
+    for sh in SHEARED:
+        u1, g1 = oracle.mstokes(*SHEARED, 1.7, src, f, trg + np.array(sh)[:, None])
+        assert rel(u1, u) < 1e-12 and rel(g1, g) < 1e-12
+    assert np.max(np.abs(g[0] + g[3])) < 1e-12 * np.max(np.abs(g))
+    h = 1e-5
+    for k in range(2):
+        dp = np.zeros((2, 1)); dp[k] = h
+        fd = (oracle.mstokes(*SHEARED, 1.7, src, f, trg + dp)[0]
+              - oracle.mstokes(*SHEARED, 1.7, src, f, trg - dp)[0]) / (2 * h)
+        assert rel(np.stack([g[k], g[2 + k]]), fd) < 1e-6
+
+
+def test_mstokes_tends_to_stokes_quadratically_in_beta():
+    # zero net force: the symbol (I - k k^T/k^2)/(beta^2 + k^2) differs from
+    # the Stokes one by O(beta^2) summably, so the error falls by 4 when beta halves
+    src, f, trg = _setup(*SHEARED, ns=7, nt=5, seed=43, stokes=True)
+    us, gs = oracle.stokes(*SHEARED, src, f, trg)
+    err = []
+    for beta in (0.5, 0.25):
+        u, g = oracle.mstokes(*SHEARED, beta, src, f, trg)
+        err.append((rel(u, us), rel(g, gs)))
+    for c in range(2):
+        assert 3.5 < err[0][c] / err[1][c] < 4.5, err
+    assert max(err[1]) < 1e-2, err
+
+
+def test_mstokes_large_beta_is_the_laplace_hessian():
+    # away from the sources beta^2 u -> Hess(G_L^per) f: the screened part
+    # dies like K0(beta r); Hess by differences of the Laplace oracle's gradient
+    rng = np.random.default_rng(44)
+    e1, e2 = (1.0, 0.0), (0.0, 1.0)
+    src = np.array([[-0.3, 0.2, 0.1], [0.25, -0.2, 0.3]])
+    f = W.neutral_forces(rng, 3)
+    trg = np.array([[0.45, -0.4], [-0.3, -0.45]])      # >= 0.25 from every source image
+    beta = 160.0
+    u, _ = oracle.mstokes(e1, e2, beta, src, f, trg)
+    h = 1e-4
+    ref = np.zeros((2, 2))
+    for j in range(2):
+        dp = np.zeros((2, 1)); dp[j] = h
+        gp = oracle.laplace(e1, e2, src, f[j], trg + dp)[1]
+        gm = oracle.laplace(e1, e2, src, f[j], trg - dp)[1]
+        gp2 = oracle.laplace(e1, e2, src, f[j], trg + 2 * dp)[1]
+        gm2 = oracle.laplace(e1, e2, src, f[j], trg - 2 * dp)[1]
+        ref += (8 * (gp - gm) - (gp2 - gm2)) / (12 * h)   # d_j grad_i phi[f_j]
+    assert rel(beta ** 2 * u, ref) < 1e-8
+
+
+def test_mstokes_cell_mean_is_net_force_over_beta2_area():
+    # integrating (beta^2 - Lap) u + grad p = f over the cell: beta^2 |C| mean(u) = F
+    # (periodic u and p); midpoint rule over the cell in lattice coordinates
+    rng = np.random.default_rng(45)
+    e1, e2 = (1.0, 0.0), (0.35, 0.9)
+    src = W.cell_points(rng, e1, e2, 3)
+    f = rng.standard_normal((2, 3))
+    beta, n = 3.0, 128
+    g = (np.arange(n) + 0.5) / n - 0.5
+    a, b = np.meshgrid(g, g, indexing="ij")
+    trg = np.array([a.ravel() * e1[0] + b.ravel() * e2[0], a.ravel() * e1[1] + b.ravel() * e2[1]])
+    u, _ = oracle.mstokes(e1, e2, beta, src, f, trg, tol=1e-12)
+    mean = f.sum(axis=1) / (beta ** 2 * 0.9)
+    assert np.max(np.abs(u.mean(axis=1) - mean)) < 1e-4 * np.max(np.abs(mean))
+
+
+def test_mstokes_tight_pair_is_free_space():
+    # a force pair 1e-3 apart seen from 3e-3: the images add O((r/L)^3)
+    delta = 1e-3
+    src = np.array([[0.0, delta], [0.0, 0.0]])
+    f = np.array([[1.0, -1.0], [0.5, -0.5]])
+    trg = np.array([[0.5 * delta, 3 * delta, -2 * delta], [2 * delta, -delta, 2 * delta]])
+    u, g = oracle.mstokes((1.0, 0.0), (0.0, 1.0), 20.0, src, f, trg)
+    uf, gf = oracle.free_space("mstokes", src, f, trg, beta=20.0)
+    assert rel(u, uf) < 1e-6 and rel(g, gf) < 1e-6
+
+
+def test_mstokes_self_term_is_the_limit_at_the_source():
+    # u_self(x_i) = lim_{h -> 0} [u(x_i + h) - G_MS(h) f_i], with G_MS from
+    # the free-space operator form; the +-h average cancels the O(h) term.
+    # Both sides cancel 1/r^2 terms near r = 0, so h stays >= 1e-4
+    rng = np.random.default_rng(46)
+    n = 7
+    src = W.cell_points(rng, *SHEARED, n)
+    f = rng.standard_normal((2, n))
+    i, beta = 3, 2.0
+    u_self, _ = oracle.mstokes(*SHEARED, beta, src, f, None)
+    for h in (1e-3, 3e-4, 1e-4):
+        acc = np.zeros(2)
+        for dv in ((h, 0.0), (-h, 0.0), (0.0, h), (0.0, -h)):
+            t = src[:, [i]] + np.array(dv)[:, None]
+            u, _ = oracle.mstokes(*SHEARED, beta, src, f, t)
+            G, _ = oracle.free_space("mstokes", src[:, [i]], f[:, [i]], t, beta=beta)
+            acc += u[:, 0] - G[:, 0]
+        acc /= 4
+        assert np.abs(acc - u_self[:, i]).max() < 1e-8 * np.abs(u_self).max() + 2 * h * h, (h, acc, u_self[:, i])
